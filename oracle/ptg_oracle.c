@@ -1,0 +1,491 @@
+/*
+ * ptg_oracle.c -- plain FP64 CPU oracle for polynomial gradient-noise fBm.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg load this library.  The product path (the HIP library) never
+ * calls it, and this file shares no code, header, table or constant generator with
+ * that library: every constant below is typed here from its definition.
+ *
+ * Source: Thorimbert & Chopard, "Polynomial methods for fast Procedural Terrain
+ * Generation" (arXiv:1610.03525).
+ *
+ *  - Sec. 2.1, eq. (mixedderiv): corner constraints are prescribed values of the
+ *    mixed partial derivatives h^d at the 2^D corners of the unit cell.
+ *  - Sec. 2.1, eq. (independance): on an edge, h depends on that edge's two corners
+ *    only (so neighbouring cells agree on shared edges).
+ *  - Sec. 2.2, eq. (polynomial): h is a tensor polynomial with exponents 0..n per axis,
+ *    (n+1)^D coefficients; eq. (nconstraints) bounds the constraint count.
+ *  - Sec. 3.4: D1M1N3 with h(0)=0, h(1)=1 and zero end slopes is the smoothstep S3;
+ *    D3M1N3 is the 3D analogue; second-order constraints (M=2) give smoother cells.
+ *  - Sec. 3.2: Perlin's blend (comparison path) with fade S3 (or S5, Sec. 5.1).
+ *  - Sec. 4: the fBm octave sum, amplitude ratio (persistence) and frequency ratio
+ *    (lacunarity) per octave.
+ *
+ * Readings taken where the paper is silent (each one is listed in the design notes):
+ *  - Cell polynomial: the unique tensor polynomial of degree n = 2M+1 per axis whose
+ *    value is 0 at every corner, whose first partial derivatives equal the corner's
+ *    gradient, and whose every other mixed derivative h^d with 0 <= d_k <= M is 0.
+ *    With these (M+1)^D conditions per corner the system is square.  Its solution
+ *    is the tensor Hermite form evaluated below.
+ *  - Octaves o = 0..N-1, amplitude p^o, frequency f0*L^o (both by repeated FP64
+ *    multiplication), no normalisation of the sum.
+ *  - Sample X (int64 world index) sits at the sample centre: u = (X + 1/2) * f_o,
+ *    cell = floor(u), local t = u - cell.
+ *  - Lattice: a stated 32-bit hash of (node index, octave, seed) built from the
+ *    MurmurHash3 32-bit finalizer (fmix32), mapped to a unit gradient (circle angle
+ *    in 2D, Archimedes' cylinder map on the sphere in 3D).
+ *
+ * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -fPIC -shared
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_MAX_OCTAVES 32
+
+static const double ORC_TWO_PI = 6.283185307179586476925286766559;
+
+/* ------------------------------------------------------------------------- */
+/* Lattice hash                                                              */
+/* ------------------------------------------------------------------------- */
+
+/* MurmurHash3 32-bit finalizer (Appleby): xor-shift / multiply avalanche. */
+uint32_t orc_fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+/* Absorb one int64 lattice index: its low 32-bit word, then its high word
+ * (two's complement), each xor-ed into the state and followed by fmix32. */
+static uint32_t orc_absorb_index(uint32_t k, int64_t i)
+{
+    uint64_t u = (uint64_t)i;
+    uint32_t lo = (uint32_t)(u & 0xFFFFFFFFu);
+    uint32_t hi = (uint32_t)(u >> 32);
+    k = orc_fmix32(k ^ lo);
+    k = orc_fmix32(k ^ hi);
+    return k;
+}
+
+/* Per-(seed, octave) prefix of every key. */
+uint32_t orc_prefix(uint32_t seed, int32_t octave)
+{
+    uint32_t k = orc_fmix32(seed ^ 0x9E3779B9u);
+    k = orc_fmix32(k ^ (uint32_t)octave);
+    return k;
+}
+
+/* 2D key: the y index is absorbed after the prefix, the x index is hashed from its
+ * own salt, and the two are combined by one more fmix32. */
+uint32_t orc_key2(int64_t ix, int64_t iy, int32_t octave, uint32_t seed)
+{
+    uint32_t ky = orc_absorb_index(orc_prefix(seed, octave), iy);
+    uint32_t kx = orc_absorb_index(0x27D4EB2Fu, ix);
+    return orc_fmix32(ky ^ kx);
+}
+
+/* 3D key: z, then y, absorbed after the prefix; x as in 2D. */
+uint32_t orc_key3(int64_t ix, int64_t iy, int64_t iz, int32_t octave, uint32_t seed)
+{
+    uint32_t kzy = orc_absorb_index(orc_absorb_index(orc_prefix(seed, octave), iz), iy);
+    uint32_t kx = orc_absorb_index(0x27D4EB2Fu, ix);
+    return orc_fmix32(kzy ^ kx);
+}
+
+/* Second 32-bit word of a 3D node (the azimuth of its gradient). */
+uint32_t orc_key3_second(uint32_t key)
+{
+    return orc_fmix32(key ^ 0x165667B1u);
+}
+
+/* 2D unit gradient: angle = 2*pi * (top 24 bits of the key) / 2^24. */
+void orc_grad2(uint32_t key, double *g)
+{
+    double turns = (double)(key >> 8) * (1.0 / 16777216.0);
+    double th = ORC_TWO_PI * turns;
+    g[0] = cos(th);
+    g[1] = sin(th);
+}
+
+/* 3D unit gradient, uniform on the sphere (Archimedes: z uniform on [-1,1]):
+ * z = 1 - (2m+1)/2^24 with m the top 24 bits of the key, azimuth from the second word. */
+void orc_grad3(uint32_t key, double *g)
+{
+    uint32_t m1 = key >> 8;
+    uint32_t m2 = orc_key3_second(key) >> 8;
+    double z = 1.0 - (2.0 * (double)m1 + 1.0) * (1.0 / 16777216.0);
+    double phi = ORC_TWO_PI * ((double)m2 * (1.0 / 16777216.0));
+    double r2 = 1.0 - z * z;
+    double r = sqrt(r2 > 0.0 ? r2 : 0.0);
+    g[0] = r * cos(phi);
+    g[1] = r * sin(phi);
+    g[2] = z;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Coordinate step and octave parameters                                     */
+/* ------------------------------------------------------------------------- */
+
+/* Frequencies f_o = f0 * L^o and amplitudes a_o = p^o, by repeated multiplication. */
+void orc_octave_params(double f0, double lac, double pers, int32_t n, double *freq, double *amp)
+{
+    double f = f0, a = 1.0;
+    for (int32_t o = 0; o < n; ++o) {
+        if (freq) freq[o] = f;
+        if (amp) amp[o] = a;
+        f = f * lac;
+        a = a * pers;
+    }
+}
+
+/* Sample centre X + 1/2 in lattice units of frequency f: cell index and local fraction. */
+void orc_coord(int64_t X, double f, int64_t *cell, double *t)
+{
+    double u = ((double)X + 0.5) * f;
+    double c = floor(u);
+    *cell = (int64_t)c;
+    *t = u - c;
+}
+
+/* ------------------------------------------------------------------------- */
+/* 1D Hermite bases on [0,1]                                                 */
+/* ------------------------------------------------------------------------- */
+
+/* Value bases b0[c] (1 at corner c, 0 at the other, zero derivatives up to M at both
+ * ends) and slope bases b1[c] (zero value, unit first derivative at corner c, zero
+ * first derivative at the other end, zero higher derivatives up to M).
+ * Cubic (M=1): b0[1] = S3 = 3t^2 - 2t^3 (Sec. 3.2), b1[0] = t(1-t)^2, b1[1] = -t^2(1-t).
+ * Quintic (M=2): b0[1] = S5 = 6t^5 - 15t^4 + 10t^3 (Sec. 5.1),
+ *   b1[0] = t - 6t^3 + 8t^4 - 3t^5, b1[1] = -4t^3 + 7t^4 - 3t^5. */
+void orc_basis(int32_t smooth, double t, double *b0, double *b1)
+{
+    double t2 = t * t, t3 = t2 * t;
+    if (smooth == 1) {
+        double s = 3.0 * t2 - 2.0 * t3;
+        b0[0] = 1.0 - s;
+        b0[1] = s;
+        b1[0] = t * (1.0 - t) * (1.0 - t);
+        b1[1] = -t2 * (1.0 - t);
+    } else {
+        double t4 = t3 * t, t5 = t4 * t;
+        double s = 6.0 * t5 - 15.0 * t4 + 10.0 * t3;
+        b0[0] = 1.0 - s;
+        b0[1] = s;
+        b1[0] = t - 6.0 * t3 + 8.0 * t4 - 3.0 * t5;
+        b1[1] = -4.0 * t3 + 7.0 * t4 - 3.0 * t5;
+    }
+}
+
+/* Monomial coefficients of the same bases: bases[k][e] is the coefficient of t^e,
+ * k = 0: b0[0], 1: b0[1], 2: b1[0], 3: b1[1]; degree n = 2M+1. */
+static void orc_basis_monomials(int32_t smooth, double bases[4][6])
+{
+    memset(bases, 0, sizeof(double) * 24);
+    if (smooth == 1) {
+        /* 1 - 3t^2 + 2t^3 */
+        bases[0][0] = 1.0; bases[0][2] = -3.0; bases[0][3] = 2.0;
+        /* 3t^2 - 2t^3 */
+        bases[1][2] = 3.0; bases[1][3] = -2.0;
+        /* t - 2t^2 + t^3 */
+        bases[2][1] = 1.0; bases[2][2] = -2.0; bases[2][3] = 1.0;
+        /* -t^2 + t^3 */
+        bases[3][2] = -1.0; bases[3][3] = 1.0;
+    } else {
+        /* 1 - 10t^3 + 15t^4 - 6t^5 */
+        bases[0][0] = 1.0; bases[0][3] = -10.0; bases[0][4] = 15.0; bases[0][5] = -6.0;
+        /* 10t^3 - 15t^4 + 6t^5 */
+        bases[1][3] = 10.0; bases[1][4] = -15.0; bases[1][5] = 6.0;
+        /* t - 6t^3 + 8t^4 - 3t^5 */
+        bases[2][1] = 1.0; bases[2][3] = -6.0; bases[2][4] = 8.0; bases[2][5] = -3.0;
+        /* -4t^3 + 7t^4 - 3t^5 */
+        bases[3][3] = -4.0; bases[3][4] = 7.0; bases[3][5] = -3.0;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* One cell                                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* 2D cell: corners are indexed c = cx + 2*cy, grad[2*c + a] is component a (0 = x,
+ * 1 = y) of the gradient at corner c.
+ * h = sum_c [ gx_c * b1[cx](tx) * b0[cy](ty) + gy_c * b0[cx](tx) * b1[cy](ty) ]. */
+double orc_cell_2d(int32_t smooth, const double *grad, double tx, double ty)
+{
+    double bx0[2], bx1[2], by0[2], by1[2];
+    orc_basis(smooth, tx, bx0, bx1);
+    orc_basis(smooth, ty, by0, by1);
+    double h = 0.0;
+    for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+            int c = cx + 2 * cy;
+            h += grad[2 * c + 0] * bx1[cx] * by0[cy];
+            h += grad[2 * c + 1] * bx0[cx] * by1[cy];
+        }
+    return h;
+}
+
+/* 3D cell: corner c = cx + 2*cy + 4*cz, grad[3*c + a]. */
+double orc_cell_3d(int32_t smooth, const double *grad, double tx, double ty, double tz)
+{
+    double b0[3][2], b1[3][2];
+    orc_basis(smooth, tx, b0[0], b1[0]);
+    orc_basis(smooth, ty, b0[1], b1[1]);
+    orc_basis(smooth, tz, b0[2], b1[2]);
+    double h = 0.0;
+    for (int cz = 0; cz < 2; ++cz)
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+                int c = cx + 2 * cy + 4 * cz;
+                h += grad[3 * c + 0] * b1[0][cx] * b0[1][cy] * b0[2][cz];
+                h += grad[3 * c + 1] * b0[0][cx] * b1[1][cy] * b0[2][cz];
+                h += grad[3 * c + 2] * b0[0][cx] * b0[1][cy] * b1[2][cz];
+            }
+    return h;
+}
+
+/* Monomial coefficients c[i*(n+1) + j] of x^i y^j (eq. polynomial, D = 2) obtained by
+ * expanding the Hermite form above. */
+void orc_coeffs_2d(int32_t smooth, const double *grad, double *c)
+{
+    double B[4][6];
+    orc_basis_monomials(smooth, B);
+    int n1 = 2 * smooth + 2;
+    memset(c, 0, sizeof(double) * (size_t)(n1 * n1));
+    for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+            int k = cx + 2 * cy;
+            double gx = grad[2 * k + 0], gy = grad[2 * k + 1];
+            for (int i = 0; i < n1; ++i)
+                for (int j = 0; j < n1; ++j) {
+                    /* x-slope basis of corner cx times y-value basis of corner cy */
+                    c[i * n1 + j] += gx * B[2 + cx][i] * B[cy][j];
+                    c[i * n1 + j] += gy * B[cx][i] * B[2 + cy][j];
+                }
+        }
+}
+
+/* Monomial coefficients c[(i*(n+1) + j)*(n+1) + k] of x^i y^j z^k (D = 3). */
+void orc_coeffs_3d(int32_t smooth, const double *grad, double *c)
+{
+    double B[4][6];
+    orc_basis_monomials(smooth, B);
+    int n1 = 2 * smooth + 2;
+    memset(c, 0, sizeof(double) * (size_t)(n1 * n1 * n1));
+    for (int cz = 0; cz < 2; ++cz)
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+                int q = cx + 2 * cy + 4 * cz;
+                double gx = grad[3 * q + 0], gy = grad[3 * q + 1], gz = grad[3 * q + 2];
+                for (int i = 0; i < n1; ++i)
+                    for (int j = 0; j < n1; ++j)
+                        for (int k = 0; k < n1; ++k) {
+                            double *dst = &c[(i * n1 + j) * n1 + k];
+                            *dst += gx * B[2 + cx][i] * B[cy][j] * B[cz][k];
+                            *dst += gy * B[cx][i] * B[2 + cy][j] * B[cz][k];
+                            *dst += gz * B[cx][i] * B[cy][j] * B[2 + cz][k];
+                        }
+            }
+}
+
+/* Perlin's polynomial (Sec. 3.2) on one cell, fade S3 (order 3) or S5 (order 5):
+ * v_ij = f_ij (x - i) + g_ij (y - j); h0 = v00 + S(x)(v10 - v00);
+ * h1 = v01 + S(x)(v11 - v01); h = h0 + S(y)(h1 - h0).  Same corner indexing as above. */
+double orc_perlin_cell(int32_t fade_order, const double *grad, double x, double y)
+{
+    double v[4];
+    for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+            int c = cx + 2 * cy;
+            v[c] = grad[2 * c] * (x - cx) + grad[2 * c + 1] * (y - cy);
+        }
+    double sx, sy;
+    if (fade_order == 5) {
+        sx = 6.0 * pow(x, 5) - 15.0 * pow(x, 4) + 10.0 * pow(x, 3);
+        sy = 6.0 * pow(y, 5) - 15.0 * pow(y, 4) + 10.0 * pow(y, 3);
+    } else {
+        sx = 3.0 * x * x - 2.0 * x * x * x;
+        sy = 3.0 * y * y - 2.0 * y * y * y;
+    }
+    double h0 = v[0] + sx * (v[1] - v[0]);
+    double h1 = v[2] + sx * (v[3] - v[2]);
+    return h0 + sy * (h1 - h0);
+}
+
+/* ------------------------------------------------------------------------- */
+/* fBm over samples                                                          */
+/* ------------------------------------------------------------------------- */
+
+static int orc_check(int32_t smooth, int32_t octaves, double f0, double lac, double pers)
+{
+    if (smooth != 1 && smooth != 2) return ORC_EINVAL;
+    if (octaves < 1 || octaves > ORC_MAX_OCTAVES) return ORC_EINVAL;
+    if (!(f0 > 0.0) || !(lac > 0.0) || !(pers > 0.0)) return ORC_EINVAL;
+    if (!isfinite(f0) || !isfinite(lac) || !isfinite(pers)) return ORC_EINVAL;
+    return ORC_OK;
+}
+
+/* H at one 2D sample (X, Y): sum over octaves o of p^o * h_o, in octave order. */
+static double orc_sample_2d(int32_t smooth, int32_t octaves, const double *freq, const double *amp,
+                            uint32_t seed, int64_t X, int64_t Y)
+{
+    double H = 0.0;
+    for (int32_t o = 0; o < octaves; ++o) {
+        int64_t cx, cy;
+        double tx, ty, grad[8];
+        orc_coord(X, freq[o], &cx, &tx);
+        orc_coord(Y, freq[o], &cy, &ty);
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx)
+                orc_grad2(orc_key2(cx + dx, cy + dy, o, seed), &grad[2 * (dx + 2 * dy)]);
+        H += amp[o] * orc_cell_2d(smooth, grad, tx, ty);
+    }
+    return H;
+}
+
+static double orc_sample_3d(int32_t smooth, int32_t octaves, const double *freq, const double *amp,
+                            uint32_t seed, int64_t X, int64_t Y, int64_t Z)
+{
+    double H = 0.0;
+    for (int32_t o = 0; o < octaves; ++o) {
+        int64_t cx, cy, cz;
+        double tx, ty, tz, grad[24];
+        orc_coord(X, freq[o], &cx, &tx);
+        orc_coord(Y, freq[o], &cy, &ty);
+        orc_coord(Z, freq[o], &cz, &tz);
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx)
+                    orc_grad3(orc_key3(cx + dx, cy + dy, cz + dz, o, seed),
+                              &grad[3 * (dx + 2 * dy + 4 * dz)]);
+        H += amp[o] * orc_cell_3d(smooth, grad, tx, ty, tz);
+    }
+    return H;
+}
+
+static void orc_set_threads(int32_t nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+/* Row-major [ny][nx] field; sample (i, j) is world (x0 + i, y0 + j). */
+int orc_fbm_2d(int32_t smooth, int32_t octaves, double pers, double lac, double f0, uint32_t seed,
+               int64_t x0, int64_t y0, int64_t nx, int64_t ny, double *out, int32_t nthreads)
+{
+    if (orc_check(smooth, octaves, f0, lac, pers) != ORC_OK || nx < 0 || ny < 0 || !out)
+        return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i)
+            out[j * nx + i] = orc_sample_2d(smooth, octaves, freq, amp, seed, x0 + i, y0 + j);
+    return ORC_OK;
+}
+
+/* Row-major [nz][ny][nx] volume. */
+int orc_fbm_3d(int32_t smooth, int32_t octaves, double pers, double lac, double f0, uint32_t seed,
+               int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz, double *out,
+               int32_t nthreads)
+{
+    if (orc_check(smooth, octaves, f0, lac, pers) != ORC_OK || nx < 0 || ny < 0 || nz < 0 || !out)
+        return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+    int64_t lines = ny * nz;
+#pragma omp parallel for schedule(static)
+    for (int64_t l = 0; l < lines; ++l) {
+        int64_t j = l % ny, k = l / ny;
+        for (int64_t i = 0; i < nx; ++i)
+            out[l * nx + i] = orc_sample_3d(smooth, octaves, freq, amp, seed, x0 + i, y0 + j, z0 + k);
+    }
+    return ORC_OK;
+}
+
+/* The same sum at an explicit list of world samples (for sampled checks of large fields). */
+int orc_fbm_points_2d(int32_t smooth, int32_t octaves, double pers, double lac, double f0,
+                      uint32_t seed, const int64_t *X, const int64_t *Y, int64_t n, double *out,
+                      int32_t nthreads)
+{
+    if (orc_check(smooth, octaves, f0, lac, pers) != ORC_OK || n < 0 || !X || !Y || !out)
+        return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q)
+        out[q] = orc_sample_2d(smooth, octaves, freq, amp, seed, X[q], Y[q]);
+    return ORC_OK;
+}
+
+int orc_fbm_points_3d(int32_t smooth, int32_t octaves, double pers, double lac, double f0,
+                      uint32_t seed, const int64_t *X, const int64_t *Y, const int64_t *Z, int64_t n,
+                      double *out, int32_t nthreads)
+{
+    if (orc_check(smooth, octaves, f0, lac, pers) != ORC_OK || n < 0 || !X || !Y || !Z || !out)
+        return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q)
+        out[q] = orc_sample_3d(smooth, octaves, freq, amp, seed, X[q], Y[q], Z[q]);
+    return ORC_OK;
+}
+
+/* Perlin fBm (comparison path, Sec. 3.2) over a 2D field with the same lattice, octave
+ * and coordinate conventions. */
+int orc_perlin_2d(int32_t fade_order, int32_t octaves, double pers, double lac, double f0,
+                  uint32_t seed, int64_t x0, int64_t y0, int64_t nx, int64_t ny, double *out,
+                  int32_t nthreads)
+{
+    if ((fade_order != 3 && fade_order != 5) || orc_check(1, octaves, f0, lac, pers) != ORC_OK ||
+        nx < 0 || ny < 0 || !out)
+        return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i) {
+            double H = 0.0;
+            for (int32_t o = 0; o < octaves; ++o) {
+                int64_t cx, cy;
+                double tx, ty, grad[8];
+                orc_coord(x0 + i, freq[o], &cx, &tx);
+                orc_coord(y0 + j, freq[o], &cy, &ty);
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx)
+                        orc_grad2(orc_key2(cx + dx, cy + dy, o, seed), &grad[2 * (dx + 2 * dy)]);
+                H += amp[o] * orc_perlin_cell(fade_order, grad, tx, ty);
+            }
+            out[j * nx + i] = H;
+        }
+    return ORC_OK;
+}
+
+/* Number of OpenMP threads a parallel region would use (reported with timings). */
+int32_t orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
