@@ -1,0 +1,168 @@
+/*
+ * ptg.h -- C ABI of libptg: polynomial gradient-noise fBm on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Thorimbert & Chopard, "Polynomial methods for fast Procedural Terrain
+ * Generation" (arXiv:1610.03525).  Per octave the library
+ *   a1. maps every sample to a lattice cell and a local fraction (FP64 coordinate step),
+ *   a2. hashes the lattice nodes to unit gradients (K1),
+ *   a3. forms each cell's boundary-constrained polynomial from its corner gradients (K2;
+ *       Sec. 2, eqs. mixedderiv / independance / polynomial; Sec. 3.1, 3.4),
+ *   a4. evaluates that polynomial at every sample (K3), and
+ *   a5. accumulates the octaves with amplitude p^o and frequency f0 * L^o (Sec. 4).
+ *
+ * Conventions (the readings taken where the paper is silent):
+ *   - Cell polynomial: tensor polynomial of degree n = 2M+1 per axis (M = smoothness)
+ *     whose value is 0 at each corner, whose gradient equals the corner's lattice
+ *     gradient, and whose other mixed derivatives h^d, 0 <= d_k <= M, are 0.  M = 1 gives
+ *     C1 cubic cells (D2M1N3 / D3M1N3 with zero twist), M = 2 C2 quintic cells.
+ *   - Octave o = 0..N-1: frequency f_o = base_freq * lacunarity^o and amplitude
+ *     a_o = persistence^o, each by repeated FP64 multiplication; no normalisation.
+ *   - Sample at int64 world index X sits at X + 1/2: u = (X + 1/2) * f_o (FP64),
+ *     cell = floor(u), fraction t = u - cell rounded to FP32.
+ *   - Lattice hash (all arithmetic mod 2^32), fmix32 = MurmurHash3 finalizer:
+ *       prefix  = fmix32(fmix32(seed ^ 0x9E3779B9) ^ octave)
+ *       line(k, i) = fmix32(fmix32(k ^ lo32(i)) ^ hi32(i))      (i as two's complement)
+ *       key2    = fmix32(line(prefix, iy) ^ line(0x27D4EB2F, ix))
+ *       key3    = fmix32(line(line(prefix, iz), iy) ^ line(0x27D4EB2F, ix))
+ *       second3 = fmix32(key3 ^ 0x165667B1)
+ *     2D gradient: angle 2*pi*(key >> 8)/2^24.  3D gradient: z = 1 - (2*(key>>8)+1)/2^24,
+ *     azimuth 2*pi*(second3 >> 8)/2^24, radius sqrt(1 - z^2).
+ *
+ * Memory: every `void *` buffer argument named *_dev is device memory (e.g. a torch CUDA
+ * tensor's data_ptr on ROCm) owned by the caller; `stream` is a hipStream_t (NULL = the
+ * default stream).  Calls are asynchronous on that stream unless stated otherwise.
+ * Errors: every entry point returns PTG_OK (0) or a negative PTG_E* code.  All argument
+ * checks happen before any launch, so a rejected call writes nothing.  The message of
+ * the last failure on the calling thread is returned by ptg_last_error().  No C++
+ * exception crosses this interface.
+ */
+#ifndef PTG_H
+#define PTG_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define PTG_API __attribute__((visibility("default")))
+#else
+#define PTG_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------ */
+#define PTG_OK 0
+#define PTG_EINVAL (-1)     /* an argument is out of range or a pointer is NULL        */
+#define PTG_ENOMEM (-2)     /* a device or host allocation failed                      */
+#define PTG_E2BIG (-3)      /* a request is larger than the whole serving budget       */
+#define PTG_EAGAIN (-4)     /* non-blocking submit: no room now                        */
+#define PTG_ETIMEDOUT (-5)  /* wait timed out; the request is still pending            */
+#define PTG_ESHUTDOWN (-6)  /* server is shutting down / was destroyed                 */
+#define PTG_EHIP (-7)       /* a HIP runtime call failed (text in ptg_last_error)      */
+#define PTG_ENOENT (-8)     /* unknown or already released ticket                      */
+
+/* ---- limits ------------------------------------------------------------------ */
+#define PTG_MAX_OCTAVES 16
+/* |world index| + extent must stay below 2^52 so X + 1/2 is exact in FP64 */
+#define PTG_MAX_WORLD_ABS 4503599627370496LL
+
+/* ---- output element types ---------------------------------------------------- */
+#define PTG_F32 0
+#define PTG_F16 1
+
+/* ---- evaluation forms -------------------------------------------------------- */
+#define PTG_FORM_PLAIN 0      /* FP32 VALU evaluation, any parameters                  */
+#define PTG_FORM_MFMA_F16 1   /* 2D only: V_x C V_y^T on FP16 MFMA, FP32 accumulate    */
+#define PTG_FORM_MFMA_BF16 2  /* 2D only: same on BF16 MFMA                            */
+
+/* ---- bases for the MFMA forms (Vandermonde rows fed to the matrix cores) ------ */
+#define PTG_BASIS_MONOMIAL 0  /* V(t) = [1, t, t^2, t^3], C = monomial coefficients   */
+#define PTG_BASIS_CENTRED 1   /* V(t) = [1, s, s^2, s^3] with s = t - 1/2              */
+
+/* Problem parameters (Sec. 2.2 DdMmNn naming: dim = d, smoothness = m, n = 2m+1;
+ * Sec. 4: octaves, persistence, lacunarity). */
+typedef struct ptg_params {
+    int32_t dim;          /* 2 or 3                                                    */
+    int32_t smoothness;   /* 1 = C1 cubic cells, 2 = C2 quintic cells                  */
+    int32_t octaves;      /* 1 .. PTG_MAX_OCTAVES                                      */
+    int32_t out_dtype;    /* PTG_F32 or PTG_F16                                        */
+    double persistence;   /* amplitude ratio per octave, finite, > 0                   */
+    double lacunarity;    /* frequency ratio per octave, finite, > 0                   */
+    double base_freq;     /* lattice cells per sample at octave 0, finite, > 0; every  */
+                          /* octave's frequency must be <= 1 cell per sample           */
+    uint32_t seed;        /* lattice seed                                              */
+    int32_t form;         /* PTG_FORM_*                                                */
+    int32_t basis;        /* PTG_BASIS_* (MFMA forms only)                             */
+    int32_t reserved;     /* must be 0                                                 */
+} ptg_params;
+
+/* Library version string (static storage). */
+PTG_API const char *ptg_version(void);
+
+/* Message of the last failing call on this thread ("" if none).  Thread-local storage,
+ * valid until the next failing call on the same thread. */
+PTG_API const char *ptg_last_error(void);
+
+/* Fill a ptg_params with the defaults: dim 2, smoothness 1, 8 octaves, persistence 0.5,
+ * lacunarity 2, base_freq 1/512, seed 1, FP32, plain form. */
+PTG_API void ptg_params_default(ptg_params *p);
+
+/* ---- a1-a5: dense fields ----------------------------------------------------- */
+
+/* 2D fBm heightmap H(X, Y) = sum_o a_o h_o((X+1/2) f_o, (Y+1/2) f_o) for the samples
+ * X = x0 + i, Y = y0 + j, 0 <= i < nx, 0 <= j < ny (Sec. 4 octave sum of Sec. 2 cells).
+ * out_dev: device buffer of element type p->out_dtype, row-major; sample (i, j) at
+ *   out_dev[j * row_pitch + i]; row_pitch >= nx (elements).  nx or ny == 0 is a no-op.
+ * p->dim must be 2.  Asynchronous on `stream`.
+ * Errors: PTG_EINVAL (bad parameters, NULL out_dev with a non-empty field, |x0|, |x0+nx|,
+ *   |y0| or |y0+ny| >= PTG_MAX_WORLD_ABS, an MFMA form with smoothness 2 or dim 3),
+ *   PTG_ENOMEM (workspace), PTG_EHIP (launch failure). */
+PTG_API int ptg_fbm_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny,
+               void *out_dev, int64_t row_pitch, void *stream);
+
+/* 3D fBm volume over X = x0+i, Y = y0+j, Z = z0+k; out_dev dense row-major
+ * [nz][ny][nx] of p->out_dtype (D3M1N3 / D3M2N5 cells, Sec. 3.4).  p->dim must be 3 and
+ * p->form PTG_FORM_PLAIN.  Errors as ptg_fbm_2d. */
+PTG_API int ptg_fbm_3d(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny,
+               int64_t nz, void *out_dev, void *stream);
+
+/* ---- stage entry points (the same device code the fields run, exposed per stage) */
+
+/* a1. Coordinate step for n consecutive world samples x0 .. x0+n-1 and octaves
+ * 0 .. octaves-1 of (base_freq, lacunarity): cells_dev[o*n + i] (int64) and
+ * frac_dev[o*n + i] (float).  Errors: PTG_EINVAL, PTG_EHIP. */
+PTG_API int ptg_coords(double base_freq, double lacunarity, int32_t octaves, int64_t x0, int64_t n,
+               int64_t *cells_dev, float *frac_dev, void *stream);
+
+/* a2. K1 lattice kernel, 2D: for the node box ix0 <= ix < ix0+nx, iy0 <= iy < iy0+ny of
+ * octave `octave`: keys_dev[j*nx + i] (uint32, may be NULL) and the unit gradient,
+ * SoA: grad_dev[j*nx + i] = x component, grad_dev[nx*ny + j*nx + i] = y component
+ * (may be NULL).  Errors: PTG_EINVAL (negative sizes, octave < 0), PTG_EHIP. */
+PTG_API int ptg_lattice_2d(uint32_t seed, int32_t octave, int64_t ix0, int64_t iy0, int64_t nx,
+                   int64_t ny, uint32_t *keys_dev, float *grad_dev, void *stream);
+
+/* a2. K1, 3D: node box of nx*ny*nz nodes, index q = (k*ny + j)*nx + i; keys_dev[q],
+ * second words second_dev[q] (may be NULL), gradients SoA grad_dev[c*nx*ny*nz + q]. */
+PTG_API int ptg_lattice_3d(uint32_t seed, int32_t octave, int64_t ix0, int64_t iy0, int64_t iz0,
+                   int64_t nx, int64_t ny, int64_t nz, uint32_t *keys_dev, uint32_t *second_dev,
+                   float *grad_dev, void *stream);
+
+/* a3. K2 per-cell coefficient kernel, 2D: from a node-gradient box in the layout K1
+ * writes (nnx*nny nodes, SoA), the monomial coefficients c_ij of h = sum c_ij x^i y^j
+ * (eq. polynomial, D = 2, n = 2*smoothness+1) of every cell of the box:
+ * coeff_dev[(cj*(nnx-1) + ci)*(n+1)^2 + i*(n+1) + j], scaled by `amplitude`.
+ * Each workgroup stages its corner gradients in LDS.  nnx, nny >= 2.
+ * Errors: PTG_EINVAL, PTG_EHIP. */
+PTG_API int ptg_cells_2d(int32_t smoothness, const float *grad_dev, int64_t nnx, int64_t nny,
+                 float amplitude, float *coeff_dev, void *stream);
+
+/* a3. K2, 3D: coefficient c_ijk of x^i y^j z^k at
+ * coeff_dev[cell*(n+1)^3 + (i*(n+1) + j)*(n+1) + k], cell = (ck*(nny-1) + cj)*(nnx-1) + ci. */
+PTG_API int ptg_cells_3d(int32_t smoothness, const float *grad_dev, int64_t nnx, int64_t nny,
+                 int64_t nnz, float amplitude, float *coeff_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTG_H */

@@ -1,0 +1,224 @@
+"""paper_1610_03525_amd -- Python binding of libptg (polynomial gradient-noise fBm on MI355X).
+
+Argument marshalling only: tensors become device pointers, the current torch stream
+becomes the hipStream_t, and every step of the computation runs in the HIP kernels of
+``libptg.so`` (C ABI in ``include/ptg.h``).  There is no CPU fallback: if the library
+is not built, every call raises ``RuntimeError``.
+
+Method: Thorimbert & Chopard, "Polynomial methods for fast Procedural Terrain Generation"
+(arXiv:1610.03525) -- boundary-constrained cell polynomials (Sec. 2, Sec. 3.4) summed over
+fBm octaves (Sec. 4).
+"""
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libptg.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "ptg.h")
+
+PTG_OK = 0
+PTG_EINVAL = -1
+PTG_ENOMEM = -2
+PTG_E2BIG = -3
+PTG_EAGAIN = -4
+PTG_ETIMEDOUT = -5
+PTG_ESHUTDOWN = -6
+PTG_EHIP = -7
+PTG_ENOENT = -8
+
+PTG_F32 = 0
+PTG_F16 = 1
+FORMS = {"plain": 0, "mfma_f16": 1, "mfma_bf16": 2}
+BASES = {"monomial": 0, "centred": 1}
+
+
+class PtgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ptg error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("smoothness", ctypes.c_int32),
+        ("octaves", ctypes.c_int32),
+        ("out_dtype", ctypes.c_int32),
+        ("persistence", ctypes.c_double),
+        ("lacunarity", ctypes.c_double),
+        ("base_freq", ctypes.c_double),
+        ("seed", ctypes.c_uint32),
+        ("form", ctypes.c_int32),
+        ("basis", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+_LIB = None
+_i32, _u32, _i64, _f32, _f64 = ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
+_vp = ctypes.c_void_p
+_PP = ctypes.POINTER(Params)
+
+
+def lib():
+    """The loaded libptg.so; raises RuntimeError when it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.ptg_version.restype = ctypes.c_char_p
+    L.ptg_last_error.restype = ctypes.c_char_p
+    L.ptg_params_default.argtypes = [_PP]
+    L.ptg_fbm_2d.argtypes = [_PP, _i64, _i64, _i64, _i64, _vp, _i64, _vp]
+    L.ptg_fbm_3d.argtypes = [_PP, _i64, _i64, _i64, _i64, _i64, _i64, _vp, _vp]
+    L.ptg_coords.argtypes = [_f64, _f64, _i32, _i64, _i64, _vp, _vp, _vp]
+    L.ptg_lattice_2d.argtypes = [_u32, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _vp]
+    L.ptg_lattice_3d.argtypes = [_u32, _i32, _i64, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp]
+    L.ptg_cells_2d.argtypes = [_i32, _vp, _i64, _i64, _f32, _vp, _vp]
+    L.ptg_cells_3d.argtypes = [_i32, _vp, _i64, _i64, _i64, _f32, _vp, _vp]
+    for name in ("ptg_fbm_2d", "ptg_fbm_3d", "ptg_coords", "ptg_lattice_2d", "ptg_lattice_3d",
+                 "ptg_cells_2d", "ptg_cells_3d"):
+        getattr(L, name).restype = _i32
+    _LIB = L
+    return L
+
+
+def declared_symbols():
+    """Names of the functions include/ptg.h declares (PTG_API prototypes)."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"PTG_API\s+[\w\s\*]*?\b(ptg_\w+)\s*\(", text)))
+
+
+def last_error() -> str:
+    return lib().ptg_last_error().decode()
+
+
+def _check(rc):
+    if rc != PTG_OK:
+        raise PtgError(rc, last_error())
+
+
+def params(dim=2, smoothness=1, octaves=8, persistence=0.5, lacunarity=2.0, base_freq=1.0 / 512, seed=1,
+           out_dtype=PTG_F32, form="plain", basis="monomial") -> Params:
+    p = Params()
+    p.dim = dim
+    p.smoothness = smoothness
+    p.octaves = octaves
+    p.out_dtype = out_dtype
+    p.persistence = persistence
+    p.lacunarity = lacunarity
+    p.base_freq = base_freq
+    p.seed = seed & 0xFFFFFFFF
+    p.form = FORMS[form] if isinstance(form, str) else int(form)
+    p.basis = BASES[basis] if isinstance(basis, str) else int(basis)
+    p.reserved = 0
+    return p
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev_ptr(t, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device (cuda) torch tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _out_dtype(t):
+    import torch
+    if t.dtype == torch.float32:
+        return PTG_F32
+    if t.dtype == torch.float16:
+        return PTG_F16
+    raise TypeError("output must be float32 or float16")
+
+
+# ---- dense fields -------------------------------------------------------------------
+
+def fbm_2d_raw(p: Params, x0, y0, nx, ny, out_ptr, pitch, stream_handle):
+    _check(lib().ptg_fbm_2d(ctypes.byref(p), x0, y0, nx, ny, out_ptr, pitch, stream_handle))
+
+
+def fbm_3d_raw(p: Params, x0, y0, z0, nx, ny, nz, out_ptr, stream_handle):
+    _check(lib().ptg_fbm_3d(ctypes.byref(p), x0, y0, z0, nx, ny, nz, out_ptr, stream_handle))
+
+
+def fbm_2d(out, *, x0=0, y0=0, stream=None, **kw):
+    """Fill a 2D (ny, nx) float32/float16 device tensor (row stride >= nx) with the fBm field
+    whose element (j, i) is world sample (x0 + i, y0 + j)."""
+    if out.dim() != 2 or out.stride(1) != 1:
+        raise ValueError("out must be 2D with unit column stride")
+    p = params(dim=2, out_dtype=_out_dtype(out), **kw)
+    ny, nx = out.shape
+    fbm_2d_raw(p, x0, y0, nx, ny, _dev_ptr(out) if out.numel() else None, out.stride(0), _stream(stream))
+    return out
+
+
+def fbm_3d(out, *, x0=0, y0=0, z0=0, stream=None, **kw):
+    """Fill a contiguous (nz, ny, nx) device tensor with the 3D fBm volume."""
+    if out.dim() != 3 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous 3D tensor")
+    p = params(dim=3, out_dtype=_out_dtype(out), **kw)
+    nz, ny, nx = out.shape
+    fbm_3d_raw(p, x0, y0, z0, nx, ny, nz, _dev_ptr(out) if out.numel() else None, _stream(stream))
+    return out
+
+
+# ---- stages -------------------------------------------------------------------------
+
+def coords(base_freq, lacunarity, octaves, x0, cells_out, frac_out, stream=None):
+    """a1: cells_out (octaves, n) int64 and frac_out (octaves, n) float32 device tensors."""
+    import torch
+    n = cells_out.shape[1]
+    _check(lib().ptg_coords(base_freq, lacunarity, octaves, x0, n, _dev_ptr(cells_out, torch.int64),
+                            _dev_ptr(frac_out, torch.float32), _stream(stream)))
+
+
+def lattice_2d(seed, octave, ix0, iy0, keys_out=None, grad_out=None, stream=None):
+    """K1: keys_out (ny, nx) int32 tensor (uint32 bits) and/or grad_out (2, ny, nx) float32."""
+    import torch
+    ref = keys_out if keys_out is not None else grad_out[0]
+    ny, nx = ref.shape
+    kp = _dev_ptr(keys_out, torch.int32) if keys_out is not None else None
+    gp = _dev_ptr(grad_out, torch.float32) if grad_out is not None else None
+    _check(lib().ptg_lattice_2d(seed & 0xFFFFFFFF, octave, ix0, iy0, nx, ny, kp, gp, _stream(stream)))
+
+
+def lattice_3d(seed, octave, ix0, iy0, iz0, keys_out=None, second_out=None, grad_out=None, stream=None):
+    import torch
+    ref = keys_out if keys_out is not None else (second_out if second_out is not None else grad_out[0])
+    nz, ny, nx = ref.shape
+    kp = _dev_ptr(keys_out, torch.int32) if keys_out is not None else None
+    sp = _dev_ptr(second_out, torch.int32) if second_out is not None else None
+    gp = _dev_ptr(grad_out, torch.float32) if grad_out is not None else None
+    _check(lib().ptg_lattice_3d(seed & 0xFFFFFFFF, octave, ix0, iy0, iz0, nx, ny, nz, kp, sp, gp, _stream(stream)))
+
+
+def cells_2d(smoothness, grad, amplitude, coeff_out, stream=None):
+    """K2: grad (2, nny, nnx) float32 -> coeff_out (nny-1, nnx-1, n+1, n+1) float32."""
+    import torch
+    _, nny, nnx = grad.shape
+    _check(lib().ptg_cells_2d(smoothness, _dev_ptr(grad, torch.float32), nnx, nny, amplitude,
+                              _dev_ptr(coeff_out, torch.float32), _stream(stream)))
+
+
+def cells_3d(smoothness, grad, amplitude, coeff_out, stream=None):
+    import torch
+    _, nnz, nny, nnx = grad.shape
+    _check(lib().ptg_cells_3d(smoothness, _dev_ptr(grad, torch.float32), nnx, nny, nnz, amplitude,
+                              _dev_ptr(coeff_out, torch.float32), _stream(stream)))
+
+
+def version() -> str:
+    return lib().ptg_version().decode()

@@ -1,0 +1,58 @@
+// ptg_launch.h -- host-side launch descriptors shared by the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ptg {
+
+constexpr int kMaxOctaves = 16;
+
+// Dense 2D field, general (any-parameter) K3: 64 x 64 sample tiles, 256 threads.
+constexpr int kTile2 = 64;
+// Dense 3D field, general K3: 64 x 8 x 8 sample tiles, 256 threads.
+constexpr int kTile3X = 64;
+constexpr int kTile3Y = 8;
+constexpr int kTile3Z = 8;
+
+struct Fbm2dArgs {
+    int64_t x0, y0, nx, ny, pitch;
+    void *out;
+    double freq[kMaxOctaves];
+    float amp[kMaxOctaves];
+    int32_t octaves;
+    uint32_t seed;
+    int32_t capx, capy;  // LDS footprint capacity (nodes per axis) for every octave
+    int32_t tiles_x;     // tiles per row of the tile grid
+    int32_t pad;
+};
+
+struct Fbm3dArgs {
+    int64_t x0, y0, z0, nx, ny, nz;
+    void *out;
+    double freq[kMaxOctaves];
+    float amp[kMaxOctaves];
+    int32_t octaves;
+    uint32_t seed;
+    int32_t capx, capy, capz;
+    int32_t tiles_x, tiles_y;
+    int32_t pad;
+};
+
+// Launch wrappers (defined in the .hip translation units).  They assume validated
+// arguments and return the HIP status of the launch.
+hipError_t launch_fbm2d_general(const Fbm2dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
+hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
+
+hipError_t launch_coords(double f0, double lac, int octaves, int64_t x0, int64_t n, int64_t *cells, float *frac,
+                         hipStream_t s);
+hipError_t launch_lattice2d(uint32_t seed, int octave, int64_t ix0, int64_t iy0, int64_t nx, int64_t ny,
+                            uint32_t *keys, float *grad, hipStream_t s);
+hipError_t launch_lattice3d(uint32_t seed, int octave, int64_t ix0, int64_t iy0, int64_t iz0, int64_t nx,
+                            int64_t ny, int64_t nz, uint32_t *keys, uint32_t *second, float *grad, hipStream_t s);
+hipError_t launch_cells2d(int smooth, const float *grad, int64_t nnx, int64_t nny, float amp, float *coeff,
+                          hipStream_t s);
+hipError_t launch_cells3d(int smooth, const float *grad, int64_t nnx, int64_t nny, int64_t nnz, float amp,
+                          float *coeff, hipStream_t s);
+
+}  // namespace ptg

@@ -1,0 +1,283 @@
+"""GPU parity: every stage of the HIP path against the FP64 oracle, through the C ABI.
+
+Bar (fixed in advance from the arithmetic):
+* coordinate step: int64 cells bit-exact, FP32 fractions equal to the oracle's FP64
+  fraction rounded to FP32 (same FP64 operations on both sides);
+* lattice: uint32 keys bit-exact; gradients within 2^-20 of the FP64 map;
+* per-cell coefficients: within 2e-6 * (sum of |terms|) of the FP64 expansion;
+* fields: max |H_gpu - H_oracle| <= 1e-5 * A, A = sum_o p^o (total amplitude).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+torch = pytest.importorskip("torch")
+import paper_1610_03525_amd as ptg  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _amp_total(p, n):
+    return sum(p ** o for o in range(n))
+
+
+def _sync():
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------------
+# a1 coordinate step
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("f0,lac,x0", [
+    (1 / 512, 2.0, 0), (1 / 512, 2.0, -3 * 2 ** 20 - 7), (8 / 256, 2.0, 2 ** 33 + 5),
+    (0.013, 1.87, -123456789), (1 / 16384 * 32, 2.0, (2 ** 24 - 3) * 512),
+])
+def test_coords_bit_exact(f0, lac, x0):
+    n, octs = 777, 8
+    cells = torch.empty((octs, n), dtype=torch.int64, device=DEV)
+    frac = torch.empty((octs, n), dtype=torch.float32, device=DEV)
+    ptg.coords(f0, lac, octs, x0, cells, frac)
+    _sync()
+    cells, frac = cells.cpu().numpy(), frac.cpu().numpy()
+    freq, _ = O.octave_params(f0, lac, 0.5, octs)
+    for o in range(octs):
+        for i in range(0, n, 7):
+            c, t = O.coord(x0 + i, freq[o])
+            assert cells[o, i] == c
+            assert frac[o, i] == np.float32(t)
+
+
+# ---------------------------------------------------------------------------------
+# a2 lattice hash (K1)
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,octave,ix0,iy0", [
+    (1, 0, 0, 0), (2, 3, -40, -17), (0xDEADBEEF, 9, -3 * 2 ** 20 - 7, 2 ** 33 + 5),
+    (3, 15, (2 ** 24 - 3), -(2 ** 24 - 5)), (0, 2, -(2 ** 46), 2 ** 46 - 64),
+])
+def test_lattice2d_keys_bit_exact(seed, octave, ix0, iy0):
+    nx, ny = 37, 29
+    keys = torch.empty((ny, nx), dtype=torch.int32, device=DEV)
+    grad = torch.empty((2, ny, nx), dtype=torch.float32, device=DEV)
+    ptg.lattice_2d(seed, octave, ix0, iy0, keys, grad)
+    _sync()
+    k = keys.cpu().numpy().view(np.uint32)
+    g = grad.cpu().numpy()
+    ref = O.keys2_box(ix0, iy0, nx, ny, octave, seed)
+    np.testing.assert_array_equal(k, ref)
+    worst = 0.0
+    for j in range(ny):
+        for i in range(nx):
+            gr = O.grad2(int(ref[j, i]))
+            worst = max(worst, abs(g[0, j, i] - gr[0]), abs(g[1, j, i] - gr[1]))
+    assert worst <= 2 ** -20, worst
+
+
+@pytest.mark.parametrize("seed,octave,ix0,iy0,iz0", [
+    (1, 0, 0, 0, 0), (7, 5, -9, 13, -2 ** 33), (0xFFFFFFFF, 12, 2 ** 40, -(2 ** 40), 77),
+])
+def test_lattice3d_keys_bit_exact(seed, octave, ix0, iy0, iz0):
+    nx, ny, nz = 11, 7, 5
+    keys = torch.empty((nz, ny, nx), dtype=torch.int32, device=DEV)
+    sec = torch.empty((nz, ny, nx), dtype=torch.int32, device=DEV)
+    grad = torch.empty((3, nz, ny, nx), dtype=torch.float32, device=DEV)
+    ptg.lattice_3d(seed, octave, ix0, iy0, iz0, keys, sec, grad)
+    _sync()
+    k = keys.cpu().numpy().view(np.uint32)
+    s = sec.cpu().numpy().view(np.uint32)
+    g = grad.cpu().numpy()
+    ref = O.keys3_box(ix0, iy0, iz0, nx, ny, nz, octave, seed)
+    np.testing.assert_array_equal(k, ref)
+    worst = 0.0
+    for q in np.ndindex(nz, ny, nx):
+        assert s[q] == O.key3_second(int(ref[q]))
+        gr = O.grad3(int(ref[q]))
+        worst = max(worst, max(abs(g[(a,) + q] - gr[a]) for a in range(3)))
+    assert worst <= 2 ** -20, worst
+
+
+# ---------------------------------------------------------------------------------
+# a3 per-cell coefficients (K2)
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("smooth", [1, 2])
+def test_cells2d_against_oracle(smooth):
+    seed, octave, ix0, iy0, nnx, nny = 5, 2, -21, 1000, 35, 19
+    amp = 0.25
+    grad = torch.empty((2, nny, nnx), dtype=torch.float32, device=DEV)
+    ptg.lattice_2d(seed, octave, ix0, iy0, None, grad)
+    n1 = 2 * smooth + 2
+    coeff = torch.empty((nny - 1, nnx - 1, n1, n1), dtype=torch.float32, device=DEV)
+    ptg.cells_2d(smooth, grad, amp, coeff)
+    _sync()
+    c = coeff.cpu().numpy()
+    for cj in range(nny - 1):
+        for ci in range(nnx - 1):
+            g = np.array([O.grad2(O.key2(ix0 + ci + dx, iy0 + cj + dy, octave, seed))
+                          for dy in (0, 1) for dx in (0, 1)])
+            ref = amp * O.coeffs_2d(smooth, g)
+            tol = 2e-6 * amp * (16 if smooth == 1 else 200)
+            assert np.max(np.abs(c[cj, ci] - ref)) <= tol
+
+
+@pytest.mark.parametrize("smooth", [1, 2])
+def test_cells3d_against_oracle(smooth):
+    seed, octave, ix0, iy0, iz0, nn = 9, 1, 3, -4, 5, 6
+    grad = torch.empty((3, nn, nn, nn), dtype=torch.float32, device=DEV)
+    ptg.lattice_3d(seed, octave, ix0, iy0, iz0, None, None, grad)
+    n1 = 2 * smooth + 2
+    coeff = torch.empty((nn - 1, nn - 1, nn - 1, n1, n1, n1), dtype=torch.float32, device=DEV)
+    ptg.cells_3d(smooth, grad, 1.0, coeff)
+    _sync()
+    c = coeff.cpu().numpy()
+    for ck, cj, ci in [(0, 0, 0), (4, 4, 4), (2, 1, 3), (1, 4, 0)]:
+        g = np.array([O.grad3(O.key3(ix0 + ci + dx, iy0 + cj + dy, iz0 + ck + dz, octave, seed))
+                      for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)])
+        ref = O.coeffs_3d(smooth, g)
+        tol = 2e-6 * (64 if smooth == 1 else 3000)
+        assert np.max(np.abs(c[ck, cj, ci] - ref)) <= tol
+
+
+# ---------------------------------------------------------------------------------
+# a1-a5 fields (K3)
+# ---------------------------------------------------------------------------------
+def _gpu_fbm2(nx, ny, x0, y0, dtype=torch.float32, pitch=None, **kw):
+    if pitch is None:
+        out = torch.empty((ny, nx), dtype=dtype, device=DEV)
+    else:
+        out = torch.full((ny, pitch), 7.0, dtype=dtype, device=DEV)[:, :nx]
+    ptg.fbm_2d(out, x0=x0, y0=y0, **kw)
+    _sync()
+    return out
+
+
+@pytest.mark.parametrize("smooth", [1, 2])
+@pytest.mark.parametrize("seed", [1, 2, 3, 0xDEADBEEF])
+@pytest.mark.parametrize("origin", [(0, 0), (-3 * 2 ** 20 - 7, 2 ** 33 + 5)])
+def test_fbm2d_256_4oct_full_field(smooth, seed, origin):
+    """2D 256x256, 4 octaves, base lattice 8x8, L = 2, p = 0.5 (the correctness workload)."""
+    kw = dict(smoothness=smooth, octaves=4, persistence=0.5, lacunarity=2.0, base_freq=8 / 256, seed=seed)
+    g = _gpu_fbm2(256, 256, *origin, **kw).cpu().numpy().astype(np.float64)
+    ref = O.fbm_2d(smooth, 4, 0.5, 2.0, 8 / 256, seed, origin[0], origin[1], 256, 256)
+    err = np.max(np.abs(g - ref))
+    assert err <= 1e-5 * _amp_total(0.5, 4), err
+
+
+@pytest.mark.parametrize("nx,ny,pitch", [(1, 1, None), (67, 45, None), (130, 3, 200), (5, 131, 9), (64, 64, 64)])
+def test_fbm2d_ragged_edges_and_pitch(nx, ny, pitch):
+    kw = dict(smoothness=1, octaves=5, persistence=0.5, lacunarity=2.0, base_freq=1 / 16, seed=11)
+    out = _gpu_fbm2(nx, ny, -70, 33, pitch=pitch, **kw)
+    g = out.cpu().numpy().astype(np.float64)
+    ref = O.fbm_2d(1, 5, 0.5, 2.0, 1 / 16, 11, -70, 33, nx, ny)
+    assert np.max(np.abs(g - ref)) <= 1e-5 * _amp_total(0.5, 5)
+    if pitch is not None:
+        full = out.as_strided((ny, pitch), (pitch, 1)).cpu().numpy()
+        assert np.all(full[:, nx:] == 7.0)  # nothing written past the row
+
+
+@pytest.mark.parametrize("smooth", [1, 2])
+def test_fbm2d_non_dyadic_parameters(smooth):
+    kw = dict(smoothness=smooth, octaves=6, persistence=0.61, lacunarity=1.87, base_freq=0.013, seed=77)
+    x0, y0 = -123456789, 987654321
+    g = _gpu_fbm2(150, 97, x0, y0, **kw).cpu().numpy().astype(np.float64)
+    ref = O.fbm_2d(smooth, 6, 0.61, 1.87, 0.013, 77, x0, y0, 150, 97)
+    assert np.max(np.abs(g - ref)) <= 1e-5 * _amp_total(0.61, 6)
+
+
+def test_fbm2d_finest_lattice_one_cell_per_sample():
+    kw = dict(smoothness=1, octaves=6, persistence=0.5, lacunarity=2.0, base_freq=1 / 32, seed=4)
+    g = _gpu_fbm2(96, 80, 5, -5, **kw).cpu().numpy().astype(np.float64)
+    ref = O.fbm_2d(1, 6, 0.5, 2.0, 1 / 32, 4, 5, -5, 96, 80)
+    assert np.max(np.abs(g - ref)) <= 1e-5 * _amp_total(0.5, 6)
+
+
+def test_fbm2d_sixteen_octaves_large_offset():
+    kw = dict(smoothness=2, octaves=16, persistence=0.5, lacunarity=2.0, base_freq=2.0 ** -15, seed=12)
+    x0, y0 = 2 ** 45 + 3, -(2 ** 44) - 1
+    g = _gpu_fbm2(100, 70, x0, y0, **kw).cpu().numpy().astype(np.float64)
+    ref = O.fbm_2d(2, 16, 0.5, 2.0, 2.0 ** -15, 12, x0, y0, 100, 70)
+    assert np.max(np.abs(g - ref)) <= 1e-5 * _amp_total(0.5, 16)
+
+
+def test_fbm2d_fp16_output():
+    kw = dict(smoothness=1, octaves=4, persistence=0.5, lacunarity=2.0, base_freq=8 / 256, seed=1)
+    g = _gpu_fbm2(256, 256, 0, 0, dtype=torch.float16, **kw).cpu().numpy().astype(np.float64)
+    ref = O.fbm_2d(1, 4, 0.5, 2.0, 8 / 256, 1, 0, 0, 256, 256)
+    # FP16 rounding of |H| < 1: half an ulp at [0.5, 1) is 2^-12
+    assert np.max(np.abs(g - ref)) <= 2.0 ** -12 + 1e-5 * 1.875
+
+
+def test_fbm2d_tiles_stitch_bit_exactly():
+    """A tile equals the matching crop of a larger field (per-sample arithmetic does not
+    depend on where the tile boundaries fall)."""
+    kw = dict(smoothness=1, octaves=6, persistence=0.5, lacunarity=2.0, base_freq=1 / 64, seed=3)
+    big = _gpu_fbm2(300, 200, -3 * 2 ** 20 - 7 - 5, 2 ** 33 + 5 - 9, **kw)
+    small = _gpu_fbm2(130, 70, -3 * 2 ** 20 - 7, 2 ** 33 + 5, **kw)
+    assert torch.equal(big[9:79, 5:135], small)
+
+
+def test_fbm2d_8192_8oct_sampled():
+    """2D 8192x8192, 8 octaves, base lattice 16x16 (the throughput workload): oracle at
+    sampled samples + one full 64x64 tile + the last row/column."""
+    kw = dict(smoothness=1, octaves=8, persistence=0.5, lacunarity=2.0, base_freq=16 / 8192, seed=1)
+    out = _gpu_fbm2(8192, 8192, 0, 0, **kw)
+    g = out.cpu().numpy()
+    rng = np.random.default_rng(2024)
+    X = rng.integers(0, 8192, size=20000)
+    Y = rng.integers(0, 8192, size=20000)
+    X = np.concatenate([X, np.arange(8192), np.full(8192, 8191), np.arange(4096, 4160).repeat(64)])
+    Y = np.concatenate([Y, np.full(8192, 8191), np.arange(8192), np.tile(np.arange(1000, 1064), 64)])
+    ref = O.fbm_points_2d(1, 8, 0.5, 2.0, 16 / 8192, 1, X, Y)
+    err = np.max(np.abs(g[Y, X].astype(np.float64) - ref))
+    assert err <= 1e-5 * _amp_total(0.5, 8), err
+
+
+# ---------------------------------------------------------------------------------
+# 3D
+# ---------------------------------------------------------------------------------
+def _gpu_fbm3(nx, ny, nz, x0, y0, z0, **kw):
+    out = torch.empty((nz, ny, nx), dtype=torch.float32, device=DEV)
+    ptg.fbm_3d(out, x0=x0, y0=y0, z0=z0, **kw)
+    _sync()
+    return out
+
+
+@pytest.mark.parametrize("smooth", [1, 2])
+@pytest.mark.parametrize("dims,origin", [((64, 40, 24), (0, 0, 0)), ((70, 9, 11), (-5, 2 ** 33 + 1, -(2 ** 20)))])
+def test_fbm3d_full_field(smooth, dims, origin):
+    kw = dict(smoothness=smooth, octaves=6, persistence=0.5, lacunarity=2.0, base_freq=1 / 64, seed=1)
+    g = _gpu_fbm3(*dims, *origin, **kw).cpu().numpy().astype(np.float64)
+    ref = O.fbm_3d(smooth, 6, 0.5, 2.0, 1 / 64, 1, *origin, *dims)
+    err = np.max(np.abs(g - ref))
+    assert err <= 1e-5 * _amp_total(0.5, 6), err
+
+
+def test_fbm3d_512_6oct_c2_sampled():
+    """3D 512^3, 6 octaves, base lattice 8^3, C2 quintic: sampled against the oracle."""
+    kw = dict(smoothness=2, octaves=6, persistence=0.5, lacunarity=2.0, base_freq=8 / 512, seed=1)
+    out = _gpu_fbm3(512, 512, 512, 0, 0, 0, **kw)
+    rng = np.random.default_rng(7)
+    n = 20000
+    X, Y, Z = (rng.integers(0, 512, size=n) for _ in range(3))
+    g = out[torch.from_numpy(Z).to(DEV), torch.from_numpy(Y).to(DEV), torch.from_numpy(X).to(DEV)].cpu().numpy()
+    ref = O.fbm_points_3d(2, 6, 0.5, 2.0, 8 / 512, 1, X, Y, Z)
+    err = np.max(np.abs(g.astype(np.float64) - ref))
+    assert err <= 1e-5 * _amp_total(0.5, 6), err
+
+
+def test_fbm3d_non_dyadic_and_ragged():
+    kw = dict(smoothness=1, octaves=4, persistence=0.7, lacunarity=2.3, base_freq=0.021, seed=99)
+    g = _gpu_fbm3(33, 17, 10, 1000, -2000, 3000, **kw).cpu().numpy().astype(np.float64)
+    ref = O.fbm_3d(1, 4, 0.7, 2.3, 0.021, 99, 1000, -2000, 3000, 33, 17, 10)
+    assert np.max(np.abs(g - ref)) <= 1e-5 * _amp_total(0.7, 4)
+
+
+def test_empty_fields_are_noops():
+    out = torch.empty((0, 16), dtype=torch.float32, device=DEV)
+    ptg.fbm_2d(out, base_freq=1 / 8, octaves=2)
+    out3 = torch.empty((4, 0, 4), dtype=torch.float32, device=DEV)
+    ptg.fbm_3d(out3, base_freq=1 / 8, octaves=2)
+    _sync()
