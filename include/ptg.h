@@ -76,6 +76,12 @@ extern "C" {
 #define PTG_FORM_MFMA_F16 1   /* 2D only: V_x C V_y^T on FP16 MFMA, FP32 accumulate    */
 #define PTG_FORM_MFMA_BF16 2  /* 2D only: same on BF16 MFMA                            */
 
+/* ---- kernel choice for the plain form ----------------------------------------- */
+#define PTG_PATH_AUTO 0     /* dyadic kernel when it applies, else the general kernel    */
+#define PTG_PATH_GENERAL 1  /* any base frequency / lacunarity / origin                  */
+#define PTG_PATH_DYADIC 2   /* 2D only: base_freq = 2^-k (k <= 22), lacunarity = 2;     */
+                            /* PTG_EINVAL when the parameters are not of that kind       */
+
 /* ---- bases for the MFMA forms (Vandermonde rows fed to the matrix cores) ------ */
 #define PTG_BASIS_MONOMIAL 0  /* V(t) = [1, t, t^2, t^3], C = monomial coefficients   */
 #define PTG_BASIS_CENTRED 1   /* V(t) = [1, s, s^2, s^3] with s = t - 1/2              */
@@ -94,7 +100,7 @@ typedef struct ptg_params {
     uint32_t seed;        /* lattice seed                                              */
     int32_t form;         /* PTG_FORM_*                                                */
     int32_t basis;        /* PTG_BASIS_* (MFMA forms only)                             */
-    int32_t reserved;     /* must be 0                                                 */
+    int32_t path;         /* PTG_PATH_*: kernel choice for the plain form              */
 } ptg_params;
 
 /* Library version string (static storage). */

@@ -31,6 +31,7 @@ PTG_F32 = 0
 PTG_F16 = 1
 FORMS = {"plain": 0, "mfma_f16": 1, "mfma_bf16": 2}
 BASES = {"monomial": 0, "centred": 1}
+PATHS = {"auto": 0, "general": 1, "dyadic": 2}
 
 
 class PtgError(RuntimeError):
@@ -51,7 +52,7 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint32),
         ("form", ctypes.c_int32),
         ("basis", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("path", ctypes.c_int32),
     ]
 
 
@@ -103,7 +104,7 @@ def _check(rc):
 
 
 def params(dim=2, smoothness=1, octaves=8, persistence=0.5, lacunarity=2.0, base_freq=1.0 / 512, seed=1,
-           out_dtype=PTG_F32, form="plain", basis="monomial") -> Params:
+           out_dtype=PTG_F32, form="plain", basis="monomial", path="auto") -> Params:
     p = Params()
     p.dim = dim
     p.smoothness = smoothness
@@ -115,7 +116,7 @@ def params(dim=2, smoothness=1, octaves=8, persistence=0.5, lacunarity=2.0, base
     p.seed = seed & 0xFFFFFFFF
     p.form = FORMS[form] if isinstance(form, str) else int(form)
     p.basis = BASES[basis] if isinstance(basis, str) else int(basis)
-    p.reserved = 0
+    p.path = PATHS[path] if isinstance(path, str) else int(path)
     return p
 
 

@@ -39,9 +39,39 @@ struct Fbm3dArgs {
     int32_t pad;
 };
 
+// Dense 2D field, dyadic K3 (base frequency 2^-k, lacunarity 2): world-aligned tiles of
+// kDyTileX x kDyTileY samples, 4 waves side by side, each 64 columns x 32 rows.
+constexpr int kDyTileX = 256;
+constexpr int kDyTileY = 32;
+constexpr int kDyMaxShift = 22;  // period 2^s samples, s <= 22 keeps fractions exact in FP32
+
+constexpr int kDyTabMaxP = 512;
+constexpr size_t kDyMaxLds = 160 * 1024;  // LDS of one gfx950 compute unit  // octaves of period <= 512 read their bases from an LDS table
+
+struct Fbm2dDyadicArgs {
+    int64_t x0, y0, nx, ny, pitch;  // output window (world) and row pitch (elements)
+    int64_t tx_base, ty_base;       // world origin of tile (0, 0), tile-aligned
+    int64_t tiles;
+    void *out;
+    float amp[kMaxOctaves];
+    float inv2p[kMaxOctaves];  // 2^-(s+1)
+    int32_t shift[kMaxOctaves];
+    int32_t nnx[kMaxOctaves], nny[kMaxOctaves];     // footprint nodes per axis
+    int32_t noff[kMaxOctaves];                      // node-block offset of each octave
+    int32_t pxoff[kMaxOctaves], pyoff[kMaxOctaves]; // key-prefix offsets
+    int32_t toff[kMaxOctaves];                      // basis-table offset, -1: no table
+    int32_t nodes_total, px_total, py_total, tab_total, tab_first;
+    int32_t octaves;
+    uint32_t seed;
+    int32_t tiles_x;
+    int32_t grid;
+    int32_t n_c0;  // leading octaves of period >= 64
+};
+
 // Launch wrappers (defined in the .hip translation units).  They assume validated
 // arguments and return the HIP status of the launch.
 hipError_t launch_fbm2d_general(const Fbm2dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
+hipError_t launch_fbm2d_dyadic(const Fbm2dDyadicArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
 
 hipError_t launch_coords(double f0, double lac, int octaves, int64_t x0, int64_t n, int64_t *cells, float *frac,

@@ -1,14 +1,116 @@
 // ptg_plan.hip -- octave plan and kernel choice for the dense fields.
 #include <algorithm>
+#include <cmath>
 
 #include "ptg_internal.h"
 #include "ptg_launch.h"
 
 namespace ptg {
 
+// Base frequency 2^-k with 0 <= k <= kDyMaxShift and lacunarity exactly 2 (every octave
+// period then a power of two >= 1, checked by the caller's frequency validation).
+static bool dyadic_shift(const ptg_params *p, int *k_out)
+{
+    if (p->lacunarity != 2.0) return false;
+    int e = 0;
+    const double m = std::frexp(p->base_freq, &e);  // base_freq = m * 2^e, m in [0.5, 1)
+    if (m != 0.5) return false;
+    const int k = 1 - e;  // base_freq = 2^-k
+    if (k < 0 || k > kDyMaxShift || k - (p->octaves - 1) < 0) return false;
+    *k_out = k;
+    return true;
+}
+
+static int64_t floor_to(int64_t a, int64_t b)  // largest multiple of b <= a (b > 0)
+{
+    int64_t q = a / b;
+    if (q * b > a) --q;
+    return q * b;
+}
+
+static int device_cus()
+{
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
+static int fbm2d_dyadic(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out,
+                        int64_t pitch, hipStream_t s)
+{
+    constexpr int TX = kDyTileX, TY = kDyTileY;
+    Fbm2dDyadicArgs a{};
+    a.x0 = x0;
+    a.y0 = y0;
+    a.nx = nx;
+    a.ny = ny;
+    a.pitch = pitch;
+    a.out = out;
+    a.tx_base = floor_to(x0, TX);
+    a.ty_base = floor_to(y0, TY);
+    const int64_t tiles_x = (x0 + nx - a.tx_base + TX - 1) / TX;
+    const int64_t tiles_y = (y0 + ny - a.ty_base + TY - 1) / TY;
+    a.tiles_x = (int32_t)tiles_x;
+    a.tiles = tiles_x * tiles_y;
+    double freq[kMaxOctaves];
+    octave_tables(p, freq, a.amp);
+    a.octaves = p->octaves;
+    a.seed = p->seed;
+    int nodes = 0, px = 0, py = 0, tab = 0;
+    a.tab_first = p->octaves;
+    for (int o = 0; o < p->octaves; ++o) {
+        const int sh = k - o;
+        a.shift[o] = sh;
+        if (sh >= 6) a.n_c0 = o + 1;
+        a.inv2p[o] = std::ldexp(1.0f, -(sh + 1));
+        a.nnx[o] = std::max(TX >> sh, 1) + 1;
+        a.nny[o] = std::max(TY >> sh, 1) + 1;
+        a.noff[o] = nodes;
+        a.pxoff[o] = px;
+        a.pyoff[o] = py;
+        nodes += a.nnx[o] * a.nny[o];
+        px += a.nnx[o];
+        py += a.nny[o];
+        if ((1 << sh) <= kDyTabMaxP) {
+            if (a.tab_first == p->octaves) a.tab_first = o;
+            a.toff[o] = tab;
+            tab += 1 << sh;
+        } else {
+            a.toff[o] = -1;
+        }
+    }
+    a.nodes_total = nodes;
+    a.px_total = px;
+    a.py_total = py;
+    a.tab_total = tab;
+    // workgroups: a few per compute unit, each walking tiles with a grid stride
+    a.grid = (int32_t)std::min<int64_t>(a.tiles, (int64_t)device_cus() * 4);
+    const size_t lds = (size_t)tab * 16 + (size_t)nodes * 8 + (size_t)(px + py) * 4 + (size_t)nodes * 4 +
+                       (size_t)(px + py) * 4;
+    if (lds > kDyMaxLds) return 1;  // footprint too large for one workgroup: caller falls back
+    hipError_t e = launch_fbm2d_dyadic(a, p->smoothness, p->out_dtype == PTG_F16, lds, s);
+    return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d dyadic launch");
+}
+
 int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out, int64_t pitch,
                 hipStream_t s)
 {
+    int k = 0;
+    const bool dy = dyadic_shift(p, &k);
+    if (p->path == PTG_PATH_DYADIC && !dy)
+        return fail(PTG_EINVAL, "the dyadic kernel needs base_freq = 2^-k (k <= %d) and lacunarity 2", kDyMaxShift);
+    if (dy && p->path != PTG_PATH_GENERAL) {
+        const int rc = fbm2d_dyadic(p, k, x0, y0, nx, ny, out, pitch, s);
+        if (rc <= 0) return rc;
+        if (p->path == PTG_PATH_DYADIC)
+            return fail(PTG_EINVAL, "the dyadic kernel's lattice footprint exceeds the workgroup's LDS");
+    }
     Fbm2dArgs a{};
     a.x0 = x0;
     a.y0 = y0;

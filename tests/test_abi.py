@@ -31,7 +31,7 @@ def _fbm2(p, x0=0, y0=0, nx=16, ny=16, out=1 << 20, pitch=16):
 @pytest.mark.parametrize("field,value", [
     ("dim", 3), ("smoothness", 0), ("smoothness", 3), ("octaves", 0), ("octaves", 17), ("out_dtype", 5),
     ("persistence", 0.0), ("persistence", float("nan")), ("lacunarity", -2.0), ("base_freq", 0.0),
-    ("base_freq", float("inf")), ("form", 9), ("basis", 7), ("reserved", 1),
+    ("base_freq", float("inf")), ("form", 9), ("basis", 7), ("path", 3), ("path", -1),
 ])
 def test_rejects_bad_params(field, value):
     p = ptg.params()

@@ -281,3 +281,37 @@ def test_empty_fields_are_noops():
     out3 = torch.empty((4, 0, 4), dtype=torch.float32, device=DEV)
     ptg.fbm_3d(out3, base_freq=1 / 8, octaves=2)
     _sync()
+
+
+# ---------------------------------------------------------------------------------
+# kernel choice: the general and the dyadic (matrix-core) K3 on the same dyadic fields
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("path", ["general", "dyadic"])
+@pytest.mark.parametrize("smooth", [1, 2])
+@pytest.mark.parametrize("f0,octs,origin,shape", [
+    (8 / 256, 4, (-3 * 2 ** 20 - 7, 2 ** 33 + 5), (256, 256)),   # periods 32..4 (16x16x4 + 4x4x1)
+    (1 / 8, 4, (13, -29), (97, 71)),                              # periods 8..1 (4x4x1 + VALU), ragged
+    (2.0 ** -12, 13, (2 ** 40 + 3, -(2 ** 40) - 61), (130, 66)),  # periods 4096..1, unaligned window
+])
+def test_fbm2d_paths_against_oracle(path, smooth, f0, octs, origin, shape):
+    kw = dict(smoothness=smooth, octaves=octs, persistence=0.5, lacunarity=2.0, base_freq=f0, seed=5, path=path)
+    nx, ny = shape
+    g = _gpu_fbm2(nx, ny, *origin, **kw).cpu().numpy().astype(np.float64)
+    ref = O.fbm_2d(smooth, octs, 0.5, 2.0, f0, 5, origin[0], origin[1], nx, ny)
+    err = np.max(np.abs(g - ref))
+    assert err <= 1e-5 * _amp_total(0.5, octs), err
+
+
+def test_fbm2d_dyadic_crops_bit_exact():
+    kw = dict(smoothness=1, octaves=8, persistence=0.5, lacunarity=2.0, base_freq=1 / 256, seed=8, path="dyadic")
+    big = _gpu_fbm2(333, 211, -1000 - 5, 5000 - 9, **kw)
+    small = _gpu_fbm2(150, 77, -1000, 5000, **kw)
+    assert torch.equal(big[9:86, 5:155], small)
+
+
+def test_fbm2d_dyadic_rejects_non_dyadic():
+    out = torch.empty((8, 8), dtype=torch.float32, device=DEV)
+    with pytest.raises(ptg.PtgError):
+        ptg.fbm_2d(out, base_freq=0.013, octaves=3, path="dyadic")
+    with pytest.raises(ptg.PtgError):
+        ptg.fbm_2d(out, base_freq=1 / 64, lacunarity=1.9, octaves=3, path="dyadic")
