@@ -26,6 +26,22 @@ PERSISTENCE = 0.5
 LACUNARITY = 2.0
 SEED = 1
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fbm2d_dyadic_2d_8192x8192_8oct_c1.traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+    or None when the kernel source has changed since they were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        with open(os.path.join(ROOT, t["source"]), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != t["source_sha256"]:
+                return None
+        return t["traffic_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -165,8 +181,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "k_fbm2d (one launch per step)",
+            "traffic": measured_traffic() if args.path in ("auto", "dyadic") else None,
+            "kernel": "k_fbm2d_dyadic (one launch per step)" if args.path != "general" else "k_fbm2d_general",
             "kernel_avg_ms": k_avg_ms,
             "kernel_median_ms": k_med_ms,
             "algorithmic_bytes_per_launch": out_bytes,
