@@ -65,7 +65,9 @@ struct Fbm2dDyadicArgs {
     uint32_t seed;
     int32_t tiles_x;
     int32_t grid;
-    int32_t n_c0;  // leading octaves of period >= 64
+    int32_t n_c0;   // leading octaves of period >= 64
+    int32_t prec;   // 0: FP32 matrix cores; 1 / 2: FP16 / BF16 Vandermonde form (periods >= 16)
+    int32_t basis;  // Vandermonde variable: 0 = t, 1 = t - 1/2
 };
 
 // Launch wrappers (defined in the .hip translation units).  They assume validated

@@ -62,6 +62,8 @@ static int fbm2d_dyadic(const ptg_params *p, int k, int64_t x0, int64_t y0, int6
     octave_tables(p, freq, a.amp);
     a.octaves = p->octaves;
     a.seed = p->seed;
+    a.prec = p->form == PTG_FORM_MFMA_F16 ? 1 : (p->form == PTG_FORM_MFMA_BF16 ? 2 : 0);
+    a.basis = p->basis;
     int nodes = 0, px = 0, py = 0, tab = 0;
     a.tab_first = p->octaves;
     for (int o = 0; o < p->octaves; ++o) {
@@ -154,9 +156,16 @@ int fbm3d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm3d launch");
 }
 
-int fbm2d_mfma(const ptg_params *, int64_t, int64_t, int64_t, int64_t, void *, int64_t, hipStream_t)
+int fbm2d_mfma(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out, int64_t pitch,
+               hipStream_t s)
 {
-    return fail(PTG_EINVAL, "matrix-core form not available in this build");
+    int k = 0;
+    if (!dyadic_shift(p, &k))
+        return fail(PTG_EINVAL, "the FP16/BF16 matrix-core form needs base_freq = 2^-k (k <= %d) and lacunarity 2",
+                    kDyMaxShift);
+    const int rc = fbm2d_dyadic(p, k, x0, y0, nx, ny, out, pitch, s);
+    if (rc > 0) return fail(PTG_EINVAL, "the lattice footprint exceeds the workgroup's LDS");
+    return rc;
 }
 
 }  // namespace ptg

@@ -315,3 +315,41 @@ def test_fbm2d_dyadic_rejects_non_dyadic():
         ptg.fbm_2d(out, base_freq=0.013, octaves=3, path="dyadic")
     with pytest.raises(ptg.PtgError):
         ptg.fbm_2d(out, base_freq=1 / 64, lacunarity=1.9, octaves=3, path="dyadic")
+
+
+# ---------------------------------------------------------------------------------
+# matrix-core precision form: V(x) C V(y)^T on FP16 / BF16 MFMA, FP32 accumulation
+# ---------------------------------------------------------------------------------
+# Expected magnitudes (max |err| / A over a field), from the FP16/BF16 rounding of the
+# Vandermonde rows, the coefficients and the stage-1 result: monomial FP16 ~1e-3,
+# centred FP16 ~2e-4, BF16 ~8x worse; FP16 output adds 2^-12 relative.  The bounds below
+# are a factor ~4 above those estimates.
+MFMA_BOUNDS = {("mfma_f16", "monomial"): 6e-3, ("mfma_f16", "centred"): 2e-3,
+               ("mfma_bf16", "monomial"): 5e-2, ("mfma_bf16", "centred"): 1.5e-2}
+
+
+@pytest.mark.parametrize("form", ["mfma_f16", "mfma_bf16"])
+@pytest.mark.parametrize("basis", ["monomial", "centred"])
+def test_fbm2d_vandermonde_form_error(form, basis):
+    """2D fBm, 10 octaves, base lattice 32 x 32 over 16384 samples (periods 512..1), world
+    offset (2^24 - 3) * 512, -(2^24 - 5) * 512 samples: a 512 x 384 window, FP16 output."""
+    x0, y0 = (2 ** 24 - 3) * 512, -(2 ** 24 - 5) * 512
+    nx, ny = 512, 384
+    kw = dict(smoothness=1, octaves=10, persistence=0.5, lacunarity=2.0, base_freq=32 / 16384, seed=1,
+              form=form, basis=basis)
+    g = _gpu_fbm2(nx, ny, x0, y0, dtype=torch.float16, **kw).cpu().numpy().astype(np.float64)
+    ref = O.fbm_2d(1, 10, 0.5, 2.0, 32 / 16384, 1, x0, y0, nx, ny)
+    A = _amp_total(0.5, 10)
+    err = np.abs(g - ref)
+    mx, rms = float(err.max()) / A, float(np.sqrt(np.mean(err ** 2))) / A
+    print(f"[{form}/{basis}] max/A = {mx:.3e}  rms/A = {rms:.3e}", flush=True)
+    assert mx <= MFMA_BOUNDS[(form, basis)]
+    assert rms <= MFMA_BOUNDS[(form, basis)] / 4
+
+
+def test_fbm2d_vandermonde_form_rejects():
+    out = torch.empty((8, 8), dtype=torch.float16, device=DEV)
+    with pytest.raises(ptg.PtgError):
+        ptg.fbm_2d(out, base_freq=0.013, octaves=3, form="mfma_f16")
+    with pytest.raises(ptg.PtgError):
+        ptg.fbm_2d(out, base_freq=1 / 64, octaves=3, smoothness=2, form="mfma_f16")
