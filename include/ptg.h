@@ -168,6 +168,85 @@ PTG_API int ptg_cells_2d(int32_t smoothness, const float *grad_dev, int64_t nnx,
 PTG_API int ptg_cells_3d(int32_t smoothness, const float *grad_dev, int64_t nnx, int64_t nny,
                  int64_t nnz, float amplitude, float *coeff_dev, void *stream);
 
+/* ---- a6: serving (continuous batching of terrain tiles) ----------------------- */
+/* A server owns an output arena of hbm_budget_bytes and one persistent kernel.  Requests
+ * (terrain tiles of any size, 2D or 3D, C1 or C2, any octave parameters, FP32 output) are
+ * queued by ptg_tiles_submit, admitted while arena bytes and request slots are free, cut
+ * into work items of 64 x 64 (2D) or 64 x 8 x 8 (3D) sample tiles and published into a
+ * ring that the persistent kernel's workgroups drain while earlier requests are still
+ * running.  Each tile is computed by the same device code as ptg_fbm_2d / ptg_fbm_3d with
+ * p->path = PTG_PATH_GENERAL, so a served tile equals that call bit for bit. */
+
+typedef struct ptg_server ptg_server;
+
+#define PTG_EXEC_GPU 0   /* persistent kernel on cfg->device                             */
+#define PTG_EXEC_HOST 1  /* test-only: no GPU; each tile "completes" after fake_tile_ns   */
+                         /* on a host thread and the arena is host memory (outputs are   */
+                         /* not computed): admission, budget and shutdown logic only     */
+
+typedef struct ptg_server_cfg {
+    int64_t hbm_budget_bytes; /* output arena (owned by the server), > 0                   */
+    int32_t max_items;        /* work-item ring entries, >= 64                              */
+    int32_t workgroups;       /* persistent workgroups, 0 = 2 per compute unit              */
+    int32_t device;           /* HIP device ordinal                                         */
+    int32_t executor;         /* PTG_EXEC_GPU or PTG_EXEC_HOST                              */
+    int64_t fake_tile_ns;     /* PTG_EXEC_HOST only: simulated time per tile                */
+} ptg_server_cfg;
+
+typedef struct ptg_tile_req {
+    ptg_params params;        /* dim 2 or 3, PTG_FORM_PLAIN, PTG_F32; path is ignored       */
+    int64_t origin[3];        /* world sample index of element (0,0,0); origin[2] = 0 in 2D */
+    int64_t extent[3];        /* nx, ny, nz >= 1; nz = 1 in 2D                              */
+    uint64_t user_tag;        /* returned unchanged                                         */
+} ptg_tile_req;
+
+typedef struct ptg_tile_result {
+    int32_t status;           /* PTG_OK, PTG_ESHUTDOWN or PTG_EHIP                          */
+    int32_t reserved;
+    void *out_dev;            /* the tile, dense row-major FP32 [nz][ny][nx], valid until   */
+                              /* ptg_tile_release (device memory; host memory for           */
+                              /* PTG_EXEC_HOST)                                              */
+    int64_t bytes;
+    uint64_t user_tag;
+    int64_t t_submit_ns, t_admit_ns, t_done_ns; /* steady clock, ns                         */
+} ptg_tile_result;
+
+/* Create a server: allocates the arena, the pinned work-item ring and request table, and
+ * starts the scheduler thread; the persistent kernel runs on a stream of its own and is
+ * (re)launched whenever work is published and it is not running.
+ * Errors: PTG_EINVAL, PTG_ENOMEM, PTG_EHIP. */
+PTG_API int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out);
+
+/* Queue n requests (thread-safe, never blocks); tickets_out[i] receives request i's
+ * ticket.  Admission is in arrival order, except that a request that does not fit the
+ * free arena bytes yet lets later ones pass until it has waited 50 ms.
+ * Errors (none of the n is queued): PTG_EINVAL (a request fails validation), PTG_E2BIG (a
+ * request's output exceeds the whole budget), PTG_ESHUTDOWN. */
+PTG_API int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n, uint64_t *tickets_out);
+
+/* Wait up to timeout_ns (0: poll, < 0: forever) for a ticket and fill *res.
+ * Errors: PTG_ETIMEDOUT (still pending), PTG_ENOENT (unknown or released ticket). */
+PTG_API int ptg_tiles_wait(ptg_server *s, uint64_t ticket, int64_t timeout_ns, ptg_tile_result *res);
+
+/* Return a completed ticket's arena bytes to the server (its out_dev becomes invalid).
+ * Errors: PTG_ENOENT, PTG_EAGAIN (not complete yet). */
+PTG_API int ptg_tile_release(ptg_server *s, uint64_t ticket);
+
+typedef struct ptg_server_stats {
+    int64_t submitted, admitted, completed, released;
+    int64_t tiles_done;       /* sample tiles finished                                      */
+    int64_t pending, in_flight;
+    int64_t bytes_in_use, bytes_peak, budget;
+    int64_t kernel_launches;  /* persistent-kernel launches (it exits after idling)         */
+} ptg_server_stats;
+
+PTG_API int ptg_server_stats_get(ptg_server *s, ptg_server_stats *st);
+
+/* Stop admitting; queued requests complete with PTG_ESHUTDOWN, admitted ones run to the
+ * end; then the kernel is stopped and everything is freed (outputs of unreleased tickets
+ * too).  s is invalid afterwards. */
+PTG_API int ptg_server_destroy(ptg_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,6 +56,48 @@ class Params(ctypes.Structure):
     ]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_int64),
+        ("max_items", ctypes.c_int32),
+        ("workgroups", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("executor", ctypes.c_int32),
+        ("fake_tile_ns", ctypes.c_int64),
+    ]
+
+
+class TileReq(ctypes.Structure):
+    _fields_ = [
+        ("params", Params),
+        ("origin", ctypes.c_int64 * 3),
+        ("extent", ctypes.c_int64 * 3),
+        ("user_tag", ctypes.c_uint64),
+    ]
+
+
+class TileResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("out_dev", ctypes.c_void_p),
+        ("bytes", ctypes.c_int64),
+        ("user_tag", ctypes.c_uint64),
+        ("t_submit_ns", ctypes.c_int64),
+        ("t_admit_ns", ctypes.c_int64),
+        ("t_done_ns", ctypes.c_int64),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "submitted", "admitted", "completed", "released", "tiles_done", "pending", "in_flight",
+        "bytes_in_use", "bytes_peak", "budget", "kernel_launches")]
+
+
+PTG_EXEC_GPU = 0
+PTG_EXEC_HOST = 1
+
 _LIB = None
 _i32, _u32, _i64, _f32, _f64 = ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
 _vp = ctypes.c_void_p
@@ -80,8 +122,15 @@ def lib():
     L.ptg_lattice_3d.argtypes = [_u32, _i32, _i64, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp]
     L.ptg_cells_2d.argtypes = [_i32, _vp, _i64, _i64, _f32, _vp, _vp]
     L.ptg_cells_3d.argtypes = [_i32, _vp, _i64, _i64, _i64, _f32, _vp, _vp]
+    L.ptg_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]
+    L.ptg_tiles_submit.argtypes = [_vp, ctypes.POINTER(TileReq), _i32, ctypes.POINTER(ctypes.c_uint64)]
+    L.ptg_tiles_wait.argtypes = [_vp, ctypes.c_uint64, _i64, ctypes.POINTER(TileResult)]
+    L.ptg_tile_release.argtypes = [_vp, ctypes.c_uint64]
+    L.ptg_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+    L.ptg_server_destroy.argtypes = [_vp]
     for name in ("ptg_fbm_2d", "ptg_fbm_3d", "ptg_coords", "ptg_lattice_2d", "ptg_lattice_3d",
-                 "ptg_cells_2d", "ptg_cells_3d"):
+                 "ptg_cells_2d", "ptg_cells_3d", "ptg_server_create", "ptg_tiles_submit", "ptg_tiles_wait",
+                 "ptg_tile_release", "ptg_server_stats_get", "ptg_server_destroy"):
         getattr(L, name).restype = _i32
     _LIB = L
     return L
@@ -223,3 +272,75 @@ def cells_3d(smoothness, grad, amplitude, coeff_out, stream=None):
 
 def version() -> str:
     return lib().ptg_version().decode()
+
+
+# ---- serving ------------------------------------------------------------------------
+
+def tile_req(dim=2, origin=(0, 0, 0), extent=(64, 64, 1), user_tag=0, **kw) -> TileReq:
+    r = TileReq()
+    r.params = params(dim=dim, **kw)
+    for i in range(3):
+        r.origin[i] = origin[i] if i < len(origin) else 0
+        r.extent[i] = extent[i] if i < len(extent) else 1
+    r.user_tag = user_tag
+    return r
+
+
+class Server:
+    """Continuous-batching tile server (a persistent kernel + host scheduler in libptg)."""
+
+    def __init__(self, budget_bytes, max_items=1 << 16, workgroups=0, device=0, executor=PTG_EXEC_GPU,
+                 fake_tile_ns=0):
+        cfg = ServerCfg(budget_bytes, max_items, workgroups, device, executor, fake_tile_ns)
+        h = ctypes.c_void_p()
+        _check(lib().ptg_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+
+    def submit(self, reqs):
+        n = len(reqs)
+        arr = (TileReq * n)(*reqs)
+        tickets = (ctypes.c_uint64 * n)()
+        _check(lib().ptg_tiles_submit(self.h, arr, n, tickets))
+        return list(tickets)
+
+    def wait(self, ticket, timeout_ns=-1):
+        """TileResult of a ticket; raises PtgError(PTG_ETIMEDOUT) when still pending."""
+        res = TileResult()
+        _check(lib().ptg_tiles_wait(self.h, ticket, timeout_ns, ctypes.byref(res)))
+        return res
+
+    def release(self, ticket):
+        _check(lib().ptg_tile_release(self.h, ticket))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().ptg_server_stats_get(self.h, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.h:
+            rc = lib().ptg_server_destroy(self.h)
+            self.h = None
+            _check(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+_HIP = None
+
+
+def device_copy(dst_ptr, src_ptr, nbytes):
+    """Synchronous device-to-device copy (hipMemcpy) between raw device pointers, e.g. a
+    served tile into a torch tensor."""
+    global _HIP
+    if _HIP is None:
+        _HIP = ctypes.CDLL("libamdhip64.so")
+        _HIP.hipMemcpy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int]
+        _HIP.hipMemcpy.restype = ctypes.c_int
+    rc = _HIP.hipMemcpy(dst_ptr, src_ptr, nbytes, 3)  # hipMemcpyDeviceToDevice
+    if rc != 0:
+        raise PtgError(PTG_EHIP, f"hipMemcpy failed ({rc})")

@@ -1,0 +1,275 @@
+// ptg_general_tile.h -- K3 tile functions for any octave
+// parameters (any base frequency, lacunarity, persistence, world origin).
+//
+// One workgroup owns a tile of samples; its 64 lanes of each wave own 64 consecutive
+// columns (coalesced stores) and each wave walks a band of rows.  Per octave the
+// workgroup
+//   1. computes the tile's lattice footprint (first/last cell on each axis, FP64 step),
+//   2. hashes every footprint node once into LDS (K1 logic: per-row / per-column key
+//      prefixes, then one fmix32 per node), with the octave amplitude folded in,
+//   3. tabulates the row (and slab) basis values of the tile in LDS,
+//   4. and every lane forms, whenever its row band enters a new cell, the column form of
+//      that cell's polynomial (K2 logic: the Hermite tensor form collapsed along x),
+//      then evaluates one cubic / quintic per sample (3 FMA + 1 add) into registers.
+// Octaves accumulate in registers; each sample is stored once.
+//
+// Cell polynomial (Sec. 2, Sec. 3.4): h = sum_corners [gx b1_cx(x) b0_cy(y) + gy b0_cx(x) b1_cy(y)]
+// (2D) with b0_0 = 1 - s, b0_1 = s.  For a fixed column x it is the 1D Hermite form in y
+//   h(y) = E0 + (E1 - E0) s(y) + Q0 b10(y) + Q1 b11(y),
+//   E_cy = sum_cx gx_{cx,cy} b1_cx(x),   Q_cy = gy_{0,cy} + s(x) (gy_{1,cy} - gy_{0,cy}).
+#pragma once
+
+#include <hip/hip_fp16.h>
+
+#include "ptg_device.h"
+#include "ptg_launch.h"
+
+namespace ptg {
+
+template <typename T>
+__device__ __forceinline__ T to_out(float v);
+template <>
+__device__ __forceinline__ float to_out<float>(float v)
+{
+    return v;
+}
+template <>
+__device__ __forceinline__ __half to_out<__half>(float v)
+{
+    return __float2half_rn(v);
+}
+
+// ---------------------------------------------------------------------------------
+// 2D: tile 64 x 64 samples, 4 waves x 16 rows.
+// LDS: row table float4[64] | gx[capx*capy] | gy[capx*capy] | kx[capx] | ky[capy]
+// ---------------------------------------------------------------------------------
+template <int M, typename OutT>
+__device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t bid, float4 *lds4)
+{
+    constexpr int T = kTile2;
+    constexpr int RPT = T / 4;
+    float4 *rowt = lds4;
+    const int cap = a.capx * a.capy;
+    float *gx = reinterpret_cast<float *>(lds4 + T);
+    float *gy = gx + cap;
+    uint32_t *kx = reinterpret_cast<uint32_t *>(gy + cap);
+    uint32_t *ky = kx + a.capx;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tx0 = (bid % a.tiles_x) * T, ty0 = (bid / a.tiles_x) * T;
+    const int w = (int)min<int64_t>(T, a.nx - tx0);
+    const int h = (int)min<int64_t>(T, a.ny - ty0);
+    const int col = min(lane, w - 1);  // lanes past the edge shadow the last column
+    const int64_t X = a.x0 + tx0 + col;
+    const int64_t Xf = a.x0 + tx0, Xl = a.x0 + tx0 + w - 1;
+    const int64_t Yf = a.y0 + ty0, Yl = a.y0 + ty0 + h - 1;
+
+    float acc[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) acc[r] = 0.0f;
+
+    for (int o = 0; o < a.octaves; ++o) {
+        const double f = a.freq[o];
+        const float amp = a.amp[o];
+        const int64_t cxf = cell_of(Xf, f), cyf = cell_of(Yf, f);
+        const int nnx = (int)(cell_of(Xl, f) - cxf) + 2;
+        const int nny = (int)(cell_of(Yl, f) - cyf) + 2;
+
+        __syncthreads();  // the previous octave is done with LDS
+        const uint32_t pre = key_prefix(a.seed, o);
+        for (int i = tid; i < nnx; i += 256) kx[i] = key_xline(cxf + i);
+        for (int j = tid; j < nny; j += 256) ky[j] = absorb_index(pre, cyf + j);
+        if (tid < T) {
+            const int r = min(tid, h - 1);
+            const Coord c = coord_step(Yf + r, f);
+            float s, b10, b11;
+            Basis<M>::eval(c.t, s, b10, b11);
+            rowt[tid] = make_float4(__int_as_float((int)(c.cell - cyf)), s, b10, b11);
+        }
+        __syncthreads();
+        for (int q = tid; q < nnx * nny; q += 256) {
+            const int j = q / nnx, i = q - j * nnx;
+            const float2 g = grad2(key_combine(ky[j], kx[i]));
+            gx[q] = g.x * amp;
+            gy[q] = g.y * amp;
+        }
+        const Coord cc = coord_step(X, f);
+        const int lcx = (int)(cc.cell - cxf);
+        float sx, b10x, b11x;
+        Basis<M>::eval(cc.t, sx, b10x, b11x);
+        __syncthreads();
+
+        int prev = -1;
+        float E0 = 0.0f, dE = 0.0f, Q0 = 0.0f, Q1 = 0.0f;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const float4 re = rowt[wave * RPT + r];
+            const int lcy = __builtin_amdgcn_readfirstlane(__float_as_int(re.x));
+            if (lcy != prev) {
+                prev = lcy;
+                const int q = lcy * nnx + lcx;
+                const float fx00 = gx[q], fx10 = gx[q + 1], fx01 = gx[q + nnx], fx11 = gx[q + nnx + 1];
+                const float fy00 = gy[q], fy10 = gy[q + 1], fy01 = gy[q + nnx], fy11 = gy[q + nnx + 1];
+                const float e0 = fx00 * b10x + fx10 * b11x;
+                const float e1 = fx01 * b10x + fx11 * b11x;
+                E0 = e0;
+                dE = e1 - e0;
+                Q0 = fy00 + sx * (fy10 - fy00);
+                Q1 = fy01 + sx * (fy11 - fy01);
+            }
+            acc[r] += E0 + dE * re.y + Q0 * re.z + Q1 * re.w;
+        }
+    }
+
+    if (lane < w) {
+        OutT *out = reinterpret_cast<OutT *>(a.out);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int row = wave * RPT + r;
+            if (row < h) out[(ty0 + row) * a.pitch + tx0 + lane] = to_out<OutT>(acc[r]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// 3D: tile 64 x 8 x 8 samples; wave w owns slabs z = 2w, 2w+1, all 8 rows of each.
+// For a fixed column the cell is collapsed along x (a, b, c per (cy, cz) corner pair),
+// then along z, leaving the 1D Hermite form in y evaluated per sample.
+// LDS: y table float4[8] | z table float4[8] | g{x,y,z}[cap] | kx[capx] | kzy[capy*capz]
+// ---------------------------------------------------------------------------------
+template <int M, typename OutT>
+__device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t bid, float4 *lds4)
+{
+    constexpr int TX = kTile3X, TY = kTile3Y, TZ = kTile3Z;
+    constexpr int ZPW = TZ / 4;  // slabs per wave
+    constexpr int RPT = ZPW * TY;
+    float4 *yt = lds4;
+    float4 *zt = lds4 + TY;
+    const int cap = a.capx * a.capy * a.capz;
+    float *gxs = reinterpret_cast<float *>(lds4 + TY + TZ);
+    float *gys = gxs + cap;
+    float *gzs = gys + cap;
+    uint32_t *kx = reinterpret_cast<uint32_t *>(gzs + cap);
+    uint32_t *kzy = kx + a.capx;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tpl = (int64_t)a.tiles_x * a.tiles_y;
+    const int64_t tz = bid / tpl, rem = bid - tz * tpl;
+    const int64_t ty = rem / a.tiles_x, tx = rem - ty * a.tiles_x;
+    const int64_t tx0 = tx * TX, ty0 = ty * TY, tz0 = tz * TZ;
+    const int w = (int)min<int64_t>(TX, a.nx - tx0);
+    const int hy = (int)min<int64_t>(TY, a.ny - ty0);
+    const int hz = (int)min<int64_t>(TZ, a.nz - tz0);
+    const int col = min(lane, w - 1);
+    const int64_t X = a.x0 + tx0 + col;
+    const int64_t Xf = a.x0 + tx0, Yf = a.y0 + ty0, Zf = a.z0 + tz0;
+
+    float acc[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) acc[r] = 0.0f;
+
+    for (int o = 0; o < a.octaves; ++o) {
+        const double f = a.freq[o];
+        const float amp = a.amp[o];
+        const int64_t cxf = cell_of(Xf, f), cyf = cell_of(Yf, f), czf = cell_of(Zf, f);
+        const int nnx = (int)(cell_of(Xf + w - 1, f) - cxf) + 2;
+        const int nny = (int)(cell_of(Yf + hy - 1, f) - cyf) + 2;
+        const int nnz = (int)(cell_of(Zf + hz - 1, f) - czf) + 2;
+
+        __syncthreads();
+        const uint32_t pre = key_prefix(a.seed, o);
+        for (int i = tid; i < nnx; i += 256) kx[i] = key_xline(cxf + i);
+        for (int q = tid; q < nny * nnz; q += 256) {
+            const int k = q / nny, j = q - k * nny;
+            kzy[q] = absorb_index(absorb_index(pre, czf + k), cyf + j);
+        }
+        if (tid < TY) {
+            const int r = min(tid, hy - 1);
+            const Coord c = coord_step(Yf + r, f);
+            float s, b10, b11;
+            Basis<M>::eval(c.t, s, b10, b11);
+            yt[tid] = make_float4(__int_as_float((int)(c.cell - cyf)), s, b10, b11);
+        } else if (tid >= 64 && tid < 64 + TZ) {
+            const int r = min(tid - 64, hz - 1);
+            const Coord c = coord_step(Zf + r, f);
+            float s, b10, b11;
+            Basis<M>::eval(c.t, s, b10, b11);
+            zt[tid - 64] = make_float4(__int_as_float((int)(c.cell - czf)), s, b10, b11);
+        }
+        __syncthreads();
+        const int plane = nnx * nny;
+        for (int q = tid; q < plane * nnz; q += 256) {
+            const int row = q / nnx, i = q - row * nnx;  // row = k * nny + j
+            const float3 g = grad3(key_combine(kzy[row], kx[i]));
+            gxs[q] = g.x * amp;
+            gys[q] = g.y * amp;
+            gzs[q] = g.z * amp;
+        }
+        const Coord cc = coord_step(X, f);
+        const int lcx = (int)(cc.cell - cxf);
+        float sx, b10x, b11x;
+        Basis<M>::eval(cc.t, sx, b10x, b11x);
+        __syncthreads();
+
+        int prev_cell = -1;
+        float ca[2][2], cb[2][2], cc2[2][2];  // x-collapsed coefficients [cy][cz]
+#pragma unroll
+        for (int zz = 0; zz < ZPW; ++zz) {
+            const float4 ze = zt[wave * ZPW + zz];
+            const int lcz = __builtin_amdgcn_readfirstlane(__float_as_int(ze.x));
+            float E0 = 0.0f, dE = 0.0f, Q0 = 0.0f, Q1 = 0.0f;
+            int prev_y = -1;
+#pragma unroll
+            for (int yy = 0; yy < TY; ++yy) {
+                const float4 ye = yt[yy];
+                const int lcy = __builtin_amdgcn_readfirstlane(__float_as_int(ye.x));
+                const int cell = lcz * 65536 + lcy;
+                if (cell != prev_cell) {
+                    prev_cell = cell;
+#pragma unroll
+                    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+                        for (int cy = 0; cy < 2; ++cy) {
+                            const int q = ((lcz + cz) * nny + (lcy + cy)) * nnx + lcx;
+                            ca[cy][cz] = gxs[q] * b10x + gxs[q + 1] * b11x;
+                            cb[cy][cz] = gys[q] + sx * (gys[q + 1] - gys[q]);
+                            cc2[cy][cz] = gzs[q] + sx * (gzs[q + 1] - gzs[q]);
+                        }
+                    prev_y = -1;
+                }
+                if (lcy != prev_y) {
+                    prev_y = lcy;
+                    float Ev[2], Bq[2];
+#pragma unroll
+                    for (int cy = 0; cy < 2; ++cy) {
+                        const float A = ca[cy][0] + ze.y * (ca[cy][1] - ca[cy][0]);
+                        const float C = cc2[cy][0] * ze.z + cc2[cy][1] * ze.w;
+                        Bq[cy] = cb[cy][0] + ze.y * (cb[cy][1] - cb[cy][0]);
+                        Ev[cy] = A + C;
+                    }
+                    E0 = Ev[0];
+                    dE = Ev[1] - Ev[0];
+                    Q0 = Bq[0];
+                    Q1 = Bq[1];
+                }
+                acc[zz * TY + yy] += E0 + dE * ye.y + Q0 * ye.z + Q1 * ye.w;
+            }
+        }
+    }
+
+    if (lane < w) {
+        OutT *out = reinterpret_cast<OutT *>(a.out);
+#pragma unroll
+        for (int zz = 0; zz < ZPW; ++zz) {
+            const int z = wave * ZPW + zz;
+            if (z >= hz) continue;
+#pragma unroll
+            for (int yy = 0; yy < TY; ++yy) {
+                if (yy >= hy) continue;
+                out[((tz0 + z) * a.ny + (ty0 + yy)) * a.nx + tx0 + lane] = to_out<OutT>(acc[zz * TY + yy]);
+            }
+        }
+    }
+}
+
+}  // namespace ptg

@@ -1,0 +1,634 @@
+// ptg_serve.hip -- continuous-batching tile server (a6): a persistent kernel draining a
+// work-item ring in pinned host memory, and a host scheduler that admits requests by HBM
+// budget, publishes their work items while earlier ones run, and completes them.
+//
+// Protocol (host = scheduler thread, device = persistent kernel):
+//   * request table reqs[slot] and ring items are written by the host first; then the
+//     host publishes them with a release store of ctl->tail (pinned, fine-grained memory);
+//   * a workgroup claims item `head` (device atomic in device memory) while head < tail,
+//     read with system-scope acquire; it reads the item and the request descriptor with
+//     system-scope loads, computes its tiles with the general K3 tile functions, then adds
+//     its tile count to done_tiles[slot] (device memory); the workgroup that brings it to
+//     the request's target stores the request's sequence number into done[slot] (pinned
+//     memory, system-scope release) after a system fence;
+//   * the host sees done[slot] == seq, completes the request, and only then reuses the
+//     slot and the request's ring entries (ring space is reclaimed in ring order);
+//   * the kernel leaves when the host sets ctl->shutdown or after an idle spin limit; the
+//     host relaunches it whenever published work is outstanding and the stream is idle.
+// done_tiles[] only grows: each request's target is the slot's running total, so no
+// device memory is ever reset from the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "ptg_general_tile.h"
+#include "ptg_internal.h"
+
+namespace ptg {
+
+constexpr int kReqSlots = 1024;            // requests admitted at once
+constexpr size_t kServeLds = 64 * 1024;    // dynamic LDS of a serving workgroup
+constexpr int kTilesPerItem = 4;           // sample tiles per work item
+constexpr int kIdleSpins = 20000;          // ~30 ms of polling before an idle kernel exits
+constexpr int64_t kStarveNs = 50000000;    // after 50 ms a waiting request blocks later ones
+
+struct ServeReqDesc {
+    int32_t dim, smooth, slot;
+    uint32_t seq;
+    uint64_t target;  // done_tiles[slot] when this request is complete
+    int64_t ntiles;
+    union {
+        Fbm2dArgs a2;
+        Fbm3dArgs a3;
+    };
+};
+static_assert(sizeof(ServeReqDesc) % 8 == 0, "descriptor is copied in 8-byte words");
+
+struct ServeItem {
+    int32_t slot;
+    int32_t ntiles;
+    int64_t tile0;
+};
+
+struct ServeHostCtl {  // pinned host memory
+    uint64_t tail;
+    int32_t shutdown;
+    int32_t pad;
+};
+
+struct ServeDevCtl {  // device memory
+    uint64_t head;
+    uint64_t done_tiles[kReqSlots];
+};
+
+__device__ __forceinline__ uint64_t sys_load64(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ __launch_bounds__(256) void k_serve(ServeHostCtl *hc, const ServeItem *ring, const ServeReqDesc *reqs,
+                                               uint32_t *done, ServeDevCtl *dc, int32_t ring_size)
+{
+    extern __shared__ float4 lds4[];
+    __shared__ uint64_t s_req[sizeof(ServeReqDesc) / 8];
+    __shared__ int s_cmd;
+    __shared__ ServeItem s_item;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            int cmd = 0;
+            uint64_t idx = 0;
+            for (int spin = 0; spin < kIdleSpins;) {
+                const uint64_t tail = __hip_atomic_load(&hc->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                uint64_t head = __hip_atomic_load(&dc->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (head < tail) {
+                    if (__hip_atomic_compare_exchange_strong(&dc->head, &head, head + 1, __ATOMIC_ACQUIRE,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        idx = head;
+                        cmd = 1;
+                        break;
+                    }
+                    continue;  // another workgroup took it; head only grows up to tail
+                }
+                if (__hip_atomic_load(&hc->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
+                __builtin_amdgcn_s_sleep(127);
+                ++spin;
+            }
+            if (cmd == 1) {
+                const uint64_t *w = reinterpret_cast<const uint64_t *>(ring + (idx % (uint64_t)ring_size));
+                const uint64_t w0 = sys_load64(w), w1 = sys_load64(w + 1);
+                s_item.slot = (int32_t)(w0 & 0xFFFFFFFFu);
+                s_item.ntiles = (int32_t)(w0 >> 32);
+                s_item.tile0 = (int64_t)w1;
+            }
+            s_cmd = cmd;
+        }
+        __syncthreads();
+        if (s_cmd != 1) return;  // shutdown or idle: every wave of the workgroup leaves
+        {
+            const uint64_t *src = reinterpret_cast<const uint64_t *>(reqs + s_item.slot);
+            for (int i = tid; i < (int)(sizeof(ServeReqDesc) / 8); i += 256) s_req[i] = sys_load64(src + i);
+        }
+        __syncthreads();
+        const ServeReqDesc &rq = *reinterpret_cast<const ServeReqDesc *>(s_req);
+        const int64_t t1 = s_item.tile0 + s_item.ntiles;
+        for (int64_t t = s_item.tile0; t < t1; ++t) {
+            if (rq.dim == 2) {
+                if (rq.smooth == 1)
+                    fbm2d_general_tile<1, float>(rq.a2, t, lds4);
+                else
+                    fbm2d_general_tile<2, float>(rq.a2, t, lds4);
+            } else {
+                if (rq.smooth == 1)
+                    fbm3d_general_tile<1, float>(rq.a3, t, lds4);
+                else
+                    fbm3d_general_tile<2, float>(rq.a3, t, lds4);
+            }
+            __syncthreads();  // LDS reuse by the next tile
+        }
+        if (tid == 0) {
+            __threadfence_system();  // this workgroup's output is visible before it is counted
+            const uint64_t n = (uint64_t)s_item.ntiles;
+            const uint64_t old = __hip_atomic_fetch_add(&dc->done_tiles[rq.slot], n, __ATOMIC_ACQ_REL,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            if (old + n == rq.target) {
+                __threadfence_system();
+                __hip_atomic_store(done + rq.slot, rq.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        __syncthreads();  // s_req / s_item are rewritten by the next claim
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------------
+static int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// First-fit allocator over [0, size) with 256-byte granules.
+class Arena {
+  public:
+    explicit Arena(int64_t size) { free_[0] = size; }
+    int64_t alloc(int64_t bytes)
+    {
+        bytes = (bytes + 255) & ~int64_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const int64_t off = it->first, rest = it->second - bytes;
+                free_.erase(it);
+                if (rest > 0) free_[off + bytes] = rest;
+                used_ += bytes;
+                return off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t bytes)
+    {
+        bytes = (bytes + 255) & ~int64_t(255);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    int64_t used() const { return used_; }
+
+  private:
+    int64_t used_ = 0;
+    std::map<int64_t, int64_t> free_;
+};
+
+struct Request {
+    ptg_tile_req req;
+    int64_t bytes = 0, ntiles = 0, arena_off = -1;
+    int32_t slot = -1;
+    uint32_t seq = 0;
+    uint64_t ring_begin = 0, ring_end = 0;
+    int status = 1;  // 1: pending, 2: in flight, PTG_OK / error: complete
+    int64_t t_submit = 0, t_admit = 0, t_done = 0, fake_done_at = 0;
+};
+
+}  // namespace ptg
+
+struct ptg_server {
+    ptg_server_cfg cfg{};
+    bool gpu = true;
+    hipStream_t stream = nullptr;
+    int workgroups = 0;
+    ptg::ServeHostCtl *hc = nullptr;
+    ptg::ServeItem *ring = nullptr;
+    ptg::ServeReqDesc *reqs = nullptr;
+    uint32_t *done = nullptr;
+    ptg::ServeDevCtl *dc = nullptr;
+    char *arena_mem = nullptr;
+    std::unique_ptr<ptg::Arena> arena;
+
+    std::mutex mu;
+    std::condition_variable cv_done, cv_work;
+    std::map<uint64_t, ptg::Request> by_ticket;
+    std::deque<uint64_t> pending;
+    std::vector<uint64_t> inflight;
+    struct RingSpan {
+        uint64_t ticket, end;
+        bool done;
+    };
+    std::deque<RingSpan> ring_order;  // admitted requests in ring order
+    std::vector<int32_t> free_slots;
+    std::vector<uint64_t> slot_total;
+    uint64_t next_ticket = 1, tail = 0, reclaimed = 0;
+    uint32_t seq = 0;
+    bool stopping = false, quit = false;
+    bool kernel_running = false;
+    int64_t fake_busy_until = 0;
+    ptg_server_stats st{};
+    std::thread th;
+    std::string err;
+};
+
+namespace ptg {
+
+static void complete(ptg_server *s, uint64_t ticket, int status)
+{
+    Request &r = s->by_ticket[ticket];
+    r.status = status;
+    r.t_done = now_ns();
+    if (r.slot >= 0) s->free_slots.push_back(r.slot);
+    // ring entries are reused in ring order: reclaim up to the first unfinished request
+    for (auto &e : s->ring_order)
+        if (e.ticket == ticket) e.done = true;
+    while (!s->ring_order.empty() && s->ring_order.front().done) {
+        s->reclaimed = s->ring_order.front().end;
+        s->ring_order.pop_front();
+    }
+    s->st.completed++;
+    if (status == PTG_OK) s->st.tiles_done += r.ntiles;
+    s->cv_done.notify_all();
+}
+
+static void publish(ptg_server *s, uint64_t ticket, Request &r)
+{
+    const int32_t slot = s->free_slots.back();
+    s->free_slots.pop_back();
+    r.slot = slot;
+    r.seq = ++s->seq;
+    r.t_admit = now_ns();
+    r.status = 2;
+    const uint64_t items = (r.ntiles + kTilesPerItem - 1) / kTilesPerItem;
+    r.ring_begin = s->tail;
+    r.ring_end = s->tail + items;
+    s->ring_order.push_back({ticket, r.ring_end, false});
+    s->inflight.push_back(ticket);
+    s->st.admitted++;
+    s->st.bytes_in_use = s->arena->used();
+    s->st.bytes_peak = std::max(s->st.bytes_peak, s->st.bytes_in_use);
+    if (!s->gpu) {
+        s->fake_busy_until = std::max(s->fake_busy_until, r.t_admit) + r.ntiles * s->cfg.fake_tile_ns;
+        r.fake_done_at = s->fake_busy_until;
+        s->tail = r.ring_end;
+        return;
+    }
+    ServeReqDesc d;
+    std::memset(&d, 0, sizeof(d));
+    const ptg_params *p = &r.req.params;
+    void *out = s->arena_mem + r.arena_off;
+    d.dim = p->dim;
+    d.smooth = p->smoothness;
+    d.slot = slot;
+    d.seq = r.seq;
+    s->slot_total[slot] += (uint64_t)r.ntiles;
+    d.target = s->slot_total[slot];
+    d.ntiles = r.ntiles;
+    if (p->dim == 2)
+        general_args_2d(p, r.req.origin[0], r.req.origin[1], r.req.extent[0], r.req.extent[1], out, r.req.extent[0],
+                        &d.a2);
+    else
+        general_args_3d(p, r.req.origin[0], r.req.origin[1], r.req.origin[2], r.req.extent[0], r.req.extent[1],
+                        r.req.extent[2], out, &d.a3);
+    std::memcpy(&s->reqs[slot], &d, sizeof(d));
+    for (uint64_t i = 0; i < items; ++i) {
+        ServeItem it;
+        it.slot = slot;
+        it.tile0 = (int64_t)i * kTilesPerItem;
+        it.ntiles = (int32_t)std::min<int64_t>(kTilesPerItem, r.ntiles - it.tile0);
+        std::memcpy(&s->ring[(r.ring_begin + i) % (uint64_t)s->cfg.max_items], &it, sizeof(it));
+    }
+    s->tail = r.ring_end;
+    std::atomic_thread_fence(std::memory_order_release);
+    __atomic_store_n(&s->hc->tail, s->tail, __ATOMIC_RELEASE);
+}
+
+static void admit(ptg_server *s)
+{
+    const int64_t now = now_ns();
+    for (auto it = s->pending.begin(); it != s->pending.end();) {
+        Request &r = s->by_ticket[*it];
+        const uint64_t items = (r.ntiles + kTilesPerItem - 1) / kTilesPerItem;
+        if (s->free_slots.empty()) break;
+        if (s->tail + items - s->reclaimed > (uint64_t)s->cfg.max_items) break;  // ring order is FIFO
+        const int64_t off = s->arena->alloc(r.bytes);
+        if (off < 0) {
+            if (now - r.t_submit > kStarveNs) break;  // it waited long enough: nobody passes it
+            ++it;
+            continue;
+        }
+        r.arena_off = off;
+        const uint64_t ticket = *it;
+        it = s->pending.erase(it);
+        publish(s, ticket, r);
+    }
+}
+
+static void poll_done(ptg_server *s)
+{
+    const int64_t now = now_ns();
+    for (size_t i = 0; i < s->inflight.size();) {
+        Request &r = s->by_ticket[s->inflight[i]];
+        const bool fin = s->gpu ? (__atomic_load_n(&s->done[r.slot], __ATOMIC_ACQUIRE) == r.seq) : (now >= r.fake_done_at);
+        if (fin) {
+            complete(s, s->inflight[i], PTG_OK);
+            s->inflight[i] = s->inflight.back();
+            s->inflight.pop_back();
+        } else {
+            ++i;
+        }
+    }
+}
+
+static void fail_inflight(ptg_server *s, int status)
+{
+    for (uint64_t t : s->inflight) complete(s, t, status);
+    s->inflight.clear();
+}
+
+static void ensure_kernel(ptg_server *s)
+{
+    if (!s->gpu || s->inflight.empty()) return;
+    if (s->kernel_running) {
+        const hipError_t q = hipStreamQuery(s->stream);
+        if (q == hipErrorNotReady) return;
+        s->kernel_running = false;
+        if (q != hipSuccess) {
+            s->err = hipGetErrorString(q);
+            fail_inflight(s, PTG_EHIP);
+            return;
+        }
+    }
+    hipLaunchKernelGGL(k_serve, dim3(s->workgroups), dim3(256), kServeLds, s->stream, s->hc, s->ring, s->reqs, s->done,
+                       s->dc, s->cfg.max_items);
+    if (hipGetLastError() != hipSuccess) {
+        fail_inflight(s, PTG_EHIP);
+        return;
+    }
+    s->kernel_running = true;
+    s->st.kernel_launches++;
+}
+
+static void service(ptg_server *s)
+{
+    if (s->gpu) (void)hipSetDevice(s->cfg.device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        if (!s->stopping) admit(s);
+        poll_done(s);
+        ensure_kernel(s);
+        if (s->stopping && s->inflight.empty()) break;
+        if (s->inflight.empty()) {
+            s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+        } else {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        }
+    }
+}
+
+static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *bytes, int64_t *ntiles)
+{
+    const ptg_params *p = &r->params;
+    if (!p || (p->dim != 2 && p->dim != 3)) return fail(PTG_EINVAL, "request dim must be 2 or 3");
+    int rc = validate_params(p, p->dim);
+    if (rc) return rc;
+    if (p->form != PTG_FORM_PLAIN || p->out_dtype != PTG_F32)
+        return fail(PTG_EINVAL, "served tiles use the plain form with FP32 output");
+    const int nd = p->dim;
+    for (int a = 0; a < 3; ++a) {
+        if (a < nd) {
+            if (r->extent[a] < 1) return fail(PTG_EINVAL, "request extent must be >= 1");
+            if ((rc = validate_extent("tile", r->origin[a], r->extent[a]))) return rc;
+        } else if (r->extent[a] != 1 || r->origin[a] != 0) {
+            return fail(PTG_EINVAL, "a 2D request has extent[2] = 1 and origin[2] = 0");
+        }
+    }
+    const int64_t nx = r->extent[0], ny = r->extent[1], nz = r->extent[2];
+    if (nx > (1LL << 40) / ny || nx * ny > (1LL << 40) / nz) return fail(PTG_EINVAL, "request too large");
+    *bytes = nx * ny * nz * 4;
+    double freq[kMaxOctaves];
+    float amp[kMaxOctaves];
+    octave_tables(p, freq, amp);
+    size_t lds;
+    if (nd == 2) {
+        *ntiles = ((nx + kTile2 - 1) / kTile2) * ((ny + kTile2 - 1) / kTile2);
+        const int c = footprint_cap(freq, p->octaves, kTile2);
+        lds = (size_t)kTile2 * 16 + (size_t)c * c * 8 + (size_t)2 * c * 4;
+    } else {
+        *ntiles = ((nx + kTile3X - 1) / kTile3X) * ((ny + kTile3Y - 1) / kTile3Y) * ((nz + kTile3Z - 1) / kTile3Z);
+        const int cx = footprint_cap(freq, p->octaves, kTile3X), cy = footprint_cap(freq, p->octaves, kTile3Y),
+                  cz = footprint_cap(freq, p->octaves, kTile3Z);
+        lds = (size_t)(kTile3Y + kTile3Z) * 16 + (size_t)cx * cy * cz * 12 + (size_t)(cx + cy * cz) * 4;
+    }
+    if (lds > kServeLds) return fail(PTG_EINVAL, "the request's lattice is too fine for a serving workgroup");
+    if (*ntiles > 0x7FFFFFFFLL) return fail(PTG_EINVAL, "request too large");
+    const uint64_t items = (*ntiles + kTilesPerItem - 1) / kTilesPerItem;
+    if (items > (uint64_t)s->cfg.max_items) return fail(PTG_E2BIG, "request needs more work items than the ring holds");
+    if (((*bytes + 255) & ~int64_t(255)) > s->cfg.hbm_budget_bytes)
+        return fail(PTG_E2BIG, "request output (%lld bytes) exceeds the budget", (long long)*bytes);
+    return PTG_OK;
+}
+
+static void free_server(ptg_server *s)
+{
+    if (s->gpu) {
+        if (s->stream) (void)hipStreamDestroy(s->stream);
+        if (s->hc) (void)hipHostFree(s->hc);
+        if (s->ring) (void)hipHostFree(s->ring);
+        if (s->reqs) (void)hipHostFree(s->reqs);
+        if (s->done) (void)hipHostFree(s->done);
+        if (s->dc) (void)hipFree(s->dc);
+        if (s->arena_mem) (void)hipFree(s->arena_mem);
+    } else {
+        std::free(s->arena_mem);
+    }
+    delete s;
+}
+
+}  // namespace ptg
+
+using namespace ptg;
+
+extern "C" {
+
+int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out)
+{
+    if (!cfg || !out) return fail(PTG_EINVAL, "NULL argument");
+    if (cfg->hbm_budget_bytes <= 0) return fail(PTG_EINVAL, "hbm_budget_bytes must be > 0");
+    if (cfg->max_items < 64 || cfg->max_items > (1 << 24)) return fail(PTG_EINVAL, "max_items must be in 64..2^24");
+    if (cfg->workgroups < 0 || cfg->workgroups > 65536) return fail(PTG_EINVAL, "bad workgroup count");
+    if (cfg->executor != PTG_EXEC_GPU && cfg->executor != PTG_EXEC_HOST) return fail(PTG_EINVAL, "bad executor");
+    if (cfg->executor == PTG_EXEC_HOST && cfg->fake_tile_ns < 0) return fail(PTG_EINVAL, "fake_tile_ns < 0");
+    *out = nullptr;
+    ptg_server *s = new ptg_server();
+    s->cfg = *cfg;
+    s->gpu = cfg->executor == PTG_EXEC_GPU;
+    s->st.budget = cfg->hbm_budget_bytes;
+    for (int i = kReqSlots - 1; i >= 0; --i) s->free_slots.push_back(i);
+    s->slot_total.assign(kReqSlots, 0);
+    s->arena.reset(new Arena(cfg->hbm_budget_bytes));
+    if (s->gpu) {
+        hipError_t e = hipSetDevice(cfg->device);
+        if (e != hipSuccess) {
+            free_server(s);
+            return hip_fail(e, "hipSetDevice");
+        }
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device) != hipSuccess || cus <= 0)
+            cus = 256;
+        s->workgroups = cfg->workgroups > 0 ? cfg->workgroups : 2 * cus;
+        e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&s->hc, sizeof(ServeHostCtl), hipHostMallocCoherent);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&s->ring, sizeof(ServeItem) * (size_t)cfg->max_items, hipHostMallocCoherent);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&s->reqs, sizeof(ServeReqDesc) * kReqSlots, hipHostMallocCoherent);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&s->done, sizeof(uint32_t) * kReqSlots, hipHostMallocCoherent);
+        if (e == hipSuccess) e = hipMalloc((void **)&s->dc, sizeof(ServeDevCtl));
+        if (e == hipSuccess) e = hipMemset(s->dc, 0, sizeof(ServeDevCtl));
+        if (e == hipSuccess) e = hipMalloc((void **)&s->arena_mem, (size_t)cfg->hbm_budget_bytes);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_serve),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kServeLds);
+        if (e != hipSuccess) {
+            const int code = (e == hipErrorOutOfMemory) ? PTG_ENOMEM : PTG_EHIP;
+            hip_fail(e, "server allocation");
+            free_server(s);
+            return code;
+        }
+        std::memset(s->hc, 0, sizeof(ServeHostCtl));
+        std::memset(s->done, 0, sizeof(uint32_t) * kReqSlots);
+    } else {
+        s->arena_mem = static_cast<char *>(std::malloc((size_t)cfg->hbm_budget_bytes));
+        if (!s->arena_mem) {
+            free_server(s);
+            return fail(PTG_ENOMEM, "arena allocation");
+        }
+    }
+    s->th = std::thread(service, s);
+    *out = s;
+    return PTG_OK;
+}
+
+int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n, uint64_t *tickets_out)
+{
+    if (!s || (n > 0 && (!reqs || !tickets_out)) || n < 0) return fail(PTG_EINVAL, "bad arguments");
+    std::vector<int64_t> bytes(n), tiles(n);
+    for (int32_t i = 0; i < n; ++i) {
+        const int rc = validate_req(s, &reqs[i], &bytes[i], &tiles[i]);
+        if (rc) return rc;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return fail(PTG_ESHUTDOWN, "server is shutting down");
+    const int64_t t = now_ns();
+    for (int32_t i = 0; i < n; ++i) {
+        const uint64_t ticket = s->next_ticket++;
+        Request &r = s->by_ticket[ticket];
+        r.req = reqs[i];
+        r.bytes = bytes[i];
+        r.ntiles = tiles[i];
+        r.t_submit = t;
+        s->pending.push_back(ticket);
+        tickets_out[i] = ticket;
+        s->st.submitted++;
+    }
+    s->cv_work.notify_all();
+    return PTG_OK;
+}
+
+int ptg_tiles_wait(ptg_server *s, uint64_t ticket, int64_t timeout_ns, ptg_tile_result *res)
+{
+    if (!s || !res) return fail(PTG_EINVAL, "bad arguments");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->by_ticket.find(ticket);
+    if (it == s->by_ticket.end()) return fail(PTG_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    auto ready = [&] {
+        auto j = s->by_ticket.find(ticket);
+        return j == s->by_ticket.end() || j->second.status <= 0;
+    };
+    if (timeout_ns < 0)
+        s->cv_done.wait(lk, ready);
+    else if (timeout_ns > 0)
+        s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), ready);
+    it = s->by_ticket.find(ticket);
+    if (it == s->by_ticket.end()) return fail(PTG_ENOENT, "ticket released");
+    const Request &r = it->second;
+    if (r.status > 0) return fail(PTG_ETIMEDOUT, "request still pending");
+    std::memset(res, 0, sizeof(*res));
+    res->status = r.status;
+    res->out_dev = (r.status == PTG_OK) ? s->arena_mem + r.arena_off : nullptr;
+    res->bytes = r.bytes;
+    res->user_tag = r.req.user_tag;
+    res->t_submit_ns = r.t_submit;
+    res->t_admit_ns = r.t_admit;
+    res->t_done_ns = r.t_done;
+    return PTG_OK;
+}
+
+int ptg_tile_release(ptg_server *s, uint64_t ticket)
+{
+    if (!s) return fail(PTG_EINVAL, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->by_ticket.find(ticket);
+    if (it == s->by_ticket.end()) return fail(PTG_ENOENT, "unknown ticket");
+    if (it->second.status > 0) return fail(PTG_EAGAIN, "request not complete");
+    if (it->second.arena_off >= 0) s->arena->release(it->second.arena_off, it->second.bytes);
+    s->by_ticket.erase(it);
+    s->st.released++;
+    s->st.bytes_in_use = s->arena->used();
+    s->cv_work.notify_all();
+    return PTG_OK;
+}
+
+int ptg_server_stats_get(ptg_server *s, ptg_server_stats *st)
+{
+    if (!s || !st) return fail(PTG_EINVAL, "bad arguments");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *st = s->st;
+    st->pending = (int64_t)s->pending.size();
+    st->in_flight = (int64_t)s->inflight.size();
+    st->bytes_in_use = s->arena->used();
+    return PTG_OK;
+}
+
+int ptg_server_destroy(ptg_server *s)
+{
+    if (!s) return fail(PTG_EINVAL, "NULL server");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+        for (uint64_t t : s->pending) complete(s, t, PTG_ESHUTDOWN);
+        s->pending.clear();
+        s->cv_work.notify_all();
+    }
+    s->th.join();
+    int rc = PTG_OK;
+    if (s->gpu) {
+        __atomic_store_n(&s->hc->shutdown, 1, __ATOMIC_RELEASE);
+        const hipError_t e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "server kernel");
+    }
+    free_server(s);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+"""GPU tile server: every served tile equals the stand-alone call of the same request
+(general kernel) bit for bit, alone and in a mixed, continuously arriving stream; samples
+agree with the FP64 oracle within 1e-5 * A."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+torch = pytest.importorskip("torch")
+import paper_1610_03525_amd as ptg  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+F0 = 2.0 ** -12
+
+
+def _mix(n, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        dim = 3 if rng.random() < 0.2 else 2
+        smooth = int(rng.integers(1, 3))
+        if dim == 2:
+            side = int(rng.choice([16, 64, 100, 128, 256, 300]))
+            octs = int(rng.integers(4, 13))
+            ext = (side, int(rng.choice([side, side // 2 + 3])), 1)
+        else:
+            side = int(rng.choice([8, 32, 64]))
+            octs = int(rng.integers(4, 9))
+            ext = (side, side, int(rng.choice([side, 5])))
+        org = tuple(int(v) for v in rng.integers(-(1 << 46), 1 << 46, size=dim)) + (0,) * (3 - dim)
+        reqs.append(dict(dim=dim, smoothness=smooth, octaves=octs, base_freq=F0, persistence=0.5, lacunarity=2.0,
+                         seed=int(rng.integers(0, 1 << 32)), origin=org, extent=ext, user_tag=i))
+    return reqs
+
+
+def _solo(r):
+    nx, ny, nz = r["extent"]
+    kw = dict(smoothness=r["smoothness"], octaves=r["octaves"], base_freq=r["base_freq"], seed=r["seed"],
+              persistence=r["persistence"], lacunarity=r["lacunarity"])
+    if r["dim"] == 2:
+        out = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+        ptg.fbm_2d(out, x0=r["origin"][0], y0=r["origin"][1], path="general", **kw)
+    else:
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
+        ptg.fbm_3d(out, x0=r["origin"][0], y0=r["origin"][1], z0=r["origin"][2], **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+def _fetch(res, r):
+    nx, ny, nz = r["extent"]
+    t = torch.empty((nz, ny, nx) if r["dim"] == 3 else (ny, nx), dtype=torch.float32, device="cuda")
+    ptg.device_copy(t.data_ptr(), res.out_dev, res.bytes)
+    return t
+
+
+def _tile_req(r):
+    q = dict(r)
+    return ptg.tile_req(dim=q.pop("dim"), origin=q.pop("origin"), extent=q.pop("extent"), user_tag=q.pop("user_tag"),
+                        **q)
+
+
+def test_served_tiles_equal_solo_calls_bit_exact():
+    reqs = _mix(40, 1610)
+    with ptg.Server(1 << 30) as srv:
+        tickets = srv.submit([_tile_req(r) for r in reqs])
+        for t, r in zip(tickets, reqs):
+            res = srv.wait(t, int(60e9))
+            assert res.status == ptg.PTG_OK and res.user_tag == r["user_tag"]
+            got = _fetch(res, r)
+            srv.release(t)
+            assert torch.equal(got, _solo(r)), r
+        st = srv.stats()
+        assert st["completed"] == 40 and st["bytes_peak"] <= (1 << 30)
+
+
+def test_alone_and_in_a_continuous_mix_are_identical():
+    reqs = _mix(30, 7)
+    probe = reqs[5]
+    with ptg.Server(1 << 29) as srv:
+        (t_alone,) = srv.submit([_tile_req(probe)])
+        alone = _fetch(srv.wait(t_alone, int(60e9)), probe)
+        srv.release(t_alone)
+        got = {}
+
+        def submitter():
+            for r in reqs:  # arrivals spread in time, submitted while others run
+                got[r["user_tag"]] = srv.submit([_tile_req(r)])[0]
+                time.sleep(0.002)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        for r in reqs:
+            res = srv.wait(got[r["user_tag"]], int(60e9))
+            assert res.status == ptg.PTG_OK
+            if r is probe:
+                assert torch.equal(_fetch(res, r), alone)
+            srv.release(got[r["user_tag"]])
+
+
+def test_kernel_relaunches_after_idle_and_small_budget_admission():
+    reqs = _mix(12, 3)
+    biggest = max(r["extent"][0] * r["extent"][1] * r["extent"][2] * 4 for r in reqs)
+    with ptg.Server(biggest + 4096) as srv:  # room for about one request at a time
+        tickets = srv.submit([_tile_req(r) for r in reqs[:6]])
+        for t, r in zip(tickets, reqs[:6]):
+            res = srv.wait(t, int(60e9))
+            assert torch.equal(_fetch(res, r), _solo(r))
+            srv.release(t)
+        time.sleep(0.4)  # the persistent kernel exits after ~0.1 s of idling
+        tickets = srv.submit([_tile_req(r) for r in reqs[6:]])
+        for t, r in zip(tickets, reqs[6:]):
+            res = srv.wait(t, int(60e9))
+            assert torch.equal(_fetch(res, r), _solo(r))
+            srv.release(t)
+        st = srv.stats()
+        assert st["kernel_launches"] >= 2 and st["bytes_peak"] <= biggest + 4096
+
+
+def test_served_samples_match_oracle():
+    r = dict(dim=2, smoothness=2, octaves=12, base_freq=F0, persistence=0.5, lacunarity=2.0, seed=99,
+             origin=((1 << 40) + 17, -(1 << 41) - 3, 0), extent=(200, 150, 1), user_tag=1)
+    with ptg.Server(1 << 24) as srv:
+        (t,) = srv.submit([_tile_req(r)])
+        g = _fetch(srv.wait(t, int(60e9)), r).cpu().numpy().astype(np.float64)
+        srv.release(t)
+    rng = np.random.default_rng(0)
+    i = rng.integers(0, 200, 500)
+    j = rng.integers(0, 150, 500)
+    ref = O.fbm_points_2d(2, 12, 0.5, 2.0, F0, 99, r["origin"][0] + i, r["origin"][1] + j)
+    assert np.max(np.abs(g[j, i] - ref)) <= 1e-5 * sum(0.5 ** o for o in range(12))

@@ -1,0 +1,147 @@
+"""Scheduler logic of the tile server on the CPU (test-only host executor: no GPU, tiles
+"complete" after a fixed time each, outputs are not computed).  Checks admission by
+budget, rejection of oversized or invalid requests, no starvation, ordering, timeouts,
+release rules and shutdown."""
+import time
+
+import pytest
+
+import paper_1610_03525_amd as ptg
+
+F0 = 2.0 ** -12
+
+
+def _srv(budget, tile_ns=20000, max_items=1 << 12):
+    return ptg.Server(budget, max_items=max_items, executor=ptg.PTG_EXEC_HOST, fake_tile_ns=tile_ns)
+
+
+def _req(side, dim=2, tag=0, octaves=6, smooth=1):
+    ext = (side, side, 1) if dim == 2 else (side, side, side)
+    return ptg.tile_req(dim=dim, origin=(0, 0, 0), extent=ext, user_tag=tag, octaves=octaves, base_freq=F0,
+                        smoothness=smooth)
+
+
+def _wait_all(s, tickets, timeout_s=20.0):
+    out = []
+    for t in tickets:
+        out.append(s.wait(t, int(timeout_s * 1e9)))
+    return out
+
+
+def test_budget_is_never_exceeded_and_all_complete():
+    budget = 3 * 256 * 256 * 4  # room for three 256^2 tiles
+    with _srv(budget) as s:
+        tickets = s.submit([_req(256, tag=i) for i in range(12)])
+        done = 0
+        while done < 12:
+            for t in list(tickets):
+                try:
+                    r = s.wait(t, 0)
+                except ptg.PtgError as e:
+                    assert e.code == ptg.PTG_ETIMEDOUT
+                    continue
+                assert r.status == ptg.PTG_OK
+                s.release(t)
+                tickets.remove(t)
+                done += 1
+            st = s.stats()
+            assert st["bytes_in_use"] <= budget
+            time.sleep(0.001)
+        st = s.stats()
+        assert st["bytes_peak"] <= budget and st["completed"] == 12 and st["released"] == 12
+
+
+def test_rejects_oversized_and_invalid_requests():
+    with _srv(64 * 64 * 4) as s:
+        with pytest.raises(ptg.PtgError) as e:
+            s.submit([_req(128)])
+        assert e.value.code == ptg.PTG_E2BIG
+        bad = _req(64)
+        bad.extent[2] = 2  # a 2D request must have nz = 1
+        with pytest.raises(ptg.PtgError) as e:
+            s.submit([_req(64), bad])
+        assert e.value.code == ptg.PTG_EINVAL
+        assert s.stats()["submitted"] == 0  # none of the batch was queued
+        with pytest.raises(ptg.PtgError):
+            s.submit([ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=2.0)])  # finer than samples
+        with pytest.raises(ptg.PtgError):
+            s.submit([ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=F0, form="mfma_f16")])
+
+
+def test_results_carry_tags_and_ordered_timestamps():
+    with _srv(1 << 24) as s:
+        tickets = s.submit([_req(64, tag=100 + i) for i in range(5)] + [_req(32, dim=3, tag=7, smooth=2)])
+        res = _wait_all(s, tickets)
+        for i, r in enumerate(res[:5]):
+            assert r.user_tag == 100 + i and r.bytes == 64 * 64 * 4
+        assert res[5].user_tag == 7 and res[5].bytes == 32 ** 3 * 4
+        for r in res:
+            assert r.status == ptg.PTG_OK and r.t_submit_ns <= r.t_admit_ns <= r.t_done_ns
+        # admission in arrival order when everything fits
+        admits = [r.t_admit_ns for r in res]
+        assert admits == sorted(admits)
+
+
+def test_no_starvation_of_a_large_request():
+    """A request that does not fit lets later ones pass only until it has waited 50 ms;
+    from then on nothing is admitted before it."""
+    budget = 1024 * 1024 * 4
+    with _srv(budget, tile_ns=200000) as s:
+        small = s.submit([_req(512, tag=i) for i in range(2)])
+        big = s.submit([_req(1024, tag=99)])[0]
+        more = s.submit([_req(256, tag=200 + i) for i in range(40)])
+        res = {}
+        open_t = small + [big] + more
+        t_end = time.time() + 30
+        while open_t and time.time() < t_end:
+            for t in list(open_t):
+                try:
+                    r = s.wait(t, 0)
+                except ptg.PtgError:
+                    continue
+                res[t] = (r.status, r.t_submit_ns, r.t_admit_ns)
+                s.release(t)
+                open_t.remove(t)
+            time.sleep(0.002)
+        assert not open_t, "requests left unfinished"
+        assert all(v[0] == ptg.PTG_OK for v in res.values())
+        b_sub, b_adm = res[big][1], res[big][2]
+        for t in more:
+            if res[t][2] > b_sub + 60_000_000:
+                assert res[t][2] >= b_adm
+
+
+def test_wait_release_rules():
+    with _srv(1 << 20, tile_ns=5_000_000) as s:
+        (t,) = s.submit([_req(128)])
+        with pytest.raises(ptg.PtgError) as e:
+            s.wait(t, 0)
+        assert e.value.code == ptg.PTG_ETIMEDOUT
+        with pytest.raises(ptg.PtgError) as e:
+            s.release(t)
+        assert e.value.code == ptg.PTG_EAGAIN
+        assert s.wait(t, int(5e9)).status == ptg.PTG_OK
+        s.release(t)
+        with pytest.raises(ptg.PtgError) as e:
+            s.release(t)
+        assert e.value.code == ptg.PTG_ENOENT
+        with pytest.raises(ptg.PtgError) as e:
+            s.wait(12345, 0)
+        assert e.value.code == ptg.PTG_ENOENT
+
+
+def test_shutdown_with_work_queued_does_not_hang():
+    s = _srv(256 * 256 * 4, tile_ns=1_000_000)
+    s.submit([_req(256) for _ in range(50)])
+    t0 = time.time()
+    s.close()  # queued ones are completed with PTG_ESHUTDOWN, admitted ones run out
+    assert time.time() - t0 < 10.0
+
+
+def test_create_validation():
+    L = ptg.lib()
+    import ctypes
+    h = ctypes.c_void_p()
+    for cfg in [ptg.ServerCfg(0, 1024, 0, 0, 1, 0), ptg.ServerCfg(1 << 20, 8, 0, 0, 1, 0),
+                ptg.ServerCfg(1 << 20, 1024, 0, 0, 7, 0), ptg.ServerCfg(1 << 20, 1024, -1, 0, 1, 0)]:
+        assert L.ptg_server_create(ctypes.byref(cfg), ctypes.byref(h)) == ptg.PTG_EINVAL
