@@ -8,7 +8,10 @@ evaluation and octave accumulation for the whole field.  Inputs are parameters o
 the output buffer is allocated before the timed region.
 
 Prints ONE JSON line (rank 0).  Extra fields: the measured pure-store write roofline,
-per-kernel event timing, and the FP64 CPU oracle timed on the host cores.
+per-kernel event timing, the FP64 CPU oracle timed on the host cores, and "serving": the
+terrain-tile stream (Poisson arrivals of uneven 2D/3D requests) through the tile server
+against the plain per-tile path, direct and hipGraph-batched: capacity in tiles/s and
+p50/p99 latency at 0.5, 0.8 and 0.95 of the plain path's capacity.
 """
 import argparse
 import json
@@ -52,6 +55,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="wall-time budget of the oracle sample")
     ap.add_argument("--path", default="auto", choices=["auto", "general", "dyadic"])
+    ap.add_argument("--serve-requests", type=int, default=5000, help="tile-stream length (0: skip serving)")
     ap.add_argument("--profile-calibration", action="store_true",
                     help="also run a plain torch fill and copy of the field size (counter calibration)")
     return ap.parse_args()
@@ -151,6 +155,8 @@ def main():
         print(f"field out of bounds: max|H| = {amax}", file=sys.stderr)
         sys.exit(1)
 
+    serving = run_serving(args.serve_requests) if args.serve_requests > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_seconds)
@@ -195,8 +201,130 @@ def main():
             "path_frac_of_measured": achieved_gbs / fill_gbs,
         },
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(rec), flush=True)
+
+
+# ---- tile stream -------------------------------------------------------------------
+SERVE_F0 = 2.0 ** -12  # world-fixed base frequency so that tiles stitch (4096 samples per cell)
+
+
+def tile_stream(n, seed=1610):
+    """Requests of the serving workload: 90% 2D tiles of side in {128..2048} with 4..12
+    octaves, 10% 3D tiles of side in {64, 128, 256} with 4..8 octaves; C1/C2 50/50; int64
+    world origins in [-2^46, 2^46); random 32-bit seeds."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        if rng.random() < 0.9:
+            dim, side, octs = 2, int(rng.choice([128, 256, 512, 1024, 2048])), int(rng.integers(4, 13))
+            ext = (side, side, 1)
+        else:
+            dim, side, octs = 3, int(rng.choice([64, 128, 256])), int(rng.integers(4, 9))
+            ext = (side, side, side)
+        smooth = int(rng.integers(1, 3))
+        org = [int(v) for v in rng.integers(-(1 << 46), 1 << 46, size=3)]
+        if dim == 2:
+            org[2] = 0
+        out.append(dict(dim=dim, smoothness=smooth, octaves=octs, seed=int(rng.integers(0, 1 << 32)),
+                        origin=org, extent=ext))
+    return out
+
+
+def run_serving(n):
+    """The tile stream through the server and through the plain per-tile path (one
+    ptg_fbm_* call per request; auto kernel choice), driven by the native open-loop
+    generator: capacity (all requests at t = 0) and Poisson arrivals at 0.5, 0.8, 0.95 of
+    the plain path's capacity.  Latency = host-visible completion - arrival; p50/p99 over
+    the steady state (the first 10% of requests dropped)."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_1610_03525_amd as ptg
+
+    lg = ctypes.CDLL(os.path.join(os.path.dirname(ptg.LIB_PATH), "libptg_loadgen.so"))
+    p64 = ctypes.POINTER(ctypes.c_int64)
+    lg.ptg_lg_served.argtypes = [ctypes.c_void_p, ctypes.POINTER(ptg.TileReq), p64, ctypes.c_int32, p64, p64]
+    lg.ptg_lg_plain.argtypes = [ctypes.POINTER(ptg.TileReq), p64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                ctypes.c_int32, ctypes.c_int32, p64, p64]
+    reqs = tile_stream(n)
+    treq = (ptg.TileReq * n)()
+    for i, r in enumerate(reqs):
+        treq[i] = ptg.tile_req(dim=r["dim"], origin=r["origin"], extent=r["extent"], user_tag=i,
+                               smoothness=r["smoothness"], octaves=r["octaves"], base_freq=SERVE_F0, seed=r["seed"])
+    osamp = sum(r["extent"][0] * r["extent"][1] * r["extent"][2] * r["octaves"] for r in reqs)
+    arena_bytes = 4 << 30
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+
+    def i64(x):
+        return np.ascontiguousarray(x, dtype=np.int64)
+
+    def ptr(a):
+        return a.ctypes.data_as(p64)
+
+    def summary(arr, done):
+        lat = (done - arr) / 1e6
+        k = n // 10
+        span = (done.max() - arr[0]) / 1e9
+        return {"p50_ms": round(float(np.percentile(lat[k:], 50)), 4),
+                "p99_ms": round(float(np.percentile(lat[k:], 99)), 4),
+                "tiles_s": round(n / span, 1), "octave_samples_s": osamp / span}
+
+    def plain(arr, mode):
+        arr, done, st = i64(arr), i64(np.zeros(n)), i64(np.zeros(1))
+        rc = lg.ptg_lg_plain(treq, ptr(arr), n, arena.data_ptr(), arena_bytes, mode, 64, ptr(done), ptr(st))
+        if rc != 0:
+            raise RuntimeError(f"plain stream failed ({rc}): {ptg.last_error()}")
+        out = summary(arr, done)
+        out["launch_units"] = int(st[0])
+        return out
+
+    def served(arr, budget):
+        arr, done, adm = i64(arr), i64(np.zeros(n)), i64(np.zeros(n))
+        with ptg.Server(budget) as srv:
+            rc = lg.ptg_lg_served(srv.h, treq, ptr(arr), n, ptr(done), ptr(adm))
+            if rc != 0:
+                raise RuntimeError(f"served stream failed ({rc}): {ptg.last_error()}")
+            st = srv.stats()
+        out = summary(arr, done)
+        out["admit_wait_p99_ms"] = round(float(np.percentile((adm - arr)[n // 10:] / 1e6, 99)), 4)
+        out["kernel_launches"] = st["kernel_launches"]
+        out["bytes_peak"] = st["bytes_peak"]
+        return out
+
+    zero = np.zeros(n)
+    cap = {"plain": plain(zero, 0), "plain_graph": plain(zero, 1), "served": served(zero, 4 << 30)}
+    rate = cap["plain"]["tiles_s"]
+    gaps = np.random.default_rng(1611).exponential(1.0, size=n)
+    loads = []
+    for f in (0.5, 0.8, 0.95):
+        arr = np.cumsum(gaps) / (f * rate) * 1e9
+        arr -= arr[0]
+        loads.append({"load": f, "rate_req_s": round(f * rate, 1), "plain": plain(arr, 0),
+                      "plain_graph": plain(arr, 1), "served": served(arr, 4 << 30)})
+    arr = np.cumsum(gaps) / (0.8 * rate) * 1e9
+    arr -= arr[0]
+    budgets = {f"{b}GiB": served(arr, b << 30) for b in (1, 16)}
+    budgets["4GiB"] = loads[1]["served"]
+    del arena
+    return {
+        "workload": "terrain-tile stream: 90% 2D tiles side in {128,256,512,1024,2048}, octaves 4..12; "
+                    "10% 3D tiles side in {64,128,256}, octaves 4..8; C1/C2 50/50; base frequency 2^-12, "
+                    "lacunarity 2, persistence 0.5; random int64 origins and seeds; FP32 output; seed 1610",
+        "requests": n,
+        "octave_samples": osamp,
+        "plain_path": "one ptg_fbm_2d/3d call per request on one stream (auto kernel choice); plain_graph: "
+                      "all requests that have arrived (up to 64) captured into one hipGraph per launch",
+        "served_path": "ptg_tiles_submit into one persistent kernel (general tile kernel), HBM budget 4 GiB",
+        "capacity": cap,
+        "open_loop": loads,
+        "served_budget_at_0.8": budgets,
+    }
 
 
 def cpu_baseline(budget_s):

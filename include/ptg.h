@@ -191,6 +191,9 @@ typedef struct ptg_server_cfg {
     int32_t device;           /* HIP device ordinal                                         */
     int32_t executor;         /* PTG_EXEC_GPU or PTG_EXEC_HOST                              */
     int64_t fake_tile_ns;     /* PTG_EXEC_HOST only: simulated time per tile                */
+    int32_t tiles_per_item;   /* sample tiles per work item, 1..16; 0 = from each request's */
+                              /* size (enough items for every workgroup, at most 16 tiles)  */
+    int32_t reserved;         /* 0                                                          */
 } ptg_server_cfg;
 
 typedef struct ptg_tile_req {
@@ -212,8 +215,11 @@ typedef struct ptg_tile_result {
 } ptg_tile_result;
 
 /* Create a server: allocates the arena, the pinned work-item ring and request table, and
- * starts the scheduler thread; the persistent kernel runs on a stream of its own and is
- * (re)launched whenever work is published and it is not running.
+ * starts the scheduler thread; the persistent kernel runs on a stream of its own, is
+ * launched when work is published and it is not running, and is parked (its workgroups
+ * leave) after 5 ms with nothing in flight.  A device-wide synchronisation (e.g.
+ * hipDeviceSynchronize) therefore returns only once the server's in-flight work is done
+ * and the kernel has parked; synchronise streams instead where that matters.
  * Errors: PTG_EINVAL, PTG_ENOMEM, PTG_EHIP. */
 PTG_API int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out);
 

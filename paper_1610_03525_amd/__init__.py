@@ -64,6 +64,8 @@ class ServerCfg(ctypes.Structure):
         ("device", ctypes.c_int32),
         ("executor", ctypes.c_int32),
         ("fake_tile_ns", ctypes.c_int64),
+        ("tiles_per_item", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -290,8 +292,8 @@ class Server:
     """Continuous-batching tile server (a persistent kernel + host scheduler in libptg)."""
 
     def __init__(self, budget_bytes, max_items=1 << 16, workgroups=0, device=0, executor=PTG_EXEC_GPU,
-                 fake_tile_ns=0):
-        cfg = ServerCfg(budget_bytes, max_items, workgroups, device, executor, fake_tile_ns)
+                 fake_tile_ns=0, tiles_per_item=0):
+        cfg = ServerCfg(budget_bytes, max_items, workgroups, device, executor, fake_tile_ns, tiles_per_item)
         h = ctypes.c_void_p()
         _check(lib().ptg_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.h = h

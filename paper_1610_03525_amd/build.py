@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libptg.so")
+LOADGEN = os.path.join(HERE, "libptg_loadgen.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -49,7 +50,23 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)
     os.replace(LIB + ".tmp", LIB)
+    build_loadgen(verbose)
     return LIB
+
+
+def build_loadgen(verbose: bool = False) -> str:
+    """libptg_loadgen.so: the native open-loop stream driver used by the serving benchmark
+    (host code over libptg's C ABI, found next to it at run time)."""
+    src = os.path.join(HERE, "loadgen", "ptg_loadgen.cpp")
+    cmd = [HIPCC] + FLAGS + ["-I" + os.path.join(HERE, "loadgen"), "-shared", src, "-L" + HERE, "-lptg",
+                             "-Wl,-rpath,$ORIGIN", "-lpthread", "-o", LOADGEN + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if p.returncode != 0:
+        raise RuntimeError("hipcc failed (loadgen):\n" + p.stdout.decode(errors="replace"))
+    os.replace(LOADGEN + ".tmp", LOADGEN)
+    return LOADGEN
 
 
 def _drain(procs):

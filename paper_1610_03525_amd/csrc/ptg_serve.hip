@@ -3,20 +3,29 @@
 // budget, publishes their work items while earlier ones run, and completes them.
 //
 // Protocol (host = scheduler thread, device = persistent kernel):
-//   * request table reqs[slot] and ring items are written by the host first; then the
+//   * the request table reqs[slot] and ring items are written by the host first; then the
 //     host publishes them with a release store of ctl->tail (pinned, fine-grained memory);
-//   * a workgroup claims item `head` (device atomic in device memory) while head < tail,
-//     read with system-scope acquire; it reads the item and the request descriptor with
-//     system-scope loads, computes its tiles with the general K3 tile functions, then adds
-//     its tile count to done_tiles[slot] (device memory); the workgroup that brings it to
-//     the request's target stores the request's sequence number into done[slot] (pinned
-//     memory, system-scope release) after a system fence;
+//   * a workgroup reserves the next item index with a fetch-add on head (device memory),
+//     so reservations never retry; the index may be ahead of what is published;
+//   * mirror (device memory) is the tail as last read from host memory.  The workgroup
+//     holding index == mirror is the only one that reads host memory (system-scope
+//     acquire of tail): when tail has moved past it, it raises mirror to tail and runs
+//     its item.  Every other waiting workgroup watches mirror with a backed-off poll;
+//   * a workgroup runs its item (system-scope loads of the item and, unless it still
+//     holds it, the request descriptor), computes the tiles with the general K3 tile
+//     functions, then adds its tile count to done_tiles[slot] (device memory); the
+//     workgroup that brings it to the request's target stores the request's sequence
+//     number into done[slot] (pinned memory, system-scope release) after a system fence;
 //   * the host sees done[slot] == seq, completes the request, and only then reuses the
 //     slot and the request's ring entries (ring space is reclaimed in ring order);
-//   * the kernel leaves when the host sets ctl->shutdown or after an idle spin limit; the
-//     host relaunches it whenever published work is outstanding and the stream is idle.
+//   * parking: once the host has had nothing in flight for a while (or is shutting down)
+//     it stops publishing and sets ctl->park.  The poller that sees park with tail not
+//     past its index sets parked, and every workgroup whose item is unpublished leaves;
+//     items below tail are all run before their holders look at park.  The host then
+//     waits for the stream, and before the next launch a one-thread kernel resets head
+//     and mirror to the frozen tail (abandoned reservations are all >= that tail).
 // done_tiles[] only grows: each request's target is the slot's running total, so no
-// device memory is ever reset from the host.
+// device memory is cleared while the server runs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,8 +47,9 @@ namespace ptg {
 
 constexpr int kReqSlots = 1024;            // requests admitted at once
 constexpr size_t kServeLds = 64 * 1024;    // dynamic LDS of a serving workgroup
-constexpr int kTilesPerItem = 4;           // sample tiles per work item
-constexpr int kIdleSpins = 20000;          // ~30 ms of polling before an idle kernel exits
+constexpr int kMaxTilesPerItem = 16;      // sample tiles per work item, upper bound
+constexpr int64_t kParkNs = 5000000;       // nothing in flight for 5 ms: park the kernel
+constexpr int64_t kSpinNs = 2000000;       // the scheduler spins until 2 ms after the last event
 constexpr int64_t kStarveNs = 50000000;    // after 50 ms a waiting request blocks later ones
 
 struct ServeReqDesc {
@@ -55,21 +65,31 @@ struct ServeReqDesc {
 static_assert(sizeof(ServeReqDesc) % 8 == 0, "descriptor is copied in 8-byte words");
 
 struct ServeItem {
-    int32_t slot;
-    int32_t ntiles;
-    int64_t tile0;
+    uint32_t slot, seq;    // request slot and the sequence number of its current request
+    uint32_t ntiles, tile0;
 };
+static_assert(sizeof(ServeItem) == 16, "an item is two 8-byte words");
 
 struct ServeHostCtl {  // pinned host memory
-    uint64_t tail;
-    int32_t shutdown;
+    uint64_t tail;         // items published
+    int32_t park;          // 1: workgroups whose item is not published leave
     int32_t pad;
 };
 
-struct ServeDevCtl {  // device memory
-    uint64_t head;
+struct ServeDevCtl {       // device memory
+    uint64_t head;         // next item index to reserve
+    uint64_t mirror;       // tail as last read from host memory (never above tail)
+    uint32_t parked;       // the poller saw park with nothing left to run
+    uint32_t pad;
     uint64_t done_tiles[kReqSlots];
 };
+
+__global__ void k_serve_reset(ServeDevCtl *dc, uint64_t start)
+{
+    dc->head = start;
+    dc->mirror = start;
+    dc->parked = 0;
+}
 
 __device__ __forceinline__ uint64_t sys_load64(const uint64_t *p)
 {
@@ -83,45 +103,66 @@ __global__ __launch_bounds__(256) void k_serve(ServeHostCtl *hc, const ServeItem
     __shared__ uint64_t s_req[sizeof(ServeReqDesc) / 8];
     __shared__ int s_cmd;
     __shared__ ServeItem s_item;
+    __shared__ uint32_t s_have_slot, s_have_seq;  // request whose descriptor s_req holds
     const int tid = threadIdx.x;
+    if (tid == 0) s_have_slot = 0xFFFFFFFFu;
     for (;;) {
         if (tid == 0) {
-            int cmd = 0;
-            uint64_t idx = 0;
-            for (int spin = 0; spin < kIdleSpins;) {
-                const uint64_t tail = __hip_atomic_load(&hc->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-                uint64_t head = __hip_atomic_load(&dc->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (head < tail) {
-                    if (__hip_atomic_compare_exchange_strong(&dc->head, &head, head + 1, __ATOMIC_ACQUIRE,
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                        idx = head;
+            const uint64_t my = __hip_atomic_fetch_add(&dc->head, (uint64_t)1, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            int cmd = 0, nap = 8;
+            // Polls are relaxed loads (an acquire on this chip invalidates the L2, which a
+            // spinning workgroup would do continuously); one acquire fence follows success.
+            for (;;) {
+                const uint64_t m = __hip_atomic_load(&dc->mirror, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (my < m) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    cmd = 1;
+                    break;
+                }
+                if (my == m) {  // first unpublished index: poll host memory
+                    const int32_t pk = __hip_atomic_load(&hc->park, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    if (pk) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the tail read next is final
+                    const uint64_t t = __hip_atomic_load(&hc->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    if (t > my) {
+                        if (!pk) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+                        __hip_atomic_fetch_max(&dc->mirror, t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                         cmd = 1;
                         break;
                     }
-                    continue;  // another workgroup took it; head only grows up to tail
+                    if (pk) {  // t == my == mirror: every published item is held below us
+                        __hip_atomic_store(&dc->parked, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(4);
+                } else {
+                    if (__hip_atomic_load(&dc->parked, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                    for (int z = 0; z < nap; z += 8) __builtin_amdgcn_s_sleep(8);  // ~nap * 64 clocks
+                    nap = nap < 128 ? 2 * nap : 128;
                 }
-                if (__hip_atomic_load(&hc->shutdown, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
-                __builtin_amdgcn_s_sleep(127);
-                ++spin;
             }
             if (cmd == 1) {
-                const uint64_t *w = reinterpret_cast<const uint64_t *>(ring + (idx % (uint64_t)ring_size));
+                const uint64_t *w = reinterpret_cast<const uint64_t *>(ring + (my % (uint64_t)ring_size));
                 const uint64_t w0 = sys_load64(w), w1 = sys_load64(w + 1);
-                s_item.slot = (int32_t)(w0 & 0xFFFFFFFFu);
-                s_item.ntiles = (int32_t)(w0 >> 32);
-                s_item.tile0 = (int64_t)w1;
+                s_item.slot = (uint32_t)w0;
+                s_item.seq = (uint32_t)(w0 >> 32);
+                s_item.ntiles = (uint32_t)w1;
+                s_item.tile0 = (uint32_t)(w1 >> 32);
+                if (s_item.slot == s_have_slot && s_item.seq == s_have_seq) cmd = 2;  // descriptor held
+                s_have_slot = s_item.slot;
+                s_have_seq = s_item.seq;
             }
             s_cmd = cmd;
         }
         __syncthreads();
-        if (s_cmd != 1) return;  // shutdown or idle: every wave of the workgroup leaves
-        {
+        if (s_cmd == 0) return;  // parked: every wave of the workgroup leaves
+        if (s_cmd == 1) {
             const uint64_t *src = reinterpret_cast<const uint64_t *>(reqs + s_item.slot);
             for (int i = tid; i < (int)(sizeof(ServeReqDesc) / 8); i += 256) s_req[i] = sys_load64(src + i);
+            __syncthreads();
         }
-        __syncthreads();
         const ServeReqDesc &rq = *reinterpret_cast<const ServeReqDesc *>(s_req);
-        const int64_t t1 = s_item.tile0 + s_item.ntiles;
+        const int64_t t1 = (int64_t)s_item.tile0 + s_item.ntiles;
         for (int64_t t = s_item.tile0; t < t1; ++t) {
             if (rq.dim == 2) {
                 if (rq.smooth == 1)
@@ -137,12 +178,15 @@ __global__ __launch_bounds__(256) void k_serve(ServeHostCtl *hc, const ServeItem
             __syncthreads();  // LDS reuse by the next tile
         }
         if (tid == 0) {
-            __threadfence_system();  // this workgroup's output is visible before it is counted
+            // this workgroup's output reaches memory before it is counted (release: L2
+            // write-back); only the workgroup that completes the request also acquires the
+            // other workgroups' releases before it signals the host
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
             const uint64_t n = (uint64_t)s_item.ntiles;
-            const uint64_t old = __hip_atomic_fetch_add(&dc->done_tiles[rq.slot], n, __ATOMIC_ACQ_REL,
+            const uint64_t old = __hip_atomic_fetch_add(&dc->done_tiles[rq.slot], n, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT);
             if (old + n == rq.target) {
-                __threadfence_system();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __hip_atomic_store(done + rq.slot, rq.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }
@@ -204,7 +248,7 @@ class Arena {
 
 struct Request {
     ptg_tile_req req;
-    int64_t bytes = 0, ntiles = 0, arena_off = -1;
+    int64_t bytes = 0, ntiles = 0, arena_off = -1, per_item = 1, items = 0;
     int32_t slot = -1;
     uint32_t seq = 0;
     uint64_t ring_begin = 0, ring_end = 0;
@@ -242,7 +286,11 @@ struct ptg_server {
     uint64_t next_ticket = 1, tail = 0, reclaimed = 0;
     uint32_t seq = 0;
     bool stopping = false, quit = false;
-    bool kernel_running = false;
+    bool kernel_running = false, park_requested = false;
+    uint64_t base = 0;        // first item index of the next launch (tail when the last one parked)
+    int64_t idle_since = 0;   // when the in-flight set last became empty
+    int64_t last_event = 0;   // last submission or completion
+    int64_t tiles_in_flight = 0;
     int64_t fake_busy_until = 0;
     ptg_server_stats st{};
     std::thread th;
@@ -251,11 +299,29 @@ struct ptg_server {
 
 namespace ptg {
 
+// Tiles per work item: the configured count; else sized to the load.  With little in
+// flight a request is cut into small items that spread over many workgroups (latency);
+// with a backlog items grow to kMaxTilesPerItem tiles (fewer claims and completions per
+// tile: throughput).  Never more items than the ring holds (validation guarantees that
+// kMaxTilesPerItem tiles per item fit).
+static int64_t tiles_per_item(const ptg_server *s, int64_t ntiles)
+{
+    int64_t per = s->cfg.tiles_per_item;
+    if (per <= 0) {
+        const int64_t wg = std::max(s->workgroups, 1);
+        per = std::max<int64_t>(1, std::min<int64_t>(kMaxTilesPerItem, (s->tiles_in_flight + ntiles) / (2 * wg)));
+    }
+    const int64_t need = (ntiles + s->cfg.max_items - 1) / s->cfg.max_items;
+    return std::max(per, need);
+}
+
 static void complete(ptg_server *s, uint64_t ticket, int status)
 {
     Request &r = s->by_ticket[ticket];
+    if (r.status == 2) s->tiles_in_flight -= r.ntiles;
     r.status = status;
     r.t_done = now_ns();
+    s->last_event = r.t_done;
     if (r.slot >= 0) s->free_slots.push_back(r.slot);
     // ring entries are reused in ring order: reclaim up to the first unfinished request
     for (auto &e : s->ring_order)
@@ -277,7 +343,8 @@ static void publish(ptg_server *s, uint64_t ticket, Request &r)
     r.seq = ++s->seq;
     r.t_admit = now_ns();
     r.status = 2;
-    const uint64_t items = (r.ntiles + kTilesPerItem - 1) / kTilesPerItem;
+    s->tiles_in_flight += r.ntiles;
+    const uint64_t items = (uint64_t)r.items;
     r.ring_begin = s->tail;
     r.ring_end = s->tail + items;
     s->ring_order.push_back({ticket, r.ring_end, false});
@@ -311,9 +378,11 @@ static void publish(ptg_server *s, uint64_t ticket, Request &r)
     std::memcpy(&s->reqs[slot], &d, sizeof(d));
     for (uint64_t i = 0; i < items; ++i) {
         ServeItem it;
-        it.slot = slot;
-        it.tile0 = (int64_t)i * kTilesPerItem;
-        it.ntiles = (int32_t)std::min<int64_t>(kTilesPerItem, r.ntiles - it.tile0);
+        it.slot = (uint32_t)slot;
+        it.seq = r.seq;
+        const int64_t t0 = (int64_t)i * r.per_item;
+        it.tile0 = (uint32_t)t0;
+        it.ntiles = (uint32_t)std::min<int64_t>(r.per_item, r.ntiles - t0);
         std::memcpy(&s->ring[(r.ring_begin + i) % (uint64_t)s->cfg.max_items], &it, sizeof(it));
     }
     s->tail = r.ring_end;
@@ -326,7 +395,9 @@ static void admit(ptg_server *s)
     const int64_t now = now_ns();
     for (auto it = s->pending.begin(); it != s->pending.end();) {
         Request &r = s->by_ticket[*it];
-        const uint64_t items = (r.ntiles + kTilesPerItem - 1) / kTilesPerItem;
+        r.per_item = tiles_per_item(s, r.ntiles);
+        r.items = (r.ntiles + r.per_item - 1) / r.per_item;
+        const uint64_t items = (uint64_t)r.items;
         if (s->free_slots.empty()) break;
         if (s->tail + items - s->reclaimed > (uint64_t)s->cfg.max_items) break;  // ring order is FIFO
         const int64_t off = s->arena->alloc(r.bytes);
@@ -364,22 +435,37 @@ static void fail_inflight(ptg_server *s, int status)
     s->inflight.clear();
 }
 
+// Kernel state: running (launched, not yet seen finished) and park_requested (ctl->park
+// set, nothing is published until the kernel has left).
+static void check_kernel(ptg_server *s)
+{
+    if (!s->gpu || !s->kernel_running) return;
+    const hipError_t q = hipStreamQuery(s->stream);
+    if (q == hipErrorNotReady) return;
+    s->kernel_running = false;
+    if (q != hipSuccess) {
+        s->err = hipGetErrorString(q);
+        fail_inflight(s, PTG_EHIP);
+    } else if (!s->park_requested && !s->inflight.empty()) {
+        s->err = "the serving kernel left with work in flight";
+        fail_inflight(s, PTG_EHIP);
+    }
+    // every published item below tail has run (park is only set with nothing in flight,
+    // or at shutdown after the in-flight set drained): the next launch starts at tail
+    s->base = s->tail;
+    s->park_requested = false;
+    __atomic_store_n(&s->hc->park, 0, __ATOMIC_RELEASE);
+}
+
 static void ensure_kernel(ptg_server *s)
 {
-    if (!s->gpu || s->inflight.empty()) return;
-    if (s->kernel_running) {
-        const hipError_t q = hipStreamQuery(s->stream);
-        if (q == hipErrorNotReady) return;
-        s->kernel_running = false;
-        if (q != hipSuccess) {
-            s->err = hipGetErrorString(q);
-            fail_inflight(s, PTG_EHIP);
-            return;
-        }
-    }
+    if (!s->gpu || s->inflight.empty() || s->kernel_running || s->park_requested) return;
+    hipLaunchKernelGGL(k_serve_reset, dim3(1), dim3(1), 0, s->stream, s->dc, s->base);
     hipLaunchKernelGGL(k_serve, dim3(s->workgroups), dim3(256), kServeLds, s->stream, s->hc, s->ring, s->reqs, s->done,
                        s->dc, s->cfg.max_items);
-    if (hipGetLastError() != hipSuccess) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        s->err = hipGetErrorString(e);
         fail_inflight(s, PTG_EHIP);
         return;
     }
@@ -387,21 +473,43 @@ static void ensure_kernel(ptg_server *s)
     s->st.kernel_launches++;
 }
 
+static void maybe_park(ptg_server *s, int64_t now)
+{
+    if (!s->gpu || !s->kernel_running || s->park_requested || !s->inflight.empty()) return;
+    // requests still pending wait for arena bytes that only ptg_tile_release frees: they do
+    // not keep the kernel (and with it a device-wide synchronisation) waiting
+    if (!s->stopping && now - s->idle_since < kParkNs) return;
+    s->park_requested = true;
+    __atomic_store_n(&s->hc->park, 1, __ATOMIC_RELEASE);
+}
+
 static void service(ptg_server *s)
 {
     if (s->gpu) (void)hipSetDevice(s->cfg.device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        if (!s->stopping) admit(s);
+        check_kernel(s);
+        if (!s->stopping && !s->park_requested) admit(s);
+        const bool busy = !s->inflight.empty();
         poll_done(s);
+        const int64_t now = now_ns();
+        if (busy && s->inflight.empty()) s->idle_since = now;
         ensure_kernel(s);
-        if (s->stopping && s->inflight.empty()) break;
-        if (s->inflight.empty()) {
-            s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
-        } else {
+        maybe_park(s, now);
+        if (s->stopping && s->inflight.empty() && !s->kernel_running) break;
+        // spin while requests are in flight or soon after the last event (completion is
+        // seen within a poll, not a sleep); then sleep briefly while a kernel may still
+        // need parking, and block when there is nothing to do
+        if (!s->inflight.empty() || now - s->last_event < kSpinNs) {
             lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            std::this_thread::yield();
             lk.lock();
+        } else if (s->kernel_running) {
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(200));
+            lk.lock();
+        } else {
+            s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
         }
     }
 }
@@ -442,7 +550,8 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
     }
     if (lds > kServeLds) return fail(PTG_EINVAL, "the request's lattice is too fine for a serving workgroup");
     if (*ntiles > 0x7FFFFFFFLL) return fail(PTG_EINVAL, "request too large");
-    const uint64_t items = (*ntiles + kTilesPerItem - 1) / kTilesPerItem;
+    const int64_t per = s->cfg.tiles_per_item > 0 ? s->cfg.tiles_per_item : kMaxTilesPerItem;
+    const uint64_t items = (uint64_t)((*ntiles + per - 1) / per);
     if (items > (uint64_t)s->cfg.max_items) return fail(PTG_E2BIG, "request needs more work items than the ring holds");
     if (((*bytes + 255) & ~int64_t(255)) > s->cfg.hbm_budget_bytes)
         return fail(PTG_E2BIG, "request output (%lld bytes) exceeds the budget", (long long)*bytes);
@@ -479,6 +588,8 @@ int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out)
     if (cfg->workgroups < 0 || cfg->workgroups > 65536) return fail(PTG_EINVAL, "bad workgroup count");
     if (cfg->executor != PTG_EXEC_GPU && cfg->executor != PTG_EXEC_HOST) return fail(PTG_EINVAL, "bad executor");
     if (cfg->executor == PTG_EXEC_HOST && cfg->fake_tile_ns < 0) return fail(PTG_EINVAL, "fake_tile_ns < 0");
+    if (cfg->tiles_per_item < 0 || cfg->tiles_per_item > kMaxTilesPerItem || cfg->reserved != 0)
+        return fail(PTG_EINVAL, "tiles_per_item must be in 0..%d", kMaxTilesPerItem);
     *out = nullptr;
     ptg_server *s = new ptg_server();
     s->cfg = *cfg;
@@ -487,6 +598,7 @@ int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out)
     for (int i = kReqSlots - 1; i >= 0; --i) s->free_slots.push_back(i);
     s->slot_total.assign(kReqSlots, 0);
     s->arena.reset(new Arena(cfg->hbm_budget_bytes));
+    s->workgroups = cfg->workgroups > 0 ? cfg->workgroups : 512;
     if (s->gpu) {
         hipError_t e = hipSetDevice(cfg->device);
         if (e != hipSuccess) {
@@ -540,6 +652,7 @@ int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n, uint64_
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stopping) return fail(PTG_ESHUTDOWN, "server is shutting down");
     const int64_t t = now_ns();
+    s->last_event = t;
     for (int32_t i = 0; i < n; ++i) {
         const uint64_t ticket = s->next_ticket++;
         Request &r = s->by_ticket[ticket];
@@ -620,10 +733,9 @@ int ptg_server_destroy(ptg_server *s)
         s->pending.clear();
         s->cv_work.notify_all();
     }
-    s->th.join();
+    s->th.join();  // in-flight requests run out, then the kernel is parked and has left
     int rc = PTG_OK;
     if (s->gpu) {
-        __atomic_store_n(&s->hc->shutdown, 1, __ATOMIC_RELEASE);
         const hipError_t e = hipStreamSynchronize(s->stream);
         if (e != hipSuccess) rc = hip_fail(e, "server kernel");
     }

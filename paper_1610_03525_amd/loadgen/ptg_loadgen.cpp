@@ -1,0 +1,205 @@
+// ptg_loadgen.cpp -- open-loop load generation for terrain-tile streams: the same request
+// stream with given arrival times driven through (a) the tile server and (b) the plain
+// per-tile path (one ptg_fbm_2d / ptg_fbm_3d call per request on one stream, launched
+// directly or captured in batches into HIP graphs).  Native threads issue and complete
+// requests at their arrival times, so the measured latencies are those of the paths, not
+// of an interpreter.  Benchmark support; not part of the library's C ABI.
+#include "ptg_loadgen.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <thread>
+#include <vector>
+
+namespace {
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// Sleep through most of the wait, spin the last 100 us.
+void wait_until(int64_t t)
+{
+    for (;;) {
+        const int64_t d = t - now_ns();
+        if (d <= 0) return;
+        if (d > 150000)
+            std::this_thread::sleep_for(std::chrono::nanoseconds(d - 100000));
+        else
+            std::this_thread::yield();
+    }
+}
+
+bool arrivals_ok(const int64_t *a, int32_t n)
+{
+    for (int32_t i = 0; i < n; ++i)
+        if (a[i] < 0 || (i > 0 && a[i] < a[i - 1])) return false;
+    return true;
+}
+
+int plain_call(const ptg_tile_req &r, void *out, hipStream_t s)
+{
+    if (r.params.dim == 2)
+        return ptg_fbm_2d(&r.params, r.origin[0], r.origin[1], r.extent[0], r.extent[1], out, r.extent[0], s);
+    return ptg_fbm_3d(&r.params, r.origin[0], r.origin[1], r.origin[2], r.extent[0], r.extent[1], r.extent[2], out, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ptg_lg_served(ptg_server *s, const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n, int64_t *done_ns,
+                  int64_t *admit_ns)
+{
+    if (!s || !reqs || !arrival_ns || !done_ns || n < 1 || !arrivals_ok(arrival_ns, n)) return PTG_EINVAL;
+    std::vector<uint64_t> tickets((size_t)n);
+    std::atomic<int32_t> published{0};
+    std::atomic<int> err{PTG_OK};
+    const int64_t t0 = now_ns() + 1000000;
+    std::thread sub([&] {
+        int32_t i = 0;
+        while (i < n && err.load() == PTG_OK) {
+            wait_until(t0 + arrival_ns[i]);
+            const int64_t now = now_ns();
+            int32_t j = i + 1;
+            while (j < n && t0 + arrival_ns[j] <= now) ++j;
+            const int rc = ptg_tiles_submit(s, reqs + i, j - i, tickets.data() + i);
+            if (rc != PTG_OK) {
+                err.store(rc);
+                break;
+            }
+            published.store(j, std::memory_order_release);
+            i = j;
+        }
+    });
+    int rc = PTG_OK;
+    for (int32_t i = 0; i < n && rc == PTG_OK; ++i) {
+        while (published.load(std::memory_order_acquire) <= i) {
+            if (err.load() != PTG_OK) break;
+            std::this_thread::yield();
+        }
+        if (err.load() != PTG_OK) {
+            rc = err.load();
+            break;
+        }
+        ptg_tile_result res;
+        rc = ptg_tiles_wait(s, tickets[(size_t)i], 120000000000LL, &res);
+        if (rc == PTG_OK && res.status != PTG_OK) rc = res.status;
+        if (rc == PTG_OK) {
+            done_ns[i] = res.t_done_ns - t0;
+            if (admit_ns) admit_ns[i] = res.t_admit_ns - t0;
+            rc = ptg_tile_release(s, tickets[(size_t)i]);
+        }
+    }
+    if (rc != PTG_OK) err.store(rc);
+    sub.join();
+    return rc;
+}
+
+int ptg_lg_plain(const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n, void *arena, int64_t arena_bytes,
+                 int32_t mode, int32_t max_batch, int64_t *done_ns, int64_t *stats)
+{
+    if (!reqs || !arrival_ns || !done_ns || !arena || n < 1 || !arrivals_ok(arrival_ns, n) ||
+        (mode != PTG_LG_DIRECT && mode != PTG_LG_GRAPH) || max_batch < 1)
+        return PTG_EINVAL;
+    std::vector<int64_t> off((size_t)n);
+    int64_t o = 0;
+    for (int32_t i = 0; i < n; ++i) {  // outputs laid out in arrival order, wrapping (one stream orders reuse)
+        int64_t b = reqs[i].extent[0] * reqs[i].extent[1] * reqs[i].extent[2] * 4;
+        b = (b + 255) & ~int64_t(255);
+        if (b > arena_bytes) return PTG_E2BIG;
+        if (o + b > arena_bytes) o = 0;
+        off[(size_t)i] = o;
+        o += b;
+    }
+    // st executes; cs only records captures (its work is never run), so the completion
+    // thread's event waits never touch a stream that is capturing
+    hipStream_t st = nullptr, cs = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return PTG_EHIP;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(st);
+        return PTG_EHIP;
+    }
+    // one completion event per launch unit (a request, or a captured batch)
+    std::vector<hipEvent_t> ev((size_t)n, nullptr);
+    for (auto &e : ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            for (auto &f : ev)
+                if (f) (void)hipEventDestroy(f);
+            (void)hipStreamDestroy(st);
+            (void)hipStreamDestroy(cs);
+            return PTG_EHIP;
+        }
+    std::vector<int32_t> unit_end((size_t)n, 0);     // unit u covers requests [u, unit_end[u])
+    std::vector<hipGraphExec_t> execs((size_t)n, nullptr);
+    std::atomic<int32_t> issued{0};                  // requests whose unit has been launched
+    std::atomic<int> err{PTG_OK};
+    int64_t launches = 0;
+    const int64_t t0 = now_ns() + 1000000;
+    std::thread wt([&] {  // completion side: units finish in stream order
+        int32_t u = 0;
+        while (u < n) {
+            while (issued.load(std::memory_order_acquire) <= u) {
+                if (err.load() != PTG_OK) return;
+                std::this_thread::yield();
+            }
+            if (hipEventSynchronize(ev[(size_t)u]) != hipSuccess) {
+                err.store(PTG_EHIP);
+                return;
+            }
+            const int64_t t = now_ns() - t0;
+            const int32_t e = unit_end[(size_t)u];
+            for (int32_t k = u; k < e; ++k) done_ns[k] = t;
+            if (execs[(size_t)u]) {
+                (void)hipGraphExecDestroy(execs[(size_t)u]);
+                execs[(size_t)u] = nullptr;
+            }
+            u = e;
+        }
+    });
+    int32_t i = 0;
+    while (i < n && err.load() == PTG_OK) {
+        wait_until(t0 + arrival_ns[i]);
+        int rc = PTG_OK;
+        int32_t j = i + 1;
+        if (mode == PTG_LG_DIRECT) {
+            rc = plain_call(reqs[i], (char *)arena + off[(size_t)i], st);
+        } else {  // every request that has arrived, up to max_batch, in one graph
+            const int64_t now = now_ns();
+            while (j < n && j - i < max_batch && t0 + arrival_ns[j] <= now) ++j;
+            hipGraph_t g = nullptr;
+            if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = PTG_EHIP;
+            for (int32_t k = i; k < j && rc == PTG_OK; ++k) rc = plain_call(reqs[k], (char *)arena + off[(size_t)k], cs);
+            if (hipStreamEndCapture(cs, &g) != hipSuccess && rc == PTG_OK) rc = PTG_EHIP;
+            if (rc == PTG_OK && hipGraphInstantiate(&execs[(size_t)i], g, nullptr, nullptr, 0) != hipSuccess)
+                rc = PTG_EHIP;
+            if (g) (void)hipGraphDestroy(g);
+            if (rc == PTG_OK && hipGraphLaunch(execs[(size_t)i], st) != hipSuccess) rc = PTG_EHIP;
+        }
+        if (rc == PTG_OK && hipEventRecord(ev[(size_t)i], st) != hipSuccess) rc = PTG_EHIP;
+        if (rc != PTG_OK) {
+            err.store(rc);
+            break;
+        }
+        ++launches;
+        unit_end[(size_t)i] = j;
+        issued.store(j, std::memory_order_release);
+        i = j;
+    }
+    wt.join();
+    if (hipStreamSynchronize(st) != hipSuccess && err.load() == PTG_OK) err.store(PTG_EHIP);
+    for (auto &x : execs)  // graphs whose completion was not taken (after an error)
+        if (x) (void)hipGraphExecDestroy(x);
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(st);
+    (void)hipStreamDestroy(cs);
+    if (stats) stats[0] = launches;
+    return err.load();
+}
+
+}  // extern "C"

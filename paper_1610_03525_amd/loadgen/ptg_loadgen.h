@@ -1,0 +1,41 @@
+/* ptg_loadgen.h -- open-loop load generation over the tile server and the plain per-tile
+ * path (benchmark support, built as libptg_loadgen.so on top of libptg.so).
+ *
+ * A stream of n requests with arrival offsets arrival_ns[i] (ns from the start, non-
+ * decreasing) is issued at those times by a native thread.  Outputs: done_ns[i], the time
+ * (ns from the start) at which the host saw request i complete.  Latency = done - arrival.
+ */
+#ifndef PTG_LOADGEN_H
+#define PTG_LOADGEN_H
+
+#include "ptg.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PTG_LG_DIRECT 0 /* one ptg_fbm_* launch per request as it arrives                  */
+#define PTG_LG_GRAPH 1  /* every request that has arrived (up to max_batch) captured into   */
+                        /* one HIP graph, instantiated and launched; its requests complete  */
+                        /* together                                                          */
+
+/* Through server s: requests are submitted at their arrival times (all that have arrived
+ * in one ptg_tiles_submit call); completions are taken in request order and released at
+ * once.  done_ns is the server's completion time (t_done_ns); admit_ns (optional) its
+ * admission time.  Returns PTG_OK or the first error of the server calls. */
+PTG_API int ptg_lg_served(ptg_server *s, const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n,
+                          int64_t *done_ns, int64_t *admit_ns);
+
+/* Through the plain path on a stream of its own: request i writes its dense output into
+ * arena (device memory, arena_bytes) at an offset that wraps around in arrival order; the
+ * single stream orders the reuse.  stats[0] (optional) receives the number of launch units
+ * (requests, or graphs).  Returns PTG_OK, PTG_EINVAL, PTG_E2BIG (a request larger than the
+ * arena) or PTG_EHIP. */
+PTG_API int ptg_lg_plain(const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n, void *arena,
+                         int64_t arena_bytes, int32_t mode, int32_t max_batch, int64_t *done_ns, int64_t *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -46,7 +46,7 @@ def _solo(r):
     else:
         out = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
         ptg.fbm_3d(out, x0=r["origin"][0], y0=r["origin"][1], z0=r["origin"][2], **kw)
-    torch.cuda.synchronize()
+    torch.cuda.current_stream().synchronize()  # not the device: the server's kernel may be running
     return out
 
 
@@ -111,7 +111,7 @@ def test_kernel_relaunches_after_idle_and_small_budget_admission():
             res = srv.wait(t, int(60e9))
             assert torch.equal(_fetch(res, r), _solo(r))
             srv.release(t)
-        time.sleep(0.4)  # the persistent kernel exits after ~0.1 s of idling
+        time.sleep(0.1)  # the persistent kernel is parked after 5 ms with nothing in flight
         tickets = srv.submit([_tile_req(r) for r in reqs[6:]])
         for t, r in zip(tickets, reqs[6:]):
             res = srv.wait(t, int(60e9))
@@ -133,3 +133,52 @@ def test_served_samples_match_oracle():
     j = rng.integers(0, 150, 500)
     ref = O.fbm_points_2d(2, 12, 0.5, 2.0, F0, 99, r["origin"][0] + i, r["origin"][1] + j)
     assert np.max(np.abs(g[j, i] - ref)) <= 1e-5 * sum(0.5 ** o for o in range(12))
+
+
+def test_plain_stream_direct_and_graph_batched_write_what_solo_calls_write():
+    """The benchmark's plain per-tile stream (native driver; direct launches, and batches
+    captured into HIP graphs) leaves each request's output at its arena offset equal to the
+    same ptg_fbm_* call made on its own."""
+    import ctypes
+    import os
+    lg = ctypes.CDLL(os.path.join(os.path.dirname(ptg.LIB_PATH), "libptg_loadgen.so"))
+    p64 = ctypes.POINTER(ctypes.c_int64)
+    lg.ptg_lg_plain.argtypes = [ctypes.POINTER(ptg.TileReq), p64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                ctypes.c_int32, ctypes.c_int32, p64, p64]
+    reqs = _mix(24, 11)
+    n = len(reqs)
+    tr = (ptg.TileReq * n)(*[_tile_req(r) for r in reqs])
+    sizes = [r["extent"][0] * r["extent"][1] * r["extent"][2] * 4 for r in reqs]
+    offs, o = [], 0
+    for b in sizes:
+        offs.append(o)
+        o += (b + 255) & ~255
+    arena = torch.zeros(o, dtype=torch.uint8, device="cuda")
+    for mode in (0, 1):
+        arena.zero_()
+        torch.cuda.synchronize()
+        arr = np.ascontiguousarray(np.arange(n) * 100_000, dtype=np.int64)
+        done = np.zeros(n, dtype=np.int64)
+        st = np.zeros(1, dtype=np.int64)
+        rc = lg.ptg_lg_plain(tr, arr.ctypes.data_as(p64), n, arena.data_ptr(), o, mode, 8, done.ctypes.data_as(p64),
+                             st.ctypes.data_as(p64))
+        assert rc == ptg.PTG_OK, ptg.last_error()
+        assert np.all(done >= arr) and 1 <= st[0] <= n
+        for r, off, b in zip(reqs, offs, sizes):
+            got = arena[off:off + b].view(torch.float32)
+            want = _solo_auto(r).reshape(-1)
+            assert torch.equal(got, want), (mode, r)
+
+
+def _solo_auto(r):
+    nx, ny, nz = r["extent"]
+    kw = dict(smoothness=r["smoothness"], octaves=r["octaves"], base_freq=r["base_freq"], seed=r["seed"],
+              persistence=r["persistence"], lacunarity=r["lacunarity"])
+    if r["dim"] == 2:
+        out = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+        ptg.fbm_2d(out, x0=r["origin"][0], y0=r["origin"][1], **kw)
+    else:
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
+        ptg.fbm_3d(out, x0=r["origin"][0], y0=r["origin"][1], z0=r["origin"][2], **kw)
+    torch.cuda.current_stream().synchronize()
+    return out
