@@ -366,12 +366,21 @@ __global__ __launch_bounds__(256) void k_fbm2d_dyadic(const Fbm2dDyadicArgs a)
     const int k = lane >> 4, m = lane & 15;
 
     // ---- once per workgroup: basis tables, hashing work lists, key prefixes per octave ---
+    // (the per-octave table offsets and steps are first staged in LDS: a lane-dependent
+    // index into the kernel arguments would be a chain of dependent global loads)
+    __shared__ int p_toff[kMaxOctaves];
+    __shared__ float p_inv2p[kMaxOctaves];
+    if (tid < N) {
+        p_toff[tid] = a.toff[tid];
+        p_inv2p[tid] = a.inv2p[tid];
+    }
+    __syncthreads();
     for (int q = tid; q < a.tab_total; q += NT) {
         int o = a.tab_first;  // every octave from tab_first on has a table, in order
-        while (o + 1 < N && q >= a.toff[o + 1]) ++o;
-        const int r = q - a.toff[o];
+        while (o + 1 < N && q >= p_toff[o + 1]) ++o;
+        const int r = q - p_toff[o];
         float S, b10, b11;
-        Basis<M>::eval((float)(2 * r + 1) * a.inv2p[o], S, b10, b11);
+        Basis<M>::eval((float)(2 * r + 1) * p_inv2p[o], S, b10, b11);
         sh.tab[q] = make_float4(1.0f - S, S, b10, b11);
     }
     for (int o = 0; o < N; ++o) {

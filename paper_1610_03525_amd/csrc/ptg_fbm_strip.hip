@@ -1,0 +1,394 @@
+// ptg_fbm_strip.hip -- K3 for dyadic octave ladders (base frequency 2^-k, lacunarity 2),
+// plain FP32 form on the vector ALUs.
+//
+// With f_o = 2^-s the sample-centre fraction is exact: t = (2 (X mod 2^s) + 1) / 2^(s+1).
+// One wave owns a world-aligned strip of kStripW x kStripH samples, lane = column, and walks
+// strips with a grid stride; the waves of a workgroup never synchronise after the prologue.
+//
+// Cell polynomial (Sec. 2, Sec. 3.4), fixed column x: the 1D Hermite form in y
+//   h(y) = E0 + (E1 - E0) S(t) + Q0 b10(t) + Q1 b11(t),
+//   E_cy = gx(cx, cy) b10(tx) + gx(cx+1, cy) b11(tx),  Q_cy = gy(cx, cy) + S(tx) (gy(cx+1, cy) - gy(cx, cy)).
+// Octaves are summed in three ways:
+//  * period >= kStripH: a lane's column meets one cell of the octave over the whole strip,
+//    so each such octave's column form is re-expanded in the strip's centred row
+//    coordinate v = (2 r - 31) / 64 (t - 1/2 = tau + sigma v, sigma = 32 / P) and all of
+//    them are added into ONE polynomial of degree 2M+1 per lane, evaluated by Horner per row;
+//  * period 16: the same, once per half strip;
+//  * period <= 8: the column form is formed once per cell row and evaluated per row with
+//    the row bases as constants (the row's position inside its cell is fixed by the unrolled
+//    row loop); which of these periods occur is a template parameter (the finest shift LO),
+//    so the row loop carries no per-row tests.
+// Bases along x of the periods <= 64 depend on the lane only and are formed once per wave.
+// Octaves accumulate in FP32; each sample is stored once.
+//
+// Per strip the wave first hashes its own footprint nodes into a private LDS block (K1
+// logic: one key per node column and row, one fmix32 per node, amplitude folded in); the
+// work lists that map lanes to nodes are the same for every strip and are built once per
+// workgroup.
+#include <hip/hip_fp16.h>
+
+#include "ptg_device.h"
+#include "ptg_launch.h"
+
+namespace ptg {
+
+template <typename T>
+__device__ __forceinline__ T st_out(float v);
+template <>
+__device__ __forceinline__ float st_out<float>(float v)
+{
+    return v;
+}
+template <>
+__device__ __forceinline__ __half st_out<__half>(float v)
+{
+    return __float2half_rn(v);
+}
+
+struct XB {  // 1D bases of a column fraction: S, b10, b11
+    float s, b10, b11;
+};
+
+template <int M>
+__device__ __forceinline__ XB xbases(float t)
+{
+    XB r;
+    Basis<M>::eval(t, r.s, r.b10, r.b11);
+    return r;
+}
+
+// Row bases at the fraction (j + 1/2) / P: constant once the row loop is unrolled.
+template <int M>
+__host__ __device__ constexpr XB row_bases(int j, int P)
+{
+    const float t = (float)(2 * j + 1) / (float)(2 * P);
+    const float t2 = t * t;
+    const float u = 1.0f - t;
+    if (M == 1) return XB{t2 * (3.0f - 2.0f * t), t * u * u, -t2 * u};
+    const float t3 = t2 * t;
+    return XB{t3 * (10.0f + t * (-15.0f + 6.0f * t)), t + t3 * (-6.0f + t * (8.0f - 3.0f * t)),
+              t3 * (-4.0f + t * (7.0f - 3.0f * t))};
+}
+
+struct CF {  // column form of one cell at one column
+    float E0, dE, Q0, Q1;
+};
+
+// nb -> node (cx, cy) of the cell; (cx, cy + 1) follows, column cx + 1 is nny further.
+__device__ __forceinline__ CF column_form(const float2 *nb, int nny, const XB &xb)
+{
+    const float2 n00 = nb[0], n01 = nb[1], n10 = nb[nny], n11 = nb[nny + 1];
+    CF c;
+    c.E0 = n00.x * xb.b10 + n10.x * xb.b11;
+    const float E1 = n01.x * xb.b10 + n11.x * xb.b11;
+    c.dE = E1 - c.E0;
+    c.Q0 = n00.y + xb.s * (n10.y - n00.y);
+    c.Q1 = n01.y + xb.s * (n11.y - n01.y);
+    return c;
+}
+
+// Add the column form, as a polynomial in v with t - 1/2 = tau + sigma v, to C.
+// Powers of u = t - 1/2 of the bases (exact binary fractions):
+//   cubic:   S = 1/2 + 3/2 u - 2 u^3,  b10 = 1/8 - 1/4 u - 1/2 u^2 + u^3,  b11 = -1/8 - 1/4 u + 1/2 u^2 + u^3
+//   quintic: S = 1/2 + 15/8 u - 5 u^3 + 6 u^5,
+//            b10 = 5/32 - 7/16 u - 3/4 u^2 + 5/2 u^3 + 1/2 u^4 - 3 u^5,
+//            b11 = -5/32 - 7/16 u + 3/4 u^2 + 5/2 u^3 - 1/2 u^4 - 3 u^5
+template <int M, bool SHIFT = true>
+__device__ __forceinline__ void add_mapped(float (&C)[2 * M + 2], const CF &c, float tau, float sigma)
+{
+    constexpr int D = 2 * M + 1;
+    const float Dq = c.Q0 - c.Q1, Sq = c.Q0 + c.Q1;
+    float m[D + 1];
+    if (M == 1) {
+        m[0] = c.E0 + 0.5f * c.dE + 0.125f * Dq;
+        m[1] = 1.5f * c.dE - 0.25f * Sq;
+        m[2] = -0.5f * Dq;
+        m[3] = Sq - 2.0f * c.dE;
+    } else {
+        m[0] = c.E0 + 0.5f * c.dE + 0.15625f * Dq;
+        m[1] = 1.875f * c.dE - 0.4375f * Sq;
+        m[2] = -0.75f * Dq;
+        m[3] = 2.5f * Sq - 5.0f * c.dE;
+        m[4] = 0.5f * Dq;
+        m[D] = 6.0f * c.dE - 3.0f * Sq;
+    }
+    // Taylor shift to u = tau (repeated synthetic division), then scale u - tau = sigma v
+    if (SHIFT) {
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = D - 1; j >= i; --j) m[j] += tau * m[j + 1];
+    }
+    float sp = 1.0f;  // sigma is a power of two: exact powers
+#pragma unroll
+    for (int b = 0; b <= D; ++b) {
+        C[b] += m[b] * sp;
+        sp *= sigma;
+    }
+}
+
+// An octave of fixed period (<= 64): its node block, row count, and the lane's x-bases
+// (strips are 64-aligned, so for such a period the column fraction depends on the lane only).
+struct Fixed {
+    const float2 *nb;
+    int nny;
+    XB xb;
+};
+
+template <int M>
+struct RowCtx {
+    Fixed f16, f8, f4, f2, f1;
+    int lane;
+    int64_t pitch;
+};
+
+// val += dE S + Q0 b10 + Q1 b11 at one row (E0 is in the constant term), as an FMA chain.
+__device__ __forceinline__ float add_direct(float val, const CF &c, const XB &rb)
+{
+    val = __builtin_fmaf(c.dE, rb.s, val);
+    val = __builtin_fmaf(c.Q0, rb.b10, val);
+    return __builtin_fmaf(c.Q1, rb.b11, val);
+}
+
+// The 32 rows of a strip: the fused polynomial C (+ the period-16 piece per half) by
+// Horner, plus the direct octaves; FULL = every sample of the strip is stored.
+template <int M, typename OutT, int LO, bool FULL>
+__device__ __forceinline__ void strip_rows(const RowCtx<M> &x, const float (&C)[2 * M + 2], OutT *rp, int rlo, int rhi,
+                                           bool lane_ok)
+{
+    constexpr int D1 = 2 * M + 2;
+    constexpr bool H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
+    const int lane = x.lane;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        float Ch[D1];
+#pragma unroll
+        for (int b = 0; b < D1; ++b) Ch[b] = C[b];
+        if (H16) {  // period 16: one cell row per half strip, t - 1/2 = (1/2 - h) + 2 v
+            const CF c = column_form(x.f16.nb + (lane >> 4) * x.f16.nny + h, x.f16.nny, x.f16.xb);
+            add_mapped<M>(Ch, c, 0.5f - (float)h, 2.0f);
+        }
+        CF c8{}, c4{}, c2{}, c1{};
+        float c0 = Ch[0];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 16 * h + r;
+            bool fresh = false;
+            if (H8 && (row & 7) == 0) {
+                c8 = column_form(x.f8.nb + (lane >> 3) * x.f8.nny + (row >> 3), x.f8.nny, x.f8.xb);
+                fresh = true;
+            }
+            if (H4 && (row & 3) == 0) {
+                c4 = column_form(x.f4.nb + (lane >> 2) * x.f4.nny + (row >> 2), x.f4.nny, x.f4.xb);
+                fresh = true;
+            }
+            if (H2 && (row & 1) == 0) {
+                c2 = column_form(x.f2.nb + (lane >> 1) * x.f2.nny + (row >> 1), x.f2.nny, x.f2.xb);
+                fresh = true;
+            }
+            if (H1) {
+                c1 = column_form(x.f1.nb + lane * x.f1.nny + row, x.f1.nny, x.f1.xb);
+                fresh = true;
+            }
+            if (fresh) {  // constant term: the fused polynomial's plus the direct octaves' E0
+                c0 = Ch[0];
+                if (H8) c0 += c8.E0;
+                if (H4) c0 += c4.E0;
+                if (H2) c0 += c2.E0;
+                if (H1) c0 += c1.E0;
+            }
+            const float v = (float)(2 * row - (kStripH - 1)) * (1.0f / (float)(2 * kStripH));
+            float val = Ch[D1 - 1];
+#pragma unroll
+            for (int b = D1 - 2; b >= 1; --b) val = __builtin_fmaf(val, v, Ch[b]);
+            val = __builtin_fmaf(val, v, c0);
+            if (H8) val = add_direct(val, c8, row_bases<M>(row & 7, 8));
+            if (H4) val = add_direct(val, c4, row_bases<M>(row & 3, 4));
+            if (H2) val = add_direct(val, c2, row_bases<M>(row & 1, 2));
+            if (H1) val = add_direct(val, c1, row_bases<M>(0, 1));
+            if (FULL || (row >= rlo && row < rhi && lane_ok)) rp[lane] = st_out<OutT>(val);
+            rp += x.pitch;
+        }
+    }
+}
+
+template <int M, typename OutT, int LO>
+__global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
+{
+    constexpr int D1 = 2 * M + 2;
+    constexpr bool H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
+    extern __shared__ float4 lds4[];
+    __shared__ uint32_t pre_key[kMaxOctaves];
+    __shared__ int p_shift[kMaxOctaves], p_noff[kMaxOctaves];
+    __shared__ float p_amp[kMaxOctaves], p_inv2p[kMaxOctaves];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int N = a.octaves;
+    const int nodes_total = a.nodes_total, keys_total = a.keys_total;
+    // LDS: [wl_key | wl_node] shared, then per wave [nodes (float2) | keys (u32)]
+    uint32_t *wl_key = reinterpret_cast<uint32_t *>(lds4);
+    uint32_t *wl_node = wl_key + keys_total;
+    const int shared_words = (keys_total + nodes_total + 3) & ~3;
+    const int wave_words = (2 * nodes_total + keys_total + 3) & ~3;
+    float2 *nodes = reinterpret_cast<float2 *>(reinterpret_cast<uint32_t *>(lds4) + shared_words + wave * wave_words);
+    uint32_t *keys = reinterpret_cast<uint32_t *>(nodes + nodes_total);
+
+    // ---- once per workgroup: work lists and per-octave constants ----------------------
+    for (int o = 0; o < N; ++o) {
+        const int nnx = a.nnx[o], nny = a.nny[o], kx = a.kxoff[o], ky = a.kyoff[o], no = a.noff[o];
+        for (int i = tid; i < nnx + nny; i += 256)
+            wl_key[kx + i] = ((uint32_t)o << 24) | (i < nnx ? (uint32_t)i : ((1u << 23) | (uint32_t)(i - nnx)));
+        for (int q = tid; q < nnx * nny; q += 256) {
+            const int i = q / nny, j = q - i * nny;  // column-major
+            wl_node[no + q] = ((uint32_t)o << 28) | ((uint32_t)(ky + j) << 14) | (uint32_t)(kx + i);
+        }
+    }
+    if (tid < N) {
+        pre_key[tid] = key_prefix(a.seed, tid);
+        p_shift[tid] = a.shift[tid];
+        p_noff[tid] = a.noff[tid];
+        p_amp[tid] = a.amp[tid];
+        p_inv2p[tid] = a.inv2p[tid];
+    }
+    __syncthreads();
+
+    // Fixed-period octaves: node block, its row count, and the lane's x-bases (strips are
+    // 64-aligned, so for a period <= 64 the column fraction depends on the lane only).
+    auto fixed = [&](int o) -> Fixed {
+        Fixed f{nodes, 2, XB{0.0f, 0.0f, 0.0f}};
+        if (o >= 0) {
+            const int s = p_shift[o];
+            f.nb = nodes + p_noff[o];
+            f.nny = a.nny[o];
+            f.xb = xbases<M>((float)(2 * (lane & ((1 << s) - 1)) + 1) * p_inv2p[o]);
+        }
+        return f;
+    };
+    const Fixed f64 = fixed(a.o64), f32 = fixed(a.o32), f16 = fixed(H16 ? a.o16 : -1), f8 = fixed(H8 ? a.o8 : -1),
+                f4 = fixed(H4 ? a.o4 : -1), f2 = fixed(H2 ? a.o2 : -1), f1 = fixed(H1 ? a.o1 : -1);
+    const bool has64 = a.o64 >= 0, has32 = a.o32 >= 0;
+    const int n_generic = a.n_generic;
+
+    const int64_t nwaves = (int64_t)gridDim.x * kStripWavesPerWg;
+    const int64_t xe = a.x0 + a.nx, ye = a.y0 + a.ny;
+    OutT *out = reinterpret_cast<OutT *>(a.out);
+    for (int64_t st = (int64_t)blockIdx.x * kStripWavesPerWg + wave; st < a.strips; st += nwaves) {
+        const int64_t bsy = st / a.strips_x, bsx = st - bsy * a.strips_x;
+        const int64_t X0 = a.sx_base + bsx * kStripW, Y0 = a.sy_base + bsy * kStripH;
+
+        // ---- hashing: column / row keys, then amplitude-scaled node gradients ------------
+        for (int q = lane; q < keys_total; q += 64) {
+            const uint32_t it = wl_key[q];
+            const int o = it >> 24;
+            const bool row = (it & (1u << 23)) != 0;
+            const int64_t base = row ? Y0 : X0;
+            const uint32_t k0 = row ? pre_key[o] : 0x27D4EB2Fu;  // row keys: octave prefix; column keys: x salt
+            keys[q] = absorb_index(k0, (base >> p_shift[o]) + (int64_t)(it & 0x7FFFFF));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int q = lane; q < nodes_total; q += 64) {
+            const uint32_t it = wl_node[q];
+            const float amp = p_amp[it >> 28];
+            const float2 g = grad2(key_combine(keys[(it >> 14) & 0x3FFF], keys[it & 0x3FFF]));
+            nodes[q] = make_float2(g.x * amp, g.y * amp);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        // ---- octaves of period >= kStripH: one polynomial in v per lane ----------------
+        float C[D1];
+#pragma unroll
+        for (int b = 0; b < D1; ++b) C[b] = 0.0f;
+        for (int o = 0; o < n_generic; ++o) {  // period >= 128: the strip is inside one cell
+            const int s = p_shift[o];
+            const uint32_t mask = (1u << s) - 1u;
+            const float inv2p = p_inv2p[o];
+            const XB xb = xbases<M>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p);
+            const CF c = column_form(nodes + p_noff[o], 2, xb);
+            const float invp = 2.0f * inv2p;
+            const float tau = (float)(((uint32_t)Y0 & mask) + (uint32_t)(kStripH / 2)) * invp - 0.5f;
+            add_mapped<M>(C, c, tau, (float)kStripH * invp);
+        }
+        if (has64) {  // t - 1/2 = +-1/4 + v/2
+            const CF c = column_form(f64.nb, 2, f64.xb);
+            add_mapped<M>(C, c, ((uint32_t)Y0 & 32u) ? 0.25f : -0.25f, 0.5f);
+        }
+        if (has32) {  // t - 1/2 = v: no shift
+            const CF c = column_form(f32.nb + (lane >> 5) * 2, 2, f32.xb);
+            add_mapped<M, false>(C, c, 0.0f, 1.0f);
+        }
+
+        // ---- rows: one store per row of the wave; interior strips take the unmasked path --
+        const int rlo = (int)max<int64_t>(0, min<int64_t>(kStripH, a.y0 - Y0));
+        const int rhi = (int)max<int64_t>(0, min<int64_t>(kStripH, ye - Y0));
+        const int clo = (int)max<int64_t>(0, min<int64_t>(kStripW, a.x0 - X0));
+        const int chi = (int)max<int64_t>(0, min<int64_t>(kStripW, xe - X0));
+        OutT *row0 = out + (Y0 - a.y0) * a.pitch + (X0 - a.x0);
+        const RowCtx<M> rc{f16, f8, f4, f2, f1, lane, a.pitch};
+        if (rlo == 0 && rhi == kStripH && clo == 0 && chi == kStripW)
+            strip_rows<M, OutT, LO, true>(rc, C, row0, 0, kStripH, false);
+        else
+            strip_rows<M, OutT, LO, false>(rc, C, row0, rlo, rhi, lane >= clo && lane < chi);
+        __builtin_amdgcn_wave_barrier();  // the next strip rewrites this wave's keys and nodes
+    }
+}
+
+template <int M, typename OutT, int LO>
+static hipError_t launch_st(const Fbm2dStripArgs &a, int grid, size_t lds, hipStream_t s)
+{
+    auto kern = k_fbm2d_strip<M, OutT, LO>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int M, typename OutT>
+static hipError_t launch_lo(const Fbm2dStripArgs &a, int grid, size_t lds, hipStream_t s)
+{
+    switch (a.lo) {
+    case 0: return launch_st<M, OutT, 0>(a, grid, lds, s);
+    case 1: return launch_st<M, OutT, 1>(a, grid, lds, s);
+    case 2: return launch_st<M, OutT, 2>(a, grid, lds, s);
+    case 3: return launch_st<M, OutT, 3>(a, grid, lds, s);
+    case 4: return launch_st<M, OutT, 4>(a, grid, lds, s);
+    default: return launch_st<M, OutT, 5>(a, grid, lds, s);
+    }
+}
+
+template <int M, typename OutT>
+static int resident_st(int lo, size_t lds)
+{
+    int n = 0;
+    hipError_t e;
+    switch (lo) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, 0>, 256, lds); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, 1>, 256, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, 2>, 256, lds); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, 3>, 256, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, 4>, 256, lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, 5>, 256, lds); break;
+    }
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+int strip_wgs_per_cu(int smooth, bool f16, int lo, size_t lds)
+{
+    if (smooth == 1) return f16 ? resident_st<1, __half>(lo, lds) : resident_st<1, float>(lo, lds);
+    return f16 ? resident_st<2, __half>(lo, lds) : resident_st<2, float>(lo, lds);
+}
+
+hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, bool f16, int grid, size_t lds, hipStream_t s)
+{
+    if (smooth == 1) return f16 ? launch_lo<1, __half>(a, grid, lds, s) : launch_lo<1, float>(a, grid, lds, s);
+    return f16 ? launch_lo<2, __half>(a, grid, lds, s) : launch_lo<2, float>(a, grid, lds, s);
+}
+
+}  // namespace ptg

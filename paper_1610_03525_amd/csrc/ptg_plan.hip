@@ -100,6 +100,71 @@ static int fbm2d_dyadic(const ptg_params *p, int k, int64_t x0, int64_t y0, int6
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d dyadic launch");
 }
 
+// Plain FP32 dyadic field through the strip kernel; returns 1 when a strip's node
+// footprint does not fit the workgroup's LDS (the caller falls back).
+static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out,
+                       int64_t pitch, hipStream_t s)
+{
+    constexpr int SW = kStripW, SH = kStripH;
+    Fbm2dStripArgs a{};
+    a.x0 = x0;
+    a.y0 = y0;
+    a.nx = nx;
+    a.ny = ny;
+    a.pitch = pitch;
+    a.out = out;
+    a.sx_base = floor_to(x0, SW);
+    a.sy_base = floor_to(y0, SH);
+    const int64_t strips_x = (x0 + nx - a.sx_base + SW - 1) / SW;
+    const int64_t strips_y = (y0 + ny - a.sy_base + SH - 1) / SH;
+    if (strips_x > 0x7FFFFFFFLL) return 1;
+    a.strips_x = (int32_t)strips_x;
+    a.strips = strips_x * strips_y;
+    double freq[kMaxOctaves];
+    octave_tables(p, freq, a.amp);
+    a.octaves = p->octaves;
+    a.seed = p->seed;
+    a.o64 = a.o32 = a.o16 = a.o8 = a.o4 = a.o2 = a.o1 = -1;
+    const int smin = k - (p->octaves - 1);
+    // the row loop assumes every period from 16 down to the finest is present
+    if (smin <= 4 && k < 4) return 1;
+    a.lo = std::min(smin, 5);
+    int nodes = 0, keys = 0;
+    for (int o = 0; o < p->octaves; ++o) {
+        const int sh = k - o;
+        a.shift[o] = sh;
+        a.inv2p[o] = std::ldexp(1.0f, -(sh + 1));
+        if (sh >= 7) a.n_generic = o + 1;
+        if (sh == 6) a.o64 = o;
+        if (sh == 5) a.o32 = o;
+        if (sh == 4) a.o16 = o;
+        if (sh == 3) a.o8 = o;
+        if (sh == 2) a.o4 = o;
+        if (sh == 1) a.o2 = o;
+        if (sh == 0) a.o1 = o;
+        a.nnx[o] = std::max(SW >> std::min(sh, 30), 1) + 1;
+        a.nny[o] = std::max(SH >> std::min(sh, 30), 1) + 1;
+        a.noff[o] = nodes;
+        a.kxoff[o] = keys;
+        a.kyoff[o] = keys + a.nnx[o];
+        nodes += a.nnx[o] * a.nny[o];
+        keys += a.nnx[o] + a.nny[o];
+    }
+    a.nodes_total = nodes;
+    a.keys_total = keys;
+    const size_t shared_words = (size_t)((keys + nodes + 3) & ~3);
+    const size_t wave_words = (size_t)((2 * nodes + keys + 3) & ~3);
+    const size_t lds = (shared_words + kStripWavesPerWg * wave_words) * 4;
+    if (lds > kDyMaxLds || keys >= (1 << 14)) return 1;
+    // a persistent grid of exactly the resident workgroups (a partial second round would
+    // leave most of the chip idle at the end)
+    const int64_t per_cu = strip_wgs_per_cu(p->smoothness, p->out_dtype == PTG_F16, a.lo, lds);
+    const int64_t wgs = (a.strips + kStripWavesPerWg - 1) / kStripWavesPerWg;
+    const int grid = (int)std::min<int64_t>(wgs, (int64_t)device_cus() * per_cu);
+    hipError_t e = launch_fbm2d_strip(a, p->smoothness, p->out_dtype == PTG_F16, grid, lds, s);
+    return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d strip launch");
+}
+
 size_t general_args_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out,
                        int64_t pitch, Fbm2dArgs *a)
 {
@@ -150,7 +215,9 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     if (p->path == PTG_PATH_DYADIC && !dy)
         return fail(PTG_EINVAL, "the dyadic kernel needs base_freq = 2^-k (k <= %d) and lacunarity 2", kDyMaxShift);
     if (dy && p->path != PTG_PATH_GENERAL) {
-        const int rc = fbm2d_dyadic(p, k, x0, y0, nx, ny, out, pitch, s);
+        int rc = fbm2d_strip(p, k, x0, y0, nx, ny, out, pitch, s);
+        if (rc <= 0) return rc;
+        rc = fbm2d_dyadic(p, k, x0, y0, nx, ny, out, pitch, s);
         if (rc <= 0) return rc;
         if (p->path == PTG_PATH_DYADIC)
             return fail(PTG_EINVAL, "the dyadic kernel's lattice footprint exceeds the workgroup's LDS");
