@@ -2,18 +2,21 @@
 // plain FP32 form on the vector ALUs.
 //
 // With f_o = 2^-s the sample-centre fraction is exact: t = (2 (X mod 2^s) + 1) / 2^(s+1).
-// One wave owns a world-aligned strip of kStripW x kStripH samples, lane = column, and walks
-// strips with a grid stride; the waves of a workgroup never synchronise after the prologue.
+// One wave owns a world-aligned strip of kStripW x kStripH (64 x 64) samples, lane = column,
+// and walks strips with a grid stride; the waves of a workgroup never synchronise after the
+// prologue.
 //
 // Cell polynomial (Sec. 2, Sec. 3.4), fixed column x: the 1D Hermite form in y
 //   h(y) = E0 + (E1 - E0) S(t) + Q0 b10(t) + Q1 b11(t),
 //   E_cy = gx(cx, cy) b10(tx) + gx(cx+1, cy) b11(tx),  Q_cy = gy(cx, cy) + S(tx) (gy(cx+1, cy) - gy(cx, cy)).
 // Octaves are summed in three ways:
-//  * period >= kStripH: a lane's column meets one cell of the octave over the whole strip,
-//    so each such octave's column form is re-expanded in the strip's centred row
-//    coordinate v = (2 r - 31) / 64 (t - 1/2 = tau + sigma v, sigma = 32 / P) and all of
-//    them are added into ONE polynomial of degree 2M+1 per lane, evaluated by Horner per row;
-//  * period 16: the same, once per half strip;
+//  * period >= 64: a lane's column meets one cell of the octave over the whole strip, so
+//    each such octave's column form is re-expanded in the strip's centred row coordinate
+//    v = (2 r - 63) / 128 (t - 1/2 = tau + sigma v, sigma = 64 / P) and all of them are added
+//    into ONE polynomial of degree 2M+1 per lane, evaluated by Horner per row;
+//  * periods 32 and 16: the same, once per half / quarter strip, after the fused polynomial
+//    is re-centred there (a piece is never evaluated away from its own cell: FP32 error of a
+//    quintic piece expanded about the strip centre would reach 4e-5 of the total amplitude);
 //  * period <= 8: the column form is formed once per cell row and evaluated per row with
 //    the row bases as constants (the row's position inside its cell is fixed by the unrolled
 //    row loop); which of these periods occur is a template parameter (the finest shift LO),
@@ -87,6 +90,17 @@ __device__ __forceinline__ CF column_form(const float2 *nb, int nny, const XB &x
     return c;
 }
 
+// c(v) -> c(d + w) as a polynomial in w (repeated synthetic division).
+template <int M>
+__device__ __forceinline__ void taylor_shift(float (&c)[2 * M + 2], float d)
+{
+    constexpr int D = 2 * M + 1;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = D - 1; j >= i; --j) c[j] += d * c[j + 1];
+}
+
 // Add the column form, as a polynomial in v with t - 1/2 = tau + sigma v, to C.
 // Powers of u = t - 1/2 of the bases (exact binary fractions):
 //   cubic:   S = 1/2 + 3/2 u - 2 u^3,  b10 = 1/8 - 1/4 u - 1/2 u^2 + u^3,  b11 = -1/8 - 1/4 u + 1/2 u^2 + u^3
@@ -135,9 +149,8 @@ struct Fixed {
     XB xb;
 };
 
-template <int M>
 struct RowCtx {
-    Fixed f16, f8, f4, f2, f1;
+    Fixed f32, f16, f8, f4, f2, f1;
     int lane;
     int64_t pitch;
 };
@@ -150,64 +163,81 @@ __device__ __forceinline__ float add_direct(float val, const CF &c, const XB &rb
     return __builtin_fmaf(c.Q1, rb.b11, val);
 }
 
-// The 32 rows of a strip: the fused polynomial C (+ the period-16 piece per half) by
-// Horner, plus the direct octaves; FULL = every sample of the strip is stored.
+// The rows of a strip.  The fused polynomial C (in the strip coordinate v) is re-centred
+// on each half strip, where the period-32 piece is added (t - 1/2 = 2 w), and again on each
+// quarter, where the period-16 piece is added (t - 1/2 = 4 w); every row then evaluates by
+// Horner in its quarter's coordinate w = (2 j - 15) / 128, j = row - 16 q, so no piece is
+// evaluated away from its own cell.  The direct octaves follow; FULL = every sample of the
+// strip is stored.
 template <int M, typename OutT, int LO, bool FULL>
-__device__ __forceinline__ void strip_rows(const RowCtx<M> &x, const float (&C)[2 * M + 2], OutT *rp, int rlo, int rhi,
+__device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 * M + 2], OutT *rp, int rlo, int rhi,
                                            bool lane_ok)
 {
     constexpr int D1 = 2 * M + 2;
-    constexpr bool H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
+    constexpr bool H32 = LO <= 5, H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
     const int lane = x.lane;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         float Ch[D1];
 #pragma unroll
         for (int b = 0; b < D1; ++b) Ch[b] = C[b];
-        if (H16) {  // period 16: one cell row per half strip, t - 1/2 = (1/2 - h) + 2 v
-            const CF c = column_form(x.f16.nb + (lane >> 4) * x.f16.nny + h, x.f16.nny, x.f16.xb);
-            add_mapped<M>(Ch, c, 0.5f - (float)h, 2.0f);
+        taylor_shift<M>(Ch, (float)(2 * h - 1) * 0.25f);  // half centre v = -1/4, +1/4
+        if (H32) {  // period 32: one cell row per half strip
+            const CF c = column_form(x.f32.nb + (lane >> 5) * x.f32.nny + h, x.f32.nny, x.f32.xb);
+            add_mapped<M, false>(Ch, c, 0.0f, 2.0f);
         }
-        CF c8{}, c4{}, c2{}, c1{};
-        float c0 = Ch[0];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 16 * h + r;
-            bool fresh = false;
-            if (H8 && (row & 7) == 0) {
-                c8 = column_form(x.f8.nb + (lane >> 3) * x.f8.nny + (row >> 3), x.f8.nny, x.f8.xb);
-                fresh = true;
-            }
-            if (H4 && (row & 3) == 0) {
-                c4 = column_form(x.f4.nb + (lane >> 2) * x.f4.nny + (row >> 2), x.f4.nny, x.f4.xb);
-                fresh = true;
-            }
-            if (H2 && (row & 1) == 0) {
-                c2 = column_form(x.f2.nb + (lane >> 1) * x.f2.nny + (row >> 1), x.f2.nny, x.f2.xb);
-                fresh = true;
-            }
-            if (H1) {
-                c1 = column_form(x.f1.nb + lane * x.f1.nny + row, x.f1.nny, x.f1.xb);
-                fresh = true;
-            }
-            if (fresh) {  // constant term: the fused polynomial's plus the direct octaves' E0
-                c0 = Ch[0];
-                if (H8) c0 += c8.E0;
-                if (H4) c0 += c4.E0;
-                if (H2) c0 += c2.E0;
-                if (H1) c0 += c1.E0;
-            }
-            const float v = (float)(2 * row - (kStripH - 1)) * (1.0f / (float)(2 * kStripH));
-            float val = Ch[D1 - 1];
+        for (int qh = 0; qh < 2; ++qh) {
+            const int q = 2 * h + qh;
+            float Cq[D1];
 #pragma unroll
-            for (int b = D1 - 2; b >= 1; --b) val = __builtin_fmaf(val, v, Ch[b]);
-            val = __builtin_fmaf(val, v, c0);
-            if (H8) val = add_direct(val, c8, row_bases<M>(row & 7, 8));
-            if (H4) val = add_direct(val, c4, row_bases<M>(row & 3, 4));
-            if (H2) val = add_direct(val, c2, row_bases<M>(row & 1, 2));
-            if (H1) val = add_direct(val, c1, row_bases<M>(0, 1));
-            if (FULL || (row >= rlo && row < rhi && lane_ok)) rp[lane] = st_out<OutT>(val);
-            rp += x.pitch;
+            for (int b = 0; b < D1; ++b) Cq[b] = Ch[b];
+            taylor_shift<M>(Cq, (float)(2 * qh - 1) * 0.125f);  // quarter centre, from the half's
+            if (H16) {  // period 16: one cell row per quarter
+                const CF c = column_form(x.f16.nb + (lane >> 4) * x.f16.nny + q, x.f16.nny, x.f16.xb);
+                add_mapped<M, false>(Cq, c, 0.0f, 4.0f);
+            }
+            CF c8{}, c4{}, c2{}, c1{};
+            float c0 = Cq[0];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int row = 16 * q + j;
+                bool fresh = false;
+                if (H8 && (row & 7) == 0) {
+                    c8 = column_form(x.f8.nb + (lane >> 3) * x.f8.nny + (row >> 3), x.f8.nny, x.f8.xb);
+                    fresh = true;
+                }
+                if (H4 && (row & 3) == 0) {
+                    c4 = column_form(x.f4.nb + (lane >> 2) * x.f4.nny + (row >> 2), x.f4.nny, x.f4.xb);
+                    fresh = true;
+                }
+                if (H2 && (row & 1) == 0) {
+                    c2 = column_form(x.f2.nb + (lane >> 1) * x.f2.nny + (row >> 1), x.f2.nny, x.f2.xb);
+                    fresh = true;
+                }
+                if (H1) {
+                    c1 = column_form(x.f1.nb + lane * x.f1.nny + row, x.f1.nny, x.f1.xb);
+                    fresh = true;
+                }
+                if (fresh) {  // constant term: the fused polynomial's plus the direct octaves' E0
+                    c0 = Cq[0];
+                    if (H8) c0 += c8.E0;
+                    if (H4) c0 += c4.E0;
+                    if (H2) c0 += c2.E0;
+                    if (H1) c0 += c1.E0;
+                }
+                const float w = (float)(2 * j - 15) * (1.0f / 128.0f);
+                float val = Cq[D1 - 1];
+#pragma unroll
+                for (int b = D1 - 2; b >= 1; --b) val = __builtin_fmaf(val, w, Cq[b]);
+                val = __builtin_fmaf(val, w, c0);
+                if (H8) val = add_direct(val, c8, row_bases<M>(row & 7, 8));
+                if (H4) val = add_direct(val, c4, row_bases<M>(row & 3, 4));
+                if (H2) val = add_direct(val, c2, row_bases<M>(row & 1, 2));
+                if (H1) val = add_direct(val, c1, row_bases<M>(0, 1));
+                if (FULL || (row >= rlo && row < rhi && lane_ok)) rp[lane] = st_out<OutT>(val);
+                rp += x.pitch;
+            }
         }
     }
 }
@@ -216,14 +246,15 @@ template <int M, typename OutT, int LO>
 __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
 {
     constexpr int D1 = 2 * M + 2;
-    constexpr bool H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
+    constexpr bool H32 = LO <= 5, H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
     extern __shared__ float4 lds4[];
     __shared__ uint32_t pre_key[kMaxOctaves];
     __shared__ int p_shift[kMaxOctaves], p_noff[kMaxOctaves];
     __shared__ float p_amp[kMaxOctaves], p_inv2p[kMaxOctaves];
 
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63, nthreads = blockDim.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wpg = nthreads >> 6;  // waves per workgroup
     const int N = a.octaves;
     const int nodes_total = a.nodes_total, keys_total = a.keys_total;
     // LDS: [wl_key | wl_node] shared, then per wave [nodes (float2) | keys (u32)]
@@ -237,9 +268,9 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
     // ---- once per workgroup: work lists and per-octave constants ----------------------
     for (int o = 0; o < N; ++o) {
         const int nnx = a.nnx[o], nny = a.nny[o], kx = a.kxoff[o], ky = a.kyoff[o], no = a.noff[o];
-        for (int i = tid; i < nnx + nny; i += 256)
+        for (int i = tid; i < nnx + nny; i += nthreads)
             wl_key[kx + i] = ((uint32_t)o << 24) | (i < nnx ? (uint32_t)i : ((1u << 23) | (uint32_t)(i - nnx)));
-        for (int q = tid; q < nnx * nny; q += 256) {
+        for (int q = tid; q < nnx * nny; q += nthreads) {
             const int i = q / nny, j = q - i * nny;  // column-major
             wl_node[no + q] = ((uint32_t)o << 28) | ((uint32_t)(ky + j) << 14) | (uint32_t)(kx + i);
         }
@@ -253,8 +284,6 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
     }
     __syncthreads();
 
-    // Fixed-period octaves: node block, its row count, and the lane's x-bases (strips are
-    // 64-aligned, so for a period <= 64 the column fraction depends on the lane only).
     auto fixed = [&](int o) -> Fixed {
         Fixed f{nodes, 2, XB{0.0f, 0.0f, 0.0f}};
         if (o >= 0) {
@@ -265,15 +294,16 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
         }
         return f;
     };
-    const Fixed f64 = fixed(a.o64), f32 = fixed(a.o32), f16 = fixed(H16 ? a.o16 : -1), f8 = fixed(H8 ? a.o8 : -1),
-                f4 = fixed(H4 ? a.o4 : -1), f2 = fixed(H2 ? a.o2 : -1), f1 = fixed(H1 ? a.o1 : -1);
-    const bool has64 = a.o64 >= 0, has32 = a.o32 >= 0;
+    const Fixed f64 = fixed(a.o64);
+    const RowCtx rc0{fixed(H32 ? a.o32 : -1), fixed(H16 ? a.o16 : -1), fixed(H8 ? a.o8 : -1), fixed(H4 ? a.o4 : -1),
+                     fixed(H2 ? a.o2 : -1),   fixed(H1 ? a.o1 : -1),   lane,                   a.pitch};
+    const bool has64 = a.o64 >= 0;
     const int n_generic = a.n_generic;
 
-    const int64_t nwaves = (int64_t)gridDim.x * kStripWavesPerWg;
+    const int64_t nwaves = (int64_t)gridDim.x * wpg;
     const int64_t xe = a.x0 + a.nx, ye = a.y0 + a.ny;
     OutT *out = reinterpret_cast<OutT *>(a.out);
-    for (int64_t st = (int64_t)blockIdx.x * kStripWavesPerWg + wave; st < a.strips; st += nwaves) {
+    for (int64_t st = (int64_t)blockIdx.x * wpg + wave; st < a.strips; st += nwaves) {
         const int64_t bsy = st / a.strips_x, bsx = st - bsy * a.strips_x;
         const int64_t X0 = a.sx_base + bsx * kStripW, Y0 = a.sy_base + bsy * kStripH;
 
@@ -299,7 +329,7 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-        // ---- octaves of period >= kStripH: one polynomial in v per lane ----------------
+        // ---- octaves of period >= 64: one polynomial in v per lane ------------------------
         float C[D1];
 #pragma unroll
         for (int b = 0; b < D1; ++b) C[b] = 0.0f;
@@ -313,12 +343,8 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
             const float tau = (float)(((uint32_t)Y0 & mask) + (uint32_t)(kStripH / 2)) * invp - 0.5f;
             add_mapped<M>(C, c, tau, (float)kStripH * invp);
         }
-        if (has64) {  // t - 1/2 = +-1/4 + v/2
+        if (has64) {  // t - 1/2 = v: no shift
             const CF c = column_form(f64.nb, 2, f64.xb);
-            add_mapped<M>(C, c, ((uint32_t)Y0 & 32u) ? 0.25f : -0.25f, 0.5f);
-        }
-        if (has32) {  // t - 1/2 = v: no shift
-            const CF c = column_form(f32.nb + (lane >> 5) * 2, 2, f32.xb);
             add_mapped<M, false>(C, c, 0.0f, 1.0f);
         }
 
@@ -328,17 +354,16 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
         const int clo = (int)max<int64_t>(0, min<int64_t>(kStripW, a.x0 - X0));
         const int chi = (int)max<int64_t>(0, min<int64_t>(kStripW, xe - X0));
         OutT *row0 = out + (Y0 - a.y0) * a.pitch + (X0 - a.x0);
-        const RowCtx<M> rc{f16, f8, f4, f2, f1, lane, a.pitch};
         if (rlo == 0 && rhi == kStripH && clo == 0 && chi == kStripW)
-            strip_rows<M, OutT, LO, true>(rc, C, row0, 0, kStripH, false);
+            strip_rows<M, OutT, LO, true>(rc0, C, row0, 0, kStripH, false);
         else
-            strip_rows<M, OutT, LO, false>(rc, C, row0, rlo, rhi, lane >= clo && lane < chi);
+            strip_rows<M, OutT, LO, false>(rc0, C, row0, rlo, rhi, lane >= clo && lane < chi);
         __builtin_amdgcn_wave_barrier();  // the next strip rewrites this wave's keys and nodes
     }
 }
 
 template <int M, typename OutT, int LO>
-static hipError_t launch_st(const Fbm2dStripArgs &a, int grid, size_t lds, hipStream_t s)
+static hipError_t launch_st(const Fbm2dStripArgs &a, int grid, int waves, size_t lds, hipStream_t s)
 {
     auto kern = k_fbm2d_strip<M, OutT, LO>;
     if (lds > 65536) {
@@ -346,49 +371,59 @@ static hipError_t launch_st(const Fbm2dStripArgs &a, int grid, size_t lds, hipSt
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * waves), lds, s, a);
     return hipGetLastError();
 }
 
 template <int M, typename OutT>
-static hipError_t launch_lo(const Fbm2dStripArgs &a, int grid, size_t lds, hipStream_t s)
+static hipError_t launch_lo(const Fbm2dStripArgs &a, int grid, int waves, size_t lds, hipStream_t s)
 {
     switch (a.lo) {
-    case 0: return launch_st<M, OutT, 0>(a, grid, lds, s);
-    case 1: return launch_st<M, OutT, 1>(a, grid, lds, s);
-    case 2: return launch_st<M, OutT, 2>(a, grid, lds, s);
-    case 3: return launch_st<M, OutT, 3>(a, grid, lds, s);
-    case 4: return launch_st<M, OutT, 4>(a, grid, lds, s);
-    default: return launch_st<M, OutT, 5>(a, grid, lds, s);
+    case 0: return launch_st<M, OutT, 0>(a, grid, waves, lds, s);
+    case 1: return launch_st<M, OutT, 1>(a, grid, waves, lds, s);
+    case 2: return launch_st<M, OutT, 2>(a, grid, waves, lds, s);
+    case 3: return launch_st<M, OutT, 3>(a, grid, waves, lds, s);
+    case 4: return launch_st<M, OutT, 4>(a, grid, waves, lds, s);
+    case 5: return launch_st<M, OutT, 5>(a, grid, waves, lds, s);
+    default: return launch_st<M, OutT, 6>(a, grid, waves, lds, s);
     }
+}
+
+template <int M, typename OutT, int LO>
+static int resident_one(int waves, size_t lds)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, LO>, 64 * waves, lds) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
 }
 
 template <int M, typename OutT>
-static int resident_st(int lo, size_t lds)
+static int resident_st(int lo, int waves, size_t lds)
 {
-    int n = 0;
-    hipError_t e;
     switch (lo) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, 0>, 256, lds); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, 1>, 256, lds); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, 2>, 256, lds); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, 3>, 256, lds); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, 4>, 256, lds); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, 5>, 256, lds); break;
+    case 0: return resident_one<M, OutT, 0>(waves, lds);
+    case 1: return resident_one<M, OutT, 1>(waves, lds);
+    case 2: return resident_one<M, OutT, 2>(waves, lds);
+    case 3: return resident_one<M, OutT, 3>(waves, lds);
+    case 4: return resident_one<M, OutT, 4>(waves, lds);
+    case 5: return resident_one<M, OutT, 5>(waves, lds);
+    default: return resident_one<M, OutT, 6>(waves, lds);
     }
-    return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-int strip_wgs_per_cu(int smooth, bool f16, int lo, size_t lds)
+int strip_wgs_per_cu(int smooth, bool f16, int lo, int waves, size_t lds)
 {
-    if (smooth == 1) return f16 ? resident_st<1, __half>(lo, lds) : resident_st<1, float>(lo, lds);
-    return f16 ? resident_st<2, __half>(lo, lds) : resident_st<2, float>(lo, lds);
+    if (smooth == 1) return f16 ? resident_st<1, __half>(lo, waves, lds) : resident_st<1, float>(lo, waves, lds);
+    return f16 ? resident_st<2, __half>(lo, waves, lds) : resident_st<2, float>(lo, waves, lds);
 }
 
-hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, bool f16, int grid, size_t lds, hipStream_t s)
+hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, bool f16, int grid, int waves, size_t lds,
+                              hipStream_t s)
 {
-    if (smooth == 1) return f16 ? launch_lo<1, __half>(a, grid, lds, s) : launch_lo<1, float>(a, grid, lds, s);
-    return f16 ? launch_lo<2, __half>(a, grid, lds, s) : launch_lo<2, float>(a, grid, lds, s);
+    if (smooth == 1)
+        return f16 ? launch_lo<1, __half>(a, grid, waves, lds, s) : launch_lo<1, float>(a, grid, waves, lds, s);
+    return f16 ? launch_lo<2, __half>(a, grid, waves, lds, s) : launch_lo<2, float>(a, grid, waves, lds, s);
 }
 
 }  // namespace ptg

@@ -74,8 +74,8 @@ struct Fbm2dDyadicArgs {
 // kStripW x kStripH samples, one wave each (lane = column).  Per-octave node footprints of
 // a strip do not depend on its position, so the node / key layout is fixed per launch.
 constexpr int kStripW = 64;
-constexpr int kStripH = 32;
-constexpr int kStripWavesPerWg = 4;
+constexpr int kStripH = 64;
+constexpr int kStripWavesPerWg = 4;  // at most; fewer when a wave's nodes need more LDS
 
 struct Fbm2dStripArgs {
     int64_t x0, y0, nx, ny, pitch;  // output window (world) and row pitch (elements)
@@ -94,15 +94,16 @@ struct Fbm2dStripArgs {
     int32_t strips_x;
     int32_t n_generic;                // octaves 0 .. n_generic-1 have period >= 128
     int32_t o64, o32, o16, o8, o4, o2, o1;  // octave of period 64, 32, ..., 1, or -1
-    int32_t lo;                       // min(finest shift, 5): selects the kernel's row loop
+    int32_t lo;                       // min(finest shift, 6): selects the kernel's row loop
 };
 
 // Launch wrappers (defined in the .hip translation units).  They assume validated
 // arguments and return the HIP status of the launch.
 hipError_t launch_fbm2d_general(const Fbm2dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fbm2d_dyadic(const Fbm2dDyadicArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
-hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, bool f16, int grid, size_t lds_bytes, hipStream_t s);
-int strip_wgs_per_cu(int smooth, bool f16, int lo, size_t lds_bytes);  // resident workgroups per CU
+hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, bool f16, int grid, int waves, size_t lds_bytes,
+                              hipStream_t s);
+int strip_wgs_per_cu(int smooth, bool f16, int lo, int waves, size_t lds_bytes);  // resident workgroups per CU
 hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
 
 hipError_t launch_coords(double f0, double lac, int octaves, int64_t x0, int64_t n, int64_t *cells, float *frac,

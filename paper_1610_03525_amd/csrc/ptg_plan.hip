@@ -126,9 +126,9 @@ static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
     a.seed = p->seed;
     a.o64 = a.o32 = a.o16 = a.o8 = a.o4 = a.o2 = a.o1 = -1;
     const int smin = k - (p->octaves - 1);
-    // the row loop assumes every period from 16 down to the finest is present
-    if (smin <= 4 && k < 4) return 1;
-    a.lo = std::min(smin, 5);
+    // the row loop assumes every period from 32 down to the finest is present
+    if (smin <= 5 && k < 5) return 1;
+    a.lo = std::min(smin, 6);
     int nodes = 0, keys = 0;
     for (int o = 0; o < p->octaves; ++o) {
         const int sh = k - o;
@@ -154,14 +154,18 @@ static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
     a.keys_total = keys;
     const size_t shared_words = (size_t)((keys + nodes + 3) & ~3);
     const size_t wave_words = (size_t)((2 * nodes + keys + 3) & ~3);
-    const size_t lds = (shared_words + kStripWavesPerWg * wave_words) * 4;
-    if (lds > kDyMaxLds || keys >= (1 << 14)) return 1;
+    if (keys >= (1 << 14)) return 1;
+    // waves per workgroup: as many (up to 4) as the private node blocks allow in LDS
+    int waves = kStripWavesPerWg;
+    while (waves > 1 && (shared_words + waves * wave_words) * 4 > kDyMaxLds) --waves;
+    const size_t lds = (shared_words + waves * wave_words) * 4;
+    if (lds > kDyMaxLds) return 1;
     // a persistent grid of exactly the resident workgroups (a partial second round would
     // leave most of the chip idle at the end)
-    const int64_t per_cu = strip_wgs_per_cu(p->smoothness, p->out_dtype == PTG_F16, a.lo, lds);
-    const int64_t wgs = (a.strips + kStripWavesPerWg - 1) / kStripWavesPerWg;
+    const int64_t per_cu = strip_wgs_per_cu(p->smoothness, p->out_dtype == PTG_F16, a.lo, waves, lds);
+    const int64_t wgs = (a.strips + waves - 1) / waves;
     const int grid = (int)std::min<int64_t>(wgs, (int64_t)device_cus() * per_cu);
-    hipError_t e = launch_fbm2d_strip(a, p->smoothness, p->out_dtype == PTG_F16, grid, lds, s);
+    hipError_t e = launch_fbm2d_strip(a, p->smoothness, p->out_dtype == PTG_F16, grid, waves, lds, s);
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d strip launch");
 }
 
