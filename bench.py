@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="wall-time budget of the oracle sample")
     ap.add_argument("--path", default="auto", choices=["auto", "general", "dyadic"])
     ap.add_argument("--serve-requests", type=int, default=5000, help="tile-stream length (0: skip serving)")
+    ap.add_argument("--no-other-configs", action="store_true", help="skip the 3D, precision-form and small fields")
     ap.add_argument("--profile-calibration", action="store_true",
                     help="also run a plain torch fill and copy of the field size (counter calibration)")
     return ap.parse_args()
@@ -163,6 +164,7 @@ def main():
         print(f"field out of bounds: max|H| = {amax}", file=sys.stderr)
         sys.exit(1)
 
+    others = None if args.no_other_configs else other_configs(torch, ptg, stream)
     serving = run_serving(args.serve_requests) if args.serve_requests > 0 else None
 
     cpu = None
@@ -209,9 +211,66 @@ def main():
             "path_frac_of_measured": achieved_gbs / fill_gbs,
         },
         "cpu_baseline": cpu,
+        "other_configs": others,
         "serving": serving,
     }
     print(json.dumps(rec), flush=True)
+
+
+# ---- the other benchmark fields ---------------------------------------------------------
+def _time_launches(torch, stream, fn, n=10):
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(n):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / n
+
+
+def other_configs(torch, ptg, stream):
+    """3D 512^3 6-octave C2 volume; 16384^2 10-octave field at a world offset of 2^24 cells
+    through the plain FP32 path and the FP16 / BF16 matrix-core form (their errors against
+    the FP64 oracle are measured by the GPU tests); 256^2 4-octave field (launch-bound)."""
+    res = {}
+    sh = stream.cuda_stream
+    # 3D 512^3, 6 octaves, base lattice 8^3, C2
+    vol = torch.empty((512, 512, 512), dtype=torch.float32, device="cuda")
+    p3 = ptg.params(dim=3, smoothness=2, octaves=6, base_freq=8 / 512, seed=1)
+    ms = _time_launches(torch, stream, lambda: ptg.fbm_3d_raw(p3, 0, 0, 0, 512, 512, 512, vol.data_ptr(), sh), 5)
+    n3 = 512 ** 3
+    res["3d_512_6oct_c2"] = {"workload": "3D fBm 512^3, 6 octaves, base lattice 8^3, C2 quintic, FP32, seed 1",
+                             "kernel": "k_fbm3d_general", "ms": ms, "octave_samples_s": n3 * 6 / (ms * 1e-3),
+                             "hbm_frac": n3 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del vol
+    # 16384^2, 10 octaves, base lattice 32^2, offset (2^24 - 3) * 512, -(2^24 - 5) * 512
+    n, f0 = 16384, 32 / 16384
+    x0, y0 = (2 ** 24 - 3) * 512, -(2 ** 24 - 5) * 512
+    forms = {}
+    for form, basis, dt in (("plain", "monomial", torch.float32), ("mfma_f16", "monomial", torch.float16),
+                            ("mfma_f16", "centred", torch.float16), ("mfma_bf16", "monomial", torch.float16),
+                            ("mfma_bf16", "centred", torch.float16)):
+        out = torch.empty((n, n), dtype=dt, device="cuda")
+        q = ptg.params(smoothness=1, octaves=10, base_freq=f0, seed=1, form=form, basis=basis,
+                       out_dtype=ptg.PTG_F16 if dt == torch.float16 else ptg.PTG_F32)
+        ms = _time_launches(torch, stream, lambda: ptg.fbm_2d_raw(q, x0, y0, n, n, out.data_ptr(), n, sh), 5)
+        forms[f"{form}/{basis}" if form != "plain" else "plain_fp32"] = {
+            "ms": ms, "octave_samples_s": n * n * 10 / (ms * 1e-3),
+            "hbm_frac": n * n * out.element_size() / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del out
+    res["2d_16384_10oct_offset"] = {
+        "workload": "2D fBm 16384^2, 10 octaves, base lattice 32^2, world offset (2^24-3)*512, -(2^24-5)*512 "
+                    "samples, C1; FP16 output for the matrix-core forms, FP32 for the plain path",
+        "forms": forms}
+    # 256^2, 4 octaves, base lattice 8^2
+    small = torch.empty((256, 256), dtype=torch.float32, device="cuda")
+    q = ptg.params(smoothness=1, octaves=4, base_freq=8 / 256, seed=1)
+    ms = _time_launches(torch, stream, lambda: ptg.fbm_2d_raw(q, 0, 0, 256, 256, small.data_ptr(), 256, sh), 20)
+    res["2d_256_4oct"] = {"workload": "2D fBm 256^2, 4 octaves, base lattice 8^2, C1, FP32", "ms": ms,
+                          "octave_samples_s": 256 * 256 * 4 / (ms * 1e-3)}
+    return res
 
 
 # ---- tile stream -------------------------------------------------------------------
