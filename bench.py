@@ -29,7 +29,7 @@ PERSISTENCE = 0.5
 LACUNARITY = 2.0
 SEED = 1
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fbm2d_dyadic_2d_8192x8192_8oct_c1.traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fbm2d_strip_2d_8192x8192_8oct_c1.traffic.json")
 
 
 def measured_traffic():
