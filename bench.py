@@ -242,7 +242,7 @@ def other_configs(torch, ptg, stream):
     ms = _time_launches(torch, stream, lambda: ptg.fbm_3d_raw(p3, 0, 0, 0, 512, 512, 512, vol.data_ptr(), sh), 5)
     n3 = 512 ** 3
     res["3d_512_6oct_c2"] = {"workload": "3D fBm 512^3, 6 octaves, base lattice 8^3, C2 quintic, FP32, seed 1",
-                             "kernel": "k_fbm3d_general", "ms": ms, "octave_samples_s": n3 * 6 / (ms * 1e-3),
+                             "kernel": "k_fbm3d_strip", "ms": ms, "octave_samples_s": n3 * 6 / (ms * 1e-3),
                              "hbm_frac": n3 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     del vol
     # 16384^2, 10 octaves, base lattice 32^2, offset (2^24 - 3) * 512, -(2^24 - 5) * 512

@@ -79,8 +79,9 @@ extern "C" {
 /* ---- kernel choice for the plain form ----------------------------------------- */
 #define PTG_PATH_AUTO 0     /* dyadic kernel when it applies, else the general kernel    */
 #define PTG_PATH_GENERAL 1  /* any base frequency / lacunarity / origin                  */
-#define PTG_PATH_DYADIC 2   /* 2D only: base_freq = 2^-k (k <= 22), lacunarity = 2;     */
-                            /* PTG_EINVAL when the parameters are not of that kind       */
+#define PTG_PATH_DYADIC 2   /* base_freq = 2^-k (k <= 22), lacunarity = 2 (in 3D the     */
+                            /* ladder must also start at period >= 4 when it reaches   */
+                            /* period 4); PTG_EINVAL when the parameters are otherwise  */
 
 /* ---- bases for the MFMA forms (Vandermonde rows fed to the matrix cores) ------ */
 #define PTG_BASIS_MONOMIAL 0  /* V(t) = [1, t, t^2, t^3], C = monomial coefficients   */

@@ -51,7 +51,6 @@ int validate_params(const ptg_params *p, int dim)
         return fail(PTG_EINVAL, "unknown basis %d", p->basis);
     if (p->path != PTG_PATH_AUTO && p->path != PTG_PATH_GENERAL && p->path != PTG_PATH_DYADIC)
         return fail(PTG_EINVAL, "unknown path %d", p->path);
-    if (p->path == PTG_PATH_DYADIC && dim != 2) return fail(PTG_EINVAL, "the dyadic kernel is 2D only");
     double f = p->base_freq, a = 1.0;
     for (int o = 0; o < p->octaves; ++o) {
         if (!(f <= 1.0) || !(f > 0.0))

@@ -97,6 +97,34 @@ struct Fbm2dStripArgs {
     int32_t lo;                       // min(finest shift, 6): selects the kernel's row loop
 };
 
+// 3D dyadic ladders, plain FP32 form on the vector ALUs: world-aligned blocks of
+// k3BlockX x k3BlockY x k3BlockZ samples, one wave each (lane = x column).
+constexpr int k3BlockX = 64;
+constexpr int k3BlockY = 8;
+constexpr int k3BlockZ = 4;
+constexpr int k3TabMaxP = 64;  // octaves of period <= 64 read their bases from an LDS table
+
+struct Fbm3dStripArgs {
+    int64_t x0, y0, z0, nx, ny, nz;  // output volume (world), dense [nz][ny][nx]
+    int64_t bx_base, by_base, bz_base;
+    int64_t blocks;
+    void *out;
+    float amp[kMaxOctaves];
+    float inv2p[kMaxOctaves];       // 2^-(shift + 1)
+    int32_t shift[kMaxOctaves];     // period 2^shift; shift[o] = shift[0] - o
+    int32_t nnx[kMaxOctaves], nny[kMaxOctaves], nnz[kMaxOctaves];
+    int32_t noff[kMaxOctaves];      // node block: (i * nny + j) * nnz + k
+    int32_t kxoff[kMaxOctaves], kzyoff[kMaxOctaves];  // column keys, (z, y) row keys (k * nny + j)
+    int32_t toff[kMaxOctaves];      // basis table offset (period <= k3TabMaxP) or -1
+    int32_t nodes_total, keys_total, tab_total;
+    int32_t octaves;
+    uint32_t seed;
+    int32_t blocks_x, blocks_y;
+    int32_t n_coarse;               // octaves 0 .. n_coarse-1 have period >= 8
+    int32_t o4, o2, o1;             // octave of period 4, 2, 1, or -1
+    int32_t lo;                     // min(finest shift, 3): selects the kernel's row loop
+};
+
 // Launch wrappers (defined in the .hip translation units).  They assume validated
 // arguments and return the HIP status of the launch.
 hipError_t launch_fbm2d_general(const Fbm2dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
@@ -105,6 +133,9 @@ hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, bool f16, int
                               hipStream_t s);
 int strip_wgs_per_cu(int smooth, bool f16, int lo, int waves, size_t lds_bytes);  // resident workgroups per CU
 hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
+hipError_t launch_fbm3d_strip(const Fbm3dStripArgs &a, int smooth, bool f16, int grid, int waves, size_t lds_bytes,
+                              hipStream_t s);
+int strip3_wgs_per_cu(int smooth, bool f16, int lo, int waves, size_t lds_bytes);
 
 hipError_t launch_coords(double f0, double lac, int octaves, int64_t x0, int64_t n, int64_t *cells, float *frac,
                          hipStream_t s);

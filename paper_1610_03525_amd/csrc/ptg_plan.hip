@@ -232,9 +232,93 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d launch");
 }
 
+// Plain FP32 dyadic volume through the 3D strip kernel; returns 1 when it does not apply
+// (a ladder starting below period 4, or a node block larger than LDS): the caller falls back.
+static int fbm3d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny,
+                       int64_t nz, void *out, hipStream_t s)
+{
+    constexpr int BX = k3BlockX, BY = k3BlockY, BZ = k3BlockZ;
+    Fbm3dStripArgs a{};
+    a.x0 = x0;
+    a.y0 = y0;
+    a.z0 = z0;
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.out = out;
+    a.bx_base = floor_to(x0, BX);
+    a.by_base = floor_to(y0, BY);
+    a.bz_base = floor_to(z0, BZ);
+    const int64_t bxn = (x0 + nx - a.bx_base + BX - 1) / BX;
+    const int64_t byn = (y0 + ny - a.by_base + BY - 1) / BY;
+    const int64_t bzn = (z0 + nz - a.bz_base + BZ - 1) / BZ;
+    if (bxn > 0x7FFFFFFFLL || byn > 0x7FFFFFFFLL) return 1;
+    a.blocks_x = (int32_t)bxn;
+    a.blocks_y = (int32_t)byn;
+    a.blocks = bxn * byn * bzn;
+    double freq[kMaxOctaves];
+    octave_tables(p, freq, a.amp);
+    a.octaves = p->octaves;
+    a.seed = p->seed;
+    a.o4 = a.o2 = a.o1 = -1;
+    const int smin = k - (p->octaves - 1);
+    if (smin <= 2 && k < 2) return 1;  // the row loop assumes every period from 4 down to the finest
+    a.lo = std::min(smin, 3);
+    int nodes = 0, keys = 0, tab = 0;
+    for (int o = 0; o < p->octaves; ++o) {
+        const int sh = k - o;
+        a.shift[o] = sh;
+        a.inv2p[o] = std::ldexp(1.0f, -(sh + 1));
+        if (sh >= 3) a.n_coarse = o + 1;
+        if (sh == 2) a.o4 = o;
+        if (sh == 1) a.o2 = o;
+        if (sh == 0) a.o1 = o;
+        const int c = std::min(sh, 30);
+        a.nnx[o] = std::max(BX >> c, 1) + 1;
+        a.nny[o] = std::max(BY >> c, 1) + 1;
+        a.nnz[o] = std::max(BZ >> c, 1) + 1;
+        a.noff[o] = nodes;
+        a.kxoff[o] = keys;
+        a.kzyoff[o] = keys + a.nnx[o];
+        nodes += a.nnx[o] * a.nny[o] * a.nnz[o];
+        keys += a.nnx[o] + a.nny[o] * a.nnz[o];
+        if ((1 << c) <= k3TabMaxP) {
+            a.toff[o] = tab;
+            tab += 1 << c;
+        } else {
+            a.toff[o] = -1;
+        }
+    }
+    a.nodes_total = nodes;
+    a.keys_total = keys;
+    a.tab_total = tab;
+    if (keys >= (1 << 14)) return 1;
+    const size_t shared_words = (size_t)4 * tab + (size_t)((keys + nodes + 3) & ~3);
+    const size_t wave_words = (size_t)((3 * nodes + keys + 3) & ~3);
+    int waves = 4;
+    while (waves > 1 && (shared_words + waves * wave_words) * 4 > kDyMaxLds) --waves;
+    const size_t lds = (shared_words + waves * wave_words) * 4;
+    if (lds > kDyMaxLds) return 1;
+    const int64_t per_cu = strip3_wgs_per_cu(p->smoothness, p->out_dtype == PTG_F16, a.lo, waves, lds);
+    const int64_t wgs = (a.blocks + waves - 1) / waves;
+    const int grid = (int)std::min<int64_t>(wgs, (int64_t)device_cus() * per_cu);
+    hipError_t e = launch_fbm3d_strip(a, p->smoothness, p->out_dtype == PTG_F16, grid, waves, lds, s);
+    return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm3d strip launch");
+}
+
 int fbm3d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz,
                 void *out, hipStream_t s)
 {
+    int k = 0;
+    const bool dy = dyadic_shift(p, &k);
+    if (p->path == PTG_PATH_DYADIC && !dy)
+        return fail(PTG_EINVAL, "the dyadic kernel needs base_freq = 2^-k (k <= %d) and lacunarity 2", kDyMaxShift);
+    if (dy && p->path != PTG_PATH_GENERAL) {
+        const int rc = fbm3d_strip(p, k, x0, y0, z0, nx, ny, nz, out, s);
+        if (rc <= 0) return rc;
+        if (p->path == PTG_PATH_DYADIC)
+            return fail(PTG_EINVAL, "the 3D dyadic kernel does not apply (ladder below period 4, or LDS)");
+    }
     Fbm3dArgs a{};
     const size_t lds = general_args_3d(p, x0, y0, z0, nx, ny, nz, out, &a);
     hipError_t e = launch_fbm3d_general(a, p->smoothness, p->out_dtype == PTG_F16, lds, s);

@@ -275,6 +275,48 @@ def test_fbm3d_non_dyadic_and_ragged():
     assert np.max(np.abs(g - ref)) <= 1e-5 * _amp_total(0.7, 4)
 
 
+# Each dyadic ladder below selects a different specialisation of the 3D strip kernel
+# (finest period 1, 2, 4, >= 8; no coarse octave; periods beyond the LDS tables) or its
+# fallback; every field is an unaligned window with ragged edges against 64x8x4 blocks.
+@pytest.mark.parametrize("path", ["auto", "general"])
+@pytest.mark.parametrize("smooth", [1, 2])
+@pytest.mark.parametrize("f0,octs,origin,shape", [
+    (1 / 64, 7, (-5, 2 ** 33 + 1, -(2 ** 20) + 3), (70, 19, 13)),   # periods 64..1
+    (1 / 64, 6, (3, -11, 7), (129, 9, 6)),                          # periods 64..2
+    (1 / 32, 4, (61, 5, -1), (67, 17, 9)),                          # periods 32..4
+    (1 / 256, 6, (-300, 77, 1000), (130, 12, 5)),                   # periods 256..8
+    (1 / 4, 3, (2, 3, 1), (65, 8, 4)),                              # periods 4..1, no coarse octave
+    (2.0 ** -20, 5, (2 ** 40 + 9, -(2 ** 41) - 3, 2 ** 39), (66, 10, 3)),  # periods 2^20..2^16
+    (1 / 2, 2, (0, 0, 0), (40, 6, 5)),                              # periods 2, 1: general kernel
+])
+def test_fbm3d_ladders_against_oracle(path, smooth, f0, octs, origin, shape):
+    kw = dict(smoothness=smooth, octaves=octs, persistence=0.5, lacunarity=2.0, base_freq=f0, seed=21, path=path)
+    g = _gpu_fbm3(*shape, *origin, **kw).cpu().numpy().astype(np.float64)
+    ref = O.fbm_3d(smooth, octs, 0.5, 2.0, f0, 21, *origin, *shape)
+    err = np.max(np.abs(g - ref))
+    assert err <= 1e-5 * _amp_total(0.5, octs), err
+
+
+def test_fbm3d_dyadic_path_rejects_ladders_it_cannot_take():
+    out = torch.empty((4, 4, 4), dtype=torch.float32, device=DEV)
+    with pytest.raises(ptg.PtgError):
+        ptg.fbm_3d(out, base_freq=1 / 2, octaves=2, path="dyadic")
+    with pytest.raises(ptg.PtgError):
+        ptg.fbm_3d(out, base_freq=0.03, octaves=2, path="dyadic")
+
+
+def test_fbm3d_fp16_output_and_crops():
+    kw = dict(smoothness=2, octaves=6, persistence=0.5, lacunarity=2.0, base_freq=1 / 64, seed=4)
+    big = _gpu_fbm3(100, 20, 10, 60, -9, 5, **kw)
+    small = _gpu_fbm3(50, 7, 4, 70, -5, 8, **kw)
+    assert torch.equal(big[3:7, 4:11, 10:60], small)
+    h = torch.empty((10, 20, 100), dtype=torch.float16, device=DEV)
+    ptg.fbm_3d(h, x0=60, y0=-9, z0=5, **kw)
+    _sync()
+    ref = O.fbm_3d(2, 6, 0.5, 2.0, 1 / 64, 4, 60, -9, 5, 100, 20, 10)
+    assert np.max(np.abs(h.cpu().numpy().astype(np.float64) - ref)) <= 2.0 ** -12 + 1e-5 * _amp_total(0.5, 6)
+
+
 def test_empty_fields_are_noops():
     out = torch.empty((0, 16), dtype=torch.float32, device=DEV)
     ptg.fbm_2d(out, base_freq=1 / 8, octaves=2)
@@ -300,6 +342,18 @@ def test_fbm2d_paths_against_oracle(path, smooth, f0, octs, origin, shape):
     ref = O.fbm_2d(smooth, octs, 0.5, 2.0, f0, 5, origin[0], origin[1], nx, ny)
     err = np.max(np.abs(g - ref))
     assert err <= 1e-5 * _amp_total(0.5, octs), err
+
+
+@pytest.mark.parametrize("smooth", [1, 2])
+@pytest.mark.parametrize("f0,octs", [(2.0 ** -10, 8), (2.0 ** -11, 8), (2.0 ** -12, 8), (2.0 ** -13, 8),
+                                     (2.0 ** -14, 6), (2.0 ** -6, 5), (2.0 ** -5, 6)])
+def test_fbm2d_strip_finest_periods(smooth, f0, octs):
+    """Finest period 8, 16, 32, 64, 512; a ladder from period 64 to 4; one from 32 to 1."""
+    x0, y0, nx, ny = -77, 2 ** 35 + 13, 203, 131
+    kw = dict(smoothness=smooth, octaves=octs, persistence=0.5, lacunarity=2.0, base_freq=f0, seed=3)
+    g = _gpu_fbm2(nx, ny, x0, y0, **kw).cpu().numpy().astype(np.float64)
+    ref = O.fbm_2d(smooth, octs, 0.5, 2.0, f0, 3, x0, y0, nx, ny)
+    assert np.max(np.abs(g - ref)) <= 1e-5 * _amp_total(0.5, octs)
 
 
 def test_fbm2d_dyadic_crops_bit_exact():
