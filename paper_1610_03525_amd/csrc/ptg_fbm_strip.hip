@@ -141,51 +141,169 @@ __device__ __forceinline__ void add_mapped(float (&C)[2 * M + 2], const CF &c, f
     }
 }
 
-// An octave of fixed period (<= 64): its node block, row count, and the lane's x-bases
-// (strips are 64-aligned, so for such a period the column fraction depends on the lane only).
+// An octave of fixed period P <= 64: the lane's node column (strips are 64-aligned, so the
+// column index is lane >> s and a column holds 64 / P + 1 node rows) and its x-bases.
 struct Fixed {
-    const float2 *nb;
-    int nny;
+    const float2 *col;
     XB xb;
 };
 
 struct RowCtx {
     Fixed f32, f16, f8, f4, f2, f1;
-    int lane;
     int64_t pitch;
 };
 
-// val += dE S + Q0 b10 + Q1 b11 at one row (E0 is in the constant term), as an FMA chain.
-__device__ __forceinline__ float add_direct(float val, const CF &c, const XB &rb)
+// A node row collapsed along x at the lane's column: value term E and y-slope term Q.  The
+// cell between node rows lo and hi has the column form E0 = lo.E, dE = hi.E - lo.E,
+// Q0 = lo.Q, Q1 = hi.Q, and adjacent cells share their common node row.
+struct NR {
+    float E, Q;
+};
+
+template <int NNY>
+__device__ __forceinline__ NR node_row(const Fixed &f, int j)
 {
-    val = __builtin_fmaf(c.dE, rb.s, val);
-    val = __builtin_fmaf(c.Q0, rb.b10, val);
-    return __builtin_fmaf(c.Q1, rb.b11, val);
+    const float2 a = f.col[j], b = f.col[j + NNY];
+    return NR{a.x * f.xb.b10 + b.x * f.xb.b11, a.y + f.xb.s * (b.y - a.y)};
+}
+
+// Add the cell between node rows lo and hi, as a polynomial in the segment coordinate w
+// (t - 1/2 = SIG w: the cell is centred on the segment), to C.  The constants are the
+// centred power coefficients of the bases listed at add_mapped, times SIG^b.
+template <int M, int SIG>
+__device__ __forceinline__ void add_piece(float (&C)[2 * M + 2], const NR &lo, const NR &hi)
+{
+    constexpr float s1 = (float)SIG, s2 = s1 * s1, s3 = s2 * s1, s4 = s3 * s1, s5 = s4 * s1;
+    const float dE = hi.E - lo.E, Sq = lo.Q + hi.Q, Dq = lo.Q - hi.Q;
+    C[0] += lo.E;
+    C[0] = __builtin_fmaf(dE, 0.5f, C[0]);
+    if (M == 1) {
+        C[0] = __builtin_fmaf(Dq, 0.125f, C[0]);
+        C[1] = __builtin_fmaf(dE, 1.5f * s1, C[1]);
+        C[1] = __builtin_fmaf(Sq, -0.25f * s1, C[1]);
+        C[2] = __builtin_fmaf(Dq, -0.5f * s2, C[2]);
+        C[3] = __builtin_fmaf(Sq, s3, C[3]);
+        C[3] = __builtin_fmaf(dE, -2.0f * s3, C[3]);
+    } else {
+        C[0] = __builtin_fmaf(Dq, 0.15625f, C[0]);
+        C[1] = __builtin_fmaf(dE, 1.875f * s1, C[1]);
+        C[1] = __builtin_fmaf(Sq, -0.4375f * s1, C[1]);
+        C[2] = __builtin_fmaf(Dq, -0.75f * s2, C[2]);
+        C[3] = __builtin_fmaf(Sq, 2.5f * s3, C[3]);
+        C[3] = __builtin_fmaf(dE, -5.0f * s3, C[3]);
+        C[4] = __builtin_fmaf(Dq, 0.5f * s4, C[4]);
+        C[5] = __builtin_fmaf(dE, 6.0f * s5, C[5]);
+        C[5] = __builtin_fmaf(Sq, -3.0f * s5, C[5]);
+    }
+}
+
+// val += dE S + Q0 b10 + Q1 b11 at one row (E0 is in the constant term), as an FMA chain.
+__device__ __forceinline__ float add_direct(float val, const NR &lo, const NR &hi, const XB &rb)
+{
+    val = __builtin_fmaf(hi.E - lo.E, rb.s, val);
+    val = __builtin_fmaf(lo.Q, rb.b10, val);
+    return __builtin_fmaf(hi.Q, rb.b11, val);
+}
+
+// Node rows [r0 / P, (r0 + R) / P] of a direct octave over a segment; the first one is
+// carried from the previous segment and the last one is carried to the next.
+template <int P, int R>
+struct SegRows {
+    NR n[R / P + 1];
+    __device__ __forceinline__ void load(const Fixed &f, int r0, NR &carry)
+    {
+        n[0] = carry;
+#pragma unroll
+        for (int j = 1; j <= R / P; ++j) n[j] = node_row<64 / P + 1>(f, r0 / P + j);
+        carry = n[R / P];
+    }
+};
+
+// The R rows [r0, r0 + R) of a strip, given the polynomial Cs of everything coarser than the
+// direct octaves, centred on the segment (row k at w = (2 k - R + 1) / 128).  Rows are taken
+// in pairs symmetric about the centre, w and -w, from the even and odd parts of Cs; the
+// direct octaves' E0 terms go into each row's constant term, the rest is 3 FMA per octave.
+template <int M, typename OutT, int R, bool D8, bool D4, bool D2, bool D1, bool FULL>
+__device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[2 * M + 2], int r0, NR (&carry)[4],
+                                             OutT *rp, int lane, int rlo, int rhi, bool lane_ok)
+{
+    SegRows<8, R> s8;
+    SegRows<4, R> s4;
+    SegRows<2, R> s2;
+    SegRows<1, R> s1;
+    if (D8) s8.load(x.f8, r0, carry[0]);
+    if (D4) s4.load(x.f4, r0, carry[1]);
+    if (D2) s2.load(x.f2, r0, carry[2]);
+    if (D1) s1.load(x.f1, r0, carry[3]);
+    // row pointers walk outwards from the centre pair (uniform, one add each per pair)
+    OutT *pa = rp + (int64_t)(r0 + R / 2 - 1) * x.pitch, *pb = pa + x.pitch;
+#pragma unroll
+    for (int p = 0; p < R / 2; ++p) {
+        const int rb = R / 2 + p;
+        const float w = (float)(2 * rb - R + 1) * (1.0f / 128.0f);
+        const float w2 = w * w;
+        float odd, even2 = 0.0f;
+        if (M == 1) {
+            odd = __builtin_fmaf(Cs[3], w2, Cs[1]);
+        } else {
+            odd = __builtin_fmaf(__builtin_fmaf(Cs[5], w2, Cs[3]), w2, Cs[1]);
+            even2 = __builtin_fmaf(Cs[4], w2, Cs[2]);
+        }
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int k = side ? rb : R / 2 - 1 - p;  // row in the segment
+            const int row = r0 + k;                   // row in the strip
+            float c0 = Cs[0];
+            if (D8) c0 += s8.n[k / 8].E;
+            if (D4) c0 += s4.n[k / 4].E;
+            if (D2) c0 += s2.n[k / 2].E;
+            if (D1) c0 += s1.n[k].E;
+            float val = __builtin_fmaf(M == 1 ? Cs[2] : even2, w2, c0);
+            val = __builtin_fmaf(side ? w : -w, odd, val);
+            if (D8) val = add_direct(val, s8.n[k / 8], s8.n[k / 8 + 1], row_bases<M>(row & 7, 8));
+            if (D4) val = add_direct(val, s4.n[k / 4], s4.n[k / 4 + 1], row_bases<M>(row & 3, 4));
+            if (D2) val = add_direct(val, s2.n[k / 2], s2.n[k / 2 + 1], row_bases<M>(row & 1, 2));
+            if (D1) val = add_direct(val, s1.n[k], s1.n[k + 1], row_bases<M>(0, 1));
+            OutT *const rrow = side ? pb : pa;
+            if (FULL || (row >= rlo && row < rhi && lane_ok)) rrow[lane] = st_out<OutT>(val);
+        }
+        pa -= x.pitch;
+        pb += x.pitch;
+    }
 }
 
 // The rows of a strip.  The fused polynomial C (in the strip coordinate v) is re-centred
 // on each half strip, where the period-32 piece is added (t - 1/2 = 2 w), and again on each
-// quarter, where the period-16 piece is added (t - 1/2 = 4 w); every row then evaluates by
-// Horner in its quarter's coordinate w = (2 j - 15) / 128, j = row - 16 q, so no piece is
-// evaluated away from its own cell.  The direct octaves follow; FULL = every sample of the
-// strip is stored.
+// quarter, where the period-16 piece is added (t - 1/2 = 4 w).  For cubic cells the same is
+// done once more per period-8 cell (t - 1/2 = 8 w), where re-centring (6 FMA) and the piece
+// cost less than evaluating the octave on its own at every row; for quintic cells (15 FMA
+// per re-centring) period 8 stays a direct octave.  No piece is evaluated away from its own
+// cell.  FULL = every sample of the strip is stored.
 template <int M, typename OutT, int LO, bool FULL>
-__device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 * M + 2], OutT *rp, int rlo, int rhi,
-                                           bool lane_ok)
+__device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 * M + 2], OutT *rp, int lane, int rlo,
+                                           int rhi, bool lane_ok)
 {
     constexpr int D1 = 2 * M + 2;
     constexpr bool H32 = LO <= 5, H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
-    const int lane = x.lane;
+    constexpr bool PIECE8 = H8 && M == 1;
+    NR carry[4];  // bottom node rows of the next segment: periods 8, 4, 2, 1
+    if (H8) carry[0] = node_row<9>(x.f8, 0);
+    if (H4) carry[1] = node_row<17>(x.f4, 0);
+    if (H2) carry[2] = node_row<33>(x.f2, 0);
+    if (H1) carry[3] = node_row<65>(x.f1, 0);
+    NR n32[3], n16lo;
+    if (H32) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) n32[j] = node_row<3>(x.f32, j);
+    }
+    if (H16) n16lo = node_row<5>(x.f16, 0);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         float Ch[D1];
 #pragma unroll
         for (int b = 0; b < D1; ++b) Ch[b] = C[b];
         taylor_shift<M>(Ch, (float)(2 * h - 1) * 0.25f);  // half centre v = -1/4, +1/4
-        if (H32) {  // period 32: one cell row per half strip
-            const CF c = column_form(x.f32.nb + (lane >> 5) * x.f32.nny + h, x.f32.nny, x.f32.xb);
-            add_mapped<M, false>(Ch, c, 0.0f, 2.0f);
-        }
+        if (H32) add_piece<M, 2>(Ch, n32[h], n32[h + 1]);
 #pragma unroll
         for (int qh = 0; qh < 2; ++qh) {
             const int q = 2 * h + qh;
@@ -193,50 +311,26 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
 #pragma unroll
             for (int b = 0; b < D1; ++b) Cq[b] = Ch[b];
             taylor_shift<M>(Cq, (float)(2 * qh - 1) * 0.125f);  // quarter centre, from the half's
-            if (H16) {  // period 16: one cell row per quarter
-                const CF c = column_form(x.f16.nb + (lane >> 4) * x.f16.nny + q, x.f16.nny, x.f16.xb);
-                add_mapped<M, false>(Cq, c, 0.0f, 4.0f);
+            if (H16) {
+                const NR hi = node_row<5>(x.f16, q + 1);
+                add_piece<M, 4>(Cq, n16lo, hi);
+                n16lo = hi;
             }
-            CF c8{}, c4{}, c2{}, c1{};
-            float c0 = Cq[0];
+            if (PIECE8) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int row = 16 * q + j;
-                bool fresh = false;
-                if (H8 && (row & 7) == 0) {
-                    c8 = column_form(x.f8.nb + (lane >> 3) * x.f8.nny + (row >> 3), x.f8.nny, x.f8.xb);
-                    fresh = true;
-                }
-                if (H4 && (row & 3) == 0) {
-                    c4 = column_form(x.f4.nb + (lane >> 2) * x.f4.nny + (row >> 2), x.f4.nny, x.f4.xb);
-                    fresh = true;
-                }
-                if (H2 && (row & 1) == 0) {
-                    c2 = column_form(x.f2.nb + (lane >> 1) * x.f2.nny + (row >> 1), x.f2.nny, x.f2.xb);
-                    fresh = true;
-                }
-                if (H1) {
-                    c1 = column_form(x.f1.nb + lane * x.f1.nny + row, x.f1.nny, x.f1.xb);
-                    fresh = true;
-                }
-                if (fresh) {  // constant term: the fused polynomial's plus the direct octaves' E0
-                    c0 = Cq[0];
-                    if (H8) c0 += c8.E0;
-                    if (H4) c0 += c4.E0;
-                    if (H2) c0 += c2.E0;
-                    if (H1) c0 += c1.E0;
-                }
-                const float w = (float)(2 * j - 15) * (1.0f / 128.0f);
-                float val = Cq[D1 - 1];
+                for (int e = 0; e < 2; ++e) {
+                    float Ce[D1];
 #pragma unroll
-                for (int b = D1 - 2; b >= 1; --b) val = __builtin_fmaf(val, w, Cq[b]);
-                val = __builtin_fmaf(val, w, c0);
-                if (H8) val = add_direct(val, c8, row_bases<M>(row & 7, 8));
-                if (H4) val = add_direct(val, c4, row_bases<M>(row & 3, 4));
-                if (H2) val = add_direct(val, c2, row_bases<M>(row & 1, 2));
-                if (H1) val = add_direct(val, c1, row_bases<M>(0, 1));
-                if (FULL || (row >= rlo && row < rhi && lane_ok)) rp[lane] = st_out<OutT>(val);
-                rp += x.pitch;
+                    for (int b = 0; b < D1; ++b) Ce[b] = Cq[b];
+                    taylor_shift<M>(Ce, (float)(2 * e - 1) * 0.0625f);  // period-8 cell centre
+                    const NR lo = carry[0], hi = node_row<9>(x.f8, 2 * q + e + 1);
+                    add_piece<M, 8>(Ce, lo, hi);
+                    carry[0] = hi;
+                    segment_rows<M, OutT, 8, false, H4, H2, H1, FULL>(x, Ce, 16 * q + 8 * e, carry, rp, lane, rlo, rhi,
+                                                                       lane_ok);
+                }
+            } else {
+                segment_rows<M, OutT, 16, H8, H4, H2, H1, FULL>(x, Cq, 16 * q, carry, rp, lane, rlo, rhi, lane_ok);
             }
         }
     }
@@ -285,18 +379,17 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
     __syncthreads();
 
     auto fixed = [&](int o) -> Fixed {
-        Fixed f{nodes, 2, XB{0.0f, 0.0f, 0.0f}};
+        Fixed f{nodes, XB{0.0f, 0.0f, 0.0f}};
         if (o >= 0) {
             const int s = p_shift[o];
-            f.nb = nodes + p_noff[o];
-            f.nny = a.nny[o];
+            f.col = nodes + p_noff[o] + (lane >> s) * ((kStripH >> s) + 1);
             f.xb = xbases<M>((float)(2 * (lane & ((1 << s) - 1)) + 1) * p_inv2p[o]);
         }
         return f;
     };
     const Fixed f64 = fixed(a.o64);
     const RowCtx rc0{fixed(H32 ? a.o32 : -1), fixed(H16 ? a.o16 : -1), fixed(H8 ? a.o8 : -1), fixed(H4 ? a.o4 : -1),
-                     fixed(H2 ? a.o2 : -1),   fixed(H1 ? a.o1 : -1),   lane,                   a.pitch};
+                     fixed(H2 ? a.o2 : -1),   fixed(H1 ? a.o1 : -1),   a.pitch};
     const bool has64 = a.o64 >= 0;
     const int n_generic = a.n_generic;
 
@@ -343,10 +436,7 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
             const float tau = (float)(((uint32_t)Y0 & mask) + (uint32_t)(kStripH / 2)) * invp - 0.5f;
             add_mapped<M>(C, c, tau, (float)kStripH * invp);
         }
-        if (has64) {  // t - 1/2 = v: no shift
-            const CF c = column_form(f64.nb, 2, f64.xb);
-            add_mapped<M, false>(C, c, 0.0f, 1.0f);
-        }
+        if (has64) add_piece<M, 1>(C, node_row<2>(f64, 0), node_row<2>(f64, 1));  // t - 1/2 = v
 
         // ---- rows: one store per row of the wave; interior strips take the unmasked path --
         const int rlo = (int)max<int64_t>(0, min<int64_t>(kStripH, a.y0 - Y0));
@@ -355,9 +445,9 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
         const int chi = (int)max<int64_t>(0, min<int64_t>(kStripW, xe - X0));
         OutT *row0 = out + (Y0 - a.y0) * a.pitch + (X0 - a.x0);
         if (rlo == 0 && rhi == kStripH && clo == 0 && chi == kStripW)
-            strip_rows<M, OutT, LO, true>(rc0, C, row0, 0, kStripH, false);
+            strip_rows<M, OutT, LO, true>(rc0, C, row0, lane, 0, kStripH, false);
         else
-            strip_rows<M, OutT, LO, false>(rc0, C, row0, rlo, rhi, lane >= clo && lane < chi);
+            strip_rows<M, OutT, LO, false>(rc0, C, row0, lane, rlo, rhi, lane >= clo && lane < chi);
         __builtin_amdgcn_wave_barrier();  // the next strip rewrites this wave's keys and nodes
     }
 }
