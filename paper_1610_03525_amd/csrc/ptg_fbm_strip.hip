@@ -60,6 +60,19 @@ __device__ __forceinline__ XB xbases(float t)
     return r;
 }
 
+// A lane's x-weights of one octave with the octave amplitude folded in: the value term of a
+// node row is gx0 e0 + gx1 e1 (e = amp b1), its y-slope term gy0 q0 + gy1 q1 (q = amp b0).
+struct XA {
+    float q0, q1, e0, e1;
+};
+
+template <int M>
+__device__ __forceinline__ XA xweights(float t, float amp)
+{
+    const XB b = xbases<M>(t);
+    return XA{amp * (1.0f - b.s), amp * b.s, amp * b.b10, amp * b.b11};
+}
+
 // Row bases at the fraction (j + 1/2) / P: constant once the row loop is unrolled.
 template <int M>
 __host__ __device__ constexpr XB row_bases(int j, int P)
@@ -78,15 +91,15 @@ struct CF {  // column form of one cell at one column
 };
 
 // nb -> node (cx, cy) of the cell; (cx, cy + 1) follows, column cx + 1 is nny further.
-__device__ __forceinline__ CF column_form(const float2 *nb, int nny, const XB &xb)
+__device__ __forceinline__ CF column_form(const float2 *nb, int nny, const XA &xa)
 {
     const float2 n00 = nb[0], n01 = nb[1], n10 = nb[nny], n11 = nb[nny + 1];
     CF c;
-    c.E0 = n00.x * xb.b10 + n10.x * xb.b11;
-    const float E1 = n01.x * xb.b10 + n11.x * xb.b11;
+    c.E0 = n00.x * xa.e0 + n10.x * xa.e1;
+    const float E1 = n01.x * xa.e0 + n11.x * xa.e1;
     c.dE = E1 - c.E0;
-    c.Q0 = n00.y + xb.s * (n10.y - n00.y);
-    c.Q1 = n01.y + xb.s * (n11.y - n01.y);
+    c.Q0 = n00.y * xa.q0 + n10.y * xa.q1;
+    c.Q1 = n01.y * xa.q0 + n11.y * xa.q1;
     return c;
 }
 
@@ -145,7 +158,7 @@ __device__ __forceinline__ void add_mapped(float (&C)[2 * M + 2], const CF &c, f
 // column index is lane >> s and a column holds 64 / P + 1 node rows) and its x-bases.
 struct Fixed {
     const float2 *col;
-    XB xb;
+    XA xa;
 };
 
 struct RowCtx {
@@ -164,7 +177,7 @@ template <int NNY>
 __device__ __forceinline__ NR node_row(const Fixed &f, int j)
 {
     const float2 a = f.col[j], b = f.col[j + NNY];
-    return NR{a.x * f.xb.b10 + b.x * f.xb.b11, a.y + f.xb.s * (b.y - a.y)};
+    return NR{a.x * f.xa.e0 + b.x * f.xa.e1, a.y * f.xa.q0 + b.y * f.xa.q1};
 }
 
 // Add the cell between node rows lo and hi, as a polynomial in the segment coordinate w
@@ -269,6 +282,10 @@ __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[
         }
         pa -= x.pitch;
         pb += x.pitch;
+        // keep each pair's stores next to its arithmetic: without this the scheduler hoists
+        // most of a strip's row arithmetic ahead of the first store and then issues the
+        // stores in one burst, with the values held in registers
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -362,11 +379,15 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
     // ---- once per workgroup: work lists and per-octave constants ----------------------
     for (int o = 0; o < N; ++o) {
         const int nnx = a.nnx[o], nny = a.nny[o], kx = a.kxoff[o], ky = a.kyoff[o], no = a.noff[o];
-        for (int i = tid; i < nnx + nny; i += nthreads)
-            wl_key[kx + i] = ((uint32_t)o << 24) | (i < nnx ? (uint32_t)i : ((1u << 23) | (uint32_t)(i - nnx)));
-        for (int q = tid; q < nnx * nny; q += nthreads) {
-            const int i = q / nny, j = q - i * nny;  // column-major
-            wl_node[no + q] = ((uint32_t)o << 28) | ((uint32_t)(ky + j) << 14) | (uint32_t)(kx + i);
+        for (int i = tid; i < nnx + nny; i += nthreads) {
+            if (i < nnx)
+                wl_key[kx + i] = ((uint32_t)o << 24) | (uint32_t)i;
+            else
+                wl_key[ky + i - nnx] = ((uint32_t)o << 24) | (uint32_t)(i - nnx);
+        }
+        for (int q = tid; q < nnx * nny; q += nthreads) {  // byte offsets of the node's two keys
+            const int i = q / nny, j = q - i * nny;          // column-major
+            wl_node[no + q] = ((uint32_t)(ky + j) << 18) | ((uint32_t)(kx + i) << 2);
         }
     }
     if (tid < N) {
@@ -379,11 +400,11 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
     __syncthreads();
 
     auto fixed = [&](int o) -> Fixed {
-        Fixed f{nodes, XB{0.0f, 0.0f, 0.0f}};
+        Fixed f{nodes, XA{0.0f, 0.0f, 0.0f, 0.0f}};
         if (o >= 0) {
             const int s = p_shift[o];
             f.col = nodes + p_noff[o] + (lane >> s) * ((kStripH >> s) + 1);
-            f.xb = xbases<M>((float)(2 * (lane & ((1 << s) - 1)) + 1) * p_inv2p[o]);
+            f.xa = xweights<M>((float)(2 * (lane & ((1 << s) - 1)) + 1) * p_inv2p[o], p_amp[o]);
         }
         return f;
     };
@@ -395,28 +416,38 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
 
     const int64_t nwaves = (int64_t)gridDim.x * wpg;
     const int64_t xe = a.x0 + a.nx, ye = a.y0 + a.ny;
+    const int keys_col = a.keys_col;
     OutT *out = reinterpret_cast<OutT *>(a.out);
+    // the column keys stay valid while the wave's strips share a strip column (the stride
+    // over strips is often a multiple of the strips per row)
+    int64_t keyed_bsx = -1;
     for (int64_t st = (int64_t)blockIdx.x * wpg + wave; st < a.strips; st += nwaves) {
         const int64_t bsy = st / a.strips_x, bsx = st - bsy * a.strips_x;
         const int64_t X0 = a.sx_base + bsx * kStripW, Y0 = a.sy_base + bsy * kStripH;
 
-        // ---- hashing: column / row keys, then amplitude-scaled node gradients ------------
-        for (int q = lane; q < keys_total; q += 64) {
+        // ---- hashing: column keys (x salt), row keys (octave prefix), then node gradients
+        // (unit vectors: the amplitude is in the lanes' x-weights) -------------------------
+        if (bsx != keyed_bsx) {
+            for (int q = lane; q < keys_col; q += 64) {
+                const uint32_t it = wl_key[q];
+                keys[q] = key_xline((X0 >> p_shift[it >> 24]) + (int64_t)(it & 0xFFFFFF));
+            }
+            keyed_bsx = bsx;
+        }
+        for (int q = keys_col + lane; q < keys_total; q += 64) {
             const uint32_t it = wl_key[q];
             const int o = it >> 24;
-            const bool row = (it & (1u << 23)) != 0;
-            const int64_t base = row ? Y0 : X0;
-            const uint32_t k0 = row ? pre_key[o] : 0x27D4EB2Fu;  // row keys: octave prefix; column keys: x salt
-            keys[q] = absorb_index(k0, (base >> p_shift[o]) + (int64_t)(it & 0x7FFFFF));
+            keys[q] = absorb_index(pre_key[o], (Y0 >> p_shift[o]) + (int64_t)(it & 0xFFFFFF));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const char *key_bytes = reinterpret_cast<const char *>(keys);
         for (int q = lane; q < nodes_total; q += 64) {
             const uint32_t it = wl_node[q];
-            const float amp = p_amp[it >> 28];
-            const float2 g = grad2(key_combine(keys[(it >> 14) & 0x3FFF], keys[it & 0x3FFF]));
-            nodes[q] = make_float2(g.x * amp, g.y * amp);
+            const uint32_t krow = *reinterpret_cast<const uint32_t *>(key_bytes + (it >> 16));
+            const uint32_t kcol = *reinterpret_cast<const uint32_t *>(key_bytes + (it & 0xFFFFu));
+            nodes[q] = grad2(key_combine(krow, kcol));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -430,8 +461,8 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
             const int s = p_shift[o];
             const uint32_t mask = (1u << s) - 1u;
             const float inv2p = p_inv2p[o];
-            const XB xb = xbases<M>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p);
-            const CF c = column_form(nodes + p_noff[o], 2, xb);
+            const XA xa = xweights<M>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p, p_amp[o]);
+            const CF c = column_form(nodes + p_noff[o], 2, xa);
             const float invp = 2.0f * inv2p;
             const float tau = (float)(((uint32_t)Y0 & mask) + (uint32_t)(kStripH / 2)) * invp - 0.5f;
             add_mapped<M>(C, c, tau, (float)kStripH * invp);

@@ -87,8 +87,8 @@ struct Fbm2dStripArgs {
     int32_t shift[kMaxOctaves];                     // period 2^shift; shift[o] = shift[0] - o
     int32_t nnx[kMaxOctaves], nny[kMaxOctaves];     // node columns / rows of a strip's footprint
     int32_t noff[kMaxOctaves];                      // node block (column-major, nny rows)
-    int32_t kxoff[kMaxOctaves], kyoff[kMaxOctaves]; // column / row key offsets
-    int32_t nodes_total, keys_total;
+    int32_t kxoff[kMaxOctaves], kyoff[kMaxOctaves]; // column / row key offsets (all column keys first)
+    int32_t nodes_total, keys_total, keys_col;      // keys [0, keys_col) are column keys
     int32_t octaves;
     uint32_t seed;
     int32_t strips_x;

@@ -129,7 +129,11 @@ static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
     // the row loop assumes every period from 32 down to the finest is present
     if (smin <= 5 && k < 5) return 1;
     a.lo = std::min(smin, 6);
-    int nodes = 0, keys = 0;
+    int nodes = 0, keys = 0, kcol = 0;
+    for (int o = 0; o < p->octaves; ++o)  // column keys of every octave first, then row keys
+        kcol += std::max(SW >> std::min(k - o, 30), 1) + 1;
+    a.keys_col = kcol;
+    kcol = 0;
     for (int o = 0; o < p->octaves; ++o) {
         const int sh = k - o;
         a.shift[o] = sh;
@@ -145,9 +149,10 @@ static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
         a.nnx[o] = std::max(SW >> std::min(sh, 30), 1) + 1;
         a.nny[o] = std::max(SH >> std::min(sh, 30), 1) + 1;
         a.noff[o] = nodes;
-        a.kxoff[o] = keys;
-        a.kyoff[o] = keys + a.nnx[o];
+        a.kxoff[o] = kcol;
+        a.kyoff[o] = a.keys_col + (keys - kcol);
         nodes += a.nnx[o] * a.nny[o];
+        kcol += a.nnx[o];
         keys += a.nnx[o] + a.nny[o];
     }
     a.nodes_total = nodes;
