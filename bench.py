@@ -89,21 +89,17 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # timed region: exactly `steps` steps, bracketed by device synchronisation
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    # kernel duration with HIP events on the launch stream: one pair around `steps`
-    # back-to-back launches (the GPU never waits for the host), averaged per launch
+    # timed region: exactly `steps` steps, bracketed by device synchronisation; one pair of
+    # HIP events on the launch stream brackets the same back-to-back launches (the GPU
+    # never waits for the host), giving the kernel's average duration in the timed region
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
         step()
     e1.record(stream)
     torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     k_avg_ms = e0.elapsed_time(e1) / args.steps
     # per-launch spread (each launch bracketed by its own events; includes launch gaps)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
