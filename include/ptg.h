@@ -169,11 +169,68 @@ PTG_API int ptg_cells_2d(int32_t smoothness, const float *grad_dev, int64_t nnx,
 PTG_API int ptg_cells_3d(int32_t smoothness, const float *grad_dev, int64_t nnx, int64_t nny,
                  int64_t nnz, float amplitude, float *coeff_dev, void *stream);
 
+/* ---- a6: tile-shape autotuner ------------------------------------------------
+ * Each dense-field call runs one kernel class; some classes have a free launch shape that
+ * changes neither the arithmetic nor the result (every sample is computed by the same
+ * operations whatever the shape):
+ *   PTG_TUNE_GENERAL_2D  general 2D kernel: tile height in rows, 16, 32 or 64 (tiles are
+ *                        64 wide); a shorter tile hashes more duplicated footprint nodes
+ *                        but gives small fields more workgroups;
+ *   PTG_TUNE_STRIP_2D    dyadic 2D kernel (64 x 64 strips, one per wave): waves per
+ *                        workgroup, 1, 2 or 4;
+ *   PTG_TUNE_STRIP_3D    dyadic 3D kernel (64 x 8 x 4 blocks, one per wave): waves per
+ *                        workgroup, 1, 2 or 4;
+ *   PTG_TUNE_GENERAL_3D, PTG_TUNE_DYADIC_2D (precision forms, dyadic 2D tiles): fixed.
+ * A class is keyed by (kernel, smoothness, output type, ceil(log2(samples)), ladder class:
+ * log2 of the finest period for the dyadic kernels, of 1 / the largest frequency, capped
+ * at 8, for the general ones).  The library keeps one table per process (thread-safe);
+ * untuned classes use the defaults (64 rows, 4 waves). */
+#define PTG_TUNE_GENERAL_2D 1
+#define PTG_TUNE_STRIP_2D 2
+#define PTG_TUNE_GENERAL_3D 3
+#define PTG_TUNE_STRIP_3D 4
+#define PTG_TUNE_DYADIC_2D 5
+#define PTG_TUNE_MAX_CANDIDATES 4
+
+typedef struct ptg_tune_result {
+    int32_t kernel;          /* PTG_TUNE_* class the call runs                          */
+    int32_t value;           /* shape now recorded for it (0: nothing to tune)          */
+    int32_t n;               /* candidates timed (1 when the class has no free shape)   */
+    int32_t default_value;   /* the untuned shape                                       */
+    int32_t candidates[PTG_TUNE_MAX_CANDIDATES];
+    double us[PTG_TUNE_MAX_CANDIDATES]; /* mean launch time of each candidate, us       */
+} ptg_tune_result;
+
+/* Time every candidate shape of the class that ptg_fbm_2d(p, x0, y0, nx, ny, out_dev,
+ * row_pitch, stream) runs (one warm-up, then `reps` back-to-back launches bracketed by HIP
+ * events, per candidate; reps <= 0 means 5), record the fastest for that class and fill
+ * *res.  out_dev receives the field (every candidate writes the same values).  Synchronous:
+ * returns after the timings.  Errors: as ptg_fbm_2d, PTG_EINVAL for a NULL res. */
+PTG_API int ptg_tune_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out_dev,
+                        int64_t row_pitch, void *stream, int32_t reps, ptg_tune_result *res);
+PTG_API int ptg_tune_3d(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny,
+                        int64_t nz, void *out_dev, void *stream, int32_t reps, ptg_tune_result *res);
+
+/* The class and shape a call with these parameters and extents would use now, without
+ * launching anything (host only; origins do not affect the choice).  *kernel and *value
+ * as in ptg_tune_result.  Errors: PTG_EINVAL (parameters, NULL outputs). */
+PTG_API int ptg_tune_query_2d(const ptg_params *p, int64_t nx, int64_t ny, int32_t *kernel, int32_t *value);
+PTG_API int ptg_tune_query_3d(const ptg_params *p, int64_t nx, int64_t ny, int64_t nz, int32_t *kernel,
+                              int32_t *value);
+
+/* Record a shape for the class of such a call (e.g. one tuned in an earlier process).
+ * Errors: PTG_EINVAL (parameters, or value not a candidate of the class). */
+PTG_API int ptg_tune_set_2d(const ptg_params *p, int64_t nx, int64_t ny, int32_t value);
+PTG_API int ptg_tune_set_3d(const ptg_params *p, int64_t nx, int64_t ny, int64_t nz, int32_t value);
+
+/* Forget every recorded shape. */
+PTG_API void ptg_tune_reset(void);
+
 /* ---- a6: serving (continuous batching of terrain tiles) ----------------------- */
 /* A server owns an output arena of hbm_budget_bytes and one persistent kernel.  Requests
  * (terrain tiles of any size, 2D or 3D, C1 or C2, any octave parameters, FP32 output) are
  * queued by ptg_tiles_submit, admitted while arena bytes and request slots are free, cut
- * into work items of 64 x 64 (2D) or 64 x 8 x 8 (3D) sample tiles and published into a
+ * into work items of 64 x tile_h (2D) or 64 x 8 x 8 (3D) sample tiles and published into a
  * ring that the persistent kernel's workgroups drain while earlier requests are still
  * running.  Each tile is computed by the same device code as ptg_fbm_2d / ptg_fbm_3d with
  * p->path = PTG_PATH_GENERAL, so a served tile equals that call bit for bit. */
@@ -194,6 +251,11 @@ typedef struct ptg_server_cfg {
     int64_t fake_tile_ns;     /* PTG_EXEC_HOST only: simulated time per tile                */
     int32_t tiles_per_item;   /* sample tiles per work item, 1..16; 0 = from each request's */
                               /* size (enough items for every workgroup, at most 16 tiles)  */
+    int32_t autotune;         /* 1: at creation (PTG_EXEC_GPU) time the 2D tile heights on  */
+                              /* a 512 x 512, 8-octave field per cell order (ptg_tune_2d,   */
+                              /* general kernel; needs a budget >= 1 MiB) and use the best  */
+    int32_t tile_h;           /* 2D tile height in rows: 16, 32 or 64; 0 = the tuned one    */
+                              /* (autotune), else 64.  3D tiles are 64 x 8 x 8              */
     int32_t reserved;         /* 0                                                          */
 } ptg_server_cfg;
 
@@ -245,6 +307,7 @@ typedef struct ptg_server_stats {
     int64_t pending, in_flight;
     int64_t bytes_in_use, bytes_peak, budget;
     int64_t kernel_launches;  /* persistent-kernel launches (it exits after idling)         */
+    int32_t tile_h[2];        /* 2D tile height used for C1 / C2 requests                    */
 } ptg_server_stats;
 
 PTG_API int ptg_server_stats_get(ptg_server *s, ptg_server_stats *st);

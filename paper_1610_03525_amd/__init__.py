@@ -65,6 +65,8 @@ class ServerCfg(ctypes.Structure):
         ("executor", ctypes.c_int32),
         ("fake_tile_ns", ctypes.c_int64),
         ("tiles_per_item", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
+        ("tile_h", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]
 
@@ -94,7 +96,22 @@ class TileResult(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "submitted", "admitted", "completed", "released", "tiles_done", "pending", "in_flight",
-        "bytes_in_use", "bytes_peak", "budget", "kernel_launches")]
+        "bytes_in_use", "bytes_peak", "budget", "kernel_launches")] + [("tile_h", ctypes.c_int32 * 2)]
+
+
+PTG_TUNE_GENERAL_2D, PTG_TUNE_STRIP_2D, PTG_TUNE_GENERAL_3D, PTG_TUNE_STRIP_3D, PTG_TUNE_DYADIC_2D = 1, 2, 3, 4, 5
+TUNE_NAMES = {1: "general_2d", 2: "strip_2d", 3: "general_3d", 4: "strip_3d", 5: "dyadic_2d"}
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [
+        ("kernel", ctypes.c_int32),
+        ("value", ctypes.c_int32),
+        ("n", ctypes.c_int32),
+        ("default_value", ctypes.c_int32),
+        ("candidates", ctypes.c_int32 * 4),
+        ("us", ctypes.c_double * 4),
+    ]
 
 
 PTG_EXEC_GPU = 0
@@ -130,9 +147,20 @@ def lib():
     L.ptg_tile_release.argtypes = [_vp, ctypes.c_uint64]
     L.ptg_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
     L.ptg_server_destroy.argtypes = [_vp]
+    _TR = ctypes.POINTER(TuneResult)
+    _IP = ctypes.POINTER(_i32)
+    L.ptg_tune_2d.argtypes = [_PP, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _i32, _TR]
+    L.ptg_tune_3d.argtypes = [_PP, _i64, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _i32, _TR]
+    L.ptg_tune_query_2d.argtypes = [_PP, _i64, _i64, _IP, _IP]
+    L.ptg_tune_query_3d.argtypes = [_PP, _i64, _i64, _i64, _IP, _IP]
+    L.ptg_tune_set_2d.argtypes = [_PP, _i64, _i64, _i32]
+    L.ptg_tune_set_3d.argtypes = [_PP, _i64, _i64, _i64, _i32]
+    L.ptg_tune_reset.argtypes = []
+    L.ptg_tune_reset.restype = None
     for name in ("ptg_fbm_2d", "ptg_fbm_3d", "ptg_coords", "ptg_lattice_2d", "ptg_lattice_3d",
                  "ptg_cells_2d", "ptg_cells_3d", "ptg_server_create", "ptg_tiles_submit", "ptg_tiles_wait",
-                 "ptg_tile_release", "ptg_server_stats_get", "ptg_server_destroy"):
+                 "ptg_tile_release", "ptg_server_stats_get", "ptg_server_destroy", "ptg_tune_2d", "ptg_tune_3d",
+                 "ptg_tune_query_2d", "ptg_tune_query_3d", "ptg_tune_set_2d", "ptg_tune_set_3d"):
         getattr(L, name).restype = _i32
     _LIB = L
     return L
@@ -278,6 +306,62 @@ def version() -> str:
 
 # ---- serving ------------------------------------------------------------------------
 
+# ---- a6: tile-shape autotuner -----------------------------------------------------
+
+def _tune_dict(r: TuneResult) -> dict:
+    return {"kernel": TUNE_NAMES.get(r.kernel, r.kernel), "value": r.value, "default": r.default_value,
+            "candidates": {int(r.candidates[i]): float(r.us[i]) for i in range(r.n)}}
+
+
+def tune_2d(out, *, x0=0, y0=0, stream=None, reps=5, **kw) -> dict:
+    """Time every candidate shape of the kernel class that fbm_2d(out, ...) runs, record the
+    fastest (used by later calls of that class) and return the timings (us per launch).
+    out receives the field."""
+    if out.dim() != 2 or out.stride(1) != 1:
+        raise ValueError("out must be a 2D tensor with unit column stride")
+    p = params(dim=2, out_dtype=_out_dtype(out), **kw)
+    ny, nx = out.shape
+    r = TuneResult()
+    _check(lib().ptg_tune_2d(p, x0, y0, nx, ny, _dev_ptr(out), out.stride(0), _stream(stream), reps,
+                             ctypes.byref(r)))
+    return _tune_dict(r)
+
+
+def tune_3d(out, *, x0=0, y0=0, z0=0, stream=None, reps=5, **kw) -> dict:
+    if out.dim() != 3 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous 3D tensor")
+    p = params(dim=3, out_dtype=_out_dtype(out), **kw)
+    nz, ny, nx = out.shape
+    r = TuneResult()
+    _check(lib().ptg_tune_3d(p, x0, y0, z0, nx, ny, nz, _dev_ptr(out), _stream(stream), reps, ctypes.byref(r)))
+    return _tune_dict(r)
+
+
+def tune_query(shape, out_dtype=PTG_F32, **kw):
+    """(kernel class name, shape) a call over `shape` ((ny, nx) or (nz, ny, nx)) would use
+    now; host only."""
+    k, v = _i32(), _i32()
+    if len(shape) == 2:
+        p = params(dim=2, out_dtype=out_dtype, **kw)
+        _check(lib().ptg_tune_query_2d(p, shape[1], shape[0], ctypes.byref(k), ctypes.byref(v)))
+    else:
+        p = params(dim=3, out_dtype=out_dtype, **kw)
+        _check(lib().ptg_tune_query_3d(p, shape[2], shape[1], shape[0], ctypes.byref(k), ctypes.byref(v)))
+    return TUNE_NAMES.get(k.value, k.value), v.value
+
+
+def tune_set(shape, value, out_dtype=PTG_F32, **kw):
+    """Record a shape for the kernel class of a call over `shape`."""
+    if len(shape) == 2:
+        _check(lib().ptg_tune_set_2d(params(dim=2, out_dtype=out_dtype, **kw), shape[1], shape[0], value))
+    else:
+        _check(lib().ptg_tune_set_3d(params(dim=3, out_dtype=out_dtype, **kw), shape[2], shape[1], shape[0], value))
+
+
+def tune_reset():
+    lib().ptg_tune_reset()
+
+
 def tile_req(dim=2, origin=(0, 0, 0), extent=(64, 64, 1), user_tag=0, **kw) -> TileReq:
     r = TileReq()
     r.params = params(dim=dim, **kw)
@@ -292,8 +376,9 @@ class Server:
     """Continuous-batching tile server (a persistent kernel + host scheduler in libptg)."""
 
     def __init__(self, budget_bytes, max_items=1 << 16, workgroups=0, device=0, executor=PTG_EXEC_GPU,
-                 fake_tile_ns=0, tiles_per_item=0):
-        cfg = ServerCfg(budget_bytes, max_items, workgroups, device, executor, fake_tile_ns, tiles_per_item)
+                 fake_tile_ns=0, tiles_per_item=0, autotune=0, tile_h=0):
+        cfg = ServerCfg(budget_bytes, max_items, workgroups, device, executor, fake_tile_ns, tiles_per_item,
+                        autotune, tile_h)
         h = ctypes.c_void_p()
         _check(lib().ptg_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.h = h
@@ -317,7 +402,9 @@ class Server:
     def stats(self) -> dict:
         st = ServerStats()
         _check(lib().ptg_server_stats_get(self.h, ctypes.byref(st)))
-        return {n: getattr(st, n) for n, _ in ServerStats._fields_}
+        d = {n: getattr(st, n) for n, _ in ServerStats._fields_}
+        d["tile_h"] = list(st.tile_h)
+        return d
 
     def close(self):
         if self.h:
@@ -336,13 +423,19 @@ _HIP = None
 
 
 def device_copy(dst_ptr, src_ptr, nbytes):
-    """Synchronous device-to-device copy (hipMemcpy) between raw device pointers, e.g. a
-    served tile into a torch tensor."""
+    """Device-to-device copy between raw device pointers (e.g. a served tile into a torch
+    tensor), complete when this returns.  A device-to-device hipMemcpy may return before the
+    copy has run, so the null stream it is queued on is synchronised as well (only that
+    stream: the server's own stream is non-blocking and never waited for)."""
     global _HIP
     if _HIP is None:
         _HIP = ctypes.CDLL("libamdhip64.so")
         _HIP.hipMemcpy.argtypes = [_vp, _vp, ctypes.c_size_t, ctypes.c_int]
         _HIP.hipMemcpy.restype = ctypes.c_int
+        _HIP.hipStreamSynchronize.argtypes = [_vp]
+        _HIP.hipStreamSynchronize.restype = ctypes.c_int
     rc = _HIP.hipMemcpy(dst_ptr, src_ptr, nbytes, 3)  # hipMemcpyDeviceToDevice
+    if rc == 0:
+        rc = _HIP.hipStreamSynchronize(None)
     if rc != 0:
         raise PtgError(PTG_EHIP, f"hipMemcpy failed ({rc})")

@@ -133,7 +133,8 @@ int ptg_fbm_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t 
     if (nx == 0 || ny == 0) return PTG_OK;
     if (!out_dev) return fail(PTG_EINVAL, "out_dev is NULL");
     if (row_pitch < nx) return fail(PTG_EINVAL, "row_pitch %lld < nx %lld", (long long)row_pitch, (long long)nx);
-    const int64_t tiles_x = (nx + kTile2 - 1) / kTile2, tiles_y = (ny + kTile2 - 1) / kTile2;
+    // the general kernel's smallest tiles are 64 x 16
+    const int64_t tiles_x = (nx + kTile2 - 1) / kTile2, tiles_y = (ny + 15) / 16;
     if (tiles_x * tiles_y > 0x7FFFFFFFLL) return fail(PTG_EINVAL, "field too large for one launch");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (p->form != PTG_FORM_PLAIN) return fbm2d_mfma(p, x0, y0, nx, ny, out_dev, row_pitch, s);

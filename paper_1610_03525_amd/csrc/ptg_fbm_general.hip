@@ -4,11 +4,11 @@
 
 namespace ptg {
 
-template <int M, typename OutT>
+template <int M, typename OutT, int TH>
 __global__ __launch_bounds__(256) void k_fbm2d_general(const Fbm2dArgs a)
 {
     extern __shared__ float4 lds4[];
-    fbm2d_general_tile<M, OutT>(a, blockIdx.x, lds4);
+    fbm2d_general_tile<M, OutT, TH>(a, blockIdx.x, lds4);
 }
 
 template <int M, typename OutT>
@@ -30,15 +30,25 @@ static hipError_t launch_dyn(void (*kernel)(Args), dim3 grid, size_t lds, hipStr
     return hipGetLastError();
 }
 
+template <int TH>
+static hipError_t launch_2d_th(const Fbm2dArgs &a, int smooth, bool f16, dim3 grid, size_t lds, hipStream_t s)
+{
+    if (smooth == 1)
+        return f16 ? launch_dyn(k_fbm2d_general<1, __half, TH>, grid, lds, s, a)
+                   : launch_dyn(k_fbm2d_general<1, float, TH>, grid, lds, s, a);
+    return f16 ? launch_dyn(k_fbm2d_general<2, __half, TH>, grid, lds, s, a)
+               : launch_dyn(k_fbm2d_general<2, float, TH>, grid, lds, s, a);
+}
+
 hipError_t launch_fbm2d_general(const Fbm2dArgs &a, int smooth, bool f16, size_t lds, hipStream_t s)
 {
-    const int64_t tiles = (int64_t)a.tiles_x * ((a.ny + kTile2 - 1) / kTile2);
+    const int64_t tiles = (int64_t)a.tiles_x * ((a.ny + a.tile_h - 1) / a.tile_h);
     dim3 grid((unsigned)tiles);
-    if (smooth == 1)
-        return f16 ? launch_dyn(k_fbm2d_general<1, __half>, grid, lds, s, a)
-                   : launch_dyn(k_fbm2d_general<1, float>, grid, lds, s, a);
-    return f16 ? launch_dyn(k_fbm2d_general<2, __half>, grid, lds, s, a)
-               : launch_dyn(k_fbm2d_general<2, float>, grid, lds, s, a);
+    switch (a.tile_h) {
+    case 16: return launch_2d_th<16>(a, smooth, f16, grid, lds, s);
+    case 32: return launch_2d_th<32>(a, smooth, f16, grid, lds, s);
+    default: return launch_2d_th<64>(a, smooth, f16, grid, lds, s);
+    }
 }
 
 hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t lds, hipStream_t s)

@@ -40,25 +40,25 @@ __device__ __forceinline__ __half to_out<__half>(float v)
 }
 
 // ---------------------------------------------------------------------------------
-// 2D: tile 64 x 64 samples, 4 waves x 16 rows.
-// LDS: row table float4[64] | gx[capx*capy] | gy[capx*capy] | kx[capx] | ky[capy]
+// 2D: tile 64 x TH samples (TH = 16, 32 or 64 rows), 4 waves x TH/4 rows.
+// LDS: row table float4[TH] | gx[capx*capy] | gy[capx*capy] | kx[capx] | ky[capy]
 // ---------------------------------------------------------------------------------
-template <int M, typename OutT>
+template <int M, typename OutT, int TH>
 __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t bid, float4 *lds4)
 {
     constexpr int T = kTile2;
-    constexpr int RPT = T / 4;
+    constexpr int RPT = TH / 4;
     float4 *rowt = lds4;
     const int cap = a.capx * a.capy;
-    float *gx = reinterpret_cast<float *>(lds4 + T);
+    float *gx = reinterpret_cast<float *>(lds4 + TH);
     float *gy = gx + cap;
     uint32_t *kx = reinterpret_cast<uint32_t *>(gy + cap);
     uint32_t *ky = kx + a.capx;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t tx0 = (bid % a.tiles_x) * T, ty0 = (bid / a.tiles_x) * T;
+    const int64_t tx0 = (bid % a.tiles_x) * T, ty0 = (bid / a.tiles_x) * TH;
     const int w = (int)min<int64_t>(T, a.nx - tx0);
-    const int h = (int)min<int64_t>(T, a.ny - ty0);
+    const int h = (int)min<int64_t>(TH, a.ny - ty0);
     const int col = min(lane, w - 1);  // lanes past the edge shadow the last column
     const int64_t X = a.x0 + tx0 + col;
     const int64_t Xf = a.x0 + tx0, Xl = a.x0 + tx0 + w - 1;
@@ -79,7 +79,7 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
         const uint32_t pre = key_prefix(a.seed, o);
         for (int i = tid; i < nnx; i += 256) kx[i] = key_xline(cxf + i);
         for (int j = tid; j < nny; j += 256) ky[j] = absorb_index(pre, cyf + j);
-        if (tid < T) {
+        if (tid < TH) {
             const int r = min(tid, h - 1);
             const Coord c = coord_step(Yf + r, f);
             float s, b10, b11;

@@ -19,9 +19,33 @@ int footprint_cap(const double *freq, int octaves, int extent);
 
 // Kernel arguments of the general K3 for one field; return the dynamic LDS bytes.
 size_t general_args_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out,
-                       int64_t pitch, Fbm2dArgs *a);
+                       int64_t pitch, int tile_h, Fbm2dArgs *a);
 size_t general_args_3d(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz,
                        void *out, Fbm3dArgs *a);
+
+// ---- tile-shape tuning (a6) -----------------------------------------------------
+// A launch class: which kernel a call runs (PTG_TUNE_*), its cell order, output type,
+// size class (ceil log2 of the samples) and ladder class (finest period, log2, capped).
+struct TuneKey {
+    int32_t kernel, smooth, f16, size_class, ladder;
+    bool operator<(const TuneKey &o) const;
+};
+// The shape a launch of class k uses: the value forced by the tuner on this thread, else
+// the recorded choice, else dflt.  Also remembers k as this thread's last class.
+int tune_pick(const TuneKey &k, int dflt);
+// Dry run on this thread: the drivers choose their kernel and shape, then return PTG_OK
+// without launching (tune queries); and the value the tuner forces (0 = none).
+bool tune_dry();
+// Scope of one tuned or queried call on this thread (not nestable).
+struct TuneScope {
+    TuneScope(bool dry, int force);
+    ~TuneScope();
+    bool picked() const;  // a driver chose its class inside the scope
+    TuneKey key() const;  // the class it chose
+    int value() const;    // and the shape it used
+};
+int size_class(int64_t samples);
+int ladder_class(const double *freq, int octaves);
 
 // Dense-field drivers (arguments already validated, field non-empty).
 int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out, int64_t pitch,

@@ -9,7 +9,7 @@ namespace ptg {
 constexpr int kMaxOctaves = 16;
 
 // Dense 2D field, general (any-parameter) K3: 64 x 64 sample tiles, 256 threads.
-constexpr int kTile2 = 64;
+constexpr int kTile2 = 64;  // tile width, and the largest tile height
 // Dense 3D field, general K3: 64 x 8 x 8 sample tiles, 256 threads.
 constexpr int kTile3X = 64;
 constexpr int kTile3Y = 8;
@@ -24,7 +24,7 @@ struct Fbm2dArgs {
     uint32_t seed;
     int32_t capx, capy;  // LDS footprint capacity (nodes per axis) for every octave
     int32_t tiles_x;     // tiles per row of the tile grid
-    int32_t pad;
+    int32_t tile_h;      // rows per tile: 16, 32 or 64 (tile shape chosen by the tuner)
 };
 
 struct Fbm3dArgs {

@@ -96,6 +96,8 @@ static int fbm2d_dyadic(const ptg_params *p, int k, int64_t x0, int64_t y0, int6
     const size_t lds = (size_t)tab * 16 + (size_t)nodes * 8 + (size_t)(px + py) * 4 + (size_t)nodes * 4 +
                        (size_t)(px + py) * 4;
     if (lds > kDyMaxLds) return 1;  // footprint too large for one workgroup: caller falls back
+    (void)tune_pick(TuneKey{PTG_TUNE_DYADIC_2D, p->smoothness, p->out_dtype == PTG_F16, size_class(nx * ny), k}, 0);
+    if (tune_dry()) return PTG_OK;
     hipError_t e = launch_fbm2d_dyadic(a, p->smoothness, p->out_dtype == PTG_F16, lds, s);
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d dyadic launch");
 }
@@ -160,11 +162,15 @@ static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
     const size_t shared_words = (size_t)((keys + nodes + 3) & ~3);
     const size_t wave_words = (size_t)((2 * nodes + keys + 3) & ~3);
     if (keys >= (1 << 14)) return 1;
-    // waves per workgroup: as many (up to 4) as the private node blocks allow in LDS
-    int waves = kStripWavesPerWg;
+    // waves per workgroup: the tuned count (default 4), at most what the private node
+    // blocks allow in LDS
+    int waves = tune_pick(TuneKey{PTG_TUNE_STRIP_2D, p->smoothness, p->out_dtype == PTG_F16, size_class(nx * ny),
+                                  a.lo},
+                          kStripWavesPerWg);
     while (waves > 1 && (shared_words + waves * wave_words) * 4 > kDyMaxLds) --waves;
     const size_t lds = (shared_words + waves * wave_words) * 4;
     if (lds > kDyMaxLds) return 1;
+    if (tune_dry()) return PTG_OK;
     // a persistent grid of exactly the resident workgroups (a partial second round would
     // leave most of the chip idle at the end)
     const int64_t per_cu = strip_wgs_per_cu(p->smoothness, p->out_dtype == PTG_F16, a.lo, waves, lds);
@@ -175,7 +181,7 @@ static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
 }
 
 size_t general_args_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out,
-                       int64_t pitch, Fbm2dArgs *a)
+                       int64_t pitch, int tile_h, Fbm2dArgs *a)
 {
     *a = Fbm2dArgs{};
     a->x0 = x0;
@@ -187,10 +193,11 @@ size_t general_args_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, 
     octave_tables(p, a->freq, a->amp);
     a->octaves = p->octaves;
     a->seed = p->seed;
+    a->tile_h = tile_h;
     a->capx = footprint_cap(a->freq, p->octaves, kTile2);
-    a->capy = a->capx;
+    a->capy = footprint_cap(a->freq, p->octaves, tile_h);
     a->tiles_x = (int32_t)((nx + kTile2 - 1) / kTile2);
-    return (size_t)kTile2 * 16 + (size_t)a->capx * a->capy * 8 + (size_t)(a->capx + a->capy) * 4;
+    return (size_t)tile_h * 16 + (size_t)a->capx * a->capy * 8 + (size_t)(a->capx + a->capy) * 4;
 }
 
 size_t general_args_3d(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz,
@@ -232,7 +239,14 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
             return fail(PTG_EINVAL, "the dyadic kernel's lattice footprint exceeds the workgroup's LDS");
     }
     Fbm2dArgs a{};
-    const size_t lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, &a);
+    double freq[kMaxOctaves];
+    float amp[kMaxOctaves];
+    octave_tables(p, freq, amp);
+    const int tile_h = tune_pick(TuneKey{PTG_TUNE_GENERAL_2D, p->smoothness, p->out_dtype == PTG_F16,
+                                         size_class(nx * ny), ladder_class(freq, p->octaves)},
+                                 kTile2);
+    const size_t lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, tile_h, &a);
+    if (tune_dry()) return PTG_OK;
     hipError_t e = launch_fbm2d_general(a, p->smoothness, p->out_dtype == PTG_F16, lds, s);
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d launch");
 }
@@ -300,10 +314,13 @@ static int fbm3d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
     if (keys >= (1 << 14)) return 1;
     const size_t shared_words = (size_t)4 * tab + (size_t)((keys + nodes + 3) & ~3);
     const size_t wave_words = (size_t)((3 * nodes + keys + 3) & ~3);
-    int waves = 4;
+    int waves = tune_pick(TuneKey{PTG_TUNE_STRIP_3D, p->smoothness, p->out_dtype == PTG_F16,
+                                  size_class(nx * ny * nz), a.lo},
+                          4);
     while (waves > 1 && (shared_words + waves * wave_words) * 4 > kDyMaxLds) --waves;
     const size_t lds = (shared_words + waves * wave_words) * 4;
     if (lds > kDyMaxLds) return 1;
+    if (tune_dry()) return PTG_OK;
     const int64_t per_cu = strip3_wgs_per_cu(p->smoothness, p->out_dtype == PTG_F16, a.lo, waves, lds);
     const int64_t wgs = (a.blocks + waves - 1) / waves;
     const int grid = (int)std::min<int64_t>(wgs, (int64_t)device_cus() * per_cu);
@@ -326,6 +343,10 @@ int fbm3d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t
     }
     Fbm3dArgs a{};
     const size_t lds = general_args_3d(p, x0, y0, z0, nx, ny, nz, out, &a);
+    (void)tune_pick(TuneKey{PTG_TUNE_GENERAL_3D, p->smoothness, p->out_dtype == PTG_F16, size_class(nx * ny * nz),
+                            ladder_class(a.freq, p->octaves)},
+                    0);
+    if (tune_dry()) return PTG_OK;
     hipError_t e = launch_fbm3d_general(a, p->smoothness, p->out_dtype == PTG_F16, lds, s);
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm3d launch");
 }

@@ -165,10 +165,22 @@ __global__ __launch_bounds__(256) void k_serve(ServeHostCtl *hc, const ServeItem
         const int64_t t1 = (int64_t)s_item.tile0 + s_item.ntiles;
         for (int64_t t = s_item.tile0; t < t1; ++t) {
             if (rq.dim == 2) {
-                if (rq.smooth == 1)
-                    fbm2d_general_tile<1, float>(rq.a2, t, lds4);
-                else
-                    fbm2d_general_tile<2, float>(rq.a2, t, lds4);
+                const int th = rq.a2.tile_h;
+                if (rq.smooth == 1) {
+                    if (th == 16)
+                        fbm2d_general_tile<1, float, 16>(rq.a2, t, lds4);
+                    else if (th == 32)
+                        fbm2d_general_tile<1, float, 32>(rq.a2, t, lds4);
+                    else
+                        fbm2d_general_tile<1, float, 64>(rq.a2, t, lds4);
+                } else {
+                    if (th == 16)
+                        fbm2d_general_tile<2, float, 16>(rq.a2, t, lds4);
+                    else if (th == 32)
+                        fbm2d_general_tile<2, float, 32>(rq.a2, t, lds4);
+                    else
+                        fbm2d_general_tile<2, float, 64>(rq.a2, t, lds4);
+                }
             } else {
                 if (rq.smooth == 1)
                     fbm3d_general_tile<1, float>(rq.a3, t, lds4);
@@ -261,6 +273,7 @@ struct Request {
 struct ptg_server {
     ptg_server_cfg cfg{};
     bool gpu = true;
+    int tile_h2[2] = {ptg::kTile2, ptg::kTile2};  // 2D tile height for C1 / C2 requests
     hipStream_t stream = nullptr;
     int workgroups = 0;
     ptg::ServeHostCtl *hc = nullptr;
@@ -371,7 +384,7 @@ static void publish(ptg_server *s, uint64_t ticket, Request &r)
     d.ntiles = r.ntiles;
     if (p->dim == 2)
         general_args_2d(p, r.req.origin[0], r.req.origin[1], r.req.extent[0], r.req.extent[1], out, r.req.extent[0],
-                        &d.a2);
+                        s->tile_h2[p->smoothness - 1], &d.a2);
     else
         general_args_3d(p, r.req.origin[0], r.req.origin[1], r.req.origin[2], r.req.extent[0], r.req.extent[1],
                         r.req.extent[2], out, &d.a3);
@@ -539,9 +552,10 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
     octave_tables(p, freq, amp);
     size_t lds;
     if (nd == 2) {
-        *ntiles = ((nx + kTile2 - 1) / kTile2) * ((ny + kTile2 - 1) / kTile2);
-        const int c = footprint_cap(freq, p->octaves, kTile2);
-        lds = (size_t)kTile2 * 16 + (size_t)c * c * 8 + (size_t)2 * c * 4;
+        const int th = s->tile_h2[p->smoothness - 1];
+        *ntiles = ((nx + kTile2 - 1) / kTile2) * ((ny + th - 1) / th);
+        const int cx = footprint_cap(freq, p->octaves, kTile2), cy = footprint_cap(freq, p->octaves, th);
+        lds = (size_t)th * 16 + (size_t)cx * cy * 8 + (size_t)(cx + cy) * 4;
     } else {
         *ntiles = ((nx + kTile3X - 1) / kTile3X) * ((ny + kTile3Y - 1) / kTile3Y) * ((nz + kTile3Z - 1) / kTile3Z);
         const int cx = footprint_cap(freq, p->octaves, kTile3X), cy = footprint_cap(freq, p->octaves, kTile3Y),
@@ -588,8 +602,14 @@ int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out)
     if (cfg->workgroups < 0 || cfg->workgroups > 65536) return fail(PTG_EINVAL, "bad workgroup count");
     if (cfg->executor != PTG_EXEC_GPU && cfg->executor != PTG_EXEC_HOST) return fail(PTG_EINVAL, "bad executor");
     if (cfg->executor == PTG_EXEC_HOST && cfg->fake_tile_ns < 0) return fail(PTG_EINVAL, "fake_tile_ns < 0");
-    if (cfg->tiles_per_item < 0 || cfg->tiles_per_item > kMaxTilesPerItem || cfg->reserved != 0)
+    if (cfg->tiles_per_item < 0 || cfg->tiles_per_item > kMaxTilesPerItem)
         return fail(PTG_EINVAL, "tiles_per_item must be in 0..%d", kMaxTilesPerItem);
+    if ((cfg->autotune != 0 && cfg->autotune != 1) || cfg->reserved != 0)
+        return fail(PTG_EINVAL, "autotune must be 0 or 1, reserved 0");
+    if (cfg->tile_h != 0 && cfg->tile_h != 16 && cfg->tile_h != 32 && cfg->tile_h != 64)
+        return fail(PTG_EINVAL, "tile_h must be 0, 16, 32 or 64");
+    if (cfg->autotune && cfg->executor == PTG_EXEC_GPU && cfg->hbm_budget_bytes < (1 << 20))
+        return fail(PTG_EINVAL, "autotune needs a budget of at least 1 MiB");
     *out = nullptr;
     ptg_server *s = new ptg_server();
     s->cfg = *cfg;
@@ -598,6 +618,7 @@ int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out)
     for (int i = kReqSlots - 1; i >= 0; --i) s->free_slots.push_back(i);
     s->slot_total.assign(kReqSlots, 0);
     s->arena.reset(new Arena(cfg->hbm_budget_bytes));
+    if (cfg->tile_h != 0) s->tile_h2[0] = s->tile_h2[1] = cfg->tile_h;
     s->workgroups = cfg->workgroups > 0 ? cfg->workgroups : 512;
     if (s->gpu) {
         hipError_t e = hipSetDevice(cfg->device);
@@ -629,6 +650,22 @@ int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out)
         }
         std::memset(s->hc, 0, sizeof(ServeHostCtl));
         std::memset(s->done, 0, sizeof(uint32_t) * kReqSlots);
+        if (cfg->autotune && cfg->tile_h == 0) {  // tile heights timed on the arena, before any request
+            for (int m = 1; m <= 2; ++m) {
+                ptg_params p;
+                ptg_params_default(&p);
+                p.smoothness = m;
+                p.base_freq = 1.0 / 4096.0;
+                p.path = PTG_PATH_GENERAL;
+                ptg_tune_result r;
+                const int rc = ptg_tune_2d(&p, 0, 0, 512, 512, s->arena_mem, 512, s->stream, 5, &r);
+                if (rc != PTG_OK) {
+                    free_server(s);
+                    return rc;
+                }
+                s->tile_h2[m - 1] = r.value;
+            }
+        }
     } else {
         s->arena_mem = static_cast<char *>(std::malloc((size_t)cfg->hbm_budget_bytes));
         if (!s->arena_mem) {
@@ -720,6 +757,8 @@ int ptg_server_stats_get(ptg_server *s, ptg_server_stats *st)
     st->pending = (int64_t)s->pending.size();
     st->in_flight = (int64_t)s->inflight.size();
     st->bytes_in_use = s->arena->used();
+    st->tile_h[0] = s->tile_h2[0];
+    st->tile_h[1] = s->tile_h2[1];
     return PTG_OK;
 }
 

@@ -45,7 +45,7 @@ def _solo(r):
         ptg.fbm_2d(out, x0=r["origin"][0], y0=r["origin"][1], path="general", **kw)
     else:
         out = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
-        ptg.fbm_3d(out, x0=r["origin"][0], y0=r["origin"][1], z0=r["origin"][2], **kw)
+        ptg.fbm_3d(out, x0=r["origin"][0], y0=r["origin"][1], z0=r["origin"][2], path="general", **kw)
     torch.cuda.current_stream().synchronize()  # not the device: the server's kernel may be running
     return out
 

@@ -1,0 +1,87 @@
+"""Tile-shape autotuner, host side: which kernel class a call runs, the recorded shapes,
+and the validation of shapes and server settings (no GPU: queries never launch)."""
+import ctypes
+
+import pytest
+
+torch = pytest.importorskip("torch")
+import paper_1610_03525_amd as ptg  # noqa: E402
+
+
+@pytest.fixture(autouse=True)
+def _clean_table():
+    ptg.tune_reset()
+    yield
+    ptg.tune_reset()
+
+
+@pytest.mark.parametrize("shape,kw,expect", [
+    ((8192, 8192), dict(octaves=8, base_freq=16 / 8192), ("strip_2d", 4)),            # dyadic ladder to period 4
+    ((256, 300), dict(octaves=4, base_freq=0.013), ("general_2d", 64)),               # any base frequency
+    ((256, 256), dict(octaves=4, base_freq=1 / 32, path="general"), ("general_2d", 64)),
+    ((512, 512, 512), dict(smoothness=2, octaves=6, base_freq=8 / 512), ("strip_3d", 4)),
+    ((100, 100, 40), dict(smoothness=2, octaves=6, base_freq=0.02), ("general_3d", 0)),
+    ((40, 6, 5), dict(octaves=2, base_freq=0.5), ("general_3d", 0)),                   # ladder from period 2
+    ((2048, 2048), dict(octaves=4, base_freq=1 / 64, form=1), ("dyadic_2d", 0)),       # FP16 matrix-core form
+])
+def test_query_reports_the_kernel_class(shape, kw, expect):
+    assert ptg.tune_query(shape, **kw) == expect
+
+
+def test_set_query_reset_roundtrip():
+    kw = dict(octaves=4, base_freq=0.013)
+    for v in (16, 32, 64):
+        ptg.tune_set((256, 300), v, **kw)
+        assert ptg.tune_query((256, 300), **kw) == ("general_2d", v)
+    # another class (size class of 2^20 samples) is untouched
+    assert ptg.tune_query((1024, 1024), **kw) == ("general_2d", 64)
+    # C2 is a class of its own
+    assert ptg.tune_query((256, 300), smoothness=2, **kw) == ("general_2d", 64)
+    ptg.tune_set((8192, 8192), 2, octaves=8, base_freq=16 / 8192)
+    assert ptg.tune_query((8192, 8192), octaves=8, base_freq=16 / 8192) == ("strip_2d", 2)
+    ptg.tune_reset()
+    assert ptg.tune_query((256, 300), **kw) == ("general_2d", 64)
+    assert ptg.tune_query((8192, 8192), octaves=8, base_freq=16 / 8192) == ("strip_2d", 4)
+
+
+@pytest.mark.parametrize("shape,kw,value", [
+    ((256, 300), dict(octaves=4, base_freq=0.013), 8),            # not a tile height
+    ((256, 300), dict(octaves=4, base_freq=0.013), 4),            # a waves count, not a tile height
+    ((8192, 8192), dict(octaves=8, base_freq=16 / 8192), 3),      # not a waves count
+    ((100, 100, 40), dict(smoothness=2, octaves=6, base_freq=0.02), 64),  # general 3D: nothing to tune
+    ((2048, 2048), dict(octaves=4, base_freq=1 / 64, form=1), 2),
+])
+def test_set_rejects_shapes_that_are_not_candidates(shape, kw, value):
+    with pytest.raises(ptg.PtgError):
+        ptg.tune_set(shape, value, **kw)
+
+
+def test_query_validates_parameters():
+    with pytest.raises(ptg.PtgError):
+        ptg.tune_query((0, 16), octaves=4)
+    with pytest.raises(ptg.PtgError):
+        ptg.tune_query((16, 16), octaves=0)
+    with pytest.raises(ptg.PtgError):
+        ptg.tune_query((16, 16), base_freq=-1.0)
+
+
+def test_server_cfg_tile_settings_validation():
+    L = ptg.lib()
+    h = ctypes.c_void_p()
+    bad = [dict(tile_h=8), dict(tile_h=128), dict(autotune=2)]
+    for kw in bad:
+        cfg = ptg.ServerCfg(1 << 20, 1024, 0, 0, ptg.PTG_EXEC_HOST, 0, 0, kw.get("autotune", 0), kw.get("tile_h", 0))
+        assert L.ptg_server_create(ctypes.byref(cfg), ctypes.byref(h)) == ptg.PTG_EINVAL
+    with ptg.Server(1 << 20, executor=ptg.PTG_EXEC_HOST, tile_h=32) as s:
+        assert s.stats()["tile_h"] == [32, 32]
+    with ptg.Server(1 << 20, executor=ptg.PTG_EXEC_HOST) as s:
+        assert s.stats()["tile_h"] == [64, 64]
+
+
+def test_server_tile_height_sets_the_tile_count():
+    """A 2D request of 128 x 100 samples is 2 x 2 tiles of 64 x 64, or 2 x 7 of 64 x 16."""
+    for th, tiles in ((64, 4), (32, 8), (16, 14)):
+        with ptg.Server(1 << 22, executor=ptg.PTG_EXEC_HOST, fake_tile_ns=1000, tile_h=th) as s:
+            (t,) = s.submit([ptg.tile_req(dim=2, extent=(128, 100, 1), octaves=4, base_freq=2.0 ** -12)])
+            s.wait(t, 10_000_000_000)
+            assert s.stats()["tiles_done"] == tiles
