@@ -230,10 +230,13 @@ PTG_API void ptg_tune_reset(void);
 /* A server owns an output arena of hbm_budget_bytes and one persistent kernel.  Requests
  * (terrain tiles of any size, 2D or 3D, C1 or C2, any octave parameters, FP32 output) are
  * queued by ptg_tiles_submit, admitted while arena bytes and request slots are free, cut
- * into work items of 64 x tile_h (2D) or 64 x 8 x 8 (3D) sample tiles and published into a
- * ring that the persistent kernel's workgroups drain while earlier requests are still
- * running.  Each tile is computed by the same device code as ptg_fbm_2d / ptg_fbm_3d with
- * p->path = PTG_PATH_GENERAL, so a served tile equals that call bit for bit. */
+ * into work items and published into a ring that the persistent kernel's workgroups drain
+ * while earlier requests are still running.  A 2D request whose ladder is dyadic (base_freq
+ * 2^-k, lacunarity 2, finest period >= 2) and whose 64 x 64 strip footprint fits a serving
+ * workgroup runs as strips, one per wave, with the same device code as ptg_fbm_2d with
+ * PTG_PATH_DYADIC; every other request runs as 64 x tile_h (2D) or 64 x 8 x 8 (3D) sample
+ * tiles with the device code of PTG_PATH_GENERAL.  A served tile equals the corresponding
+ * stand-alone call bit for bit (ptg_tile_result.kernel says which). */
 
 typedef struct ptg_server ptg_server;
 
@@ -249,8 +252,9 @@ typedef struct ptg_server_cfg {
     int32_t device;           /* HIP device ordinal                                         */
     int32_t executor;         /* PTG_EXEC_GPU or PTG_EXEC_HOST                              */
     int64_t fake_tile_ns;     /* PTG_EXEC_HOST only: simulated time per tile                */
-    int32_t tiles_per_item;   /* sample tiles per work item, 1..16; 0 = from each request's */
-                              /* size (enough items for every workgroup, at most 16 tiles)  */
+    int32_t tiles_per_item;   /* sample tiles per work item, 1..16 (strip requests: 4 strips */
+                              /* per tile, one per wave); 0 = from each request's size      */
+                              /* (enough items for every workgroup, at most 16 tiles)       */
     int32_t autotune;         /* 1: at creation (PTG_EXEC_GPU) time the 2D tile heights on  */
                               /* a 512 x 512, 8-octave field per cell order (ptg_tune_2d,   */
                               /* general kernel; needs a budget >= 1 MiB) and use the best  */
@@ -268,7 +272,9 @@ typedef struct ptg_tile_req {
 
 typedef struct ptg_tile_result {
     int32_t status;           /* PTG_OK, PTG_ESHUTDOWN or PTG_EHIP                          */
-    int32_t reserved;
+    int32_t kernel;           /* code that computed it: PTG_TUNE_STRIP_2D (the dyadic strip */
+                              /* code; equals ptg_fbm_2d with PTG_PATH_DYADIC bit for bit),  */
+                              /* PTG_TUNE_GENERAL_2D / _3D (equals PTG_PATH_GENERAL)          */
     void *out_dev;            /* the tile, dense row-major FP32 [nz][ny][nx], valid until   */
                               /* ptg_tile_release (device memory; host memory for           */
                               /* PTG_EXEC_HOST)                                              */
@@ -303,7 +309,7 @@ PTG_API int ptg_tile_release(ptg_server *s, uint64_t ticket);
 
 typedef struct ptg_server_stats {
     int64_t submitted, admitted, completed, released;
-    int64_t tiles_done;       /* sample tiles finished                                      */
+    int64_t tiles_done;       /* sample tiles (or 64 x 64 strips) finished                  */
     int64_t pending, in_flight;
     int64_t bytes_in_use, bytes_peak, budget;
     int64_t kernel_launches;  /* persistent-kernel launches (it exits after idling)         */

@@ -83,7 +83,7 @@ class TileReq(ctypes.Structure):
 class TileResult(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("kernel", ctypes.c_int32),
         ("out_dev", ctypes.c_void_p),
         ("bytes", ctypes.c_int64),
         ("user_tag", ctypes.c_uint64),

@@ -23,6 +23,13 @@ size_t general_args_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, 
 size_t general_args_3d(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz,
                        void *out, Fbm3dArgs *a);
 
+// base_freq = 2^-k with lacunarity 2 and every octave within one cell per sample.
+bool dyadic_shift(const ptg_params *p, int *k_out);
+// Kernel arguments of the 2D strip kernel for a dyadic field (k from dyadic_shift);
+// returns 1 when the strip kernel does not apply (a ladder it cannot take, too many keys).
+int strip_args_2d(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out,
+                  int64_t pitch, Fbm2dStripArgs *a);
+
 // ---- tile-shape tuning (a6) -----------------------------------------------------
 // A launch class: which kernel a call runs (PTG_TUNE_*), its cell order, output type,
 // size class (ceil log2 of the samples) and ladder class (finest period, log2, capped).

@@ -129,6 +129,17 @@ struct Fbm3dStripArgs {
 // arguments and return the HIP status of the launch.
 hipError_t launch_fbm2d_general(const Fbm2dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fbm2d_dyadic(const Fbm2dDyadicArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
+// LDS words of the strip kernel's work lists (shared by a workgroup) and of one wave's
+// private node block (node gradients, then keys).
+__host__ __device__ inline int strip_shared_words(int nodes_total, int keys_total)
+{
+    return (keys_total + nodes_total + 3) & ~3;
+}
+__host__ __device__ inline int strip_wave_words(int nodes_total, int keys_total)
+{
+    return (2 * nodes_total + keys_total + 3) & ~3;
+}
+
 hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, bool f16, int grid, int waves, size_t lds_bytes,
                               hipStream_t s);
 int strip_wgs_per_cu(int smooth, bool f16, int lo, int waves, size_t lds_bytes);  // resident workgroups per CU

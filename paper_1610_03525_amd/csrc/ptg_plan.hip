@@ -9,7 +9,7 @@ namespace ptg {
 
 // Base frequency 2^-k with 0 <= k <= kDyMaxShift and lacunarity exactly 2 (every octave
 // period then a power of two >= 1, checked by the caller's frequency validation).
-static bool dyadic_shift(const ptg_params *p, int *k_out)
+bool dyadic_shift(const ptg_params *p, int *k_out)
 {
     if (p->lacunarity != 2.0) return false;
     int e = 0;
@@ -102,13 +102,12 @@ static int fbm2d_dyadic(const ptg_params *p, int k, int64_t x0, int64_t y0, int6
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d dyadic launch");
 }
 
-// Plain FP32 dyadic field through the strip kernel; returns 1 when a strip's node
-// footprint does not fit the workgroup's LDS (the caller falls back).
-static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out,
-                       int64_t pitch, hipStream_t s)
+int strip_args_2d(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out,
+                  int64_t pitch, Fbm2dStripArgs *ap)
 {
     constexpr int SW = kStripW, SH = kStripH;
-    Fbm2dStripArgs a{};
+    Fbm2dStripArgs &a = *ap;
+    a = Fbm2dStripArgs{};
     a.x0 = x0;
     a.y0 = y0;
     a.nx = nx;
@@ -159,9 +158,19 @@ static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
     }
     a.nodes_total = nodes;
     a.keys_total = keys;
-    const size_t shared_words = (size_t)((keys + nodes + 3) & ~3);
-    const size_t wave_words = (size_t)((2 * nodes + keys + 3) & ~3);
     if (keys >= (1 << 14)) return 1;
+    return 0;
+}
+
+// Plain FP32 dyadic field through the strip kernel; returns 1 when a strip's node
+// footprint does not fit the workgroup's LDS (the caller falls back).
+static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out,
+                       int64_t pitch, hipStream_t s)
+{
+    Fbm2dStripArgs a;
+    if (strip_args_2d(p, k, x0, y0, nx, ny, out, pitch, &a)) return 1;
+    const size_t shared_words = (size_t)strip_shared_words(a.nodes_total, a.keys_total);
+    const size_t wave_words = (size_t)strip_wave_words(a.nodes_total, a.keys_total);
     // waves per workgroup: the tuned count (default 4), at most what the private node
     // blocks allow in LDS
     int waves = tune_pick(TuneKey{PTG_TUNE_STRIP_2D, p->smoothness, p->out_dtype == PTG_F16, size_class(nx * ny),

@@ -42,6 +42,7 @@
 
 #include "ptg_general_tile.h"
 #include "ptg_internal.h"
+#include "ptg_strip_tile.h"
 
 namespace ptg {
 
@@ -51,15 +52,21 @@ constexpr int kMaxTilesPerItem = 16;      // sample tiles per work item, upper b
 constexpr int64_t kParkNs = 5000000;       // nothing in flight for 5 ms: park the kernel
 constexpr int64_t kSpinNs = 2000000;       // the scheduler spins until 2 ms after the last event
 constexpr int64_t kStarveNs = 50000000;    // after 50 ms a waiting request blocks later ones
+constexpr int kServeWaves = 4;             // waves of a serving workgroup (256 threads)
+// a strip request's LDS: [StripShared | key and node work lists | one node block per wave]
+constexpr int kStripSharedWords = (int)((sizeof(StripShared) + 15) / 16 * 4);
 
 struct ServeReqDesc {
     int32_t dim, smooth, slot;
     uint32_t seq;
     uint64_t target;  // done_tiles[slot] when this request is complete
     int64_t ntiles;
+    int32_t kernel;   // PTG_TUNE_GENERAL_2D / _GENERAL_3D (tiles) or PTG_TUNE_STRIP_2D (64 x 64 strips)
+    int32_t pad;
     union {
         Fbm2dArgs a2;
         Fbm3dArgs a3;
+        Fbm2dStripArgs as;
     };
 };
 static_assert(sizeof(ServeReqDesc) % 8 == 0, "descriptor is copied in 8-byte words");
@@ -96,7 +103,34 @@ __device__ __forceinline__ uint64_t sys_load64(const uint64_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-__global__ __launch_bounds__(256) void k_serve(ServeHostCtl *hc, const ServeItem *ring, const ServeReqDesc *reqs,
+// Strips [t0, t1) of a dyadic 2D request: wave w takes t0 + w, t0 + w + 4, ... (the same
+// per-strip code as the dense strip kernel, so a served strip equals that kernel's output).
+template <int M, int LO>
+__device__ __forceinline__ void serve_strips(const Fbm2dStripArgs &a, const StripShared &sh, uint32_t *wl, int64_t t0,
+                                             int64_t t1, int tid)
+{
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    float2 *nodes = reinterpret_cast<float2 *>(wl + strip_shared_words(a.nodes_total, a.keys_total) +
+                                               wave * strip_wave_words(a.nodes_total, a.keys_total));
+    StripWave<M, float, LO> w(a, sh, nodes, lane);
+    for (int64_t st = t0 + wave; st < t1; st += kServeWaves) w.run(a, sh, wl, wl + a.keys_total, st);
+}
+
+template <int M>
+__device__ __forceinline__ void serve_strips_lo(const Fbm2dStripArgs &a, const StripShared &sh, uint32_t *wl,
+                                                int64_t t0, int64_t t1, int tid)
+{
+    switch (a.lo) {  // admission guarantees 1 <= lo <= 6
+    case 1: serve_strips<M, 1>(a, sh, wl, t0, t1, tid); break;
+    case 2: serve_strips<M, 2>(a, sh, wl, t0, t1, tid); break;
+    case 3: serve_strips<M, 3>(a, sh, wl, t0, t1, tid); break;
+    case 4: serve_strips<M, 4>(a, sh, wl, t0, t1, tid); break;
+    case 5: serve_strips<M, 5>(a, sh, wl, t0, t1, tid); break;
+    default: serve_strips<M, 6>(a, sh, wl, t0, t1, tid); break;
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeItem *ring, const ServeReqDesc *reqs,
                                                uint32_t *done, ServeDevCtl *dc, int32_t ring_size)
 {
     extern __shared__ float4 lds4[];
@@ -163,7 +197,21 @@ __global__ __launch_bounds__(256) void k_serve(ServeHostCtl *hc, const ServeItem
         }
         const ServeReqDesc &rq = *reinterpret_cast<const ServeReqDesc *>(s_req);
         const int64_t t1 = (int64_t)s_item.tile0 + s_item.ntiles;
-        for (int64_t t = s_item.tile0; t < t1; ++t) {
+        if (rq.kernel == PTG_TUNE_STRIP_2D) {
+            // the work lists stay in LDS while this workgroup's items come from one request
+            StripShared &sh = *reinterpret_cast<StripShared *>(lds4);
+            uint32_t *wl = reinterpret_cast<uint32_t *>(lds4) + kStripSharedWords;
+            if (s_cmd == 1) {
+                strip_prologue(rq.as, sh, wl, wl + rq.as.keys_total, tid, 256);
+                __syncthreads();
+            }
+            if (rq.smooth == 1)
+                serve_strips_lo<1>(rq.as, sh, wl, s_item.tile0, t1, tid);
+            else
+                serve_strips_lo<2>(rq.as, sh, wl, s_item.tile0, t1, tid);
+            __syncthreads();
+        }
+        for (int64_t t = s_item.tile0; rq.kernel != PTG_TUNE_STRIP_2D && t < t1; ++t) {
             if (rq.dim == 2) {
                 const int th = rq.a2.tile_h;
                 if (rq.smooth == 1) {
@@ -261,6 +309,7 @@ class Arena {
 struct Request {
     ptg_tile_req req;
     int64_t bytes = 0, ntiles = 0, arena_off = -1, per_item = 1, items = 0;
+    int32_t kernel = 0;  // PTG_TUNE_* class that computes it
     int32_t slot = -1;
     uint32_t seq = 0;
     uint64_t ring_begin = 0, ring_end = 0;
@@ -382,7 +431,13 @@ static void publish(ptg_server *s, uint64_t ticket, Request &r)
     s->slot_total[slot] += (uint64_t)r.ntiles;
     d.target = s->slot_total[slot];
     d.ntiles = r.ntiles;
-    if (p->dim == 2)
+    d.kernel = r.kernel;
+    if (r.kernel == PTG_TUNE_STRIP_2D) {
+        int k = 0;
+        (void)dyadic_shift(p, &k);  // validated at submission
+        (void)strip_args_2d(p, k, r.req.origin[0], r.req.origin[1], r.req.extent[0], r.req.extent[1], out,
+                            r.req.extent[0], &d.as);
+    } else if (p->dim == 2)
         general_args_2d(p, r.req.origin[0], r.req.origin[1], r.req.extent[0], r.req.extent[1], out, r.req.extent[0],
                         s->tile_h2[p->smoothness - 1], &d.a2);
     else
@@ -408,7 +463,10 @@ static void admit(ptg_server *s)
     const int64_t now = now_ns();
     for (auto it = s->pending.begin(); it != s->pending.end();) {
         Request &r = s->by_ticket[*it];
-        r.per_item = tiles_per_item(s, r.ntiles);
+        // a strip is one wave's work: items of a strip request hold whole workgroups' worth
+        r.per_item = r.kernel == PTG_TUNE_STRIP_2D
+                         ? kServeWaves * tiles_per_item(s, (r.ntiles + kServeWaves - 1) / kServeWaves)
+                         : tiles_per_item(s, r.ntiles);
         r.items = (r.ntiles + r.per_item - 1) / r.per_item;
         const uint64_t items = (uint64_t)r.items;
         if (s->free_slots.empty()) break;
@@ -527,7 +585,7 @@ static void service(ptg_server *s)
     }
 }
 
-static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *bytes, int64_t *ntiles)
+static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *bytes, int64_t *ntiles, int32_t *kernel)
 {
     const ptg_params *p = &r->params;
     if (!p || (p->dim != 2 && p->dim != 3)) return fail(PTG_EINVAL, "request dim must be 2 or 3");
@@ -551,7 +609,18 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
     float amp[kMaxOctaves];
     octave_tables(p, freq, amp);
     size_t lds;
-    if (nd == 2) {
+    int k = 0;
+    Fbm2dStripArgs sa;
+    *kernel = nd == 2 ? PTG_TUNE_GENERAL_2D : PTG_TUNE_GENERAL_3D;
+    if (nd == 2 && dyadic_shift(p, &k) &&
+        strip_args_2d(p, k, r->origin[0], r->origin[1], nx, ny, nullptr, nx, &sa) == 0 && sa.lo >= 1 &&
+        (size_t)(kStripSharedWords + strip_shared_words(sa.nodes_total, sa.keys_total) +
+                 kServeWaves * strip_wave_words(sa.nodes_total, sa.keys_total)) * 4 <= kServeLds) {
+        // dyadic ladder whose strip footprint fits a serving workgroup: the strip code
+        *kernel = PTG_TUNE_STRIP_2D;
+        *ntiles = sa.strips;
+        lds = 0;
+    } else if (nd == 2) {
         const int th = s->tile_h2[p->smoothness - 1];
         *ntiles = ((nx + kTile2 - 1) / kTile2) * ((ny + th - 1) / th);
         const int cx = footprint_cap(freq, p->octaves, kTile2), cy = footprint_cap(freq, p->octaves, th);
@@ -564,7 +633,8 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
     }
     if (lds > kServeLds) return fail(PTG_EINVAL, "the request's lattice is too fine for a serving workgroup");
     if (*ntiles > 0x7FFFFFFFLL) return fail(PTG_EINVAL, "request too large");
-    const int64_t per = s->cfg.tiles_per_item > 0 ? s->cfg.tiles_per_item : kMaxTilesPerItem;
+    const int64_t per = (*kernel == PTG_TUNE_STRIP_2D ? kServeWaves : 1) *
+                        (s->cfg.tiles_per_item > 0 ? s->cfg.tiles_per_item : kMaxTilesPerItem);
     const uint64_t items = (uint64_t)((*ntiles + per - 1) / per);
     if (items > (uint64_t)s->cfg.max_items) return fail(PTG_E2BIG, "request needs more work items than the ring holds");
     if (((*bytes + 255) & ~int64_t(255)) > s->cfg.hbm_budget_bytes)
@@ -682,8 +752,9 @@ int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n, uint64_
 {
     if (!s || (n > 0 && (!reqs || !tickets_out)) || n < 0) return fail(PTG_EINVAL, "bad arguments");
     std::vector<int64_t> bytes(n), tiles(n);
+    std::vector<int32_t> kernels(n);
     for (int32_t i = 0; i < n; ++i) {
-        const int rc = validate_req(s, &reqs[i], &bytes[i], &tiles[i]);
+        const int rc = validate_req(s, &reqs[i], &bytes[i], &tiles[i], &kernels[i]);
         if (rc) return rc;
     }
     std::lock_guard<std::mutex> lk(s->mu);
@@ -696,6 +767,7 @@ int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n, uint64_
         r.req = reqs[i];
         r.bytes = bytes[i];
         r.ntiles = tiles[i];
+        r.kernel = kernels[i];
         r.t_submit = t;
         s->pending.push_back(ticket);
         tickets_out[i] = ticket;
@@ -725,6 +797,7 @@ int ptg_tiles_wait(ptg_server *s, uint64_t ticket, int64_t timeout_ns, ptg_tile_
     if (r.status > 0) return fail(PTG_ETIMEDOUT, "request still pending");
     std::memset(res, 0, sizeof(*res));
     res->status = r.status;
+    res->kernel = r.kernel;
     res->out_dev = (r.status == PTG_OK) ? s->arena_mem + r.arena_off : nullptr;
     res->bytes = r.bytes;
     res->user_tag = r.req.user_tag;

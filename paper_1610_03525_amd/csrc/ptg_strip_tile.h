@@ -1,0 +1,500 @@
+// ptg_strip_tile.h -- K3 for 2D dyadic octave ladders (base frequency 2^-k, lacunarity 2),
+// plain FP32 form on the vector ALUs: the per-strip device code, shared by the dense
+// kernel (ptg_fbm_strip.hip) and the persistent serving kernel (ptg_serve.hip).
+//
+// With f_o = 2^-s the sample-centre fraction is exact: t = (2 (X mod 2^s) + 1) / 2^(s+1).
+// One wave owns a world-aligned strip of kStripW x kStripH (64 x 64) samples, lane = column,
+// and walks strips with a grid stride; the waves of a workgroup never synchronise after the
+// prologue.
+//
+// Cell polynomial (Sec. 2, Sec. 3.4), fixed column x: the 1D Hermite form in y
+//   h(y) = E0 + (E1 - E0) S(t) + Q0 b10(t) + Q1 b11(t),
+//   E_cy = gx(cx, cy) b10(tx) + gx(cx+1, cy) b11(tx),  Q_cy = gy(cx, cy) + S(tx) (gy(cx+1, cy) - gy(cx, cy)).
+// Octaves are summed in three ways:
+//  * period >= 64: a lane's column meets one cell of the octave over the whole strip, so
+//    each such octave's column form is re-expanded in the strip's centred row coordinate
+//    v = (2 r - 63) / 128 (t - 1/2 = tau + sigma v, sigma = 64 / P) and all of them are added
+//    into ONE polynomial of degree 2M+1 per lane;
+//  * periods 32 and 16 (and 8 for cubic cells): the same, once per half / quarter /
+//    period-8 cell, after the fused polynomial is re-centred there (a piece is never
+//    evaluated away from its own cell: FP32 error of a quintic piece expanded about the
+//    strip centre would reach 4e-5 of the total amplitude); rows are evaluated in pairs
+//    symmetric about the segment centre from the polynomial's even and odd parts;
+//  * the finer periods: each node row is collapsed along x once (adjacent cells share it)
+//    and evaluated per row with the row bases as constants (the row's position inside its
+//    cell is fixed by the unrolled row loop); which of these periods occur is a template
+//    parameter (the finest shift LO), so the row loop carries no per-row tests.
+// x-weights of the periods <= 64 depend on the lane only and are formed once per wave; the
+// octave amplitude is folded into them.  Octaves accumulate in FP32; each sample is stored
+// once.
+//
+// Per strip the wave first hashes its own footprint nodes into a private LDS block (K1
+// logic: one key per node column and row, one fmix32 per node, unit gradients); the work
+// lists that map lanes to nodes are the same for every strip and are built once per
+// workgroup.
+#pragma once
+
+#include <hip/hip_fp16.h>
+
+#include "ptg_device.h"
+#include "ptg_launch.h"
+
+namespace ptg {
+
+template <typename T>
+__device__ __forceinline__ T st_out(float v);
+template <>
+__device__ __forceinline__ float st_out<float>(float v)
+{
+    return v;
+}
+template <>
+__device__ __forceinline__ __half st_out<__half>(float v)
+{
+    return __float2half_rn(v);
+}
+
+struct XB {  // 1D bases of a column fraction: S, b10, b11
+    float s, b10, b11;
+};
+
+template <int M>
+__device__ __forceinline__ XB xbases(float t)
+{
+    XB r;
+    Basis<M>::eval(t, r.s, r.b10, r.b11);
+    return r;
+}
+
+// A lane's x-weights of one octave with the octave amplitude folded in: the value term of a
+// node row is gx0 e0 + gx1 e1 (e = amp b1), its y-slope term gy0 q0 + gy1 q1 (q = amp b0).
+struct XA {
+    float q0, q1, e0, e1;
+};
+
+template <int M>
+__device__ __forceinline__ XA xweights(float t, float amp)
+{
+    const XB b = xbases<M>(t);
+    return XA{amp * (1.0f - b.s), amp * b.s, amp * b.b10, amp * b.b11};
+}
+
+// Row bases at the fraction (j + 1/2) / P: constant once the row loop is unrolled.
+template <int M>
+__host__ __device__ constexpr XB row_bases(int j, int P)
+{
+    const float t = (float)(2 * j + 1) / (float)(2 * P);
+    const float t2 = t * t;
+    const float u = 1.0f - t;
+    if (M == 1) return XB{t2 * (3.0f - 2.0f * t), t * u * u, -t2 * u};
+    const float t3 = t2 * t;
+    return XB{t3 * (10.0f + t * (-15.0f + 6.0f * t)), t + t3 * (-6.0f + t * (8.0f - 3.0f * t)),
+              t3 * (-4.0f + t * (7.0f - 3.0f * t))};
+}
+
+struct CF {  // column form of one cell at one column
+    float E0, dE, Q0, Q1;
+};
+
+// nb -> node (cx, cy) of the cell; (cx, cy + 1) follows, column cx + 1 is nny further.
+__device__ __forceinline__ CF column_form(const float2 *nb, int nny, const XA &xa)
+{
+    const float2 n00 = nb[0], n01 = nb[1], n10 = nb[nny], n11 = nb[nny + 1];
+    CF c;
+    c.E0 = n00.x * xa.e0 + n10.x * xa.e1;
+    const float E1 = n01.x * xa.e0 + n11.x * xa.e1;
+    c.dE = E1 - c.E0;
+    c.Q0 = n00.y * xa.q0 + n10.y * xa.q1;
+    c.Q1 = n01.y * xa.q0 + n11.y * xa.q1;
+    return c;
+}
+
+// c(v) -> c(d + w) as a polynomial in w (repeated synthetic division).
+template <int M>
+__device__ __forceinline__ void taylor_shift(float (&c)[2 * M + 2], float d)
+{
+    constexpr int D = 2 * M + 1;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = D - 1; j >= i; --j) c[j] += d * c[j + 1];
+}
+
+// Add the column form, as a polynomial in v with t - 1/2 = tau + sigma v, to C.
+// Powers of u = t - 1/2 of the bases (exact binary fractions):
+//   cubic:   S = 1/2 + 3/2 u - 2 u^3,  b10 = 1/8 - 1/4 u - 1/2 u^2 + u^3,  b11 = -1/8 - 1/4 u + 1/2 u^2 + u^3
+//   quintic: S = 1/2 + 15/8 u - 5 u^3 + 6 u^5,
+//            b10 = 5/32 - 7/16 u - 3/4 u^2 + 5/2 u^3 + 1/2 u^4 - 3 u^5,
+//            b11 = -5/32 - 7/16 u + 3/4 u^2 + 5/2 u^3 - 1/2 u^4 - 3 u^5
+template <int M, bool SHIFT = true>
+__device__ __forceinline__ void add_mapped(float (&C)[2 * M + 2], const CF &c, float tau, float sigma)
+{
+    constexpr int D = 2 * M + 1;
+    const float Dq = c.Q0 - c.Q1, Sq = c.Q0 + c.Q1;
+    float m[D + 1];
+    if (M == 1) {
+        m[0] = c.E0 + 0.5f * c.dE + 0.125f * Dq;
+        m[1] = 1.5f * c.dE - 0.25f * Sq;
+        m[2] = -0.5f * Dq;
+        m[3] = Sq - 2.0f * c.dE;
+    } else {
+        m[0] = c.E0 + 0.5f * c.dE + 0.15625f * Dq;
+        m[1] = 1.875f * c.dE - 0.4375f * Sq;
+        m[2] = -0.75f * Dq;
+        m[3] = 2.5f * Sq - 5.0f * c.dE;
+        m[4] = 0.5f * Dq;
+        m[D] = 6.0f * c.dE - 3.0f * Sq;
+    }
+    // Taylor shift to u = tau (repeated synthetic division), then scale u - tau = sigma v
+    if (SHIFT) {
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = D - 1; j >= i; --j) m[j] += tau * m[j + 1];
+    }
+    float sp = 1.0f;  // sigma is a power of two: exact powers
+#pragma unroll
+    for (int b = 0; b <= D; ++b) {
+        C[b] += m[b] * sp;
+        sp *= sigma;
+    }
+}
+
+// An octave of fixed period P <= 64: the lane's node column (strips are 64-aligned, so the
+// column index is lane >> s and a column holds 64 / P + 1 node rows) and its x-bases.
+struct Fixed {
+    const float2 *col;
+    XA xa;
+};
+
+struct RowCtx {
+    Fixed f32, f16, f8, f4, f2, f1;
+    int64_t pitch;
+};
+
+// A node row collapsed along x at the lane's column: value term E and y-slope term Q.  The
+// cell between node rows lo and hi has the column form E0 = lo.E, dE = hi.E - lo.E,
+// Q0 = lo.Q, Q1 = hi.Q, and adjacent cells share their common node row.
+struct NR {
+    float E, Q;
+};
+
+template <int NNY>
+__device__ __forceinline__ NR node_row(const Fixed &f, int j)
+{
+    const float2 a = f.col[j], b = f.col[j + NNY];
+    return NR{a.x * f.xa.e0 + b.x * f.xa.e1, a.y * f.xa.q0 + b.y * f.xa.q1};
+}
+
+// Add the cell between node rows lo and hi, as a polynomial in the segment coordinate w
+// (t - 1/2 = SIG w: the cell is centred on the segment), to C.  The constants are the
+// centred power coefficients of the bases listed at add_mapped, times SIG^b.
+template <int M, int SIG>
+__device__ __forceinline__ void add_piece(float (&C)[2 * M + 2], const NR &lo, const NR &hi)
+{
+    constexpr float s1 = (float)SIG, s2 = s1 * s1, s3 = s2 * s1, s4 = s3 * s1, s5 = s4 * s1;
+    const float dE = hi.E - lo.E, Sq = lo.Q + hi.Q, Dq = lo.Q - hi.Q;
+    C[0] += lo.E;
+    C[0] = __builtin_fmaf(dE, 0.5f, C[0]);
+    if (M == 1) {
+        C[0] = __builtin_fmaf(Dq, 0.125f, C[0]);
+        C[1] = __builtin_fmaf(dE, 1.5f * s1, C[1]);
+        C[1] = __builtin_fmaf(Sq, -0.25f * s1, C[1]);
+        C[2] = __builtin_fmaf(Dq, -0.5f * s2, C[2]);
+        C[3] = __builtin_fmaf(Sq, s3, C[3]);
+        C[3] = __builtin_fmaf(dE, -2.0f * s3, C[3]);
+    } else {
+        C[0] = __builtin_fmaf(Dq, 0.15625f, C[0]);
+        C[1] = __builtin_fmaf(dE, 1.875f * s1, C[1]);
+        C[1] = __builtin_fmaf(Sq, -0.4375f * s1, C[1]);
+        C[2] = __builtin_fmaf(Dq, -0.75f * s2, C[2]);
+        C[3] = __builtin_fmaf(Sq, 2.5f * s3, C[3]);
+        C[3] = __builtin_fmaf(dE, -5.0f * s3, C[3]);
+        C[4] = __builtin_fmaf(Dq, 0.5f * s4, C[4]);
+        C[5] = __builtin_fmaf(dE, 6.0f * s5, C[5]);
+        C[5] = __builtin_fmaf(Sq, -3.0f * s5, C[5]);
+    }
+}
+
+// val += dE S + Q0 b10 + Q1 b11 at one row (E0 is in the constant term), as an FMA chain.
+__device__ __forceinline__ float add_direct(float val, const NR &lo, const NR &hi, const XB &rb)
+{
+    val = __builtin_fmaf(hi.E - lo.E, rb.s, val);
+    val = __builtin_fmaf(lo.Q, rb.b10, val);
+    return __builtin_fmaf(hi.Q, rb.b11, val);
+}
+
+// Node rows [r0 / P, (r0 + R) / P] of a direct octave over a segment; the first one is
+// carried from the previous segment and the last one is carried to the next.
+template <int P, int R>
+struct SegRows {
+    NR n[R / P + 1];
+    __device__ __forceinline__ void load(const Fixed &f, int r0, NR &carry)
+    {
+        n[0] = carry;
+#pragma unroll
+        for (int j = 1; j <= R / P; ++j) n[j] = node_row<64 / P + 1>(f, r0 / P + j);
+        carry = n[R / P];
+    }
+};
+
+// The R rows [r0, r0 + R) of a strip, given the polynomial Cs of everything coarser than the
+// direct octaves, centred on the segment (row k at w = (2 k - R + 1) / 128).  Rows are taken
+// in pairs symmetric about the centre, w and -w, from the even and odd parts of Cs; the
+// direct octaves' E0 terms go into each row's constant term, the rest is 3 FMA per octave.
+template <int M, typename OutT, int R, bool D8, bool D4, bool D2, bool D1, bool FULL>
+__device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[2 * M + 2], int r0, NR (&carry)[4],
+                                             OutT *rp, int lane, int rlo, int rhi, bool lane_ok)
+{
+    SegRows<8, R> s8;
+    SegRows<4, R> s4;
+    SegRows<2, R> s2;
+    SegRows<1, R> s1;
+    if (D8) s8.load(x.f8, r0, carry[0]);
+    if (D4) s4.load(x.f4, r0, carry[1]);
+    if (D2) s2.load(x.f2, r0, carry[2]);
+    if (D1) s1.load(x.f1, r0, carry[3]);
+    // row pointers walk outwards from the centre pair (uniform, one add each per pair)
+    OutT *pa = rp + (int64_t)(r0 + R / 2 - 1) * x.pitch, *pb = pa + x.pitch;
+#pragma unroll
+    for (int p = 0; p < R / 2; ++p) {
+        const int rb = R / 2 + p;
+        const float w = (float)(2 * rb - R + 1) * (1.0f / 128.0f);
+        const float w2 = w * w;
+        float odd, even2 = 0.0f;
+        if (M == 1) {
+            odd = __builtin_fmaf(Cs[3], w2, Cs[1]);
+        } else {
+            odd = __builtin_fmaf(__builtin_fmaf(Cs[5], w2, Cs[3]), w2, Cs[1]);
+            even2 = __builtin_fmaf(Cs[4], w2, Cs[2]);
+        }
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int k = side ? rb : R / 2 - 1 - p;  // row in the segment
+            const int row = r0 + k;                   // row in the strip
+            float c0 = Cs[0];
+            if (D8) c0 += s8.n[k / 8].E;
+            if (D4) c0 += s4.n[k / 4].E;
+            if (D2) c0 += s2.n[k / 2].E;
+            if (D1) c0 += s1.n[k].E;
+            float val = __builtin_fmaf(M == 1 ? Cs[2] : even2, w2, c0);
+            val = __builtin_fmaf(side ? w : -w, odd, val);
+            if (D8) val = add_direct(val, s8.n[k / 8], s8.n[k / 8 + 1], row_bases<M>(row & 7, 8));
+            if (D4) val = add_direct(val, s4.n[k / 4], s4.n[k / 4 + 1], row_bases<M>(row & 3, 4));
+            if (D2) val = add_direct(val, s2.n[k / 2], s2.n[k / 2 + 1], row_bases<M>(row & 1, 2));
+            if (D1) val = add_direct(val, s1.n[k], s1.n[k + 1], row_bases<M>(0, 1));
+            OutT *const rrow = side ? pb : pa;
+            if (FULL || (row >= rlo && row < rhi && lane_ok)) rrow[lane] = st_out<OutT>(val);
+        }
+        pa -= x.pitch;
+        pb += x.pitch;
+        // keep each pair's stores next to its arithmetic: without this the scheduler hoists
+        // most of a strip's row arithmetic ahead of the first store and then issues the
+        // stores in one burst, with the values held in registers
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// The rows of a strip.  The fused polynomial C (in the strip coordinate v) is re-centred
+// on each half strip, where the period-32 piece is added (t - 1/2 = 2 w), and again on each
+// quarter, where the period-16 piece is added (t - 1/2 = 4 w).  For cubic cells the same is
+// done once more per period-8 cell (t - 1/2 = 8 w), where re-centring (6 FMA) and the piece
+// cost less than evaluating the octave on its own at every row; for quintic cells (15 FMA
+// per re-centring) period 8 stays a direct octave.  No piece is evaluated away from its own
+// cell.  FULL = every sample of the strip is stored.
+template <int M, typename OutT, int LO, bool FULL>
+__device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 * M + 2], OutT *rp, int lane, int rlo,
+                                           int rhi, bool lane_ok)
+{
+    constexpr int D1 = 2 * M + 2;
+    constexpr bool H32 = LO <= 5, H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
+    constexpr bool PIECE8 = H8 && M == 1;
+    NR carry[4];  // bottom node rows of the next segment: periods 8, 4, 2, 1
+    if (H8) carry[0] = node_row<9>(x.f8, 0);
+    if (H4) carry[1] = node_row<17>(x.f4, 0);
+    if (H2) carry[2] = node_row<33>(x.f2, 0);
+    if (H1) carry[3] = node_row<65>(x.f1, 0);
+    NR n32[3], n16lo;
+    if (H32) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) n32[j] = node_row<3>(x.f32, j);
+    }
+    if (H16) n16lo = node_row<5>(x.f16, 0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        float Ch[D1];
+#pragma unroll
+        for (int b = 0; b < D1; ++b) Ch[b] = C[b];
+        taylor_shift<M>(Ch, (float)(2 * h - 1) * 0.25f);  // half centre v = -1/4, +1/4
+        if (H32) add_piece<M, 2>(Ch, n32[h], n32[h + 1]);
+#pragma unroll
+        for (int qh = 0; qh < 2; ++qh) {
+            const int q = 2 * h + qh;
+            float Cq[D1];
+#pragma unroll
+            for (int b = 0; b < D1; ++b) Cq[b] = Ch[b];
+            taylor_shift<M>(Cq, (float)(2 * qh - 1) * 0.125f);  // quarter centre, from the half's
+            if (H16) {
+                const NR hi = node_row<5>(x.f16, q + 1);
+                add_piece<M, 4>(Cq, n16lo, hi);
+                n16lo = hi;
+            }
+            if (PIECE8) {
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    float Ce[D1];
+#pragma unroll
+                    for (int b = 0; b < D1; ++b) Ce[b] = Cq[b];
+                    taylor_shift<M>(Ce, (float)(2 * e - 1) * 0.0625f);  // period-8 cell centre
+                    const NR lo = carry[0], hi = node_row<9>(x.f8, 2 * q + e + 1);
+                    add_piece<M, 8>(Ce, lo, hi);
+                    carry[0] = hi;
+                    segment_rows<M, OutT, 8, false, H4, H2, H1, FULL>(x, Ce, 16 * q + 8 * e, carry, rp, lane, rlo, rhi,
+                                                                       lane_ok);
+                }
+            } else {
+                segment_rows<M, OutT, 16, H8, H4, H2, H1, FULL>(x, Cq, 16 * q, carry, rp, lane, rlo, rhi, lane_ok);
+            }
+        }
+    }
+}
+
+
+// Per-octave constants a workgroup stages in LDS once (the strip code reads them from there).
+struct StripShared {
+    uint32_t pre_key[kMaxOctaves];
+    int shift[kMaxOctaves], noff[kMaxOctaves];
+    float amp[kMaxOctaves], inv2p[kMaxOctaves];
+};
+
+// Once per workgroup (every thread, a barrier after it): the work lists that map lanes to
+// keys and nodes (the same for every strip of a field) and the per-octave constants.
+__device__ __forceinline__ void strip_prologue(const Fbm2dStripArgs &a, StripShared &sh, uint32_t *wl_key,
+                                               uint32_t *wl_node, int tid, int nthreads)
+{
+    const int N = a.octaves;
+    for (int o = 0; o < N; ++o) {
+        const int nnx = a.nnx[o], nny = a.nny[o], kx = a.kxoff[o], ky = a.kyoff[o], no = a.noff[o];
+        for (int i = tid; i < nnx + nny; i += nthreads) {
+            if (i < nnx)
+                wl_key[kx + i] = ((uint32_t)o << 24) | (uint32_t)i;
+            else
+                wl_key[ky + i - nnx] = ((uint32_t)o << 24) | (uint32_t)(i - nnx);
+        }
+        for (int q = tid; q < nnx * nny; q += nthreads) {  // byte offsets of the node's two keys
+            const int i = q / nny, j = q - i * nny;          // column-major
+            wl_node[no + q] = ((uint32_t)(ky + j) << 18) | ((uint32_t)(kx + i) << 2);
+        }
+    }
+    if (tid < N) {
+        sh.pre_key[tid] = key_prefix(a.seed, tid);
+        sh.shift[tid] = a.shift[tid];
+        sh.noff[tid] = a.noff[tid];
+        sh.amp[tid] = a.amp[tid];
+        sh.inv2p[tid] = a.inv2p[tid];
+    }
+}
+
+// One wave's strips of a field: the lane's x-weights of the fixed-period octaves (formed
+// once) and the strip column whose keys its LDS block holds.
+template <int M, typename OutT, int LO>
+struct StripWave {
+    static constexpr int D1 = 2 * M + 2;
+    static constexpr bool H32 = LO <= 5, H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
+    float2 *nodes;
+    uint32_t *keys;
+    int lane;
+    Fixed f64;
+    RowCtx rc0;
+    // the column keys stay valid while the wave's strips share a strip column (the stride
+    // over strips is often a multiple of the strips per row)
+    int64_t keyed_bsx = -1;
+
+    __device__ __forceinline__ Fixed fixed(const StripShared &sh, int o) const
+    {
+        Fixed f{nodes, XA{0.0f, 0.0f, 0.0f, 0.0f}};
+        if (o >= 0) {
+            const int s = sh.shift[o];
+            f.col = nodes + sh.noff[o] + (lane >> s) * ((kStripH >> s) + 1);
+            f.xa = xweights<M>((float)(2 * (lane & ((1 << s) - 1)) + 1) * sh.inv2p[o], sh.amp[o]);
+        }
+        return f;
+    }
+
+    __device__ __forceinline__ StripWave(const Fbm2dStripArgs &a, const StripShared &sh, float2 *nodes_, int lane_)
+        : nodes(nodes_), keys(reinterpret_cast<uint32_t *>(nodes_ + a.nodes_total)), lane(lane_)
+    {
+        f64 = fixed(sh, a.o64);
+        rc0 = RowCtx{fixed(sh, H32 ? a.o32 : -1), fixed(sh, H16 ? a.o16 : -1), fixed(sh, H8 ? a.o8 : -1),
+                     fixed(sh, H4 ? a.o4 : -1),   fixed(sh, H2 ? a.o2 : -1),   fixed(sh, H1 ? a.o1 : -1),
+                     a.pitch};
+    }
+
+    // Strip st of the field: hash its footprint, sum its coarse octaves, write its rows.
+    __device__ __forceinline__ void run(const Fbm2dStripArgs &a, const StripShared &sh, const uint32_t *wl_key,
+                                        const uint32_t *wl_node, int64_t st)
+    {
+        const int nodes_total = a.nodes_total, keys_total = a.keys_total, keys_col = a.keys_col;
+        const int64_t bsy = st / a.strips_x, bsx = st - bsy * a.strips_x;
+        const int64_t X0 = a.sx_base + bsx * kStripW, Y0 = a.sy_base + bsy * kStripH;
+
+        // ---- hashing: column keys (x salt), row keys (octave prefix), then node gradients
+        // (unit vectors: the amplitude is in the lanes' x-weights) -------------------------
+        if (bsx != keyed_bsx) {
+            for (int q = lane; q < keys_col; q += 64) {
+                const uint32_t it = wl_key[q];
+                keys[q] = key_xline((X0 >> sh.shift[it >> 24]) + (int64_t)(it & 0xFFFFFF));
+            }
+            keyed_bsx = bsx;
+        }
+        for (int q = keys_col + lane; q < keys_total; q += 64) {
+            const uint32_t it = wl_key[q];
+            const int o = it >> 24;
+            keys[q] = absorb_index(sh.pre_key[o], (Y0 >> sh.shift[o]) + (int64_t)(it & 0xFFFFFF));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const char *key_bytes = reinterpret_cast<const char *>(keys);
+        for (int q = lane; q < nodes_total; q += 64) {
+            const uint32_t it = wl_node[q];
+            const uint32_t krow = *reinterpret_cast<const uint32_t *>(key_bytes + (it >> 16));
+            const uint32_t kcol = *reinterpret_cast<const uint32_t *>(key_bytes + (it & 0xFFFFu));
+            nodes[q] = grad2(key_combine(krow, kcol));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        // ---- octaves of period >= 64: one polynomial in v per lane ------------------------
+        float C[D1];
+#pragma unroll
+        for (int b = 0; b < D1; ++b) C[b] = 0.0f;
+        for (int o = 0; o < a.n_generic; ++o) {  // period >= 128: the strip is inside one cell
+            const int s = sh.shift[o];
+            const uint32_t mask = (1u << s) - 1u;
+            const float inv2p = sh.inv2p[o];
+            const XA xa = xweights<M>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p, sh.amp[o]);
+            const CF c = column_form(nodes + sh.noff[o], 2, xa);
+            const float invp = 2.0f * inv2p;
+            const float tau = (float)(((uint32_t)Y0 & mask) + (uint32_t)(kStripH / 2)) * invp - 0.5f;
+            add_mapped<M>(C, c, tau, (float)kStripH * invp);
+        }
+        if (a.o64 >= 0) add_piece<M, 1>(C, node_row<2>(f64, 0), node_row<2>(f64, 1));  // t - 1/2 = v
+
+        // ---- rows: one store per row of the wave; interior strips take the unmasked path --
+        const int64_t xe = a.x0 + a.nx, ye = a.y0 + a.ny;
+        const int rlo = (int)max<int64_t>(0, min<int64_t>(kStripH, a.y0 - Y0));
+        const int rhi = (int)max<int64_t>(0, min<int64_t>(kStripH, ye - Y0));
+        const int clo = (int)max<int64_t>(0, min<int64_t>(kStripW, a.x0 - X0));
+        const int chi = (int)max<int64_t>(0, min<int64_t>(kStripW, xe - X0));
+        OutT *row0 = reinterpret_cast<OutT *>(a.out) + (Y0 - a.y0) * a.pitch + (X0 - a.x0);
+        if (rlo == 0 && rhi == kStripH && clo == 0 && chi == kStripW)
+            strip_rows<M, OutT, LO, true>(rc0, C, row0, lane, 0, kStripH, false);
+        else
+            strip_rows<M, OutT, LO, false>(rc0, C, row0, lane, rlo, rhi, lane >= clo && lane < chi);
+        __builtin_amdgcn_wave_barrier();  // the next strip rewrites this wave's keys and nodes
+    }
+};
+
+}  // namespace ptg

@@ -96,13 +96,14 @@ def test_tune_3d_and_untunable_classes():
 
 
 def _served_equals_solo(srv):
-    reqs = [dict(smoothness=m, octaves=o, base_freq=2.0 ** -12, seed=s, origin=(x, y, 0), extent=(nx, ny, 1))
+    # non-dyadic ladders: the server computes them as general tiles of the tuned height
+    reqs = [dict(smoothness=m, octaves=o, base_freq=3e-4, seed=s, origin=(x, y, 0), extent=(nx, ny, 1))
             for m, o, s, x, y, nx, ny in [(1, 9, 5, -1000, 2 ** 40, 200, 130), (2, 12, 6, 77, -3, 64, 17),
                                           (1, 4, 7, 2 ** 45, 5, 130, 300), (2, 6, 8, 0, 0, 16, 16)]]
     tickets = srv.submit([ptg.tile_req(dim=2, **r) for r in reqs])
     for t, r in zip(tickets, reqs):
         res = srv.wait(t, int(60e9))
-        assert res.status == ptg.PTG_OK
+        assert res.status == ptg.PTG_OK and res.kernel == ptg.PTG_TUNE_GENERAL_2D
         nx, ny, _ = r["extent"]
         got = torch.empty((ny, nx), dtype=torch.float32, device=DEV)
         ptg.device_copy(got.data_ptr(), res.out_dev, res.bytes)

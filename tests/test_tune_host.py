@@ -79,9 +79,17 @@ def test_server_cfg_tile_settings_validation():
 
 
 def test_server_tile_height_sets_the_tile_count():
-    """A 2D request of 128 x 100 samples is 2 x 2 tiles of 64 x 64, or 2 x 7 of 64 x 16."""
+    """A non-dyadic 2D request of 128 x 100 samples is 2 x 2 general tiles of 64 x 64, or
+    2 x 7 of 64 x 16; a dyadic one is world-aligned 64 x 64 strips (3 x 3 at this origin)
+    whatever the tile height, computed by the strip code."""
     for th, tiles in ((64, 4), (32, 8), (16, 14)):
         with ptg.Server(1 << 22, executor=ptg.PTG_EXEC_HOST, fake_tile_ns=1000, tile_h=th) as s:
-            (t,) = s.submit([ptg.tile_req(dim=2, extent=(128, 100, 1), octaves=4, base_freq=2.0 ** -12)])
-            s.wait(t, 10_000_000_000)
-            assert s.stats()["tiles_done"] == tiles
+            (t,) = s.submit([ptg.tile_req(dim=2, extent=(128, 100, 1), octaves=4, base_freq=3e-4)])
+            res = s.wait(t, 10_000_000_000)
+            assert s.stats()["tiles_done"] == tiles and res.kernel == ptg.PTG_TUNE_GENERAL_2D
+            (t,) = s.submit([ptg.tile_req(dim=2, origin=(-7, 30, 0), extent=(128, 100, 1), octaves=4,
+                                          base_freq=2.0 ** -12)])
+            res = s.wait(t, 10_000_000_000)
+            assert s.stats()["tiles_done"] == tiles + 9 and res.kernel == ptg.PTG_TUNE_STRIP_2D
+            (t,) = s.submit([ptg.tile_req(dim=3, extent=(64, 8, 8), octaves=4, base_freq=2.0 ** -12)])
+            assert s.wait(t, 10_000_000_000).kernel == ptg.PTG_TUNE_GENERAL_3D
