@@ -234,9 +234,11 @@ PTG_API void ptg_tune_reset(void);
  * while earlier requests are still running.  A 2D request whose ladder is dyadic (base_freq
  * 2^-k, lacunarity 2, finest period >= 2) and whose 64 x 64 strip footprint fits a serving
  * workgroup runs as strips, one per wave, with the same device code as ptg_fbm_2d with
- * PTG_PATH_DYADIC; every other request runs as 64 x tile_h (2D) or 64 x 8 x 8 (3D) sample
- * tiles with the device code of PTG_PATH_GENERAL.  A served tile equals the corresponding
- * stand-alone call bit for bit (ptg_tile_result.kernel says which). */
+ * PTG_PATH_DYADIC; a 3D request with a dyadic ladder of finest period >= 8 runs as 64 x 8 x 4
+ * blocks with the device code of ptg_fbm_3d with PTG_PATH_DYADIC; every other request runs
+ * as 64 x tile_h (2D) or 64 x 8 x 8 (3D) sample tiles with the device code of
+ * PTG_PATH_GENERAL.  A served tile equals the corresponding stand-alone call bit for bit
+ * (ptg_tile_result.kernel says which). */
 
 typedef struct ptg_server ptg_server;
 
@@ -253,7 +255,8 @@ typedef struct ptg_server_cfg {
     int32_t executor;         /* PTG_EXEC_GPU or PTG_EXEC_HOST                              */
     int64_t fake_tile_ns;     /* PTG_EXEC_HOST only: simulated time per tile                */
     int32_t tiles_per_item;   /* sample tiles per work item, 1..16 (strip requests: 4 strips */
-                              /* per tile, one per wave); 0 = from each request's size      */
+                              /* or 3D blocks per tile, one per wave); 0 = from each        */
+                              /* request's size                                              */
                               /* (enough items for every workgroup, at most 16 tiles)       */
     int32_t autotune;         /* 1: at creation (PTG_EXEC_GPU) time the 2D tile heights on  */
                               /* a 512 x 512, 8-octave field per cell order (ptg_tune_2d,   */
@@ -272,9 +275,10 @@ typedef struct ptg_tile_req {
 
 typedef struct ptg_tile_result {
     int32_t status;           /* PTG_OK, PTG_ESHUTDOWN or PTG_EHIP                          */
-    int32_t kernel;           /* code that computed it: PTG_TUNE_STRIP_2D (the dyadic strip */
-                              /* code; equals ptg_fbm_2d with PTG_PATH_DYADIC bit for bit),  */
-                              /* PTG_TUNE_GENERAL_2D / _3D (equals PTG_PATH_GENERAL)          */
+    int32_t kernel;           /* code that computed it: PTG_TUNE_STRIP_2D / _STRIP_3D (the  */
+                              /* dyadic strip code; equals ptg_fbm_2d / _3d with            */
+                              /* PTG_PATH_DYADIC bit for bit), PTG_TUNE_GENERAL_2D / _3D     */
+                              /* (equals PTG_PATH_GENERAL)                                   */
     void *out_dev;            /* the tile, dense row-major FP32 [nz][ny][nx], valid until   */
                               /* ptg_tile_release (device memory; host memory for           */
                               /* PTG_EXEC_HOST)                                              */
@@ -309,7 +313,7 @@ PTG_API int ptg_tile_release(ptg_server *s, uint64_t ticket);
 
 typedef struct ptg_server_stats {
     int64_t submitted, admitted, completed, released;
-    int64_t tiles_done;       /* sample tiles (or 64 x 64 strips) finished                  */
+    int64_t tiles_done;       /* sample tiles (or strips / 3D blocks) finished              */
     int64_t pending, in_flight;
     int64_t bytes_in_use, bytes_peak, budget;
     int64_t kernel_launches;  /* persistent-kernel launches (it exits after idling)         */

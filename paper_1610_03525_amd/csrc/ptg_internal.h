@@ -30,6 +30,11 @@ bool dyadic_shift(const ptg_params *p, int *k_out);
 int strip_args_2d(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out,
                   int64_t pitch, Fbm2dStripArgs *a);
 
+// Kernel arguments of the 3D strip kernel for a dyadic volume; returns 1 when it does not
+// apply (a ladder starting below period 4, too many keys).
+int strip3_args(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz,
+                void *out, Fbm3dStripArgs *a);
+
 // ---- tile-shape tuning (a6) -----------------------------------------------------
 // A launch class: which kernel a call runs (PTG_TUNE_*), its cell order, output type,
 // size class (ceil log2 of the samples) and ladder class (finest period, log2, capped).

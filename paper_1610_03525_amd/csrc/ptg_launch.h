@@ -140,6 +140,17 @@ __host__ __device__ inline int strip_wave_words(int nodes_total, int keys_total)
     return (2 * nodes_total + keys_total + 3) & ~3;
 }
 
+// LDS words of the 3D strip kernel's basis table and work lists (shared) and of one wave's
+// node block (gx, gy, gz, then keys).
+__host__ __device__ inline int strip3_shared_words(int tab_total, int nodes_total, int keys_total)
+{
+    return 4 * tab_total + ((keys_total + nodes_total + 3) & ~3);
+}
+__host__ __device__ inline int strip3_wave_words(int nodes_total, int keys_total)
+{
+    return (3 * nodes_total + keys_total + 3) & ~3;
+}
+
 hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, bool f16, int grid, int waves, size_t lds_bytes,
                               hipStream_t s);
 int strip_wgs_per_cu(int smooth, bool f16, int lo, int waves, size_t lds_bytes);  // resident workgroups per CU

@@ -260,13 +260,12 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d launch");
 }
 
-// Plain FP32 dyadic volume through the 3D strip kernel; returns 1 when it does not apply
-// (a ladder starting below period 4, or a node block larger than LDS): the caller falls back.
-static int fbm3d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny,
-                       int64_t nz, void *out, hipStream_t s)
+int strip3_args(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz,
+                void *out, Fbm3dStripArgs *ap)
 {
     constexpr int BX = k3BlockX, BY = k3BlockY, BZ = k3BlockZ;
-    Fbm3dStripArgs a{};
+    Fbm3dStripArgs &a = *ap;
+    a = Fbm3dStripArgs{};
     a.x0 = x0;
     a.y0 = y0;
     a.z0 = z0;
@@ -321,8 +320,18 @@ static int fbm3d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
     a.keys_total = keys;
     a.tab_total = tab;
     if (keys >= (1 << 14)) return 1;
-    const size_t shared_words = (size_t)4 * tab + (size_t)((keys + nodes + 3) & ~3);
-    const size_t wave_words = (size_t)((3 * nodes + keys + 3) & ~3);
+    return 0;
+}
+
+// Plain FP32 dyadic volume through the 3D strip kernel; returns 1 when it does not apply
+// (a ladder starting below period 4, or a node block larger than LDS): the caller falls back.
+static int fbm3d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny,
+                       int64_t nz, void *out, hipStream_t s)
+{
+    Fbm3dStripArgs a;
+    if (strip3_args(p, k, x0, y0, z0, nx, ny, nz, out, &a)) return 1;
+    const size_t shared_words = (size_t)strip3_shared_words(a.tab_total, a.nodes_total, a.keys_total);
+    const size_t wave_words = (size_t)strip3_wave_words(a.nodes_total, a.keys_total);
     int waves = tune_pick(TuneKey{PTG_TUNE_STRIP_3D, p->smoothness, p->out_dtype == PTG_F16,
                                   size_class(nx * ny * nz), a.lo},
                           4);

@@ -42,6 +42,7 @@
 
 #include "ptg_general_tile.h"
 #include "ptg_internal.h"
+#include "ptg_strip3_tile.h"
 #include "ptg_strip_tile.h"
 
 namespace ptg {
@@ -55,18 +56,22 @@ constexpr int64_t kStarveNs = 50000000;    // after 50 ms a waiting request bloc
 constexpr int kServeWaves = 4;             // waves of a serving workgroup (256 threads)
 // a strip request's LDS: [StripShared | key and node work lists | one node block per wave]
 constexpr int kStripSharedWords = (int)((sizeof(StripShared) + 15) / 16 * 4);
+// a 3D strip request's: [Strip3Shared | basis table, key and node work lists | per-wave blocks]
+constexpr int kStrip3SharedWords = (int)((sizeof(Strip3Shared) + 15) / 16 * 4);
 
 struct ServeReqDesc {
     int32_t dim, smooth, slot;
     uint32_t seq;
     uint64_t target;  // done_tiles[slot] when this request is complete
     int64_t ntiles;
-    int32_t kernel;   // PTG_TUNE_GENERAL_2D / _GENERAL_3D (tiles) or PTG_TUNE_STRIP_2D (64 x 64 strips)
+    int32_t kernel;   // PTG_TUNE_GENERAL_2D / _GENERAL_3D (tiles), PTG_TUNE_STRIP_2D (64 x 64 strips),
+                      // PTG_TUNE_STRIP_3D (64 x 8 x 4 blocks)
     int32_t pad;
     union {
         Fbm2dArgs a2;
         Fbm3dArgs a3;
         Fbm2dStripArgs as;
+        Fbm3dStripArgs a3s;
     };
 };
 static_assert(sizeof(ServeReqDesc) % 8 == 0, "descriptor is copied in 8-byte words");
@@ -129,6 +134,21 @@ __device__ __forceinline__ void serve_strips_lo(const Fbm2dStripArgs &a, const S
     default: serve_strips<M, 6>(a, sh, wl, t0, t1, tid); break;
     }
 }
+
+// Blocks [t0, t1) of a dyadic 3D request, wave w taking t0 + w, t0 + w + 4, ... (the dense
+// 3D strip kernel's per-block code).
+template <int M, int LO>
+__device__ __forceinline__ void serve_blocks(const Fbm3dStripArgs &a, const Strip3Shared &sh, float4 *tab, int64_t t0,
+                                             int64_t t1, int tid)
+{
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t *wl_key = reinterpret_cast<const uint32_t *>(tab + a.tab_total);
+    float *gx = reinterpret_cast<float *>(tab) + strip3_shared_words(a.tab_total, a.nodes_total, a.keys_total) +
+                wave * strip3_wave_words(a.nodes_total, a.keys_total);
+    Strip3Wave<M, float, LO> w(a, sh, gx, lane);
+    for (int64_t b = t0 + wave; b < t1; b += kServeWaves) w.run(a, sh, tab, wl_key, wl_key + a.keys_total, b);
+}
+
 
 __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeItem *ring, const ServeReqDesc *reqs,
                                                uint32_t *done, ServeDevCtl *dc, int32_t ring_size)
@@ -210,8 +230,25 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
             else
                 serve_strips_lo<2>(rq.as, sh, wl, s_item.tile0, t1, tid);
             __syncthreads();
+        } else if (rq.kernel == PTG_TUNE_STRIP_3D) {
+            Strip3Shared &sh = *reinterpret_cast<Strip3Shared *>(lds4);
+            float4 *tab = lds4 + kStrip3SharedWords / 4;
+            if (s_cmd == 1) {
+                uint32_t *wl_key = reinterpret_cast<uint32_t *>(tab + rq.a3s.tab_total);
+                if (rq.smooth == 1)
+                    strip3_prologue<1>(rq.a3s, sh, tab, wl_key, wl_key + rq.a3s.keys_total, tid, 256);
+                else
+                    strip3_prologue<2>(rq.a3s, sh, tab, wl_key, wl_key + rq.a3s.keys_total, tid, 256);
+                __syncthreads();
+            }
+            if (rq.smooth == 1)  // admission: finest period >= 8 (lo = 3)
+                serve_blocks<1, 3>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
+            else
+                serve_blocks<2, 3>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
+            __syncthreads();
         }
-        for (int64_t t = s_item.tile0; rq.kernel != PTG_TUNE_STRIP_2D && t < t1; ++t) {
+        const bool tiles = rq.kernel == PTG_TUNE_GENERAL_2D || rq.kernel == PTG_TUNE_GENERAL_3D;
+        for (int64_t t = s_item.tile0; tiles && t < t1; ++t) {
             if (rq.dim == 2) {
                 const int th = rq.a2.tile_h;
                 if (rq.smooth == 1) {
@@ -437,6 +474,11 @@ static void publish(ptg_server *s, uint64_t ticket, Request &r)
         (void)dyadic_shift(p, &k);  // validated at submission
         (void)strip_args_2d(p, k, r.req.origin[0], r.req.origin[1], r.req.extent[0], r.req.extent[1], out,
                             r.req.extent[0], &d.as);
+    } else if (r.kernel == PTG_TUNE_STRIP_3D) {
+        int k = 0;
+        (void)dyadic_shift(p, &k);
+        (void)strip3_args(p, k, r.req.origin[0], r.req.origin[1], r.req.origin[2], r.req.extent[0], r.req.extent[1],
+                          r.req.extent[2], out, &d.a3s);
     } else if (p->dim == 2)
         general_args_2d(p, r.req.origin[0], r.req.origin[1], r.req.extent[0], r.req.extent[1], out, r.req.extent[0],
                         s->tile_h2[p->smoothness - 1], &d.a2);
@@ -464,9 +506,9 @@ static void admit(ptg_server *s)
     for (auto it = s->pending.begin(); it != s->pending.end();) {
         Request &r = s->by_ticket[*it];
         // a strip is one wave's work: items of a strip request hold whole workgroups' worth
-        r.per_item = r.kernel == PTG_TUNE_STRIP_2D
-                         ? kServeWaves * tiles_per_item(s, (r.ntiles + kServeWaves - 1) / kServeWaves)
-                         : tiles_per_item(s, r.ntiles);
+        const bool strips = r.kernel == PTG_TUNE_STRIP_2D || r.kernel == PTG_TUNE_STRIP_3D;
+        r.per_item = strips ? kServeWaves * tiles_per_item(s, (r.ntiles + kServeWaves - 1) / kServeWaves)
+                            : tiles_per_item(s, r.ntiles);
         r.items = (r.ntiles + r.per_item - 1) / r.per_item;
         const uint64_t items = (uint64_t)r.items;
         if (s->free_slots.empty()) break;
@@ -611,8 +653,18 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
     size_t lds;
     int k = 0;
     Fbm2dStripArgs sa;
+    Fbm3dStripArgs sb;
     *kernel = nd == 2 ? PTG_TUNE_GENERAL_2D : PTG_TUNE_GENERAL_3D;
-    if (nd == 2 && dyadic_shift(p, &k) &&
+    if (nd == 3 && dyadic_shift(p, &k) &&
+        strip3_args(p, k, r->origin[0], r->origin[1], r->origin[2], nx, ny, nz, nullptr, &sb) == 0 && sb.lo == 3 &&
+        (size_t)(kStrip3SharedWords + strip3_shared_words(sb.tab_total, sb.nodes_total, sb.keys_total) +
+                 kServeWaves * strip3_wave_words(sb.nodes_total, sb.keys_total)) * 4 <= kServeLds) {
+        // dyadic ladder whose finest period is >= 8 (the serving kernel carries that class of
+        // the 3D strip code only; finer ladders keep its registers beyond two workgroups per CU)
+        *kernel = PTG_TUNE_STRIP_3D;
+        *ntiles = sb.blocks;
+        lds = 0;
+    } else if (nd == 2 && dyadic_shift(p, &k) &&
         strip_args_2d(p, k, r->origin[0], r->origin[1], nx, ny, nullptr, nx, &sa) == 0 && sa.lo >= 1 &&
         (size_t)(kStripSharedWords + strip_shared_words(sa.nodes_total, sa.keys_total) +
                  kServeWaves * strip_wave_words(sa.nodes_total, sa.keys_total)) * 4 <= kServeLds) {
@@ -633,7 +685,7 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
     }
     if (lds > kServeLds) return fail(PTG_EINVAL, "the request's lattice is too fine for a serving workgroup");
     if (*ntiles > 0x7FFFFFFFLL) return fail(PTG_EINVAL, "request too large");
-    const int64_t per = (*kernel == PTG_TUNE_STRIP_2D ? kServeWaves : 1) *
+    const int64_t per = (*kernel == PTG_TUNE_STRIP_2D || *kernel == PTG_TUNE_STRIP_3D ? kServeWaves : 1) *
                         (s->cfg.tiles_per_item > 0 ? s->cfg.tiles_per_item : kMaxTilesPerItem);
     const uint64_t items = (uint64_t)((*ntiles + per - 1) / per);
     if (items > (uint64_t)s->cfg.max_items) return fail(PTG_E2BIG, "request needs more work items than the ring holds");

@@ -49,7 +49,8 @@ def _solo(r, kernel):
         ptg.fbm_2d(out, x0=r["origin"][0], y0=r["origin"][1], path=path, **kw)
     else:
         out = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
-        ptg.fbm_3d(out, x0=r["origin"][0], y0=r["origin"][1], z0=r["origin"][2], path="general", **kw)
+        path = "dyadic" if kernel == ptg.PTG_TUNE_STRIP_3D else "general"
+        ptg.fbm_3d(out, x0=r["origin"][0], y0=r["origin"][1], z0=r["origin"][2], path=path, **kw)
     torch.cuda.current_stream().synchronize()  # not the device: the server's kernel may be running
     return out
 
@@ -76,8 +77,9 @@ def test_served_tiles_equal_solo_calls_bit_exact():
             assert res.status == ptg.PTG_OK and res.user_tag == r["user_tag"]
             got = _fetch(res, r)
             srv.release(t)
-            want = ptg.PTG_TUNE_STRIP_2D if (r["dim"] == 2 and r["base_freq"] == F0) else (
-                ptg.PTG_TUNE_GENERAL_2D if r["dim"] == 2 else ptg.PTG_TUNE_GENERAL_3D)
+            dyadic = r["base_freq"] == F0  # 3D ladders here end at period >= 32
+            want = (ptg.PTG_TUNE_STRIP_2D if dyadic else ptg.PTG_TUNE_GENERAL_2D) if r["dim"] == 2 else (
+                ptg.PTG_TUNE_STRIP_3D if dyadic else ptg.PTG_TUNE_GENERAL_3D)
             assert res.kernel == want, (res.kernel, r)
             assert torch.equal(got, _solo(r, res.kernel)), r
         st = srv.stats()
