@@ -102,6 +102,23 @@ __device__ __forceinline__ VW row_vw(const float *gx, const float *gy, const flo
 
 __device__ __forceinline__ Y1 cell_y1(const VW &lo, const VW &hi) { return Y1{lo.V, hi.V - lo.V, lo.W, hi.W}; }
 
+// One node (y, z) of a block collapsed along x at the lane's column (value term E, slope
+// terms Qy, Qz); two of them on consecutive z nodes give the row's V and W at a slice.
+struct XC {
+    float E, Qy, Qz;
+};
+
+__device__ __forceinline__ XC col_x(const float *gx, const float *gy, const float *gz, int na, int sx, const B3 &xb)
+{
+    const int b = na + sx;
+    return XC{gx[na] * xb.b10 + gx[b] * xb.b11, gy[na] + xb.s * (gy[b] - gy[na]), gz[na] + xb.s * (gz[b] - gz[na])};
+}
+
+__device__ __forceinline__ VW z_vw(const XC &lo, const XC &hi, const B3 &zb)
+{
+    return VW{lo.E + zb.s * (hi.E - lo.E) + lo.Qz * zb.b10 + hi.Qz * zb.b11, lo.Qy + zb.s * (hi.Qy - lo.Qy)};
+}
+
 __device__ __forceinline__ float y1_at(const Y1 &f, const B3 &yb)
 {
     return f.E0 + f.dE * yb.s + f.W0 * yb.b10 + f.W1 * yb.b11;
@@ -278,73 +295,98 @@ struct Strip3Wave {
             }
         }
 
-        // ---- periods 4, 2, 1 and the stores, one slice at a time (a rolled loop keeps the
-        // fine cells' node loads from being hoisted for every slice at once) -----------------
+        // ---- periods 4, 2, 1 and the stores, slice by slice.  Period 4 has one cell in z
+        // over the block: its nodes are collapsed along x once.  Slices go in pairs that share
+        // one period-2 cell in z (a rolled loop over the pairs keeps the fine cells' node loads
+        // from being hoisted for every slice at once) ------------------------------------------
+        XC x4[BY / 4 + 1][2];
+        if (H4) {
+            const int n0 = f4.noff + (lane >> 2) * f4.nny * f4.nnz;
+#pragma unroll
+            for (int j = 0; j <= BY / 4; ++j)
+#pragma unroll
+                for (int dk = 0; dk < 2; ++dk) x4[j][dk] = col_x(gx, gy, gz, n0 + j * f4.nnz + dk, f4.nny * f4.nnz, f4.xb);
+        }
 #pragma unroll 1
-        for (int zz = 0; zz < BZ; ++zz) {
-            const int64_t Z = Z0 + zz;
-            float t[BY];
-            switch (zz) {  // uniform: copy the slice's coarse sum without indexing registers
-            case 0:
+        for (int pz = 0; pz < BZ / 2; ++pz) {
+            XC x2[BY / 2 + 1][2];
+            if (H2) {  // period 2: node rows 0..4, z nodes pz and pz + 1
+                const int n0 = f2.noff + (lane >> 1) * f2.nny * f2.nnz + pz;
 #pragma unroll
-                for (int r = 0; r < BY; ++r) t[r] = acc[0][r];
-                break;
-            case 1:
+                for (int j = 0; j <= BY / 2; ++j)
 #pragma unroll
-                for (int r = 0; r < BY; ++r) t[r] = acc[1][r];
-                break;
-            case 2:
-#pragma unroll
-                for (int r = 0; r < BY; ++r) t[r] = acc[2][r];
-                break;
-            default:
-#pragma unroll
-                for (int r = 0; r < BY; ++r) t[r] = acc[BZ - 1][r];
-                break;
+                    for (int dk = 0; dk < 2; ++dk)
+                        x2[j][dk] = col_x(gx, gy, gz, n0 + j * f2.nnz + dk, f2.nny * f2.nnz, f2.xb);
             }
-            if (H4) {  // period 4: two cells in y (node rows 0..2), one in z (blocks are 4-aligned in z)
-                const B3 zb = b3_eval<M>((float)(2 * (zz & 3) + 1) * 0.125f);
-                const int n0 = f4.noff + (lane >> 2) * f4.nny * f4.nnz;
-                VW vw[BY / 4 + 1];
 #pragma unroll
-                for (int j = 0; j <= BY / 4; ++j) vw[j] = row_vw(gx, gy, gz, n0 + j * f4.nnz, f4.nny * f4.nnz, f4.xb, zb);
+            for (int h = 0; h < 2; ++h) {
+                const int zz = 2 * pz + h;
+                const int64_t Z = Z0 + zz;
+                float t[BY];
+                B3 zb4;
+                switch (zz) {  // uniform: the slice's coarse sum (no indexed registers) and period-4 z-bases
+                case 0:
 #pragma unroll
-                for (int c = 0; c < BY / 4; ++c) {
-                    const Y1 f = cell_y1(vw[c], vw[c + 1]);
+                    for (int r = 0; r < BY; ++r) t[r] = acc[0][r];
+                    zb4 = b3_const<M>(0, 4);
+                    break;
+                case 1:
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) t[4 * c + r] += y1_at(f, b3_const<M>(r, 4));
+                    for (int r = 0; r < BY; ++r) t[r] = acc[1][r];
+                    zb4 = b3_const<M>(1, 4);
+                    break;
+                case 2:
+#pragma unroll
+                    for (int r = 0; r < BY; ++r) t[r] = acc[2][r];
+                    zb4 = b3_const<M>(2, 4);
+                    break;
+                default:
+#pragma unroll
+                    for (int r = 0; r < BY; ++r) t[r] = acc[BZ - 1][r];
+                    zb4 = b3_const<M>(3, 4);
+                    break;
                 }
-            }
-            if (H2) {  // period 2: node rows 0..4
-                const B3 zb = b3_eval<M>((zz & 1) ? 0.75f : 0.25f);
-                const int n0 = f2.noff + (lane >> 1) * f2.nny * f2.nnz + (zz >> 1);
-                VW vw[BY / 2 + 1];
+                if (H4) {  // period 4: two cells in y (node rows 0..2)
+                    VW vw[BY / 4 + 1];
 #pragma unroll
-                for (int j = 0; j <= BY / 2; ++j) vw[j] = row_vw(gx, gy, gz, n0 + j * f2.nnz, f2.nny * f2.nnz, f2.xb, zb);
+                    for (int j = 0; j <= BY / 4; ++j) vw[j] = z_vw(x4[j][0], x4[j][1], zb4);
 #pragma unroll
-                for (int c = 0; c < BY / 2; ++c) {
-                    const Y1 f = cell_y1(vw[c], vw[c + 1]);
+                    for (int c = 0; c < BY / 4; ++c) {
+                        const Y1 f = cell_y1(vw[c], vw[c + 1]);
 #pragma unroll
-                    for (int r = 0; r < 2; ++r) t[2 * c + r] += y1_at(f, b3_const<M>(r, 2));
+                        for (int r = 0; r < 4; ++r) t[4 * c + r] += y1_at(f, b3_const<M>(r, 4));
+                    }
                 }
-            }
-            if (H1) {  // period 1: node rows 0..8
-                const B3 zb = b3_eval<M>(0.5f);
-                const int n0 = f1.noff + lane * f1.nny * f1.nnz + zz;
-                VW prev = row_vw(gx, gy, gz, n0, f1.nny * f1.nnz, f1.xb, zb);
+                if (H2) {
+                    const B3 zb = b3_const<M>(h, 2);
+                    VW vw[BY / 2 + 1];
 #pragma unroll
-                for (int c = 0; c < BY; ++c) {
-                    const VW next = row_vw(gx, gy, gz, n0 + (c + 1) * f1.nnz, f1.nny * f1.nnz, f1.xb, zb);
-                    t[c] += y1_at(cell_y1(prev, next), b3_const<M>(0, 1));
-                    prev = next;
+                    for (int j = 0; j <= BY / 2; ++j) vw[j] = z_vw(x2[j][0], x2[j][1], zb);
+#pragma unroll
+                    for (int c = 0; c < BY / 2; ++c) {
+                        const Y1 f = cell_y1(vw[c], vw[c + 1]);
+#pragma unroll
+                        for (int r = 0; r < 2; ++r) t[2 * c + r] += y1_at(f, b3_const<M>(r, 2));
+                    }
                 }
-            }
-            if (Z >= a.z0 && Z < ze && lane_ok) {
-                OutT *slice = out + ((Z - a.z0) * a.ny + (Y0 - a.y0)) * a.nx + (X - a.x0);
+                if (H1) {  // period 1: node rows 0..8
+                    const B3 zb = b3_const<M>(0, 1);
+                    const int n0 = f1.noff + lane * f1.nny * f1.nnz + zz;
+                    VW prev = row_vw(gx, gy, gz, n0, f1.nny * f1.nnz, f1.xb, zb);
 #pragma unroll
-                for (int r = 0; r < BY; ++r) {
-                    const int64_t Y = Y0 + r;
-                    if (Y >= a.y0 && Y < ye) slice[(int64_t)r * a.nx] = s3_out<OutT>(t[r]);
+                    for (int c = 0; c < BY; ++c) {
+                        const VW next = row_vw(gx, gy, gz, n0 + (c + 1) * f1.nnz, f1.nny * f1.nnz, f1.xb, zb);
+                        t[c] += y1_at(cell_y1(prev, next), b3_const<M>(0, 1));
+                        prev = next;
+                    }
+                }
+                if (Z >= a.z0 && Z < ze && lane_ok) {
+                    OutT *slice = out + ((Z - a.z0) * a.ny + (Y0 - a.y0)) * a.nx + (X - a.x0);
+#pragma unroll
+                    for (int r = 0; r < BY; ++r) {
+                        const int64_t Y = Y0 + r;
+                        if (Y >= a.y0 && Y < ye) slice[(int64_t)r * a.nx] = s3_out<OutT>(t[r]);
+                    }
                 }
             }
         }
