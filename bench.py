@@ -34,16 +34,20 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fbm2d_strip_2d_8192x8192_8oct_c
 
 def measured_traffic():
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
-    or None when the kernel source has changed since they were taken."""
+    or None when the kernel's sources (the files listed, hashed in order) have changed
+    since they were taken."""
     import hashlib
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
-        with open(os.path.join(ROOT, t["source"]), "rb") as fh:
-            if hashlib.sha256(fh.read()).hexdigest() != t["source_sha256"]:
-                return None
+        h = hashlib.sha256()
+        for src in t["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != t["sources_sha256"]:
+            return None
         return t["traffic_bytes"]
-    except (OSError, KeyError, ValueError):
+    except (OSError, KeyError, ValueError, TypeError):
         return None
 
 

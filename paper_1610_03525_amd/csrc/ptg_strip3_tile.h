@@ -254,20 +254,23 @@ struct Strip3Wave {
         const int64_t X = X0 + lane;
         const bool lane_ok = X >= a.x0 && X < xe;
         // ---- periods >= 8: one cell over the block; its nodes and bases are read once ------
-        float acc[BZ][BY];
+        float acc[BZ][BY], e0[BZ];  // per row: the dE / W terms; per slice: the cells' E0 terms
 #pragma unroll
-        for (int zz = 0; zz < BZ; ++zz)
+        for (int zz = 0; zz < BZ; ++zz) {
+            e0[zz] = 0.0f;
 #pragma unroll
             for (int r = 0; r < BY; ++r) acc[zz][r] = 0.0f;
+        }
         for (int o = 0; o < n_coarse; ++o) {
-            const int s = sh.shift[o];
+            // per-octave values from the arguments: uniform (scalar) in the dense kernel
+            const int s = a.shift[o];
             const uint32_t mask = (1u << s) - 1u;
-            const float inv2p = sh.inv2p[o];
-            const int to = sh.toff[o];
+            const float inv2p = a.inv2p[o];
+            const int to = a.toff[o];
             const B3 xb = b3_at<M>(tab, to, X, mask, inv2p);
-            const int nny = sh.nny[o], nnz = sh.nnz[o];
+            const int nny = a.nny[o], nnz = a.nnz[o];
             const int cxl = (int)((((uint32_t)X0 & mask) + (uint32_t)lane) >> s);
-            const int n0 = sh.noff[o] + cxl * nny * nnz, sx = nny * nnz;
+            const int n0 = a.noff[o] + cxl * nny * nnz, sx = nny * nnz;
             float ex[2][2], qy[2][2], qz[2][2];  // x-collapsed corners (y node, z node)
 #pragma unroll
             for (int dj = 0; dj < 2; ++dj)
@@ -290,10 +293,19 @@ struct Strip3Wave {
                     vw[dj] = VW{ex[dj][0] + zb.s * (ex[dj][1] - ex[dj][0]) + qz[dj][0] * zb.b10 + qz[dj][1] * zb.b11,
                                 qy[dj][0] + zb.s * (qy[dj][1] - qy[dj][0])};
                 const Y1 f = cell_y1(vw[0], vw[1]);
+                e0[zz] += f.E0;  // the same at every row of the slice
 #pragma unroll
-                for (int r = 0; r < BY; ++r) acc[zz][r] += y1_at(f, yb[r]);
+                for (int r = 0; r < BY; ++r) {
+                    float v = __builtin_fmaf(f.dE, yb[r].s, acc[zz][r]);
+                    v = __builtin_fmaf(f.W0, yb[r].b10, v);
+                    acc[zz][r] = __builtin_fmaf(f.W1, yb[r].b11, v);
+                }
             }
         }
+#pragma unroll
+        for (int zz = 0; zz < BZ; ++zz)
+#pragma unroll
+            for (int r = 0; r < BY; ++r) acc[zz][r] += e0[zz];
 
         // ---- periods 4, 2, 1 and the stores, slice by slice.  Period 4 has one cell in z
         // over the block: its nodes are collapsed along x once.  Slices go in pairs that share

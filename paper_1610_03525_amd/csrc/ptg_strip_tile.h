@@ -471,11 +471,12 @@ struct StripWave {
 #pragma unroll
         for (int b = 0; b < D1; ++b) C[b] = 0.0f;
         for (int o = 0; o < a.n_generic; ++o) {  // period >= 128: the strip is inside one cell
-            const int s = sh.shift[o];
+            // per-octave values from the arguments: uniform (scalar) in the dense kernel
+            const int s = a.shift[o];
             const uint32_t mask = (1u << s) - 1u;
-            const float inv2p = sh.inv2p[o];
-            const XA xa = xweights<M>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p, sh.amp[o]);
-            const CF c = column_form(nodes + sh.noff[o], 2, xa);
+            const float inv2p = a.inv2p[o];
+            const XA xa = xweights<M>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p, a.amp[o]);
+            const CF c = column_form(nodes + a.noff[o], 2, xa);
             const float invp = 2.0f * inv2p;
             const float tau = (float)(((uint32_t)Y0 & mask) + (uint32_t)(kStripH / 2)) * invp - 0.5f;
             add_mapped<M>(C, c, tau, (float)kStripH * invp);
