@@ -238,7 +238,9 @@ PTG_API void ptg_tune_reset(void);
  * blocks with the device code of ptg_fbm_3d with PTG_PATH_DYADIC; every other request runs
  * as 64 x tile_h (2D) or 64 x 8 x 8 (3D) sample tiles with the device code of
  * PTG_PATH_GENERAL.  A served tile equals the corresponding stand-alone call bit for bit
- * (ptg_tile_result.kernel says which). */
+ * (ptg_tile_result.kernel says which).  With cfg->lattice_cache the general 2D tiles read
+ * their node gradients (the K1 output of ptg_lattice_2d) from blocks cached in the arena
+ * across requests of the same seed. */
 
 typedef struct ptg_server ptg_server;
 
@@ -263,7 +265,17 @@ typedef struct ptg_server_cfg {
                               /* general kernel; needs a budget >= 1 MiB) and use the best  */
     int32_t tile_h;           /* 2D tile height in rows: 16, 32 or 64; 0 = the tuned one    */
                               /* (autotune), else 64.  3D tiles are 64 x 8 x 8              */
-    int32_t reserved;         /* 0                                                          */
+    int32_t lattice_cache;    /* 1: device-resident lattice cache for 2D requests served as */
+                              /* general tiles: the FP32 node gradients of each octave in    */
+                              /* blocks of 32 x 32 nodes keyed by (seed, octave, block),     */
+                              /* 8 KiB each in the arena (counted in the budget).  A request */
+                              /* references the blocks of its footprint at admission; the    */
+                              /* missing ones are first filled by the persistent kernel (K1),*/
+                              /* then its tiles read the gradients instead of hashing them   */
+                              /* (same results bit for bit).  Blocks stay resident after     */
+                              /* use and are evicted, least recently used first, when arena  */
+                              /* bytes are needed.  Requests whose footprint needs more than */
+                              /* 2048 blocks hash.  Budget at most 1 TiB.  0: no cache       */
 } ptg_server_cfg;
 
 typedef struct ptg_tile_req {
@@ -318,6 +330,11 @@ typedef struct ptg_server_stats {
     int64_t bytes_in_use, bytes_peak, budget;
     int64_t kernel_launches;  /* persistent-kernel launches (it exits after idling)         */
     int32_t tile_h[2];        /* 2D tile height used for C1 / C2 requests                    */
+    int64_t lat_blocks;       /* lattice-cache blocks resident (referenced or not)           */
+    int64_t lat_bytes;        /* their arena bytes (part of bytes_in_use)                    */
+    int64_t lat_hits;         /* blocks admitted requests found resident                     */
+    int64_t lat_misses;       /* blocks admitted requests had to fill                        */
+    int64_t lat_evictions;    /* unreferenced blocks freed for other allocations             */
 } ptg_server_stats;
 
 PTG_API int ptg_server_stats_get(ptg_server *s, ptg_server_stats *st);

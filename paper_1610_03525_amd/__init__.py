@@ -67,7 +67,7 @@ class ServerCfg(ctypes.Structure):
         ("tiles_per_item", ctypes.c_int32),
         ("autotune", ctypes.c_int32),
         ("tile_h", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("lattice_cache", ctypes.c_int32),
     ]
 
 
@@ -96,7 +96,8 @@ class TileResult(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "submitted", "admitted", "completed", "released", "tiles_done", "pending", "in_flight",
-        "bytes_in_use", "bytes_peak", "budget", "kernel_launches")] + [("tile_h", ctypes.c_int32 * 2)]
+        "bytes_in_use", "bytes_peak", "budget", "kernel_launches")] + [("tile_h", ctypes.c_int32 * 2)] + [
+        (n, ctypes.c_int64) for n in ("lat_blocks", "lat_bytes", "lat_hits", "lat_misses", "lat_evictions")]
 
 
 PTG_TUNE_GENERAL_2D, PTG_TUNE_STRIP_2D, PTG_TUNE_GENERAL_3D, PTG_TUNE_STRIP_3D, PTG_TUNE_DYADIC_2D = 1, 2, 3, 4, 5
@@ -376,9 +377,9 @@ class Server:
     """Continuous-batching tile server (a persistent kernel + host scheduler in libptg)."""
 
     def __init__(self, budget_bytes, max_items=1 << 16, workgroups=0, device=0, executor=PTG_EXEC_GPU,
-                 fake_tile_ns=0, tiles_per_item=0, autotune=0, tile_h=0):
+                 fake_tile_ns=0, tiles_per_item=0, autotune=0, tile_h=0, lattice_cache=0):
         cfg = ServerCfg(budget_bytes, max_items, workgroups, device, executor, fake_tile_ns, tiles_per_item,
-                        autotune, tile_h)
+                        autotune, tile_h, lattice_cache)
         h = ctypes.c_void_p()
         _check(lib().ptg_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.h = h

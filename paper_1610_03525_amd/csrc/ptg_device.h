@@ -87,7 +87,7 @@ __device__ __forceinline__ Coord coord_step(int64_t X, double f)
     return r;
 }
 
-__device__ __forceinline__ int64_t cell_of(int64_t X, double f)
+__host__ __device__ __forceinline__ int64_t cell_of(int64_t X, double f)
 {
 #pragma clang fp contract(off)
     return (int64_t)__builtin_floor(((double)X + 0.5) * f);

@@ -39,12 +39,31 @@ __device__ __forceinline__ __half to_out<__half>(float v)
     return __float2half_rn(v);
 }
 
+// Device-resident lattice cache (serving): the unit gradients of one octave's nodes in
+// blocks of kLatBlk x kLatBlk nodes, SoA per block (x components at [(iy & 31) * 32 +
+// (ix & 31)], y components kLatBlk^2 floats further), anywhere in the arena.  A request
+// sees the blocks that cover its footprint as a table per octave: block (bx, by) =
+// (ix >> 5, iy >> 5) is entry tbl0[o] + (by - by0[o]) * nbx[o] + (bx - bx0[o]), whose
+// value is the block's arena offset in 256-byte units.  The blocks hold the K1 output for
+// their nodes, so loading them gives the same gradients as hashing them.
+constexpr int kLatBlkLog = 5;
+constexpr int kLatBlk = 1 << kLatBlkLog;
+constexpr int kLatBlkFloats = 2 * kLatBlk * kLatBlk;
+struct LatCache {
+    const char *base;       // arena
+    const uint32_t *tbl;    // table entries (LDS copy)
+    int32_t n;              // entries
+    const int64_t *bx0, *by0;
+    const int32_t *nbx, *tbl0;
+};
+
 // ---------------------------------------------------------------------------------
 // 2D: tile 64 x TH samples (TH = 16, 32 or 64 rows), 4 waves x TH/4 rows.
 // LDS: row table float4[TH] | gx[capx*capy] | gy[capx*capy] | kx[capx] | ky[capy]
 // ---------------------------------------------------------------------------------
 template <int M, typename OutT, int TH>
-__device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t bid, float4 *lds4)
+__device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t bid, float4 *lds4,
+                                                   const LatCache *lat = nullptr)
 {
     constexpr int T = kTile2;
     constexpr int RPT = TH / 4;
@@ -76,9 +95,11 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
         const int nny = (int)(cell_of(Yl, f) - cyf) + 2;
 
         __syncthreads();  // the previous octave is done with LDS
-        const uint32_t pre = key_prefix(a.seed, o);
-        for (int i = tid; i < nnx; i += 256) kx[i] = key_xline(cxf + i);
-        for (int j = tid; j < nny; j += 256) ky[j] = absorb_index(pre, cyf + j);
+        if (!lat) {  // keys of the footprint's node columns and rows
+            const uint32_t pre = key_prefix(a.seed, o);
+            for (int i = tid; i < nnx; i += 256) kx[i] = key_xline(cxf + i);
+            for (int j = tid; j < nny; j += 256) ky[j] = absorb_index(pre, cyf + j);
+        }
         if (tid < TH) {
             const int r = min(tid, h - 1);
             const Coord c = coord_step(Yf + r, f);
@@ -87,11 +108,43 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
             rowt[tid] = make_float4(__int_as_float((int)(c.cell - cyf)), s, b10, b11);
         }
         __syncthreads();
-        for (int q = tid; q < nnx * nny; q += 256) {
-            const int j = q / nnx, i = q - j * nnx;
-            const float2 g = grad2(key_combine(ky[j], kx[i]));
-            gx[q] = g.x * amp;
-            gy[q] = g.y * amp;
+        if (lat) {  // gradients from the cached lattice blocks
+            // node (cxf + i, cyf + j) relative to the origin of the octave's first block
+            const int ox = (int)(cxf - (lat->bx0[o] << kLatBlkLog)), oy = (int)(cyf - (lat->by0[o] << kLatBlkLog));
+            const int nb = lat->nbx[o], e0 = lat->tbl0[o], nn = nnx * nny;
+            // kLatIlp nodes per thread per pass, their loads issued together (a gather's
+            // latency is paid once per pass, not once per node)
+            constexpr int kLatIlp = 4;
+            for (int q0 = tid; q0 < nn; q0 += kLatIlp * 256) {
+                float vx[kLatIlp], vy[kLatIlp];
+#pragma unroll
+                for (int k = 0; k < kLatIlp; ++k) {
+                    const int q = min(q0 + k * 256, nn - 1);  // past the end: reload the last node
+                    const int j = q / nnx, i = q - j * nnx;
+                    const int X = ox + i, Y = oy + j;
+                    int e = e0 + (Y >> kLatBlkLog) * nb + (X >> kLatBlkLog);
+                    e = min(max(e, 0), lat->n - 1);  // in range by construction; never read outside the table
+                    const float *blk = reinterpret_cast<const float *>(lat->base + (size_t)lat->tbl[e] * 256);
+                    const int w = (Y & (kLatBlk - 1)) * kLatBlk + (X & (kLatBlk - 1));
+                    vx[k] = blk[w];
+                    vy[k] = blk[kLatBlk * kLatBlk + w];
+                }
+#pragma unroll
+                for (int k = 0; k < kLatIlp; ++k) {
+                    const int q = q0 + k * 256;
+                    if (q < nn) {
+                        gx[q] = vx[k] * amp;
+                        gy[q] = vy[k] * amp;
+                    }
+                }
+            }
+        } else {
+            for (int q = tid; q < nnx * nny; q += 256) {
+                const int j = q / nnx, i = q - j * nnx;
+                const float2 g = grad2(key_combine(ky[j], kx[i]));
+                gx[q] = g.x * amp;
+                gy[q] = g.y * amp;
+            }
         }
         const Coord cc = coord_step(X, f);
         const int lcx = (int)(cc.cell - cxf);

@@ -34,10 +34,12 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "ptg_general_tile.h"
@@ -54,6 +56,8 @@ constexpr int64_t kParkNs = 5000000;       // nothing in flight for 5 ms: park t
 constexpr int64_t kSpinNs = 2000000;       // the scheduler spins until 2 ms after the last event
 constexpr int64_t kStarveNs = 50000000;    // after 50 ms a waiting request blocks later ones
 constexpr int kServeWaves = 4;             // waves of a serving workgroup (256 threads)
+constexpr int kMaxLatTbl = 2048;           // lattice-cache blocks one request may use (LDS table)
+constexpr int64_t kLatBlockBytes = (int64_t)kLatBlkFloats * 4;
 // a strip request's LDS: [StripShared | key and node work lists | one node block per wave]
 constexpr int kStripSharedWords = (int)((sizeof(StripShared) + 15) / 16 * 4);
 // a 3D strip request's: [Strip3Shared | basis table, key and node work lists | per-wave blocks]
@@ -73,6 +77,15 @@ struct ServeReqDesc {
         Fbm2dStripArgs as;
         Fbm3dStripArgs a3s;
     };
+    // lattice cache (general 2D requests): 0 = the tiles hash their nodes, 1 = the tiles
+    // read the cached blocks through the table, 2 = the items fill blocks (tile index t =
+    // fill word t: table entry | octave << 16)
+    int32_t lat_mode;
+    int32_t lat_n;                // table entries
+    const uint32_t *lat_host;     // pinned: [table (kMaxLatTbl words) | fill words]
+    char *lat_base;               // the arena
+    int64_t lat_bx0[kMaxOctaves], lat_by0[kMaxOctaves];
+    int32_t lat_nbx[kMaxOctaves], lat_tbl0[kMaxOctaves];
 };
 static_assert(sizeof(ServeReqDesc) % 8 == 0, "descriptor is copied in 8-byte words");
 
@@ -106,6 +119,30 @@ __global__ void k_serve_reset(ServeDevCtl *dc, uint64_t start)
 __device__ __forceinline__ uint64_t sys_load64(const uint64_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t sys_load32(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Fill one lattice-cache block (fill word t of the request): the K1 gradients of its
+// kLatBlk x kLatBlk nodes, the same key and gradient functions as the tiles' own hashing.
+__device__ __forceinline__ void fill_lat_block(const ServeReqDesc &rq, const uint32_t *tbl, int64_t t, int tid)
+{
+    const uint32_t fw = sys_load32(rq.lat_host + kMaxLatTbl + t);
+    const int o = min((int)(fw >> 16), kMaxOctaves - 1);
+    const int e = min((int)(fw & 0xFFFFu), rq.lat_n - 1);  // the host writes entries < lat_n
+    const int nb = max(rq.lat_nbx[o], 1);
+    const int local = e - rq.lat_tbl0[o];
+    const int64_t bx = rq.lat_bx0[o] + local % nb, by = rq.lat_by0[o] + local / nb;
+    float *dst = reinterpret_cast<float *>(rq.lat_base + (size_t)tbl[e] * 256);
+    const uint32_t pre = key_prefix(rq.a2.seed, o);
+    for (int q = tid; q < kLatBlk * kLatBlk; q += 256) {
+        const int64_t ix = bx * kLatBlk + (q & (kLatBlk - 1)), iy = by * kLatBlk + (q >> kLatBlkLog);
+        const float2 g = grad2(key_combine(absorb_index(pre, iy), key_xline(ix)));
+        dst[q] = g.x;
+        dst[kLatBlk * kLatBlk + q] = g.y;
+    }
 }
 
 // Strips [t0, t1) of a dyadic 2D request: wave w takes t0 + w, t0 + w + 4, ... (the same
@@ -158,6 +195,7 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
     __shared__ int s_cmd;
     __shared__ ServeItem s_item;
     __shared__ uint32_t s_have_slot, s_have_seq;  // request whose descriptor s_req holds
+    __shared__ uint32_t s_tbl[kMaxLatTbl];        // its lattice-cache table
     const int tid = threadIdx.x;
     if (tid == 0) s_have_slot = 0xFFFFFFFFu;
     for (;;) {
@@ -214,6 +252,11 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
             const uint64_t *src = reinterpret_cast<const uint64_t *>(reqs + s_item.slot);
             for (int i = tid; i < (int)(sizeof(ServeReqDesc) / 8); i += 256) s_req[i] = sys_load64(src + i);
             __syncthreads();
+            const ServeReqDesc &d = *reinterpret_cast<const ServeReqDesc *>(s_req);
+            if (d.lat_mode != 0) {
+                for (int i = tid; i < d.lat_n; i += 256) s_tbl[i] = sys_load32(d.lat_host + i);
+                __syncthreads();
+            }
         }
         const ServeReqDesc &rq = *reinterpret_cast<const ServeReqDesc *>(s_req);
         const int64_t t1 = (int64_t)s_item.tile0 + s_item.ntiles;
@@ -247,24 +290,34 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
                 serve_blocks<2, 3>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
             __syncthreads();
         }
-        const bool tiles = rq.kernel == PTG_TUNE_GENERAL_2D || rq.kernel == PTG_TUNE_GENERAL_3D;
+        if (rq.lat_mode == 2) {
+            for (int64_t t = s_item.tile0; t < t1; ++t) fill_lat_block(rq, s_tbl, t, tid);
+            // every wave's block stores have reached the L2 (vmcnt(0)) before the barrier, so
+            // the release below writes them back: tiles of other workgroups (other XCDs) read
+            // them as soon as the host has seen the fills done
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            __syncthreads();
+        }
+        const bool tiles = rq.lat_mode != 2 && (rq.kernel == PTG_TUNE_GENERAL_2D || rq.kernel == PTG_TUNE_GENERAL_3D);
         for (int64_t t = s_item.tile0; tiles && t < t1; ++t) {
             if (rq.dim == 2) {
                 const int th = rq.a2.tile_h;
+                const LatCache lc{rq.lat_base, s_tbl, rq.lat_n, rq.lat_bx0, rq.lat_by0, rq.lat_nbx, rq.lat_tbl0};
+                const LatCache *lat = rq.lat_mode == 1 ? &lc : nullptr;
                 if (rq.smooth == 1) {
                     if (th == 16)
-                        fbm2d_general_tile<1, float, 16>(rq.a2, t, lds4);
+                        fbm2d_general_tile<1, float, 16>(rq.a2, t, lds4, lat);
                     else if (th == 32)
-                        fbm2d_general_tile<1, float, 32>(rq.a2, t, lds4);
+                        fbm2d_general_tile<1, float, 32>(rq.a2, t, lds4, lat);
                     else
-                        fbm2d_general_tile<1, float, 64>(rq.a2, t, lds4);
+                        fbm2d_general_tile<1, float, 64>(rq.a2, t, lds4, lat);
                 } else {
                     if (th == 16)
-                        fbm2d_general_tile<2, float, 16>(rq.a2, t, lds4);
+                        fbm2d_general_tile<2, float, 16>(rq.a2, t, lds4, lat);
                     else if (th == 32)
-                        fbm2d_general_tile<2, float, 32>(rq.a2, t, lds4);
+                        fbm2d_general_tile<2, float, 32>(rq.a2, t, lds4, lat);
                     else
-                        fbm2d_general_tile<2, float, 64>(rq.a2, t, lds4);
+                        fbm2d_general_tile<2, float, 64>(rq.a2, t, lds4, lat);
                 }
             } else {
                 if (rq.smooth == 1)
@@ -343,14 +396,55 @@ class Arena {
     std::map<int64_t, int64_t> free_;
 };
 
+// A lattice-cache block: kLatBlk x kLatBlk nodes (bx, by) of one octave of one seed.
+struct LatKey {
+    uint32_t seed;
+    int32_t octave;
+    int64_t bx, by;
+    bool operator==(const LatKey &o) const
+    {
+        return seed == o.seed && octave == o.octave && bx == o.bx && by == o.by;
+    }
+};
+struct LatKeyHash {
+    size_t operator()(const LatKey &k) const
+    {
+        uint64_t h = ((uint64_t)k.seed << 8 | (uint32_t)k.octave) * 0x9E3779B97F4A7C15ull;
+        h = (h ^ (uint64_t)k.bx) * 0xBF58476D1CE4E5B9ull;
+        h = (h ^ (uint64_t)k.by) * 0x94D049BB133111EBull;
+        return (size_t)(h ^ (h >> 31));
+    }
+};
+struct LatBlock {
+    int64_t off = -1;
+    int32_t refs = 0;        // admitted requests that use it
+    uint64_t filler = 0;     // ticket whose fill phase writes it; 0 = written
+    bool bad = false;        // its fill failed: dropped once unreferenced
+    std::list<LatKey>::iterator lru;  // position in the LRU list while unreferenced
+    std::vector<uint64_t> waiters;    // other requests that read it once written
+};
+
 struct Request {
     ptg_tile_req req;
     int64_t bytes = 0, ntiles = 0, arena_off = -1, per_item = 1, items = 0;
     int32_t kernel = 0;  // PTG_TUNE_* class that computes it
+    // lattice cache: the blocks of its footprint (table order), the fill words of the ones
+    // its first phase writes, and the table geometry per octave
+    int32_t lat = 0, lat_n = 0;
+    int64_t lat_bx0[kMaxOctaves] = {}, lat_by0[kMaxOctaves] = {};
+    int32_t lat_nbx[kMaxOctaves] = {}, lat_tbl0[kMaxOctaves] = {};
+    std::vector<LatKey> lat_keys;
+    std::vector<uint32_t> lat_fill;
+    int64_t fill_per = 1, fill_items = 0;
+    int32_t next_phase = 2;  // waiting: 1 = its fills, 2 = its tiles are published next
+    int32_t lat_unready = 0; // its blocks not written yet (its own fills and others')
+    bool lat_bad = false;    // a block it reads will never be written (its filler failed)
     int32_t slot = -1;
     uint32_t seq = 0;
     uint64_t ring_begin = 0, ring_end = 0;
-    int status = 1;  // 1: pending, 2: in flight, PTG_OK / error: complete
+    // 1: pending, 2: tiles in flight, 3: fills in flight, 4: admitted, waiting for blocks
+    // that other requests fill or for ring space; PTG_OK / error: complete
+    int status = 1;
     int64_t t_submit = 0, t_admit = 0, t_done = 0, fake_done_at = 0;
 };
 
@@ -377,6 +471,7 @@ struct ptg_server {
     std::vector<uint64_t> inflight;
     struct RingSpan {
         uint64_t ticket, end;
+        int32_t phase;  // 1: a request's fills, 2: its tiles
         bool done;
     };
     std::deque<RingSpan> ring_order;  // admitted requests in ring order
@@ -387,6 +482,13 @@ struct ptg_server {
     bool stopping = false, quit = false;
     bool kernel_running = false, park_requested = false;
     uint64_t base = 0;        // first item index of the next launch (tail when the last one parked)
+    // lattice cache: resident blocks, the unreferenced ones in LRU order (front = oldest),
+    // admitted requests waiting for their next phase, per-slot tables in pinned memory
+    std::unordered_map<ptg::LatKey, ptg::LatBlock, ptg::LatKeyHash> lat_cache;
+    std::list<ptg::LatKey> lat_lru;
+    int64_t lat_lru_bytes = 0;
+    std::vector<uint64_t> lat_waiting;
+    uint32_t *lat_host = nullptr;
     int64_t idle_since = 0;   // when the in-flight set last became empty
     int64_t last_event = 0;   // last submission or completion
     int64_t tiles_in_flight = 0;
@@ -414,45 +516,220 @@ static int64_t tiles_per_item(const ptg_server *s, int64_t ntiles)
     return std::max(per, need);
 }
 
-static void complete(ptg_server *s, uint64_t ticket, int status)
+static int64_t round256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+// ---- lattice cache ------------------------------------------------------------------
+
+// Blocks covering a 2D request's footprint per octave (every node its general tiles read):
+// the table entries, or -1 beyond kMaxLatTbl.  With r, also its table geometry.
+static int lat_geometry(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, Request *r)
 {
-    Request &r = s->by_ticket[ticket];
-    if (r.status == 2) s->tiles_in_flight -= r.ntiles;
-    r.status = status;
-    r.t_done = now_ns();
-    s->last_event = r.t_done;
-    if (r.slot >= 0) s->free_slots.push_back(r.slot);
-    // ring entries are reused in ring order: reclaim up to the first unfinished request
+    double freq[kMaxOctaves];
+    float amp[kMaxOctaves];
+    octave_tables(p, freq, amp);
+    int64_t n = 0;
+    for (int o = 0; o < p->octaves; ++o) {
+        const double f = freq[o];
+        const int64_t bx0 = cell_of(x0, f) >> kLatBlkLog, bx1 = (cell_of(x0 + nx - 1, f) + 1) >> kLatBlkLog;
+        const int64_t by0 = cell_of(y0, f) >> kLatBlkLog, by1 = (cell_of(y0 + ny - 1, f) + 1) >> kLatBlkLog;
+        const int64_t nbx = bx1 - bx0 + 1, nby = by1 - by0 + 1;
+        if (nbx > kMaxLatTbl || nby > kMaxLatTbl || n + nbx * nby > kMaxLatTbl) return -1;
+        if (r) {
+            r->lat_bx0[o] = bx0;
+            r->lat_by0[o] = by0;
+            r->lat_nbx[o] = (int32_t)nbx;
+            r->lat_tbl0[o] = (int32_t)n;
+        }
+        n += nbx * nby;
+    }
+    return (int)n;
+}
+
+static void lat_evict_oldest(ptg_server *s)
+{
+    const LatKey k = s->lat_lru.front();
+    s->lat_lru.pop_front();
+    s->lat_lru_bytes -= kLatBlockBytes;
+    auto it = s->lat_cache.find(k);
+    s->arena->release(it->second.off, kLatBlockBytes);
+    s->lat_cache.erase(it);
+    s->st.lat_evictions++;
+}
+
+// Arena bytes, evicting unreferenced lattice blocks (oldest first) when they are needed.
+static int64_t arena_alloc(ptg_server *s, int64_t bytes)
+{
+    int64_t off = s->arena->alloc(bytes);
+    if (off >= 0 || s->lat_lru.empty()) return off;
+    if (s->cfg.hbm_budget_bytes - s->arena->used() + s->lat_lru_bytes < round256(bytes)) return -1;  // hopeless
+    while (off < 0 && !s->lat_lru.empty()) {
+        lat_evict_oldest(s);
+        off = s->arena->alloc(bytes);
+    }
+    return off;
+}
+
+// Drop a request's references; blocks left unreferenced join the LRU list, or are freed
+// when their fill never completed (failed: the request's own fills did not run).
+static void lat_unref(ptg_server *s, uint64_t ticket, Request &r, bool failed)
+{
+    for (const LatKey &k : r.lat_keys) {
+        auto it = s->lat_cache.find(k);
+        LatBlock &b = it->second;
+        if (failed && b.filler == ticket) {
+            b.bad = true;
+            for (uint64_t w : b.waiters) {
+                auto wr = s->by_ticket.find(w);
+                if (wr != s->by_ticket.end()) wr->second.lat_bad = true;
+            }
+            b.waiters.clear();
+        }
+        auto me = std::find(b.waiters.begin(), b.waiters.end(), ticket);
+        if (me != b.waiters.end()) b.waiters.erase(me);
+        if (--b.refs > 0) continue;
+        if (b.bad || b.filler != 0) {
+            s->arena->release(b.off, kLatBlockBytes);
+            s->lat_cache.erase(it);
+        } else {
+            b.lru = s->lat_lru.insert(s->lat_lru.end(), k);
+            s->lat_lru_bytes += kLatBlockBytes;
+        }
+    }
+    r.lat_keys.clear();
+    r.lat_fill.clear();
+}
+
+// Reference every block of a cached request; the missing ones get arena bytes and a fill
+// word (its fill phase writes them).  False, holding nothing, when the arena cannot take
+// the missing blocks now.
+static bool lat_acquire(ptg_server *s, uint64_t ticket, Request &r)
+{
+    const ptg_params *p = &r.req.params;
+    r.lat_n = lat_geometry(p, r.req.origin[0], r.req.origin[1], r.req.extent[0], r.req.extent[1], &r);
+    r.lat_keys.clear();
+    r.lat_fill.clear();
+    r.lat_unready = 0;
+    r.lat_bad = false;
+    std::vector<uint32_t> tbl((size_t)r.lat_n);
+    int64_t hits = 0;
+    for (int o = 0; o < p->octaves; ++o) {
+        const int nbx = r.lat_nbx[o];
+        const int nby = ((o + 1 < p->octaves ? r.lat_tbl0[o + 1] : r.lat_n) - r.lat_tbl0[o]) / nbx;
+        for (int j = 0; j < nby; ++j)
+            for (int i = 0; i < nbx; ++i) {
+                const int e = r.lat_tbl0[o] + j * nbx + i;
+                const LatKey k{p->seed, o, r.lat_bx0[o] + i, r.lat_by0[o] + j};
+                auto it = s->lat_cache.find(k);
+                if (it == s->lat_cache.end()) {
+                    const int64_t off = arena_alloc(s, kLatBlockBytes);
+                    if (off < 0) {
+                        lat_unref(s, ticket, r, true);
+                        return false;
+                    }
+                    it = s->lat_cache.emplace(k, LatBlock{}).first;
+                    it->second.off = off;
+                    it->second.filler = ticket;
+                    r.lat_fill.push_back((uint32_t)e | ((uint32_t)o << 16));
+                    ++r.lat_unready;
+                } else {
+                    LatBlock &b = it->second;
+                    if (b.refs == 0) {
+                        s->lat_lru.erase(b.lru);
+                        s->lat_lru_bytes -= kLatBlockBytes;
+                    }
+                    if (b.bad) r.lat_bad = true;
+                    if (b.filler != 0 && !b.bad) {  // another request's fill writes it
+                        ++r.lat_unready;
+                        b.waiters.push_back(ticket);
+                    }
+                    ++hits;
+                }
+                it->second.refs++;
+                r.lat_keys.push_back(k);
+                tbl[(size_t)e] = (uint32_t)(it->second.off >> 8);
+            }
+    }
+    s->st.lat_hits += hits;
+    s->st.lat_misses += (int64_t)r.lat_fill.size();
+    if (s->gpu) {
+        uint32_t *h = s->lat_host + (size_t)r.slot * 2 * kMaxLatTbl;
+        std::memcpy(h, tbl.data(), tbl.size() * 4);
+        std::memcpy(h + kMaxLatTbl, r.lat_fill.data(), r.lat_fill.size() * 4);
+    }
+    const int64_t wg = std::max(s->workgroups, 1), nf = (int64_t)r.lat_fill.size();
+    // a block is a small job (kLatBlk^2 hashes): about 8 items per request of up to 16 blocks
+    // each (fewer claims and completion fences per block)
+    r.fill_per = std::max<int64_t>((nf + 7) / 8, std::min<int64_t>(kMaxTilesPerItem, nf / (2 * wg)));
+    r.fill_per = std::max<int64_t>(1, std::min<int64_t>(kMaxTilesPerItem, r.fill_per));
+    r.fill_per = std::max<int64_t>(r.fill_per, (nf + s->cfg.max_items - 1) / s->cfg.max_items);
+    r.fill_items = (nf + r.fill_per - 1) / r.fill_per;
+    return true;
+}
+
+// A request's fills are done: its blocks are written, for it and for their waiters.
+static void lat_filled(ptg_server *s, Request &r)
+{
+    for (uint32_t fw : r.lat_fill) {
+        LatBlock &b = s->lat_cache.find(r.lat_keys[fw & 0xFFFFu])->second;
+        b.filler = 0;
+        --r.lat_unready;
+        for (uint64_t w : b.waiters) {
+            auto wr = s->by_ticket.find(w);
+            if (wr != s->by_ticket.end()) --wr->second.lat_unready;
+        }
+        b.waiters.clear();
+    }
+}
+
+// ---- request life cycle ---------------------------------------------------------------
+
+// Ring entries are reused in ring order: mark a published span finished and reclaim up to
+// the first unfinished one.
+static void span_done(ptg_server *s, uint64_t ticket, int32_t phase)
+{
     for (auto &e : s->ring_order)
-        if (e.ticket == ticket) e.done = true;
+        if (e.ticket == ticket && (phase == 0 || e.phase == phase)) e.done = true;
     while (!s->ring_order.empty() && s->ring_order.front().done) {
         s->reclaimed = s->ring_order.front().end;
         s->ring_order.pop_front();
     }
+}
+
+static void complete(ptg_server *s, uint64_t ticket, int status)
+{
+    Request &r = s->by_ticket[ticket];
+    if (r.status == 2) s->tiles_in_flight -= r.ntiles;
+    if (r.lat) lat_unref(s, ticket, r, status != PTG_OK);
+    r.status = status;
+    r.t_done = now_ns();
+    s->last_event = r.t_done;
+    if (r.slot >= 0) s->free_slots.push_back(r.slot);
+    span_done(s, ticket, 0);
     s->st.completed++;
     if (status == PTG_OK) s->st.tiles_done += r.ntiles;
+    s->st.bytes_in_use = s->arena->used();
     s->cv_done.notify_all();
 }
 
-static void publish(ptg_server *s, uint64_t ticket, Request &r)
+// Publish one phase of an admitted request (slot held): 1 = the fills of its missing
+// lattice blocks, 2 = its tiles.
+static void publish(ptg_server *s, uint64_t ticket, Request &r, int phase)
 {
-    const int32_t slot = s->free_slots.back();
-    s->free_slots.pop_back();
-    r.slot = slot;
+    const int32_t slot = r.slot;
     r.seq = ++s->seq;
-    r.t_admit = now_ns();
-    r.status = 2;
-    s->tiles_in_flight += r.ntiles;
-    const uint64_t items = (uint64_t)r.items;
+    r.status = phase == 1 ? 3 : 2;
+    const int64_t nwork = phase == 1 ? (int64_t)r.lat_fill.size() : r.ntiles;
+    const int64_t per = phase == 1 ? r.fill_per : r.per_item;
+    const uint64_t items = (uint64_t)(phase == 1 ? r.fill_items : r.items);
+    if (phase == 2) s->tiles_in_flight += r.ntiles;
     r.ring_begin = s->tail;
     r.ring_end = s->tail + items;
-    s->ring_order.push_back({ticket, r.ring_end, false});
+    s->ring_order.push_back({ticket, r.ring_end, phase, false});
     s->inflight.push_back(ticket);
-    s->st.admitted++;
     s->st.bytes_in_use = s->arena->used();
     s->st.bytes_peak = std::max(s->st.bytes_peak, s->st.bytes_in_use);
     if (!s->gpu) {
-        s->fake_busy_until = std::max(s->fake_busy_until, r.t_admit) + r.ntiles * s->cfg.fake_tile_ns;
+        s->fake_busy_until = std::max(s->fake_busy_until, now_ns()) + nwork * s->cfg.fake_tile_ns;
         r.fake_done_at = s->fake_busy_until;
         s->tail = r.ring_end;
         return;
@@ -465,9 +742,9 @@ static void publish(ptg_server *s, uint64_t ticket, Request &r)
     d.smooth = p->smoothness;
     d.slot = slot;
     d.seq = r.seq;
-    s->slot_total[slot] += (uint64_t)r.ntiles;
+    s->slot_total[slot] += (uint64_t)nwork;
     d.target = s->slot_total[slot];
-    d.ntiles = r.ntiles;
+    d.ntiles = nwork;
     d.kernel = r.kernel;
     if (r.kernel == PTG_TUNE_STRIP_2D) {
         int k = 0;
@@ -485,19 +762,61 @@ static void publish(ptg_server *s, uint64_t ticket, Request &r)
     else
         general_args_3d(p, r.req.origin[0], r.req.origin[1], r.req.origin[2], r.req.extent[0], r.req.extent[1],
                         r.req.extent[2], out, &d.a3);
+    if (r.lat) {
+        d.lat_mode = phase == 1 ? 2 : 1;
+        d.lat_n = r.lat_n;
+        d.lat_host = s->lat_host + (size_t)slot * 2 * kMaxLatTbl;
+        d.lat_base = s->arena_mem;
+        for (int o = 0; o < kMaxOctaves; ++o) {
+            d.lat_bx0[o] = r.lat_bx0[o];
+            d.lat_by0[o] = r.lat_by0[o];
+            d.lat_nbx[o] = r.lat_nbx[o];
+            d.lat_tbl0[o] = r.lat_tbl0[o];
+        }
+    }
     std::memcpy(&s->reqs[slot], &d, sizeof(d));
     for (uint64_t i = 0; i < items; ++i) {
         ServeItem it;
         it.slot = (uint32_t)slot;
         it.seq = r.seq;
-        const int64_t t0 = (int64_t)i * r.per_item;
+        const int64_t t0 = (int64_t)i * per;
         it.tile0 = (uint32_t)t0;
-        it.ntiles = (uint32_t)std::min<int64_t>(r.per_item, r.ntiles - t0);
+        it.ntiles = (uint32_t)std::min<int64_t>(per, nwork - t0);
         std::memcpy(&s->ring[(r.ring_begin + i) % (uint64_t)s->cfg.max_items], &it, sizeof(it));
     }
     s->tail = r.ring_end;
     std::atomic_thread_fence(std::memory_order_release);
     __atomic_store_n(&s->hc->tail, s->tail, __ATOMIC_RELEASE);
+}
+
+static bool ring_fits(const ptg_server *s, uint64_t items)
+{
+    return s->tail + items - s->reclaimed <= (uint64_t)s->cfg.max_items;
+}
+
+// Publish a waiting request's next phase if it can go: fills need ring space; tiles need
+// ring space and every block they read written (by their own fills or another's).
+static bool lat_try(ptg_server *s, uint64_t ticket, Request &r)
+{
+    if (r.lat_bad) {
+        complete(s, ticket, PTG_EHIP);
+        return true;
+    }
+    if (r.next_phase == 2 && r.lat_unready > 0) return false;
+    if (!ring_fits(s, (uint64_t)(r.next_phase == 1 ? r.fill_items : r.items))) return false;
+    publish(s, ticket, r, r.next_phase);
+    return true;
+}
+
+static void lat_advance(ptg_server *s)
+{
+    for (size_t i = 0; i < s->lat_waiting.size();) {
+        const uint64_t ticket = s->lat_waiting[i];
+        if (lat_try(s, ticket, s->by_ticket[ticket]))
+            s->lat_waiting.erase(s->lat_waiting.begin() + (ptrdiff_t)i);  // the others keep their order
+        else
+            ++i;
+    }
 }
 
 static void admit(ptg_server *s)
@@ -512,8 +831,8 @@ static void admit(ptg_server *s)
         r.items = (r.ntiles + r.per_item - 1) / r.per_item;
         const uint64_t items = (uint64_t)r.items;
         if (s->free_slots.empty()) break;
-        if (s->tail + items - s->reclaimed > (uint64_t)s->cfg.max_items) break;  // ring order is FIFO
-        const int64_t off = s->arena->alloc(r.bytes);
+        if (!ring_fits(s, items)) break;  // ring order is FIFO
+        const int64_t off = arena_alloc(s, round256(r.bytes));
         if (off < 0) {
             if (now - r.t_submit > kStarveNs) break;  // it waited long enough: nobody passes it
             ++it;
@@ -521,8 +840,27 @@ static void admit(ptg_server *s)
         }
         r.arena_off = off;
         const uint64_t ticket = *it;
+        r.slot = s->free_slots.back();
+        s->free_slots.pop_back();
+        if (r.lat && !lat_acquire(s, ticket, r)) {  // its missing blocks do not fit yet
+            s->free_slots.push_back(r.slot);
+            r.slot = -1;
+            s->arena->release(r.arena_off, round256(r.bytes));
+            r.arena_off = -1;
+            if (now - r.t_submit > kStarveNs) break;
+            ++it;
+            continue;
+        }
         it = s->pending.erase(it);
-        publish(s, ticket, r);
+        r.t_admit = now_ns();
+        s->st.admitted++;
+        if (r.lat) {
+            r.next_phase = r.lat_fill.empty() ? 2 : 1;
+            r.status = 4;
+            if (!lat_try(s, ticket, r)) s->lat_waiting.push_back(ticket);
+            continue;
+        }
+        publish(s, ticket, r, 2);
     }
 }
 
@@ -530,22 +868,35 @@ static void poll_done(ptg_server *s)
 {
     const int64_t now = now_ns();
     for (size_t i = 0; i < s->inflight.size();) {
-        Request &r = s->by_ticket[s->inflight[i]];
+        const uint64_t ticket = s->inflight[i];
+        Request &r = s->by_ticket[ticket];
         const bool fin = s->gpu ? (__atomic_load_n(&s->done[r.slot], __ATOMIC_ACQUIRE) == r.seq) : (now >= r.fake_done_at);
-        if (fin) {
-            complete(s, s->inflight[i], PTG_OK);
-            s->inflight[i] = s->inflight.back();
-            s->inflight.pop_back();
-        } else {
+        if (!fin) {
             ++i;
+            continue;
+        }
+        s->inflight[i] = s->inflight.back();
+        s->inflight.pop_back();
+        if (r.status == 3) {  // fills done: the tiles follow
+            lat_filled(s, r);
+            span_done(s, ticket, 1);
+            r.next_phase = 2;
+            r.status = 4;
+            s->lat_waiting.push_back(ticket);
+            s->last_event = now;
+        } else {
+            complete(s, ticket, PTG_OK);
         }
     }
 }
 
 static void fail_inflight(ptg_server *s, int status)
 {
-    for (uint64_t t : s->inflight) complete(s, t, status);
+    std::vector<uint64_t> all(s->inflight);
+    all.insert(all.end(), s->lat_waiting.begin(), s->lat_waiting.end());
     s->inflight.clear();
+    s->lat_waiting.clear();
+    for (uint64_t t : all) complete(s, t, status);
 }
 
 // Kernel state: running (launched, not yet seen finished) and park_requested (ctl->park
@@ -602,18 +953,20 @@ static void service(ptg_server *s)
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         check_kernel(s);
+        if (!s->park_requested) lat_advance(s);
         if (!s->stopping && !s->park_requested) admit(s);
         const bool busy = !s->inflight.empty();
         poll_done(s);
+        if (!s->park_requested) lat_advance(s);
         const int64_t now = now_ns();
         if (busy && s->inflight.empty()) s->idle_since = now;
         ensure_kernel(s);
         maybe_park(s, now);
-        if (s->stopping && s->inflight.empty() && !s->kernel_running) break;
+        if (s->stopping && s->inflight.empty() && s->lat_waiting.empty() && !s->kernel_running) break;
         // spin while requests are in flight or soon after the last event (completion is
         // seen within a poll, not a sleep); then sleep briefly while a kernel may still
         // need parking, and block when there is nothing to do
-        if (!s->inflight.empty() || now - s->last_event < kSpinNs) {
+        if (!s->inflight.empty() || !s->lat_waiting.empty() || now - s->last_event < kSpinNs) {
             lk.unlock();
             std::this_thread::yield();
             lk.lock();
@@ -627,7 +980,8 @@ static void service(ptg_server *s)
     }
 }
 
-static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *bytes, int64_t *ntiles, int32_t *kernel)
+static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *bytes, int64_t *ntiles, int32_t *kernel,
+                        int32_t *lat)
 {
     const ptg_params *p = &r->params;
     if (!p || (p->dim != 2 && p->dim != 3)) return fail(PTG_EINVAL, "request dim must be 2 or 3");
@@ -689,8 +1043,15 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
                         (s->cfg.tiles_per_item > 0 ? s->cfg.tiles_per_item : kMaxTilesPerItem);
     const uint64_t items = (uint64_t)((*ntiles + per - 1) / per);
     if (items > (uint64_t)s->cfg.max_items) return fail(PTG_E2BIG, "request needs more work items than the ring holds");
-    if (((*bytes + 255) & ~int64_t(255)) > s->cfg.hbm_budget_bytes)
+    if (round256(*bytes) > s->cfg.hbm_budget_bytes)
         return fail(PTG_E2BIG, "request output (%lld bytes) exceeds the budget", (long long)*bytes);
+    // lattice cache: general 2D requests whose blocks fit the table and, all missing, the
+    // budget beside the output (others hash their nodes)
+    *lat = 0;
+    if (s->cfg.lattice_cache && *kernel == PTG_TUNE_GENERAL_2D) {
+        const int n = lat_geometry(p, r->origin[0], r->origin[1], nx, ny, nullptr);
+        if (n > 0 && round256(*bytes) + n * kLatBlockBytes <= s->cfg.hbm_budget_bytes) *lat = 1;
+    }
     return PTG_OK;
 }
 
@@ -698,6 +1059,7 @@ static void free_server(ptg_server *s)
 {
     if (s->gpu) {
         if (s->stream) (void)hipStreamDestroy(s->stream);
+        if (s->lat_host) (void)hipHostFree(s->lat_host);
         if (s->hc) (void)hipHostFree(s->hc);
         if (s->ring) (void)hipHostFree(s->ring);
         if (s->reqs) (void)hipHostFree(s->reqs);
@@ -726,10 +1088,12 @@ int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out)
     if (cfg->executor == PTG_EXEC_HOST && cfg->fake_tile_ns < 0) return fail(PTG_EINVAL, "fake_tile_ns < 0");
     if (cfg->tiles_per_item < 0 || cfg->tiles_per_item > kMaxTilesPerItem)
         return fail(PTG_EINVAL, "tiles_per_item must be in 0..%d", kMaxTilesPerItem);
-    if ((cfg->autotune != 0 && cfg->autotune != 1) || cfg->reserved != 0)
-        return fail(PTG_EINVAL, "autotune must be 0 or 1, reserved 0");
+    if ((cfg->autotune != 0 && cfg->autotune != 1) || (cfg->lattice_cache != 0 && cfg->lattice_cache != 1))
+        return fail(PTG_EINVAL, "autotune and lattice_cache must be 0 or 1");
     if (cfg->tile_h != 0 && cfg->tile_h != 16 && cfg->tile_h != 32 && cfg->tile_h != 64)
         return fail(PTG_EINVAL, "tile_h must be 0, 16, 32 or 64");
+    if (cfg->lattice_cache && cfg->hbm_budget_bytes > (int64_t(1) << 40))
+        return fail(PTG_EINVAL, "lattice_cache needs a budget of at most 1 TiB");
     if (cfg->autotune && cfg->executor == PTG_EXEC_GPU && cfg->hbm_budget_bytes < (1 << 20))
         return fail(PTG_EINVAL, "autotune needs a budget of at least 1 MiB");
     *out = nullptr;
@@ -753,6 +1117,9 @@ int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out)
             cus = 256;
         s->workgroups = cfg->workgroups > 0 ? cfg->workgroups : 2 * cus;
         e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (e == hipSuccess && cfg->lattice_cache)
+            e = hipHostMalloc((void **)&s->lat_host, sizeof(uint32_t) * 2 * kMaxLatTbl * kReqSlots,
+                              hipHostMallocCoherent);
         if (e == hipSuccess) e = hipHostMalloc((void **)&s->hc, sizeof(ServeHostCtl), hipHostMallocCoherent);
         if (e == hipSuccess)
             e = hipHostMalloc((void **)&s->ring, sizeof(ServeItem) * (size_t)cfg->max_items, hipHostMallocCoherent);
@@ -805,8 +1172,9 @@ int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n, uint64_
     if (!s || (n > 0 && (!reqs || !tickets_out)) || n < 0) return fail(PTG_EINVAL, "bad arguments");
     std::vector<int64_t> bytes(n), tiles(n);
     std::vector<int32_t> kernels(n);
+    std::vector<int32_t> lat(n);
     for (int32_t i = 0; i < n; ++i) {
-        const int rc = validate_req(s, &reqs[i], &bytes[i], &tiles[i], &kernels[i]);
+        const int rc = validate_req(s, &reqs[i], &bytes[i], &tiles[i], &kernels[i], &lat[i]);
         if (rc) return rc;
     }
     std::lock_guard<std::mutex> lk(s->mu);
@@ -820,6 +1188,7 @@ int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n, uint64_
         r.bytes = bytes[i];
         r.ntiles = tiles[i];
         r.kernel = kernels[i];
+        r.lat = lat[i];
         r.t_submit = t;
         s->pending.push_back(ticket);
         tickets_out[i] = ticket;
@@ -866,7 +1235,7 @@ int ptg_tile_release(ptg_server *s, uint64_t ticket)
     auto it = s->by_ticket.find(ticket);
     if (it == s->by_ticket.end()) return fail(PTG_ENOENT, "unknown ticket");
     if (it->second.status > 0) return fail(PTG_EAGAIN, "request not complete");
-    if (it->second.arena_off >= 0) s->arena->release(it->second.arena_off, it->second.bytes);
+    if (it->second.arena_off >= 0) s->arena->release(it->second.arena_off, round256(it->second.bytes));
     s->by_ticket.erase(it);
     s->st.released++;
     s->st.bytes_in_use = s->arena->used();
@@ -882,6 +1251,8 @@ int ptg_server_stats_get(ptg_server *s, ptg_server_stats *st)
     st->pending = (int64_t)s->pending.size();
     st->in_flight = (int64_t)s->inflight.size();
     st->bytes_in_use = s->arena->used();
+    st->lat_blocks = (int64_t)s->lat_cache.size();
+    st->lat_bytes = st->lat_blocks * kLatBlockBytes;
     st->tile_h[0] = s->tile_h2[0];
     st->tile_h[1] = s->tile_h2[1];
     return PTG_OK;

@@ -142,6 +142,58 @@ def test_kernel_relaunches_after_idle_and_small_budget_admission():
         assert st["kernel_launches"] >= 2 and st["bytes_peak"] <= biggest + 4096
 
 
+def _lat_mix(n, seed):
+    """General 2D requests over a few seeds and overlapping windows, so lattice blocks are
+    shared between requests; one far from the origin (negative block indices)."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        side = int(rng.choice([64, 100, 160, 256]))
+        reqs.append(dict(dim=2, smoothness=int(rng.integers(1, 3)), octaves=int(rng.integers(3, 8)),
+                         base_freq=float(rng.choice([0.0031, 0.0077, 0.013])), persistence=0.5, lacunarity=2.0,
+                         seed=int(rng.choice([7, 8, 9])), origin=(int(rng.integers(-600, 600)),
+                                                                  int(rng.integers(-600, 600)), 0),
+                         extent=(side, side // 2 + 7, 1), user_tag=i))
+    reqs.append(dict(dim=2, smoothness=2, octaves=7, base_freq=0.0077, persistence=0.5, lacunarity=2.0, seed=7,
+                     origin=(-(1 << 45) + 17, (1 << 44) + 5, 0), extent=(130, 70, 1), user_tag=n))
+    return reqs
+
+
+@pytest.mark.parametrize("budget", [1 << 30, 3 << 20])
+def test_lattice_cache_tiles_equal_solo_calls_bit_exact(budget):
+    """With the lattice cache the general 2D tiles read their node gradients from blocks
+    that the persistent kernel filled (shared by requests of one seed; evicted and refilled
+    under the small budget): every tile equals the stand-alone general call bit for bit."""
+    reqs = _lat_mix(40, 31)
+    with ptg.Server(budget, lattice_cache=1) as srv:
+        _drain(srv, srv.submit([_tile_req(r) for r in reqs[:20]]), reqs[:20])
+        _drain(srv, srv.submit([_tile_req(r) for r in reqs[20:]]), reqs[20:])  # blocks resident from the first half
+        st = srv.stats()
+        assert st["lat_hits"] > 0 and st["lat_misses"] > 0 and st["completed"] == len(reqs)
+        assert st["bytes_peak"] <= budget
+        if budget < (1 << 24):
+            assert st["lat_evictions"] > 0
+
+
+def test_lattice_cached_samples_match_oracle():
+    r = dict(dim=2, smoothness=1, octaves=7, base_freq=0.0093, persistence=0.5, lacunarity=2.0, seed=4242,
+             origin=(-(1 << 43) - 29, (1 << 42) + 3, 0), extent=(190, 120, 1), user_tag=1)
+    with ptg.Server(1 << 26, lattice_cache=1) as srv:
+        g = []
+        for _ in range(2):  # filled, then found resident
+            (t,) = srv.submit([_tile_req(r)])
+            g.append(_fetch(srv.wait(t, int(60e9)), r).cpu().numpy().astype(np.float64))
+            srv.release(t)
+        st = srv.stats()
+        assert st["lat_misses"] > 0 and st["lat_hits"] == st["lat_misses"]
+    assert np.array_equal(g[0], g[1])
+    rng = np.random.default_rng(1)
+    i = rng.integers(0, 190, 500)
+    j = rng.integers(0, 120, 500)
+    ref = O.fbm_points_2d(1, 7, 0.5, 2.0, 0.0093, 4242, r["origin"][0] + i, r["origin"][1] + j)
+    assert np.max(np.abs(g[0][j, i] - ref)) <= 1e-5 * sum(0.5 ** o for o in range(7))
+
+
 def test_served_samples_match_oracle():
     r = dict(dim=2, smoothness=2, octaves=12, base_freq=F0, persistence=0.5, lacunarity=2.0, seed=99,
              origin=((1 << 40) + 17, -(1 << 41) - 3, 0), extent=(200, 150, 1), user_tag=1)

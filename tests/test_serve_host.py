@@ -187,3 +187,113 @@ def test_loadgen_rejects_bad_arrivals():
     done = np.zeros(2, dtype=np.int64)
     with _srv(1 << 24) as s:
         assert lg.ptg_lg_served(s.h, reqs, arr.ctypes.data_as(p64), 2, done.ctypes.data_as(p64), None) == ptg.PTG_EINVAL
+
+
+def _lattice_blocks(origin, extent, octaves, f0, lac=2.0):
+    """Lattice-cache blocks (32 x 32 nodes) covering a 2D request's footprint per octave:
+    nodes floor((X + 1/2) f) .. floor((X_last + 1/2) f) + 1 on each axis."""
+    import math
+    total, f = 0, f0
+    for _ in range(octaves):
+        nb = []
+        for a in range(2):
+            c0 = math.floor((origin[a] + 0.5) * f)
+            c1 = math.floor((origin[a] + extent[a] - 1 + 0.5) * f) + 1
+            nb.append((c1 >> 5) - (c0 >> 5) + 1)
+        total += nb[0] * nb[1]
+        f *= lac
+    return total
+
+
+def test_lattice_cache_blocks_are_shared_counted_and_evicted():
+    """General 2D requests hold their output and reference the 8 KiB blocks of their
+    footprint; a repeated request (same seed) finds them resident; released requests leave
+    the blocks resident until arena bytes are needed; strip requests use none."""
+    org, ext, octv, f0 = (5, -3, 0), (128, 100, 1), 6, 0.0137
+    out = 128 * 100 * 4
+    nb = _lattice_blocks(org, ext, octv, f0)
+    assert nb > octv
+    req = ptg.tile_req(dim=2, origin=org, extent=ext, octaves=octv, base_freq=f0, seed=11)
+    with ptg.Server(1 << 22, executor=ptg.PTG_EXEC_HOST, fake_tile_ns=1000, lattice_cache=1) as s:
+        (t1,) = s.submit([req])
+        r1 = s.wait(t1, 10_000_000_000)
+        assert r1.status == ptg.PTG_OK and r1.kernel == ptg.PTG_TUNE_GENERAL_2D and r1.bytes == out
+        st = s.stats()
+        assert (st["lat_misses"], st["lat_hits"], st["lat_blocks"]) == (nb, 0, nb)
+        assert st["bytes_in_use"] == out + nb * 8192 and st["lat_bytes"] == nb * 8192
+        assert st["tiles_done"] == 2 * 2  # fills are not tiles
+        (t2,) = s.submit([req])
+        assert s.wait(t2, 10_000_000_000).status == ptg.PTG_OK
+        st = s.stats()
+        assert (st["lat_misses"], st["lat_hits"], st["lat_blocks"]) == (nb, nb, nb)
+        assert st["bytes_in_use"] == 2 * out + nb * 8192
+        s.release(t1)
+        s.release(t2)
+        assert s.stats()["bytes_in_use"] == nb * 8192  # resident, unreferenced
+        # another seed: its own blocks; a strip request: none
+        (t3,) = s.submit([ptg.tile_req(dim=2, origin=org, extent=ext, octaves=octv, base_freq=f0, seed=12)])
+        (t4,) = s.submit([ptg.tile_req(dim=2, origin=org, extent=ext, octaves=octv, base_freq=2.0 ** -10, seed=11)])
+        assert s.wait(t3, 10_000_000_000).status == ptg.PTG_OK
+        assert s.wait(t4, 10_000_000_000).kernel == ptg.PTG_TUNE_STRIP_2D
+        st = s.stats()
+        assert (st["lat_misses"], st["lat_blocks"]) == (2 * nb, 2 * nb)
+        s.release(t3)
+        s.release(t4)
+    # eviction: a budget that holds one request's output and blocks; a large output evicts them
+    budget = out + nb * 8192 + 4096
+    with ptg.Server(budget, executor=ptg.PTG_EXEC_HOST, fake_tile_ns=1000, lattice_cache=1) as s:
+        (t1,) = s.submit([req])
+        assert s.wait(t1, 10_000_000_000).status == ptg.PTG_OK
+        s.release(t1)
+        big = ptg.tile_req(dim=2, extent=(256, (budget - 8192) // 1024, 1), octaves=3, base_freq=2.0 ** -10)
+        (t2,) = s.submit([big])
+        assert s.wait(t2, 10_000_000_000).status == ptg.PTG_OK
+        st = s.stats()
+        assert st["lat_evictions"] > 0 and st["bytes_peak"] <= budget
+        assert st["bytes_in_use"] == st["lat_bytes"] + 256 * ((budget - 8192) // 1024) * 4
+        s.release(t2)
+        (t3,) = s.submit([req])  # its blocks were evicted: filled again
+        assert s.wait(t3, 10_000_000_000).status == ptg.PTG_OK
+        assert s.stats()["lat_misses"] > nb
+    # a budget that holds the output but not its blocks: the request hashes instead
+    with ptg.Server(out + 256, executor=ptg.PTG_EXEC_HOST, fake_tile_ns=1000, lattice_cache=1) as s:
+        (t,) = s.submit([req])
+        assert s.wait(t, 10_000_000_000).status == ptg.PTG_OK
+        st = s.stats()
+        assert st["lat_misses"] == 0 and st["lat_blocks"] == 0
+    import ctypes
+    h = ctypes.c_void_p()
+    for cfg in (ptg.ServerCfg(1 << 20, 1024, 0, 0, ptg.PTG_EXEC_HOST, 0, 0, 0, 0, 2),
+                ptg.ServerCfg((1 << 40) + 256, 1024, 0, 0, ptg.PTG_EXEC_HOST, 0, 0, 0, 0, 1)):
+        assert ptg.lib().ptg_server_create(ctypes.byref(cfg), ctypes.byref(h)) == ptg.PTG_EINVAL
+
+
+def test_lattice_cache_waiting_requests_and_shutdown():
+    """Requests that share blocks still being filled wait for them; many overlapping
+    requests over a small budget all complete; shutdown with requests admitted and waiting
+    ends cleanly."""
+    f0 = 0.0113
+    reqs = [ptg.tile_req(dim=2, origin=(37 * i, -11 * i, 0), extent=(96, 80, 1), octaves=5, base_freq=f0, seed=5,
+                         smoothness=1 + i % 2) for i in range(24)]
+    per = 96 * 80 * 4 + _lattice_blocks((0, 0), (96 + 37 * 24, 80 + 11 * 24), 5, f0) * 8192
+    with ptg.Server(per, executor=ptg.PTG_EXEC_HOST, fake_tile_ns=2000, lattice_cache=1) as s:
+        left = set(s.submit(reqs))
+        t_end = time.time() + 20
+        while left and time.time() < t_end:  # completions in any order, released at once
+            for t in list(left):
+                try:
+                    res = s.wait(t, 0)
+                except ptg.PtgError as e:
+                    assert e.code == ptg.PTG_ETIMEDOUT
+                    continue
+                assert res.status == ptg.PTG_OK
+                s.release(t)
+                left.discard(t)
+            time.sleep(0.0005)
+        assert not left
+        st = s.stats()
+        assert st["completed"] == 24 and st["lat_hits"] > 0 and st["bytes_peak"] <= per
+    s = ptg.Server(1 << 24, executor=ptg.PTG_EXEC_HOST, fake_tile_ns=50000, lattice_cache=1)
+    s.submit(reqs)
+    time.sleep(0.002)
+    s.close()
