@@ -16,7 +16,7 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
     // LDS: [wl_key | wl_node] shared, then per wave [nodes (float2) | keys (u32)]
     uint32_t *wl_key = reinterpret_cast<uint32_t *>(lds4);
     uint32_t *wl_node = wl_key + a.keys_total;
-    const int shared_words = strip_shared_words(a.nodes_total, a.keys_total);
+    const int shared_words = strip_shared_words(a.nodes_hashed, a.keys_total);
     const int wave_words = strip_wave_words(a.nodes_total, a.keys_total);
     float2 *nodes = reinterpret_cast<float2 *>(reinterpret_cast<uint32_t *>(lds4) + shared_words + wave * wave_words);
 

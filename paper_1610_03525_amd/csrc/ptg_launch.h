@@ -86,9 +86,13 @@ struct Fbm2dStripArgs {
     float inv2p[kMaxOctaves];                       // 2^-(shift + 1)
     int32_t shift[kMaxOctaves];                     // period 2^shift; shift[o] = shift[0] - o
     int32_t nnx[kMaxOctaves], nny[kMaxOctaves];     // node columns / rows of a strip's footprint
-    int32_t noff[kMaxOctaves];                      // node block (column-major, nny rows)
+    int32_t noff[kMaxOctaves];                      // node block (column-major, nbr rows)
+    int32_t nbr[kMaxOctaves];                       // rows of the node block: nny, or for the
+                                                    // streamed periods (<= 2 in a ladder that
+                                                    // reaches them) one row segment's, R / P + 1
     int32_t kxoff[kMaxOctaves], kyoff[kMaxOctaves]; // column / row key offsets (all column keys first)
     int32_t nodes_total, keys_total, keys_col;      // keys [0, keys_col) are column keys
+    int32_t nodes_hashed;                           // nodes [0, nodes_hashed) are hashed per strip
     int32_t octaves;
     uint32_t seed;
     int32_t strips_x;
@@ -131,9 +135,9 @@ hipError_t launch_fbm2d_general(const Fbm2dArgs &a, int smooth, bool f16, size_t
 hipError_t launch_fbm2d_dyadic(const Fbm2dDyadicArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
 // LDS words of the strip kernel's work lists (shared by a workgroup) and of one wave's
 // private node block (node gradients, then keys).
-__host__ __device__ inline int strip_shared_words(int nodes_total, int keys_total)
+__host__ __device__ inline int strip_shared_words(int nodes_hashed, int keys_total)
 {
-    return (keys_total + nodes_total + 3) & ~3;
+    return (keys_total + nodes_hashed + 3) & ~3;
 }
 __host__ __device__ inline int strip_wave_words(int nodes_total, int keys_total)
 {

@@ -131,6 +131,11 @@ int strip_args_2d(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx
     if (smin <= 5 && k < 5) return 1;
     a.lo = std::min(smin, 6);
     int nodes = 0, keys = 0, kcol = 0;
+    // periods 2 and 1 (ladders that reach them) are streamed: their node rows are hashed per
+    // row segment (8 rows for cubic cells, 16 for quintic) into a block of that height,
+    // instead of per strip (65 x 65 nodes at period 1 would hold 34 KB of LDS per wave)
+    const int seg_rows = p->smoothness == 1 ? 8 : 16;
+    const bool stream = a.lo <= 1;
     for (int o = 0; o < p->octaves; ++o)  // column keys of every octave first, then row keys
         kcol += std::max(SW >> std::min(k - o, 30), 1) + 1;
     a.keys_col = kcol;
@@ -149,10 +154,13 @@ int strip_args_2d(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx
         if (sh == 0) a.o1 = o;
         a.nnx[o] = std::max(SW >> std::min(sh, 30), 1) + 1;
         a.nny[o] = std::max(SH >> std::min(sh, 30), 1) + 1;
+        const bool streamed = stream && sh <= 1;  // the finest octaves: they come last
+        a.nbr[o] = streamed ? (seg_rows >> sh) + 1 : a.nny[o];
         a.noff[o] = nodes;
         a.kxoff[o] = kcol;
         a.kyoff[o] = a.keys_col + (keys - kcol);
-        nodes += a.nnx[o] * a.nny[o];
+        nodes += a.nnx[o] * a.nbr[o];
+        if (!streamed) a.nodes_hashed = nodes;
         kcol += a.nnx[o];
         keys += a.nnx[o] + a.nny[o];
     }
@@ -169,7 +177,7 @@ static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
 {
     Fbm2dStripArgs a;
     if (strip_args_2d(p, k, x0, y0, nx, ny, out, pitch, &a)) return 1;
-    const size_t shared_words = (size_t)strip_shared_words(a.nodes_total, a.keys_total);
+    const size_t shared_words = (size_t)strip_shared_words(a.nodes_hashed, a.keys_total);
     const size_t wave_words = (size_t)strip_wave_words(a.nodes_total, a.keys_total);
     // waves per workgroup: the tuned count (default 4), at most what the private node
     // blocks allow in LDS

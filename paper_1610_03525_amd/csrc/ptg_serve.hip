@@ -152,7 +152,7 @@ __device__ __forceinline__ void serve_strips(const Fbm2dStripArgs &a, const Stri
                                              int64_t t1, int tid)
 {
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    float2 *nodes = reinterpret_cast<float2 *>(wl + strip_shared_words(a.nodes_total, a.keys_total) +
+    float2 *nodes = reinterpret_cast<float2 *>(wl + strip_shared_words(a.nodes_hashed, a.keys_total) +
                                                wave * strip_wave_words(a.nodes_total, a.keys_total));
     StripWave<M, float, LO> w(a, sh, nodes, lane);
     for (int64_t st = t0 + wave; st < t1; st += kServeWaves) w.run(a, sh, wl, wl + a.keys_total, st);
@@ -1020,7 +1020,7 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
         lds = 0;
     } else if (nd == 2 && dyadic_shift(p, &k) &&
         strip_args_2d(p, k, r->origin[0], r->origin[1], nx, ny, nullptr, nx, &sa) == 0 && sa.lo >= 1 &&
-        (size_t)(kStripSharedWords + strip_shared_words(sa.nodes_total, sa.keys_total) +
+        (size_t)(kStripSharedWords + strip_shared_words(sa.nodes_hashed, sa.keys_total) +
                  kServeWaves * strip_wave_words(sa.nodes_total, sa.keys_total)) * 4 <= kServeLds) {
         // dyadic ladder whose strip footprint fits a serving workgroup: the strip code
         *kernel = PTG_TUNE_STRIP_2D;

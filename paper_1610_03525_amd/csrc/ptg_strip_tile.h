@@ -31,7 +31,9 @@
 // Per strip the wave first hashes its own footprint nodes into a private LDS block (K1
 // logic: one key per node column and row, one fmix32 per node, unit gradients); the work
 // lists that map lanes to nodes are the same for every strip and are built once per
-// workgroup.
+// workgroup.  Periods 2 and 1 are streamed instead: each row segment hashes its own node
+// rows of those octaves into a block one segment high (a whole strip's 65 x 65 nodes at
+// period 1 would fill the LDS with one or two waves per CU).
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -167,10 +169,41 @@ struct Fixed {
     XA xa;
 };
 
+// A streamed octave (period P <= 2): its block (column-major, R / P + 1 rows) and the
+// offsets of its column and row keys in the wave's key block.
+struct Streamed {
+    float2 *blk;
+    int kx, ky;
+};
+
 struct RowCtx {
     Fixed f32, f16, f8, f4, f2, f1;
     int64_t pitch;
+    const uint32_t *keys;
+    Streamed s2, s1;
 };
+
+// Wave-private LDS written by some lanes and read by others: order the accesses (the LDS
+// serves one wave's requests in order; the fences keep the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Hash node rows [j0, j0 + NROWS) of a streamed octave (period P, strip-relative rows) into
+// rows [l0, l0 + NROWS) of its block (R / P + 1 rows): the same keys and gradients as the
+// per-strip hashing.
+template <int P, int R, int NROWS>
+__device__ __forceinline__ void stream_rows(const uint32_t *keys, const Streamed &st, int j0, int l0, int lane)
+{
+    constexpr int NB = R / P + 1, NNX = kStripW / P + 1, N = NNX * NROWS;
+    for (int q = lane; q < N; q += 64) {  // column-major: consecutive lanes, consecutive rows
+        const int i = q / NROWS, jj = q - i * NROWS;
+        st.blk[i * NB + l0 + jj] = grad2(key_combine(keys[st.ky + j0 + jj], keys[st.kx + i]));
+    }
+}
 
 // A node row collapsed along x at the lane's column: value term E and y-slope term Q.  The
 // cell between node rows lo and hi has the column form E0 = lo.E, dE = hi.E - lo.E,
@@ -236,6 +269,14 @@ struct SegRows {
         for (int j = 1; j <= R / P; ++j) n[j] = node_row<64 / P + 1>(f, r0 / P + j);
         carry = n[R / P];
     }
+    // streamed octave: the segment's rows are rows 1 .. R / P of its block
+    __device__ __forceinline__ void load_streamed(const Fixed &f, NR &carry)
+    {
+        n[0] = carry;
+#pragma unroll
+        for (int j = 1; j <= R / P; ++j) n[j] = node_row<R / P + 1>(f, j);
+        carry = n[R / P];
+    }
 };
 
 // The R rows [r0, r0 + R) of a strip, given the polynomial Cs of everything coarser than the
@@ -252,8 +293,14 @@ __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[
     SegRows<1, R> s1;
     if (D8) s8.load(x.f8, r0, carry[0]);
     if (D4) s4.load(x.f4, r0, carry[1]);
-    if (D2) s2.load(x.f2, r0, carry[2]);
-    if (D1) s1.load(x.f1, r0, carry[3]);
+    if (D2 || D1) {  // streamed periods: hash this segment's node rows first
+        wave_lds_sync();  // the previous segment has read its rows
+        if (D2) stream_rows<2, R, R / 2>(x.keys, x.s2, r0 / 2 + 1, 1, lane);
+        if (D1) stream_rows<1, R, R>(x.keys, x.s1, r0 + 1, 1, lane);
+        wave_lds_sync();
+    }
+    if (D2) s2.load_streamed(x.f2, carry[2]);
+    if (D1) s1.load_streamed(x.f1, carry[3]);
     // row pointers walk outwards from the centre pair (uniform, one add each per pair)
     OutT *pa = rp + (int64_t)(r0 + R / 2 - 1) * x.pitch, *pb = pa + x.pitch;
 #pragma unroll
@@ -309,11 +356,18 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
     constexpr int D1 = 2 * M + 2;
     constexpr bool H32 = LO <= 5, H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
     constexpr bool PIECE8 = H8 && M == 1;
+    constexpr int R = (M == 1 && H8) ? 8 : 16;  // row segment (streamed block height)
     NR carry[4];  // bottom node rows of the next segment: periods 8, 4, 2, 1
     if (H8) carry[0] = node_row<9>(x.f8, 0);
     if (H4) carry[1] = node_row<17>(x.f4, 0);
-    if (H2) carry[2] = node_row<33>(x.f2, 0);
-    if (H1) carry[3] = node_row<65>(x.f1, 0);
+    if (H2 || H1) {  // streamed periods: node row 0 of the strip into block row 0
+        wave_lds_sync();  // the previous strip has read its blocks
+        if (H2) stream_rows<2, R, 1>(x.keys, x.s2, 0, 0, lane);
+        if (H1) stream_rows<1, R, 1>(x.keys, x.s1, 0, 0, lane);
+        wave_lds_sync();
+    }
+    if (H2) carry[2] = node_row<R / 2 + 1>(x.f2, 0);
+    if (H1) carry[3] = node_row<R + 1>(x.f1, 0);
     NR n32[3], n16lo;
     if (H32) {
 #pragma unroll
@@ -363,7 +417,7 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
 // Per-octave constants a workgroup stages in LDS once (the strip code reads them from there).
 struct StripShared {
     uint32_t pre_key[kMaxOctaves];
-    int shift[kMaxOctaves], noff[kMaxOctaves];
+    int shift[kMaxOctaves], noff[kMaxOctaves], nbr[kMaxOctaves];
     float amp[kMaxOctaves], inv2p[kMaxOctaves];
 };
 
@@ -381,6 +435,7 @@ __device__ __forceinline__ void strip_prologue(const Fbm2dStripArgs &a, StripSha
             else
                 wl_key[ky + i - nnx] = ((uint32_t)o << 24) | (uint32_t)(i - nnx);
         }
+        if (no >= a.nodes_hashed) continue;  // streamed: hashed per row segment
         for (int q = tid; q < nnx * nny; q += nthreads) {  // byte offsets of the node's two keys
             const int i = q / nny, j = q - i * nny;          // column-major
             wl_node[no + q] = ((uint32_t)(ky + j) << 18) | ((uint32_t)(kx + i) << 2);
@@ -390,6 +445,7 @@ __device__ __forceinline__ void strip_prologue(const Fbm2dStripArgs &a, StripSha
         sh.pre_key[tid] = key_prefix(a.seed, tid);
         sh.shift[tid] = a.shift[tid];
         sh.noff[tid] = a.noff[tid];
+        sh.nbr[tid] = a.nbr[tid];
         sh.amp[tid] = a.amp[tid];
         sh.inv2p[tid] = a.inv2p[tid];
     }
@@ -415,10 +471,15 @@ struct StripWave {
         Fixed f{nodes, XA{0.0f, 0.0f, 0.0f, 0.0f}};
         if (o >= 0) {
             const int s = sh.shift[o];
-            f.col = nodes + sh.noff[o] + (lane >> s) * ((kStripH >> s) + 1);
+            f.col = nodes + sh.noff[o] + (lane >> s) * sh.nbr[o];
             f.xa = xweights<M>((float)(2 * (lane & ((1 << s) - 1)) + 1) * sh.inv2p[o], sh.amp[o]);
         }
         return f;
+    }
+
+    __device__ __forceinline__ Streamed streamed(const StripShared &sh, const Fbm2dStripArgs &a, int o) const
+    {
+        return o >= 0 ? Streamed{nodes + sh.noff[o], a.kxoff[o], a.kyoff[o]} : Streamed{nodes, 0, 0};
     }
 
     __device__ __forceinline__ StripWave(const Fbm2dStripArgs &a, const StripShared &sh, float2 *nodes_, int lane_)
@@ -427,14 +488,17 @@ struct StripWave {
         f64 = fixed(sh, a.o64);
         rc0 = RowCtx{fixed(sh, H32 ? a.o32 : -1), fixed(sh, H16 ? a.o16 : -1), fixed(sh, H8 ? a.o8 : -1),
                      fixed(sh, H4 ? a.o4 : -1),   fixed(sh, H2 ? a.o2 : -1),   fixed(sh, H1 ? a.o1 : -1),
-                     a.pitch};
+                     a.pitch,
+                     keys,
+                     streamed(sh, a, H2 ? a.o2 : -1),
+                     streamed(sh, a, H1 ? a.o1 : -1)};
     }
 
     // Strip st of the field: hash its footprint, sum its coarse octaves, write its rows.
     __device__ __forceinline__ void run(const Fbm2dStripArgs &a, const StripShared &sh, const uint32_t *wl_key,
                                         const uint32_t *wl_node, int64_t st)
     {
-        const int nodes_total = a.nodes_total, keys_total = a.keys_total, keys_col = a.keys_col;
+        const int nodes_hashed = a.nodes_hashed, keys_total = a.keys_total, keys_col = a.keys_col;
         const int64_t bsy = st / a.strips_x, bsx = st - bsy * a.strips_x;
         const int64_t X0 = a.sx_base + bsx * kStripW, Y0 = a.sy_base + bsy * kStripH;
 
@@ -456,7 +520,7 @@ struct StripWave {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const char *key_bytes = reinterpret_cast<const char *>(keys);
-        for (int q = lane; q < nodes_total; q += 64) {
+        for (int q = lane; q < nodes_hashed; q += 64) {
             const uint32_t it = wl_node[q];
             const uint32_t krow = *reinterpret_cast<const uint32_t *>(key_bytes + (it >> 16));
             const uint32_t kcol = *reinterpret_cast<const uint32_t *>(key_bytes + (it & 0xFFFFu));
