@@ -84,6 +84,7 @@ struct DyShared {
     uint32_t *wl_node;  // node work items: octave << 28 | ky offset << 14 | kx offset
     float2 *nodes;      // [nodes_total] amplitude-scaled (gx, gy), column-major per octave
     uint32_t *kx, *ky;  // key prefixes (per tile)
+    float2 *wblk;       // this wave's block of the periods 2 and 1 ([wave_nodes])
 };
 
 // ---------------------------------------------------------------------------------
@@ -197,34 +198,55 @@ __device__ __forceinline__ void mfma4_octave(f32x4 (&acc)[2][4], const Fbm2dDyad
 }
 
 // ---------------------------------------------------------------------------------
-// Octaves of period 2 and 1: VALU, each lane its own 4 rows x 1 column per sub-tile.
+// Octaves of period P = 2^S, S = 1 or 0: VALU, each lane its own 4 rows x 1 column per
+// sub-tile.  Their nodes (about one per sample) are not held for the whole tile: per
+// 16-row group each wave hashes the (64/P + 1) x (16/P + 1) nodes of its own columns
+// into a private block (the same keys and amplitude-scaled gradients as the tile's
+// shared block), then evaluates that group.
 // ---------------------------------------------------------------------------------
-template <int M>
-__device__ __forceinline__ void valu_octave(f32x4 (&acc)[2][4], const Fbm2dDyadicArgs &a, const DyShared &sh, int o,
-                                            int lane, int xw)
+__device__ __forceinline__ void dy_wave_sync()
 {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int M, int S>
+__device__ __forceinline__ void valu_octave(f32x4 (&acc)[2][4], const Fbm2dDyadicArgs &a, const DyShared &sh, int o,
+                                            float amp, int lane, int xw)
+{
+    constexpr int P = 1 << S;
+    constexpr int NB = (16 >> S) + 1, NC = (64 >> S) + 1;  // block rows, columns
     const int k = lane >> 4, m = lane & 15;
-    const int s = a.shift[o];
-    const int P = 1 << s;
-    const int nny = a.nny[o];
-    const float2 *nd = sh.nodes + a.noff[o];
+    float2 *blk = sh.wblk + a.soff[o];
+    const uint32_t *kx = sh.kx + a.pxoff[o] + (xw >> S), *ky = sh.ky + a.pyoff[o];
     const float4 bx = sh.tab[a.toff[o] + (m & (P - 1))];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const float4 yb = sh.tab[a.toff[o] + ((4 * k + v) & (P - 1))];
-#pragma unroll
-        for (int g = 0; g < 2; ++g)
+    for (int g = 0; g < 2; ++g) {
+        const int j0 = (16 * g) >> S;  // first node row of the group (tile-relative)
+        dy_wave_sync();                 // the previous group has read the block
+#pragma unroll 2
+        for (int q = lane; q < NC * NB; q += 64) {
+            const int i = q / NB, j = q - i * NB;  // column-major
+            const float2 gr = grad2(key_combine(ky[j0 + j], kx[i]));
+            blk[q] = make_float2(gr.x * amp, gr.y * amp);
+        }
+        dy_wave_sync();
+#pragma unroll 2  // fully unrolled, the group's 64 node loads were all hoisted (228 VGPRs)
+        for (int v = 0; v < 4; ++v) {
+            const float4 yb = sh.tab[a.toff[o] + ((4 * k + v) & (P - 1))];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const int cxl = (xw + 16 * c + m) >> s;
-                const float2 *q = nd + cxl * nny + ((16 * g + 4 * k + v) >> s);
-                const float2 n00 = q[0], n01 = q[1], n10 = q[nny], n11 = q[nny + 1];
+                const int cxl = (16 * c + m) >> S;  // column in the wave's block
+                const float2 *q = blk + cxl * NB + (((16 * g + 4 * k + v) >> S) - j0);
+                const float2 n00 = q[0], n01 = q[1], n10 = q[NB], n11 = q[NB + 1];
                 const float G0 = n00.y * yb.z + n01.y * yb.w;
                 const float G1 = n10.y * yb.z + n11.y * yb.w;
                 const float F0 = n00.x * yb.x + n01.x * yb.y;
                 const float F1 = n10.x * yb.x + n11.x * yb.y;
                 acc[g][c][v] += G0 * bx.x + G1 * bx.y + F0 * bx.z + F1 * bx.w;
             }
+        }
     }
 }
 
@@ -355,6 +377,11 @@ __global__ __launch_bounds__(256) void k_fbm2d_dyadic(const Fbm2dDyadicArgs a)
     sh.wl_node = sh.wl_pre + (a.px_total + a.py_total);
     sh.kx = sh.wl_node + a.nodes_total;
     sh.ky = sh.kx + a.px_total;
+    {  // per-wave blocks after the key prefixes, 8-byte aligned
+        const int words = (int)(sh.ky + a.py_total - reinterpret_cast<uint32_t *>(lds4));
+        sh.wblk = reinterpret_cast<float2 *>(reinterpret_cast<uint32_t *>(lds4) + ((words + 1) & ~1)) +
+                  (threadIdx.x >> 6) * a.wave_nodes;
+    }
     __shared__ uint32_t pre_key[kMaxOctaves];
     __shared__ int p_shift[kMaxOctaves], p_pxoff[kMaxOctaves], p_pyoff[kMaxOctaves];
     __shared__ float p_amp[kMaxOctaves];
@@ -388,6 +415,7 @@ __global__ __launch_bounds__(256) void k_fbm2d_dyadic(const Fbm2dDyadicArgs a)
         for (int i = tid; i < nnx + nny; i += NT)
             sh.wl_pre[a.pxoff[o] + a.pyoff[o] + i] =
                 ((uint32_t)o << 24) | (i < nnx ? (uint32_t)i : ((1u << 23) | (uint32_t)(i - nnx)));
+        if (a.shift[o] <= 1) continue;  // periods 2, 1: hashed per wave and row group
         for (int q = tid; q < nnx * nny; q += NT) {
             const int i = q / nny, j = q - i * nny;  // column-major
             sh.wl_node[a.noff[o] + q] =
@@ -448,7 +476,8 @@ __global__ __launch_bounds__(256) void k_fbm2d_dyadic(const Fbm2dDyadicArgs a)
         if (o < N && a.shift[o] == 4) mfma16_octave<M, 2>(acc, a, sh, o++, Xw, Yt0, lane, xw);
         if (o < N && a.shift[o] == 3) mfma4_octave<M, 3>(acc, a, sh, o++, lane, xw);
         if (o < N && a.shift[o] == 2) mfma4_octave<M, 2>(acc, a, sh, o++, lane, xw);
-        for (; o < N; ++o) valu_octave<M>(acc, a, sh, o, lane, xw);
+        if (o < N && a.shift[o] == 1) valu_octave<M, 1>(acc, a, sh, o, p_amp[o], lane, xw), ++o;
+        if (o < N && a.shift[o] == 0) valu_octave<M, 0>(acc, a, sh, o, p_amp[o], lane, xw), ++o;
 
         // ---- store: lane holds rows 4*(lane/16)+v of column lane%16 of each sub-tile -------
         OutT *out = reinterpret_cast<OutT *>(a.out);

@@ -58,6 +58,8 @@ struct Fbm2dDyadicArgs {
     int32_t shift[kMaxOctaves];
     int32_t nnx[kMaxOctaves], nny[kMaxOctaves];     // footprint nodes per axis
     int32_t noff[kMaxOctaves];                      // node-block offset of each octave
+    int32_t soff[kMaxOctaves];                      // periods 2, 1: offset in a wave's block
+    int32_t wave_nodes;                             // nodes of a wave's block (periods 2, 1)
     int32_t pxoff[kMaxOctaves], pyoff[kMaxOctaves]; // key-prefix offsets
     int32_t toff[kMaxOctaves];                      // basis-table offset, -1: no table
     int32_t nodes_total, px_total, py_total, tab_total, tab_first;

@@ -64,7 +64,7 @@ static int fbm2d_dyadic(const ptg_params *p, int k, int64_t x0, int64_t y0, int6
     a.seed = p->seed;
     a.prec = p->form == PTG_FORM_MFMA_F16 ? 1 : (p->form == PTG_FORM_MFMA_BF16 ? 2 : 0);
     a.basis = p->basis;
-    int nodes = 0, px = 0, py = 0, tab = 0;
+    int nodes = 0, px = 0, py = 0, tab = 0, wnodes = 0;
     a.tab_first = p->octaves;
     for (int o = 0; o < p->octaves; ++o) {
         const int sh = k - o;
@@ -76,7 +76,11 @@ static int fbm2d_dyadic(const ptg_params *p, int k, int64_t x0, int64_t y0, int6
         a.noff[o] = nodes;
         a.pxoff[o] = px;
         a.pyoff[o] = py;
-        nodes += a.nnx[o] * a.nny[o];
+        a.soff[o] = wnodes;
+        if (sh <= 1)  // periods 2, 1: each wave hashes its 64 columns one 16-row group at a time
+            wnodes += ((64 >> sh) + 1) * ((16 >> sh) + 1);
+        else
+            nodes += a.nnx[o] * a.nny[o];
         px += a.nnx[o];
         py += a.nny[o];
         if ((1 << sh) <= kDyTabMaxP) {
@@ -88,13 +92,14 @@ static int fbm2d_dyadic(const ptg_params *p, int k, int64_t x0, int64_t y0, int6
         }
     }
     a.nodes_total = nodes;
+    a.wave_nodes = wnodes;
     a.px_total = px;
     a.py_total = py;
     a.tab_total = tab;
     // workgroups: a few per compute unit, each walking tiles with a grid stride
     a.grid = (int32_t)std::min<int64_t>(a.tiles, (int64_t)device_cus() * 4);
     const size_t lds = (size_t)tab * 16 + (size_t)nodes * 8 + (size_t)(px + py) * 4 + (size_t)nodes * 4 +
-                       (size_t)(px + py) * 4;
+                       (size_t)(px + py) * 4 + 8 + (size_t)(kDyTileX / 64) * wnodes * 8;
     if (lds > kDyMaxLds) return 1;  // footprint too large for one workgroup: caller falls back
     (void)tune_pick(TuneKey{PTG_TUNE_DYADIC_2D, p->smoothness, p->out_dtype == PTG_F16, size_class(nx * ny), k}, 0);
     if (tune_dry()) return PTG_OK;
