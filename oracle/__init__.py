@@ -69,6 +69,14 @@ def lib():
     L.orc_fbm_points_3d.restype = _i32
     L.orc_perlin_2d.argtypes = [_i32, _i32, _f64, _f64, _f64, _u32, _i64, _i64, _i64, _i64, _pd, _i32]
     L.orc_perlin_2d.restype = _i32
+    L.orc_height2.argtypes = [_u32]
+    L.orc_height2.restype = _f64
+    L.orc_zg_cell.argtypes = [_pd, _f64, _f64]
+    L.orc_zg_cell.restype = _f64
+    L.orc_zg_fbm_2d.argtypes = [_i32, _f64, _f64, _f64, _u32, _i64, _i64, _i64, _i64, _pd, _i32]
+    L.orc_zg_fbm_2d.restype = _i32
+    L.orc_zg_fbm_points_2d.argtypes = [_i32, _f64, _f64, _f64, _u32, _pi64, _pi64, _i64, _pd, _i32]
+    L.orc_zg_fbm_points_2d.restype = _i32
     L.orc_max_threads.argtypes = []
     L.orc_max_threads.restype = _i32
     _LIB = L
@@ -233,6 +241,34 @@ def perlin_2d(fade_order, octaves, pers, lac, f0, seed, x0, y0, nx, ny, nthreads
     out = np.empty((ny, nx), dtype=np.float64)
     _chk(lib().orc_perlin_2d(fade_order, octaves, pers, lac, f0, seed & 0xFFFFFFFF, x0, y0, nx, ny,
                              _dp(out), nthreads))
+    return out
+
+
+# --- zero-gradient D2M1N3 (Sec. 3.3) ------------------------------------------
+
+def height2(key: int) -> float:
+    """Node height of the zero-gradient model, uniform on [-1, 1)."""
+    return float(lib().orc_height2(key & 0xFFFFFFFF))
+
+
+def zg_cell(h, x: float, y: float) -> float:
+    """Zero-gradient D2M1N3 cell at local (x, y); h = (h00, h10, h01, h11)."""
+    hh = np.ascontiguousarray(h, dtype=np.float64).reshape(4)
+    return float(lib().orc_zg_cell(_dp(hh), x, y))
+
+
+def zg_fbm_2d(octaves, pers, lac, f0, seed, x0, y0, nx, ny, nthreads=0) -> np.ndarray:
+    out = np.empty((ny, nx), dtype=np.float64)
+    _chk(lib().orc_zg_fbm_2d(octaves, pers, lac, f0, seed & 0xFFFFFFFF, x0, y0, nx, ny, _dp(out), nthreads))
+    return out
+
+
+def zg_fbm_points_2d(octaves, pers, lac, f0, seed, X, Y, nthreads=0) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.int64)
+    Y = np.ascontiguousarray(Y, dtype=np.int64)
+    out = np.empty(X.shape[0], dtype=np.float64)
+    _chk(lib().orc_zg_fbm_points_2d(octaves, pers, lac, f0, seed & 0xFFFFFFFF, _ip(X), _ip(Y), X.shape[0],
+                                    _dp(out), nthreads))
     return out
 
 

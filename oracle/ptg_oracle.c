@@ -20,6 +20,9 @@
  *  - Sec. 3.2: Perlin's blend (comparison path) with fade S3 (or S5, Sec. 5.1).
  *  - Sec. 4: the fBm octave sum, amplitude ratio (persistence) and frequency ratio
  *    (lacunarity) per octave.
+ *  - Sec. 3.3, eq. (zg): the zero-gradient D2M1N3 cell (random corner heights, zero
+ *    corner gradients), with the sign of its xy term read from the Sec. 3.1
+ *    coefficients (see orc_zg_cell).
  *
  * Readings taken where the paper is silent (each one is listed in the design notes):
  *  - Cell polynomial: the unique tensor polynomial of degree n = 2M+1 per axis whose
@@ -33,7 +36,8 @@
  *    cell = floor(u), local t = u - cell.
  *  - Lattice: a stated 32-bit hash of (node index, octave, seed) built from the
  *    MurmurHash3 32-bit finalizer (fmix32), mapped to a unit gradient (circle angle
- *    in 2D, Archimedes' cylinder map on the sphere in 3D).
+ *    in 2D, Archimedes' cylinder map on the sphere in 3D), or for the zero-gradient
+ *    model to a node height uniform on [-1, 1) from the same key's top 24 bits.
  *
  * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fopenmp -fPIC -shared
  */
@@ -477,6 +481,74 @@ int orc_perlin_2d(int32_t fade_order, int32_t octaves, double pers, double lac, 
             }
             out[j * nx + i] = H;
         }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Zero-gradient D2M1N3 (Sec. 3.3, eq. zg)                                   */
+/* ------------------------------------------------------------------------- */
+
+/* Node height of the zero-gradient model: uniform on [-1, 1) from the top 24 bits of
+ * the node's key, h = m / 2^23 - 1 (exact in binary). */
+double orc_height2(uint32_t key)
+{
+    return (double)(key >> 8) / 8388608.0 - 1.0;
+}
+
+/* D2M1N3 with all corner gradients zero (Sec. 3.3): with the corner heights
+ * h = {h00, h10, h01, h11}, dx = h10 - h00, dy = h01 - h00, A = h11 + h00 - h10 - h01
+ * and the smoothstep S3(t) = 3t^2 - 2t^3,
+ *   h(x, y) = h00 + S3(x) dx + S3(y) dy + A (S3(x) y + S3(y) x - x y).
+ * The paper prints the last term as +xy; the Sec. 3.1 coefficients with f = g = 0
+ * (c11 = -A, c21 = c12 = 3A, c31 = c13 = -2A) give -xy, which is also what makes
+ * h(1, 1) = h11.  That corrected form is the one evaluated here. */
+double orc_zg_cell(const double *h, double x, double y)
+{
+    double sx = x * x * (3.0 - 2.0 * x), sy = y * y * (3.0 - 2.0 * y);
+    double dx = h[1] - h[0], dy = h[2] - h[0], A = h[3] + h[0] - h[1] - h[2];
+    return h[0] + sx * dx + sy * dy + A * (sx * y + sy * x - x * y);
+}
+
+static double orc_zg_sample(int32_t octaves, const double *freq, const double *amp, uint32_t seed, int64_t X,
+                            int64_t Y)
+{
+    double H = 0.0;
+    for (int32_t o = 0; o < octaves; ++o) {
+        int64_t cx, cy;
+        double tx, ty, h[4];
+        orc_coord(X, freq[o], &cx, &tx);
+        orc_coord(Y, freq[o], &cy, &ty);
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) h[dx + 2 * dy] = orc_height2(orc_key2(cx + dx, cy + dy, o, seed));
+        H += amp[o] * orc_zg_cell(h, tx, ty);
+    }
+    return H;
+}
+
+/* Zero-gradient fBm over a row-major [ny][nx] field (same lattice, octave and
+ * coordinate conventions as orc_fbm_2d). */
+int orc_zg_fbm_2d(int32_t octaves, double pers, double lac, double f0, uint32_t seed, int64_t x0, int64_t y0,
+                  int64_t nx, int64_t ny, double *out, int32_t nthreads)
+{
+    if (orc_check(1, octaves, f0, lac, pers) != ORC_OK || nx < 0 || ny < 0 || !out) return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i) out[j * nx + i] = orc_zg_sample(octaves, freq, amp, seed, x0 + i, y0 + j);
+    return ORC_OK;
+}
+
+int orc_zg_fbm_points_2d(int32_t octaves, double pers, double lac, double f0, uint32_t seed, const int64_t *X,
+                         const int64_t *Y, int64_t n, double *out, int32_t nthreads)
+{
+    if (orc_check(1, octaves, f0, lac, pers) != ORC_OK || n < 0 || !X || !Y || !out) return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q) out[q] = orc_zg_sample(octaves, freq, amp, seed, X[q], Y[q]);
     return ORC_OK;
 }
 
