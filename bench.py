@@ -234,7 +234,8 @@ def _time_launches(torch, stream, fn, n=10):
 def other_configs(torch, ptg, stream):
     """3D 512^3 6-octave C2 volume; 16384^2 10-octave field at a world offset of 2^24 cells
     through the plain FP32 path and the FP16 / BF16 matrix-core form (their errors against
-    the FP64 oracle are measured by the GPU tests); 256^2 4-octave field (launch-bound)."""
+    the FP64 oracle are measured by the GPU tests); the zero-gradient model on the 8192^2
+    8-octave field (dyadic and general ladders); 256^2 4-octave field (launch-bound)."""
     res = {}
     sh = stream.cuda_stream
     # 3D 512^3, 6 octaves, base lattice 8^3, C2
@@ -265,6 +266,20 @@ def other_configs(torch, ptg, stream):
         "workload": "2D fBm 16384^2, 10 octaves, base lattice 32^2, world offset (2^24-3)*512, -(2^24-5)*512 "
                     "samples, C1; FP16 output for the matrix-core forms, FP32 for the plain path",
         "forms": forms}
+    # the zero-gradient model (Sec. 3.3) on the headline field: 8192^2, 8 octaves, base lattice 16^2
+    zf = torch.empty((8192, 8192), dtype=torch.float32, device="cuda")
+    zg = {}
+    for name, f0z, lac in (("dyadic (strip kernel)", 16 / 8192, 2.0), ("base 0.0031, lacunarity 2.1 (general)",
+                                                                      0.0031, 2.1)):
+        q = ptg.params(smoothness=1, octaves=8, base_freq=f0z, lacunarity=lac, seed=1, model="zero_gradient")
+        ms = _time_launches(torch, stream, lambda: ptg.fbm_2d_raw(q, 0, 0, 8192, 8192, zf.data_ptr(), 8192, sh), 10)
+        zg[name] = {"ms": ms, "octave_samples_s": 8192 * 8192 * 8 / (ms * 1e-3),
+                    "hbm_frac": 8192 * 8192 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    res["2d_8192_8oct_zero_gradient"] = {
+        "workload": "zero-gradient D2M1N3 (random node heights, zero corner gradients), 8192^2, 8 octaves, "
+                    "persistence 0.5, FP32, seed 1",
+        "ladders": zg}
+    del zf
     # 256^2, 4 octaves, base lattice 8^2
     small = torch.empty((256, 256), dtype=torch.float32, device="cuda")
     q = ptg.params(smoothness=1, octaves=4, base_freq=8 / 256, seed=1)

@@ -87,6 +87,16 @@ extern "C" {
 #define PTG_BASIS_MONOMIAL 0  /* V(t) = [1, t, t^2, t^3], C = monomial coefficients   */
 #define PTG_BASIS_CENTRED 1   /* V(t) = [1, s, s^2, s^3] with s = t - 1/2              */
 
+/* ---- cell models ------------------------------------------------------------ */
+#define PTG_MODEL_GRADIENT 0       /* value 0 and the lattice gradient at every corner     */
+                                   /* (Sec. 2 with zero heights; C1 or C2 across faces)    */
+#define PTG_MODEL_ZERO_GRADIENT 1  /* zero-gradient D2M1N3 (Sec. 3.3): a random height per */
+                                   /* node (uniform on [-1, 1) from the node's key: top 24  */
+                                   /* bits / 2^23 - 1), zero gradients at the corners;      */
+                                   /* continuous across faces, its gradient pinned at the   */
+                                   /* nodes only.  2D, smoothness 1, plain form, fields only */
+                                   /* (not served)                                          */
+
 /* Problem parameters (Sec. 2.2 DdMmNn naming: dim = d, smoothness = m, n = 2m+1;
  * Sec. 4: octaves, persistence, lacunarity). */
 typedef struct ptg_params {
@@ -102,6 +112,7 @@ typedef struct ptg_params {
     int32_t form;         /* PTG_FORM_*                                                */
     int32_t basis;        /* PTG_BASIS_* (MFMA forms only)                             */
     int32_t path;         /* PTG_PATH_*: kernel choice for the plain form              */
+    int32_t model;        /* PTG_MODEL_*                                               */
 } ptg_params;
 
 /* Library version string (static storage). */
@@ -141,6 +152,12 @@ PTG_API int ptg_fbm_3d(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, 
  * frac_dev[o*n + i] (float).  Errors: PTG_EINVAL, PTG_EHIP. */
 PTG_API int ptg_coords(double base_freq, double lacunarity, int32_t octaves, int64_t x0, int64_t n,
                int64_t *cells_dev, float *frac_dev, void *stream);
+
+/* a2. K1 for the zero-gradient model (Sec. 3.3): node heights of the node box
+ * ix0 <= ix < ix0+nx, iy0 <= iy < iy0+ny of octave `octave`, heights_dev[j*nx + i]
+ * (FP32, exact: top 24 key bits / 2^23 - 1).  Errors: PTG_EINVAL, PTG_EHIP. */
+PTG_API int ptg_heights_2d(uint32_t seed, int32_t octave, int64_t ix0, int64_t iy0, int64_t nx, int64_t ny,
+                   float *heights_dev, void *stream);
 
 /* a2. K1 lattice kernel, 2D: for the node box ix0 <= ix < ix0+nx, iy0 <= iy < iy0+ny of
  * octave `octave`: keys_dev[j*nx + i] (uint32, may be NULL) and the unit gradient,

@@ -32,6 +32,9 @@ PTG_F16 = 1
 FORMS = {"plain": 0, "mfma_f16": 1, "mfma_bf16": 2}
 BASES = {"monomial": 0, "centred": 1}
 PATHS = {"auto": 0, "general": 1, "dyadic": 2}
+MODELS = {"gradient": 0, "zero_gradient": 1}
+PTG_MODEL_GRADIENT = 0
+PTG_MODEL_ZERO_GRADIENT = 1
 
 
 class PtgError(RuntimeError):
@@ -53,6 +56,7 @@ class Params(ctypes.Structure):
         ("form", ctypes.c_int32),
         ("basis", ctypes.c_int32),
         ("path", ctypes.c_int32),
+        ("model", ctypes.c_int32),
     ]
 
 
@@ -140,6 +144,7 @@ def lib():
     L.ptg_coords.argtypes = [_f64, _f64, _i32, _i64, _i64, _vp, _vp, _vp]
     L.ptg_lattice_2d.argtypes = [_u32, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _vp]
     L.ptg_lattice_3d.argtypes = [_u32, _i32, _i64, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp]
+    L.ptg_heights_2d.argtypes = [_u32, _i32, _i64, _i64, _i64, _i64, _vp, _vp]
     L.ptg_cells_2d.argtypes = [_i32, _vp, _i64, _i64, _f32, _vp, _vp]
     L.ptg_cells_3d.argtypes = [_i32, _vp, _i64, _i64, _i64, _f32, _vp, _vp]
     L.ptg_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]
@@ -158,7 +163,7 @@ def lib():
     L.ptg_tune_set_3d.argtypes = [_PP, _i64, _i64, _i64, _i32]
     L.ptg_tune_reset.argtypes = []
     L.ptg_tune_reset.restype = None
-    for name in ("ptg_fbm_2d", "ptg_fbm_3d", "ptg_coords", "ptg_lattice_2d", "ptg_lattice_3d",
+    for name in ("ptg_fbm_2d", "ptg_fbm_3d", "ptg_coords", "ptg_lattice_2d", "ptg_lattice_3d", "ptg_heights_2d",
                  "ptg_cells_2d", "ptg_cells_3d", "ptg_server_create", "ptg_tiles_submit", "ptg_tiles_wait",
                  "ptg_tile_release", "ptg_server_stats_get", "ptg_server_destroy", "ptg_tune_2d", "ptg_tune_3d",
                  "ptg_tune_query_2d", "ptg_tune_query_3d", "ptg_tune_set_2d", "ptg_tune_set_3d"):
@@ -184,7 +189,7 @@ def _check(rc):
 
 
 def params(dim=2, smoothness=1, octaves=8, persistence=0.5, lacunarity=2.0, base_freq=1.0 / 512, seed=1,
-           out_dtype=PTG_F32, form="plain", basis="monomial", path="auto") -> Params:
+           out_dtype=PTG_F32, form="plain", basis="monomial", path="auto", model="gradient") -> Params:
     p = Params()
     p.dim = dim
     p.smoothness = smoothness
@@ -197,6 +202,7 @@ def params(dim=2, smoothness=1, octaves=8, persistence=0.5, lacunarity=2.0, base
     p.form = FORMS[form] if isinstance(form, str) else int(form)
     p.basis = BASES[basis] if isinstance(basis, str) else int(basis)
     p.path = PATHS[path] if isinstance(path, str) else int(path)
+    p.model = MODELS[model] if isinstance(model, str) else int(model)
     return p
 
 
@@ -274,6 +280,14 @@ def lattice_2d(seed, octave, ix0, iy0, keys_out=None, grad_out=None, stream=None
     kp = _dev_ptr(keys_out, torch.int32) if keys_out is not None else None
     gp = _dev_ptr(grad_out, torch.float32) if grad_out is not None else None
     _check(lib().ptg_lattice_2d(seed & 0xFFFFFFFF, octave, ix0, iy0, nx, ny, kp, gp, _stream(stream)))
+
+
+def heights_2d(seed, octave, ix0, iy0, out, stream=None):
+    """K1 of the zero-gradient model: node heights into out (ny, nx) float32."""
+    import torch
+    ny, nx = out.shape
+    _check(lib().ptg_heights_2d(seed & 0xFFFFFFFF, octave, ix0, iy0, nx, ny, _dev_ptr(out, torch.float32),
+                                _stream(stream)))
 
 
 def lattice_3d(seed, octave, ix0, iy0, iz0, keys_out=None, second_out=None, grad_out=None, stream=None):

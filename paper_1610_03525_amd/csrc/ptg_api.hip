@@ -51,6 +51,10 @@ int validate_params(const ptg_params *p, int dim)
         return fail(PTG_EINVAL, "unknown basis %d", p->basis);
     if (p->path != PTG_PATH_AUTO && p->path != PTG_PATH_GENERAL && p->path != PTG_PATH_DYADIC)
         return fail(PTG_EINVAL, "unknown path %d", p->path);
+    if (p->model != PTG_MODEL_GRADIENT && p->model != PTG_MODEL_ZERO_GRADIENT)
+        return fail(PTG_EINVAL, "unknown model %d", p->model);
+    if (p->model == PTG_MODEL_ZERO_GRADIENT && (dim != 2 || p->smoothness != 1 || p->form != PTG_FORM_PLAIN))
+        return fail(PTG_EINVAL, "the zero-gradient model is 2D, smoothness 1, plain form");
     double f = p->base_freq, a = 1.0;
     for (int o = 0; o < p->octaves; ++o) {
         if (!(f <= 1.0) || !(f > 0.0))
@@ -184,6 +188,18 @@ int ptg_lattice_2d(uint32_t seed, int32_t octave, int64_t ix0, int64_t iy0, int6
     hipError_t e = launch_lattice2d(seed, octave, ix0, iy0, nx, ny, keys_dev, grad_dev,
                                     reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? PTG_OK : hip_fail(e, "lattice2d launch");
+}
+
+int ptg_heights_2d(uint32_t seed, int32_t octave, int64_t ix0, int64_t iy0, int64_t nx, int64_t ny,
+                   float *heights_dev, void *stream)
+{
+    if (octave < 0) return fail(PTG_EINVAL, "octave < 0");
+    if (nx < 0 || ny < 0) return fail(PTG_EINVAL, "negative node box");
+    if (nx == 0 || ny == 0) return PTG_OK;
+    if (!heights_dev) return fail(PTG_EINVAL, "heights_dev is NULL");
+    if (nx > (1LL << 40) / ny || (nx * ny + 255) / 256 > 0x7FFFFFFFLL) return fail(PTG_EINVAL, "box too large");
+    hipError_t e = launch_heights2d(seed, octave, ix0, iy0, nx, ny, heights_dev, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PTG_OK : hip_fail(e, "heights2d launch");
 }
 
 int ptg_lattice_3d(uint32_t seed, int32_t octave, int64_t ix0, int64_t iy0, int64_t iz0, int64_t nx, int64_t ny,

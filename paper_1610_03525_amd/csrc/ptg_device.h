@@ -54,6 +54,10 @@ __device__ __forceinline__ float2 grad2(uint32_t key)
     return make_float2(__builtin_amdgcn_cosf(turns), __builtin_amdgcn_sinf(turns));
 }
 
+// Node height of the zero-gradient model (Sec. 3.3): m / 2^23 - 1 with m the key's top 24
+// bits, uniform on [-1, 1) and exact in FP32.
+__device__ __forceinline__ float height2(uint32_t key) { return (float)(key >> 8) * (1.0f / 8388608.0f) - 1.0f; }
+
 // 3D unit gradient: z = 1 - (2m+1)/2^24 (exact in FP32), azimuth from the second word,
 // radius sqrt((1-z)(1+z)).
 __device__ __forceinline__ float3 grad3(uint32_t key)

@@ -4,11 +4,11 @@
 
 namespace ptg {
 
-template <int M, typename OutT, int TH>
+template <int M, typename OutT, int TH, int MD = 0>
 __global__ __launch_bounds__(256) void k_fbm2d_general(const Fbm2dArgs a)
 {
     extern __shared__ float4 lds4[];
-    fbm2d_general_tile<M, OutT, TH>(a, blockIdx.x, lds4);
+    fbm2d_general_tile<M, OutT, TH, MD>(a, blockIdx.x, lds4);
 }
 
 template <int M, typename OutT>
@@ -33,6 +33,9 @@ static hipError_t launch_dyn(void (*kernel)(Args), dim3 grid, size_t lds, hipStr
 template <int TH>
 static hipError_t launch_2d_th(const Fbm2dArgs &a, int smooth, bool f16, dim3 grid, size_t lds, hipStream_t s)
 {
+    if (a.model == 1)  // zero-gradient model (smoothness 1, validated)
+        return f16 ? launch_dyn(k_fbm2d_general<1, __half, TH, 1>, grid, lds, s, a)
+                   : launch_dyn(k_fbm2d_general<1, float, TH, 1>, grid, lds, s, a);
     if (smooth == 1)
         return f16 ? launch_dyn(k_fbm2d_general<1, __half, TH>, grid, lds, s, a)
                    : launch_dyn(k_fbm2d_general<1, float, TH>, grid, lds, s, a);

@@ -5,7 +5,7 @@
 
 namespace ptg {
 
-template <int M, typename OutT, int LO>
+template <int M, typename OutT, int LO, int MD>
 __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
 {
     extern __shared__ float4 lds4[];
@@ -22,15 +22,15 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
 
     strip_prologue(a, sh, wl_key, wl_node, tid, nthreads);
     __syncthreads();
-    StripWave<M, OutT, LO> w(a, sh, nodes, lane);
+    StripWave<M, OutT, LO, MD> w(a, sh, nodes, lane);
     const int64_t nwaves = (int64_t)gridDim.x * wpg;
     for (int64_t st = (int64_t)blockIdx.x * wpg + wave; st < a.strips; st += nwaves) w.run(a, sh, wl_key, wl_node, st);
 }
 
-template <int M, typename OutT, int LO>
+template <int M, typename OutT, int LO, int MD>
 static hipError_t launch_st(const Fbm2dStripArgs &a, int grid, int waves, size_t lds, hipStream_t s)
 {
-    auto kern = k_fbm2d_strip<M, OutT, LO>;
+    auto kern = k_fbm2d_strip<M, OutT, LO, MD>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -40,55 +40,60 @@ static hipError_t launch_st(const Fbm2dStripArgs &a, int grid, int waves, size_t
     return hipGetLastError();
 }
 
-template <int M, typename OutT>
+template <int M, typename OutT, int MD>
 static hipError_t launch_lo(const Fbm2dStripArgs &a, int grid, int waves, size_t lds, hipStream_t s)
 {
     switch (a.lo) {
-    case 0: return launch_st<M, OutT, 0>(a, grid, waves, lds, s);
-    case 1: return launch_st<M, OutT, 1>(a, grid, waves, lds, s);
-    case 2: return launch_st<M, OutT, 2>(a, grid, waves, lds, s);
-    case 3: return launch_st<M, OutT, 3>(a, grid, waves, lds, s);
-    case 4: return launch_st<M, OutT, 4>(a, grid, waves, lds, s);
-    case 5: return launch_st<M, OutT, 5>(a, grid, waves, lds, s);
-    default: return launch_st<M, OutT, 6>(a, grid, waves, lds, s);
+    case 0: return launch_st<M, OutT, 0, MD>(a, grid, waves, lds, s);
+    case 1: return launch_st<M, OutT, 1, MD>(a, grid, waves, lds, s);
+    case 2: return launch_st<M, OutT, 2, MD>(a, grid, waves, lds, s);
+    case 3: return launch_st<M, OutT, 3, MD>(a, grid, waves, lds, s);
+    case 4: return launch_st<M, OutT, 4, MD>(a, grid, waves, lds, s);
+    case 5: return launch_st<M, OutT, 5, MD>(a, grid, waves, lds, s);
+    default: return launch_st<M, OutT, 6, MD>(a, grid, waves, lds, s);
     }
 }
 
-template <int M, typename OutT, int LO>
+template <int M, typename OutT, int LO, int MD>
 static int resident_one(int waves, size_t lds)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, LO>, 64 * waves, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, LO, MD>, 64 * waves, lds) !=
+        hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
 
-template <int M, typename OutT>
+template <int M, typename OutT, int MD>
 static int resident_st(int lo, int waves, size_t lds)
 {
     switch (lo) {
-    case 0: return resident_one<M, OutT, 0>(waves, lds);
-    case 1: return resident_one<M, OutT, 1>(waves, lds);
-    case 2: return resident_one<M, OutT, 2>(waves, lds);
-    case 3: return resident_one<M, OutT, 3>(waves, lds);
-    case 4: return resident_one<M, OutT, 4>(waves, lds);
-    case 5: return resident_one<M, OutT, 5>(waves, lds);
-    default: return resident_one<M, OutT, 6>(waves, lds);
+    case 0: return resident_one<M, OutT, 0, MD>(waves, lds);
+    case 1: return resident_one<M, OutT, 1, MD>(waves, lds);
+    case 2: return resident_one<M, OutT, 2, MD>(waves, lds);
+    case 3: return resident_one<M, OutT, 3, MD>(waves, lds);
+    case 4: return resident_one<M, OutT, 4, MD>(waves, lds);
+    case 5: return resident_one<M, OutT, 5, MD>(waves, lds);
+    default: return resident_one<M, OutT, 6, MD>(waves, lds);
     }
 }
 
-int strip_wgs_per_cu(int smooth, bool f16, int lo, int waves, size_t lds)
+// model 1 (zero-gradient) is smoothness 1 only
+int strip_wgs_per_cu(int smooth, int model, bool f16, int lo, int waves, size_t lds)
 {
-    if (smooth == 1) return f16 ? resident_st<1, __half>(lo, waves, lds) : resident_st<1, float>(lo, waves, lds);
-    return f16 ? resident_st<2, __half>(lo, waves, lds) : resident_st<2, float>(lo, waves, lds);
+    if (model == 1) return f16 ? resident_st<1, __half, 1>(lo, waves, lds) : resident_st<1, float, 1>(lo, waves, lds);
+    if (smooth == 1) return f16 ? resident_st<1, __half, 0>(lo, waves, lds) : resident_st<1, float, 0>(lo, waves, lds);
+    return f16 ? resident_st<2, __half, 0>(lo, waves, lds) : resident_st<2, float, 0>(lo, waves, lds);
 }
 
-hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, bool f16, int grid, int waves, size_t lds,
-                              hipStream_t s)
+hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, int model, bool f16, int grid, int waves,
+                              size_t lds, hipStream_t s)
 {
+    if (model == 1)
+        return f16 ? launch_lo<1, __half, 1>(a, grid, waves, lds, s) : launch_lo<1, float, 1>(a, grid, waves, lds, s);
     if (smooth == 1)
-        return f16 ? launch_lo<1, __half>(a, grid, waves, lds, s) : launch_lo<1, float>(a, grid, waves, lds, s);
-    return f16 ? launch_lo<2, __half>(a, grid, waves, lds, s) : launch_lo<2, float>(a, grid, waves, lds, s);
+        return f16 ? launch_lo<1, __half, 0>(a, grid, waves, lds, s) : launch_lo<1, float, 0>(a, grid, waves, lds, s);
+    return f16 ? launch_lo<2, __half, 0>(a, grid, waves, lds, s) : launch_lo<2, float, 0>(a, grid, waves, lds, s);
 }
 
 }  // namespace ptg

@@ -61,7 +61,11 @@ struct LatCache {
 // 2D: tile 64 x TH samples (TH = 16, 32 or 64 rows), 4 waves x TH/4 rows.
 // LDS: row table float4[TH] | gx[capx*capy] | gy[capx*capy] | kx[capx] | ky[capy]
 // ---------------------------------------------------------------------------------
-template <int M, typename OutT, int TH>
+// MD = 1: the zero-gradient model (Sec. 3.3; M = 1): gx holds the node heights, and a
+// cell at the lane's column x is E0 + dE S(y) + dQ (y - S(y)) with, per node row j,
+// E_j = h0j + S(x) D_j, Q_j = (S(x) - x) D_j, D_j = h1j - h0j; y - S(y) = b10(y) + b11(y),
+// so the row evaluation is the gradient model's with Q0 = Q1 = dQ.
+template <int M, typename OutT, int TH, int MD = 0>
 __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t bid, float4 *lds4,
                                                    const LatCache *lat = nullptr)
 {
@@ -138,6 +142,11 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
                     }
                 }
             }
+        } else if (MD == 1) {
+            for (int q = tid; q < nnx * nny; q += 256) {
+                const int j = q / nnx, i = q - j * nnx;
+                gx[q] = height2(key_combine(ky[j], kx[i])) * amp;
+            }
         } else {
             for (int q = tid; q < nnx * nny; q += 256) {
                 const int j = q / nnx, i = q - j * nnx;
@@ -158,7 +167,16 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
         for (int r = 0; r < RPT; ++r) {
             const float4 re = rowt[wave * RPT + r];
             const int lcy = __builtin_amdgcn_readfirstlane(__float_as_int(re.x));
-            if (lcy != prev) {
+            if (lcy != prev && MD == 1) {
+                prev = lcy;
+                const int q = lcy * nnx + lcx;
+                const float h00 = gx[q], h10 = gx[q + 1], h01 = gx[q + nnx], h11 = gx[q + nnx + 1];
+                const float d0 = h10 - h00, d1 = h11 - h01;
+                E0 = h00 + sx * d0;
+                dE = (h01 + sx * d1) - E0;
+                Q0 = (sx - cc.t) * (d1 - d0);
+                Q1 = Q0;
+            } else if (lcy != prev) {
                 prev = lcy;
                 const int q = lcy * nnx + lcx;
                 const float fx00 = gx[q], fx10 = gx[q + 1], fx01 = gx[q + nnx], fx11 = gx[q + nnx + 1];

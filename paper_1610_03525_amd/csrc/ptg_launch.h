@@ -25,6 +25,7 @@ struct Fbm2dArgs {
     int32_t capx, capy;  // LDS footprint capacity (nodes per axis) for every octave
     int32_t tiles_x;     // tiles per row of the tile grid
     int32_t tile_h;      // rows per tile: 16, 32 or 64 (tile shape chosen by the tuner)
+    int32_t model;       // PTG_MODEL_*
 };
 
 struct Fbm3dArgs {
@@ -157,9 +158,9 @@ __host__ __device__ inline int strip3_wave_words(int nodes_total, int keys_total
     return (3 * nodes_total + keys_total + 3) & ~3;
 }
 
-hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, bool f16, int grid, int waves, size_t lds_bytes,
+hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, int model, bool f16, int grid, int waves, size_t lds_bytes,
                               hipStream_t s);
-int strip_wgs_per_cu(int smooth, bool f16, int lo, int waves, size_t lds_bytes);  // resident workgroups per CU
+int strip_wgs_per_cu(int smooth, int model, bool f16, int lo, int waves, size_t lds_bytes);  // resident WGs per CU
 hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fbm3d_strip(const Fbm3dStripArgs &a, int smooth, bool f16, int grid, int waves, size_t lds_bytes,
                               hipStream_t s);
@@ -169,6 +170,8 @@ hipError_t launch_coords(double f0, double lac, int octaves, int64_t x0, int64_t
                          hipStream_t s);
 hipError_t launch_lattice2d(uint32_t seed, int octave, int64_t ix0, int64_t iy0, int64_t nx, int64_t ny,
                             uint32_t *keys, float *grad, hipStream_t s);
+hipError_t launch_heights2d(uint32_t seed, int octave, int64_t ix0, int64_t iy0, int64_t nx, int64_t ny,
+                            float *heights, hipStream_t s);
 hipError_t launch_lattice3d(uint32_t seed, int octave, int64_t ix0, int64_t iy0, int64_t iz0, int64_t nx,
                             int64_t ny, int64_t nz, uint32_t *keys, uint32_t *second, float *grad, hipStream_t s);
 hipError_t launch_cells2d(int smooth, const float *grad, int64_t nnx, int64_t nny, float amp, float *coeff,

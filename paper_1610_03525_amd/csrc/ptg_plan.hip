@@ -186,8 +186,8 @@ static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
     const size_t wave_words = (size_t)strip_wave_words(a.nodes_total, a.keys_total);
     // waves per workgroup: the tuned count (default 4), at most what the private node
     // blocks allow in LDS
-    int waves = tune_pick(TuneKey{PTG_TUNE_STRIP_2D, p->smoothness, p->out_dtype == PTG_F16, size_class(nx * ny),
-                                  a.lo},
+    int waves = tune_pick(TuneKey{PTG_TUNE_STRIP_2D, p->smoothness + 2 * p->model, p->out_dtype == PTG_F16,
+                                  size_class(nx * ny), a.lo},
                           kStripWavesPerWg);
     while (waves > 1 && (shared_words + waves * wave_words) * 4 > kDyMaxLds) --waves;
     const size_t lds = (shared_words + waves * wave_words) * 4;
@@ -195,10 +195,10 @@ static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
     if (tune_dry()) return PTG_OK;
     // a persistent grid of exactly the resident workgroups (a partial second round would
     // leave most of the chip idle at the end)
-    const int64_t per_cu = strip_wgs_per_cu(p->smoothness, p->out_dtype == PTG_F16, a.lo, waves, lds);
+    const int64_t per_cu = strip_wgs_per_cu(p->smoothness, p->model, p->out_dtype == PTG_F16, a.lo, waves, lds);
     const int64_t wgs = (a.strips + waves - 1) / waves;
     const int grid = (int)std::min<int64_t>(wgs, (int64_t)device_cus() * per_cu);
-    hipError_t e = launch_fbm2d_strip(a, p->smoothness, p->out_dtype == PTG_F16, grid, waves, lds, s);
+    hipError_t e = launch_fbm2d_strip(a, p->smoothness, p->model, p->out_dtype == PTG_F16, grid, waves, lds, s);
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d strip launch");
 }
 
@@ -216,6 +216,7 @@ size_t general_args_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, 
     a->octaves = p->octaves;
     a->seed = p->seed;
     a->tile_h = tile_h;
+    a->model = p->model;
     a->capx = footprint_cap(a->freq, p->octaves, kTile2);
     a->capy = footprint_cap(a->freq, p->octaves, tile_h);
     a->tiles_x = (int32_t)((nx + kTile2 - 1) / kTile2);
@@ -255,8 +256,10 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     if (dy && p->path != PTG_PATH_GENERAL) {
         int rc = fbm2d_strip(p, k, x0, y0, nx, ny, out, pitch, s);
         if (rc <= 0) return rc;
-        rc = fbm2d_dyadic(p, k, x0, y0, nx, ny, out, pitch, s);
-        if (rc <= 0) return rc;
+        if (p->model == PTG_MODEL_GRADIENT) {  // the matrix-core tile kernel has no zero-gradient cells
+            rc = fbm2d_dyadic(p, k, x0, y0, nx, ny, out, pitch, s);
+            if (rc <= 0) return rc;
+        }
         if (p->path == PTG_PATH_DYADIC)
             return fail(PTG_EINVAL, "the dyadic kernel's lattice footprint exceeds the workgroup's LDS");
     }
@@ -264,7 +267,7 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     double freq[kMaxOctaves];
     float amp[kMaxOctaves];
     octave_tables(p, freq, amp);
-    const int tile_h = tune_pick(TuneKey{PTG_TUNE_GENERAL_2D, p->smoothness, p->out_dtype == PTG_F16,
+    const int tile_h = tune_pick(TuneKey{PTG_TUNE_GENERAL_2D, p->smoothness + 2 * p->model, p->out_dtype == PTG_F16,
                                          size_class(nx * ny), ladder_class(freq, p->octaves)},
                                  kTile2);
     const size_t lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, tile_h, &a);

@@ -66,6 +66,16 @@ __global__ __launch_bounds__(256) void k_lattice2d(uint32_t seed, int octave, in
     }
 }
 
+// Zero-gradient model (Sec. 3.3): the node heights of a 2D node box.
+__global__ __launch_bounds__(256) void k_heights2d(uint32_t seed, int octave, int64_t ix0, int64_t iy0, int64_t nx,
+                                                   int64_t ny, float *__restrict__ h)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= nx * ny) return;
+    const int64_t j = q / nx, i = q - j * nx;
+    h[q] = height2(key_combine(absorb_index(key_prefix(seed, octave), iy0 + j), key_xline(ix0 + i)));
+}
+
 __global__ __launch_bounds__(256) void k_lattice3d(uint32_t seed, int octave, int64_t ix0, int64_t iy0, int64_t iz0,
                                                    int64_t nx, int64_t ny, int64_t nz, uint32_t *__restrict__ keys,
                                                    uint32_t *__restrict__ second, float *__restrict__ grad)
@@ -93,6 +103,15 @@ hipError_t launch_lattice2d(uint32_t seed, int octave, int64_t ix0, int64_t iy0,
     const int64_t n = nx * ny;
     hipLaunchKernelGGL(k_lattice2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed, octave, ix0, iy0, nx,
                        ny, keys, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_heights2d(uint32_t seed, int octave, int64_t ix0, int64_t iy0, int64_t nx, int64_t ny,
+                            float *heights, hipStream_t s)
+{
+    const int64_t n = nx * ny;
+    hipLaunchKernelGGL(k_heights2d, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, seed, octave, ix0, iy0, nx,
+                       ny, heights);
     return hipGetLastError();
 }
 

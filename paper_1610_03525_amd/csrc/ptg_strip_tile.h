@@ -74,10 +74,12 @@ struct XA {
     float q0, q1, e0, e1;
 };
 
-template <int M>
+template <int M, int MD = 0>
 __device__ __forceinline__ XA xweights(float t, float amp)
 {
     const XB b = xbases<M>(t);
+    if (MD == 1)  // zero-gradient model: the nodes hold heights (E = h0 + S D, Q = (S - t) D)
+        return XA{amp * (t - b.s), amp * (b.s - t), amp * (1.0f - b.s), amp * b.s};
     return XA{amp * (1.0f - b.s), amp * b.s, amp * b.b10, amp * b.b11};
 }
 
@@ -99,6 +101,9 @@ struct CF {  // column form of one cell at one column
 };
 
 // nb -> node (cx, cy) of the cell; (cx, cy + 1) follows, column cx + 1 is nny further.
+// Zero-gradient model (MD = 1, Sec. 3.3): the cell is E0 + dE S(t) + dQ (t - S(t)) and
+// t - S(t) = b10(t) + b11(t), i.e. the gradient form with Q0 = Q1 = dQ.
+template <int MD = 0>
 __device__ __forceinline__ CF column_form(const float2 *nb, int nny, const XA &xa)
 {
     const float2 n00 = nb[0], n01 = nb[1], n10 = nb[nny], n11 = nb[nny + 1];
@@ -108,6 +113,7 @@ __device__ __forceinline__ CF column_form(const float2 *nb, int nny, const XA &x
     c.dE = E1 - c.E0;
     c.Q0 = n00.y * xa.q0 + n10.y * xa.q1;
     c.Q1 = n01.y * xa.q0 + n11.y * xa.q1;
+    if (MD == 1) c.Q0 = c.Q1 = c.Q1 - c.Q0;
     return c;
 }
 
@@ -169,6 +175,18 @@ struct Fixed {
     XA xa;
 };
 
+// A node's LDS entry: its unit gradient, or for the zero-gradient model its height in both
+// components (the node-row collapse then reads the height for E and for Q).
+template <int MD>
+__device__ __forceinline__ float2 node_value(uint32_t key)
+{
+    if (MD == 1) {
+        const float h = height2(key);
+        return make_float2(h, h);
+    }
+    return grad2(key);
+}
+
 // A streamed octave (period P <= 2): its block (column-major, R / P + 1 rows) and the
 // offsets of its column and row keys in the wave's key block.
 struct Streamed {
@@ -195,13 +213,13 @@ __device__ __forceinline__ void wave_lds_sync()
 // Hash node rows [j0, j0 + NROWS) of a streamed octave (period P, strip-relative rows) into
 // rows [l0, l0 + NROWS) of its block (R / P + 1 rows): the same keys and gradients as the
 // per-strip hashing.
-template <int P, int R, int NROWS>
+template <int P, int R, int NROWS, int MD = 0>
 __device__ __forceinline__ void stream_rows(const uint32_t *keys, const Streamed &st, int j0, int l0, int lane)
 {
     constexpr int NB = R / P + 1, NNX = kStripW / P + 1, N = NNX * NROWS;
     for (int q = lane; q < N; q += 64) {  // column-major: consecutive lanes, consecutive rows
         const int i = q / NROWS, jj = q - i * NROWS;
-        st.blk[i * NB + l0 + jj] = grad2(key_combine(keys[st.ky + j0 + jj], keys[st.kx + i]));
+        st.blk[i * NB + l0 + jj] = node_value<MD>(key_combine(keys[st.ky + j0 + jj], keys[st.kx + i]));
     }
 }
 
@@ -222,14 +240,20 @@ __device__ __forceinline__ NR node_row(const Fixed &f, int j)
 // Add the cell between node rows lo and hi, as a polynomial in the segment coordinate w
 // (t - 1/2 = SIG w: the cell is centred on the segment), to C.  The constants are the
 // centred power coefficients of the bases listed at add_mapped, times SIG^b.
-template <int M, int SIG>
+template <int M, int SIG, int MD = 0>
 __device__ __forceinline__ void add_piece(float (&C)[2 * M + 2], const NR &lo, const NR &hi)
 {
     constexpr float s1 = (float)SIG, s2 = s1 * s1, s3 = s2 * s1, s4 = s3 * s1, s5 = s4 * s1;
     const float dE = hi.E - lo.E, Sq = lo.Q + hi.Q, Dq = lo.Q - hi.Q;
     C[0] += lo.E;
     C[0] = __builtin_fmaf(dE, 0.5f, C[0]);
-    if (M == 1) {
+    if (MD == 1) {  // zero-gradient model (M = 1): Q0 = Q1 = dQ, so Dq = 0 and Sq = 2 dQ
+        const float dQ = hi.Q - lo.Q;
+        C[1] = __builtin_fmaf(dE, 1.5f * s1, C[1]);
+        C[1] = __builtin_fmaf(dQ, -0.5f * s1, C[1]);
+        C[3] = __builtin_fmaf(dQ, 2.0f * s3, C[3]);
+        C[3] = __builtin_fmaf(dE, -2.0f * s3, C[3]);
+    } else if (M == 1) {
         C[0] = __builtin_fmaf(Dq, 0.125f, C[0]);
         C[1] = __builtin_fmaf(dE, 1.5f * s1, C[1]);
         C[1] = __builtin_fmaf(Sq, -0.25f * s1, C[1]);
@@ -250,9 +274,11 @@ __device__ __forceinline__ void add_piece(float (&C)[2 * M + 2], const NR &lo, c
 }
 
 // val += dE S + Q0 b10 + Q1 b11 at one row (E0 is in the constant term), as an FMA chain.
+template <int MD = 0>
 __device__ __forceinline__ float add_direct(float val, const NR &lo, const NR &hi, const XB &rb)
 {
     val = __builtin_fmaf(hi.E - lo.E, rb.s, val);
+    if (MD == 1) return __builtin_fmaf(hi.Q - lo.Q, rb.b10 + rb.b11, val);  // zero-gradient: t - S(t)
     val = __builtin_fmaf(lo.Q, rb.b10, val);
     return __builtin_fmaf(hi.Q, rb.b11, val);
 }
@@ -283,7 +309,7 @@ struct SegRows {
 // direct octaves, centred on the segment (row k at w = (2 k - R + 1) / 128).  Rows are taken
 // in pairs symmetric about the centre, w and -w, from the even and odd parts of Cs; the
 // direct octaves' E0 terms go into each row's constant term, the rest is 3 FMA per octave.
-template <int M, typename OutT, int R, bool D8, bool D4, bool D2, bool D1, bool FULL>
+template <int M, typename OutT, int R, bool D8, bool D4, bool D2, bool D1, bool FULL, int MD = 0>
 __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[2 * M + 2], int r0, NR (&carry)[4],
                                              OutT *rp, int lane, int rlo, int rhi, bool lane_ok)
 {
@@ -295,8 +321,8 @@ __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[
     if (D4) s4.load(x.f4, r0, carry[1]);
     if (D2 || D1) {  // streamed periods: hash this segment's node rows first
         wave_lds_sync();  // the previous segment has read its rows
-        if (D2) stream_rows<2, R, R / 2>(x.keys, x.s2, r0 / 2 + 1, 1, lane);
-        if (D1) stream_rows<1, R, R>(x.keys, x.s1, r0 + 1, 1, lane);
+        if (D2) stream_rows<2, R, R / 2, MD>(x.keys, x.s2, r0 / 2 + 1, 1, lane);
+        if (D1) stream_rows<1, R, R, MD>(x.keys, x.s1, r0 + 1, 1, lane);
         wave_lds_sync();
     }
     if (D2) s2.load_streamed(x.f2, carry[2]);
@@ -326,10 +352,10 @@ __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[
             if (D1) c0 += s1.n[k].E;
             float val = __builtin_fmaf(M == 1 ? Cs[2] : even2, w2, c0);
             val = __builtin_fmaf(side ? w : -w, odd, val);
-            if (D8) val = add_direct(val, s8.n[k / 8], s8.n[k / 8 + 1], row_bases<M>(row & 7, 8));
-            if (D4) val = add_direct(val, s4.n[k / 4], s4.n[k / 4 + 1], row_bases<M>(row & 3, 4));
-            if (D2) val = add_direct(val, s2.n[k / 2], s2.n[k / 2 + 1], row_bases<M>(row & 1, 2));
-            if (D1) val = add_direct(val, s1.n[k], s1.n[k + 1], row_bases<M>(0, 1));
+            if (D8) val = add_direct<MD>(val, s8.n[k / 8], s8.n[k / 8 + 1], row_bases<M>(row & 7, 8));
+            if (D4) val = add_direct<MD>(val, s4.n[k / 4], s4.n[k / 4 + 1], row_bases<M>(row & 3, 4));
+            if (D2) val = add_direct<MD>(val, s2.n[k / 2], s2.n[k / 2 + 1], row_bases<M>(row & 1, 2));
+            if (D1) val = add_direct<MD>(val, s1.n[k], s1.n[k + 1], row_bases<M>(0, 1));
             OutT *const rrow = side ? pb : pa;
             if (FULL || (row >= rlo && row < rhi && lane_ok)) rrow[lane] = st_out<OutT>(val);
         }
@@ -349,7 +375,7 @@ __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[
 // cost less than evaluating the octave on its own at every row; for quintic cells (15 FMA
 // per re-centring) period 8 stays a direct octave.  No piece is evaluated away from its own
 // cell.  FULL = every sample of the strip is stored.
-template <int M, typename OutT, int LO, bool FULL>
+template <int M, typename OutT, int LO, bool FULL, int MD = 0>
 __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 * M + 2], OutT *rp, int lane, int rlo,
                                            int rhi, bool lane_ok)
 {
@@ -362,8 +388,8 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
     if (H4) carry[1] = node_row<17>(x.f4, 0);
     if (H2 || H1) {  // streamed periods: node row 0 of the strip into block row 0
         wave_lds_sync();  // the previous strip has read its blocks
-        if (H2) stream_rows<2, R, 1>(x.keys, x.s2, 0, 0, lane);
-        if (H1) stream_rows<1, R, 1>(x.keys, x.s1, 0, 0, lane);
+        if (H2) stream_rows<2, R, 1, MD>(x.keys, x.s2, 0, 0, lane);
+        if (H1) stream_rows<1, R, 1, MD>(x.keys, x.s1, 0, 0, lane);
         wave_lds_sync();
     }
     if (H2) carry[2] = node_row<R / 2 + 1>(x.f2, 0);
@@ -380,7 +406,7 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
 #pragma unroll
         for (int b = 0; b < D1; ++b) Ch[b] = C[b];
         taylor_shift<M>(Ch, (float)(2 * h - 1) * 0.25f);  // half centre v = -1/4, +1/4
-        if (H32) add_piece<M, 2>(Ch, n32[h], n32[h + 1]);
+        if (H32) add_piece<M, 2, MD>(Ch, n32[h], n32[h + 1]);
 #pragma unroll
         for (int qh = 0; qh < 2; ++qh) {
             const int q = 2 * h + qh;
@@ -390,7 +416,7 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
             taylor_shift<M>(Cq, (float)(2 * qh - 1) * 0.125f);  // quarter centre, from the half's
             if (H16) {
                 const NR hi = node_row<5>(x.f16, q + 1);
-                add_piece<M, 4>(Cq, n16lo, hi);
+                add_piece<M, 4, MD>(Cq, n16lo, hi);
                 n16lo = hi;
             }
             if (PIECE8) {
@@ -401,13 +427,13 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
                     for (int b = 0; b < D1; ++b) Ce[b] = Cq[b];
                     taylor_shift<M>(Ce, (float)(2 * e - 1) * 0.0625f);  // period-8 cell centre
                     const NR lo = carry[0], hi = node_row<9>(x.f8, 2 * q + e + 1);
-                    add_piece<M, 8>(Ce, lo, hi);
+                    add_piece<M, 8, MD>(Ce, lo, hi);
                     carry[0] = hi;
-                    segment_rows<M, OutT, 8, false, H4, H2, H1, FULL>(x, Ce, 16 * q + 8 * e, carry, rp, lane, rlo, rhi,
-                                                                       lane_ok);
+                    segment_rows<M, OutT, 8, false, H4, H2, H1, FULL, MD>(x, Ce, 16 * q + 8 * e, carry, rp, lane, rlo,
+                                                                           rhi, lane_ok);
                 }
             } else {
-                segment_rows<M, OutT, 16, H8, H4, H2, H1, FULL>(x, Cq, 16 * q, carry, rp, lane, rlo, rhi, lane_ok);
+                segment_rows<M, OutT, 16, H8, H4, H2, H1, FULL, MD>(x, Cq, 16 * q, carry, rp, lane, rlo, rhi, lane_ok);
             }
         }
     }
@@ -453,7 +479,7 @@ __device__ __forceinline__ void strip_prologue(const Fbm2dStripArgs &a, StripSha
 
 // One wave's strips of a field: the lane's x-weights of the fixed-period octaves (formed
 // once) and the strip column whose keys its LDS block holds.
-template <int M, typename OutT, int LO>
+template <int M, typename OutT, int LO, int MD = 0>
 struct StripWave {
     static constexpr int D1 = 2 * M + 2;
     static constexpr bool H32 = LO <= 5, H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
@@ -472,7 +498,7 @@ struct StripWave {
         if (o >= 0) {
             const int s = sh.shift[o];
             f.col = nodes + sh.noff[o] + (lane >> s) * sh.nbr[o];
-            f.xa = xweights<M>((float)(2 * (lane & ((1 << s) - 1)) + 1) * sh.inv2p[o], sh.amp[o]);
+            f.xa = xweights<M, MD>((float)(2 * (lane & ((1 << s) - 1)) + 1) * sh.inv2p[o], sh.amp[o]);
         }
         return f;
     }
@@ -524,7 +550,7 @@ struct StripWave {
             const uint32_t it = wl_node[q];
             const uint32_t krow = *reinterpret_cast<const uint32_t *>(key_bytes + (it >> 16));
             const uint32_t kcol = *reinterpret_cast<const uint32_t *>(key_bytes + (it & 0xFFFFu));
-            nodes[q] = grad2(key_combine(krow, kcol));
+            nodes[q] = node_value<MD>(key_combine(krow, kcol));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -539,13 +565,14 @@ struct StripWave {
             const int s = a.shift[o];
             const uint32_t mask = (1u << s) - 1u;
             const float inv2p = a.inv2p[o];
-            const XA xa = xweights<M>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p, a.amp[o]);
-            const CF c = column_form(nodes + a.noff[o], 2, xa);
+            const XA xa =
+                xweights<M, MD>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p, a.amp[o]);
+            const CF c = column_form<MD>(nodes + a.noff[o], 2, xa);
             const float invp = 2.0f * inv2p;
             const float tau = (float)(((uint32_t)Y0 & mask) + (uint32_t)(kStripH / 2)) * invp - 0.5f;
             add_mapped<M>(C, c, tau, (float)kStripH * invp);
         }
-        if (a.o64 >= 0) add_piece<M, 1>(C, node_row<2>(f64, 0), node_row<2>(f64, 1));  // t - 1/2 = v
+        if (a.o64 >= 0) add_piece<M, 1, MD>(C, node_row<2>(f64, 0), node_row<2>(f64, 1));  // t - 1/2 = v
 
         // ---- rows: one store per row of the wave; interior strips take the unmasked path --
         const int64_t xe = a.x0 + a.nx, ye = a.y0 + a.ny;
@@ -555,9 +582,9 @@ struct StripWave {
         const int chi = (int)max<int64_t>(0, min<int64_t>(kStripW, xe - X0));
         OutT *row0 = reinterpret_cast<OutT *>(a.out) + (Y0 - a.y0) * a.pitch + (X0 - a.x0);
         if (rlo == 0 && rhi == kStripH && clo == 0 && chi == kStripW)
-            strip_rows<M, OutT, LO, true>(rc0, C, row0, lane, 0, kStripH, false);
+            strip_rows<M, OutT, LO, true, MD>(rc0, C, row0, lane, 0, kStripH, false);
         else
-            strip_rows<M, OutT, LO, false>(rc0, C, row0, lane, rlo, rhi, lane >= clo && lane < chi);
+            strip_rows<M, OutT, LO, false, MD>(rc0, C, row0, lane, rlo, rhi, lane >= clo && lane < chi);
         __builtin_amdgcn_wave_barrier();  // the next strip rewrites this wave's keys and nodes
     }
 };

@@ -17,11 +17,34 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_params_layout_matches_header():
-    # the binding's struct mirrors ptg_params: 4 int32, 3 double, uint32 + 3 int32
-    assert ctypes.sizeof(ptg.Params) == 4 * 4 + 3 * 8 + 4 * 4
+    # the binding's struct mirrors ptg_params: 4 int32, 3 double, uint32 + 4 int32, 8-byte aligned
+    assert ctypes.sizeof(ptg.Params) == 4 * 4 + 3 * 8 + 5 * 4 + 4
+    assert ptg.Params.model.offset == 4 * 4 + 3 * 8 + 4 * 4
     p = ptg.Params()
     ptg.lib().ptg_params_default(ctypes.byref(p))
     assert (p.dim, p.smoothness, p.octaves, p.persistence, p.lacunarity, p.seed) == (2, 1, 8, 0.5, 2.0, 1)
+    assert p.model == ptg.PTG_MODEL_GRADIENT
+
+
+def test_zero_gradient_model_validation():
+    """The zero-gradient model (Sec. 3.3) is 2D C1 plain form only, and not served."""
+    L = ptg.lib()
+    ok = ptg.params(model="zero_gradient", base_freq=1 / 64, octaves=3)
+    assert ptg.lib().ptg_tune_query_2d(ctypes.byref(ok), 64, 64, ctypes.byref(ctypes.c_int32()),
+                                       ctypes.byref(ctypes.c_int32())) == ptg.PTG_OK
+    for kw in (dict(model=2), dict(model=-1), dict(model="zero_gradient", smoothness=2),
+               dict(model="zero_gradient", form="mfma_f16")):
+        p = ptg.params(base_freq=1 / 64, octaves=3, **kw)
+        assert L.ptg_fbm_2d(ctypes.byref(p), 0, 0, 16, 16, ctypes.c_void_p(1 << 20), 16, None) == ptg.PTG_EINVAL
+    p3 = ptg.params(dim=3, model="zero_gradient", base_freq=1 / 64, octaves=3)
+    assert L.ptg_fbm_3d(ctypes.byref(p3), 0, 0, 0, 8, 8, 8, ctypes.c_void_p(1 << 20), None) == ptg.PTG_EINVAL
+    assert L.ptg_heights_2d(1, -1, 0, 0, 4, 4, ctypes.c_void_p(1), None) == ptg.PTG_EINVAL
+    assert L.ptg_heights_2d(1, 0, 0, 0, 4, 4, None, None) == ptg.PTG_EINVAL
+    assert L.ptg_heights_2d(1, 0, 0, 0, 0, 4, None, None) == ptg.PTG_OK  # empty box
+    with ptg.Server(1 << 20, executor=ptg.PTG_EXEC_HOST) as s:
+        with pytest.raises(ptg.PtgError) as e:
+            s.submit([ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=1 / 64, model="zero_gradient")])
+        assert e.value.code == ptg.PTG_EINVAL
 
 
 def _fbm2(p, x0=0, y0=0, nx=16, ny=16, out=1 << 20, pitch=16):
