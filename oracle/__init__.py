@@ -77,6 +77,14 @@ def lib():
     L.orc_zg_fbm_2d.restype = _i32
     L.orc_zg_fbm_points_2d.argtypes = [_i32, _f64, _f64, _f64, _u32, _pi64, _pi64, _i64, _pd, _i32]
     L.orc_zg_fbm_points_2d.restype = _i32
+    L.orc_height2_second.argtypes = [_u32]
+    L.orc_height2_second.restype = _f64
+    L.orc_hg_cell.argtypes = [_i32, _pd, _pd, _f64, _f64, _f64]
+    L.orc_hg_cell.restype = _f64
+    L.orc_hg_fbm_2d.argtypes = [_i32, _i32, _f64, _f64, _f64, _f64, _u32, _i64, _i64, _i64, _i64, _pd, _i32]
+    L.orc_hg_fbm_2d.restype = _i32
+    L.orc_hg_fbm_points_2d.argtypes = [_i32, _i32, _f64, _f64, _f64, _f64, _u32, _pi64, _pi64, _i64, _pd, _i32]
+    L.orc_hg_fbm_points_2d.restype = _i32
     L.orc_max_threads.argtypes = []
     L.orc_max_threads.restype = _i32
     _LIB = L
@@ -268,6 +276,35 @@ def zg_fbm_points_2d(octaves, pers, lac, f0, seed, X, Y, nthreads=0) -> np.ndarr
     Y = np.ascontiguousarray(Y, dtype=np.int64)
     out = np.empty(X.shape[0], dtype=np.float64)
     _chk(lib().orc_zg_fbm_points_2d(octaves, pers, lac, f0, seed & 0xFFFFFFFF, _ip(X), _ip(Y), X.shape[0],
+                                    _dp(out), nthreads))
+    return out
+
+
+# --- heights and weighted gradients (Sec. 3.1, Sec. 4 w) -------------------------
+
+def height2_second(key: int) -> float:
+    """Node height of the height-and-gradient model (the key's second word)."""
+    return float(lib().orc_height2_second(key & 0xFFFFFFFF))
+
+
+def hg_cell(smooth: int, h, grad, w: float, x: float, y: float) -> float:
+    hh = np.ascontiguousarray(h, dtype=np.float64).reshape(4)
+    g = np.ascontiguousarray(grad, dtype=np.float64).reshape(8)
+    return float(lib().orc_hg_cell(smooth, _dp(hh), _dp(g), w, x, y))
+
+
+def hg_fbm_2d(smooth, octaves, pers, lac, f0, w, seed, x0, y0, nx, ny, nthreads=0) -> np.ndarray:
+    out = np.empty((ny, nx), dtype=np.float64)
+    _chk(lib().orc_hg_fbm_2d(smooth, octaves, pers, lac, f0, w, seed & 0xFFFFFFFF, x0, y0, nx, ny, _dp(out),
+                             nthreads))
+    return out
+
+
+def hg_fbm_points_2d(smooth, octaves, pers, lac, f0, w, seed, X, Y, nthreads=0) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.int64)
+    Y = np.ascontiguousarray(Y, dtype=np.int64)
+    out = np.empty(X.shape[0], dtype=np.float64)
+    _chk(lib().orc_hg_fbm_points_2d(smooth, octaves, pers, lac, f0, w, seed & 0xFFFFFFFF, _ip(X), _ip(Y), X.shape[0],
                                     _dp(out), nthreads))
     return out
 

@@ -23,6 +23,8 @@
  *  - Sec. 3.3, eq. (zg): the zero-gradient D2M1N3 cell (random corner heights, zero
  *    corner gradients), with the sign of its xy term read from the Sec. 3.1
  *    coefficients (see orc_zg_cell).
+ *  - Sec. 3.1 with non-zero heights and Sec. 4's gradient weight w: corner heights and
+ *    w-scaled corner gradients in the same tensor Hermite form (see orc_hg_cell).
  *
  * Readings taken where the paper is silent (each one is listed in the design notes):
  *  - Cell polynomial: the unique tensor polynomial of degree n = 2M+1 per axis whose
@@ -549,6 +551,81 @@ int orc_zg_fbm_points_2d(int32_t octaves, double pers, double lac, double f0, ui
     orc_set_threads(nthreads);
 #pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < n; ++q) out[q] = orc_zg_sample(octaves, freq, amp, seed, X[q], Y[q]);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Heights and weighted gradients (Sec. 3.1 with non-zero heights, Sec. 4 w) */
+/* ------------------------------------------------------------------------- */
+
+/* Node height of the height-and-gradient model: uniform on [-1, 1) from the top 24 bits
+ * of the node's second word (the gradient takes the first word's top bits, so the two
+ * are independent). */
+double orc_height2_second(uint32_t key)
+{
+    return orc_height2(orc_key3_second(key));
+}
+
+/* Tensor Hermite cell with corner heights h[c] and corner gradients w * grad[2c..2c+1]
+ * (c = cx + 2 cy; mixed derivatives zero): h(x, y) = sum_c h_c B0_cx(x) B0_cy(y) plus
+ * w times the zero-height cell of orc_cell_2d. */
+double orc_hg_cell(int32_t smooth, const double *h, const double *grad, double w, double tx, double ty)
+{
+    double bx0[2], bx1[2], by0[2], by1[2];
+    orc_basis(smooth, tx, bx0, bx1);
+    orc_basis(smooth, ty, by0, by1);
+    double v = 0.0;
+    for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) v += h[cx + 2 * cy] * bx0[cx] * by0[cy];
+    return v + w * orc_cell_2d(smooth, grad, tx, ty);
+}
+
+static double orc_hg_sample(int32_t smooth, int32_t octaves, const double *freq, const double *amp, double w,
+                            uint32_t seed, int64_t X, int64_t Y)
+{
+    double H = 0.0;
+    for (int32_t o = 0; o < octaves; ++o) {
+        int64_t cx, cy;
+        double tx, ty, h[4], grad[8];
+        orc_coord(X, freq[o], &cx, &tx);
+        orc_coord(Y, freq[o], &cy, &ty);
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                uint32_t key = orc_key2(cx + dx, cy + dy, o, seed);
+                h[dx + 2 * dy] = orc_height2_second(key);
+                orc_grad2(key, &grad[2 * (dx + 2 * dy)]);
+            }
+        H += amp[o] * orc_hg_cell(smooth, h, grad, w, tx, ty);
+    }
+    return H;
+}
+
+/* Height-and-gradient fBm over a row-major [ny][nx] field; w = gradient weight. */
+int orc_hg_fbm_2d(int32_t smooth, int32_t octaves, double pers, double lac, double f0, double w, uint32_t seed,
+                  int64_t x0, int64_t y0, int64_t nx, int64_t ny, double *out, int32_t nthreads)
+{
+    if (orc_check(smooth, octaves, f0, lac, pers) != ORC_OK || !isfinite(w) || nx < 0 || ny < 0 || !out)
+        return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i)
+            out[j * nx + i] = orc_hg_sample(smooth, octaves, freq, amp, w, seed, x0 + i, y0 + j);
+    return ORC_OK;
+}
+
+int orc_hg_fbm_points_2d(int32_t smooth, int32_t octaves, double pers, double lac, double f0, double w,
+                         uint32_t seed, const int64_t *X, const int64_t *Y, int64_t n, double *out, int32_t nthreads)
+{
+    if (orc_check(smooth, octaves, f0, lac, pers) != ORC_OK || !isfinite(w) || n < 0 || !X || !Y || !out)
+        return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q) out[q] = orc_hg_sample(smooth, octaves, freq, amp, w, seed, X[q], Y[q]);
     return ORC_OK;
 }
 
