@@ -220,8 +220,12 @@ def main():
 
 # ---- the other benchmark fields ---------------------------------------------------------
 def _time_launches(torch, stream, fn, n=10):
+    """Average time of n back-to-back launches, after one warm-up launch and a short idle
+    period (the previous configuration's heavy launches leave the clock lowered for a while;
+    every configuration starts from the same state)."""
     fn()
     torch.cuda.synchronize()
+    time.sleep(0.3)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(stream)
     for _ in range(n):
@@ -235,7 +239,8 @@ def other_configs(torch, ptg, stream):
     """3D 512^3 6-octave C2 volume; 16384^2 10-octave field at a world offset of 2^24 cells
     through the plain FP32 path and the FP16 / BF16 matrix-core form (their errors against
     the FP64 oracle are measured by the GPU tests); the zero-gradient model on the 8192^2
-    8-octave field (dyadic and general ladders); 256^2 4-octave field (launch-bound)."""
+    8-octave field (dyadic and general ladders) and the height-and-gradient model on it (C1,
+    C2); 256^2 4-octave field (launch-bound)."""
     res = {}
     sh = stream.cuda_stream
     # 3D 512^3, 6 octaves, base lattice 8^3, C2
@@ -279,6 +284,18 @@ def other_configs(torch, ptg, stream):
         "workload": "zero-gradient D2M1N3 (random node heights, zero corner gradients), 8192^2, 8 octaves, "
                     "persistence 0.5, FP32, seed 1",
         "ladders": zg}
+    # heights and w-weighted gradients (tensor Hermite), same field, C1 and C2, w = 0.01
+    hg = {}
+    for m in (1, 2):
+        q = ptg.params(smoothness=m, octaves=8, base_freq=16 / 8192, seed=1, model="height_gradient",
+                       gradient_weight=0.01)
+        ms = _time_launches(torch, stream, lambda: ptg.fbm_2d_raw(q, 0, 0, 8192, 8192, zf.data_ptr(), 8192, sh), 10)
+        hg[f"C{m}"] = {"ms": ms, "octave_samples_s": 8192 * 8192 * 8 / (ms * 1e-3),
+                       "hbm_frac": 8192 * 8192 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    res["2d_8192_8oct_height_gradient"] = {
+        "workload": "heights and gradients (weight 0.01) in tensor Hermite cells, 8192^2, 8 octaves, base lattice "
+                    "16^2, FP32, seed 1, strip kernel",
+        "smoothness": hg}
     del zf
     # 256^2, 4 octaves, base lattice 8^2
     small = torch.empty((256, 256), dtype=torch.float32, device="cuda")

@@ -96,6 +96,11 @@ extern "C" {
                                    /* continuous across faces, its gradient pinned at the   */
                                    /* nodes only.  2D, smoothness 1, plain form, fields only */
                                    /* (not served)                                          */
+#define PTG_MODEL_HEIGHT_GRADIENT 2 /* tensor Hermite cells with a random height per node    */
+                                   /* (uniform on [-1, 1) from the node's second hash word) */
+                                   /* and the lattice gradient times gradient_weight w      */
+                                   /* (Sec. 3.1 heights, Sec. 4 w); C1 / C2 across faces.   */
+                                   /* 2D, plain form, fields only (not served)              */
 
 /* Problem parameters (Sec. 2.2 DdMmNn naming: dim = d, smoothness = m, n = 2m+1;
  * Sec. 4: octaves, persistence, lacunarity). */
@@ -113,6 +118,8 @@ typedef struct ptg_params {
     int32_t basis;        /* PTG_BASIS_* (MFMA forms only)                             */
     int32_t path;         /* PTG_PATH_*: kernel choice for the plain form              */
     int32_t model;        /* PTG_MODEL_*                                               */
+    double gradient_weight; /* w of PTG_MODEL_HEIGHT_GRADIENT (finite; default 0.01, the */
+                          /* paper's h0 / 100 with h0 = 1); ignored by the other models */
 } ptg_params;
 
 /* Library version string (static storage). */
@@ -123,7 +130,7 @@ PTG_API const char *ptg_version(void);
 PTG_API const char *ptg_last_error(void);
 
 /* Fill a ptg_params with the defaults: dim 2, smoothness 1, 8 octaves, persistence 0.5,
- * lacunarity 2, base_freq 1/512, seed 1, FP32, plain form. */
+ * lacunarity 2, base_freq 1/512, seed 1, FP32, plain form, gradient model (w = 0.01). */
 PTG_API void ptg_params_default(ptg_params *p);
 
 /* ---- a1-a5: dense fields ----------------------------------------------------- */

@@ -32,9 +32,10 @@ PTG_F16 = 1
 FORMS = {"plain": 0, "mfma_f16": 1, "mfma_bf16": 2}
 BASES = {"monomial": 0, "centred": 1}
 PATHS = {"auto": 0, "general": 1, "dyadic": 2}
-MODELS = {"gradient": 0, "zero_gradient": 1}
+MODELS = {"gradient": 0, "zero_gradient": 1, "height_gradient": 2}
 PTG_MODEL_GRADIENT = 0
 PTG_MODEL_ZERO_GRADIENT = 1
+PTG_MODEL_HEIGHT_GRADIENT = 2
 
 
 class PtgError(RuntimeError):
@@ -57,6 +58,7 @@ class Params(ctypes.Structure):
         ("basis", ctypes.c_int32),
         ("path", ctypes.c_int32),
         ("model", ctypes.c_int32),
+        ("gradient_weight", ctypes.c_double),
     ]
 
 
@@ -189,7 +191,8 @@ def _check(rc):
 
 
 def params(dim=2, smoothness=1, octaves=8, persistence=0.5, lacunarity=2.0, base_freq=1.0 / 512, seed=1,
-           out_dtype=PTG_F32, form="plain", basis="monomial", path="auto", model="gradient") -> Params:
+           out_dtype=PTG_F32, form="plain", basis="monomial", path="auto", model="gradient",
+           gradient_weight=0.01) -> Params:
     p = Params()
     p.dim = dim
     p.smoothness = smoothness
@@ -203,6 +206,7 @@ def params(dim=2, smoothness=1, octaves=8, persistence=0.5, lacunarity=2.0, base
     p.basis = BASES[basis] if isinstance(basis, str) else int(basis)
     p.path = PATHS[path] if isinstance(path, str) else int(path)
     p.model = MODELS[model] if isinstance(model, str) else int(model)
+    p.gradient_weight = gradient_weight
     return p
 
 

@@ -51,8 +51,12 @@ int validate_params(const ptg_params *p, int dim)
         return fail(PTG_EINVAL, "unknown basis %d", p->basis);
     if (p->path != PTG_PATH_AUTO && p->path != PTG_PATH_GENERAL && p->path != PTG_PATH_DYADIC)
         return fail(PTG_EINVAL, "unknown path %d", p->path);
-    if (p->model != PTG_MODEL_GRADIENT && p->model != PTG_MODEL_ZERO_GRADIENT)
+    if (p->model != PTG_MODEL_GRADIENT && p->model != PTG_MODEL_ZERO_GRADIENT && p->model != PTG_MODEL_HEIGHT_GRADIENT)
         return fail(PTG_EINVAL, "unknown model %d", p->model);
+    if (p->model == PTG_MODEL_HEIGHT_GRADIENT && (dim != 2 || p->form != PTG_FORM_PLAIN))
+        return fail(PTG_EINVAL, "the height-and-gradient model is 2D, plain form");
+    if (p->model == PTG_MODEL_HEIGHT_GRADIENT && !std::isfinite(p->gradient_weight))
+        return fail(PTG_EINVAL, "gradient_weight must be finite");
     if (p->model == PTG_MODEL_ZERO_GRADIENT && (dim != 2 || p->smoothness != 1 || p->form != PTG_FORM_PLAIN))
         return fail(PTG_EINVAL, "the zero-gradient model is 2D, smoothness 1, plain form");
     double f = p->base_freq, a = 1.0;
@@ -125,6 +129,7 @@ void ptg_params_default(ptg_params *p)
     p->seed = 1;
     p->form = PTG_FORM_PLAIN;
     p->basis = PTG_BASIS_MONOMIAL;
+    p->gradient_weight = 0.01;
 }
 
 int ptg_fbm_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out_dev,

@@ -58,6 +58,10 @@ __device__ __forceinline__ float2 grad2(uint32_t key)
 // bits, uniform on [-1, 1) and exact in FP32.
 __device__ __forceinline__ float height2(uint32_t key) { return (float)(key >> 8) * (1.0f / 8388608.0f) - 1.0f; }
 
+// Node height of the height-and-gradient model: the same map on the node's second word
+// (its gradient angle takes the first word's top bits).
+__device__ __forceinline__ float height2_second(uint32_t key) { return height2(key3_second(key)); }
+
 // 3D unit gradient: z = 1 - (2m+1)/2^24 (exact in FP32), azimuth from the second word,
 // radius sqrt((1-z)(1+z)).
 __device__ __forceinline__ float3 grad3(uint32_t key)

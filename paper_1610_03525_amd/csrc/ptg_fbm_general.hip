@@ -36,6 +36,13 @@ static hipError_t launch_2d_th(const Fbm2dArgs &a, int smooth, bool f16, dim3 gr
     if (a.model == 1)  // zero-gradient model (smoothness 1, validated)
         return f16 ? launch_dyn(k_fbm2d_general<1, __half, TH, 1>, grid, lds, s, a)
                    : launch_dyn(k_fbm2d_general<1, float, TH, 1>, grid, lds, s, a);
+    if (a.model == 2) {  // heights and weighted gradients
+        if (smooth == 1)
+            return f16 ? launch_dyn(k_fbm2d_general<1, __half, TH, 2>, grid, lds, s, a)
+                       : launch_dyn(k_fbm2d_general<1, float, TH, 2>, grid, lds, s, a);
+        return f16 ? launch_dyn(k_fbm2d_general<2, __half, TH, 2>, grid, lds, s, a)
+                   : launch_dyn(k_fbm2d_general<2, float, TH, 2>, grid, lds, s, a);
+    }
     if (smooth == 1)
         return f16 ? launch_dyn(k_fbm2d_general<1, __half, TH>, grid, lds, s, a)
                    : launch_dyn(k_fbm2d_general<1, float, TH>, grid, lds, s, a);

@@ -17,7 +17,7 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
     uint32_t *wl_key = reinterpret_cast<uint32_t *>(lds4);
     uint32_t *wl_node = wl_key + a.keys_total;
     const int shared_words = strip_shared_words(a.nodes_hashed, a.keys_total);
-    const int wave_words = strip_wave_words(a.nodes_total, a.keys_total);
+    const int wave_words = strip_wave_words(a.nodes_total, a.keys_total, MD == 2);
     float2 *nodes = reinterpret_cast<float2 *>(reinterpret_cast<uint32_t *>(lds4) + shared_words + wave * wave_words);
 
     strip_prologue(a, sh, wl_key, wl_node, tid, nthreads);
@@ -78,10 +78,13 @@ static int resident_st(int lo, int waves, size_t lds)
     }
 }
 
-// model 1 (zero-gradient) is smoothness 1 only
+// model 1 (zero-gradient) is smoothness 1 only; model 2 (heights and gradients) either
 int strip_wgs_per_cu(int smooth, int model, bool f16, int lo, int waves, size_t lds)
 {
     if (model == 1) return f16 ? resident_st<1, __half, 1>(lo, waves, lds) : resident_st<1, float, 1>(lo, waves, lds);
+    if (model == 2 && smooth == 1)
+        return f16 ? resident_st<1, __half, 2>(lo, waves, lds) : resident_st<1, float, 2>(lo, waves, lds);
+    if (model == 2) return f16 ? resident_st<2, __half, 2>(lo, waves, lds) : resident_st<2, float, 2>(lo, waves, lds);
     if (smooth == 1) return f16 ? resident_st<1, __half, 0>(lo, waves, lds) : resident_st<1, float, 0>(lo, waves, lds);
     return f16 ? resident_st<2, __half, 0>(lo, waves, lds) : resident_st<2, float, 0>(lo, waves, lds);
 }
@@ -91,6 +94,10 @@ hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, int model, bo
 {
     if (model == 1)
         return f16 ? launch_lo<1, __half, 1>(a, grid, waves, lds, s) : launch_lo<1, float, 1>(a, grid, waves, lds, s);
+    if (model == 2 && smooth == 1)
+        return f16 ? launch_lo<1, __half, 2>(a, grid, waves, lds, s) : launch_lo<1, float, 2>(a, grid, waves, lds, s);
+    if (model == 2)
+        return f16 ? launch_lo<2, __half, 2>(a, grid, waves, lds, s) : launch_lo<2, float, 2>(a, grid, waves, lds, s);
     if (smooth == 1)
         return f16 ? launch_lo<1, __half, 0>(a, grid, waves, lds, s) : launch_lo<1, float, 0>(a, grid, waves, lds, s);
     return f16 ? launch_lo<2, __half, 0>(a, grid, waves, lds, s) : launch_lo<2, float, 0>(a, grid, waves, lds, s);

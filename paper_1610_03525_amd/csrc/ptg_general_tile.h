@@ -65,6 +65,8 @@ struct LatCache {
 // cell at the lane's column x is E0 + dE S(y) + dQ (y - S(y)) with, per node row j,
 // E_j = h0j + S(x) D_j, Q_j = (S(x) - x) D_j, D_j = h1j - h0j; y - S(y) = b10(y) + b11(y),
 // so the row evaluation is the gradient model's with Q0 = Q1 = dQ.
+// MD = 2: heights and w-weighted gradients (tensor Hermite): gh holds the heights, gx / gy
+// the gradients times w, and a node row's value term gains h0j (1 - S(x)) + h1j S(x).
 template <int M, typename OutT, int TH, int MD = 0>
 __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t bid, float4 *lds4,
                                                    const LatCache *lat = nullptr)
@@ -75,7 +77,8 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
     const int cap = a.capx * a.capy;
     float *gx = reinterpret_cast<float *>(lds4 + TH);
     float *gy = gx + cap;
-    uint32_t *kx = reinterpret_cast<uint32_t *>(gy + cap);
+    float *gh = gy + cap;  // MD = 2 only
+    uint32_t *kx = reinterpret_cast<uint32_t *>(MD == 2 ? gh + cap : gy + cap);
     uint32_t *ky = kx + a.capx;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -147,6 +150,16 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
                 const int j = q / nnx, i = q - j * nnx;
                 gx[q] = height2(key_combine(ky[j], kx[i])) * amp;
             }
+        } else if (MD == 2) {
+            const float aw = amp * a.gw;
+            for (int q = tid; q < nnx * nny; q += 256) {
+                const int j = q / nnx, i = q - j * nnx;
+                const uint32_t key = key_combine(ky[j], kx[i]);
+                const float2 g = grad2(key);
+                gx[q] = g.x * aw;
+                gy[q] = g.y * aw;
+                gh[q] = height2_second(key) * amp;
+            }
         } else {
             for (int q = tid; q < nnx * nny; q += 256) {
                 const int j = q / nnx, i = q - j * nnx;
@@ -181,8 +194,12 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
                 const int q = lcy * nnx + lcx;
                 const float fx00 = gx[q], fx10 = gx[q + 1], fx01 = gx[q + nnx], fx11 = gx[q + nnx + 1];
                 const float fy00 = gy[q], fy10 = gy[q + 1], fy01 = gy[q + nnx], fy11 = gy[q + nnx + 1];
-                const float e0 = fx00 * b10x + fx10 * b11x;
-                const float e1 = fx01 * b10x + fx11 * b11x;
+                float e0 = fx00 * b10x + fx10 * b11x;
+                float e1 = fx01 * b10x + fx11 * b11x;
+                if (MD == 2) {  // the heights' value term along the row
+                    e0 += gh[q] + sx * (gh[q + 1] - gh[q]);
+                    e1 += gh[q + nnx] + sx * (gh[q + nnx + 1] - gh[q + nnx]);
+                }
                 E0 = e0;
                 dE = e1 - e0;
                 Q0 = fy00 + sx * (fy10 - fy00);

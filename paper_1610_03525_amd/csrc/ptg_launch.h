@@ -26,6 +26,7 @@ struct Fbm2dArgs {
     int32_t tiles_x;     // tiles per row of the tile grid
     int32_t tile_h;      // rows per tile: 16, 32 or 64 (tile shape chosen by the tuner)
     int32_t model;       // PTG_MODEL_*
+    float gw;            // gradient weight (height-and-gradient model)
 };
 
 struct Fbm3dArgs {
@@ -96,6 +97,7 @@ struct Fbm2dStripArgs {
     int32_t kxoff[kMaxOctaves], kyoff[kMaxOctaves]; // column / row key offsets (all column keys first)
     int32_t nodes_total, keys_total, keys_col;      // keys [0, keys_col) are column keys
     int32_t nodes_hashed;                           // nodes [0, nodes_hashed) are hashed per strip
+    float gw;                                       // gradient weight (height-and-gradient model)
     int32_t octaves;
     uint32_t seed;
     int32_t strips_x;
@@ -142,9 +144,10 @@ __host__ __device__ inline int strip_shared_words(int nodes_hashed, int keys_tot
 {
     return (keys_total + nodes_hashed + 3) & ~3;
 }
-__host__ __device__ inline int strip_wave_words(int nodes_total, int keys_total)
+// hw = 1: a node height (float) per node besides its gradient (height-and-gradient model)
+__host__ __device__ inline int strip_wave_words(int nodes_total, int keys_total, int hw = 0)
 {
-    return (2 * nodes_total + keys_total + 3) & ~3;
+    return ((2 + hw) * nodes_total + keys_total + 3) & ~3;
 }
 
 // LDS words of the 3D strip kernel's basis table and work lists (shared) and of one wave's

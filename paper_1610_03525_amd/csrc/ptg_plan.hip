@@ -130,6 +130,7 @@ int strip_args_2d(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx
     octave_tables(p, freq, a.amp);
     a.octaves = p->octaves;
     a.seed = p->seed;
+    a.gw = (float)p->gradient_weight;
     a.o64 = a.o32 = a.o16 = a.o8 = a.o4 = a.o2 = a.o1 = -1;
     const int smin = k - (p->octaves - 1);
     // the row loop assumes every period from 32 down to the finest is present
@@ -183,7 +184,8 @@ static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
     Fbm2dStripArgs a;
     if (strip_args_2d(p, k, x0, y0, nx, ny, out, pitch, &a)) return 1;
     const size_t shared_words = (size_t)strip_shared_words(a.nodes_hashed, a.keys_total);
-    const size_t wave_words = (size_t)strip_wave_words(a.nodes_total, a.keys_total);
+    const size_t wave_words =
+        (size_t)strip_wave_words(a.nodes_total, a.keys_total, p->model == PTG_MODEL_HEIGHT_GRADIENT);
     // waves per workgroup: the tuned count (default 4), at most what the private node
     // blocks allow in LDS
     int waves = tune_pick(TuneKey{PTG_TUNE_STRIP_2D, p->smoothness + 2 * p->model, p->out_dtype == PTG_F16,
@@ -217,10 +219,12 @@ size_t general_args_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, 
     a->seed = p->seed;
     a->tile_h = tile_h;
     a->model = p->model;
+    a->gw = (float)p->gradient_weight;
     a->capx = footprint_cap(a->freq, p->octaves, kTile2);
     a->capy = footprint_cap(a->freq, p->octaves, tile_h);
     a->tiles_x = (int32_t)((nx + kTile2 - 1) / kTile2);
-    return (size_t)tile_h * 16 + (size_t)a->capx * a->capy * 8 + (size_t)(a->capx + a->capy) * 4;
+    return (size_t)tile_h * 16 + (size_t)a->capx * a->capy * (p->model == PTG_MODEL_HEIGHT_GRADIENT ? 12 : 8) +
+           (size_t)(a->capx + a->capy) * 4;
 }
 
 size_t general_args_3d(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz,
@@ -256,10 +260,13 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     if (dy && p->path != PTG_PATH_GENERAL) {
         int rc = fbm2d_strip(p, k, x0, y0, nx, ny, out, pitch, s);
         if (rc <= 0) return rc;
-        if (p->model == PTG_MODEL_GRADIENT) {  // the matrix-core tile kernel has no zero-gradient cells
+        if (p->model == PTG_MODEL_GRADIENT) {  // the matrix-core tile kernel has gradient-model cells only
             rc = fbm2d_dyadic(p, k, x0, y0, nx, ny, out, pitch, s);
             if (rc <= 0) return rc;
         }
+        if (p->path == PTG_PATH_DYADIC && p->model != PTG_MODEL_GRADIENT)
+            return fail(PTG_EINVAL, "the dyadic path of this model is the strip kernel, which needs a ladder whose "
+                                    "coarsest period is >= 32 (or finest >= 64) and a footprint that fits LDS");
         if (p->path == PTG_PATH_DYADIC)
             return fail(PTG_EINVAL, "the dyadic kernel's lattice footprint exceeds the workgroup's LDS");
     }

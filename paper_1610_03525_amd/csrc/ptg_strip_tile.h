@@ -70,17 +70,23 @@ __device__ __forceinline__ XB xbases(float t)
 
 // A lane's x-weights of one octave with the octave amplitude folded in: the value term of a
 // node row is gx0 e0 + gx1 e1 (e = amp b1), its y-slope term gy0 q0 + gy1 q1 (q = amp b0).
+// Height-and-gradient model (MD = 2): the gradient weights carry w, and the node heights'
+// value term is h0 v0 + h1 v1 (v = amp b0).
 struct XA {
-    float q0, q1, e0, e1;
+    float q0, q1, e0, e1, v0, v1;
 };
 
 template <int M, int MD = 0>
-__device__ __forceinline__ XA xweights(float t, float amp)
+__device__ __forceinline__ XA xweights(float t, float amp, float gw = 1.0f)
 {
     const XB b = xbases<M>(t);
     if (MD == 1)  // zero-gradient model: the nodes hold heights (E = h0 + S D, Q = (S - t) D)
-        return XA{amp * (t - b.s), amp * (b.s - t), amp * (1.0f - b.s), amp * b.s};
-    return XA{amp * (1.0f - b.s), amp * b.s, amp * b.b10, amp * b.b11};
+        return XA{amp * (t - b.s), amp * (b.s - t), amp * (1.0f - b.s), amp * b.s, 0.0f, 0.0f};
+    if (MD == 2) {
+        const float aw = amp * gw;
+        return XA{aw * (1.0f - b.s), aw * b.s, aw * b.b10, aw * b.b11, amp * (1.0f - b.s), amp * b.s};
+    }
+    return XA{amp * (1.0f - b.s), amp * b.s, amp * b.b10, amp * b.b11, 0.0f, 0.0f};
 }
 
 // Row bases at the fraction (j + 1/2) / P: constant once the row loop is unrolled.
@@ -104,12 +110,16 @@ struct CF {  // column form of one cell at one column
 // Zero-gradient model (MD = 1, Sec. 3.3): the cell is E0 + dE S(t) + dQ (t - S(t)) and
 // t - S(t) = b10(t) + b11(t), i.e. the gradient form with Q0 = Q1 = dQ.
 template <int MD = 0>
-__device__ __forceinline__ CF column_form(const float2 *nb, int nny, const XA &xa)
+__device__ __forceinline__ CF column_form(const float2 *nb, int nny, const XA &xa, const float *hb = nullptr)
 {
     const float2 n00 = nb[0], n01 = nb[1], n10 = nb[nny], n11 = nb[nny + 1];
     CF c;
     c.E0 = n00.x * xa.e0 + n10.x * xa.e1;
-    const float E1 = n01.x * xa.e0 + n11.x * xa.e1;
+    float E1 = n01.x * xa.e0 + n11.x * xa.e1;
+    if (MD == 2) {  // heights (hb: the node heights at the same offsets)
+        c.E0 += hb[0] * xa.v0 + hb[nny] * xa.v1;
+        E1 += hb[1] * xa.v0 + hb[nny + 1] * xa.v1;
+    }
     c.dE = E1 - c.E0;
     c.Q0 = n00.y * xa.q0 + n10.y * xa.q1;
     c.Q1 = n01.y * xa.q0 + n11.y * xa.q1;
@@ -173,6 +183,7 @@ __device__ __forceinline__ void add_mapped(float (&C)[2 * M + 2], const CF &c, f
 struct Fixed {
     const float2 *col;
     XA xa;
+    const float *hcol;  // the column's node heights (height-and-gradient model)
 };
 
 // A node's LDS entry: its unit gradient, or for the zero-gradient model its height in both
@@ -192,6 +203,7 @@ __device__ __forceinline__ float2 node_value(uint32_t key)
 struct Streamed {
     float2 *blk;
     int kx, ky;
+    float *hblk;  // node heights (height-and-gradient model)
 };
 
 struct RowCtx {
@@ -219,7 +231,9 @@ __device__ __forceinline__ void stream_rows(const uint32_t *keys, const Streamed
     constexpr int NB = R / P + 1, NNX = kStripW / P + 1, N = NNX * NROWS;
     for (int q = lane; q < N; q += 64) {  // column-major: consecutive lanes, consecutive rows
         const int i = q / NROWS, jj = q - i * NROWS;
-        st.blk[i * NB + l0 + jj] = node_value<MD>(key_combine(keys[st.ky + j0 + jj], keys[st.kx + i]));
+        const uint32_t key = key_combine(keys[st.ky + j0 + jj], keys[st.kx + i]);
+        st.blk[i * NB + l0 + jj] = node_value<MD>(key);
+        if (MD == 2) st.hblk[i * NB + l0 + jj] = height2_second(key);
     }
 }
 
@@ -230,11 +244,13 @@ struct NR {
     float E, Q;
 };
 
-template <int NNY>
+template <int NNY, int MD = 0>
 __device__ __forceinline__ NR node_row(const Fixed &f, int j)
 {
     const float2 a = f.col[j], b = f.col[j + NNY];
-    return NR{a.x * f.xa.e0 + b.x * f.xa.e1, a.y * f.xa.q0 + b.y * f.xa.q1};
+    NR r{a.x * f.xa.e0 + b.x * f.xa.e1, a.y * f.xa.q0 + b.y * f.xa.q1};
+    if (MD == 2) r.E += f.hcol[j] * f.xa.v0 + f.hcol[j + NNY] * f.xa.v1;
+    return r;
 }
 
 // Add the cell between node rows lo and hi, as a polynomial in the segment coordinate w
@@ -285,14 +301,14 @@ __device__ __forceinline__ float add_direct(float val, const NR &lo, const NR &h
 
 // Node rows [r0 / P, (r0 + R) / P] of a direct octave over a segment; the first one is
 // carried from the previous segment and the last one is carried to the next.
-template <int P, int R>
+template <int P, int R, int MD = 0>
 struct SegRows {
     NR n[R / P + 1];
     __device__ __forceinline__ void load(const Fixed &f, int r0, NR &carry)
     {
         n[0] = carry;
 #pragma unroll
-        for (int j = 1; j <= R / P; ++j) n[j] = node_row<64 / P + 1>(f, r0 / P + j);
+        for (int j = 1; j <= R / P; ++j) n[j] = node_row<64 / P + 1, MD>(f, r0 / P + j);
         carry = n[R / P];
     }
     // streamed octave: the segment's rows are rows 1 .. R / P of its block
@@ -300,7 +316,7 @@ struct SegRows {
     {
         n[0] = carry;
 #pragma unroll
-        for (int j = 1; j <= R / P; ++j) n[j] = node_row<R / P + 1>(f, j);
+        for (int j = 1; j <= R / P; ++j) n[j] = node_row<R / P + 1, MD>(f, j);
         carry = n[R / P];
     }
 };
@@ -313,10 +329,10 @@ template <int M, typename OutT, int R, bool D8, bool D4, bool D2, bool D1, bool 
 __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[2 * M + 2], int r0, NR (&carry)[4],
                                              OutT *rp, int lane, int rlo, int rhi, bool lane_ok)
 {
-    SegRows<8, R> s8;
-    SegRows<4, R> s4;
-    SegRows<2, R> s2;
-    SegRows<1, R> s1;
+    SegRows<8, R, MD> s8;
+    SegRows<4, R, MD> s4;
+    SegRows<2, R, MD> s2;
+    SegRows<1, R, MD> s1;
     if (D8) s8.load(x.f8, r0, carry[0]);
     if (D4) s4.load(x.f4, r0, carry[1]);
     if (D2 || D1) {  // streamed periods: hash this segment's node rows first
@@ -384,22 +400,22 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
     constexpr bool PIECE8 = H8 && M == 1;
     constexpr int R = (M == 1 && H8) ? 8 : 16;  // row segment (streamed block height)
     NR carry[4];  // bottom node rows of the next segment: periods 8, 4, 2, 1
-    if (H8) carry[0] = node_row<9>(x.f8, 0);
-    if (H4) carry[1] = node_row<17>(x.f4, 0);
+    if (H8) carry[0] = node_row<9, MD>(x.f8, 0);
+    if (H4) carry[1] = node_row<17, MD>(x.f4, 0);
     if (H2 || H1) {  // streamed periods: node row 0 of the strip into block row 0
         wave_lds_sync();  // the previous strip has read its blocks
         if (H2) stream_rows<2, R, 1, MD>(x.keys, x.s2, 0, 0, lane);
         if (H1) stream_rows<1, R, 1, MD>(x.keys, x.s1, 0, 0, lane);
         wave_lds_sync();
     }
-    if (H2) carry[2] = node_row<R / 2 + 1>(x.f2, 0);
-    if (H1) carry[3] = node_row<R + 1>(x.f1, 0);
+    if (H2) carry[2] = node_row<R / 2 + 1, MD>(x.f2, 0);
+    if (H1) carry[3] = node_row<R + 1, MD>(x.f1, 0);
     NR n32[3], n16lo;
     if (H32) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) n32[j] = node_row<3>(x.f32, j);
+        for (int j = 0; j < 3; ++j) n32[j] = node_row<3, MD>(x.f32, j);
     }
-    if (H16) n16lo = node_row<5>(x.f16, 0);
+    if (H16) n16lo = node_row<5, MD>(x.f16, 0);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         float Ch[D1];
@@ -415,7 +431,7 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
             for (int b = 0; b < D1; ++b) Cq[b] = Ch[b];
             taylor_shift<M>(Cq, (float)(2 * qh - 1) * 0.125f);  // quarter centre, from the half's
             if (H16) {
-                const NR hi = node_row<5>(x.f16, q + 1);
+                const NR hi = node_row<5, MD>(x.f16, q + 1);
                 add_piece<M, 4, MD>(Cq, n16lo, hi);
                 n16lo = hi;
             }
@@ -426,7 +442,7 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
 #pragma unroll
                     for (int b = 0; b < D1; ++b) Ce[b] = Cq[b];
                     taylor_shift<M>(Ce, (float)(2 * e - 1) * 0.0625f);  // period-8 cell centre
-                    const NR lo = carry[0], hi = node_row<9>(x.f8, 2 * q + e + 1);
+                    const NR lo = carry[0], hi = node_row<9, MD>(x.f8, 2 * q + e + 1);
                     add_piece<M, 8, MD>(Ce, lo, hi);
                     carry[0] = hi;
                     segment_rows<M, OutT, 8, false, H4, H2, H1, FULL, MD>(x, Ce, 16 * q + 8 * e, carry, rp, lane, rlo,
@@ -445,6 +461,7 @@ struct StripShared {
     uint32_t pre_key[kMaxOctaves];
     int shift[kMaxOctaves], noff[kMaxOctaves], nbr[kMaxOctaves];
     float amp[kMaxOctaves], inv2p[kMaxOctaves];
+    float gw;  // gradient weight (height-and-gradient model)
 };
 
 // Once per workgroup (every thread, a barrier after it): the work lists that map lanes to
@@ -472,6 +489,7 @@ __device__ __forceinline__ void strip_prologue(const Fbm2dStripArgs &a, StripSha
         sh.shift[tid] = a.shift[tid];
         sh.noff[tid] = a.noff[tid];
         sh.nbr[tid] = a.nbr[tid];
+        if (tid == 0) sh.gw = a.gw;
         sh.amp[tid] = a.amp[tid];
         sh.inv2p[tid] = a.inv2p[tid];
     }
@@ -484,6 +502,7 @@ struct StripWave {
     static constexpr int D1 = 2 * M + 2;
     static constexpr bool H32 = LO <= 5, H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
     float2 *nodes;
+    float *heights;  // height-and-gradient model: a height per node after the gradients
     uint32_t *keys;
     int lane;
     Fixed f64;
@@ -494,22 +513,25 @@ struct StripWave {
 
     __device__ __forceinline__ Fixed fixed(const StripShared &sh, int o) const
     {
-        Fixed f{nodes, XA{0.0f, 0.0f, 0.0f, 0.0f}};
+        Fixed f{nodes, XA{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, heights};
         if (o >= 0) {
             const int s = sh.shift[o];
             f.col = nodes + sh.noff[o] + (lane >> s) * sh.nbr[o];
-            f.xa = xweights<M, MD>((float)(2 * (lane & ((1 << s) - 1)) + 1) * sh.inv2p[o], sh.amp[o]);
+            f.hcol = heights + sh.noff[o] + (lane >> s) * sh.nbr[o];
+            f.xa = xweights<M, MD>((float)(2 * (lane & ((1 << s) - 1)) + 1) * sh.inv2p[o], sh.amp[o], sh.gw);
         }
         return f;
     }
 
     __device__ __forceinline__ Streamed streamed(const StripShared &sh, const Fbm2dStripArgs &a, int o) const
     {
-        return o >= 0 ? Streamed{nodes + sh.noff[o], a.kxoff[o], a.kyoff[o]} : Streamed{nodes, 0, 0};
+        return o >= 0 ? Streamed{nodes + sh.noff[o], a.kxoff[o], a.kyoff[o], heights + sh.noff[o]}
+                      : Streamed{nodes, 0, 0, heights};
     }
 
     __device__ __forceinline__ StripWave(const Fbm2dStripArgs &a, const StripShared &sh, float2 *nodes_, int lane_)
-        : nodes(nodes_), keys(reinterpret_cast<uint32_t *>(nodes_ + a.nodes_total)), lane(lane_)
+        : nodes(nodes_), heights(reinterpret_cast<float *>(nodes_ + a.nodes_total)),
+          keys(reinterpret_cast<uint32_t *>(nodes_ + a.nodes_total) + (MD == 2 ? a.nodes_total : 0)), lane(lane_)
     {
         f64 = fixed(sh, a.o64);
         rc0 = RowCtx{fixed(sh, H32 ? a.o32 : -1), fixed(sh, H16 ? a.o16 : -1), fixed(sh, H8 ? a.o8 : -1),
@@ -550,7 +572,9 @@ struct StripWave {
             const uint32_t it = wl_node[q];
             const uint32_t krow = *reinterpret_cast<const uint32_t *>(key_bytes + (it >> 16));
             const uint32_t kcol = *reinterpret_cast<const uint32_t *>(key_bytes + (it & 0xFFFFu));
-            nodes[q] = node_value<MD>(key_combine(krow, kcol));
+            const uint32_t key = key_combine(krow, kcol);
+            nodes[q] = node_value<MD>(key);
+            if (MD == 2) heights[q] = height2_second(key);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -565,14 +589,14 @@ struct StripWave {
             const int s = a.shift[o];
             const uint32_t mask = (1u << s) - 1u;
             const float inv2p = a.inv2p[o];
-            const XA xa =
-                xweights<M, MD>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p, a.amp[o]);
-            const CF c = column_form<MD>(nodes + a.noff[o], 2, xa);
+            const XA xa = xweights<M, MD>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p,
+                                          a.amp[o], a.gw);
+            const CF c = column_form<MD>(nodes + a.noff[o], 2, xa, heights + a.noff[o]);
             const float invp = 2.0f * inv2p;
             const float tau = (float)(((uint32_t)Y0 & mask) + (uint32_t)(kStripH / 2)) * invp - 0.5f;
             add_mapped<M>(C, c, tau, (float)kStripH * invp);
         }
-        if (a.o64 >= 0) add_piece<M, 1, MD>(C, node_row<2>(f64, 0), node_row<2>(f64, 1));  // t - 1/2 = v
+        if (a.o64 >= 0) add_piece<M, 1, MD>(C, node_row<2, MD>(f64, 0), node_row<2, MD>(f64, 1));  // t - 1/2 = v
 
         // ---- rows: one store per row of the wave; interior strips take the unmasked path --
         const int64_t xe = a.x0 + a.nx, ye = a.y0 + a.ny;

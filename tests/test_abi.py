@@ -17,33 +17,43 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_params_layout_matches_header():
-    # the binding's struct mirrors ptg_params: 4 int32, 3 double, uint32 + 4 int32, 8-byte aligned
-    assert ctypes.sizeof(ptg.Params) == 4 * 4 + 3 * 8 + 5 * 4 + 4
+    # the binding's struct mirrors ptg_params: 4 int32, 3 double, uint32 + 4 int32, double
     assert ptg.Params.model.offset == 4 * 4 + 3 * 8 + 4 * 4
+    assert ptg.Params.gradient_weight.offset == 64 and ctypes.sizeof(ptg.Params) == 72
     p = ptg.Params()
     ptg.lib().ptg_params_default(ctypes.byref(p))
     assert (p.dim, p.smoothness, p.octaves, p.persistence, p.lacunarity, p.seed) == (2, 1, 8, 0.5, 2.0, 1)
-    assert p.model == ptg.PTG_MODEL_GRADIENT
+    assert p.model == ptg.PTG_MODEL_GRADIENT and p.gradient_weight == 0.01
 
 
-def test_zero_gradient_model_validation():
-    """The zero-gradient model (Sec. 3.3) is 2D C1 plain form only, and not served."""
+def test_model_validation():
+    """The zero-gradient model (Sec. 3.3) is 2D C1 plain form only, the height-and-gradient
+    model 2D plain form with a finite weight; neither is served."""
     L = ptg.lib()
     ok = ptg.params(model="zero_gradient", base_freq=1 / 64, octaves=3)
     assert ptg.lib().ptg_tune_query_2d(ctypes.byref(ok), 64, 64, ctypes.byref(ctypes.c_int32()),
                                        ctypes.byref(ctypes.c_int32())) == ptg.PTG_OK
-    for kw in (dict(model=2), dict(model=-1), dict(model="zero_gradient", smoothness=2),
-               dict(model="zero_gradient", form="mfma_f16")):
+    for kw in (dict(model=3), dict(model=-1), dict(model="zero_gradient", smoothness=2),
+               dict(model="zero_gradient", form="mfma_f16"), dict(model="height_gradient", form="mfma_bf16"),
+               dict(model="height_gradient", gradient_weight=float("inf")),
+               dict(model="height_gradient", gradient_weight=float("nan"))):
         p = ptg.params(base_freq=1 / 64, octaves=3, **kw)
         assert L.ptg_fbm_2d(ctypes.byref(p), 0, 0, 16, 16, ctypes.c_void_p(1 << 20), 16, None) == ptg.PTG_EINVAL
-    p3 = ptg.params(dim=3, model="zero_gradient", base_freq=1 / 64, octaves=3)
-    assert L.ptg_fbm_3d(ctypes.byref(p3), 0, 0, 0, 8, 8, 8, ctypes.c_void_p(1 << 20), None) == ptg.PTG_EINVAL
+    for m in ("zero_gradient", "height_gradient"):
+        p3 = ptg.params(dim=3, model=m, base_freq=1 / 64, octaves=3)
+        assert L.ptg_fbm_3d(ctypes.byref(p3), 0, 0, 0, 8, 8, 8, ctypes.c_void_p(1 << 20), None) == ptg.PTG_EINVAL
+    ok2 = ptg.params(model="height_gradient", smoothness=2, base_freq=1 / 64, octaves=3, gradient_weight=-0.3)
+    assert ptg.lib().ptg_tune_query_2d(ctypes.byref(ok2), 64, 64, ctypes.byref(ctypes.c_int32()),
+                                       ctypes.byref(ctypes.c_int32())) == ptg.PTG_OK
     assert L.ptg_heights_2d(1, -1, 0, 0, 4, 4, ctypes.c_void_p(1), None) == ptg.PTG_EINVAL
     assert L.ptg_heights_2d(1, 0, 0, 0, 4, 4, None, None) == ptg.PTG_EINVAL
     assert L.ptg_heights_2d(1, 0, 0, 0, 0, 4, None, None) == ptg.PTG_OK  # empty box
     with ptg.Server(1 << 20, executor=ptg.PTG_EXEC_HOST) as s:
         with pytest.raises(ptg.PtgError) as e:
             s.submit([ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=1 / 64, model="zero_gradient")])
+        assert e.value.code == ptg.PTG_EINVAL
+        with pytest.raises(ptg.PtgError) as e:
+            s.submit([ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=1 / 64, model="height_gradient")])
         assert e.value.code == ptg.PTG_EINVAL
 
 
