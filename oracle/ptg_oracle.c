@@ -173,7 +173,10 @@ void orc_coord(int64_t X, double f, int64_t *cell, double *t)
  * first derivative at the other end, zero higher derivatives up to M).
  * Cubic (M=1): b0[1] = S3 = 3t^2 - 2t^3 (Sec. 3.2), b1[0] = t(1-t)^2, b1[1] = -t^2(1-t).
  * Quintic (M=2): b0[1] = S5 = 6t^5 - 15t^4 + 10t^3 (Sec. 5.1),
- *   b1[0] = t - 6t^3 + 8t^4 - 3t^5, b1[1] = -4t^3 + 7t^4 - 3t^5. */
+ *   b1[0] = t - 6t^3 + 8t^4 - 3t^5, b1[1] = -4t^3 + 7t^4 - 3t^5.
+ * Septic (M=3, derivatives up to 3 constrained, Sec. 2.2 with n = 7):
+ *   b0[1] = S7 = 35t^4 - 84t^5 + 70t^6 - 20t^7,
+ *   b1[0] = t - 20t^4 + 45t^5 - 36t^6 + 10t^7, b1[1] = -15t^4 + 39t^5 - 34t^6 + 10t^7. */
 void orc_basis(int32_t smooth, double t, double *b0, double *b1)
 {
     double t2 = t * t, t3 = t2 * t;
@@ -183,21 +186,28 @@ void orc_basis(int32_t smooth, double t, double *b0, double *b1)
         b0[1] = s;
         b1[0] = t * (1.0 - t) * (1.0 - t);
         b1[1] = -t2 * (1.0 - t);
-    } else {
+    } else if (smooth == 2) {
         double t4 = t3 * t, t5 = t4 * t;
         double s = 6.0 * t5 - 15.0 * t4 + 10.0 * t3;
         b0[0] = 1.0 - s;
         b0[1] = s;
         b1[0] = t - 6.0 * t3 + 8.0 * t4 - 3.0 * t5;
         b1[1] = -4.0 * t3 + 7.0 * t4 - 3.0 * t5;
+    } else {
+        double t4 = t3 * t, t5 = t4 * t, t6 = t5 * t, t7 = t6 * t;
+        double s = 35.0 * t4 - 84.0 * t5 + 70.0 * t6 - 20.0 * t7;
+        b0[0] = 1.0 - s;
+        b0[1] = s;
+        b1[0] = t - 20.0 * t4 + 45.0 * t5 - 36.0 * t6 + 10.0 * t7;
+        b1[1] = -15.0 * t4 + 39.0 * t5 - 34.0 * t6 + 10.0 * t7;
     }
 }
 
 /* Monomial coefficients of the same bases: bases[k][e] is the coefficient of t^e,
  * k = 0: b0[0], 1: b0[1], 2: b1[0], 3: b1[1]; degree n = 2M+1. */
-static void orc_basis_monomials(int32_t smooth, double bases[4][6])
+static void orc_basis_monomials(int32_t smooth, double bases[4][8])
 {
-    memset(bases, 0, sizeof(double) * 24);
+    memset(bases, 0, sizeof(double) * 32);
     if (smooth == 1) {
         /* 1 - 3t^2 + 2t^3 */
         bases[0][0] = 1.0; bases[0][2] = -3.0; bases[0][3] = 2.0;
@@ -207,7 +217,7 @@ static void orc_basis_monomials(int32_t smooth, double bases[4][6])
         bases[2][1] = 1.0; bases[2][2] = -2.0; bases[2][3] = 1.0;
         /* -t^2 + t^3 */
         bases[3][2] = -1.0; bases[3][3] = 1.0;
-    } else {
+    } else if (smooth == 2) {
         /* 1 - 10t^3 + 15t^4 - 6t^5 */
         bases[0][0] = 1.0; bases[0][3] = -10.0; bases[0][4] = 15.0; bases[0][5] = -6.0;
         /* 10t^3 - 15t^4 + 6t^5 */
@@ -216,6 +226,15 @@ static void orc_basis_monomials(int32_t smooth, double bases[4][6])
         bases[2][1] = 1.0; bases[2][3] = -6.0; bases[2][4] = 8.0; bases[2][5] = -3.0;
         /* -4t^3 + 7t^4 - 3t^5 */
         bases[3][3] = -4.0; bases[3][4] = 7.0; bases[3][5] = -3.0;
+    } else {
+        /* 1 - 35t^4 + 84t^5 - 70t^6 + 20t^7 */
+        bases[0][0] = 1.0; bases[0][4] = -35.0; bases[0][5] = 84.0; bases[0][6] = -70.0; bases[0][7] = 20.0;
+        /* 35t^4 - 84t^5 + 70t^6 - 20t^7 */
+        bases[1][4] = 35.0; bases[1][5] = -84.0; bases[1][6] = 70.0; bases[1][7] = -20.0;
+        /* t - 20t^4 + 45t^5 - 36t^6 + 10t^7 */
+        bases[2][1] = 1.0; bases[2][4] = -20.0; bases[2][5] = 45.0; bases[2][6] = -36.0; bases[2][7] = 10.0;
+        /* -15t^4 + 39t^5 - 34t^6 + 10t^7 */
+        bases[3][4] = -15.0; bases[3][5] = 39.0; bases[3][6] = -34.0; bases[3][7] = 10.0;
     }
 }
 
@@ -264,7 +283,7 @@ double orc_cell_3d(int32_t smooth, const double *grad, double tx, double ty, dou
  * expanding the Hermite form above. */
 void orc_coeffs_2d(int32_t smooth, const double *grad, double *c)
 {
-    double B[4][6];
+    double B[4][8];
     orc_basis_monomials(smooth, B);
     int n1 = 2 * smooth + 2;
     memset(c, 0, sizeof(double) * (size_t)(n1 * n1));
@@ -284,7 +303,7 @@ void orc_coeffs_2d(int32_t smooth, const double *grad, double *c)
 /* Monomial coefficients c[(i*(n+1) + j)*(n+1) + k] of x^i y^j z^k (D = 3). */
 void orc_coeffs_3d(int32_t smooth, const double *grad, double *c)
 {
-    double B[4][6];
+    double B[4][8];
     orc_basis_monomials(smooth, B);
     int n1 = 2 * smooth + 2;
     memset(c, 0, sizeof(double) * (size_t)(n1 * n1 * n1));
@@ -334,7 +353,7 @@ double orc_perlin_cell(int32_t fade_order, const double *grad, double x, double 
 
 static int orc_check(int32_t smooth, int32_t octaves, double f0, double lac, double pers)
 {
-    if (smooth != 1 && smooth != 2) return ORC_EINVAL;
+    if (smooth < 1 || smooth > 3) return ORC_EINVAL;
     if (octaves < 1 || octaves > ORC_MAX_OCTAVES) return ORC_EINVAL;
     if (!(f0 > 0.0) || !(lac > 0.0) || !(pers > 0.0)) return ORC_EINVAL;
     if (!isfinite(f0) || !isfinite(lac) || !isfinite(pers)) return ORC_EINVAL;
