@@ -292,6 +292,12 @@ def other_configs(torch, ptg, stream):
         ms = _time_launches(torch, stream, lambda: ptg.fbm_2d_raw(q, 0, 0, 8192, 8192, zf.data_ptr(), 8192, sh), 10)
         hg[f"C{m}"] = {"ms": ms, "octave_samples_s": 8192 * 8192 * 8 / (ms * 1e-3),
                        "hbm_frac": 8192 * 8192 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    q = ptg.params(smoothness=3, octaves=8, base_freq=16 / 8192, seed=1)
+    ms = _time_launches(torch, stream, lambda: ptg.fbm_2d_raw(q, 0, 0, 8192, 8192, zf.data_ptr(), 8192, sh), 5)
+    res["2d_8192_8oct_c3"] = {"workload": "septic (C3) cells, gradient model, 8192^2, 8 octaves, base lattice 16^2, "
+                                          "FP32, seed 1 (general kernel)",
+                              "ms": ms, "octave_samples_s": 8192 * 8192 * 8 / (ms * 1e-3),
+                              "hbm_frac": 8192 * 8192 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     res["2d_8192_8oct_height_gradient"] = {
         "workload": "heights and gradients (weight 0.01) in tensor Hermite cells, 8192^2, 8 octaves, base lattice "
                     "16^2, FP32, seed 1, strip kernel",

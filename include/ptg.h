@@ -106,7 +106,8 @@ extern "C" {
  * Sec. 4: octaves, persistence, lacunarity). */
 typedef struct ptg_params {
     int32_t dim;          /* 2 or 3                                                    */
-    int32_t smoothness;   /* 1 = C1 cubic cells, 2 = C2 quintic cells                  */
+    int32_t smoothness;   /* 1 = C1 cubic, 2 = C2 quintic, 3 = C3 septic cells (3: the  */
+                          /* general kernels only; not served, no matrix-core form)    */
     int32_t octaves;      /* 1 .. PTG_MAX_OCTAVES                                      */
     int32_t out_dtype;    /* PTG_F32 or PTG_F16                                        */
     double persistence;   /* amplitude ratio per octave, finite, > 0                   */

@@ -34,8 +34,9 @@ int validate_params(const ptg_params *p, int dim)
 {
     if (!p) return fail(PTG_EINVAL, "params is NULL");
     if (p->dim != dim) return fail(PTG_EINVAL, "params.dim is %d, this entry point takes %d", p->dim, dim);
-    if (p->smoothness != 1 && p->smoothness != 2)
-        return fail(PTG_EINVAL, "smoothness must be 1 (C1 cubic) or 2 (C2 quintic), got %d", p->smoothness);
+    if (p->smoothness < 1 || p->smoothness > 3)
+        return fail(PTG_EINVAL, "smoothness must be 1 (C1 cubic), 2 (C2 quintic) or 3 (C3 septic), got %d",
+                    p->smoothness);
     if (p->octaves < 1 || p->octaves > PTG_MAX_OCTAVES)
         return fail(PTG_EINVAL, "octaves must be in 1..%d, got %d", PTG_MAX_OCTAVES, p->octaves);
     if (p->out_dtype != PTG_F32 && p->out_dtype != PTG_F16)

@@ -134,6 +134,20 @@ struct Basis<2> {
     }
 };
 
+// Septic cells (M = 3: derivatives up to third order constrained): the degree-7
+// smoothstep and the two slope bases with zero second and third end derivatives.
+template <>
+struct Basis<3> {
+    __device__ __forceinline__ static void eval(float t, float &s, float &b10, float &b11)
+    {
+        const float t2 = t * t;
+        const float t4 = t2 * t2;
+        s = t4 * (35.0f + t * (-84.0f + t * (70.0f - 20.0f * t)));
+        b10 = t + t4 * (-20.0f + t * (45.0f + t * (-36.0f + 10.0f * t)));
+        b11 = t4 * (-15.0f + t * (39.0f + t * (-34.0f + 10.0f * t)));
+    }
+};
+
 // Monomial coefficients of the four 1D bases, rows: 1-s, s, b10, b11; column e = t^e.
 // Used by the per-cell coefficient kernel (K2) to expand the tensor form.
 template <int M>

@@ -40,9 +40,15 @@ static hipError_t launch_2d_th(const Fbm2dArgs &a, int smooth, bool f16, dim3 gr
         if (smooth == 1)
             return f16 ? launch_dyn(k_fbm2d_general<1, __half, TH, 2>, grid, lds, s, a)
                        : launch_dyn(k_fbm2d_general<1, float, TH, 2>, grid, lds, s, a);
+        if (smooth == 3)
+            return f16 ? launch_dyn(k_fbm2d_general<3, __half, TH, 2>, grid, lds, s, a)
+                       : launch_dyn(k_fbm2d_general<3, float, TH, 2>, grid, lds, s, a);
         return f16 ? launch_dyn(k_fbm2d_general<2, __half, TH, 2>, grid, lds, s, a)
                    : launch_dyn(k_fbm2d_general<2, float, TH, 2>, grid, lds, s, a);
     }
+    if (smooth == 3)
+        return f16 ? launch_dyn(k_fbm2d_general<3, __half, TH>, grid, lds, s, a)
+                   : launch_dyn(k_fbm2d_general<3, float, TH>, grid, lds, s, a);
     if (smooth == 1)
         return f16 ? launch_dyn(k_fbm2d_general<1, __half, TH>, grid, lds, s, a)
                    : launch_dyn(k_fbm2d_general<1, float, TH>, grid, lds, s, a);
@@ -68,6 +74,9 @@ hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t
     if (smooth == 1)
         return f16 ? launch_dyn(k_fbm3d_general<1, __half>, grid, lds, s, a)
                    : launch_dyn(k_fbm3d_general<1, float>, grid, lds, s, a);
+    if (smooth == 3)
+        return f16 ? launch_dyn(k_fbm3d_general<3, __half>, grid, lds, s, a)
+                   : launch_dyn(k_fbm3d_general<3, float>, grid, lds, s, a);
     return f16 ? launch_dyn(k_fbm3d_general<2, __half>, grid, lds, s, a)
                : launch_dyn(k_fbm3d_general<2, float>, grid, lds, s, a);
 }

@@ -257,7 +257,9 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     const bool dy = dyadic_shift(p, &k);
     if (p->path == PTG_PATH_DYADIC && !dy)
         return fail(PTG_EINVAL, "the dyadic kernel needs base_freq = 2^-k (k <= %d) and lacunarity 2", kDyMaxShift);
-    if (dy && p->path != PTG_PATH_GENERAL) {
+    if (p->path == PTG_PATH_DYADIC && p->smoothness == 3)
+        return fail(PTG_EINVAL, "septic cells (smoothness 3) run on the general kernel only");
+    if (dy && p->path != PTG_PATH_GENERAL && p->smoothness <= 2) {
         int rc = fbm2d_strip(p, k, x0, y0, nx, ny, out, pitch, s);
         if (rc <= 0) return rc;
         if (p->model == PTG_MODEL_GRADIENT) {  // the matrix-core tile kernel has gradient-model cells only
@@ -376,7 +378,9 @@ int fbm3d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t
     const bool dy = dyadic_shift(p, &k);
     if (p->path == PTG_PATH_DYADIC && !dy)
         return fail(PTG_EINVAL, "the dyadic kernel needs base_freq = 2^-k (k <= %d) and lacunarity 2", kDyMaxShift);
-    if (dy && p->path != PTG_PATH_GENERAL) {
+    if (p->path == PTG_PATH_DYADIC && p->smoothness == 3)
+        return fail(PTG_EINVAL, "septic cells (smoothness 3) run on the general kernel only");
+    if (dy && p->path != PTG_PATH_GENERAL && p->smoothness <= 2) {
         const int rc = fbm3d_strip(p, k, x0, y0, z0, nx, ny, nz, out, s);
         if (rc <= 0) return rc;
         if (p->path == PTG_PATH_DYADIC)

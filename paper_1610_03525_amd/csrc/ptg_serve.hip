@@ -990,6 +990,7 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
     if (p->form != PTG_FORM_PLAIN || p->out_dtype != PTG_F32)
         return fail(PTG_EINVAL, "served tiles use the plain form with FP32 output");
     if (p->model != PTG_MODEL_GRADIENT) return fail(PTG_EINVAL, "served tiles use the gradient model");
+    if (p->smoothness > 2) return fail(PTG_EINVAL, "served tiles are C1 or C2");
     const int nd = p->dim;
     for (int a = 0; a < 3; ++a) {
         if (a < nd) {

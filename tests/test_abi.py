@@ -39,6 +39,12 @@ def test_model_validation():
                dict(model="height_gradient", gradient_weight=float("nan"))):
         p = ptg.params(base_freq=1 / 64, octaves=3, **kw)
         assert L.ptg_fbm_2d(ctypes.byref(p), 0, 0, 16, 16, ctypes.c_void_p(1 << 20), 16, None) == ptg.PTG_EINVAL
+    # septic cells: general kernels only (no matrix-core form, no dyadic path, not served)
+    for kw in (dict(smoothness=3, form="mfma_f16"), dict(smoothness=3, path="dyadic")):
+        p = ptg.params(base_freq=1 / 64, octaves=3, **kw)
+        assert L.ptg_fbm_2d(ctypes.byref(p), 0, 0, 16, 16, ctypes.c_void_p(1 << 20), 16, None) == ptg.PTG_EINVAL
+    assert ptg.tune_query((64, 64), smoothness=3, octaves=3, base_freq=1 / 64) == ("general_2d", 64)
+    assert ptg.tune_query((64, 64, 64), smoothness=3, octaves=3, base_freq=1 / 16) == ("general_3d", 0)
     for m in ("zero_gradient", "height_gradient"):
         p3 = ptg.params(dim=3, model=m, base_freq=1 / 64, octaves=3)
         assert L.ptg_fbm_3d(ctypes.byref(p3), 0, 0, 0, 8, 8, 8, ctypes.c_void_p(1 << 20), None) == ptg.PTG_EINVAL
@@ -55,6 +61,9 @@ def test_model_validation():
         with pytest.raises(ptg.PtgError) as e:
             s.submit([ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=1 / 64, model="height_gradient")])
         assert e.value.code == ptg.PTG_EINVAL
+        with pytest.raises(ptg.PtgError) as e:
+            s.submit([ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=1 / 64, smoothness=3)])
+        assert e.value.code == ptg.PTG_EINVAL
 
 
 def _fbm2(p, x0=0, y0=0, nx=16, ny=16, out=1 << 20, pitch=16):
@@ -62,7 +71,7 @@ def _fbm2(p, x0=0, y0=0, nx=16, ny=16, out=1 << 20, pitch=16):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("dim", 3), ("smoothness", 0), ("smoothness", 3), ("octaves", 0), ("octaves", 17), ("out_dtype", 5),
+    ("dim", 3), ("smoothness", 0), ("smoothness", 4), ("octaves", 0), ("octaves", 17), ("out_dtype", 5),
     ("persistence", 0.0), ("persistence", float("nan")), ("lacunarity", -2.0), ("base_freq", 0.0),
     ("base_freq", float("inf")), ("form", 9), ("basis", 7), ("path", 3), ("path", -1),
 ])
