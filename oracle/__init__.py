@@ -85,6 +85,11 @@ def lib():
     L.orc_hg_fbm_2d.restype = _i32
     L.orc_hg_fbm_points_2d.argtypes = [_i32, _i32, _f64, _f64, _f64, _f64, _u32, _pi64, _pi64, _i64, _pd, _i32]
     L.orc_hg_fbm_points_2d.restype = _i32
+    L.orc_basis_deriv.argtypes = [_i32, _f64, _pd, _pd]
+    L.orc_cell_2d_grad.argtypes = [_i32, _i32, _pd, _pd, _f64, _f64, _f64, _pd]
+    L.orc_fbm_2d_grad.argtypes = [_i32, _i32, _i32, _f64, _f64, _f64, _f64, _u32, _i64, _i64, _i64, _i64, _pd, _pd,
+                                  _pd, _i32]
+    L.orc_fbm_2d_grad.restype = _i32
     L.orc_max_threads.argtypes = []
     L.orc_max_threads.restype = _i32
     _LIB = L
@@ -307,6 +312,35 @@ def hg_fbm_points_2d(smooth, octaves, pers, lac, f0, w, seed, X, Y, nthreads=0) 
     _chk(lib().orc_hg_fbm_points_2d(smooth, octaves, pers, lac, f0, w, seed & 0xFFFFFFFF, _ip(X), _ip(Y), X.shape[0],
                                     _dp(out), nthreads))
     return out
+
+
+# --- analytic gradient (Sec. 5.1 gradient maps) ----------------------------------
+
+MODELS = {"gradient": 0, "zero_gradient": 1, "height_gradient": 2}
+
+
+def basis_deriv(smooth: int, t: float):
+    db0 = np.zeros(2)
+    db1 = np.zeros(2)
+    lib().orc_basis_deriv(smooth, t, _dp(db0), _dp(db1))
+    return db0, db1
+
+
+def cell_2d_grad(model, smooth, h, grad, w, x, y) -> np.ndarray:
+    """(value, d/dtx, d/dty) of one cell of the model."""
+    hh = np.ascontiguousarray(h, dtype=np.float64).reshape(4)
+    g = np.ascontiguousarray(grad, dtype=np.float64).reshape(8)
+    out = np.zeros(3)
+    lib().orc_cell_2d_grad(MODELS.get(model, model), smooth, _dp(hh), _dp(g), w, x, y, _dp(out))
+    return out
+
+
+def fbm_2d_grad(model, smooth, octaves, pers, lac, f0, w, seed, x0, y0, nx, ny, nthreads=0):
+    """(H, dH/dX, dH/dY), each (ny, nx)."""
+    outs = [np.empty((ny, nx), dtype=np.float64) for _ in range(3)]
+    _chk(lib().orc_fbm_2d_grad(MODELS.get(model, model), smooth, octaves, pers, lac, f0, w, seed & 0xFFFFFFFF, x0, y0,
+                               nx, ny, _dp(outs[0]), _dp(outs[1]), _dp(outs[2]), nthreads))
+    return tuple(outs)
 
 
 def max_threads() -> int:

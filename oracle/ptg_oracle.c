@@ -25,6 +25,8 @@
  *    coefficients (see orc_zg_cell).
  *  - Sec. 3.1 with non-zero heights and Sec. 4's gradient weight w: corner heights and
  *    w-scaled corner gradients in the same tensor Hermite form (see orc_hg_cell).
+ *  - Sec. 5.1 (the gradient-norm maps): the height field's analytic gradient, per octave
+ *    the cell derivative times the octave frequency (see orc_fbm_2d_grad).
  *
  * Readings taken where the paper is silent (each one is listed in the design notes):
  *  - Cell polynomial: the unique tensor polynomial of degree n = 2M+1 per axis whose
@@ -645,6 +647,114 @@ int orc_hg_fbm_points_2d(int32_t smooth, int32_t octaves, double pers, double la
     orc_set_threads(nthreads);
 #pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < n; ++q) out[q] = orc_hg_sample(smooth, octaves, freq, amp, w, seed, X[q], Y[q]);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Analytic gradient of the height field (the gradient maps of Sec. 5.1)     */
+/* ------------------------------------------------------------------------- */
+
+/* Derivatives d/dt of the 1D bases of orc_basis. */
+void orc_basis_deriv(int32_t smooth, double t, double *db0, double *db1)
+{
+    double t2 = t * t, t3 = t2 * t;
+    double ds;
+    if (smooth == 1) {
+        ds = 6.0 * t - 6.0 * t2;
+        db1[0] = 1.0 - 4.0 * t + 3.0 * t2;
+        db1[1] = -2.0 * t + 3.0 * t2;
+    } else if (smooth == 2) {
+        double t4 = t3 * t;
+        ds = 30.0 * t2 - 60.0 * t3 + 30.0 * t4;
+        db1[0] = 1.0 - 18.0 * t2 + 32.0 * t3 - 15.0 * t4;
+        db1[1] = -12.0 * t2 + 28.0 * t3 - 15.0 * t4;
+    } else {
+        double t4 = t3 * t, t5 = t4 * t, t6 = t5 * t;
+        ds = 140.0 * t3 - 420.0 * t4 + 420.0 * t5 - 140.0 * t6;
+        db1[0] = 1.0 - 80.0 * t3 + 225.0 * t4 - 216.0 * t5 + 70.0 * t6;
+        db1[1] = -60.0 * t3 + 195.0 * t4 - 204.0 * t5 + 70.0 * t6;
+    }
+    db0[0] = -ds;
+    db0[1] = ds;
+}
+
+/* Value and its derivatives in the cell coordinates (d/dtx, d/dty) of one cell of model
+ * 0 (gradient), 1 (zero-gradient, smooth = 1) or 2 (heights and w-weighted gradients);
+ * h[4] heights (models 1, 2), grad[8] gradients (models 0, 2). */
+void orc_cell_2d_grad(int32_t model, int32_t smooth, const double *h, const double *grad, double w, double tx,
+                      double ty, double *out)
+{
+    if (model == 1) {
+        double sx = tx * tx * (3.0 - 2.0 * tx), sy = ty * ty * (3.0 - 2.0 * ty);
+        double dsx = 6.0 * tx * (1.0 - tx), dsy = 6.0 * ty * (1.0 - ty);
+        double dx = h[1] - h[0], dy = h[2] - h[0], A = h[3] + h[0] - h[1] - h[2];
+        out[0] = orc_zg_cell(h, tx, ty);
+        out[1] = dsx * dx + A * (dsx * ty + sy - ty);
+        out[2] = dsy * dy + A * (sx + dsy * tx - tx);
+        return;
+    }
+    double bx0[2], bx1[2], by0[2], by1[2], dbx0[2], dbx1[2], dby0[2], dby1[2];
+    orc_basis(smooth, tx, bx0, bx1);
+    orc_basis(smooth, ty, by0, by1);
+    orc_basis_deriv(smooth, tx, dbx0, dbx1);
+    orc_basis_deriv(smooth, ty, dby0, dby1);
+    double v = 0.0, vx = 0.0, vy = 0.0;
+    double gw = (model == 2) ? w : 1.0;
+    for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+            int c = cx + 2 * cy;
+            double gx = gw * grad[2 * c], gy = gw * grad[2 * c + 1];
+            v += gx * bx1[cx] * by0[cy] + gy * bx0[cx] * by1[cy];
+            vx += gx * dbx1[cx] * by0[cy] + gy * dbx0[cx] * by1[cy];
+            vy += gx * bx1[cx] * dby0[cy] + gy * bx0[cx] * dby1[cy];
+            if (model == 2) {
+                v += h[c] * bx0[cx] * by0[cy];
+                vx += h[c] * dbx0[cx] * by0[cy];
+                vy += h[c] * bx0[cx] * dby0[cy];
+            }
+        }
+    out[0] = v;
+    out[1] = vx;
+    out[2] = vy;
+}
+
+/* H and its world-space gradient (dH/dX, dH/dY = sum_o a_o f_o dh_o/dt) over a row-major
+ * [ny][nx] field, for any of the three models. */
+int orc_fbm_2d_grad(int32_t model, int32_t smooth, int32_t octaves, double pers, double lac, double f0, double w,
+                    uint32_t seed, int64_t x0, int64_t y0, int64_t nx, int64_t ny, double *out_h, double *out_dx,
+                    double *out_dy, int32_t nthreads)
+{
+    if (orc_check(smooth, octaves, f0, lac, pers) != ORC_OK || model < 0 || model > 2 || (model == 1 && smooth != 1) ||
+        !isfinite(w) || nx < 0 || ny < 0 || !out_h || !out_dx || !out_dy)
+        return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i) {
+            double H = 0.0, HX = 0.0, HY = 0.0;
+            for (int32_t o = 0; o < octaves; ++o) {
+                int64_t cx, cy;
+                double tx, ty, h[4], grad[8], v[3];
+                orc_coord(x0 + i, freq[o], &cx, &tx);
+                orc_coord(y0 + j, freq[o], &cy, &ty);
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        uint32_t key = orc_key2(cx + dx, cy + dy, o, seed);
+                        int c = dx + 2 * dy;
+                        h[c] = (model == 1) ? orc_height2(key) : orc_height2_second(key);
+                        orc_grad2(key, &grad[2 * c]);
+                    }
+                orc_cell_2d_grad(model, smooth, h, grad, w, tx, ty, v);
+                H += amp[o] * v[0];
+                HX += amp[o] * freq[o] * v[1];
+                HY += amp[o] * freq[o] * v[2];
+            }
+            out_h[j * nx + i] = H;
+            out_dx[j * nx + i] = HX;
+            out_dy[j * nx + i] = HY;
+        }
     return ORC_OK;
 }
 
