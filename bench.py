@@ -298,6 +298,15 @@ def other_configs(torch, ptg, stream):
                                           "FP32, seed 1 (general kernel)",
                               "ms": ms, "octave_samples_s": 8192 * 8192 * 8 / (ms * 1e-3),
                               "hbm_frac": 8192 * 8192 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    gx, gy = torch.empty_like(zf), torch.empty_like(zf)
+    q = ptg.params(smoothness=1, octaves=8, base_freq=16 / 8192, seed=1)
+    ms = _time_launches(torch, stream, lambda: ptg.lib().ptg_fbm_2d_grad(
+        ctypes.byref(q), 0, 0, 8192, 8192, zf.data_ptr(), gx.data_ptr(), gy.data_ptr(), 8192, sh), 5)
+    res["2d_8192_8oct_gradient_output"] = {
+        "workload": "H, dH/dX, dH/dY of the 8192^2 8-octave C1 field (three FP32 outputs; general kernel)",
+        "ms": ms, "octave_samples_s": 8192 * 8192 * 8 / (ms * 1e-3),
+        "hbm_frac": 3 * 8192 * 8192 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del gx, gy
     res["2d_8192_8oct_height_gradient"] = {
         "workload": "heights and gradients (weight 0.01) in tensor Hermite cells, 8192^2, 8 octaves, base lattice "
                     "16^2, FP32, seed 1, strip kernel",

@@ -147,6 +147,14 @@ PTG_API void ptg_params_default(ptg_params *p);
 PTG_API int ptg_fbm_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny,
                void *out_dev, int64_t row_pitch, void *stream);
 
+/* The 2D field of ptg_fbm_2d and its analytic gradient (the gradient maps of Sec. 5.1):
+ * out_dev[j*row_pitch + i] = H(X, Y), dx_dev[...] = dH/dX, dy_dev[...] = dH/dY in world
+ * units (per sample: sum_o a_o f_o dh_o/dt), the three buffers of p->out_dtype with the same
+ * layout.  Any model and smoothness; plain form; computed by the general kernel.
+ * Errors: as ptg_fbm_2d (PTG_EINVAL also for a NULL output or a matrix-core form). */
+PTG_API int ptg_fbm_2d_grad(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out_dev,
+                    void *dx_dev, void *dy_dev, int64_t row_pitch, void *stream);
+
 /* 3D fBm volume over X = x0+i, Y = y0+j, Z = z0+k; out_dev dense row-major
  * [nz][ny][nx] of p->out_dtype (D3M1N3 / D3M2N5 cells, Sec. 3.4).  p->dim must be 3 and
  * p->form PTG_FORM_PLAIN.  Errors as ptg_fbm_2d. */

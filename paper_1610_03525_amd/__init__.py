@@ -143,6 +143,7 @@ def lib():
     L.ptg_params_default.argtypes = [_PP]
     L.ptg_fbm_2d.argtypes = [_PP, _i64, _i64, _i64, _i64, _vp, _i64, _vp]
     L.ptg_fbm_3d.argtypes = [_PP, _i64, _i64, _i64, _i64, _i64, _i64, _vp, _vp]
+    L.ptg_fbm_2d_grad.argtypes = [_PP, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _i64, _vp]
     L.ptg_coords.argtypes = [_f64, _f64, _i32, _i64, _i64, _vp, _vp, _vp]
     L.ptg_lattice_2d.argtypes = [_u32, _i32, _i64, _i64, _i64, _i64, _vp, _vp, _vp]
     L.ptg_lattice_3d.argtypes = [_u32, _i32, _i64, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp]
@@ -165,7 +166,7 @@ def lib():
     L.ptg_tune_set_3d.argtypes = [_PP, _i64, _i64, _i64, _i32]
     L.ptg_tune_reset.argtypes = []
     L.ptg_tune_reset.restype = None
-    for name in ("ptg_fbm_2d", "ptg_fbm_3d", "ptg_coords", "ptg_lattice_2d", "ptg_lattice_3d", "ptg_heights_2d",
+    for name in ("ptg_fbm_2d", "ptg_fbm_2d_grad", "ptg_fbm_3d", "ptg_coords", "ptg_lattice_2d", "ptg_lattice_3d", "ptg_heights_2d",
                  "ptg_cells_2d", "ptg_cells_3d", "ptg_server_create", "ptg_tiles_submit", "ptg_tiles_wait",
                  "ptg_tile_release", "ptg_server_stats_get", "ptg_server_destroy", "ptg_tune_2d", "ptg_tune_3d",
                  "ptg_tune_query_2d", "ptg_tune_query_3d", "ptg_tune_set_2d", "ptg_tune_set_3d"):
@@ -254,6 +255,20 @@ def fbm_2d(out, *, x0=0, y0=0, stream=None, **kw):
     ny, nx = out.shape
     fbm_2d_raw(p, x0, y0, nx, ny, _dev_ptr(out) if out.numel() else None, out.stride(0), _stream(stream))
     return out
+
+
+def fbm_2d_grad(out, out_dx, out_dy, *, x0=0, y0=0, stream=None, **kw):
+    """The 2D field into out and its world-space gradient dH/dX, dH/dY into out_dx, out_dy
+    (three (ny, nx) tensors of one dtype and row stride)."""
+    for t in (out, out_dx, out_dy):
+        if t.dim() != 2 or t.stride(1) != 1 or t.shape != out.shape or t.stride(0) != out.stride(0) \
+                or t.dtype != out.dtype:
+            raise ValueError("outputs must be 2D tensors of one shape, dtype and row stride")
+    p = params(dim=2, out_dtype=_out_dtype(out), **kw)
+    ny, nx = out.shape
+    ptrs = [_dev_ptr(t) if t.numel() else None for t in (out, out_dx, out_dy)]
+    _check(lib().ptg_fbm_2d_grad(ctypes.byref(p), x0, y0, nx, ny, *ptrs, out.stride(0), _stream(stream)))
+    return out, out_dx, out_dy
 
 
 def fbm_3d(out, *, x0=0, y0=0, z0=0, stream=None, **kw):

@@ -151,6 +151,22 @@ int ptg_fbm_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t 
     return fbm2d_plain(p, x0, y0, nx, ny, out_dev, row_pitch, s);
 }
 
+int ptg_fbm_2d_grad(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out_dev,
+                    void *dx_dev, void *dy_dev, int64_t row_pitch, void *stream)
+{
+    int rc = validate_params(p, 2);
+    if (rc) return rc;
+    if (p->form != PTG_FORM_PLAIN) return fail(PTG_EINVAL, "the gradient output is computed in the plain form");
+    if ((rc = validate_extent("x", x0, nx))) return rc;
+    if ((rc = validate_extent("y", y0, ny))) return rc;
+    if (nx == 0 || ny == 0) return PTG_OK;
+    if (!out_dev || !dx_dev || !dy_dev) return fail(PTG_EINVAL, "an output pointer is NULL");
+    if (row_pitch < nx) return fail(PTG_EINVAL, "row_pitch %lld < nx %lld", (long long)row_pitch, (long long)nx);
+    const int64_t tiles_x = (nx + kTile2 - 1) / kTile2, tiles_y = (ny + kTile2 - 1) / kTile2;
+    if (tiles_x * tiles_y > 0x7FFFFFFFLL) return fail(PTG_EINVAL, "field too large for one launch");
+    return fbm2d_grad(p, x0, y0, nx, ny, out_dev, dx_dev, dy_dev, row_pitch, reinterpret_cast<hipStream_t>(stream));
+}
+
 int ptg_fbm_3d(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz,
                void *out_dev, void *stream)
 {

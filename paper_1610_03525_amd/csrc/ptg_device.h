@@ -148,6 +148,42 @@ struct Basis<3> {
     }
 };
 
+// Derivatives d/dt of the bases above (the analytic gradient of the height field).
+template <int M>
+struct BasisD;
+
+template <>
+struct BasisD<1> {
+    __device__ __forceinline__ static void eval(float t, float &ds, float &db10, float &db11)
+    {
+        ds = 6.0f * t * (1.0f - t);
+        db10 = 1.0f + t * (-4.0f + 3.0f * t);
+        db11 = t * (-2.0f + 3.0f * t);
+    }
+};
+
+template <>
+struct BasisD<2> {
+    __device__ __forceinline__ static void eval(float t, float &ds, float &db10, float &db11)
+    {
+        const float t2 = t * t;
+        ds = t2 * (30.0f + t * (-60.0f + 30.0f * t));
+        db10 = 1.0f + t2 * (-18.0f + t * (32.0f - 15.0f * t));
+        db11 = t2 * (-12.0f + t * (28.0f - 15.0f * t));
+    }
+};
+
+template <>
+struct BasisD<3> {
+    __device__ __forceinline__ static void eval(float t, float &ds, float &db10, float &db11)
+    {
+        const float t3 = t * t * t;
+        ds = t3 * (140.0f + t * (-420.0f + t * (420.0f - 140.0f * t)));
+        db10 = 1.0f + t3 * (-80.0f + t * (225.0f + t * (-216.0f + 70.0f * t)));
+        db11 = t3 * (-60.0f + t * (195.0f + t * (-204.0f + 70.0f * t)));
+    }
+};
+
 // Monomial coefficients of the four 1D bases, rows: 1-s, s, b10, b11; column e = t^e.
 // Used by the per-cell coefficient kernel (K2) to expand the tensor form.
 template <int M>

@@ -11,6 +11,14 @@ __global__ __launch_bounds__(256) void k_fbm2d_general(const Fbm2dArgs a)
     fbm2d_general_tile<M, OutT, TH, MD>(a, blockIdx.x, lds4);
 }
 
+// The field and its analytic gradient, 64 x 64 tiles.
+template <int M, typename OutT, int MD>
+__global__ __launch_bounds__(256) void k_fbm2d_general_grad(const Fbm2dArgs a)
+{
+    extern __shared__ float4 lds4[];
+    fbm2d_general_tile<M, OutT, 64, MD, true>(a, blockIdx.x, lds4);
+}
+
 template <int M, typename OutT>
 __global__ __launch_bounds__(256) void k_fbm3d_general(const Fbm3dArgs a)
 {
@@ -65,6 +73,27 @@ hipError_t launch_fbm2d_general(const Fbm2dArgs &a, int smooth, bool f16, size_t
     case 32: return launch_2d_th<32>(a, smooth, f16, grid, lds, s);
     default: return launch_2d_th<64>(a, smooth, f16, grid, lds, s);
     }
+}
+
+template <typename OutT>
+static hipError_t launch_grad_t(const Fbm2dArgs &a, int smooth, dim3 grid, size_t lds, hipStream_t s)
+{
+    if (a.model == 1) return launch_dyn(k_fbm2d_general_grad<1, OutT, 1>, grid, lds, s, a);
+    if (a.model == 2) {
+        if (smooth == 1) return launch_dyn(k_fbm2d_general_grad<1, OutT, 2>, grid, lds, s, a);
+        if (smooth == 2) return launch_dyn(k_fbm2d_general_grad<2, OutT, 2>, grid, lds, s, a);
+        return launch_dyn(k_fbm2d_general_grad<3, OutT, 2>, grid, lds, s, a);
+    }
+    if (smooth == 1) return launch_dyn(k_fbm2d_general_grad<1, OutT, 0>, grid, lds, s, a);
+    if (smooth == 2) return launch_dyn(k_fbm2d_general_grad<2, OutT, 0>, grid, lds, s, a);
+    return launch_dyn(k_fbm2d_general_grad<3, OutT, 0>, grid, lds, s, a);
+}
+
+hipError_t launch_fbm2d_general_grad(const Fbm2dArgs &a, int smooth, bool f16, size_t lds, hipStream_t s)
+{
+    const int64_t tiles = (int64_t)a.tiles_x * ((a.ny + 63) / 64);
+    dim3 grid((unsigned)tiles);
+    return f16 ? launch_grad_t<__half>(a, smooth, grid, lds, s) : launch_grad_t<float>(a, smooth, grid, lds, s);
 }
 
 hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t lds, hipStream_t s)

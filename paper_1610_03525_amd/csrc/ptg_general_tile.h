@@ -67,15 +67,20 @@ struct LatCache {
 // so the row evaluation is the gradient model's with Q0 = Q1 = dQ.
 // MD = 2: heights and w-weighted gradients (tensor Hermite): gh holds the heights, gx / gy
 // the gradients times w, and a node row's value term gains h0j (1 - S(x)) + h1j S(x).
-template <int M, typename OutT, int TH, int MD = 0>
+// GRAD: also the analytic gradient dH/dX, dH/dY (to a.out_dx, a.out_dy): per octave the
+// cell's derivatives in its local coordinates times the octave frequency; the x-derivative
+// is the same row form with the x-bases differentiated, the y-derivative the row form with
+// the row bases differentiated (a second row table in LDS).
+template <int M, typename OutT, int TH, int MD = 0, bool GRAD = false>
 __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t bid, float4 *lds4,
                                                    const LatCache *lat = nullptr)
 {
     constexpr int T = kTile2;
     constexpr int RPT = TH / 4;
     float4 *rowt = lds4;
+    float4 *rowd = lds4 + TH;  // GRAD only: row-basis derivatives
     const int cap = a.capx * a.capy;
-    float *gx = reinterpret_cast<float *>(lds4 + TH);
+    float *gx = reinterpret_cast<float *>(lds4 + (GRAD ? 2 * TH : TH));
     float *gy = gx + cap;
     float *gh = gy + cap;  // MD = 2 only
     uint32_t *kx = reinterpret_cast<uint32_t *>(MD == 2 ? gh + cap : gy + cap);
@@ -90,9 +95,11 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
     const int64_t Xf = a.x0 + tx0, Xl = a.x0 + tx0 + w - 1;
     const int64_t Yf = a.y0 + ty0, Yl = a.y0 + ty0 + h - 1;
 
-    float acc[RPT];
+    float acc[RPT], accx[GRAD ? RPT : 1], accy[GRAD ? RPT : 1];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) acc[r] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < (GRAD ? RPT : 1); ++r) accx[r] = accy[r] = 0.0f;
 
     for (int o = 0; o < a.octaves; ++o) {
         const double f = a.freq[o];
@@ -113,6 +120,11 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
             float s, b10, b11;
             Basis<M>::eval(c.t, s, b10, b11);
             rowt[tid] = make_float4(__int_as_float((int)(c.cell - cyf)), s, b10, b11);
+            if (GRAD) {
+                float ds, db10, db11;
+                BasisD<M>::eval(c.t, ds, db10, db11);
+                rowd[tid] = make_float4(ds, db10, db11, 0.0f);
+            }
         }
         __syncthreads();
         if (lat) {  // gradients from the cached lattice blocks
@@ -170,12 +182,15 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
         }
         const Coord cc = coord_step(X, f);
         const int lcx = (int)(cc.cell - cxf);
-        float sx, b10x, b11x;
+        float sx, b10x, b11x, dsx = 0.0f, db10x = 0.0f, db11x = 0.0f;
         Basis<M>::eval(cc.t, sx, b10x, b11x);
+        if (GRAD) BasisD<M>::eval(cc.t, dsx, db10x, db11x);
+        const float fo = (float)f;  // d/dX = f d/dt
         __syncthreads();
 
         int prev = -1;
         float E0 = 0.0f, dE = 0.0f, Q0 = 0.0f, Q1 = 0.0f;
+        float E0x = 0.0f, dEx = 0.0f, Q0x = 0.0f, Q1x = 0.0f;  // the x-derivative's row form (GRAD)
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const float4 re = rowt[wave * RPT + r];
@@ -189,6 +204,12 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
                 dE = (h01 + sx * d1) - E0;
                 Q0 = (sx - cc.t) * (d1 - d0);
                 Q1 = Q0;
+                if (GRAD) {
+                    E0x = dsx * d0;
+                    dEx = dsx * (d1 - d0);
+                    Q0x = (dsx - 1.0f) * (d1 - d0);
+                    Q1x = Q0x;
+                }
             } else if (lcy != prev) {
                 prev = lcy;
                 const int q = lcy * nnx + lcx;
@@ -204,17 +225,41 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
                 dE = e1 - e0;
                 Q0 = fy00 + sx * (fy10 - fy00);
                 Q1 = fy01 + sx * (fy11 - fy01);
+                if (GRAD) {
+                    float e0x = fx00 * db10x + fx10 * db11x;
+                    float e1x = fx01 * db10x + fx11 * db11x;
+                    if (MD == 2) {
+                        e0x += dsx * (gh[q + 1] - gh[q]);
+                        e1x += dsx * (gh[q + nnx + 1] - gh[q + nnx]);
+                    }
+                    E0x = e0x;
+                    dEx = e1x - e0x;
+                    Q0x = dsx * (fy10 - fy00);
+                    Q1x = dsx * (fy11 - fy01);
+                }
             }
             acc[r] += E0 + dE * re.y + Q0 * re.z + Q1 * re.w;
+            if (GRAD) {
+                const float4 rd = rowd[wave * RPT + r];
+                accx[r] += fo * (E0x + dEx * re.y + Q0x * re.z + Q1x * re.w);
+                accy[r] += fo * (dE * rd.x + Q0 * rd.y + Q1 * rd.z);
+            }
         }
     }
 
     if (lane < w) {
         OutT *out = reinterpret_cast<OutT *>(a.out);
+        OutT *odx = reinterpret_cast<OutT *>(a.out_dx), *ody = reinterpret_cast<OutT *>(a.out_dy);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const int row = wave * RPT + r;
-            if (row < h) out[(ty0 + row) * a.pitch + tx0 + lane] = to_out<OutT>(acc[r]);
+            if (row >= h) continue;
+            const int64_t at = (ty0 + row) * a.pitch + tx0 + lane;
+            out[at] = to_out<OutT>(acc[r]);
+            if (GRAD) {
+                odx[at] = to_out<OutT>(accx[r]);
+                ody[at] = to_out<OutT>(accy[r]);
+            }
         }
     }
 }

@@ -66,5 +66,7 @@ int fbm3d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t
                 void *out, hipStream_t s);
 int fbm2d_mfma(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out, int64_t pitch,
                hipStream_t s);
+int fbm2d_grad(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out, void *out_dx,
+               void *out_dy, int64_t pitch, hipStream_t s);
 
 }  // namespace ptg

@@ -27,6 +27,7 @@ struct Fbm2dArgs {
     int32_t tile_h;      // rows per tile: 16, 32 or 64 (tile shape chosen by the tuner)
     int32_t model;       // PTG_MODEL_*
     float gw;            // gradient weight (height-and-gradient model)
+    void *out_dx, *out_dy;  // gradient outputs (ptg_fbm_2d_grad), same layout as out
 };
 
 struct Fbm3dArgs {
@@ -165,6 +166,7 @@ hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, int model, bo
                               hipStream_t s);
 int strip_wgs_per_cu(int smooth, int model, bool f16, int lo, int waves, size_t lds_bytes);  // resident WGs per CU
 hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
+hipError_t launch_fbm2d_general_grad(const Fbm2dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fbm3d_strip(const Fbm3dStripArgs &a, int smooth, bool f16, int grid, int waves, size_t lds_bytes,
                               hipStream_t s);
 int strip3_wgs_per_cu(int smooth, bool f16, int lo, int waves, size_t lds_bytes);

@@ -285,6 +285,19 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d launch");
 }
 
+// The field and its analytic gradient: the general kernel with 64-row tiles (any model,
+// any ladder) and a second row table for the row-basis derivatives.
+int fbm2d_grad(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out, void *out_dx,
+               void *out_dy, int64_t pitch, hipStream_t s)
+{
+    Fbm2dArgs a{};
+    const size_t lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, kTile2, &a) + (size_t)kTile2 * 16;
+    a.out_dx = out_dx;
+    a.out_dy = out_dy;
+    hipError_t e = launch_fbm2d_general_grad(a, p->smoothness, p->out_dtype == PTG_F16, lds, s);
+    return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d grad launch");
+}
+
 int strip3_args(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz,
                 void *out, Fbm3dStripArgs *ap)
 {
