@@ -55,6 +55,7 @@ constexpr int kMaxTilesPerItem = 16;      // sample tiles per work item, upper b
 constexpr int64_t kParkNs = 5000000;       // nothing in flight for 5 ms: park the kernel
 constexpr int64_t kSpinNs = 2000000;       // the scheduler spins until 2 ms after the last event
 constexpr int64_t kStarveNs = 50000000;    // after 50 ms a waiting request blocks later ones
+constexpr int64_t kQueryNs = 500000;       // stream queries of a running kernel: every 0.5 ms
 constexpr int kServeWaves = 4;             // waves of a serving workgroup (256 threads)
 constexpr int kMaxLatTbl = 2048;           // lattice-cache blocks one request may use (LDS table)
 constexpr int64_t kLatBlockBytes = (int64_t)kLatBlkFloats * 4;
@@ -490,6 +491,7 @@ struct ptg_server {
     std::vector<uint64_t> lat_waiting;
     uint32_t *lat_host = nullptr;
     int64_t idle_since = 0;   // when the in-flight set last became empty
+    int64_t last_query = 0;   // last hipStreamQuery of the running kernel
     int64_t last_event = 0;   // last submission or completion
     int64_t tiles_in_flight = 0;
     int64_t fake_busy_until = 0;
@@ -904,6 +906,11 @@ static void fail_inflight(ptg_server *s, int status)
 static void check_kernel(ptg_server *s)
 {
     if (!s->gpu || !s->kernel_running) return;
+    // the kernel only leaves after a park request (or on a fault): between those, query the
+    // stream at most every kQueryNs so the scheduler loop stays fast (a query is a runtime call)
+    const int64_t now = now_ns();
+    if (!s->park_requested && now - s->last_query < kQueryNs) return;
+    s->last_query = now;
     const hipError_t q = hipStreamQuery(s->stream);
     if (q == hipErrorNotReady) return;
     s->kernel_running = false;
