@@ -14,7 +14,12 @@
  *   - Cell polynomial: tensor polynomial of degree n = 2M+1 per axis (M = smoothness)
  *     whose value is 0 at each corner, whose gradient equals the corner's lattice
  *     gradient, and whose other mixed derivatives h^d, 0 <= d_k <= M, are 0.  M = 1 gives
- *     C1 cubic cells (D2M1N3 / D3M1N3 with zero twist), M = 2 C2 quintic cells.
+ *     C1 cubic cells (D2M1N3 / D3M1N3 with zero twist), M = 2 C2 quintic cells, M = 3
+ *     C3 septic cells.  Two more 2D cell models (ptg_params.model): the zero-gradient
+ *     model, whose nodes carry heights and zero gradients (Sec. 3.3), and the
+ *     height-and-gradient model, whose nodes carry both (Sec. 3.1; gradient weight w,
+ *     Sec. 4).
+ *   - Optional output: the analytic gradient of the field (ptg_fbm_2d_grad, Sec. 5.1).
  *   - Octave o = 0..N-1: frequency f_o = base_freq * lacunarity^o and amplitude
  *     a_o = persistence^o, each by repeated FP64 multiplication; no normalisation.
  *   - Sample at int64 world index X sits at X + 1/2: u = (X + 1/2) * f_o (FP64),
