@@ -166,6 +166,7 @@ def main():
         sys.exit(1)
 
     others = None if args.no_other_configs else other_configs(torch, ptg, stream)
+    stages = None if args.no_other_configs else stage_kernels(torch, ptg, stream)
     serving = run_serving(args.serve_requests) if args.serve_requests > 0 else None
 
     cpu = None
@@ -213,6 +214,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "other_configs": others,
+        "stage_kernels": stages,
         "serving": serving,
     }
     print(json.dumps(rec), flush=True)
@@ -318,6 +320,73 @@ def other_configs(torch, ptg, stream):
     ms = _time_launches(torch, stream, lambda: ptg.fbm_2d_raw(q, 0, 0, 256, 256, small.data_ptr(), 256, sh), 20)
     res["2d_256_4oct"] = {"workload": "2D fBm 256^2, 4 octaves, base lattice 8^2, C1, FP32", "ms": ms,
                           "octave_samples_s": 256 * 256 * 4 / (ms * 1e-3)}
+    return res
+
+
+def stage_kernels(torch, ptg, stream):
+    """The stand-alone stage kernels against the HBM roofline: a1 coordinate step, K1
+    lattice hash (2D keys + gradients, 2D node heights, 3D keys + second words +
+    gradients), K2 per-cell coefficients (2D, 3D; cubic and quintic).  Algorithmic bytes =
+    what the call must write plus what it must read (K2 reads the node gradients once)."""
+    res = {}
+    sh = stream.cuda_stream
+    lib = ptg.lib()
+
+    def rec(name, workload, kernel, call, wbytes, rbytes, n=10):
+        def fn():
+            rc = call()
+            if rc != 0:
+                raise RuntimeError(f"{name}: status {rc}: {lib.ptg_last_error().decode()}")
+        ms = _time_launches(torch, stream, fn, n)
+        gbs = (wbytes + rbytes) / (ms * 1e-3) / 1e9
+        res[name] = {"workload": workload, "kernel": kernel, "us": ms * 1e3, "bytes_written": wbytes,
+                     "bytes_read": rbytes, "GB_s": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+
+    n = 1 << 23
+    cells = torch.empty((8, n), dtype=torch.int64, device="cuda")
+    frac = torch.empty((8, n), dtype=torch.float32, device="cuda")
+    rec("coords_8M_8oct", "a1: 2^23 samples x 8 octaves (cell int64 + fraction FP32)", "k_coords",
+        lambda: lib.ptg_coords(2.0 ** -9, 2.0, 8, -(2 ** 40), n, cells.data_ptr(), frac.data_ptr(), sh),
+        8 * n * 12, 0)
+    del cells, frac
+    nx = ny = 8192
+    keys = torch.empty((ny, nx), dtype=torch.int32, device="cuda")
+    grad = torch.empty((2, ny, nx), dtype=torch.float32, device="cuda")
+    rec("lattice2d_8192x8192", "K1 2D: 8192^2 nodes, keys + unit gradients (12 B per node)", "k_lattice2d",
+        lambda: lib.ptg_lattice_2d(1, 3, -(2 ** 33), 2 ** 20, nx, ny, keys.data_ptr(), grad.data_ptr(), sh),
+        nx * ny * 12, 0)
+    rec("heights2d_8192x8192", "K1 2D node heights (zero-gradient model): 8192^2 nodes (4 B per node)",
+        "k_heights2d", lambda: lib.ptg_heights_2d(1, 3, 0, 0, nx, ny, grad.data_ptr(), sh), nx * ny * 4, 0)
+    del keys, grad
+    m = 256
+    keys = torch.empty((m, m, m), dtype=torch.int32, device="cuda")
+    sec = torch.empty((m, m, m), dtype=torch.int32, device="cuda")
+    grad = torch.empty((3, m, m, m), dtype=torch.float32, device="cuda")
+    rec("lattice3d_256cubed", "K1 3D: 256^3 nodes, keys + second words + unit gradients (20 B per node)",
+        "k_lattice3d",
+        lambda: lib.ptg_lattice_3d(1, 2, 0, -(2 ** 30), 7, m, m, m, keys.data_ptr(), sec.data_ptr(),
+                                   grad.data_ptr(), sh), m ** 3 * 20, 0)
+    del keys, sec, grad
+    for smooth, nn in ((1, 4097), (2, 2049)):
+        n1 = 2 * smooth + 2
+        grad = torch.empty((2, nn, nn), dtype=torch.float32, device="cuda")
+        lib.ptg_lattice_2d(1, 0, 0, 0, nn, nn, None, grad.data_ptr(), sh)
+        coeff = torch.empty(((nn - 1) ** 2 * n1 * n1,), dtype=torch.float32, device="cuda")
+        rec(f"cells2d_c{smooth}_{nn}", f"K2 2D C{smooth}: {nn}^2 nodes -> {(nn - 1)}^2 cells x {n1 * n1} "
+            "FP32 coefficients", f"k_cells2d<{smooth}>",
+            lambda: lib.ptg_cells_2d(smooth, grad.data_ptr(), nn, nn, ctypes.c_float(0.5), coeff.data_ptr(), sh),
+            (nn - 1) ** 2 * n1 * n1 * 4, nn * nn * 8)
+        del grad, coeff
+    for smooth, nn in ((1, 129), (2, 65)):
+        n1 = 2 * smooth + 2
+        grad = torch.empty((3, nn, nn, nn), dtype=torch.float32, device="cuda")
+        lib.ptg_lattice_3d(1, 0, 0, 0, 0, nn, nn, nn, None, None, grad.data_ptr(), sh)
+        coeff = torch.empty(((nn - 1) ** 3 * n1 ** 3,), dtype=torch.float32, device="cuda")
+        rec(f"cells3d_c{smooth}_{nn}", f"K2 3D C{smooth}: {nn}^3 nodes -> {(nn - 1)}^3 cells x {n1 ** 3} "
+            "FP32 coefficients", f"k_cells3d<{smooth}>",
+            lambda: lib.ptg_cells_3d(smooth, grad.data_ptr(), nn, nn, nn, ctypes.c_float(1.0), coeff.data_ptr(), sh),
+            (nn - 1) ** 3 * n1 ** 3 * 4, nn ** 3 * 12)
+        del grad, coeff
     return res
 
 

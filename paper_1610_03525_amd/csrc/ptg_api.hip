@@ -206,7 +206,7 @@ int ptg_lattice_2d(uint32_t seed, int32_t octave, int64_t ix0, int64_t iy0, int6
     if (nx < 0 || ny < 0) return fail(PTG_EINVAL, "negative node box");
     if (nx == 0 || ny == 0) return PTG_OK;
     if (!keys_dev && !grad_dev) return fail(PTG_EINVAL, "both outputs NULL");
-    if (nx > (1LL << 40) / ny || (nx * ny + 255) / 256 > 0x7FFFFFFFLL) return fail(PTG_EINVAL, "box too large");
+    if (nx > (1LL << 40) / ny || lattice_wgs(nx, ny) > 0x7FFFFFFFLL) return fail(PTG_EINVAL, "box too large");
     hipError_t e = launch_lattice2d(seed, octave, ix0, iy0, nx, ny, keys_dev, grad_dev,
                                     reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? PTG_OK : hip_fail(e, "lattice2d launch");
@@ -219,7 +219,7 @@ int ptg_heights_2d(uint32_t seed, int32_t octave, int64_t ix0, int64_t iy0, int6
     if (nx < 0 || ny < 0) return fail(PTG_EINVAL, "negative node box");
     if (nx == 0 || ny == 0) return PTG_OK;
     if (!heights_dev) return fail(PTG_EINVAL, "heights_dev is NULL");
-    if (nx > (1LL << 40) / ny || (nx * ny + 255) / 256 > 0x7FFFFFFFLL) return fail(PTG_EINVAL, "box too large");
+    if (nx > (1LL << 40) / ny || lattice_wgs(nx, ny) > 0x7FFFFFFFLL) return fail(PTG_EINVAL, "box too large");
     hipError_t e = launch_heights2d(seed, octave, ix0, iy0, nx, ny, heights_dev, reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? PTG_OK : hip_fail(e, "heights2d launch");
 }
@@ -231,7 +231,7 @@ int ptg_lattice_3d(uint32_t seed, int32_t octave, int64_t ix0, int64_t iy0, int6
     if (nx < 0 || ny < 0 || nz < 0) return fail(PTG_EINVAL, "negative node box");
     if (nx == 0 || ny == 0 || nz == 0) return PTG_OK;
     if (!keys_dev && !second_dev && !grad_dev) return fail(PTG_EINVAL, "all outputs NULL");
-    if (nx > (1LL << 40) / ny || nx * ny > (1LL << 40) / nz || (nx * ny * nz + 255) / 256 > 0x7FFFFFFFLL)
+    if (nx > (1LL << 40) / ny || nx * ny > (1LL << 40) / nz || lattice_wgs(nx, ny * nz) > 0x7FFFFFFFLL)
         return fail(PTG_EINVAL, "box too large");
     hipError_t e = launch_lattice3d(seed, octave, ix0, iy0, iz0, nx, ny, nz, keys_dev, second_dev, grad_dev,
                                     reinterpret_cast<hipStream_t>(stream));
@@ -244,7 +244,8 @@ int ptg_cells_2d(int32_t smoothness, const float *grad_dev, int64_t nnx, int64_t
     if (smoothness != 1 && smoothness != 2) return fail(PTG_EINVAL, "smoothness must be 1 or 2");
     if (nnx < 2 || nny < 2) return fail(PTG_EINVAL, "a node box needs at least 2 x 2 nodes");
     if (!grad_dev || !coeff_dev) return fail(PTG_EINVAL, "NULL buffer");
-    if ((nnx + 14) / 16 > 0x7FFFFFFFLL || (nny + 14) / 16 > 65535) return fail(PTG_EINVAL, "box too large");
+    if (nnx > (1LL << 40) / nny || cells2_wgs(nnx - 1, nny - 1) > 0x7FFFFFFFLL)
+        return fail(PTG_EINVAL, "box too large");
     if (!std::isfinite(amplitude)) return fail(PTG_EINVAL, "amplitude not finite");
     hipError_t e = launch_cells2d(smoothness, grad_dev, nnx, nny, amplitude, coeff_dev,
                                   reinterpret_cast<hipStream_t>(stream));
@@ -257,7 +258,7 @@ int ptg_cells_3d(int32_t smoothness, const float *grad_dev, int64_t nnx, int64_t
     if (smoothness != 1 && smoothness != 2) return fail(PTG_EINVAL, "smoothness must be 1 or 2");
     if (nnx < 2 || nny < 2 || nnz < 2) return fail(PTG_EINVAL, "a node box needs at least 2 nodes per axis");
     if (!grad_dev || !coeff_dev) return fail(PTG_EINVAL, "NULL buffer");
-    if ((nnx + 6) / 8 > 0x7FFFFFFFLL || (nny + 6) / 8 > 65535 || (nnz + 2) / 4 > 65535)
+    if (nnx > (1LL << 40) / nny || nnx * nny > (1LL << 40) / nnz || cells3_wgs(nnx - 1, nny - 1, nnz - 1) > 0x7FFFFFFFLL)
         return fail(PTG_EINVAL, "box too large");
     if (!std::isfinite(amplitude)) return fail(PTG_EINVAL, "amplitude not finite");
     hipError_t e = launch_cells3d(smoothness, grad_dev, nnx, nny, nnz, amplitude, coeff_dev,

@@ -171,6 +171,24 @@ hipError_t launch_fbm3d_strip(const Fbm3dStripArgs &a, int smooth, bool f16, int
                               hipStream_t s);
 int strip3_wgs_per_cu(int smooth, bool f16, int lo, int waves, size_t lds_bytes);
 
+// Stand-alone stage kernels (ptg_stages.hip): one-dimensional grids of these workgroups;
+// the entry points reject boxes whose workgroup count exceeds 2^31 - 1.
+constexpr int kLatRows = 16;  // K1: a workgroup covers 256 node columns x kLatRows node rows
+constexpr int kCell2W = 64, kCell2H = 4;  // K2 2D: 64 x 4 cells per workgroup (a wave per row)
+constexpr int kCell3W = 64;               // K2 3D: 64 x 2 x 2 cells per workgroup
+__host__ __device__ inline int64_t lattice_wgs(int64_t nx, int64_t rows)
+{
+    return ((nx + 255) / 256) * ((rows + kLatRows - 1) / kLatRows);
+}
+__host__ __device__ inline int64_t cells2_wgs(int64_t ncx, int64_t ncy)
+{
+    return ((ncx + kCell2W - 1) / kCell2W) * ((ncy + kCell2H - 1) / kCell2H);
+}
+__host__ __device__ inline int64_t cells3_wgs(int64_t ncx, int64_t ncy, int64_t ncz)
+{
+    return ((ncx + kCell3W - 1) / kCell3W) * ((ncy + 1) / 2) * ((ncz + 1) / 2);
+}
+
 hipError_t launch_coords(double f0, double lac, int octaves, int64_t x0, int64_t n, int64_t *cells, float *frac,
                          hipStream_t s);
 hipError_t launch_lattice2d(uint32_t seed, int octave, int64_t ix0, int64_t iy0, int64_t nx, int64_t ny,

@@ -141,6 +141,103 @@ def test_cells3d_against_oracle(smooth):
         assert np.max(np.abs(c[ck, cj, ci] - ref)) <= tol
 
 
+# Stage kernels over several workgroups: K1 covers 256 node columns x 16 node rows per
+# workgroup (3D rows wrap from one j to the next k inside a workgroup), K2 64 x 4 cells
+# (2D) and 64 x 2 x 2 cells (3D); ragged last workgroups on every axis, and K2 output
+# buffers that are and are not 16-byte aligned (vector and scalar stores).
+def test_lattice2d_multi_workgroup():
+    seed, octave, ix0, iy0, nx, ny = 77, 4, -(2 ** 35) - 130, 2 ** 21 + 3, 300, 37
+    keys = torch.empty((ny, nx), dtype=torch.int32, device=DEV)
+    grad = torch.empty((2, ny, nx), dtype=torch.float32, device=DEV)
+    ptg.lattice_2d(seed, octave, ix0, iy0, keys, grad)
+    h = torch.empty((ny, nx), dtype=torch.float32, device=DEV)
+    ptg.heights_2d(seed, octave, ix0, iy0, h)
+    _sync()
+    ref = O.keys2_box(ix0, iy0, nx, ny, octave, seed)
+    np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint32), ref)
+    g, hh = grad.cpu().numpy(), h.cpu().numpy()
+    worst = 0.0
+    for j in range(0, ny, 3):
+        for i in range(nx):
+            gr = O.grad2(int(ref[j, i]))
+            worst = max(worst, abs(g[0, j, i] - gr[0]), abs(g[1, j, i] - gr[1]))
+            assert hh[j, i] == np.float32(O.height2(int(ref[j, i])))
+    assert worst <= 2 ** -20, worst
+
+
+def test_lattice3d_rows_wrap_inside_workgroup():
+    seed, octave, ix0, iy0, iz0, nx, ny, nz = 0xC0FFEE, 3, 2 ** 33 - 100, -7, 2 ** 30, 260, 5, 7
+    keys = torch.empty((nz, ny, nx), dtype=torch.int32, device=DEV)
+    sec = torch.empty((nz, ny, nx), dtype=torch.int32, device=DEV)
+    grad = torch.empty((3, nz, ny, nx), dtype=torch.float32, device=DEV)
+    ptg.lattice_3d(seed, octave, ix0, iy0, iz0, keys, sec, grad)
+    _sync()
+    ref = O.keys3_box(ix0, iy0, iz0, nx, ny, nz, octave, seed)
+    np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint32), ref)
+    s, g = sec.cpu().numpy().view(np.uint32), grad.cpu().numpy()
+    worst = 0.0
+    for q in np.ndindex(nz, ny, nx):
+        if q[2] % 7 and q[2] < nx - 3:
+            continue  # every 7th column and the last three
+        assert s[q] == O.key3_second(int(ref[q]))
+        gr = O.grad3(int(ref[q]))
+        worst = max(worst, max(abs(g[(a,) + q] - gr[a]) for a in range(3)))
+    assert worst <= 2 ** -20, worst
+
+
+def _unaligned(n, dtype=torch.float32):
+    """A contiguous device buffer of n elements whose address is 4 bytes past 16-byte alignment."""
+    base = torch.empty(n + 4, dtype=dtype, device=DEV)
+    assert base.data_ptr() % 16 == 0
+    return base[1:1 + n]
+
+
+@pytest.mark.parametrize("smooth", [1, 2])
+@pytest.mark.parametrize("aligned", [True, False])
+def test_cells2d_multi_workgroup(smooth, aligned):
+    seed, octave, ix0, iy0, nnx, nny = 11, 5, 2 ** 40 - 70, -(2 ** 20), 140, 7
+    amp = 0.125
+    grad = torch.empty((2, nny, nnx), dtype=torch.float32, device=DEV)
+    ptg.lattice_2d(seed, octave, ix0, iy0, None, grad)
+    n1 = 2 * smooth + 2
+    shape = (nny - 1, nnx - 1, n1, n1)
+    n = int(np.prod(shape))
+    coeff = (torch.empty(n, dtype=torch.float32, device=DEV) if aligned else _unaligned(n)).view(shape)
+    assert (coeff.data_ptr() % 16 == 0) == aligned
+    ptg.cells_2d(smooth, grad, amp, coeff)
+    _sync()
+    c = coeff.cpu().numpy()
+    tol = 2e-6 * amp * (16 if smooth == 1 else 200)
+    for cj in range(nny - 1):
+        for ci in range(nnx - 1):
+            g = np.array([O.grad2(O.key2(ix0 + ci + dx, iy0 + cj + dy, octave, seed))
+                          for dy in (0, 1) for dx in (0, 1)])
+            assert np.max(np.abs(c[cj, ci] - amp * O.coeffs_2d(smooth, g))) <= tol, (cj, ci)
+
+
+@pytest.mark.parametrize("smooth", [1, 2])
+@pytest.mark.parametrize("aligned", [True, False])
+def test_cells3d_multi_workgroup(smooth, aligned):
+    seed, octave, ix0, iy0, iz0, nnx, nny, nnz = 13, 2, -65, 2 ** 31, -(2 ** 33), 67, 4, 4
+    amp = 0.5
+    grad = torch.empty((3, nnz, nny, nnx), dtype=torch.float32, device=DEV)
+    ptg.lattice_3d(seed, octave, ix0, iy0, iz0, None, None, grad)
+    n1 = 2 * smooth + 2
+    shape = (nnz - 1, nny - 1, nnx - 1, n1, n1, n1)
+    n = int(np.prod(shape))
+    coeff = (torch.empty(n, dtype=torch.float32, device=DEV) if aligned else _unaligned(n)).view(shape)
+    ptg.cells_3d(smooth, grad, amp, coeff)
+    _sync()
+    c = coeff.cpu().numpy()
+    tol = 2e-6 * amp * (64 if smooth == 1 else 3000)
+    for ck in range(nnz - 1):
+        for cj in range(nny - 1):
+            for ci in list(range(0, nnx - 1, 5)) + [62, 63, 64, 65]:
+                g = np.array([O.grad3(O.key3(ix0 + ci + dx, iy0 + cj + dy, iz0 + ck + dz, octave, seed))
+                              for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)])
+                assert np.max(np.abs(c[ck, cj, ci] - amp * O.coeffs_3d(smooth, g))) <= tol, (ck, cj, ci)
+
+
 # ---------------------------------------------------------------------------------
 # a1-a5 fields (K3)
 # ---------------------------------------------------------------------------------
