@@ -39,6 +39,12 @@ __device__ __forceinline__ __half to_out<__half>(float v)
     return __float2half_rn(v);
 }
 
+// Materialise v here, in program order.  Without it the compiler sinks every row's
+// accumulate to the end of the octave and keeps all rows' column forms live across the
+// row loop (2D tile of 64 rows: 174 VGPRs instead of 54, two waves per SIMD instead of
+// eight).  The statement emits no instruction.
+__device__ __forceinline__ void keep_here(float &v) { asm volatile("" : "+v"(v)); }
+
 // Device-resident lattice cache (serving): the unit gradients of one octave's nodes in
 // blocks of kLatBlk x kLatBlk nodes, SoA per block (x components at [(iy & 31) * 32 +
 // (ix & 31)], y components kLatBlk^2 floats further), anywhere in the arena.  A request
@@ -239,10 +245,13 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
                 }
             }
             acc[r] += E0 + dE * re.y + Q0 * re.z + Q1 * re.w;
+            keep_here(acc[r]);
             if (GRAD) {
                 const float4 rd = rowd[wave * RPT + r];
                 accx[r] += fo * (E0x + dEx * re.y + Q0x * re.z + Q1x * re.w);
                 accy[r] += fo * (dE * rd.x + Q0 * rd.y + Q1 * rd.z);
+                keep_here(accx[r]);
+                keep_here(accy[r]);
             }
         }
     }
@@ -386,6 +395,7 @@ __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t b
                     Q1 = Bq[1];
                 }
                 acc[zz * TY + yy] += E0 + dE * ye.y + Q0 * ye.z + Q1 * ye.w;
+                keep_here(acc[zz * TY + yy]);
             }
         }
     }
