@@ -211,9 +211,12 @@ PTG_API int ptg_cells_3d(int32_t smoothness, const float *grad_dev, int64_t nnx,
  * Each dense-field call runs one kernel class; some classes have a free launch shape that
  * changes neither the arithmetic nor the result (every sample is computed by the same
  * operations whatever the shape):
- *   PTG_TUNE_GENERAL_2D  general 2D kernel: tile height in rows, 16, 32 or 64 (tiles are
- *                        64 wide); a shorter tile hashes more duplicated footprint nodes
- *                        but gives small fields more workgroups;
+ *   PTG_TUNE_GENERAL_2D  general 2D kernel: tile height in rows, 16, 32, 64 or 128 (tiles
+ *                        are 64 wide; served tiles take at most 64); a shorter tile hashes
+ *                        more duplicated footprint nodes and repeats each octave's set-up
+ *                        more often, but gives small fields more workgroups (untuned: 128
+ *                        for fields of 1024 rows or more, except the height-and-gradient
+ *                        model, else 64);
  *   PTG_TUNE_STRIP_2D    dyadic 2D kernel (64 x 64 strips, one per wave): waves per
  *                        workgroup, 1, 2 or 4;
  *   PTG_TUNE_STRIP_3D    dyadic 3D kernel (64 x 8 x 4 blocks, one per wave): waves per

@@ -71,6 +71,7 @@ hipError_t launch_fbm2d_general(const Fbm2dArgs &a, int smooth, bool f16, size_t
     switch (a.tile_h) {
     case 16: return launch_2d_th<16>(a, smooth, f16, grid, lds, s);
     case 32: return launch_2d_th<32>(a, smooth, f16, grid, lds, s);
+    case 128: return launch_2d_th<128>(a, smooth, f16, grid, lds, s);
     default: return launch_2d_th<64>(a, smooth, f16, grid, lds, s);
     }
 }

@@ -43,7 +43,7 @@ struct TuneKey {
     bool operator<(const TuneKey &o) const;
 };
 // The shape a launch of class k uses: the value forced by the tuner on this thread, else
-// the recorded choice, else dflt.  Also remembers k as this thread's last class.
+// the recorded choice, else dflt.  Also remembers k and dflt as this thread's last class.
 int tune_pick(const TuneKey &k, int dflt);
 // Dry run on this thread: the drivers choose their kernel and shape, then return PTG_OK
 // without launching (tune queries); and the value the tuner forces (0 = none).
@@ -55,6 +55,7 @@ struct TuneScope {
     bool picked() const;  // a driver chose its class inside the scope
     TuneKey key() const;  // the class it chose
     int value() const;    // and the shape it used
+    int dflt() const;     // and the shape it uses untuned
 };
 int size_class(int64_t samples);
 int ladder_class(const double *freq, int octaves);

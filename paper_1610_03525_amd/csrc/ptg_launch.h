@@ -9,7 +9,7 @@ namespace ptg {
 constexpr int kMaxOctaves = 16;
 
 // Dense 2D field, general (any-parameter) K3: 64 x 64 sample tiles, 256 threads.
-constexpr int kTile2 = 64;  // tile width, and the largest tile height
+constexpr int kTile2 = 64;  // tile width, and the default (and the serving kernel's largest) tile height
 // Dense 3D field, general K3: 64 x 8 x 8 sample tiles, 256 threads.
 constexpr int kTile3X = 64;
 constexpr int kTile3Y = 8;

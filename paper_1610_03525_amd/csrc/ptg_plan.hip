@@ -276,9 +276,13 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     double freq[kMaxOctaves];
     float amp[kMaxOctaves];
     octave_tables(p, freq, amp);
+    // untuned: 128-row tiles for tall fields (each octave's set-up per tile is amortised over
+    // twice the rows), except for the height-and-gradient model, whose larger per-tile LDS
+    // block then limits the workgroups per compute unit
+    const int dflt = (ny >= 1024 && p->model != PTG_MODEL_HEIGHT_GRADIENT) ? 2 * kTile2 : kTile2;
     const int tile_h = tune_pick(TuneKey{PTG_TUNE_GENERAL_2D, p->smoothness + 2 * p->model, p->out_dtype == PTG_F16,
                                          size_class(nx * ny), ladder_class(freq, p->octaves)},
-                                 kTile2);
+                                 dflt);
     const size_t lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, tile_h, &a);
     if (tune_dry()) return PTG_OK;
     hipError_t e = launch_fbm2d_general(a, p->smoothness, p->out_dtype == PTG_F16, lds, s);

@@ -1161,7 +1161,11 @@ int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out)
                     free_server(s);
                     return rc;
                 }
-                s->tile_h2[m - 1] = r.value;
+                // the serving kernel takes tiles of at most kTile2 rows: the fastest of those
+                int best = -1;
+                for (int i = 0; i < r.n; ++i)
+                    if (r.candidates[i] <= kTile2 && (best < 0 || r.us[i] < r.us[best])) best = i;
+                s->tile_h2[m - 1] = best >= 0 ? r.candidates[best] : kTile2;
             }
         }
     } else {

@@ -30,7 +30,7 @@ std::map<TuneKey, int> g_table;
 
 struct ThreadTune {
     bool active = false, dry = false, picked = false;
-    int force = 0, value = 0;
+    int force = 0, value = 0, dflt = 0;
     TuneKey key{};
 };
 thread_local ThreadTune t_tune;
@@ -39,24 +39,14 @@ int candidates(int kernel, int *out)
 {
     switch (kernel) {
     case PTG_TUNE_GENERAL_2D:
-        out[0] = 16, out[1] = 32, out[2] = 64;
-        return 3;
+        out[0] = 16, out[1] = 32, out[2] = 64, out[3] = 128;
+        return 4;
     case PTG_TUNE_STRIP_2D:
     case PTG_TUNE_STRIP_3D:
         out[0] = 1, out[1] = 2, out[2] = 4;
         return 3;
     default:
         return 0;
-    }
-}
-
-int default_value(int kernel)
-{
-    switch (kernel) {
-    case PTG_TUNE_GENERAL_2D: return kTile2;
-    case PTG_TUNE_STRIP_2D: return kStripWavesPerWg;
-    case PTG_TUNE_STRIP_3D: return 4;
-    default: return 0;
     }
 }
 
@@ -85,6 +75,7 @@ int tune_pick(const TuneKey &k, int dflt)
         t_tune.picked = true;
         t_tune.key = k;
         t_tune.value = v;
+        t_tune.dflt = dflt;
     }
     return v;
 }
@@ -102,6 +93,7 @@ TuneScope::~TuneScope() { t_tune = ThreadTune{}; }
 bool TuneScope::picked() const { return t_tune.picked; }
 TuneKey TuneScope::key() const { return t_tune.key; }
 int TuneScope::value() const { return t_tune.value; }
+int TuneScope::dflt() const { return t_tune.dflt; }
 
 int size_class(int64_t samples)
 {
@@ -138,8 +130,8 @@ struct Call {
     }
 };
 
-// The class and current shape of a call (no launch).
-int query(const Call &c, int32_t *kernel, int32_t *value)
+// The class, current shape and untuned shape of a call (no launch).
+int query(const Call &c, int32_t *kernel, int32_t *value, int32_t *dflt = nullptr)
 {
     if (!kernel || !value) return fail(PTG_EINVAL, "NULL output pointer");
     if (c.nx < 1 || c.ny < 1 || c.nz < 1) return fail(PTG_EINVAL, "extents must be >= 1");
@@ -152,6 +144,7 @@ int query(const Call &c, int32_t *kernel, int32_t *value)
     if (!sc.picked()) return fail(PTG_EINVAL, "no kernel class chosen");
     *kernel = sc.key().kernel;
     *value = sc.value();
+    if (dflt) *dflt = sc.dflt();
     return PTG_OK;
 }
 
@@ -176,12 +169,12 @@ int tune(const Call &c, int32_t reps, ptg_tune_result *res)
     if (!res) return fail(PTG_EINVAL, "res is NULL");
     if (!c.out) return fail(PTG_EINVAL, "out_dev is NULL");
     if (reps <= 0) reps = 5;
-    int32_t kernel = 0, current = 0;
-    int rc = query(c, &kernel, &current);
+    int32_t kernel = 0, current = 0, dflt = 0;
+    int rc = query(c, &kernel, &current, &dflt);
     if (rc != PTG_OK) return rc;
     *res = ptg_tune_result{};
     res->kernel = kernel;
-    res->default_value = default_value(kernel);
+    res->default_value = dflt;
     int cand[PTG_TUNE_MAX_CANDIDATES];
     int n = candidates(kernel, cand);
     if (n == 0) {  // nothing to tune: time the one shape

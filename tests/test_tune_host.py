@@ -30,11 +30,11 @@ def test_query_reports_the_kernel_class(shape, kw, expect):
 
 def test_set_query_reset_roundtrip():
     kw = dict(octaves=4, base_freq=0.013)
-    for v in (16, 32, 64):
+    for v in (16, 32, 64, 128):
         ptg.tune_set((256, 300), v, **kw)
         assert ptg.tune_query((256, 300), **kw) == ("general_2d", v)
     # another class (size class of 2^20 samples) is untouched
-    assert ptg.tune_query((1024, 1024), **kw) == ("general_2d", 64)
+    assert ptg.tune_query((1024, 1024), **kw) == ("general_2d", 128)  # untuned: 128 rows for tall fields
     # C2 is a class of its own
     assert ptg.tune_query((256, 300), smoothness=2, **kw) == ("general_2d", 64)
     ptg.tune_set((8192, 8192), 2, octaves=8, base_freq=16 / 8192)
