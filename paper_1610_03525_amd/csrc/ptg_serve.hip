@@ -971,16 +971,14 @@ static void service(ptg_server *s)
         maybe_park(s, now);
         if (s->stopping && s->inflight.empty() && s->lat_waiting.empty() && !s->kernel_running) break;
         // spin while requests are in flight or soon after the last event (completion is
-        // seen within a poll, not a sleep); then sleep briefly while a kernel may still
-        // need parking, and block when there is nothing to do
+        // seen within a poll, not a sleep); then wait briefly while a kernel may still need
+        // parking (a submit wakes the wait at once), and block when there is nothing to do
         if (!s->inflight.empty() || !s->lat_waiting.empty() || now - s->last_event < kSpinNs) {
             lk.unlock();
             std::this_thread::yield();
             lk.lock();
         } else if (s->kernel_running) {
-            lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(200));
-            lk.lock();
+            s->cv_work.wait_for(lk, std::chrono::microseconds(200));
         } else {
             s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
         }
