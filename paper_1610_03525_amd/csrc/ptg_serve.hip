@@ -54,6 +54,7 @@ constexpr size_t kServeLds = 64 * 1024;    // dynamic LDS of a serving workgroup
 constexpr int kMaxTilesPerItem = 16;      // sample tiles per work item, upper bound
 constexpr int64_t kParkNs = 5000000;       // nothing in flight for 5 ms: park the kernel
 constexpr int64_t kSpinNs = 2000000;       // the scheduler spins until 2 ms after the last event
+constexpr int kAdmitSkips = 32;            // pending requests passed over per admission pass, at most
 constexpr int64_t kStarveNs = 50000000;    // after 50 ms a waiting request blocks later ones
 constexpr int64_t kQueryNs = 500000;       // stream queries of a running kernel: every 0.5 ms
 constexpr int kServeWaves = 4;             // waves of a serving workgroup (256 threads)
@@ -494,6 +495,7 @@ struct ptg_server {
     int64_t last_query = 0;   // last hipStreamQuery of the running kernel
     int64_t last_event = 0;   // last submission or completion
     int64_t tiles_in_flight = 0;
+    int64_t tiles_pending = 0;  // tiles of the requests waiting for admission
     int64_t fake_busy_until = 0;
     ptg_server_stats st{};
     std::thread th;
@@ -503,16 +505,17 @@ struct ptg_server {
 namespace ptg {
 
 // Tiles per work item: the configured count; else sized to the load.  With little in
-// flight a request is cut into small items that spread over many workgroups (latency);
-// with a backlog items grow to kMaxTilesPerItem tiles (fewer claims and completions per
-// tile: throughput).  Never more items than the ring holds (validation guarantees that
-// kMaxTilesPerItem tiles per item fit).
+// flight or waiting a request is cut into small items that spread over many workgroups
+// (latency); with a backlog (in flight or still pending) items grow to kMaxTilesPerItem
+// tiles (fewer claims and completions per tile: throughput).  Never more items than the
+// ring holds (validation guarantees that kMaxTilesPerItem tiles per item fit).
 static int64_t tiles_per_item(const ptg_server *s, int64_t ntiles)
 {
     int64_t per = s->cfg.tiles_per_item;
     if (per <= 0) {
         const int64_t wg = std::max(s->workgroups, 1);
-        per = std::max<int64_t>(1, std::min<int64_t>(kMaxTilesPerItem, (s->tiles_in_flight + ntiles) / (2 * wg)));
+        const int64_t load = s->tiles_in_flight + s->tiles_pending + ntiles;
+        per = std::max<int64_t>(1, std::min<int64_t>(kMaxTilesPerItem, load / (2 * wg)));
     }
     const int64_t need = (ntiles + s->cfg.max_items - 1) / s->cfg.max_items;
     return std::max(per, need);
@@ -824,6 +827,10 @@ static void lat_advance(ptg_server *s)
 static void admit(ptg_server *s)
 {
     const int64_t now = now_ns();
+    // requests that do not fit let later ones pass, but one pass looks at a bounded number
+    // of them: a long backlog would otherwise keep the scheduler (and the lock that
+    // clients need to wait and release) busy scanning it
+    int skipped = 0;
     for (auto it = s->pending.begin(); it != s->pending.end();) {
         Request &r = s->by_ticket[*it];
         // a strip is one wave's work: items of a strip request hold whole workgroups' worth
@@ -837,6 +844,7 @@ static void admit(ptg_server *s)
         const int64_t off = arena_alloc(s, round256(r.bytes));
         if (off < 0) {
             if (now - r.t_submit > kStarveNs) break;  // it waited long enough: nobody passes it
+            if (++skipped >= kAdmitSkips) break;
             ++it;
             continue;
         }
@@ -850,10 +858,12 @@ static void admit(ptg_server *s)
             s->arena->release(r.arena_off, round256(r.bytes));
             r.arena_off = -1;
             if (now - r.t_submit > kStarveNs) break;
+            if (++skipped >= kAdmitSkips) break;
             ++it;
             continue;
         }
         it = s->pending.erase(it);
+        s->tiles_pending -= r.ntiles;
         r.t_admit = now_ns();
         s->st.admitted++;
         if (r.lat) {
@@ -971,14 +981,18 @@ static void service(ptg_server *s)
         maybe_park(s, now);
         if (s->stopping && s->inflight.empty() && s->lat_waiting.empty() && !s->kernel_running) break;
         // spin while requests are in flight or soon after the last event (completion is
-        // seen within a poll, not a sleep); then wait briefly while a kernel may still need
-        // parking (a submit wakes the wait at once), and block when there is nothing to do
+        // seen within a poll, not a sleep); then sleep briefly while a kernel may still
+        // need parking (releases that arrive meanwhile free their bytes together, and the
+        // requests waiting for them are admitted together rather than one by one as each
+        // release comes in), and block when there is nothing to do
         if (!s->inflight.empty() || !s->lat_waiting.empty() || now - s->last_event < kSpinNs) {
             lk.unlock();
             std::this_thread::yield();
             lk.lock();
         } else if (s->kernel_running) {
-            s->cv_work.wait_for(lk, std::chrono::microseconds(200));
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(200));
+            lk.lock();
         } else {
             s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
         }
@@ -1202,6 +1216,7 @@ int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n, uint64_
         r.lat = lat[i];
         r.t_submit = t;
         s->pending.push_back(ticket);
+        s->tiles_pending += r.ntiles;
         tickets_out[i] = ticket;
         s->st.submitted++;
     }
@@ -1277,6 +1292,7 @@ int ptg_server_destroy(ptg_server *s)
         s->stopping = true;
         for (uint64_t t : s->pending) complete(s, t, PTG_ESHUTDOWN);
         s->pending.clear();
+        s->tiles_pending = 0;
         s->cv_work.notify_all();
     }
     s->th.join();  // in-flight requests run out, then the kernel is parked and has left
