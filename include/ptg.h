@@ -298,8 +298,8 @@ typedef struct ptg_server_cfg {
     int32_t executor;         /* PTG_EXEC_GPU or PTG_EXEC_HOST                              */
     int64_t fake_tile_ns;     /* PTG_EXEC_HOST only: simulated time per tile                */
     int32_t tiles_per_item;   /* sample tiles per work item, 1..16 (strip requests: 4 strips */
-                              /* or 3D blocks per tile, one per wave); 0 = from each        */
-                              /* request's size                                              */
+                              /* or 3D blocks per tile, one per wave); 0 = from the load:   */
+                              /* the tiles in flight and pending plus the request's own     */
                               /* (enough items for every workgroup, at most 16 tiles)       */
     int32_t autotune;         /* 1: at creation (PTG_EXEC_GPU) time the 2D tile heights on  */
                               /* a 512 x 512, 8-octave field per cell order (ptg_tune_2d,   */
