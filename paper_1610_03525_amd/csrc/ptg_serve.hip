@@ -54,7 +54,6 @@ constexpr size_t kServeLds = 64 * 1024;    // dynamic LDS of a serving workgroup
 constexpr int kMaxTilesPerItem = 16;      // sample tiles per work item, upper bound
 constexpr int64_t kParkNs = 5000000;       // nothing in flight for 5 ms: park the kernel
 constexpr int64_t kSpinNs = 2000000;       // the scheduler spins until 2 ms after the last event
-constexpr int kAdmitSkips = 32;            // pending requests passed over per admission pass, at most
 constexpr int64_t kStarveNs = 50000000;    // after 50 ms a waiting request blocks later ones
 constexpr int64_t kQueryNs = 500000;       // stream queries of a running kernel: every 0.5 ms
 constexpr int kServeWaves = 4;             // waves of a serving workgroup (256 threads)
@@ -827,10 +826,6 @@ static void lat_advance(ptg_server *s)
 static void admit(ptg_server *s)
 {
     const int64_t now = now_ns();
-    // requests that do not fit let later ones pass, but one pass looks at a bounded number
-    // of them: a long backlog would otherwise keep the scheduler (and the lock that
-    // clients need to wait and release) busy scanning it
-    int skipped = 0;
     for (auto it = s->pending.begin(); it != s->pending.end();) {
         Request &r = s->by_ticket[*it];
         // a strip is one wave's work: items of a strip request hold whole workgroups' worth
@@ -844,7 +839,6 @@ static void admit(ptg_server *s)
         const int64_t off = arena_alloc(s, round256(r.bytes));
         if (off < 0) {
             if (now - r.t_submit > kStarveNs) break;  // it waited long enough: nobody passes it
-            if (++skipped >= kAdmitSkips) break;
             ++it;
             continue;
         }
@@ -858,7 +852,6 @@ static void admit(ptg_server *s)
             s->arena->release(r.arena_off, round256(r.bytes));
             r.arena_off = -1;
             if (now - r.t_submit > kStarveNs) break;
-            if (++skipped >= kAdmitSkips) break;
             ++it;
             continue;
         }
