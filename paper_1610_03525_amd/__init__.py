@@ -282,56 +282,100 @@ def fbm_3d(out, *, x0=0, y0=0, z0=0, stream=None, **kw):
 
 
 # ---- stages -------------------------------------------------------------------------
+# The stage entry points take no buffer sizes, so every wrapper checks each tensor's dtype,
+# exact shape and contiguity against the sizes it passes before anything is launched.
+
+def _need(t, name, shape, dtype):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: expected dtype {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(int(v) for v in shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    return t
+
+
+def _ptrs(*ts):
+    """Device pointers of already checked tensors (None stays None)."""
+    return [None if t is None else _dev_ptr(t) for t in ts]
+
 
 def coords(base_freq, lacunarity, octaves, x0, cells_out, frac_out, stream=None):
     """a1: cells_out (octaves, n) int64 and frac_out (octaves, n) float32 device tensors."""
     import torch
+    if cells_out.dim() != 2:
+        raise ValueError("cells_out must be (octaves, n)")
     n = cells_out.shape[1]
-    _check(lib().ptg_coords(base_freq, lacunarity, octaves, x0, n, _dev_ptr(cells_out, torch.int64),
-                            _dev_ptr(frac_out, torch.float32), _stream(stream)))
+    cp, fp = _ptrs(_need(cells_out, "cells_out", (octaves, n), torch.int64),
+                   _need(frac_out, "frac_out", (octaves, n), torch.float32))
+    _check(lib().ptg_coords(base_freq, lacunarity, octaves, x0, n, cp, fp, _stream(stream)))
 
 
 def lattice_2d(seed, octave, ix0, iy0, keys_out=None, grad_out=None, stream=None):
     """K1: keys_out (ny, nx) int32 tensor (uint32 bits) and/or grad_out (2, ny, nx) float32."""
     import torch
-    ref = keys_out if keys_out is not None else grad_out[0]
-    ny, nx = ref.shape
-    kp = _dev_ptr(keys_out, torch.int32) if keys_out is not None else None
-    gp = _dev_ptr(grad_out, torch.float32) if grad_out is not None else None
+    if keys_out is None and grad_out is None:
+        raise ValueError("lattice_2d needs keys_out or grad_out")
+    ref = keys_out if keys_out is not None else grad_out
+    if ref.dim() < 2:
+        raise ValueError("keys_out must be (ny, nx) and grad_out (2, ny, nx)")
+    ny, nx = ref.shape[-2:]
+    kp, gp = _ptrs(_need(keys_out, "keys_out", (ny, nx), torch.int32) if keys_out is not None else None,
+                   _need(grad_out, "grad_out", (2, ny, nx), torch.float32) if grad_out is not None else None)
     _check(lib().ptg_lattice_2d(seed & 0xFFFFFFFF, octave, ix0, iy0, nx, ny, kp, gp, _stream(stream)))
 
 
 def heights_2d(seed, octave, ix0, iy0, out, stream=None):
     """K1 of the zero-gradient model: node heights into out (ny, nx) float32."""
     import torch
+    if out.dim() != 2:
+        raise ValueError("out must be (ny, nx)")
     ny, nx = out.shape
-    _check(lib().ptg_heights_2d(seed & 0xFFFFFFFF, octave, ix0, iy0, nx, ny, _dev_ptr(out, torch.float32),
-                                _stream(stream)))
+    hp, = _ptrs(_need(out, "out", (ny, nx), torch.float32))
+    _check(lib().ptg_heights_2d(seed & 0xFFFFFFFF, octave, ix0, iy0, nx, ny, hp, _stream(stream)))
 
 
 def lattice_3d(seed, octave, ix0, iy0, iz0, keys_out=None, second_out=None, grad_out=None, stream=None):
+    """K1, 3D: keys_out / second_out (nz, ny, nx) int32 and/or grad_out (3, nz, ny, nx) float32."""
     import torch
-    ref = keys_out if keys_out is not None else (second_out if second_out is not None else grad_out[0])
-    nz, ny, nx = ref.shape
-    kp = _dev_ptr(keys_out, torch.int32) if keys_out is not None else None
-    sp = _dev_ptr(second_out, torch.int32) if second_out is not None else None
-    gp = _dev_ptr(grad_out, torch.float32) if grad_out is not None else None
+    if keys_out is None and second_out is None and grad_out is None:
+        raise ValueError("lattice_3d needs at least one output")
+    ref = keys_out if keys_out is not None else (second_out if second_out is not None else grad_out)
+    if ref.dim() < 3:
+        raise ValueError("keys_out / second_out must be (nz, ny, nx) and grad_out (3, nz, ny, nx)")
+    nz, ny, nx = ref.shape[-3:]
+    kp, sp, gp = _ptrs(
+        _need(keys_out, "keys_out", (nz, ny, nx), torch.int32) if keys_out is not None else None,
+        _need(second_out, "second_out", (nz, ny, nx), torch.int32) if second_out is not None else None,
+        _need(grad_out, "grad_out", (3, nz, ny, nx), torch.float32) if grad_out is not None else None)
     _check(lib().ptg_lattice_3d(seed & 0xFFFFFFFF, octave, ix0, iy0, iz0, nx, ny, nz, kp, sp, gp, _stream(stream)))
 
 
 def cells_2d(smoothness, grad, amplitude, coeff_out, stream=None):
     """K2: grad (2, nny, nnx) float32 -> coeff_out (nny-1, nnx-1, n+1, n+1) float32."""
     import torch
+    if grad.dim() != 3 or grad.shape[1] < 2 or grad.shape[2] < 2:
+        raise ValueError("grad must be (2, nny, nnx) with nny, nnx >= 2")
     _, nny, nnx = grad.shape
-    _check(lib().ptg_cells_2d(smoothness, _dev_ptr(grad, torch.float32), nnx, nny, amplitude,
-                              _dev_ptr(coeff_out, torch.float32), _stream(stream)))
+    n1 = 2 * int(smoothness) + 2
+    gp, cp = _ptrs(_need(grad, "grad", (2, nny, nnx), torch.float32),
+                   _need(coeff_out, "coeff_out", (nny - 1, nnx - 1, n1, n1), torch.float32))
+    _check(lib().ptg_cells_2d(smoothness, gp, nnx, nny, amplitude, cp, _stream(stream)))
 
 
 def cells_3d(smoothness, grad, amplitude, coeff_out, stream=None):
+    """K2, 3D: grad (3, nnz, nny, nnx) -> coeff_out (nnz-1, nny-1, nnx-1, n+1, n+1, n+1)."""
     import torch
+    if grad.dim() != 4 or min(grad.shape[1:]) < 2:
+        raise ValueError("grad must be (3, nnz, nny, nnx) with every node count >= 2")
     _, nnz, nny, nnx = grad.shape
-    _check(lib().ptg_cells_3d(smoothness, _dev_ptr(grad, torch.float32), nnx, nny, nnz, amplitude,
-                              _dev_ptr(coeff_out, torch.float32), _stream(stream)))
+    n1 = 2 * int(smoothness) + 2
+    gp, cp = _ptrs(_need(grad, "grad", (3, nnz, nny, nnx), torch.float32),
+                   _need(coeff_out, "coeff_out", (nnz - 1, nny - 1, nnx - 1, n1, n1, n1), torch.float32))
+    _check(lib().ptg_cells_3d(smoothness, gp, nnx, nny, nnz, amplitude, cp, _stream(stream)))
 
 
 def version() -> str:

@@ -73,3 +73,45 @@ def test_field_gradient_sums_octave_cells(model, M):
                 f *= lac
                 a *= pers
             assert HX[j, i] == wx and HY[j, i] == wy
+
+
+def _field(model, M, n, pers, lac, f0, w, seed, x0, y0, nx, ny):
+    if model == "gradient":
+        return O.fbm_2d(M, n, pers, lac, f0, seed, x0, y0, nx, ny)
+    if model == "zero_gradient":
+        return O.zg_fbm_2d(n, pers, lac, f0, seed, x0, y0, nx, ny)
+    return O.hg_fbm_2d(M, n, pers, lac, f0, w, seed, x0, y0, nx, ny)
+
+
+@pytest.mark.parametrize("model,M", [("gradient", 1), ("gradient", 2), ("gradient", 3), ("zero_gradient", 1),
+                                     ("height_gradient", 1), ("height_gradient", 2)])
+@pytest.mark.parametrize("n,f0,lac", [(1, 2.0 ** -14, 2.0), (4, 2.0 ** -14, 2.0), (3, 7.11e-5, 1.93)])
+def test_world_gradient_is_the_finite_difference_of_the_field(model, M, n, f0, lac):
+    """dH/dX and dH/dY in world units against a fourth-order central difference of the
+    value-only field over world samples, (-H(X+2) + 8H(X+1) - 8H(X-1) + H(X-2)) / 12.
+    The five samples of a stencil lie in one cell of every octave (periods >= 2048
+    samples), where each octave is a polynomial of degree 2M+1 in X: the stencil is exact
+    for degree <= 4 and its remainder (|X-step|^4 f^5 h^(5) / 30, f <= 2^-11) is below
+    1e-15 for higher degrees, so the difference carries only the FP64 rounding of H.
+    Power-of-two frequencies place samples exactly at any offset (here up to 2^40); the
+    non-dyadic ladder stays within 2^20 samples of the origin, where the FP64 coordinate
+    (X + 1/2) f carries below 2e-14 of a cell."""
+    pers, w, seed = 0.5, 0.3, 77
+    span = 1 << (40 if lac == 2.0 else 20)
+    rng = np.random.default_rng(hash((model, M, n)) & 0xFFFF)
+    freq, amp = O.octave_params(f0, lac, pers, n)
+    scale = float(np.sum(amp * freq))
+    checked = 0
+    while checked < 25:
+        X, Y = (int(v) for v in rng.integers(-span, span, size=2))
+        inside = all(np.floor((X - 1.5) * f) == np.floor((X + 2.5) * f) and
+                     np.floor((Y - 1.5) * f) == np.floor((Y + 2.5) * f) for f in freq)
+        if not inside:
+            continue
+        _, HX, HY = O.fbm_2d_grad(model, M, n, pers, lac, f0, w, seed, X, Y, 1, 1)
+        row = _field(model, M, n, pers, lac, f0, w, seed, X - 2, Y, 5, 1)[0]
+        col = _field(model, M, n, pers, lac, f0, w, seed, X, Y - 2, 1, 5)[:, 0]
+        st = np.array([1.0, -8.0, 0.0, 8.0, -1.0]) / 12.0
+        assert abs(HX[0, 0] - float(st @ row)) <= 1e-9 * scale, (X, Y)
+        assert abs(HY[0, 0] - float(st @ col)) <= 1e-9 * scale, (X, Y)
+        checked += 1
