@@ -460,12 +460,15 @@ def run_serving(n):
                 "tiles_s": round(n / span, 1), "octave_samples_s": osamp / span}
 
     def plain(arr, mode):
-        arr, done, st = i64(arr), i64(np.zeros(n)), i64(np.zeros(1))
+        arr, done, st = i64(arr), i64(np.zeros(n)), i64(np.zeros(3))
         rc = lg.ptg_lg_plain(treq, ptr(arr), n, arena.data_ptr(), arena_bytes, mode, 64, ptr(done), ptr(st))
         if rc != 0:
             raise RuntimeError(f"plain stream failed ({rc}): {ptg.last_error()}")
         out = summary(arr, done)
         out["launch_units"] = int(st[0])
+        if mode == 1:
+            out["graphs_instantiated"] = int(st[1])
+            out["graph_updates"] = int(st[2])
         return out
 
     def served(arr, budget):
@@ -505,8 +508,10 @@ def run_serving(n):
         "requests": n,
         "octave_samples": osamp,
         "plain_path": "one ptg_fbm_2d/3d call per request on one stream (auto kernel choice); plain_graph: "
-                      "all requests that have arrived (up to 64) captured into one hipGraph per launch",
-        "served_path": "ptg_tiles_submit into one persistent kernel (general tile kernel), HBM budget 4 GiB",
+                      "all requests that have arrived (up to 64) as one ptg_batch graph launch (instantiated once per "
+                      "batch shape, arguments updated when a shape recurs)",
+        "served_path": "ptg_tiles_submit into one persistent kernel (dyadic 2D / 3D requests on the strip "
+                       "code, the rest on general tiles), HBM budget 4 GiB",
         "capacity": cap,
         "open_loop": loads,
         "served_budget_at_0.8": budgets,

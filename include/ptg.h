@@ -267,6 +267,56 @@ PTG_API int ptg_tune_set_3d(const ptg_params *p, int64_t nx, int64_t ny, int64_t
 /* Forget every recorded shape. */
 PTG_API void ptg_tune_reset(void);
 
+/* ---- a6: HIP-graph batches of dense fields ------------------------------------
+ * A batch collects dense-field calls -- the one kernel launch each ptg_fbm_2d / ptg_fbm_3d
+ * call makes, with its arguments -- and launches them together as the kernel nodes of one
+ * HIP graph (the plain path of the tile stream, or a terrain engine's per-frame tile set).
+ * The graph of a batch shape (the same kernels, grids, workgroup sizes and LDS sizes in the
+ * same order) is instantiated once; a later batch of that shape updates the instance's
+ * kernel-node arguments in place (hipGraphExecKernelNodeSetParams) and relaunches it, e.g.
+ * the same tiles at new origins, seeds or output buffers.  Up to 4 instances of a shape are
+ * kept so that no instance is updated while a launch of it may still run; up to 64 shapes
+ * per batch object are cached, the least recently used dropped first.  The calls of one
+ * batch may run concurrently: their outputs must not overlap.  A batch object is used by
+ * one thread at a time.  Results equal the direct calls bit for bit (same kernels, same
+ * arguments). */
+typedef struct ptg_batch ptg_batch;
+
+typedef struct ptg_batch_stats {
+    int64_t launches;        /* graph launches                                              */
+    int64_t nodes;           /* kernel nodes launched (dense-field calls)                   */
+    int64_t instantiations;  /* graphs instantiated (new shapes, or a 2nd..4th instance)    */
+    int64_t updates;         /* launches that reused an instance with updated arguments     */
+    int64_t instances;       /* instances cached now                                        */
+    int64_t pending;         /* calls recorded and not launched yet                         */
+} ptg_batch_stats;
+
+/* A batch of at most max_calls (1..4096) calls.  Errors: PTG_EINVAL, PTG_ENOMEM. */
+PTG_API int ptg_batch_create(int32_t max_calls, ptg_batch **out);
+
+/* Record the launch of ptg_fbm_2d(p, x0, y0, nx, ny, out_dev, row_pitch, -) (validated as
+ * that call; an empty field records nothing).  Nothing runs until ptg_batch_launch.
+ * Errors: as ptg_fbm_2d, PTG_EINVAL when the batch is full. */
+PTG_API int ptg_batch_add_2d(ptg_batch *b, const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny,
+                             void *out_dev, int64_t row_pitch);
+/* The same for ptg_fbm_3d. */
+PTG_API int ptg_batch_add_3d(ptg_batch *b, const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t nx,
+                             int64_t ny, int64_t nz, void *out_dev);
+
+/* Launch the recorded calls as one graph on `stream` (asynchronous; may wait for an earlier
+ * launch of the same shape when all 4 of its instances are in flight) and empty the batch.
+ * An empty batch is a no-op.  Errors: PTG_EINVAL, PTG_EHIP (the recorded calls are
+ * dropped). */
+PTG_API int ptg_batch_launch(ptg_batch *b, void *stream);
+
+/* Drop the recorded calls without launching them. */
+PTG_API int ptg_batch_clear(ptg_batch *b);
+
+PTG_API int ptg_batch_stats_get(const ptg_batch *b, ptg_batch_stats *st);
+
+/* Wait for the batch's graph launches to finish and free everything. */
+PTG_API int ptg_batch_destroy(ptg_batch *b);
+
 /* ---- a6: serving (continuous batching of terrain tiles) ----------------------- */
 /* A server owns an output arena of hbm_budget_bytes and one persistent kernel.  Requests
  * (terrain tiles of any size, 2D or 3D, C1 or C2, any octave parameters, FP32 output) are

@@ -49,6 +49,7 @@ def lib():
     L.orc_octave_params.argtypes = [_f64, _f64, _f64, _i32, _pd, _pd]
     L.orc_coord.argtypes = [_i64, _f64, _pi64, _pd]
     L.orc_basis.argtypes = [_i32, _f64, _pd, _pd]
+    L.orc_hermite_closed.argtypes = [_i32, _f64, _pd, _pd]
     L.orc_cell_2d.argtypes = [_i32, _pd, _f64, _f64]
     L.orc_cell_2d.restype = _f64
     L.orc_cell_3d.argtypes = [_i32, _pd, _f64, _f64, _f64]
@@ -174,6 +175,14 @@ def basis(smooth: int, t: float):
     b0 = np.zeros(2)
     b1 = np.zeros(2)
     lib().orc_basis(smooth, t, _dp(b0), _dp(b1))
+    return b0, b1
+
+
+def hermite_closed(M: int, t: float):
+    """The four 1D bases of order M from their closed forms (any M <= 6)."""
+    b0 = np.zeros(2)
+    b1 = np.zeros(2)
+    lib().orc_hermite_closed(M, t, _dp(b0), _dp(b1))
     return b0, b1
 
 

@@ -14,7 +14,9 @@
  *  - Sec. 2.1, eq. (independance): on an edge, h depends on that edge's two corners
  *    only (so neighbouring cells agree on shared edges).
  *  - Sec. 2.2, eq. (polynomial): h is a tensor polynomial with exponents 0..n per axis,
- *    (n+1)^D coefficients; eq. (nconstraints) bounds the constraint count.
+ *    (n+1)^D coefficients; eq. (nconstraints) bounds the constraint count.  Any order
+ *    M = 1..6 (n = 2M+1; the Conclusion's arbitrary smoothness): 1D bases from their
+ *    closed forms (orc_hermite_monomials), explicit for M <= 3.
  *  - Sec. 3.4: D1M1N3 with h(0)=0, h(1)=1 and zero end slopes is the smoothstep S3;
  *    D3M1N3 is the 3D analogue; second-order constraints (M=2) give smoother cells.
  *  - Sec. 3.2: Perlin's blend (comparison path) with fade S3 (or S5, Sec. 5.1).
@@ -56,6 +58,8 @@
 #define ORC_OK 0
 #define ORC_EINVAL (-1)
 #define ORC_MAX_OCTAVES 32
+#define ORC_MAX_SMOOTH 6               /* smoothness orders M = 1..6: degree n = 2M+1 <= 13 */
+#define ORC_MAX_N1 (2 * ORC_MAX_SMOOTH + 2)
 
 static const double ORC_TWO_PI = 6.283185307179586476925286766559;
 
@@ -170,6 +174,60 @@ void orc_coord(int64_t X, double f, int64_t *cell, double *t)
 /* 1D Hermite bases on [0,1]                                                 */
 /* ------------------------------------------------------------------------- */
 
+/* Binomial coefficient C(n, k) (exact in FP64 for the small n used here). */
+static double orc_binom(int n, int k)
+{
+    if (k < 0 || k > n) return 0.0;
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
+
+/* Monomial coefficients of the 1D Hermite bases of any order M (Sec. 2.2 with n = 2M+1:
+ * the value and the first M derivatives prescribed at both ends of [0, 1]), from their
+ * closed forms (two-point Taylor interpolation):
+ *   S(t)     = t^(M+1) sum_{k=0..M} C(M+k, k) (1-t)^k          (value 1 at t = 1, b0[1])
+ *   b1[0](t) = t (1-t)^(M+1) sum_{k=0..M-1} C(M+k, k) t^k       (unit slope at t = 0)
+ *   b1[1](t) = -b1[0](1 - t),  b0[0] = 1 - S.
+ * Each factor (1-t)^p is expanded with binomial coefficients.  bases[k][e] is the
+ * coefficient of t^e of b0[0], b0[1], b1[0], b1[1] (k = 0..3). */
+static void orc_hermite_monomials(int32_t M, double bases[4][ORC_MAX_N1])
+{
+    memset(bases, 0, sizeof(double) * 4 * ORC_MAX_N1);
+    for (int k = 0; k <= M; ++k)  /* C(M+k,k) t^(M+1) (1-t)^k */
+        for (int i = 0; i <= k; ++i)
+            bases[1][M + 1 + i] += orc_binom(M + k, k) * orc_binom(k, i) * ((i & 1) ? -1.0 : 1.0);
+    for (int e = 0; e < ORC_MAX_N1; ++e) bases[0][e] = (e == 0 ? 1.0 : 0.0) - bases[1][e];
+    for (int k = 0; k < M; ++k)  /* C(M+k,k) t^(k+1) (1-t)^(M+1) */
+        for (int i = 0; i <= M + 1; ++i)
+            bases[2][1 + k + i] += orc_binom(M + k, k) * orc_binom(M + 1, i) * ((i & 1) ? -1.0 : 1.0);
+    for (int p = 0; p < ORC_MAX_N1; ++p)  /* -sum_p c_p (1-t)^p */
+        if (bases[2][p] != 0.0)
+            for (int j = 0; j <= p; ++j) bases[3][j] -= bases[2][p] * orc_binom(p, j) * ((j & 1) ? -1.0 : 1.0);
+}
+
+/* Value (d = 0) or first derivative (d = 1) of a monomial expansion by Horner's rule. */
+static double orc_horner(const double *c, int n1, int d, double t)
+{
+    double v = 0.0;
+    for (int e = n1 - 1; e >= d; --e) v = v * t + (d ? (double)e * c[e] : c[e]);
+    return v;
+}
+
+/* The closed forms above evaluated for any order (including M <= 3, whose explicit forms
+ * below are the ones the oracle uses; the tests compare the two). */
+void orc_hermite_closed(int32_t M, double t, double *b0, double *b1)
+{
+    double B[4][ORC_MAX_N1];
+    if (M < 1 || M > ORC_MAX_SMOOTH) return;
+    orc_hermite_monomials(M, B);
+    const int n1 = 2 * M + 2;
+    b0[0] = orc_horner(B[0], n1, 0, t);
+    b0[1] = orc_horner(B[1], n1, 0, t);
+    b1[0] = orc_horner(B[2], n1, 0, t);
+    b1[1] = orc_horner(B[3], n1, 0, t);
+}
+
 /* Value bases b0[c] (1 at corner c, 0 at the other, zero derivatives up to M at both
  * ends) and slope bases b1[c] (zero value, unit first derivative at corner c, zero
  * first derivative at the other end, zero higher derivatives up to M).
@@ -178,10 +236,21 @@ void orc_coord(int64_t X, double f, int64_t *cell, double *t)
  *   b1[0] = t - 6t^3 + 8t^4 - 3t^5, b1[1] = -4t^3 + 7t^4 - 3t^5.
  * Septic (M=3, derivatives up to 3 constrained, Sec. 2.2 with n = 7):
  *   b0[1] = S7 = 35t^4 - 84t^5 + 70t^6 - 20t^7,
- *   b1[0] = t - 20t^4 + 45t^5 - 36t^6 + 10t^7, b1[1] = -15t^4 + 39t^5 - 34t^6 + 10t^7. */
+ *   b1[0] = t - 20t^4 + 45t^5 - 36t^6 + 10t^7, b1[1] = -15t^4 + 39t^5 - 34t^6 + 10t^7.
+ * M = 4..6: the closed forms of orc_hermite_monomials. */
 void orc_basis(int32_t smooth, double t, double *b0, double *b1)
 {
     double t2 = t * t, t3 = t2 * t;
+    if (smooth >= 4) { /* any higher order: the closed forms of orc_hermite_monomials */
+        double B[4][ORC_MAX_N1];
+        orc_hermite_monomials(smooth, B);
+        const int n1 = 2 * smooth + 2;
+        b0[0] = orc_horner(B[0], n1, 0, t);
+        b0[1] = orc_horner(B[1], n1, 0, t);
+        b1[0] = orc_horner(B[2], n1, 0, t);
+        b1[1] = orc_horner(B[3], n1, 0, t);
+        return;
+    }
     if (smooth == 1) {
         double s = 3.0 * t2 - 2.0 * t3;
         b0[0] = 1.0 - s;
@@ -207,10 +276,12 @@ void orc_basis(int32_t smooth, double t, double *b0, double *b1)
 
 /* Monomial coefficients of the same bases: bases[k][e] is the coefficient of t^e,
  * k = 0: b0[0], 1: b0[1], 2: b1[0], 3: b1[1]; degree n = 2M+1. */
-static void orc_basis_monomials(int32_t smooth, double bases[4][8])
+static void orc_basis_monomials(int32_t smooth, double bases[4][ORC_MAX_N1])
 {
-    memset(bases, 0, sizeof(double) * 32);
-    if (smooth == 1) {
+    memset(bases, 0, sizeof(double) * 4 * ORC_MAX_N1);
+    if (smooth >= 4) {
+        orc_hermite_monomials(smooth, bases);
+    } else if (smooth == 1) {
         /* 1 - 3t^2 + 2t^3 */
         bases[0][0] = 1.0; bases[0][2] = -3.0; bases[0][3] = 2.0;
         /* 3t^2 - 2t^3 */
@@ -285,7 +356,7 @@ double orc_cell_3d(int32_t smooth, const double *grad, double tx, double ty, dou
  * expanding the Hermite form above. */
 void orc_coeffs_2d(int32_t smooth, const double *grad, double *c)
 {
-    double B[4][8];
+    double B[4][ORC_MAX_N1];
     orc_basis_monomials(smooth, B);
     int n1 = 2 * smooth + 2;
     memset(c, 0, sizeof(double) * (size_t)(n1 * n1));
@@ -305,7 +376,7 @@ void orc_coeffs_2d(int32_t smooth, const double *grad, double *c)
 /* Monomial coefficients c[(i*(n+1) + j)*(n+1) + k] of x^i y^j z^k (D = 3). */
 void orc_coeffs_3d(int32_t smooth, const double *grad, double *c)
 {
-    double B[4][8];
+    double B[4][ORC_MAX_N1];
     orc_basis_monomials(smooth, B);
     int n1 = 2 * smooth + 2;
     memset(c, 0, sizeof(double) * (size_t)(n1 * n1 * n1));
@@ -355,7 +426,7 @@ double orc_perlin_cell(int32_t fade_order, const double *grad, double x, double 
 
 static int orc_check(int32_t smooth, int32_t octaves, double f0, double lac, double pers)
 {
-    if (smooth < 1 || smooth > 3) return ORC_EINVAL;
+    if (smooth < 1 || smooth > ORC_MAX_SMOOTH) return ORC_EINVAL;
     if (octaves < 1 || octaves > ORC_MAX_OCTAVES) return ORC_EINVAL;
     if (!(f0 > 0.0) || !(lac > 0.0) || !(pers > 0.0)) return ORC_EINVAL;
     if (!isfinite(f0) || !isfinite(lac) || !isfinite(pers)) return ORC_EINVAL;
@@ -659,6 +730,16 @@ void orc_basis_deriv(int32_t smooth, double t, double *db0, double *db1)
 {
     double t2 = t * t, t3 = t2 * t;
     double ds;
+    if (smooth >= 4) {
+        double B[4][ORC_MAX_N1];
+        orc_hermite_monomials(smooth, B);
+        const int n1 = 2 * smooth + 2;
+        db0[0] = orc_horner(B[0], n1, 1, t);
+        db0[1] = orc_horner(B[1], n1, 1, t);
+        db1[0] = orc_horner(B[2], n1, 1, t);
+        db1[1] = orc_horner(B[3], n1, 1, t);
+        return;
+    }
     if (smooth == 1) {
         ds = 6.0 * t - 6.0 * t2;
         db1[0] = 1.0 - 4.0 * t + 3.0 * t2;

@@ -124,6 +124,11 @@ class TuneResult(ctypes.Structure):
 PTG_EXEC_GPU = 0
 PTG_EXEC_HOST = 1
 
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("launches", "nodes", "instantiations", "updates", "instances",
+                                              "pending")]
+
 _LIB = None
 _i32, _u32, _i64, _f32, _f64 = ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_float, ctypes.c_double
 _vp = ctypes.c_void_p
@@ -166,10 +171,19 @@ def lib():
     L.ptg_tune_set_3d.argtypes = [_PP, _i64, _i64, _i64, _i32]
     L.ptg_tune_reset.argtypes = []
     L.ptg_tune_reset.restype = None
+    L.ptg_batch_create.argtypes = [_i32, ctypes.POINTER(ctypes.c_void_p)]
+    L.ptg_batch_add_2d.argtypes = [_vp, _PP, _i64, _i64, _i64, _i64, _vp, _i64]
+    L.ptg_batch_add_3d.argtypes = [_vp, _PP, _i64, _i64, _i64, _i64, _i64, _i64, _vp]
+    L.ptg_batch_launch.argtypes = [_vp, _vp]
+    L.ptg_batch_clear.argtypes = [_vp]
+    L.ptg_batch_stats_get.argtypes = [_vp, ctypes.POINTER(BatchStats)]
+    L.ptg_batch_destroy.argtypes = [_vp]
     for name in ("ptg_fbm_2d", "ptg_fbm_2d_grad", "ptg_fbm_3d", "ptg_coords", "ptg_lattice_2d", "ptg_lattice_3d", "ptg_heights_2d",
                  "ptg_cells_2d", "ptg_cells_3d", "ptg_server_create", "ptg_tiles_submit", "ptg_tiles_wait",
                  "ptg_tile_release", "ptg_server_stats_get", "ptg_server_destroy", "ptg_tune_2d", "ptg_tune_3d",
-                 "ptg_tune_query_2d", "ptg_tune_query_3d", "ptg_tune_set_2d", "ptg_tune_set_3d"):
+                 "ptg_tune_query_2d", "ptg_tune_query_3d", "ptg_tune_set_2d", "ptg_tune_set_3d",
+                 "ptg_batch_create", "ptg_batch_add_2d", "ptg_batch_add_3d", "ptg_batch_launch", "ptg_batch_clear",
+                 "ptg_batch_stats_get", "ptg_batch_destroy"):
         getattr(L, name).restype = _i32
     _LIB = L
     return L
@@ -438,6 +452,56 @@ def tune_set(shape, value, out_dtype=PTG_F32, **kw):
 
 def tune_reset():
     lib().ptg_tune_reset()
+
+
+class Batch:
+    """Dense-field calls launched together as one HIP graph (ptg_batch in the C ABI): the
+    graph of a batch shape is instantiated once, later batches of that shape update its
+    arguments.  The calls of one batch may run concurrently (outputs must not overlap)."""
+
+    def __init__(self, max_calls=256):
+        h = ctypes.c_void_p()
+        _check(lib().ptg_batch_create(max_calls, ctypes.byref(h)))
+        self.h = h
+
+    def add_2d(self, out, *, x0=0, y0=0, **kw):
+        if out.dim() != 2 or out.stride(1) != 1:
+            raise ValueError("out must be 2D with unit column stride")
+        p = params(dim=2, out_dtype=_out_dtype(out), **kw)
+        ny, nx = out.shape
+        _check(lib().ptg_batch_add_2d(self.h, ctypes.byref(p), x0, y0, nx, ny, _dev_ptr(out) if out.numel() else None,
+                                      out.stride(0)))
+
+    def add_3d(self, out, *, x0=0, y0=0, z0=0, **kw):
+        if out.dim() != 3 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous 3D tensor")
+        p = params(dim=3, out_dtype=_out_dtype(out), **kw)
+        nz, ny, nx = out.shape
+        _check(lib().ptg_batch_add_3d(self.h, ctypes.byref(p), x0, y0, z0, nx, ny, nz,
+                                      _dev_ptr(out) if out.numel() else None))
+
+    def launch(self, stream=None):
+        _check(lib().ptg_batch_launch(self.h, _stream(stream)))
+
+    def clear(self):
+        _check(lib().ptg_batch_clear(self.h))
+
+    def stats(self) -> dict:
+        st = BatchStats()
+        _check(lib().ptg_batch_stats_get(self.h, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in BatchStats._fields_}
+
+    def close(self):
+        if self.h:
+            rc = lib().ptg_batch_destroy(self.h)
+            self.h = None
+            _check(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def tile_req(dim=2, origin=(0, 0, 0), extent=(64, 64, 1), user_tag=0, **kw) -> TileReq:

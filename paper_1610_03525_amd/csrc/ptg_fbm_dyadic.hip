@@ -521,8 +521,7 @@ static hipError_t launch_dy(const Fbm2dDyadicArgs &a, size_t lds, hipStream_t s)
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)a.grid), dim3(256), lds, s, a);
-    return hipGetLastError();
+    return launch_k(kern, dim3((unsigned)a.grid), dim3(256), lds, s, a);
 }
 
 hipError_t launch_fbm2d_dyadic(const Fbm2dDyadicArgs &a, int smooth, bool f16, size_t lds, hipStream_t s)

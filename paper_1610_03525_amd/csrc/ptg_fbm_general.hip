@@ -34,8 +34,7 @@ static hipError_t launch_dyn(void (*kernel)(Args), dim3 grid, size_t lds, hipStr
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kernel, grid, dim3(256), lds, s, a);
-    return hipGetLastError();
+    return launch_k(kernel, grid, dim3(256), lds, s, a);
 }
 
 template <int TH>

@@ -36,8 +36,7 @@ static hipError_t launch_st(const Fbm2dStripArgs &a, int grid, int waves, size_t
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * waves), lds, s, a);
-    return hipGetLastError();
+    return launch_k(kern, dim3(grid), dim3(64 * waves), lds, s, a);
 }
 
 template <int M, typename OutT, int MD>

@@ -135,6 +135,47 @@ struct Fbm3dStripArgs {
     int32_t lo;                     // min(finest shift, 3): selects the kernel's row loop
 };
 
+// ---- launch recording (HIP graphs) --------------------------------------------------
+// Every dense-field driver launches exactly one kernel whose only argument is one of the
+// argument structs above.  Inside a batch recording (ptg_batch_add_*) on this thread the
+// launch is recorded instead -- function, shape, dynamic LDS and a copy of the argument
+// bytes -- and the batch later launches its records as the kernel nodes of one HIP graph.
+constexpr int kLaunchArgMax = 1024;
+
+struct LaunchRec {
+    const void *func;
+    dim3 grid, block;
+    uint32_t lds;
+    uint32_t arg_bytes;
+    alignas(16) unsigned char args[kLaunchArgMax];
+};
+
+struct LaunchSink {
+    LaunchRec rec;
+    int n;  // launches recorded (a driver makes one)
+};
+
+// This thread's sink (NULL: launch at once).
+LaunchSink *&launch_sink();
+
+template <typename Args>
+inline hipError_t launch_k(void (*kern)(Args), dim3 grid, dim3 block, size_t lds, hipStream_t s, const Args &a)
+{
+    static_assert(sizeof(Args) <= kLaunchArgMax, "kernel argument struct too large to record");
+    if (LaunchSink *k = launch_sink()) {
+        if (k->n++ != 0) return hipErrorInvalidValue;  // a driver records one launch
+        k->rec.func = reinterpret_cast<const void *>(kern);
+        k->rec.grid = grid;
+        k->rec.block = block;
+        k->rec.lds = (uint32_t)lds;
+        k->rec.arg_bytes = (uint32_t)sizeof(Args);
+        __builtin_memcpy(k->rec.args, &a, sizeof(Args));
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(kern, grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
 // Launch wrappers (defined in the .hip translation units).  They assume validated
 // arguments and return the HIP status of the launch.
 hipError_t launch_fbm2d_general(const Fbm2dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);

@@ -1,7 +1,7 @@
 // ptg_loadgen.cpp -- open-loop load generation for terrain-tile streams: the same request
 // stream with given arrival times driven through (a) the tile server and (b) the plain
 // per-tile path (one ptg_fbm_2d / ptg_fbm_3d call per request on one stream, launched
-// directly or captured in batches into HIP graphs).  Native threads issue and complete
+// directly or in batches as HIP graphs through the library's ptg_batch).  Native threads issue and complete
 // requests at their arrival times, so the measured latencies are those of the paths, not
 // of an interpreter.  Benchmark support; not part of the library's C ABI.
 #include "ptg_loadgen.h"
@@ -117,26 +117,26 @@ int ptg_lg_plain(const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n,
         off[(size_t)i] = o;
         o += b;
     }
-    // st executes; cs only records captures (its work is never run), so the completion
-    // thread's event waits never touch a stream that is capturing
-    hipStream_t st = nullptr, cs = nullptr;
+    hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return PTG_EHIP;
-    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    // graph mode: the library's batch object (instantiates a graph once per batch shape and
+    // updates its arguments for later batches of that shape)
+    ptg_batch *batch = nullptr;
+    if (mode == PTG_LG_GRAPH && ptg_batch_create(max_batch, &batch) != PTG_OK) {
         (void)hipStreamDestroy(st);
         return PTG_EHIP;
     }
-    // one completion event per launch unit (a request, or a captured batch)
+    // one completion event per launch unit (a request, or a batch)
     std::vector<hipEvent_t> ev((size_t)n, nullptr);
     for (auto &e : ev)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
             for (auto &f : ev)
                 if (f) (void)hipEventDestroy(f);
+            if (batch) (void)ptg_batch_destroy(batch);
             (void)hipStreamDestroy(st);
-            (void)hipStreamDestroy(cs);
             return PTG_EHIP;
         }
     std::vector<int32_t> unit_end((size_t)n, 0);     // unit u covers requests [u, unit_end[u])
-    std::vector<hipGraphExec_t> execs((size_t)n, nullptr);
     std::atomic<int32_t> issued{0};                  // requests whose unit has been launched
     std::atomic<int> err{PTG_OK};
     int64_t launches = 0;
@@ -155,10 +155,6 @@ int ptg_lg_plain(const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n,
             const int64_t t = now_ns() - t0;
             const int32_t e = unit_end[(size_t)u];
             for (int32_t k = u; k < e; ++k) done_ns[k] = t;
-            if (execs[(size_t)u]) {
-                (void)hipGraphExecDestroy(execs[(size_t)u]);
-                execs[(size_t)u] = nullptr;
-            }
             u = e;
         }
     });
@@ -169,17 +165,19 @@ int ptg_lg_plain(const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n,
         int32_t j = i + 1;
         if (mode == PTG_LG_DIRECT) {
             rc = plain_call(reqs[i], (char *)arena + off[(size_t)i], st);
-        } else {  // every request that has arrived, up to max_batch, in one graph
+        } else {  // every request that has arrived, up to max_batch, in one graph launch
             const int64_t now = now_ns();
             while (j < n && j - i < max_batch && t0 + arrival_ns[j] <= now) ++j;
-            hipGraph_t g = nullptr;
-            if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = PTG_EHIP;
-            for (int32_t k = i; k < j && rc == PTG_OK; ++k) rc = plain_call(reqs[k], (char *)arena + off[(size_t)k], cs);
-            if (hipStreamEndCapture(cs, &g) != hipSuccess && rc == PTG_OK) rc = PTG_EHIP;
-            if (rc == PTG_OK && hipGraphInstantiate(&execs[(size_t)i], g, nullptr, nullptr, 0) != hipSuccess)
-                rc = PTG_EHIP;
-            if (g) (void)hipGraphDestroy(g);
-            if (rc == PTG_OK && hipGraphLaunch(execs[(size_t)i], st) != hipSuccess) rc = PTG_EHIP;
+            for (int32_t k = i; k < j && rc == PTG_OK; ++k) {
+                const ptg_tile_req &r = reqs[k];
+                void *out = (char *)arena + off[(size_t)k];
+                rc = r.params.dim == 2
+                         ? ptg_batch_add_2d(batch, &r.params, r.origin[0], r.origin[1], r.extent[0], r.extent[1], out,
+                                            r.extent[0])
+                         : ptg_batch_add_3d(batch, &r.params, r.origin[0], r.origin[1], r.origin[2], r.extent[0],
+                                            r.extent[1], r.extent[2], out);
+            }
+            if (rc == PTG_OK) rc = ptg_batch_launch(batch, st);
         }
         if (rc == PTG_OK && hipEventRecord(ev[(size_t)i], st) != hipSuccess) rc = PTG_EHIP;
         if (rc != PTG_OK) {
@@ -193,12 +191,18 @@ int ptg_lg_plain(const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n,
     }
     wt.join();
     if (hipStreamSynchronize(st) != hipSuccess && err.load() == PTG_OK) err.store(PTG_EHIP);
-    for (auto &x : execs)  // graphs whose completion was not taken (after an error)
-        if (x) (void)hipGraphExecDestroy(x);
+    ptg_batch_stats bs{};
+    if (batch) {
+        (void)ptg_batch_stats_get(batch, &bs);
+        (void)ptg_batch_destroy(batch);
+    }
     for (auto &e : ev) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(st);
-    (void)hipStreamDestroy(cs);
-    if (stats) stats[0] = launches;
+    if (stats) {
+        stats[0] = launches;
+        stats[1] = bs.instantiations;
+        stats[2] = bs.updates;
+    }
     return err.load();
 }
 

@@ -15,9 +15,10 @@ extern "C" {
 #endif
 
 #define PTG_LG_DIRECT 0 /* one ptg_fbm_* launch per request as it arrives                  */
-#define PTG_LG_GRAPH 1  /* every request that has arrived (up to max_batch) captured into   */
-                        /* one HIP graph, instantiated and launched; its requests complete  */
-                        /* together                                                          */
+#define PTG_LG_GRAPH 1  /* every request that has arrived (up to max_batch) recorded into a */
+                        /* ptg_batch and launched as one HIP graph (instantiated once per   */
+                        /* batch shape, arguments updated for later batches of that shape); */
+                        /* its requests complete together                                    */
 
 /* Through server s: requests are submitted at their arrival times (all that have arrived
  * in one ptg_tiles_submit call); completions are taken in request order and released at
@@ -28,8 +29,9 @@ PTG_API int ptg_lg_served(ptg_server *s, const ptg_tile_req *reqs, const int64_t
 
 /* Through the plain path on a stream of its own: request i writes its dense output into
  * arena (device memory, arena_bytes) at an offset that wraps around in arrival order; the
- * single stream orders the reuse.  stats[0] (optional) receives the number of launch units
- * (requests, or graphs).  Returns PTG_OK, PTG_EINVAL, PTG_E2BIG (a request larger than the
+ * single stream orders the reuse.  stats (optional, 3 entries) receives the number of launch
+ * units (requests, or graph launches), and in graph mode the graphs instantiated and the
+ * launches that reused an instance with updated arguments.  Returns PTG_OK, PTG_EINVAL, PTG_E2BIG (a request larger than the
  * arena) or PTG_EHIP. */
 PTG_API int ptg_lg_plain(const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n, void *arena,
                          int64_t arena_bytes, int32_t mode, int32_t max_batch, int64_t *done_ns, int64_t *stats);

@@ -86,29 +86,92 @@ def test_served_tiles_equal_solo_calls_bit_exact():
         assert st["completed"] == 40 and st["bytes_peak"] <= (1 << 30)
 
 
+def _overlaps(results):
+    """Pairs of requests whose [admission, completion] intervals intersect: both were on the
+    device at once."""
+    iv = sorted((r.t_admit_ns, r.t_done_ns) for r in results)
+    n = 0
+    for i in range(len(iv)):
+        for j in range(i + 1, len(iv)):
+            if iv[j][0] < iv[i][1]:
+                n += 1
+    return n
+
+
 def test_alone_and_in_a_continuous_mix_are_identical():
+    """Every request of a mixed stream is computed alone first (one at a time on an idle
+    server), then the whole stream arrives in bursts while earlier bursts are still running:
+    each result in the mix equals its result alone bit for bit, and requests demonstrably
+    overlapped on the device (admitted before another one completed)."""
     reqs = _mix(30, 7)
-    probe = reqs[5]
     with ptg.Server(1 << 29) as srv:
-        (t_alone,) = srv.submit([_tile_req(probe)])
-        alone = _fetch(srv.wait(t_alone, int(60e9)), probe)
-        srv.release(t_alone)
+        alone = {}
+        for r in reqs:
+            (t,) = srv.submit([_tile_req(r)])
+            alone[r["user_tag"]] = _fetch(srv.wait(t, int(60e9)), r)
+            srv.release(t)
         got = {}
 
         def submitter():
-            for r in reqs:  # arrivals spread in time, submitted while others run
-                got[r["user_tag"]] = srv.submit([_tile_req(r)])[0]
-                time.sleep(0.002)
+            for b in range(0, len(reqs), 6):  # bursts of 6, 1 ms apart
+                ts = srv.submit([_tile_req(r) for r in reqs[b:b + 6]])
+                for r, t in zip(reqs[b:b + 6], ts):
+                    got[r["user_tag"]] = t
+                time.sleep(0.001)
 
         th = threading.Thread(target=submitter)
         th.start()
         th.join()
+        results = []
         for r in reqs:
             res = srv.wait(got[r["user_tag"]], int(60e9))
             assert res.status == ptg.PTG_OK
-            if r is probe:
-                assert torch.equal(_fetch(res, r), alone)
+            assert torch.equal(_fetch(res, r), alone[r["user_tag"]]), r
+            results.append(res)
             srv.release(got[r["user_tag"]])
+        assert _overlaps(results) > 0
+        probe = results[5]
+        assert any(o is not probe and o.t_admit_ns < probe.t_done_ns and probe.t_admit_ns < o.t_done_ns
+                   for o in results)
+
+
+def test_largest_stream_requests_served_bit_exact_and_against_oracle():
+    """The stream's largest requests -- 2048^2 2D tiles with 12 octaves (C1 and C2) and a
+    256^3 3D tile with 8 octaves (C2, 64 MiB) -- submitted together with small ones: each
+    equals its stand-alone call bit for bit, samples agree with the FP64 oracle, and the
+    requests overlapped on the device."""
+    rng = np.random.default_rng(2048)
+    big = []
+    for i, (dim, smooth, octs, ext) in enumerate([(2, 1, 12, (2048, 2048, 1)), (2, 2, 12, (2048, 2048, 1)),
+                                                   (3, 2, 8, (256, 256, 256)), (2, 1, 7, (128, 128, 1)),
+                                                   (3, 1, 4, (64, 64, 64)), (2, 2, 9, (512, 512, 1))]):
+        org = tuple(int(v) for v in rng.integers(-(1 << 46), 1 << 46, size=dim)) + (0,) * (3 - dim)
+        big.append(dict(dim=dim, smoothness=smooth, octaves=octs, base_freq=F0, persistence=0.5, lacunarity=2.0,
+                        seed=int(rng.integers(0, 1 << 32)), origin=org, extent=ext, user_tag=i))
+    with ptg.Server(1 << 30) as srv:
+        tickets = srv.submit([_tile_req(r) for r in big])
+        results = []
+        for t, r in zip(tickets, big):
+            res = srv.wait(t, int(120e9))
+            assert res.status == ptg.PTG_OK
+            got = _fetch(res, r)
+            results.append(res)
+            srv.release(t)
+            assert torch.equal(got, _solo(r, res.kernel)), r
+            g = got.cpu().numpy().astype(np.float64)
+            A = sum(0.5 ** o for o in range(r["octaves"]))
+            k = 400
+            if r["dim"] == 2:
+                i, j = rng.integers(0, r["extent"][0], k), rng.integers(0, r["extent"][1], k)
+                ref = O.fbm_points_2d(r["smoothness"], r["octaves"], 0.5, 2.0, F0, r["seed"], r["origin"][0] + i,
+                                      r["origin"][1] + j)
+                assert np.max(np.abs(g[j, i] - ref)) <= 1e-5 * A, r
+            else:
+                i, j, l = (rng.integers(0, r["extent"][a], k) for a in range(3))
+                ref = O.fbm_points_3d(r["smoothness"], r["octaves"], 0.5, 2.0, F0, r["seed"], r["origin"][0] + i,
+                                      r["origin"][1] + j, r["origin"][2] + l)
+                assert np.max(np.abs(g[l, j, i] - ref)) <= 1e-5 * A, r
+        assert _overlaps(results) > 0
 
 
 def _drain(srv, tickets, reqs, timeout_s=60.0):
@@ -232,7 +295,7 @@ def test_plain_stream_direct_and_graph_batched_write_what_solo_calls_write():
         torch.cuda.synchronize()
         arr = np.ascontiguousarray(np.arange(n) * 100_000, dtype=np.int64)
         done = np.zeros(n, dtype=np.int64)
-        st = np.zeros(1, dtype=np.int64)
+        st = np.zeros(3, dtype=np.int64)
         rc = lg.ptg_lg_plain(tr, arr.ctypes.data_as(p64), n, arena.data_ptr(), o, mode, 8, done.ctypes.data_as(p64),
                              st.ctypes.data_as(p64))
         assert rc == ptg.PTG_OK, ptg.last_error()

@@ -250,7 +250,7 @@ def test_field_bounded_by_total_amplitude():
 
 def test_rejects_bad_parameters():
     with pytest.raises(ValueError):
-        O.fbm_2d(4, 4, 0.5, 2.0, 0.1, 1, 0, 0, 4, 4)  # smoothness 1..3
+        O.fbm_2d(7, 4, 0.5, 2.0, 0.1, 1, 0, 0, 4, 4)  # smoothness 1..6
     with pytest.raises(ValueError):
         O.fbm_2d(1, 0, 0.5, 2.0, 0.1, 1, 0, 0, 4, 4)
     with pytest.raises(ValueError):
