@@ -258,14 +258,16 @@ def other_configs(torch, ptg, stream):
     n, f0 = 16384, 32 / 16384
     x0, y0 = (2 ** 24 - 3) * 512, -(2 ** 24 - 5) * 512
     forms = {}
-    for form, basis, dt in (("plain", "monomial", torch.float32), ("mfma_f16", "monomial", torch.float16),
-                            ("mfma_f16", "centred", torch.float16), ("mfma_bf16", "monomial", torch.float16),
-                            ("mfma_bf16", "centred", torch.float16)):
+    for form, basis, dt in (("plain", "monomial", torch.float32), ("plain", "monomial", torch.float16),
+                            ("mfma_f16", "monomial", torch.float16), ("mfma_f16", "centred", torch.float16),
+                            ("mfma_f16", "hermite", torch.float16), ("mfma_bf16", "monomial", torch.float16),
+                            ("mfma_bf16", "centred", torch.float16), ("mfma_bf16", "hermite", torch.float16)):
         out = torch.empty((n, n), dtype=dt, device="cuda")
         q = ptg.params(smoothness=1, octaves=10, base_freq=f0, seed=1, form=form, basis=basis,
                        out_dtype=ptg.PTG_F16 if dt == torch.float16 else ptg.PTG_F32)
         ms = _time_launches(torch, stream, lambda: ptg.fbm_2d_raw(q, x0, y0, n, n, out.data_ptr(), n, sh), 5)
-        forms[f"{form}/{basis}" if form != "plain" else "plain_fp32"] = {
+        name = f"{form}/{basis}" if form != "plain" else ("plain_fp32" if dt == torch.float32 else "plain_fp16_out")
+        forms[name] = {
             "ms": ms, "octave_samples_s": n * n * 10 / (ms * 1e-3),
             "hbm_frac": n * n * out.element_size() / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del out

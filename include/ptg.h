@@ -89,8 +89,14 @@ extern "C" {
                             /* period 4); PTG_EINVAL when the parameters are otherwise  */
 
 /* ---- bases for the MFMA forms (Vandermonde rows fed to the matrix cores) ------ */
-#define PTG_BASIS_MONOMIAL 0  /* V(t) = [1, t, t^2, t^3], C = monomial coefficients   */
-#define PTG_BASIS_CENTRED 1   /* V(t) = [1, s, s^2, s^3] with s = t - 1/2              */
+/* Every 4 rows x 64 columns of the field are one MFMA: per column the octaves of period */
+/* >= 16 summed as one cubic per 16-row quarter, the period-8 cell and the period-4 cell */
+/* holding the rows; the constant terms and the octaves of period 2 and 1 stay FP32.      */
+#define PTG_BASIS_MONOMIAL 0  /* V(t) = [1, t, t^2, t^3], t = the cell's (quarter's) own  */
+                              /* corner coordinate, C = monomial coefficients            */
+#define PTG_BASIS_CENTRED 1   /* V(t) = [1, s, s^2, s^3] with s = t - 1/2 (centred)       */
+#define PTG_BASIS_HERMITE 2   /* cells in their 1D Hermite bases [1, S, b10, b11] (C = the */
+                              /* corner data itself); the quarter's cubic centred         */
 
 /* ---- cell models ------------------------------------------------------------ */
 #define PTG_MODEL_GRADIENT 0       /* value 0 and the lattice gradient at every corner     */

@@ -30,7 +30,7 @@ PTG_ENOENT = -8
 PTG_F32 = 0
 PTG_F16 = 1
 FORMS = {"plain": 0, "mfma_f16": 1, "mfma_bf16": 2}
-BASES = {"monomial": 0, "centred": 1}
+BASES = {"monomial": 0, "centred": 1, "hermite": 2}
 PATHS = {"auto": 0, "general": 1, "dyadic": 2}
 MODELS = {"gradient": 0, "zero_gradient": 1, "height_gradient": 2}
 PTG_MODEL_GRADIENT = 0

@@ -48,8 +48,10 @@ int validate_params(const ptg_params *p, int dim)
         return fail(PTG_EINVAL, "unknown form %d", p->form);
     if (p->form != PTG_FORM_PLAIN && (dim != 2 || p->smoothness != 1))
         return fail(PTG_EINVAL, "the matrix-core forms are 2D C1 only");
-    if (p->basis != PTG_BASIS_MONOMIAL && p->basis != PTG_BASIS_CENTRED)
+    if (p->basis != PTG_BASIS_MONOMIAL && p->basis != PTG_BASIS_CENTRED && p->basis != PTG_BASIS_HERMITE)
         return fail(PTG_EINVAL, "unknown basis %d", p->basis);
+    if (p->form != PTG_FORM_PLAIN && p->out_dtype != PTG_F16)
+        return fail(PTG_EINVAL, "the matrix-core forms write FP16 output");
     if (p->path != PTG_PATH_AUTO && p->path != PTG_PATH_GENERAL && p->path != PTG_PATH_DYADIC)
         return fail(PTG_EINVAL, "unknown path %d", p->path);
     if (p->model != PTG_MODEL_GRADIENT && p->model != PTG_MODEL_ZERO_GRADIENT && p->model != PTG_MODEL_HEIGHT_GRADIENT)

@@ -250,120 +250,7 @@ __device__ __forceinline__ void valu_octave(f32x4 (&acc)[2][4], const Fbm2dDyadi
     }
 }
 
-// ---------------------------------------------------------------------------------
-// Matrix-core precision form for the octaves of period >= 16 (2D C1): the per-cell
-// evaluation as the Vandermonde contraction h = V(x) C V(y)^T with FP16 / BF16 operands and
-// FP32 accumulation, four octaves K-packed per instruction (v_mfma_f32_16x16x16):
-//   stage 1  T_o[b][j] = sum_a c^o_ab x_j^a      A1 = blockdiag_o(C_o^T), B1 = V(x)
-//   stage 2  H[m][j]  += sum_(o,b) y_m^b T_o[b][j]  A2 = V(y), B2 = T rounded to FP16/BF16
-// The stage-1 result layout (lane l: rows 4(l/16)+i of column l%16) is the stage-2 B
-// operand layout, so T never leaves registers.  x, y are the cell fractions t (monomial
-// basis) or t - 1/2 (centred basis); c are the monomial coefficients of the same cell in
-// that variable, formed per lane from the LDS corner gradients: c = Mx^T F My with F the
-// Hermite matrix of the gradients and M the power coefficients of the four 1D bases.
-// ---------------------------------------------------------------------------------
-// Power coefficients of the cubic bases (rows b0_0, b0_1, b1_0, b1_1; column = power):
-// in t, and in s = t - 1/2 (binomial re-expansion, exact in binary).
-__constant__ float kPowT[4][4] = {{1.f, 0.f, -3.f, 2.f}, {0.f, 0.f, 3.f, -2.f}, {0.f, 1.f, -2.f, 1.f}, {0.f, 0.f, -1.f, 1.f}};
-__constant__ float kPowS[4][4] = {{0.5f, -1.5f, 0.f, 2.f},
-                                  {0.5f, 1.5f, 0.f, -2.f},
-                                  {0.125f, -0.25f, -0.5f, 1.f},
-                                  {-0.125f, -0.25f, 0.5f, 1.f}};
-
-typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ short to_bf16_bits(float v)
-{
-    // round to nearest even
-    uint32_t u = __float_as_uint(v);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
-
-template <int PREC>
-struct MOps;
-template <>
-struct MOps<1> {
-    typedef f16x4 vec;
-    __device__ __forceinline__ static vec pack(float a, float b, float c, float d)
-    {
-        return vec{(_Float16)a, (_Float16)b, (_Float16)c, (_Float16)d};
-    }
-    __device__ __forceinline__ static f32x4 mma(vec x, vec y, f32x4 acc)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x16f16(x, y, acc, 0, 0, 0);
-    }
-};
-template <>
-struct MOps<2> {
-    typedef bf16x4 vec;
-    __device__ __forceinline__ static vec pack(float a, float b, float c, float d)
-    {
-        return vec{to_bf16_bits(a), to_bf16_bits(b), to_bf16_bits(c), to_bf16_bits(d)};
-    }
-    __device__ __forceinline__ static f32x4 mma(vec x, vec y, f32x4 acc)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, acc, 0, 0, 0);
-    }
-};
-
-template <int PREC>
-__device__ __forceinline__ void vandermonde_octaves(f32x4 (&acc)[2][4], const Fbm2dDyadicArgs &a, const DyShared &sh,
-                                                    const int *p_shift, int n_coarse, int64_t Xw, int64_t Yt0,
-                                                    int lane, int xw)
-{
-    typedef MOps<PREC> Op;
-    const int kb = lane >> 4;  // K block: this lane's octave within a group of four
-    const int m = lane & 15;
-    const float (*pw)[4] = (a.basis == 1) ? kPowS : kPowT;
-    const float shiftv = (a.basis == 1) ? 0.5f : 0.0f;
-    for (int g0 = 0; g0 < n_coarse; g0 += 4) {
-        const int o = g0 + kb;
-        const bool live = o < n_coarse;
-        const int oo = live ? o : g0;  // a valid octave index for the address arithmetic
-        const int s = p_shift[oo];
-        const uint32_t mask = (1u << s) - 1u;
-        const float inv2p = __uint_as_float((uint32_t)(126 - s) << 23);  // 2^-(s+1)
-        const int nny = a.nny[oo];
-        const float2 *nd = sh.nodes + a.noff[oo];
-        // stage-1 A row of this lane: octave block (m >> 2) meets K block kb only on the
-        // diagonal; its y power b = m & 3
-        const bool diag = live && ((m >> 2) == kb);
-        const int b = m & 3;
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-            // V(y) row for stage 2: powers 0..3 of y at row 16g + m of this lane's octave
-            const float ty = dy_frac(Yt0 + 16 * g + m, mask, inv2p) - shiftv;
-            const typename Op::vec A2 = live ? Op::pack(1.0f, ty, ty * ty, ty * ty * ty) : Op::pack(0.f, 0.f, 0.f, 0.f);
-            const int cyl = (16 * g) >> s;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                // V(x) column for stage 1: powers 0..3 of x at column 16c + m
-                const float tx = dy_frac(Xw + 16 * c + m, mask, inv2p) - shiftv;
-                const typename Op::vec B1 = Op::pack(1.0f, tx, tx * tx, tx * tx * tx);
-                // c_ab (a = 0..3) of the cell of this lane's octave: u = F My[:, b], c = Mx^T u
-                const int cxl = (xw + 16 * c) >> s;
-                const float2 *q = nd + cxl * nny + cyl;
-                const float2 n00 = q[0], n01 = q[1], n10 = q[nny], n11 = q[nny + 1];
-                const float u0 = n00.y * pw[2][b] + n01.y * pw[3][b];  // gy of corner column 0
-                const float u1 = n10.y * pw[2][b] + n11.y * pw[3][b];  // gy of corner column 1
-                const float u2 = n00.x * pw[0][b] + n01.x * pw[1][b];  // gx of corner column 0
-                const float u3 = n10.x * pw[0][b] + n11.x * pw[1][b];  // gx of corner column 1
-                float cv[4];
-#pragma unroll
-                for (int aa = 0; aa < 4; ++aa)
-                    cv[aa] = diag ? (pw[0][aa] * u0 + pw[1][aa] * u1 + pw[2][aa] * u2 + pw[3][aa] * u3) : 0.0f;
-                const typename Op::vec A1 = Op::pack(cv[0], cv[1], cv[2], cv[3]);
-                const f32x4 T = Op::mma(A1, B1, f32x4{0.f, 0.f, 0.f, 0.f});
-                const typename Op::vec B2 = Op::pack(T[0], T[1], T[2], T[3]);
-                acc[g][c] = Op::mma(A2, B2, acc[g][c]);
-            }
-        }
-    }
-}
-
-template <int M, typename OutT, int PREC>
+template <int M, typename OutT>
 __global__ __launch_bounds__(256) void k_fbm2d_dyadic(const Fbm2dDyadicArgs a)
 {
     constexpr int TX = kDyTileX;  // 256: 4 waves x 64 columns
@@ -464,13 +351,6 @@ __global__ __launch_bounds__(256) void k_fbm2d_dyadic(const Fbm2dDyadicArgs a)
 
         const int64_t Xw = Xt0 + xw;
         int o = 0;
-        if (PREC != 0) {
-            // octaves of period >= 16 through the FP16 / BF16 Vandermonde form
-            int nc = 0;
-            while (nc < N && a.shift[nc] >= 4) ++nc;
-            vandermonde_octaves<PREC == 0 ? 1 : PREC>(acc, a, sh, p_shift, nc, Xw, Yt0, lane, xw);
-            o = nc;
-        }
         for (; o < N && a.shift[o] >= 6; ++o) mfma16_octave<M, 0>(acc, a, sh, o, Xw, Yt0, lane, xw);
         if (o < N && a.shift[o] == 5) mfma16_octave<M, 1>(acc, a, sh, o++, Xw, Yt0, lane, xw);
         if (o < N && a.shift[o] == 4) mfma16_octave<M, 2>(acc, a, sh, o++, Xw, Yt0, lane, xw);
@@ -512,10 +392,10 @@ __global__ __launch_bounds__(256) void k_fbm2d_dyadic(const Fbm2dDyadicArgs a)
     }
 }
 
-template <int M, typename OutT, int PREC = 0>
+template <int M, typename OutT>
 static hipError_t launch_dy(const Fbm2dDyadicArgs &a, size_t lds, hipStream_t s)
 {
-    auto kern = k_fbm2d_dyadic<M, OutT, PREC>;
+    auto kern = k_fbm2d_dyadic<M, OutT>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -526,8 +406,6 @@ static hipError_t launch_dy(const Fbm2dDyadicArgs &a, size_t lds, hipStream_t s)
 
 hipError_t launch_fbm2d_dyadic(const Fbm2dDyadicArgs &a, int smooth, bool f16, size_t lds, hipStream_t s)
 {
-    if (a.prec == 1) return f16 ? launch_dy<1, __half, 1>(a, lds, s) : launch_dy<1, float, 1>(a, lds, s);
-    if (a.prec == 2) return f16 ? launch_dy<1, __half, 2>(a, lds, s) : launch_dy<1, float, 2>(a, lds, s);
     if (smooth == 1) return f16 ? launch_dy<1, __half>(a, lds, s) : launch_dy<1, float>(a, lds, s);
     return f16 ? launch_dy<2, __half>(a, lds, s) : launch_dy<2, float>(a, lds, s);
 }

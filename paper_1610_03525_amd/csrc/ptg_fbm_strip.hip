@@ -5,7 +5,7 @@
 
 namespace ptg {
 
-template <int M, typename OutT, int LO, int MD>
+template <int M, typename OutT, int LO, int MD, int PREC = 0>
 __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
 {
     extern __shared__ float4 lds4[];
@@ -22,15 +22,15 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
 
     strip_prologue(a, sh, wl_key, wl_node, tid, nthreads);
     __syncthreads();
-    StripWave<M, OutT, LO, MD> w(a, sh, nodes, lane);
+    StripWave<M, OutT, LO, MD, PREC> w(a, sh, nodes, lane);
     const int64_t nwaves = (int64_t)gridDim.x * wpg;
     for (int64_t st = (int64_t)blockIdx.x * wpg + wave; st < a.strips; st += nwaves) w.run(a, sh, wl_key, wl_node, st);
 }
 
-template <int M, typename OutT, int LO, int MD>
+template <int M, typename OutT, int LO, int MD, int PREC = 0>
 static hipError_t launch_st(const Fbm2dStripArgs &a, int grid, int waves, size_t lds, hipStream_t s)
 {
-    auto kern = k_fbm2d_strip<M, OutT, LO, MD>;
+    auto kern = k_fbm2d_strip<M, OutT, LO, MD, PREC>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -53,11 +53,11 @@ static hipError_t launch_lo(const Fbm2dStripArgs &a, int grid, int waves, size_t
     }
 }
 
-template <int M, typename OutT, int LO, int MD>
+template <int M, typename OutT, int LO, int MD, int PREC = 0>
 static int resident_one(int waves, size_t lds)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, LO, MD>, 64 * waves, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_fbm2d_strip<M, OutT, LO, MD, PREC>, 64 * waves, lds) !=
         hipSuccess)
         return 1;
     return n > 0 ? n : 1;
@@ -100,6 +100,45 @@ hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, int model, bo
     if (smooth == 1)
         return f16 ? launch_lo<1, __half, 0>(a, grid, waves, lds, s) : launch_lo<1, float, 0>(a, grid, waves, lds, s);
     return f16 ? launch_lo<2, __half, 0>(a, grid, waves, lds, s) : launch_lo<2, float, 0>(a, grid, waves, lds, s);
+}
+
+// The FP16 / BF16 precision form (cubic cells, gradient model, FP16 output).
+template <int PREC>
+static hipError_t launch_mx_lo(const Fbm2dStripArgs &a, int grid, int waves, size_t lds, hipStream_t s)
+{
+    switch (a.lo) {
+    case 0: return launch_st<1, __half, 0, 0, PREC>(a, grid, waves, lds, s);
+    case 1: return launch_st<1, __half, 1, 0, PREC>(a, grid, waves, lds, s);
+    case 2: return launch_st<1, __half, 2, 0, PREC>(a, grid, waves, lds, s);
+    case 3: return launch_st<1, __half, 3, 0, PREC>(a, grid, waves, lds, s);
+    case 4: return launch_st<1, __half, 4, 0, PREC>(a, grid, waves, lds, s);
+    case 5: return launch_st<1, __half, 5, 0, PREC>(a, grid, waves, lds, s);
+    default: return launch_st<1, __half, 6, 0, PREC>(a, grid, waves, lds, s);
+    }
+}
+
+template <int PREC>
+static int resident_mx(int lo, int waves, size_t lds)
+{
+    switch (lo) {
+    case 0: return resident_one<1, __half, 0, 0, PREC>(waves, lds);
+    case 1: return resident_one<1, __half, 1, 0, PREC>(waves, lds);
+    case 2: return resident_one<1, __half, 2, 0, PREC>(waves, lds);
+    case 3: return resident_one<1, __half, 3, 0, PREC>(waves, lds);
+    case 4: return resident_one<1, __half, 4, 0, PREC>(waves, lds);
+    case 5: return resident_one<1, __half, 5, 0, PREC>(waves, lds);
+    default: return resident_one<1, __half, 6, 0, PREC>(waves, lds);
+    }
+}
+
+int strip_mx_wgs_per_cu(int prec, int lo, int waves, size_t lds)
+{
+    return prec == 1 ? resident_mx<1>(lo, waves, lds) : resident_mx<2>(lo, waves, lds);
+}
+
+hipError_t launch_fbm2d_strip_mx(const Fbm2dStripArgs &a, int prec, int grid, int waves, size_t lds, hipStream_t s)
+{
+    return prec == 1 ? launch_mx_lo<1>(a, grid, waves, lds, s) : launch_mx_lo<2>(a, grid, waves, lds, s);
 }
 
 }  // namespace ptg

@@ -71,8 +71,6 @@ struct Fbm2dDyadicArgs {
     int32_t tiles_x;
     int32_t grid;
     int32_t n_c0;   // leading octaves of period >= 64
-    int32_t prec;   // 0: FP32 matrix cores; 1 / 2: FP16 / BF16 Vandermonde form (periods >= 16)
-    int32_t basis;  // Vandermonde variable: 0 = t, 1 = t - 1/2
 };
 
 // Dyadic ladders, plain FP32 form on the vector ALUs: world-aligned strips of
@@ -105,6 +103,7 @@ struct Fbm2dStripArgs {
     int32_t n_generic;                // octaves 0 .. n_generic-1 have period >= 128
     int32_t o64, o32, o16, o8, o4, o2, o1;  // octave of period 64, 32, ..., 1, or -1
     int32_t lo;                       // min(finest shift, 6): selects the kernel's row loop
+    int32_t basis;                    // precision form: PTG_BASIS_* of the MFMA terms
 };
 
 // 3D dyadic ladders, plain FP32 form on the vector ALUs: world-aligned blocks of
@@ -206,6 +205,10 @@ __host__ __device__ inline int strip3_wave_words(int nodes_total, int keys_total
 hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, int model, bool f16, int grid, int waves, size_t lds_bytes,
                               hipStream_t s);
 int strip_wgs_per_cu(int smooth, int model, bool f16, int lo, int waves, size_t lds_bytes);  // resident WGs per CU
+// The FP16 / BF16 precision form on the strip kernel (prec 1 / 2; cubic cells, FP16 output).
+hipError_t launch_fbm2d_strip_mx(const Fbm2dStripArgs &a, int prec, int grid, int waves, size_t lds_bytes,
+                                 hipStream_t s);
+int strip_mx_wgs_per_cu(int prec, int lo, int waves, size_t lds_bytes);
 hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fbm2d_general_grad(const Fbm2dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fbm3d_strip(const Fbm3dStripArgs &a, int smooth, bool f16, int grid, int waves, size_t lds_bytes,

@@ -62,8 +62,6 @@ static int fbm2d_dyadic(const ptg_params *p, int k, int64_t x0, int64_t y0, int6
     octave_tables(p, freq, a.amp);
     a.octaves = p->octaves;
     a.seed = p->seed;
-    a.prec = p->form == PTG_FORM_MFMA_F16 ? 1 : (p->form == PTG_FORM_MFMA_BF16 ? 2 : 0);
-    a.basis = p->basis;
     int nodes = 0, px = 0, py = 0, tab = 0, wnodes = 0;
     a.tab_first = p->octaves;
     for (int o = 0; o < p->octaves; ++o) {
@@ -131,6 +129,7 @@ int strip_args_2d(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx
     a.octaves = p->octaves;
     a.seed = p->seed;
     a.gw = (float)p->gradient_weight;
+    a.basis = p->basis;
     a.o64 = a.o32 = a.o16 = a.o8 = a.o4 = a.o2 = a.o1 = -1;
     const int smin = k - (p->octaves - 1);
     // the row loop assumes every period from 32 down to the finest is present
@@ -140,7 +139,7 @@ int strip_args_2d(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx
     // periods 2 and 1 (ladders that reach them) are streamed: their node rows are hashed per
     // row segment (8 rows for cubic cells, 16 for quintic) into a block of that height,
     // instead of per strip (65 x 65 nodes at period 1 would hold 34 KB of LDS per wave)
-    const int seg_rows = p->smoothness == 1 ? 8 : 16;
+    const int seg_rows = (p->smoothness == 1 && p->form == PTG_FORM_PLAIN) ? 8 : 16;
     const bool stream = a.lo <= 1;
     for (int o = 0; o < p->octaves; ++o)  // column keys of every octave first, then row keys
         kcol += std::max(SW >> std::min(k - o, 30), 1) + 1;
@@ -420,9 +419,23 @@ int fbm2d_mfma(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t 
     if (!dyadic_shift(p, &k))
         return fail(PTG_EINVAL, "the FP16/BF16 matrix-core form needs base_freq = 2^-k (k <= %d) and lacunarity 2",
                     kDyMaxShift);
-    const int rc = fbm2d_dyadic(p, k, x0, y0, nx, ny, out, pitch, s);
-    if (rc > 0) return fail(PTG_EINVAL, "the lattice footprint exceeds the workgroup's LDS");
-    return rc;
+    Fbm2dStripArgs a;
+    if (strip_args_2d(p, k, x0, y0, nx, ny, out, pitch, &a))
+        return fail(PTG_EINVAL, "the matrix-core form needs a ladder whose coarsest period is >= 32 (or whose finest "
+                                "is >= 64) and a footprint that fits LDS");
+    const int prec = p->form == PTG_FORM_MFMA_F16 ? 1 : 2;
+    const size_t shared_words = (size_t)strip_shared_words(a.nodes_hashed, a.keys_total);
+    const size_t wave_words = (size_t)strip_wave_words(a.nodes_total, a.keys_total, 0);
+    int waves = tune_pick(TuneKey{PTG_TUNE_STRIP_2D, 8 + prec, 1, size_class(nx * ny), a.lo}, kStripWavesPerWg);
+    while (waves > 1 && (shared_words + waves * wave_words) * 4 > kDyMaxLds) --waves;
+    const size_t lds = (shared_words + waves * wave_words) * 4;
+    if (lds > kDyMaxLds) return fail(PTG_EINVAL, "the lattice footprint exceeds the workgroup's LDS");
+    if (tune_dry()) return PTG_OK;
+    const int64_t per_cu = strip_mx_wgs_per_cu(prec, a.lo, waves, lds);
+    const int64_t wgs = (a.strips + waves - 1) / waves;
+    const int grid = (int)std::min<int64_t>(wgs, (int64_t)device_cus() * per_cu);
+    hipError_t e = launch_fbm2d_strip_mx(a, prec, grid, waves, lds, s);
+    return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d precision-form launch");
 }
 
 }  // namespace ptg

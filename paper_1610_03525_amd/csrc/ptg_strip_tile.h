@@ -455,6 +455,11 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
     }
 }
 
+}  // namespace ptg
+
+#include "ptg_strip_mx.h"
+
+namespace ptg {
 
 // Per-octave constants a workgroup stages in LDS once (the strip code reads them from there).
 struct StripShared {
@@ -497,7 +502,7 @@ __device__ __forceinline__ void strip_prologue(const Fbm2dStripArgs &a, StripSha
 
 // One wave's strips of a field: the lane's x-weights of the fixed-period octaves (formed
 // once) and the strip column whose keys its LDS block holds.
-template <int M, typename OutT, int LO, int MD = 0>
+template <int M, typename OutT, int LO, int MD = 0, int PREC = 0>
 struct StripWave {
     static constexpr int D1 = 2 * M + 2;
     static constexpr bool H32 = LO <= 5, H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
@@ -510,6 +515,7 @@ struct StripWave {
     // the column keys stay valid while the wave's strips share a strip column (the stride
     // over strips is often a multiple of the strips per row)
     int64_t keyed_bsx = -1;
+    MxConst<PREC ? PREC : 1> mc;  // precision form (PREC 1 / 2): the MFMA's row operands
 
     __device__ __forceinline__ Fixed fixed(const StripShared &sh, int o) const
     {
@@ -534,6 +540,7 @@ struct StripWave {
           keys(reinterpret_cast<uint32_t *>(nodes_ + a.nodes_total) + (MD == 2 ? a.nodes_total : 0)), lane(lane_)
     {
         f64 = fixed(sh, a.o64);
+        if constexpr (PREC > 0) mc.init(a.basis, lane);
         rc0 = RowCtx{fixed(sh, H32 ? a.o32 : -1), fixed(sh, H16 ? a.o16 : -1), fixed(sh, H8 ? a.o8 : -1),
                      fixed(sh, H4 ? a.o4 : -1),   fixed(sh, H2 ? a.o2 : -1),   fixed(sh, H1 ? a.o1 : -1),
                      a.pitch,
@@ -605,10 +612,16 @@ struct StripWave {
         const int clo = (int)max<int64_t>(0, min<int64_t>(kStripW, a.x0 - X0));
         const int chi = (int)max<int64_t>(0, min<int64_t>(kStripW, xe - X0));
         OutT *row0 = reinterpret_cast<OutT *>(a.out) + (Y0 - a.y0) * a.pitch + (X0 - a.x0);
-        if (rlo == 0 && rhi == kStripH && clo == 0 && chi == kStripW)
+        if constexpr (PREC > 0) {  // cubic cells, gradient model
+            if (rlo == 0 && rhi == kStripH && clo == 0 && chi == kStripW)
+                strip_rows_mx<OutT, LO, PREC, true>(rc0, C, row0, lane, 0, kStripH, false, mc);
+            else
+                strip_rows_mx<OutT, LO, PREC, false>(rc0, C, row0, lane, rlo, rhi, lane >= clo && lane < chi, mc);
+        } else if (rlo == 0 && rhi == kStripH && clo == 0 && chi == kStripW) {
             strip_rows<M, OutT, LO, true, MD>(rc0, C, row0, lane, 0, kStripH, false);
-        else
+        } else {
             strip_rows<M, OutT, LO, false, MD>(rc0, C, row0, lane, rlo, rhi, lane >= clo && lane < chi);
+        }
         __builtin_amdgcn_wave_barrier();  // the next strip rewrites this wave's keys and nodes
     }
 };

@@ -22,7 +22,8 @@ def _clean_table():
     ((512, 512, 512), dict(smoothness=2, octaves=6, base_freq=8 / 512), ("strip_3d", 4)),
     ((100, 100, 40), dict(smoothness=2, octaves=6, base_freq=0.02), ("general_3d", 0)),
     ((40, 6, 5), dict(octaves=2, base_freq=0.5), ("general_3d", 0)),                   # ladder from period 2
-    ((2048, 2048), dict(octaves=4, base_freq=1 / 64, form=1), ("dyadic_2d", 0)),       # FP16 matrix-core form
+    ((2048, 2048), dict(octaves=4, base_freq=1 / 64, form=1, out_dtype=1), ("strip_2d", 4)),  # FP16 matrix-core form
+    ((2048, 2048), dict(octaves=4, base_freq=1 / 64, form=2, out_dtype=1, basis=2), ("strip_2d", 4)),
 ])
 def test_query_reports_the_kernel_class(shape, kw, expect):
     assert ptg.tune_query(shape, **kw) == expect
@@ -49,7 +50,7 @@ def test_set_query_reset_roundtrip():
     ((256, 300), dict(octaves=4, base_freq=0.013), 4),            # a waves count, not a tile height
     ((8192, 8192), dict(octaves=8, base_freq=16 / 8192), 3),      # not a waves count
     ((100, 100, 40), dict(smoothness=2, octaves=6, base_freq=0.02), 64),  # general 3D: nothing to tune
-    ((2048, 2048), dict(octaves=4, base_freq=1 / 64, form=1), 2),
+    ((2048, 2048), dict(octaves=4, base_freq=1 / 64, form=1, out_dtype=1), 3),
 ])
 def test_set_rejects_shapes_that_are_not_candidates(shape, kw, value):
     with pytest.raises(ptg.PtgError):
