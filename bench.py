@@ -15,10 +15,13 @@ p50/p99 latency at 0.5, 0.8 and 0.95 of the plain path's capacity.
 """
 import argparse
 import ctypes
+import faulthandler
 import json
 import os
 import sys
 import time
+
+faulthandler.enable()  # a crash in native code prints the Python stack of the phase it hit
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -31,6 +34,11 @@ LACUNARITY = 2.0
 SEED = 1
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fbm2d_strip_2d_8192x8192_8oct_c1.traffic.json")
+
+
+def progress(msg):
+    """One line per finished phase on stderr (the JSON record alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def measured_traffic():
@@ -165,13 +173,18 @@ def main():
         print(f"field out of bounds: max|H| = {amax}", file=sys.stderr)
         sys.exit(1)
 
+    progress(f"headline field: {k_avg_ms * 1e3:.1f} us per launch (back to back), {ms_per_step * 1e3:.1f} us per step")
     others = None if args.no_other_configs else other_configs(torch, ptg, stream)
+    progress("other configurations done")
     stages = None if args.no_other_configs else stage_kernels(torch, ptg, stream)
+    progress("stage kernels done")
     serving = run_serving(args.serve_requests) if args.serve_requests > 0 else None
+    progress("serving done")
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_seconds)
+        progress("oracle timing done")
 
     rec = {
         "metric": "octave-samples/s at 8192^2 8-octave 2D",
@@ -254,6 +267,7 @@ def other_configs(torch, ptg, stream):
                              "kernel": "k_fbm3d_strip", "ms": ms, "octave_samples_s": n3 * 6 / (ms * 1e-3),
                              "hbm_frac": n3 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     del vol
+    progress(f"3D 512^3 C2: {ms * 1e3:.1f} us")
     # 16384^2, 10 octaves, base lattice 32^2, offset (2^24 - 3) * 512, -(2^24 - 5) * 512
     n, f0 = 16384, 32 / 16384
     x0, y0 = (2 ** 24 - 3) * 512, -(2 ** 24 - 5) * 512
@@ -267,6 +281,7 @@ def other_configs(torch, ptg, stream):
                        out_dtype=ptg.PTG_F16 if dt == torch.float16 else ptg.PTG_F32)
         ms = _time_launches(torch, stream, lambda: ptg.fbm_2d_raw(q, x0, y0, n, n, out.data_ptr(), n, sh), 5)
         name = f"{form}/{basis}" if form != "plain" else ("plain_fp32" if dt == torch.float32 else "plain_fp16_out")
+        progress(f"16384^2 10-octave {name}: {ms * 1e3:.1f} us")
         forms[name] = {
             "ms": ms, "octave_samples_s": n * n * 10 / (ms * 1e-3),
             "hbm_frac": n * n * out.element_size() / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
@@ -284,6 +299,7 @@ def other_configs(torch, ptg, stream):
         ms = _time_launches(torch, stream, lambda: ptg.fbm_2d_raw(q, 0, 0, 8192, 8192, zf.data_ptr(), 8192, sh), 10)
         zg[name] = {"ms": ms, "octave_samples_s": 8192 * 8192 * 8 / (ms * 1e-3),
                     "hbm_frac": 8192 * 8192 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    progress("zero-gradient model done")
     res["2d_8192_8oct_zero_gradient"] = {
         "workload": "zero-gradient D2M1N3 (random node heights, zero corner gradients), 8192^2, 8 octaves, "
                     "persistence 0.5, FP32, seed 1",
@@ -302,6 +318,7 @@ def other_configs(torch, ptg, stream):
                                           "FP32, seed 1 (general kernel)",
                               "ms": ms, "octave_samples_s": 8192 * 8192 * 8 / (ms * 1e-3),
                               "hbm_frac": 8192 * 8192 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    progress("height-gradient and septic done")
     gx, gy = torch.empty_like(zf), torch.empty_like(zf)
     q = ptg.params(smoothness=1, octaves=8, base_freq=16 / 8192, seed=1)
     ms = _time_launches(torch, stream, lambda: ptg.lib().ptg_fbm_2d_grad(
@@ -340,6 +357,7 @@ def stage_kernels(torch, ptg, stream):
             if rc != 0:
                 raise RuntimeError(f"{name}: status {rc}: {lib.ptg_last_error().decode()}")
         ms = _time_launches(torch, stream, fn, n)
+        progress(f"stage kernel {name}: {ms * 1e3:.1f} us")
         gbs = (wbytes + rbytes) / (ms * 1e-3) / 1e9
         res[name] = {"workload": workload, "kernel": kernel, "us": ms * 1e3, "bytes_written": wbytes,
                      "bytes_read": rbytes, "GB_s": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
@@ -467,6 +485,7 @@ def run_serving(n):
         if rc != 0:
             raise RuntimeError(f"plain stream failed ({rc}): {ptg.last_error()}")
         out = summary(arr, done)
+        progress(f"plain stream (mode {mode}): {out}")
         out["launch_units"] = int(st[0])
         if mode == 1:
             out["graphs_instantiated"] = int(st[1])
@@ -481,6 +500,7 @@ def run_serving(n):
                 raise RuntimeError(f"served stream failed ({rc}): {ptg.last_error()}")
             st = srv.stats()
         out = summary(arr, done)
+        progress(f"served stream (budget {budget >> 20} MiB): {out}")
         out["admit_wait_p99_ms"] = round(float(np.percentile((adm - arr)[n // 10:] / 1e6, 99)), 4)
         out["kernel_launches"] = st["kernel_launches"]
         out["bytes_peak"] = st["bytes_peak"]
@@ -578,6 +598,7 @@ def run_lattice_cache(lg, ptg, n):
             warm["lat_hits"] -= res["cache_cold"]["lat_hits"]
             warm["lat_misses"] -= res["cache_cold"]["lat_misses"]
             res["cache_warm"] = warm
+        progress(f"lattice cache, {name} stream done")
         res["warm_over_hash"] = round(res["cache_warm"]["requests_s"] / res["hash"]["requests_s"], 3)
         out[name] = res
     return out

@@ -277,10 +277,11 @@ PTG_API void ptg_tune_reset(void);
  * A batch collects dense-field calls -- the one kernel launch each ptg_fbm_2d / ptg_fbm_3d
  * call makes, with its arguments -- and launches them together as the kernel nodes of one
  * HIP graph (the plain path of the tile stream, or a terrain engine's per-frame tile set).
- * The graph of a batch shape (the same kernels, grids, workgroup sizes and LDS sizes in the
- * same order) is instantiated once; a later batch of that shape updates the instance's
- * kernel-node arguments in place (hipGraphExecKernelNodeSetParams) and relaunches it, e.g.
- * the same tiles at new origins, seeds or output buffers.  Up to 4 instances of a shape are
+ * The graph of a batch shape (the same kernels with the same workgroup sizes in the same
+ * order) is instantiated once; a later batch of that shape updates the instance's kernel
+ * nodes in place (grid, dynamic LDS size and arguments, hipGraphExecKernelNodeSetParams) and
+ * relaunches it, e.g. tiles of other sizes at new origins, seeds or output buffers; if the
+ * runtime refuses an update the instance is instantiated again.  Up to 4 instances of a shape are
  * kept so that no instance is updated while a launch of it may still run; up to 64 shapes
  * per batch object are cached, the least recently used dropped first.  The calls of one
  * batch may run concurrently: their outputs must not overlap.  A batch object is used by

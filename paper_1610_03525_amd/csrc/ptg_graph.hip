@@ -40,16 +40,17 @@ struct Shape {
 
 using Key = std::vector<uint64_t>;
 
+// A batch's shape is its sequence of kernels (function, workgroup size, argument bytes); the
+// grid, the dynamic LDS size and the arguments of a node are updated in place, so batches of
+// the same kernels over fields of other sizes or origins reuse the instance.
 Key shape_key(const std::vector<LaunchRec> &recs)
 {
     Key k;
-    k.reserve(recs.size() * 5);
+    k.reserve(recs.size() * 3);
     for (const LaunchRec &r : recs) {
         k.push_back(reinterpret_cast<uint64_t>(r.func));
-        k.push_back(((uint64_t)r.grid.x << 32) | r.grid.y);
-        k.push_back(((uint64_t)r.grid.z << 32) | r.block.x);
-        k.push_back(((uint64_t)r.block.y << 32) | r.block.z);
-        k.push_back(((uint64_t)r.lds << 32) | r.arg_bytes);
+        k.push_back(((uint64_t)r.block.x << 32) | ((uint64_t)r.block.y << 16) | r.block.z);
+        k.push_back(r.arg_bytes);
     }
     return k;
 }
@@ -218,16 +219,24 @@ int ptg_batch_launch(ptg_batch *b, void *stream)
         }
     }
     if (!fresh) {
-        for (size_t i = 0; i < b->recs.size(); ++i) {
+        hipError_t e = hipSuccess;
+        for (size_t i = 0; i < b->recs.size() && e == hipSuccess; ++i) {
             void *argv[1];
             const hipKernelNodeParams kp = node_params(b->recs[i], argv);
-            const hipError_t e = hipGraphExecKernelNodeSetParams(use->ex, use->nodes[i], &kp);
-            if (e != hipSuccess) {
-                b->recs.clear();
-                return hip_fail(e, "hipGraphExecKernelNodeSetParams");
-            }
+            e = hipGraphExecKernelNodeSetParams(use->ex, use->nodes[i], &kp);
         }
-        b->st.updates++;
+        if (e == hipSuccess) {
+            b->st.updates++;
+        } else {  // the runtime refused the update: instantiate this instance again
+            (void)hipGetLastError();
+            free_inst(*use);  // idle: its last launch has finished
+            const int rc = new_inst(b->recs, *use);
+            if (rc != PTG_OK) {
+                b->recs.clear();
+                return rc;
+            }
+            b->st.instantiations++;
+        }
     }
     hipError_t e = hipGraphLaunch(use->ex, s);
     if (e == hipSuccess) e = hipEventRecord(use->ev, s);

@@ -82,12 +82,12 @@ def test_fbm3d_512_6oct_c2_every_sample():
 # Precision form on the 16384^2 field: bounds on max|err| / A and RMS / A, twice the values
 # measured over the whole field on MI355X (profiles/precision_form_errors.md).
 PREC_BOUNDS = {
-    ("mfma_f16", "monomial"): (2e-3, 5e-4),
-    ("mfma_f16", "centred"): (2e-3, 5e-4),
-    ("mfma_f16", "hermite"): (2e-3, 5e-4),
-    ("mfma_bf16", "monomial"): (1.5e-2, 3.75e-3),
-    ("mfma_bf16", "centred"): (1.5e-2, 3.75e-3),
-    ("mfma_bf16", "hermite"): (1.5e-2, 3.75e-3),
+    ("mfma_f16", "monomial"): (2.1e-4, 3.0e-5),   # measured 1.03e-4, 1.48e-5
+    ("mfma_f16", "centred"): (1.4e-4, 2.9e-5),    # measured 6.98e-5, 1.44e-5
+    ("mfma_f16", "hermite"): (1.4e-4, 2.9e-5),    # measured 7.02e-5, 1.44e-5
+    ("mfma_bf16", "monomial"): (1.2e-3, 7.8e-5),  # measured 5.89e-4, 3.88e-5
+    ("mfma_bf16", "centred"): (2.7e-4, 3.2e-5),   # measured 1.35e-4, 1.58e-5
+    ("mfma_bf16", "hermite"): (2.6e-4, 3.2e-5),   # measured 1.27e-4, 1.59e-5
 }
 X4, Y4 = (2 ** 24 - 3) * 512, -(2 ** 24 - 5) * 512
 
@@ -98,7 +98,9 @@ def test_fbm2d_16384_10oct_precision_forms_every_sample():
     base = dict(smoothness=1, octaves=octs, persistence=0.5, lacunarity=2.0, base_freq=f0, seed=1)
     plain = torch.empty((n, n), dtype=torch.float32, device=DEV)
     ptg.fbm_2d(plain, x0=X4, y0=Y4, **base)
-    forms = {}
+    # the plain FP32 arithmetic with FP16 output: the output rounding floor of every FP16 form
+    forms = {("plain", "fp16_out"): torch.empty((n, n), dtype=torch.float16, device=DEV)}
+    ptg.fbm_2d(forms[("plain", "fp16_out")], x0=X4, y0=Y4, **base)
     for key in PREC_BOUNDS:
         t = torch.empty((n, n), dtype=torch.float16, device=DEV)
         ptg.fbm_2d(t, x0=X4, y0=Y4, form=key[0], basis=key[1], **base)
@@ -126,6 +128,8 @@ def test_fbm2d_16384_10oct_precision_forms_every_sample():
         print(f"[16384^2] {form}/{basis}: max/A {mx / A:.3e}  rms/A {rms / A:.3e}", flush=True)
     _record("fullfield_2d_16384_precision.json", res)
     assert worst_plain <= 1e-5 * A, worst_plain
+    # FP16 output: round to nearest even, relative error <= 2^-11 of |H| <= A / 2
+    assert res["plain/fp16_out"]["max_over_A"] <= 2.0 ** -11 / 2 + 1e-5, res["plain/fp16_out"]
     for key, (bmax, brms) in PREC_BOUNDS.items():
         assert res[f"{key[0]}/{key[1]}"]["max_over_A"] <= bmax, (key, res[f"{key[0]}/{key[1]}"])
         assert res[f"{key[0]}/{key[1]}"]["rms_over_A"] <= brms, (key, res[f"{key[0]}/{key[1]}"])
