@@ -604,27 +604,76 @@ def run_lattice_cache(lg, ptg, n):
     return out
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(fn, unit_samples, octaves, total_units, budget_s):
+    """Call fn(i) for units i = 0, 1, ... (row bands / z-slabs) until the budget is spent or
+    the workload is done; octave-samples/s and what was covered."""
+    done = 0
+    t0 = time.perf_counter()
+    while done < total_units and (done == 0 or time.perf_counter() - t0 < budget_s):
+        fn(done)
+        done += 1
+    dt = time.perf_counter() - t0
+    return done * unit_samples * octaves / dt, done, dt
+
+
 def cpu_baseline(budget_s):
-    """FP64 oracle on the host cores: row bands of the same field until the time budget
-    is spent (or the field is done); rate in octave-samples/s."""
+    """FP64 oracle on the host cores: row bands of the headline field until the time budget
+    is spent (rate in octave-samples/s = the reported value), then every configuration of
+    the benchmark on all cores and on one core, each over a bounded sample (whole field for
+    the 256^2 one, row bands / z-slabs of the others)."""
     import numpy as np  # noqa: F401
 
     import oracle as O
 
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     band = 64
-    rows = 0
-    t0 = time.perf_counter()
-    while rows < NY and time.perf_counter() - t0 < budget_s:
-        O.fbm_2d(1, OCTAVES, PERSISTENCE, LACUNARITY, BASE_FREQ, SEED, 0, rows, NX, band, nthreads=threads)
-        rows += band
-    dt = time.perf_counter() - t0
+    rate, bands, dt = _oracle_rate(
+        lambda i: O.fbm_2d(1, OCTAVES, PERSISTENCE, LACUNARITY, BASE_FREQ, SEED, 0, i * band, NX, band,
+                           nthreads=threads), NX * band, OCTAVES, NY // band, budget_s)
+    rows = bands * band
+    # every configuration, all cores and one core
+    x4, y4 = (2 ** 24 - 3) * 512, -(2 ** 24 - 5) * 512
+    cfgs = {
+        "2d_256_4oct_c1": (lambda i, t: O.fbm_2d(1, 4, 0.5, 2.0, 8 / 256, 1, 0, 0, 256, 256, nthreads=t),
+                           256 * 256, 4, 400, "the whole 256^2 field, repeated"),
+        "2d_8192_8oct_c1": (lambda i, t: O.fbm_2d(1, 8, 0.5, 2.0, 16 / 8192, 1, 0, 16 * i, 8192, 16, nthreads=t),
+                            8192 * 16, 8, 512, "16-row bands of the 8192^2 field"),
+        "3d_512_6oct_c2": (lambda i, t: O.fbm_3d(2, 6, 0.5, 2.0, 8 / 512, 1, 0, 0, i, 512, 512, 1, nthreads=t),
+                           512 * 512, 6, 512, "z-slices of the 512^3 volume"),
+        "2d_16384_10oct_c1_offset": (lambda i, t: O.fbm_2d(1, 10, 0.5, 2.0, 32 / 16384, 1, x4, y4 + 8 * i, 16384, 8,
+                                                           nthreads=t),
+                                     16384 * 8, 10, 2048, "8-row bands of the 16384^2 field at the 2^24-cell offset"),
+    }
+    per = {}
+    for name, (fn, unit, octs, total, what) in cfgs.items():
+        entry = {"sample": what}
+        for label, t, b in (("all_cores", threads, 2.0), ("one_core", 1, 1.0)):
+            r, n, d = _oracle_rate(lambda i, t=t: fn(i, t), unit, octs, total, b)
+            entry[label] = {"octave_samples_s": r, "units": n, "seconds": round(d, 2)}
+        entry["core_speedup"] = entry["all_cores"]["octave_samples_s"] / entry["one_core"]["octave_samples_s"]
+        per[name] = entry
+        progress(f"oracle {name}: {entry['all_cores']['octave_samples_s']:.3e} octave-samples/s on {threads} cores, "
+                 f"{entry['one_core']['octave_samples_s']:.3e} on one")
     return {
-        "value": rows * NX * OCTAVES / dt,
+        "value": rate,
         "unit": "octave-samples/s",
         "cores": threads,
         "kind": "oracle",
         "sample": f"rows 0..{rows - 1} of the 8192x8192 8-octave field ({rows * NX} samples, {dt:.1f} s wall)",
+        "nproc": os.cpu_count(),
+        "cpu_model": _cpu_model(),
+        "per_config": per,
     }
 
 
