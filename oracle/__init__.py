@@ -83,6 +83,14 @@ def lib():
     L.orc_hg_cell.argtypes = [_i32, _pd, _pd, _f64, _f64, _f64]
     L.orc_hg_cell.restype = _f64
     L.orc_hg_fbm_2d.argtypes = [_i32, _i32, _f64, _f64, _f64, _f64, _u32, _i64, _i64, _i64, _i64, _pd, _i32]
+    L.orc_height3.argtypes = [_u32]
+    L.orc_height3.restype = _f64
+    L.orc_hg_cell_3d.argtypes = [_i32, _pd, _pd, _f64, _f64, _f64, _f64]
+    L.orc_hg_cell_3d.restype = _f64
+    L.orc_hg_fbm_3d.argtypes = [_i32, _i32, _f64, _f64, _f64, _f64, _u32, _i64, _i64, _i64, _i64, _i64, _i64, _pd,
+                                _i32]
+    L.orc_hg_fbm_points_3d.argtypes = [_i32, _i32, _f64, _f64, _f64, _f64, _u32, _pi64, _pi64, _pi64, _i64, _pd,
+                                       _i32]
     L.orc_hg_fbm_2d.restype = _i32
     L.orc_hg_fbm_points_2d.argtypes = [_i32, _i32, _f64, _f64, _f64, _f64, _u32, _pi64, _pi64, _i64, _pd, _i32]
     L.orc_hg_fbm_points_2d.restype = _i32
@@ -320,6 +328,34 @@ def hg_fbm_points_2d(smooth, octaves, pers, lac, f0, w, seed, X, Y, nthreads=0) 
     out = np.empty(X.shape[0], dtype=np.float64)
     _chk(lib().orc_hg_fbm_points_2d(smooth, octaves, pers, lac, f0, w, seed & 0xFFFFFFFF, _ip(X), _ip(Y), X.shape[0],
                                     _dp(out), nthreads))
+    return out
+
+
+def height3(key: int) -> float:
+    """Node height of the 3D height-and-gradient model (the key's third word)."""
+    return float(lib().orc_height3(key & 0xFFFFFFFF))
+
+
+def hg_cell_3d(smooth: int, h, grad, w: float, x: float, y: float, z: float) -> float:
+    hh = np.ascontiguousarray(h, dtype=np.float64).reshape(8)
+    g = np.ascontiguousarray(grad, dtype=np.float64).reshape(24)
+    return float(lib().orc_hg_cell_3d(smooth, _dp(hh), _dp(g), w, x, y, z))
+
+
+def hg_fbm_3d(smooth, octaves, pers, lac, f0, w, seed, x0, y0, z0, nx, ny, nz, nthreads=0) -> np.ndarray:
+    out = np.empty((nz, ny, nx), dtype=np.float64)
+    _chk(lib().orc_hg_fbm_3d(smooth, octaves, pers, lac, f0, w, seed & 0xFFFFFFFF, x0, y0, z0, nx, ny, nz, _dp(out),
+                             nthreads))
+    return out
+
+
+def hg_fbm_points_3d(smooth, octaves, pers, lac, f0, w, seed, X, Y, Z, nthreads=0) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.int64)
+    Y = np.ascontiguousarray(Y, dtype=np.int64)
+    Z = np.ascontiguousarray(Z, dtype=np.int64)
+    out = np.empty(X.shape[0], dtype=np.float64)
+    _chk(lib().orc_hg_fbm_points_3d(smooth, octaves, pers, lac, f0, w, seed & 0xFFFFFFFF, _ip(X), _ip(Y), _ip(Z),
+                                    X.shape[0], _dp(out), nthreads))
     return out
 
 

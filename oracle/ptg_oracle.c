@@ -721,6 +721,89 @@ int orc_hg_fbm_points_2d(int32_t smooth, int32_t octaves, double pers, double la
     return ORC_OK;
 }
 
+/* 3D (D3M1N3 / D3M2N5 with node heights, Sec. 3.4 with Sec. 3.1's heights and Sec. 4's
+ * w).  The 3D gradient takes the first word's top bits (polar coordinate) and the second
+ * word's (azimuth), so the node height comes from a third word: the second-word map
+ * applied once more to the second word. */
+double orc_height3(uint32_t key)
+{
+    return orc_height2(orc_key3_second(orc_key3_second(key)));
+}
+
+/* 3D tensor Hermite cell with corner heights h[c] and corner gradients w * grad[3c..3c+2]
+ * (c = cx + 2 cy + 4 cz; every other mixed derivative zero): the trilinear-in-B0 height
+ * term sum_c h_c B0_cx(x) B0_cy(y) B0_cz(z) plus w times the zero-height cell. */
+double orc_hg_cell_3d(int32_t smooth, const double *h, const double *grad, double w, double tx, double ty,
+                      double tz)
+{
+    double b0[3][2], b1[3][2];
+    orc_basis(smooth, tx, b0[0], b1[0]);
+    orc_basis(smooth, ty, b0[1], b1[1]);
+    orc_basis(smooth, tz, b0[2], b1[2]);
+    double v = 0.0;
+    for (int cz = 0; cz < 2; ++cz)
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) v += h[cx + 2 * cy + 4 * cz] * b0[0][cx] * b0[1][cy] * b0[2][cz];
+    return v + w * orc_cell_3d(smooth, grad, tx, ty, tz);
+}
+
+static double orc_hg_sample_3d(int32_t smooth, int32_t octaves, const double *freq, const double *amp, double w,
+                               uint32_t seed, int64_t X, int64_t Y, int64_t Z)
+{
+    double H = 0.0;
+    for (int32_t o = 0; o < octaves; ++o) {
+        int64_t cx, cy, cz;
+        double tx, ty, tz, h[8], grad[24];
+        orc_coord(X, freq[o], &cx, &tx);
+        orc_coord(Y, freq[o], &cy, &ty);
+        orc_coord(Z, freq[o], &cz, &tz);
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    const int c = dx + 2 * dy + 4 * dz;
+                    const uint32_t key = orc_key3(cx + dx, cy + dy, cz + dz, o, seed);
+                    h[c] = orc_height3(key);
+                    orc_grad3(key, &grad[3 * c]);
+                }
+        H += amp[o] * orc_hg_cell_3d(smooth, h, grad, w, tx, ty, tz);
+    }
+    return H;
+}
+
+/* Height-and-gradient fBm over a dense [nz][ny][nx] volume; w = gradient weight. */
+int orc_hg_fbm_3d(int32_t smooth, int32_t octaves, double pers, double lac, double f0, double w, uint32_t seed,
+                  int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz, double *out,
+                  int32_t nthreads)
+{
+    if (orc_check(smooth, octaves, f0, lac, pers) != ORC_OK || !isfinite(w) || nx < 0 || ny < 0 || nz < 0 || !out)
+        return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i)
+                out[(k * ny + j) * nx + i] = orc_hg_sample_3d(smooth, octaves, freq, amp, w, seed, x0 + i, y0 + j,
+                                                               z0 + k);
+    return ORC_OK;
+}
+
+int orc_hg_fbm_points_3d(int32_t smooth, int32_t octaves, double pers, double lac, double f0, double w,
+                         uint32_t seed, const int64_t *X, const int64_t *Y, const int64_t *Z, int64_t n, double *out,
+                         int32_t nthreads)
+{
+    if (orc_check(smooth, octaves, f0, lac, pers) != ORC_OK || !isfinite(w) || n < 0 || !X || !Y || !Z || !out)
+        return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q)
+        out[q] = orc_hg_sample_3d(smooth, octaves, freq, amp, w, seed, X[q], Y[q], Z[q]);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Analytic gradient of the height field (the gradient maps of Sec. 5.1)     */
 /* ------------------------------------------------------------------------- */
