@@ -15,10 +15,10 @@
  *     whose value is 0 at each corner, whose gradient equals the corner's lattice
  *     gradient, and whose other mixed derivatives h^d, 0 <= d_k <= M, are 0.  M = 1 gives
  *     C1 cubic cells (D2M1N3 / D3M1N3 with zero twist), M = 2 C2 quintic cells, M = 3
- *     C3 septic cells.  Two more 2D cell models (ptg_params.model): the zero-gradient
- *     model, whose nodes carry heights and zero gradients (Sec. 3.3), and the
- *     height-and-gradient model, whose nodes carry both (Sec. 3.1; gradient weight w,
- *     Sec. 4).
+ *     C3 septic cells.  Two more cell models (ptg_params.model): the zero-gradient
+ *     model (2D), whose nodes carry heights and zero gradients (Sec. 3.3), and the
+ *     height-and-gradient model (2D and 3D), whose nodes carry both (Sec. 3.1; D3M1N3 of
+ *     Sec. 3.4 with heights; gradient weight w, Sec. 4).
  *   - Optional output: the analytic gradient of the field (ptg_fbm_2d_grad, Sec. 5.1).
  *   - Octave o = 0..N-1: frequency f_o = base_freq * lacunarity^o and amplitude
  *     a_o = persistence^o, each by repeated FP64 multiplication; no normalisation.
@@ -108,10 +108,12 @@ extern "C" {
                                    /* nodes only.  2D, smoothness 1, plain form, fields only */
                                    /* (not served)                                          */
 #define PTG_MODEL_HEIGHT_GRADIENT 2 /* tensor Hermite cells with a random height per node    */
-                                   /* (uniform on [-1, 1) from the node's second hash word) */
-                                   /* and the lattice gradient times gradient_weight w      */
-                                   /* (Sec. 3.1 heights, Sec. 4 w); C1 / C2 across faces.   */
-                                   /* 2D, plain form, fields only (not served)              */
+                                   /* (uniform on [-1, 1): in 2D from the node's second     */
+                                   /* hash word, in 3D from its third, fmix32(second3 ^     */
+                                   /* 0x165667B1)) and the lattice gradient times           */
+                                   /* gradient_weight w (Sec. 3.1 heights, Sec. 3.4, Sec. 4 */
+                                   /* w); C1 / C2 across faces.  2D and 3D, plain form,     */
+                                   /* fields only (not served)                              */
 
 /* Problem parameters (Sec. 2.2 DdMmNn naming: dim = d, smoothness = m, n = 2m+1;
  * Sec. 4: octaves, persistence, lacunarity). */

@@ -56,8 +56,8 @@ int validate_params(const ptg_params *p, int dim)
         return fail(PTG_EINVAL, "unknown path %d", p->path);
     if (p->model != PTG_MODEL_GRADIENT && p->model != PTG_MODEL_ZERO_GRADIENT && p->model != PTG_MODEL_HEIGHT_GRADIENT)
         return fail(PTG_EINVAL, "unknown model %d", p->model);
-    if (p->model == PTG_MODEL_HEIGHT_GRADIENT && (dim != 2 || p->form != PTG_FORM_PLAIN))
-        return fail(PTG_EINVAL, "the height-and-gradient model is 2D, plain form");
+    if (p->model == PTG_MODEL_HEIGHT_GRADIENT && p->form != PTG_FORM_PLAIN)
+        return fail(PTG_EINVAL, "the height-and-gradient model is plain form");
     if (p->model == PTG_MODEL_HEIGHT_GRADIENT && !std::isfinite(p->gradient_weight))
         return fail(PTG_EINVAL, "gradient_weight must be finite");
     if (p->model == PTG_MODEL_ZERO_GRADIENT && (dim != 2 || p->smoothness != 1 || p->form != PTG_FORM_PLAIN))

@@ -63,17 +63,23 @@ __device__ __forceinline__ float height2(uint32_t key) { return (float)(key >> 8
 __device__ __forceinline__ float height2_second(uint32_t key) { return height2(key3_second(key)); }
 
 // 3D unit gradient: z = 1 - (2m+1)/2^24 (exact in FP32), azimuth from the second word,
-// radius sqrt((1-z)(1+z)).
-__device__ __forceinline__ float3 grad3(uint32_t key)
+// radius sqrt((1-z)(1+z)) (the hardware square root, within 1 ulp).
+__device__ __forceinline__ float3 grad3_of(uint32_t key, uint32_t second)
 {
     const uint32_t m1 = key >> 8;
-    const uint32_t m2 = key3_second(key) >> 8;
+    const uint32_t m2 = second >> 8;
     const float k = (float)(2u * m1 + 1u) * (1.0f / 16777216.0f);
     const float z = 1.0f - k;
-    const float r = __builtin_sqrtf(fmaxf(k * (2.0f - k), 0.0f));
+    const float r = __builtin_amdgcn_sqrtf(fmaxf(k * (2.0f - k), 0.0f));
     const float turns = (float)m2 * (1.0f / 16777216.0f);
     return make_float3(r * __builtin_amdgcn_cosf(turns), r * __builtin_amdgcn_sinf(turns), z);
 }
+
+__device__ __forceinline__ float3 grad3(uint32_t key) { return grad3_of(key, key3_second(key)); }
+
+// Node height of the 3D height-and-gradient model: the height map on the key's third word
+// (the second-word map applied to the second word; the first two give the gradient).
+__device__ __forceinline__ float height3_of_second(uint32_t second) { return height2(key3_second(second)); }
 
 // ---------------------------------------------------------------------------------
 // Coordinate step (a1): u = (X + 1/2) * f in FP64, cell = floor(u), t = u - cell.

@@ -1,5 +1,6 @@
 // ptg_fbm_general.hip -- K3 launches for any octave parameters (the tile functions are in
 // ptg_general_tile.h, shared with the persistent serving kernel).
+#include "ptg.h"
 #include "ptg_general_tile.h"
 
 namespace ptg {
@@ -19,11 +20,11 @@ __global__ __launch_bounds__(256) void k_fbm2d_general_grad(const Fbm2dArgs a)
     fbm2d_general_tile<M, OutT, 64, MD, true>(a, blockIdx.x, lds4);
 }
 
-template <int M, typename OutT>
+template <int M, typename OutT, int MD = 0>
 __global__ __launch_bounds__(256) void k_fbm3d_general(const Fbm3dArgs a)
 {
     extern __shared__ float4 lds4[];
-    fbm3d_general_tile<M, OutT>(a, blockIdx.x, lds4);
+    fbm3d_general_tile<M, OutT, MD>(a, blockIdx.x, lds4);
 }
 
 template <typename Args>
@@ -96,18 +97,25 @@ hipError_t launch_fbm2d_general_grad(const Fbm2dArgs &a, int smooth, bool f16, s
     return f16 ? launch_grad_t<__half>(a, smooth, grid, lds, s) : launch_grad_t<float>(a, smooth, grid, lds, s);
 }
 
+template <int MD>
+static hipError_t launch_3g(const Fbm3dArgs &a, int smooth, bool f16, dim3 grid, size_t lds, hipStream_t s)
+{
+    if (smooth == 1)
+        return f16 ? launch_dyn(k_fbm3d_general<1, __half, MD>, grid, lds, s, a)
+                   : launch_dyn(k_fbm3d_general<1, float, MD>, grid, lds, s, a);
+    if (smooth == 3)
+        return f16 ? launch_dyn(k_fbm3d_general<3, __half, MD>, grid, lds, s, a)
+                   : launch_dyn(k_fbm3d_general<3, float, MD>, grid, lds, s, a);
+    return f16 ? launch_dyn(k_fbm3d_general<2, __half, MD>, grid, lds, s, a)
+               : launch_dyn(k_fbm3d_general<2, float, MD>, grid, lds, s, a);
+}
+
 hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t lds, hipStream_t s)
 {
     const int64_t tiles = (int64_t)a.tiles_x * a.tiles_y * ((a.nz + kTile3Z - 1) / kTile3Z);
     dim3 grid((unsigned)tiles);
-    if (smooth == 1)
-        return f16 ? launch_dyn(k_fbm3d_general<1, __half>, grid, lds, s, a)
-                   : launch_dyn(k_fbm3d_general<1, float>, grid, lds, s, a);
-    if (smooth == 3)
-        return f16 ? launch_dyn(k_fbm3d_general<3, __half>, grid, lds, s, a)
-                   : launch_dyn(k_fbm3d_general<3, float>, grid, lds, s, a);
-    return f16 ? launch_dyn(k_fbm3d_general<2, __half>, grid, lds, s, a)
-               : launch_dyn(k_fbm3d_general<2, float>, grid, lds, s, a);
+    return a.model == PTG_MODEL_HEIGHT_GRADIENT ? launch_3g<2>(a, smooth, f16, grid, lds, s)
+                                                : launch_3g<0>(a, smooth, f16, grid, lds, s);
 }
 
 }  // namespace ptg

@@ -279,7 +279,9 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
 // then along z, leaving the 1D Hermite form in y evaluated per sample.
 // LDS: y table float4[8] | z table float4[8] | g{x,y,z}[cap] | kx[capx] | kzy[capy*capz]
 // ---------------------------------------------------------------------------------
-template <int M, typename OutT>
+// MD = 2: node heights (third key word) and w-weighted gradients; the x collapse adds the
+// heights' value term to each corner's a.
+template <int M, typename OutT, int MD = 0>
 __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t bid, float4 *lds4)
 {
     constexpr int TX = kTile3X, TY = kTile3Y, TZ = kTile3Z;
@@ -291,7 +293,8 @@ __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t b
     float *gxs = reinterpret_cast<float *>(lds4 + TY + TZ);
     float *gys = gxs + cap;
     float *gzs = gys + cap;
-    uint32_t *kx = reinterpret_cast<uint32_t *>(gzs + cap);
+    float *hs = gzs + cap;  // node heights (MD = 2)
+    uint32_t *kx = reinterpret_cast<uint32_t *>(gzs + (MD == 2 ? 2 : 1) * cap);
     uint32_t *kzy = kx + a.capx;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -342,10 +345,13 @@ __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t b
         const int plane = nnx * nny;
         for (int q = tid; q < plane * nnz; q += 256) {
             const int row = q / nnx, i = q - row * nnx;  // row = k * nny + j
-            const float3 g = grad3(key_combine(kzy[row], kx[i]));
-            gxs[q] = g.x * amp;
-            gys[q] = g.y * amp;
-            gzs[q] = g.z * amp;
+            const uint32_t key = key_combine(kzy[row], kx[i]), second = key3_second(key);
+            const float3 g = grad3_of(key, second);
+            const float gsc = MD == 2 ? amp * a.gw : amp;
+            gxs[q] = g.x * gsc;
+            gys[q] = g.y * gsc;
+            gzs[q] = g.z * gsc;
+            if (MD == 2) hs[q] = height3_of_second(second) * amp;
         }
         const Coord cc = coord_step(X, f);
         const int lcx = (int)(cc.cell - cxf);
@@ -374,6 +380,7 @@ __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t b
                         for (int cy = 0; cy < 2; ++cy) {
                             const int q = ((lcz + cz) * nny + (lcy + cy)) * nnx + lcx;
                             ca[cy][cz] = gxs[q] * b10x + gxs[q + 1] * b11x;
+                            if (MD == 2) ca[cy][cz] += hs[q] + sx * (hs[q + 1] - hs[q]);
                             cb[cy][cz] = gys[q] + sx * (gys[q + 1] - gys[q]);
                             cc2[cy][cz] = gzs[q] + sx * (gzs[q + 1] - gzs[q]);
                         }

@@ -39,6 +39,8 @@ struct Fbm3dArgs {
     uint32_t seed;
     int32_t capx, capy, capz;
     int32_t tiles_x, tiles_y;
+    int32_t model;  // PTG_MODEL_GRADIENT or PTG_MODEL_HEIGHT_GRADIENT
+    float gw;       // gradient weight (height-and-gradient model)
     int32_t pad;
 };
 
@@ -107,11 +109,14 @@ struct Fbm2dStripArgs {
 };
 
 // 3D dyadic ladders, plain FP32 form on the vector ALUs: world-aligned blocks of
-// k3BlockX x k3BlockY x k3BlockZ samples, one wave each (lane = x column).
+// k3BlockX x k3BlockY x k3BlockZ samples, one wave each (lane = x column, a walk over the
+// block's slices in z).  Octaves of period >= k3BlockZ are "coarse" (one cell over the
+// block in y and z); periods 8, 4, 2 are "fine" (their node planes are hashed as the walk
+// enters their z cells).
 constexpr int k3BlockX = 64;
 constexpr int k3BlockY = 8;
-constexpr int k3BlockZ = 4;
-constexpr int k3TabMaxP = 64;  // octaves of period <= 64 read their bases from an LDS table
+constexpr int k3BlockZ = 16;
+constexpr int k3TabMaxP = 256;  // coarse octaves of period <= 256 take their block bases from an LDS table
 
 struct Fbm3dStripArgs {
     int64_t x0, y0, z0, nx, ny, nz;  // output volume (world), dense [nz][ny][nx]
@@ -121,17 +126,26 @@ struct Fbm3dStripArgs {
     float amp[kMaxOctaves];
     float inv2p[kMaxOctaves];       // 2^-(shift + 1)
     int32_t shift[kMaxOctaves];     // period 2^shift; shift[o] = shift[0] - o
-    int32_t nnx[kMaxOctaves], nny[kMaxOctaves], nnz[kMaxOctaves];
-    int32_t noff[kMaxOctaves];      // node block: (i * nny + j) * nnz + k
-    int32_t kxoff[kMaxOctaves], kzyoff[kMaxOctaves];  // column keys, (z, y) row keys (k * nny + j)
-    int32_t toff[kMaxOctaves];      // basis table offset (period <= k3TabMaxP) or -1
-    int32_t nodes_total, keys_total, tab_total;
+    int32_t nnx[kMaxOctaves];       // node columns of a block's footprint
+    int32_t kxoff[kMaxOctaves];     // column keys of octave o in a wave's key block
+    int32_t coff[kMaxOctaves];      // coarse octave: its nnx x 2 x 2 nodes (4 i + 2 k + j) from here
+    int32_t poff[kMaxOctaves];      // fine octave: its two z-plane slots (slot, then i * nny + j) from here
+    int32_t ytoff[kMaxOctaves], ztoff[kMaxOctaves];  // coarse octave: basis table (floats), or -1
+    int32_t tab_total;              // floats of the basis table
+    int32_t fwl[3];                 // fine octaves of period 8, 4, 2: their plane list in the node work list
+    int32_t nodes_total;            // nodes of a wave's block: coarse nodes, then the fine planes
+    int32_t coarse_nodes;           // coarse nodes (hashed per block from the work list)
+    int32_t nodes_listed;           // entries of the node work list (coarse nodes, fine planes)
+    int32_t keys_col;               // column keys of every octave
+    int32_t keys_total;             // + 4 row keys per coarse octave + the fine planes' row keys
     int32_t octaves;
     uint32_t seed;
     int32_t blocks_x, blocks_y;
-    int32_t n_coarse;               // octaves 0 .. n_coarse-1 have period >= 8
-    int32_t o4, o2, o1;             // octave of period 4, 2, 1, or -1
-    int32_t lo;                     // min(finest shift, 3): selects the kernel's row loop
+    int32_t n_coarse;               // octaves 0 .. n_coarse-1 have period >= k3BlockZ
+    int32_t o8, o4, o2;             // octave of period 8, 4, 2, or -1
+    int32_t lo;                     // min(finest shift, 4): selects the kernel's fine classes
+    int32_t model;                  // PTG_MODEL_GRADIENT or PTG_MODEL_HEIGHT_GRADIENT
+    float gw;                       // gradient weight (height-and-gradient model)
 };
 
 // ---- launch recording (HIP graphs) --------------------------------------------------
@@ -191,15 +205,17 @@ __host__ __device__ inline int strip_wave_words(int nodes_total, int keys_total,
     return ((2 + hw) * nodes_total + keys_total + 3) & ~3;
 }
 
-// LDS words of the 3D strip kernel's basis table and work lists (shared) and of one wave's
-// node block (gx, gy, gz, then keys).
-__host__ __device__ inline int strip3_shared_words(int tab_total, int nodes_total, int keys_total)
+// LDS words of the 3D strip kernel's shared part (basis table, key list, node list of the
+// coarse nodes and the fine planes; the lists start at word tab_words(tab_total)) and of one
+// wave's block (gx, gy, gz[, h], then keys).
+__host__ __device__ inline int strip3_tab_words(int tab_total) { return (tab_total + 3) & ~3; }
+__host__ __device__ inline int strip3_shared_words(int tab_total, int keys_listed, int nodes_listed)
 {
-    return 4 * tab_total + ((keys_total + nodes_total + 3) & ~3);
+    return strip3_tab_words(tab_total) + ((keys_listed + nodes_listed + 3) & ~3);
 }
-__host__ __device__ inline int strip3_wave_words(int nodes_total, int keys_total)
+__host__ __device__ inline int strip3_wave_words(int nodes_total, int keys_total, int hw = 0)
 {
-    return (3 * nodes_total + keys_total + 3) & ~3;
+    return ((3 + hw) * nodes_total + keys_total + 3) & ~3;
 }
 
 hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, int model, bool f16, int grid, int waves, size_t lds_bytes,
@@ -213,7 +229,7 @@ hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t
 hipError_t launch_fbm2d_general_grad(const Fbm2dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fbm3d_strip(const Fbm3dStripArgs &a, int smooth, bool f16, int grid, int waves, size_t lds_bytes,
                               hipStream_t s);
-int strip3_wgs_per_cu(int smooth, bool f16, int lo, int waves, size_t lds_bytes);
+int strip3_wgs_per_cu(int smooth, int model, bool f16, int lo, int waves, size_t lds_bytes);
 
 // Stand-alone stage kernels (ptg_stages.hip): one-dimensional grids of these workgroups;
 // the entry points reject boxes whose workgroup count exceeds 2^31 - 1.

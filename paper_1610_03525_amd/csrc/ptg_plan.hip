@@ -245,7 +245,10 @@ size_t general_args_3d(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, 
     a->capz = footprint_cap(a->freq, p->octaves, kTile3Z);
     a->tiles_x = (int32_t)((nx + kTile3X - 1) / kTile3X);
     a->tiles_y = (int32_t)((ny + kTile3Y - 1) / kTile3Y);
-    return (size_t)(kTile3Y + kTile3Z) * 16 + (size_t)a->capx * a->capy * a->capz * 12 +
+    a->model = p->model;
+    a->gw = (float)p->gradient_weight;
+    return (size_t)(kTile3Y + kTile3Z) * 16 +
+           (size_t)a->capx * a->capy * a->capz * (p->model == PTG_MODEL_HEIGHT_GRADIENT ? 16 : 12) +
            (size_t)(a->capx + a->capy * a->capz) * 4;
 }
 
@@ -328,39 +331,58 @@ int strip3_args(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t z0, 
     octave_tables(p, freq, a.amp);
     a.octaves = p->octaves;
     a.seed = p->seed;
-    a.o4 = a.o2 = a.o1 = -1;
+    a.model = p->model;
+    a.gw = (float)p->gradient_weight;
+    a.o8 = a.o4 = a.o2 = -1;
     const int smin = k - (p->octaves - 1);
-    if (smin <= 2 && k < 2) return 1;  // the row loop assumes every period from 4 down to the finest
-    a.lo = std::min(smin, 3);
-    int nodes = 0, keys = 0, tab = 0;
+    if (smin < 1) return 1;            // period 1: the general kernel
+    if (smin <= 3 && k < 3) return 1;  // the fine classes assume every period from 8 down to the finest
+    a.lo = std::min(smin, 4);
+    int kcol = 0, cnodes = 0, tab = 0;
     for (int o = 0; o < p->octaves; ++o) {
         const int sh = k - o;
         a.shift[o] = sh;
         a.inv2p[o] = std::ldexp(1.0f, -(sh + 1));
-        if (sh >= 3) a.n_coarse = o + 1;
-        if (sh == 2) a.o4 = o;
-        if (sh == 1) a.o2 = o;
-        if (sh == 0) a.o1 = o;
         const int c = std::min(sh, 30);
         a.nnx[o] = std::max(BX >> c, 1) + 1;
-        a.nny[o] = std::max(BY >> c, 1) + 1;
-        a.nnz[o] = std::max(BZ >> c, 1) + 1;
-        a.noff[o] = nodes;
-        a.kxoff[o] = keys;
-        a.kzyoff[o] = keys + a.nnx[o];
-        nodes += a.nnx[o] * a.nny[o] * a.nnz[o];
-        keys += a.nnx[o] + a.nny[o] * a.nnz[o];
-        if ((1 << c) <= k3TabMaxP) {
-            a.toff[o] = tab;
-            tab += 1 << c;
-        } else {
-            a.toff[o] = -1;
+        a.kxoff[o] = kcol;
+        kcol += a.nnx[o];
+        a.coff[o] = a.poff[o] = a.ytoff[o] = a.ztoff[o] = -1;
+        if ((1 << std::min(sh, 30)) >= BZ) {
+            a.n_coarse = o + 1;
+            a.coff[o] = cnodes;
+            cnodes += 4 * a.nnx[o];
+            if ((1 << std::min(sh, 30)) <= k3TabMaxP) {  // block bases from the table
+                const int E = 3 * (2 * p->smoothness + 2), P = 1 << sh;
+                a.ytoff[o] = tab;
+                tab += (P / BY) * E;
+                a.ztoff[o] = tab;
+                tab += (P / BZ) * E;
+            }
         }
+        if (sh == 3) a.o8 = o;
+        if (sh == 2) a.o4 = o;
+        if (sh == 1) a.o2 = o;
+    }
+    a.keys_col = kcol;
+    a.coarse_nodes = cnodes;
+    a.tab_total = tab;
+    int nodes = cnodes, listed = cnodes;
+    const int fine[3] = {a.o8, a.o4, a.o2};
+    for (int f = 0; f < 3; ++f) {
+        const int o = fine[f];
+        a.fwl[f] = listed;
+        if (o < 0) continue;
+        const int P = 8 >> f, plane = (BX / P + 1) * (BY / P + 1);
+        a.poff[o] = nodes;
+        nodes += 2 * plane;
+        listed += plane;
     }
     a.nodes_total = nodes;
-    a.keys_total = keys;
-    a.tab_total = tab;
-    if (keys >= (1 << 14)) return 1;
+    a.nodes_listed = listed;
+    // + the fine octaves' row keys of the block's planes (periods 8, 4, 2: 3 x 2, 5 x 3, 9 x 5)
+    a.keys_total = kcol + 4 * a.n_coarse + 66;
+    if (a.keys_total >= (1 << 14) || cnodes >= (1 << 14)) return 1;
     return 0;
 }
 
@@ -371,16 +393,18 @@ static int fbm3d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
 {
     Fbm3dStripArgs a;
     if (strip3_args(p, k, x0, y0, z0, nx, ny, nz, out, &a)) return 1;
-    const size_t shared_words = (size_t)strip3_shared_words(a.tab_total, a.nodes_total, a.keys_total);
-    const size_t wave_words = (size_t)strip3_wave_words(a.nodes_total, a.keys_total);
-    int waves = tune_pick(TuneKey{PTG_TUNE_STRIP_3D, p->smoothness, p->out_dtype == PTG_F16,
+    const int hw = p->model == PTG_MODEL_HEIGHT_GRADIENT ? 1 : 0;
+    const size_t shared_words =
+        (size_t)strip3_shared_words(a.tab_total, a.keys_col + 4 * a.n_coarse, a.nodes_listed);
+    const size_t wave_words = (size_t)strip3_wave_words(a.nodes_total, a.keys_total, hw);
+    int waves = tune_pick(TuneKey{PTG_TUNE_STRIP_3D, p->smoothness + 2 * hw, p->out_dtype == PTG_F16,
                                   size_class(nx * ny * nz), a.lo},
                           4);
     while (waves > 1 && (shared_words + waves * wave_words) * 4 > kDyMaxLds) --waves;
     const size_t lds = (shared_words + waves * wave_words) * 4;
     if (lds > kDyMaxLds) return 1;
     if (tune_dry()) return PTG_OK;
-    const int64_t per_cu = strip3_wgs_per_cu(p->smoothness, p->out_dtype == PTG_F16, a.lo, waves, lds);
+    const int64_t per_cu = strip3_wgs_per_cu(p->smoothness, p->model, p->out_dtype == PTG_F16, a.lo, waves, lds);
     const int64_t wgs = (a.blocks + waves - 1) / waves;
     const int grid = (int)std::min<int64_t>(wgs, (int64_t)device_cus() * per_cu);
     hipError_t e = launch_fbm3d_strip(a, p->smoothness, p->out_dtype == PTG_F16, grid, waves, lds, s);
@@ -400,7 +424,8 @@ int fbm3d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t
         const int rc = fbm3d_strip(p, k, x0, y0, z0, nx, ny, nz, out, s);
         if (rc <= 0) return rc;
         if (p->path == PTG_PATH_DYADIC)
-            return fail(PTG_EINVAL, "the 3D dyadic kernel does not apply (ladder below period 4, or LDS)");
+            return fail(PTG_EINVAL, "the 3D dyadic kernel does not apply (a ladder reaching period 1, finer than 8 "
+                                    "with a coarsest period below 8, or LDS)");
     }
     Fbm3dArgs a{};
     const size_t lds = general_args_3d(p, x0, y0, z0, nx, ny, nz, out, &a);

@@ -70,7 +70,7 @@ struct ServeReqDesc {
     uint64_t target;  // done_tiles[slot] when this request is complete
     int64_t ntiles;
     int32_t kernel;   // PTG_TUNE_GENERAL_2D / _GENERAL_3D (tiles), PTG_TUNE_STRIP_2D (64 x 64 strips),
-                      // PTG_TUNE_STRIP_3D (64 x 8 x 4 blocks)
+                      // PTG_TUNE_STRIP_3D (64 x 8 x 16 blocks)
     int32_t pad;
     union {
         Fbm2dArgs a2;
@@ -180,11 +180,24 @@ __device__ __forceinline__ void serve_blocks(const Fbm3dStripArgs &a, const Stri
                                              int64_t t1, int tid)
 {
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const uint32_t *wl_key = reinterpret_cast<const uint32_t *>(tab + a.tab_total);
-    float *gx = reinterpret_cast<float *>(tab) + strip3_shared_words(a.tab_total, a.nodes_total, a.keys_total) +
+    const int listed = a.keys_col + 4 * a.n_coarse;
+    const uint32_t *wl_key = reinterpret_cast<const uint32_t *>(tab) + strip3_tab_words(a.tab_total);
+    float *gx = reinterpret_cast<float *>(tab) + strip3_shared_words(a.tab_total, listed, a.nodes_listed) +
                 wave * strip3_wave_words(a.nodes_total, a.keys_total);
     Strip3Wave<M, float, LO> w(a, sh, gx, lane);
-    for (int64_t b = t0 + wave; b < t1; b += kServeWaves) w.run(a, sh, tab, wl_key, wl_key + a.keys_total, b);
+    for (int64_t b = t0 + wave; b < t1; b += kServeWaves) w.run(a, sh, tab, wl_key, wl_key + listed, b);
+}
+
+template <int M>
+__device__ __forceinline__ void serve_blocks_lo(const Fbm3dStripArgs &a, const Strip3Shared &sh, float4 *tab,
+                                                int64_t t0, int64_t t1, int tid)
+{
+    switch (a.lo) {
+    case 1: serve_blocks<M, 1>(a, sh, tab, t0, t1, tid); break;
+    case 2: serve_blocks<M, 2>(a, sh, tab, t0, t1, tid); break;
+    case 3: serve_blocks<M, 3>(a, sh, tab, t0, t1, tid); break;
+    default: serve_blocks<M, 4>(a, sh, tab, t0, t1, tid); break;
+    }
 }
 
 
@@ -278,17 +291,18 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
             Strip3Shared &sh = *reinterpret_cast<Strip3Shared *>(lds4);
             float4 *tab = lds4 + kStrip3SharedWords / 4;
             if (s_cmd == 1) {
-                uint32_t *wl_key = reinterpret_cast<uint32_t *>(tab + rq.a3s.tab_total);
+                uint32_t *wl_key = reinterpret_cast<uint32_t *>(tab) + strip3_tab_words(rq.a3s.tab_total);
+                uint32_t *wl_node = wl_key + rq.a3s.keys_col + 4 * rq.a3s.n_coarse;
                 if (rq.smooth == 1)
-                    strip3_prologue<1>(rq.a3s, sh, tab, wl_key, wl_key + rq.a3s.keys_total, tid, 256);
+                    strip3_prologue<1>(rq.a3s, sh, tab, wl_key, wl_node, tid, 256);
                 else
-                    strip3_prologue<2>(rq.a3s, sh, tab, wl_key, wl_key + rq.a3s.keys_total, tid, 256);
+                    strip3_prologue<2>(rq.a3s, sh, tab, wl_key, wl_node, tid, 256);
                 __syncthreads();
             }
-            if (rq.smooth == 1)  // admission: finest period >= 8 (lo = 3)
-                serve_blocks<1, 3>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
+            if (rq.smooth == 1)
+                serve_blocks_lo<1>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
             else
-                serve_blocks<2, 3>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
+                serve_blocks_lo<2>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
             __syncthreads();
         }
         if (rq.lat_mode == 2) {
@@ -1024,11 +1038,11 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
     Fbm3dStripArgs sb;
     *kernel = nd == 2 ? PTG_TUNE_GENERAL_2D : PTG_TUNE_GENERAL_3D;
     if (nd == 3 && dyadic_shift(p, &k) &&
-        strip3_args(p, k, r->origin[0], r->origin[1], r->origin[2], nx, ny, nz, nullptr, &sb) == 0 && sb.lo == 3 &&
-        (size_t)(kStrip3SharedWords + strip3_shared_words(sb.tab_total, sb.nodes_total, sb.keys_total) +
+        strip3_args(p, k, r->origin[0], r->origin[1], r->origin[2], nx, ny, nz, nullptr, &sb) == 0 &&
+        (size_t)(kStrip3SharedWords + strip3_shared_words(sb.tab_total, sb.keys_col + 4 * sb.n_coarse, sb.nodes_listed) +
                  kServeWaves * strip3_wave_words(sb.nodes_total, sb.keys_total)) * 4 <= kServeLds) {
-        // dyadic ladder whose finest period is >= 8 (the serving kernel carries that class of
-        // the 3D strip code only; finer ladders keep its registers beyond two workgroups per CU)
+        // dyadic ladder the 3D strip code takes (finest period >= 2) whose footprint fits a
+        // serving workgroup
         *kernel = PTG_TUNE_STRIP_3D;
         *ntiles = sb.blocks;
         lds = 0;

@@ -28,7 +28,7 @@ def test_params_layout_matches_header():
 
 def test_model_validation():
     """The zero-gradient model (Sec. 3.3) is 2D C1 plain form only, the height-and-gradient
-    model 2D plain form with a finite weight; neither is served."""
+    model plain form (2D or 3D) with a finite weight; neither is served."""
     L = ptg.lib()
     ok = ptg.params(model="zero_gradient", base_freq=1 / 64, octaves=3)
     assert ptg.lib().ptg_tune_query_2d(ctypes.byref(ok), 64, 64, ctypes.byref(ctypes.c_int32()),
@@ -45,9 +45,14 @@ def test_model_validation():
         assert L.ptg_fbm_2d(ctypes.byref(p), 0, 0, 16, 16, ctypes.c_void_p(1 << 20), 16, None) == ptg.PTG_EINVAL
     assert ptg.tune_query((64, 64), smoothness=3, octaves=3, base_freq=1 / 64) == ("general_2d", 64)
     assert ptg.tune_query((64, 64, 64), smoothness=3, octaves=3, base_freq=1 / 16) == ("general_3d", 0)
-    for m in ("zero_gradient", "height_gradient"):
-        p3 = ptg.params(dim=3, model=m, base_freq=1 / 64, octaves=3)
-        assert L.ptg_fbm_3d(ctypes.byref(p3), 0, 0, 0, 8, 8, 8, ctypes.c_void_p(1 << 20), None) == ptg.PTG_EINVAL
+    p3 = ptg.params(dim=3, model="zero_gradient", base_freq=1 / 64, octaves=3)
+    assert L.ptg_fbm_3d(ctypes.byref(p3), 0, 0, 0, 8, 8, 8, ctypes.c_void_p(1 << 20), None) == ptg.PTG_EINVAL
+    p3 = ptg.params(dim=3, model="height_gradient", base_freq=1 / 64, octaves=3, form="mfma_f16")
+    assert L.ptg_fbm_3d(ctypes.byref(p3), 0, 0, 0, 8, 8, 8, ctypes.c_void_p(1 << 20), None) == ptg.PTG_EINVAL
+    for sm in (1, 2, 3):  # 3D heights and gradients: the 3D strip kernel (C1, C2) or the general one
+        want = ("strip_3d" if sm < 3 else "general_3d")
+        assert ptg.tune_query((64, 64, 64), model="height_gradient", smoothness=sm, base_freq=1 / 64,
+                              octaves=5)[0] == want
     ok2 = ptg.params(model="height_gradient", smoothness=2, base_freq=1 / 64, octaves=3, gradient_weight=-0.3)
     assert ptg.lib().ptg_tune_query_2d(ctypes.byref(ok2), 64, 64, ctypes.byref(ctypes.c_int32()),
                                        ctypes.byref(ctypes.c_int32())) == ptg.PTG_OK

@@ -373,8 +373,9 @@ def test_fbm3d_non_dyadic_and_ragged():
 
 
 # Each dyadic ladder below selects a different specialisation of the 3D strip kernel
-# (finest period 1, 2, 4, >= 8; no coarse octave; periods beyond the LDS tables) or its
-# fallback; every field is an unaligned window with ragged edges against 64x8x4 blocks.
+# (finest period 2, 4, 8, >= 16; no coarse octave; coarse octaves with and without a basis
+# table) or its fallback (ladders reaching period 1); every field is an unaligned window
+# with ragged edges against 64 x 8 x 16 blocks, several blocks deep in z.
 @pytest.mark.parametrize("path", ["auto", "general"])
 @pytest.mark.parametrize("smooth", [1, 2])
 @pytest.mark.parametrize("f0,octs,origin,shape", [
@@ -385,6 +386,10 @@ def test_fbm3d_non_dyadic_and_ragged():
     (1 / 4, 3, (2, 3, 1), (65, 8, 4)),                              # periods 4..1, no coarse octave
     (2.0 ** -20, 5, (2 ** 40 + 9, -(2 ** 41) - 3, 2 ** 39), (66, 10, 3)),  # periods 2^20..2^16
     (1 / 2, 2, (0, 0, 0), (40, 6, 5)),                              # periods 2, 1: general kernel
+    (1 / 8, 3, (5, -3, 17), (70, 19, 37)),                          # periods 8, 4, 2: no coarse octave
+    (1 / 16, 4, (-100, 50, -33), (90, 25, 40)),                     # periods 16..2
+    (1 / 512, 8, (7, -1000, 2 ** 36 + 5), (65, 9, 20)),            # periods 512..4 (512: no table)
+    (1 / 128, 4, (-64, 8, 16), (128, 16, 32)),                      # periods 128..16, aligned blocks
 ])
 def test_fbm3d_ladders_against_oracle(path, smooth, f0, octs, origin, shape):
     kw = dict(smoothness=smooth, octaves=octs, persistence=0.5, lacunarity=2.0, base_freq=f0, seed=21, path=path)

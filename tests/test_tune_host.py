@@ -95,6 +95,6 @@ def test_server_tile_height_sets_the_tile_count():
             (t,) = s.submit([ptg.tile_req(dim=3, extent=(64, 8, 8), octaves=4, base_freq=2.0 ** -12)])
             assert s.wait(t, 10_000_000_000).kernel == ptg.PTG_TUNE_STRIP_3D  # periods 4096..512
             (t,) = s.submit([ptg.tile_req(dim=3, extent=(64, 8, 8), octaves=4, base_freq=1 / 16)])
-            assert s.wait(t, 10_000_000_000).kernel == ptg.PTG_TUNE_GENERAL_3D  # reaches period 2
+            assert s.wait(t, 10_000_000_000).kernel == ptg.PTG_TUNE_STRIP_3D  # periods 16..2
             (t,) = s.submit([ptg.tile_req(dim=3, extent=(64, 8, 8), octaves=4, base_freq=3e-4)])
             assert s.wait(t, 10_000_000_000).kernel == ptg.PTG_TUNE_GENERAL_3D  # not dyadic
