@@ -1,5 +1,5 @@
 // ptg_fbm3d_strip.hip -- K3 for 3D dyadic octave ladders: the dense-volume kernel (one wave
-// per 64 x 8 x 16 block, a grid-stride walk over the volume's blocks) and its launches; the
+// per 64 x 8 x 16 block, each wave a run of consecutive blocks in z) and its launches; the
 // per-block code is in ptg_strip3_tile.h.
 #include "ptg.h"
 #include "ptg_strip3_tile.h"
@@ -25,9 +25,14 @@ __global__ __launch_bounds__(256) void k_fbm3d_strip(const Fbm3dStripArgs a)
     strip3_prologue<M>(a, sh, lds4, wl_key, wl_node, tid, nthreads);
     __syncthreads();
     Strip3Wave<M, OutT, LO, MD> w(a, sh, gx, lane);
-    const int64_t nwaves = (int64_t)gridDim.x * wpg;
-    for (int64_t blk = (int64_t)blockIdx.x * wpg + wave; blk < a.blocks; blk += nwaves)
-        w.run(a, sh, lds4, wl_key, wl_node, blk);
+    // each wave takes a run of consecutive blocks (z fastest), carrying the fine octaves'
+    // node planes from a block to the next one above it
+    const int64_t nwaves = (int64_t)gridDim.x * wpg, chunk = (a.blocks + nwaves - 1) / nwaves;
+    const int64_t b0 = ((int64_t)blockIdx.x * wpg + wave) * chunk, b1 = min(b0 + chunk, a.blocks);
+    // (not for the height-and-gradient cells: their carried corners would keep the kernel
+    // above 256 registers)
+    for (int64_t blk = b0; blk < b1; ++blk)
+        w.run(a, sh, lds4, wl_key, wl_node, blk, MD == 0 && blk > b0 && blk % a.blocks_z != 0);
 }
 
 template <int M, typename OutT, int LO, int MD>

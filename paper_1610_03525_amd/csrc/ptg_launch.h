@@ -140,7 +140,7 @@ struct Fbm3dStripArgs {
     int32_t keys_total;             // + 4 row keys per coarse octave + the fine planes' row keys
     int32_t octaves;
     uint32_t seed;
-    int32_t blocks_x, blocks_y;
+    int32_t blocks_x, blocks_y, blocks_z;  // block index = (by * blocks_x + bx) * blocks_z + bz
     int32_t n_coarse;               // octaves 0 .. n_coarse-1 have period >= k3BlockZ
     int32_t o8, o4, o2;             // octave of period 8, 4, 2, or -1
     int32_t lo;                     // min(finest shift, 4): selects the kernel's fine classes

@@ -323,9 +323,10 @@ int strip3_args(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t z0, 
     const int64_t bxn = (x0 + nx - a.bx_base + BX - 1) / BX;
     const int64_t byn = (y0 + ny - a.by_base + BY - 1) / BY;
     const int64_t bzn = (z0 + nz - a.bz_base + BZ - 1) / BZ;
-    if (bxn > 0x7FFFFFFFLL || byn > 0x7FFFFFFFLL) return 1;
+    if (bxn > 0x7FFFFFFFLL || byn > 0x7FFFFFFFLL || bzn > 0x7FFFFFFFLL) return 1;
     a.blocks_x = (int32_t)bxn;
     a.blocks_y = (int32_t)byn;
+    a.blocks_z = (int32_t)bzn;
     a.blocks = bxn * byn * bzn;
     double freq[kMaxOctaves];
     octave_tables(p, freq, a.amp);

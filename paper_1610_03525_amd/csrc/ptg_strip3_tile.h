@@ -399,13 +399,16 @@ struct Strip3Wave {
         }
     }
 
-    // Block blk of the volume.
+    // Block blk of the volume (blocks are numbered z fastest: a column of blocks in z is a
+    // run of consecutive indices).  carry: this wave's previous block was the one below it
+    // in z, whose last node planes of the fine octaves (and the lane's corners of them) are
+    // the first of this block -- they are kept instead of hashed again.
     __device__ __forceinline__ void run(const Fbm3dStripArgs &a, const Strip3Shared &sh, const float4 *tab4,
-                                        const uint32_t *wl_key, const uint32_t *wl_node, int64_t blk)
+                                        const uint32_t *wl_key, const uint32_t *wl_node, int64_t blk,
+                                        bool carry = false)
     {
-        const int64_t bplane = (int64_t)a.blocks_x * a.blocks_y;
-        const int64_t bz = blk / bplane, rem = blk - bz * bplane;
-        const int64_t by = rem / a.blocks_x, bx = rem - by * a.blocks_x;
+        const int64_t col = blk / a.blocks_z, bz = blk - col * a.blocks_z;
+        const int64_t by = col / a.blocks_x, bx = col - by * a.blocks_x;
         const int64_t X0 = a.bx_base + bx * BX, Y0 = a.by_base + by * BY, Z0 = a.bz_base + bz * BZ;
         const int keys_col = a.keys_col, nrk = keys_col + 4 * a.n_coarse;
 
@@ -432,9 +435,11 @@ struct Strip3Wave {
             const uint32_t key = key_combine(keys[(it >> 14) & 0x3FFF], keys[it & 0x3FFF]);
             put_node(q, key, MD == 2 ? sh.amp[o] * sh.gw : sh.amp[o], sh.amp[o]);
         }
-        if (H8) fine_nodes(f8, wl_node + a.fwl[0], Z0 >> 3, 0, 2);
-        if (H4) fine_nodes(f4, wl_node + a.fwl[1], Z0 >> 2, 0, 2);
-        if (H2) fine_nodes(f2, wl_node + a.fwl[2], Z0 >> 1, 0, 2);
+        if (!carry) {
+            if (H8) fine_nodes(f8, wl_node + a.fwl[0], Z0 >> 3, 0, 2);
+            if (H4) fine_nodes(f4, wl_node + a.fwl[1], Z0 >> 2, 0, 2);
+            if (H2) fine_nodes(f2, wl_node + a.fwl[2], Z0 >> 1, 0, 2);
+        }
         wave_sync3();
 
         // ---- coarse octaves: one polynomial in (v_y, v_z) per lane ----------------------
@@ -446,16 +451,17 @@ struct Strip3Wave {
         const float *tab = reinterpret_cast<const float *>(tab4);
         for (int o = 0; o < a.n_coarse; ++o) coarse_add(Cb, sh, tab, o, X0, Y0, Z0);
 
-        // ---- fine octaves: the corners of their first z cell ------------------------------
-        if (H8) {
+        // ---- fine octaves: the corners of their first z cell (carried: the first slice
+        // advances from the previous block's last cell) -------------------------------------
+        if (!carry && H8) {
             fine_corners(f8, Z0 >> 3, f8.lo);
             fine_corners(f8, (Z0 >> 3) + 1, f8.hi);
         }
-        if (H4) {
+        if (!carry && H4) {
             fine_corners(f4, Z0 >> 2, f4.lo);
             fine_corners(f4, (Z0 >> 2) + 1, f4.hi);
         }
-        if (H2) {
+        if (!carry && H2) {
             fine_corners(f2, Z0 >> 1, f2.lo);
             fine_corners(f2, (Z0 >> 1) + 1, f2.hi);
         }
@@ -464,17 +470,19 @@ struct Strip3Wave {
         const int64_t xe = a.x0 + a.nx, ye = a.y0 + a.ny, ze = a.z0 + a.nz;
         const bool full_xy = X0 >= a.x0 && X0 + BX <= xe && Y0 >= a.y0 && Y0 + BY <= ye;
         const bool lane_ok = X0 + lane >= a.x0 && X0 + lane < xe;
-        OutT *const out = reinterpret_cast<OutT *>(a.out);
+        const int qlo = (int)max<int64_t>(0, a.z0 - Z0), qhi = (int)min<int64_t>(BZ, ze - Z0);  // stored slices
+        // slice 0's first row of the block in the output (uniform)
+        OutT *const base = reinterpret_cast<OutT *>(a.out) + (((Z0 - a.z0) * a.ny + (Y0 - a.y0)) * a.nx + (X0 - a.x0));
 #pragma unroll 1
         for (int g = 0; g < BZ / 8; ++g) {
-            slice<0>(a, sh, wl_node, Cb, g, X0, Y0, Z0, xe, ye, ze, full_xy, lane_ok, out);
-            slice<1>(a, sh, wl_node, Cb, g, X0, Y0, Z0, xe, ye, ze, full_xy, lane_ok, out);
-            slice<2>(a, sh, wl_node, Cb, g, X0, Y0, Z0, xe, ye, ze, full_xy, lane_ok, out);
-            slice<3>(a, sh, wl_node, Cb, g, X0, Y0, Z0, xe, ye, ze, full_xy, lane_ok, out);
-            slice<4>(a, sh, wl_node, Cb, g, X0, Y0, Z0, xe, ye, ze, full_xy, lane_ok, out);
-            slice<5>(a, sh, wl_node, Cb, g, X0, Y0, Z0, xe, ye, ze, full_xy, lane_ok, out);
-            slice<6>(a, sh, wl_node, Cb, g, X0, Y0, Z0, xe, ye, ze, full_xy, lane_ok, out);
-            slice<7>(a, sh, wl_node, Cb, g, X0, Y0, Z0, xe, ye, ze, full_xy, lane_ok, out);
+            slice<0>(a, sh, wl_node, Cb, g, carry, Y0, Z0, ye, qlo, qhi, full_xy, lane_ok, base);
+            slice<1>(a, sh, wl_node, Cb, g, carry, Y0, Z0, ye, qlo, qhi, full_xy, lane_ok, base);
+            slice<2>(a, sh, wl_node, Cb, g, carry, Y0, Z0, ye, qlo, qhi, full_xy, lane_ok, base);
+            slice<3>(a, sh, wl_node, Cb, g, carry, Y0, Z0, ye, qlo, qhi, full_xy, lane_ok, base);
+            slice<4>(a, sh, wl_node, Cb, g, carry, Y0, Z0, ye, qlo, qhi, full_xy, lane_ok, base);
+            slice<5>(a, sh, wl_node, Cb, g, carry, Y0, Z0, ye, qlo, qhi, full_xy, lane_ok, base);
+            slice<6>(a, sh, wl_node, Cb, g, carry, Y0, Z0, ye, qlo, qhi, full_xy, lane_ok, base);
+            slice<7>(a, sh, wl_node, Cb, g, carry, Y0, Z0, ye, qlo, qhi, full_xy, lane_ok, base);
         }
         __builtin_amdgcn_wave_barrier();  // the next block rewrites this wave's keys and nodes
     }
@@ -482,14 +490,14 @@ struct Strip3Wave {
     // Slice 8 g + Q of the block.
     template <int Q>
     __device__ __forceinline__ void slice(const Fbm3dStripArgs &a, const Strip3Shared &sh, const uint32_t *wl_node,
-                                          const float (&Cb)[D1][D1], int g, int64_t X0, int64_t Y0, int64_t Z0, int64_t xe, int64_t ye,
-                                          int64_t ze, bool full_xy, bool lane_ok, OutT *out)
+                                          const float (&Cb)[D1][D1], int g, bool carry, int64_t Y0, int64_t Z0,
+                                          int64_t ye, int qlo, int qhi, bool full_xy, bool lane_ok, OutT *base)
     {
         const int q = 8 * g + Q;
         const int64_t Z = Z0 + q;
         // a new z cell of the fine octaves whose period divides q: its upper plane
         constexpr bool A8 = H8 && Q == 0, A4 = H4 && Q % 4 == 0, A2 = H2 && Q % 2 == 0;
-        if ((A8 || A4 || A2) && (Q > 0 || g > 0)) {
+        if ((A8 || A4 || A2) && (Q > 0 || g > 0 || carry)) {
             wave_sync3();  // every lane has read the slot that is rewritten (two planes back)
             if (A8) fine_nodes(f8, wl_node + a.fwl[0], (Z >> 3) + 1, q / 8 + 1, 1);
             if (A4) fine_nodes(f4, wl_node + a.fwl[1], (Z >> 2) + 1, q / 4 + 1, 1);
@@ -556,18 +564,26 @@ struct Strip3Wave {
         }
         if (H4) fine_rows<4, Q % 4>(f4, t);
         if (H2) fine_rows<2, Q % 2>(f2, t);
-        // stores: a uniform row pointer per row, the lane's column
-        if (Z >= a.z0 && Z < ze) {
-            OutT *row = out + ((Z - a.z0) * a.ny + (Y0 - a.y0)) * a.nx + (X0 - a.x0);
+        // stores: a uniform row pointer per row plus the lane's 32-bit column offset
+        if (q >= qlo && q < qhi) {
+            OutT *row = base + (int64_t)q * a.ny * a.nx;
             if (full_xy) {
 #pragma unroll
-                for (int r = 0; r < BY; ++r) row[(int64_t)r * a.nx + lane] = s3_out<OutT>(t[r]);
+                for (int r = 0; r < BY; ++r) {
+                    row[(uint32_t)lane] = s3_out<OutT>(t[r]);
+                    row += a.nx;
+                }
             } else {
 #pragma unroll
-                for (int r = 0; r < BY; ++r)
-                    if (Y0 + r >= a.y0 && Y0 + r < ye && lane_ok) row[(int64_t)r * a.nx + lane] = s3_out<OutT>(t[r]);
+                for (int r = 0; r < BY; ++r) {
+                    if (Y0 + r >= a.y0 && Y0 + r < ye && lane_ok) row[(uint32_t)lane] = s3_out<OutT>(t[r]);
+                    row += a.nx;
+                }
             }
         }
+        // keep each slice's work together: without this the scheduler interleaves the unrolled
+        // slices and holds several slices' values in registers at once
+        __builtin_amdgcn_sched_barrier(0);
     }
 };
 
