@@ -15,7 +15,9 @@
  *     whose value is 0 at each corner, whose gradient equals the corner's lattice
  *     gradient, and whose other mixed derivatives h^d, 0 <= d_k <= M, are 0.  M = 1 gives
  *     C1 cubic cells (D2M1N3 / D3M1N3 with zero twist), M = 2 C2 quintic cells, M = 3
- *     C3 septic cells.  Two more cell models (ptg_params.model): the zero-gradient
+ *     C3 septic cells, up to M = 6; the 1D bases of any M are the closed forms of
+ *     two-point Taylor interpolation, S(t) = t^(M+1) sum_{k<=M} C(M+k,k) (1-t)^k,
+ *     b10(t) = t (1-t)^(M+1) sum_{k<M} C(M+k,k) t^k, b11(t) = -b10(1-t).  Two more cell models (ptg_params.model): the zero-gradient
  *     model (2D), whose nodes carry heights and zero gradients (Sec. 3.3), and the
  *     height-and-gradient model (2D and 3D), whose nodes carry both (Sec. 3.1; D3M1N3 of
  *     Sec. 3.4 with heights; gradient weight w, Sec. 4).
@@ -69,6 +71,7 @@ extern "C" {
 
 /* ---- limits ------------------------------------------------------------------ */
 #define PTG_MAX_OCTAVES 16
+#define PTG_MAX_SMOOTHNESS 6 /* cell order M: derivatives up to M prescribed, degree 2M+1   */
 /* |world index| + extent must stay below 2^52 so X + 1/2 is exact in FP64 */
 #define PTG_MAX_WORLD_ABS 4503599627370496LL
 
@@ -119,8 +122,11 @@ extern "C" {
  * Sec. 4: octaves, persistence, lacunarity). */
 typedef struct ptg_params {
     int32_t dim;          /* 2 or 3                                                    */
-    int32_t smoothness;   /* 1 = C1 cubic, 2 = C2 quintic, 3 = C3 septic cells (3: the  */
-                          /* general kernels only; not served, no matrix-core form)    */
+    int32_t smoothness;   /* M = 1 C1 cubic, 2 C2 quintic, 3 C3 septic .. 6 (C6, degree */
+                          /* 13; Sec. 2.2 eq. nconstraints, the Conclusion's arbitrary  */
+                          /* smoothness).  1, 2: every kernel; 3: the 2D strip and the  */
+                          /* general kernels; 4..6: the general kernels.  Served tiles  */
+                          /* take 1, 2; the matrix-core form 1; the gradient output 1..3 */
     int32_t octaves;      /* 1 .. PTG_MAX_OCTAVES                                      */
     int32_t out_dtype;    /* PTG_F32 or PTG_F16                                        */
     double persistence;   /* amplitude ratio per octave, finite, > 0                   */

@@ -34,9 +34,9 @@ int validate_params(const ptg_params *p, int dim)
 {
     if (!p) return fail(PTG_EINVAL, "params is NULL");
     if (p->dim != dim) return fail(PTG_EINVAL, "params.dim is %d, this entry point takes %d", p->dim, dim);
-    if (p->smoothness < 1 || p->smoothness > 3)
-        return fail(PTG_EINVAL, "smoothness must be 1 (C1 cubic), 2 (C2 quintic) or 3 (C3 septic), got %d",
-                    p->smoothness);
+    if (p->smoothness < 1 || p->smoothness > PTG_MAX_SMOOTHNESS)
+        return fail(PTG_EINVAL, "smoothness must be 1 (C1 cubic), 2 (C2 quintic), 3 (C3 septic) .. %d, got %d",
+                    PTG_MAX_SMOOTHNESS, p->smoothness);
     if (p->octaves < 1 || p->octaves > PTG_MAX_OCTAVES)
         return fail(PTG_EINVAL, "octaves must be in 1..%d, got %d", PTG_MAX_OCTAVES, p->octaves);
     if (p->out_dtype != PTG_F32 && p->out_dtype != PTG_F16)
@@ -159,6 +159,7 @@ int ptg_fbm_2d_grad(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int
     int rc = validate_params(p, 2);
     if (rc) return rc;
     if (p->form != PTG_FORM_PLAIN) return fail(PTG_EINVAL, "the gradient output is computed in the plain form");
+    if (p->smoothness > 3) return fail(PTG_EINVAL, "the gradient output takes smoothness 1..3");
     if ((rc = validate_extent("x", x0, nx))) return rc;
     if ((rc = validate_extent("y", y0, ny))) return rc;
     if (nx == 0 || ny == 0) return PTG_OK;

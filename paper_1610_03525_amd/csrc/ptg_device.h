@@ -113,8 +113,43 @@ __host__ __device__ __forceinline__ int64_t cell_of(int64_t X, double f)
 //         the near corner's value basis is 1 - s.
 //   b10 = slope basis of the near corner, b11 = slope basis of the far corner.
 // ---------------------------------------------------------------------------------
+// Any order M >= 4 (the value and first M derivatives prescribed at both ends): the closed
+// forms of two-point Taylor interpolation, evaluated in factored form (every term of each sum
+// is non-negative on [0, 1], so no cancellation):
+//   S(t)   = t^(M+1) sum_{k=0..M} C(M+k, k) (1-t)^k,
+//   b10(t) = t (1-t)^(M+1) sum_{k=0..M-1} C(M+k, k) t^k,
+//   b11(t) = -(1-t) t^(M+1) sum_{k=0..M-1} C(M+k, k) (1-t)^k.
+__host__ __device__ constexpr float binom_f(int n, int k)
+{
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return (float)r;
+}
+
 template <int M>
-struct Basis;
+struct Basis {
+    static_assert(M >= 4 && M <= 6, "orders 1..3 have explicit forms below; the API allows up to 6");
+    __device__ __forceinline__ static void eval(float t, float &s, float &b10, float &b11)
+    {
+        const float u = 1.0f - t;
+        float pu = binom_f(2 * M - 1, M - 1), pt = pu;  // sums over k <= M-1, Horner from the top
+#pragma unroll
+        for (int k = M - 2; k >= 0; --k) {
+            pu = __builtin_fmaf(pu, u, binom_f(M + k, k));
+            pt = __builtin_fmaf(pt, t, binom_f(M + k, k));
+        }
+        float tm = 1.0f, um = 1.0f;  // t^M, (1-t)^M
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            tm *= t;
+            um *= u;
+        }
+        const float tp = tm * t, up = um * u;
+        s = tp * __builtin_fmaf(binom_f(2 * M, M), um, pu);  // the k = M term joins the sum
+        b10 = t * up * pt;
+        b11 = -u * tp * pu;
+    }
+};
 
 template <>
 struct Basis<1> {

@@ -38,6 +38,17 @@ static hipError_t launch_dyn(void (*kernel)(Args), dim3 grid, size_t lds, hipStr
     return launch_k(kernel, grid, dim3(256), lds, s, a);
 }
 
+// Orders 4..6 (64-row tiles; gradient or height-and-gradient model).
+template <int M>
+static hipError_t launch_2d_high(const Fbm2dArgs &a, bool f16, dim3 grid, size_t lds, hipStream_t s)
+{
+    if (a.model == 2)
+        return f16 ? launch_dyn(k_fbm2d_general<M, __half, 64, 2>, grid, lds, s, a)
+                   : launch_dyn(k_fbm2d_general<M, float, 64, 2>, grid, lds, s, a);
+    return f16 ? launch_dyn(k_fbm2d_general<M, __half, 64>, grid, lds, s, a)
+               : launch_dyn(k_fbm2d_general<M, float, 64>, grid, lds, s, a);
+}
+
 template <int TH>
 static hipError_t launch_2d_th(const Fbm2dArgs &a, int smooth, bool f16, dim3 grid, size_t lds, hipStream_t s)
 {
@@ -68,6 +79,10 @@ hipError_t launch_fbm2d_general(const Fbm2dArgs &a, int smooth, bool f16, size_t
 {
     const int64_t tiles = (int64_t)a.tiles_x * ((a.ny + a.tile_h - 1) / a.tile_h);
     dim3 grid((unsigned)tiles);
+    if (smooth >= 4)  // the plan gives these orders 64-row tiles
+        return smooth == 4 ? launch_2d_high<4>(a, f16, grid, lds, s)
+             : smooth == 5 ? launch_2d_high<5>(a, f16, grid, lds, s)
+                           : launch_2d_high<6>(a, f16, grid, lds, s);
     switch (a.tile_h) {
     case 16: return launch_2d_th<16>(a, smooth, f16, grid, lds, s);
     case 32: return launch_2d_th<32>(a, smooth, f16, grid, lds, s);
@@ -106,6 +121,15 @@ static hipError_t launch_3g(const Fbm3dArgs &a, int smooth, bool f16, dim3 grid,
     if (smooth == 3)
         return f16 ? launch_dyn(k_fbm3d_general<3, __half, MD>, grid, lds, s, a)
                    : launch_dyn(k_fbm3d_general<3, float, MD>, grid, lds, s, a);
+    if (smooth == 4)
+        return f16 ? launch_dyn(k_fbm3d_general<4, __half, MD>, grid, lds, s, a)
+                   : launch_dyn(k_fbm3d_general<4, float, MD>, grid, lds, s, a);
+    if (smooth == 5)
+        return f16 ? launch_dyn(k_fbm3d_general<5, __half, MD>, grid, lds, s, a)
+                   : launch_dyn(k_fbm3d_general<5, float, MD>, grid, lds, s, a);
+    if (smooth == 6)
+        return f16 ? launch_dyn(k_fbm3d_general<6, __half, MD>, grid, lds, s, a)
+                   : launch_dyn(k_fbm3d_general<6, float, MD>, grid, lds, s, a);
     return f16 ? launch_dyn(k_fbm3d_general<2, __half, MD>, grid, lds, s, a)
                : launch_dyn(k_fbm3d_general<2, float, MD>, grid, lds, s, a);
 }

@@ -77,29 +77,42 @@ static int resident_st(int lo, int waves, size_t lds)
     }
 }
 
-// model 1 (zero-gradient) is smoothness 1 only; model 2 (heights and gradients) either
+template <int M, int MD>
+static int resident_m(bool f16, int lo, int waves, size_t lds)
+{
+    return f16 ? resident_st<M, __half, MD>(lo, waves, lds) : resident_st<M, float, MD>(lo, waves, lds);
+}
+
+// model 1 (zero-gradient) is smoothness 1 only; models 0 and 2 smoothness 1, 2 or 3
 int strip_wgs_per_cu(int smooth, int model, bool f16, int lo, int waves, size_t lds)
 {
-    if (model == 1) return f16 ? resident_st<1, __half, 1>(lo, waves, lds) : resident_st<1, float, 1>(lo, waves, lds);
-    if (model == 2 && smooth == 1)
-        return f16 ? resident_st<1, __half, 2>(lo, waves, lds) : resident_st<1, float, 2>(lo, waves, lds);
-    if (model == 2) return f16 ? resident_st<2, __half, 2>(lo, waves, lds) : resident_st<2, float, 2>(lo, waves, lds);
-    if (smooth == 1) return f16 ? resident_st<1, __half, 0>(lo, waves, lds) : resident_st<1, float, 0>(lo, waves, lds);
-    return f16 ? resident_st<2, __half, 0>(lo, waves, lds) : resident_st<2, float, 0>(lo, waves, lds);
+    if (model == 1) return resident_m<1, 1>(f16, lo, waves, lds);
+    if (model == 2)
+        return smooth == 1 ? resident_m<1, 2>(f16, lo, waves, lds)
+             : smooth == 2 ? resident_m<2, 2>(f16, lo, waves, lds)
+                           : resident_m<3, 2>(f16, lo, waves, lds);
+    return smooth == 1 ? resident_m<1, 0>(f16, lo, waves, lds)
+         : smooth == 2 ? resident_m<2, 0>(f16, lo, waves, lds)
+                       : resident_m<3, 0>(f16, lo, waves, lds);
+}
+
+template <int M, int MD>
+static hipError_t launch_m(const Fbm2dStripArgs &a, bool f16, int grid, int waves, size_t lds, hipStream_t s)
+{
+    return f16 ? launch_lo<M, __half, MD>(a, grid, waves, lds, s) : launch_lo<M, float, MD>(a, grid, waves, lds, s);
 }
 
 hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, int model, bool f16, int grid, int waves,
                               size_t lds, hipStream_t s)
 {
-    if (model == 1)
-        return f16 ? launch_lo<1, __half, 1>(a, grid, waves, lds, s) : launch_lo<1, float, 1>(a, grid, waves, lds, s);
-    if (model == 2 && smooth == 1)
-        return f16 ? launch_lo<1, __half, 2>(a, grid, waves, lds, s) : launch_lo<1, float, 2>(a, grid, waves, lds, s);
+    if (model == 1) return launch_m<1, 1>(a, f16, grid, waves, lds, s);
     if (model == 2)
-        return f16 ? launch_lo<2, __half, 2>(a, grid, waves, lds, s) : launch_lo<2, float, 2>(a, grid, waves, lds, s);
-    if (smooth == 1)
-        return f16 ? launch_lo<1, __half, 0>(a, grid, waves, lds, s) : launch_lo<1, float, 0>(a, grid, waves, lds, s);
-    return f16 ? launch_lo<2, __half, 0>(a, grid, waves, lds, s) : launch_lo<2, float, 0>(a, grid, waves, lds, s);
+        return smooth == 1 ? launch_m<1, 2>(a, f16, grid, waves, lds, s)
+             : smooth == 2 ? launch_m<2, 2>(a, f16, grid, waves, lds, s)
+                           : launch_m<3, 2>(a, f16, grid, waves, lds, s);
+    return smooth == 1 ? launch_m<1, 0>(a, f16, grid, waves, lds, s)
+         : smooth == 2 ? launch_m<2, 0>(a, f16, grid, waves, lds, s)
+                       : launch_m<3, 0>(a, f16, grid, waves, lds, s);
 }
 
 // The FP16 / BF16 precision form (cubic cells, gradient model, FP16 output).

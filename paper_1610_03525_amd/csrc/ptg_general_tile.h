@@ -126,7 +126,7 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
             float s, b10, b11;
             Basis<M>::eval(c.t, s, b10, b11);
             rowt[tid] = make_float4(__int_as_float((int)(c.cell - cyf)), s, b10, b11);
-            if (GRAD) {
+            if constexpr (GRAD) {
                 float ds, db10, db11;
                 BasisD<M>::eval(c.t, ds, db10, db11);
                 rowd[tid] = make_float4(ds, db10, db11, 0.0f);
@@ -190,7 +190,7 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
         const int lcx = (int)(cc.cell - cxf);
         float sx, b10x, b11x, dsx = 0.0f, db10x = 0.0f, db11x = 0.0f;
         Basis<M>::eval(cc.t, sx, b10x, b11x);
-        if (GRAD) BasisD<M>::eval(cc.t, dsx, db10x, db11x);
+        if constexpr (GRAD) BasisD<M>::eval(cc.t, dsx, db10x, db11x);
         const float fo = (float)f;  // d/dX = f d/dt
         __syncthreads();
 

@@ -259,12 +259,14 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     const bool dy = dyadic_shift(p, &k);
     if (p->path == PTG_PATH_DYADIC && !dy)
         return fail(PTG_EINVAL, "the dyadic kernel needs base_freq = 2^-k (k <= %d) and lacunarity 2", kDyMaxShift);
-    if (p->path == PTG_PATH_DYADIC && p->smoothness == 3)
-        return fail(PTG_EINVAL, "septic cells (smoothness 3) run on the general kernel only");
-    if (dy && p->path != PTG_PATH_GENERAL && p->smoothness <= 2) {
+    if (p->path == PTG_PATH_DYADIC && p->smoothness > 3)
+        return fail(PTG_EINVAL, "smoothness orders above 3 run on the general kernel only");
+    if (dy && p->path != PTG_PATH_GENERAL && p->smoothness <= 3) {
         int rc = fbm2d_strip(p, k, x0, y0, nx, ny, out, pitch, s);
         if (rc <= 0) return rc;
-        if (p->model == PTG_MODEL_GRADIENT) {  // the matrix-core tile kernel has gradient-model cells only
+        // the tile kernel (the strip kernel's fallback when a strip's footprint does not fit
+        // LDS) has gradient-model C1 / C2 cells only
+        if (p->model == PTG_MODEL_GRADIENT && p->smoothness <= 2) {
             rc = fbm2d_dyadic(p, k, x0, y0, nx, ny, out, pitch, s);
             if (rc <= 0) return rc;
         }
@@ -282,9 +284,11 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     // twice the rows), except for the height-and-gradient model, whose larger per-tile LDS
     // block then limits the workgroups per compute unit
     const int dflt = (ny >= 1024 && p->model != PTG_MODEL_HEIGHT_GRADIENT) ? 2 * kTile2 : kTile2;
-    const int tile_h = tune_pick(TuneKey{PTG_TUNE_GENERAL_2D, p->smoothness + 2 * p->model, p->out_dtype == PTG_F16,
+    // (orders above 3: 64-row tiles, whatever the table holds)
+    const int picked = tune_pick(TuneKey{PTG_TUNE_GENERAL_2D, p->smoothness + 2 * p->model, p->out_dtype == PTG_F16,
                                          size_class(nx * ny), ladder_class(freq, p->octaves)},
-                                 dflt);
+                                 p->smoothness >= 4 ? kTile2 : dflt);
+    const int tile_h = p->smoothness >= 4 ? kTile2 : picked;
     const size_t lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, tile_h, &a);
     if (tune_dry()) return PTG_OK;
     hipError_t e = launch_fbm2d_general(a, p->smoothness, p->out_dtype == PTG_F16, lds, s);
@@ -419,8 +423,8 @@ int fbm3d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t
     const bool dy = dyadic_shift(p, &k);
     if (p->path == PTG_PATH_DYADIC && !dy)
         return fail(PTG_EINVAL, "the dyadic kernel needs base_freq = 2^-k (k <= %d) and lacunarity 2", kDyMaxShift);
-    if (p->path == PTG_PATH_DYADIC && p->smoothness == 3)
-        return fail(PTG_EINVAL, "septic cells (smoothness 3) run on the general kernel only");
+    if (p->path == PTG_PATH_DYADIC && p->smoothness >= 3)
+        return fail(PTG_EINVAL, "3D smoothness orders above 2 run on the general kernel only");
     if (dy && p->path != PTG_PATH_GENERAL && p->smoothness <= 2) {
         const int rc = fbm3d_strip(p, k, x0, y0, z0, nx, ny, nz, out, s);
         if (rc <= 0) return rc;

@@ -98,8 +98,28 @@ __host__ __device__ constexpr XB row_bases(int j, int P)
     const float u = 1.0f - t;
     if (M == 1) return XB{t2 * (3.0f - 2.0f * t), t * u * u, -t2 * u};
     const float t3 = t2 * t;
+    if (M == 3) {
+        const float t4 = t2 * t2;
+        return XB{t4 * (35.0f + t * (-84.0f + t * (70.0f - 20.0f * t))),
+                  t + t4 * (-20.0f + t * (45.0f + t * (-36.0f + 10.0f * t))),
+                  t4 * (-15.0f + t * (39.0f + t * (-34.0f + 10.0f * t)))};
+    }
     return XB{t3 * (10.0f + t * (-15.0f + 6.0f * t)), t + t3 * (-6.0f + t * (8.0f - 3.0f * t)),
               t3 * (-4.0f + t * (7.0f - 3.0f * t))};
+}
+
+// Septic cells: powers of u = t - 1/2 of S and b10 (exact binary fractions; b11(u) = -b10(-u),
+// S(u) - 1/2 is odd):
+//   S   = 1/2 + 35/16 u - 35/4 u^3 + 21 u^5 - 20 u^7
+//   b10 = 11/64 - 19/32 u - 15/16 u^2 + 35/8 u^3 + 5/4 u^4 - 21/2 u^5 - u^6 + 10 u^7
+__host__ __device__ constexpr float septic_s(int e)
+{
+    return e == 1 ? 2.1875f : e == 3 ? -8.75f : e == 5 ? 21.0f : e == 7 ? -20.0f : 0.0f;
+}
+__host__ __device__ constexpr float septic_b10(int e)
+{
+    return e == 0 ? 0.171875f : e == 1 ? -0.59375f : e == 2 ? -0.9375f : e == 3 ? 4.375f : e == 4 ? 1.25f
+         : e == 5 ? -10.5f : e == 6 ? -1.0f : 10.0f;
 }
 
 struct CF {  // column form of one cell at one column
@@ -155,13 +175,18 @@ __device__ __forceinline__ void add_mapped(float (&C)[2 * M + 2], const CF &c, f
         m[1] = 1.5f * c.dE - 0.25f * Sq;
         m[2] = -0.5f * Dq;
         m[3] = Sq - 2.0f * c.dE;
-    } else {
+    } else if (M == 2) {
         m[0] = c.E0 + 0.5f * c.dE + 0.15625f * Dq;
         m[1] = 1.875f * c.dE - 0.4375f * Sq;
         m[2] = -0.75f * Dq;
         m[3] = 2.5f * Sq - 5.0f * c.dE;
         m[4] = 0.5f * Dq;
         m[D] = 6.0f * c.dE - 3.0f * Sq;
+    } else {  // septic: odd powers from dE and Sq, even powers from Dq (b11(u) = -b10(-u))
+        m[0] = c.E0 + 0.5f * c.dE + septic_b10(0) * Dq;
+#pragma unroll
+        for (int e = 1; e <= D; ++e)
+            m[e] = (e & 1) ? septic_s(e) * c.dE + septic_b10(e) * Sq : septic_b10(e) * Dq;
     }
     // Taylor shift to u = tau (repeated synthetic division), then scale u - tau = sigma v
     if (SHIFT) {
@@ -276,7 +301,7 @@ __device__ __forceinline__ void add_piece(float (&C)[2 * M + 2], const NR &lo, c
         C[2] = __builtin_fmaf(Dq, -0.5f * s2, C[2]);
         C[3] = __builtin_fmaf(Sq, s3, C[3]);
         C[3] = __builtin_fmaf(dE, -2.0f * s3, C[3]);
-    } else {
+    } else if (M == 2) {
         C[0] = __builtin_fmaf(Dq, 0.15625f, C[0]);
         C[1] = __builtin_fmaf(dE, 1.875f * s1, C[1]);
         C[1] = __builtin_fmaf(Sq, -0.4375f * s1, C[1]);
@@ -286,6 +311,19 @@ __device__ __forceinline__ void add_piece(float (&C)[2 * M + 2], const NR &lo, c
         C[4] = __builtin_fmaf(Dq, 0.5f * s4, C[4]);
         C[5] = __builtin_fmaf(dE, 6.0f * s5, C[5]);
         C[5] = __builtin_fmaf(Sq, -3.0f * s5, C[5]);
+    } else {  // septic
+        C[0] = __builtin_fmaf(Dq, septic_b10(0), C[0]);
+        float sp = 1.0f;
+#pragma unroll
+        for (int e = 1; e <= 2 * M + 1; ++e) {
+            sp *= s1;  // SIG^e (exact)
+            if (e & 1) {
+                C[e] = __builtin_fmaf(dE, septic_s(e) * sp, C[e]);
+                C[e] = __builtin_fmaf(Sq, septic_b10(e) * sp, C[e]);
+            } else {
+                C[e] = __builtin_fmaf(Dq, septic_b10(e) * sp, C[e]);
+            }
+        }
     }
 }
 
@@ -353,9 +391,14 @@ __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[
         float odd, even2 = 0.0f;
         if (M == 1) {
             odd = __builtin_fmaf(Cs[3], w2, Cs[1]);
-        } else {
-            odd = __builtin_fmaf(__builtin_fmaf(Cs[5], w2, Cs[3]), w2, Cs[1]);
-            even2 = __builtin_fmaf(Cs[4], w2, Cs[2]);
+        } else {  // odd part in w^2 (C1, C3, ...) and the even part beyond C0 (C2, C4, ...)
+            constexpr int D = 2 * M + 1;
+            odd = Cs[D];
+#pragma unroll
+            for (int e = D - 2; e >= 1; e -= 2) odd = __builtin_fmaf(odd, w2, Cs[e]);
+            even2 = Cs[D - 1];
+#pragma unroll
+            for (int e = D - 3; e >= 2; e -= 2) even2 = __builtin_fmaf(even2, w2, Cs[e]);
         }
 #pragma unroll
         for (int side = 0; side < 2; ++side) {

@@ -39,12 +39,20 @@ def test_model_validation():
                dict(model="height_gradient", gradient_weight=float("nan"))):
         p = ptg.params(base_freq=1 / 64, octaves=3, **kw)
         assert L.ptg_fbm_2d(ctypes.byref(p), 0, 0, 16, 16, ctypes.c_void_p(1 << 20), 16, None) == ptg.PTG_EINVAL
-    # septic cells: general kernels only (no matrix-core form, no dyadic path, not served)
-    for kw in (dict(smoothness=3, form="mfma_f16"), dict(smoothness=3, path="dyadic")):
+    # septic cells: the 2D strip and general kernels (no matrix-core form, not served);
+    # orders 4..6 the general kernels only; 7 is rejected
+    for kw in (dict(smoothness=3, form="mfma_f16"), dict(smoothness=4, path="dyadic"), dict(smoothness=7),
+               dict(smoothness=0)):
         p = ptg.params(base_freq=1 / 64, octaves=3, **kw)
         assert L.ptg_fbm_2d(ctypes.byref(p), 0, 0, 16, 16, ctypes.c_void_p(1 << 20), 16, None) == ptg.PTG_EINVAL
-    assert ptg.tune_query((64, 64), smoothness=3, octaves=3, base_freq=1 / 64) == ("general_2d", 64)
+    p = ptg.params(base_freq=1 / 64, octaves=3, smoothness=4)
+    assert L.ptg_fbm_2d_grad(ctypes.byref(p), 0, 0, 16, 16, ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21),
+                             ctypes.c_void_p(1 << 22), 16, None) == ptg.PTG_EINVAL
+    assert ptg.tune_query((64, 64), smoothness=3, octaves=3, base_freq=1 / 64)[0] == "strip_2d"
+    assert ptg.tune_query((64, 64), smoothness=5, octaves=3, base_freq=1 / 64) == ("general_2d", 64)
     assert ptg.tune_query((64, 64, 64), smoothness=3, octaves=3, base_freq=1 / 16) == ("general_3d", 0)
+    p3 = ptg.params(dim=3, base_freq=1 / 64, octaves=3, smoothness=3, path="dyadic")
+    assert L.ptg_fbm_3d(ctypes.byref(p3), 0, 0, 0, 8, 8, 8, ctypes.c_void_p(1 << 20), None) == ptg.PTG_EINVAL
     p3 = ptg.params(dim=3, model="zero_gradient", base_freq=1 / 64, octaves=3)
     assert L.ptg_fbm_3d(ctypes.byref(p3), 0, 0, 0, 8, 8, 8, ctypes.c_void_p(1 << 20), None) == ptg.PTG_EINVAL
     p3 = ptg.params(dim=3, model="height_gradient", base_freq=1 / 64, octaves=3, form="mfma_f16")
@@ -76,7 +84,7 @@ def _fbm2(p, x0=0, y0=0, nx=16, ny=16, out=1 << 20, pitch=16):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("dim", 3), ("smoothness", 0), ("smoothness", 4), ("octaves", 0), ("octaves", 17), ("out_dtype", 5),
+    ("dim", 3), ("smoothness", 0), ("smoothness", 7), ("octaves", 0), ("octaves", 17), ("out_dtype", 5),
     ("persistence", 0.0), ("persistence", float("nan")), ("lacunarity", -2.0), ("base_freq", 0.0),
     ("base_freq", float("inf")), ("form", 9), ("basis", 7), ("path", 3), ("path", -1),
 ])
