@@ -315,7 +315,7 @@ def other_configs(torch, ptg, stream):
     q = ptg.params(smoothness=3, octaves=8, base_freq=16 / 8192, seed=1)
     ms = _time_launches(torch, stream, lambda: ptg.fbm_2d_raw(q, 0, 0, 8192, 8192, zf.data_ptr(), 8192, sh), 5)
     res["2d_8192_8oct_c3"] = {"workload": "septic (C3) cells, gradient model, 8192^2, 8 octaves, base lattice 16^2, "
-                                          "FP32, seed 1 (general kernel)",
+                                          "FP32, seed 1 (strip kernel)",
                               "ms": ms, "octave_samples_s": 8192 * 8192 * 8 / (ms * 1e-3),
                               "hbm_frac": 8192 * 8192 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     progress("height-gradient and septic done")
@@ -332,6 +332,25 @@ def other_configs(torch, ptg, stream):
         "workload": "heights and gradients (weight 0.01) in tensor Hermite cells, 8192^2, 8 octaves, base lattice "
                     "16^2, FP32, seed 1, strip kernel",
         "smoothness": hg}
+    # comparison paths at the same field's parameters: Perlin's noise (S3 and S5 fades) on the
+    # general kernel, the simplex-lattice noise on its own kernel, and the polynomial cells
+    # on the general kernel (the same tile machinery as Perlin) and the strip kernel
+    cmp = {}
+    for name, kw in (("polynomial_c1_strip", dict(smoothness=1)),
+                     ("polynomial_c1_general", dict(smoothness=1, path="general")),
+                     ("perlin_s3_general", dict(model="perlin", smoothness=1)),
+                     ("perlin_s5_general", dict(model="perlin", smoothness=2)),
+                     ("simplex_lattice", dict(model="simplex"))):
+        q = ptg.params(octaves=8, base_freq=16 / 8192, seed=1, **kw)
+        ms = _time_launches(torch, stream, lambda: ptg.fbm_2d_raw(q, 0, 0, 8192, 8192, zf.data_ptr(), 8192, sh), 5)
+        cmp[name] = {"ms": ms, "octave_samples_s": 8192 * 8192 * 8 / (ms * 1e-3),
+                     "hbm_frac": 8192 * 8192 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        progress(f"comparison path {name}: {ms * 1e3:.1f} us")
+    res["2d_8192_8oct_comparison_paths"] = {
+        "workload": "8192^2, 8 octaves, base lattice 16^2, persistence 0.5, FP32, seed 1: Perlin's gradient noise "
+                    "(Sec. 3.2) and simplex-lattice gradient noise (standing for the paper's OpenSimplex) on the "
+                    "same hashed unit gradients, next to the polynomial C1 cells",
+        "paths": cmp}
     del zf
     # 256^2, 4 octaves, base lattice 8^2
     small = torch.empty((256, 256), dtype=torch.float32, device="cuda")

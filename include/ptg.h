@@ -118,6 +118,20 @@ extern "C" {
                                    /* w); C1 / C2 across faces.  2D and 3D, plain form,     */
                                    /* fields only (not served)                              */
 
+#define PTG_MODEL_PERLIN 3          /* comparison path: Perlin's gradient noise (Sec. 3.2)  */
+                                   /* on the same hashed unit gradients, corner            */
+                                   /* contributions g . (t - c) blended with the fade S3    */
+                                   /* (smoothness 1) or S5 (smoothness 2).  2D, plain form, */
+                                   /* general kernel, fields only (not served)              */
+#define PTG_MODEL_SIMPLEX 4         /* comparison path standing for the paper's OpenSimplex  */
+                                   /* timings (Sec. 5.2; the paper does not define it):     */
+                                   /* 2D simplex-lattice gradient noise written from its    */
+                                   /* public mathematical description -- skew (sqrt3-1)/2,  */
+                                   /* unskew (3-sqrt3)/6, corner kernel max(0, 1/2 -        */
+                                   /* |d|^2)^4 (g . d), g the hashed unit gradient of the   */
+                                   /* skewed index, sum x 70.  2D, smoothness 1, plain form, */
+                                   /* fields only (not served)                              */
+
 /* Problem parameters (Sec. 2.2 DdMmNn naming: dim = d, smoothness = m, n = 2m+1;
  * Sec. 4: octaves, persistence, lacunarity). */
 typedef struct ptg_params {

@@ -83,6 +83,9 @@ def lib():
     L.orc_hg_cell.argtypes = [_i32, _pd, _pd, _f64, _f64, _f64]
     L.orc_hg_cell.restype = _f64
     L.orc_hg_fbm_2d.argtypes = [_i32, _i32, _f64, _f64, _f64, _f64, _u32, _i64, _i64, _i64, _i64, _pd, _i32]
+    L.orc_simplex_at.argtypes = [_f64, _f64, _i32, _u32]
+    L.orc_simplex_at.restype = _f64
+    L.orc_simplex_2d.argtypes = [_i32, _f64, _f64, _f64, _u32, _i64, _i64, _i64, _i64, _pd, _i32]
     L.orc_height3.argtypes = [_u32]
     L.orc_height3.restype = _f64
     L.orc_hg_cell_3d.argtypes = [_i32, _pd, _pd, _f64, _f64, _f64, _f64]
@@ -328,6 +331,17 @@ def hg_fbm_points_2d(smooth, octaves, pers, lac, f0, w, seed, X, Y, nthreads=0) 
     out = np.empty(X.shape[0], dtype=np.float64)
     _chk(lib().orc_hg_fbm_points_2d(smooth, octaves, pers, lac, f0, w, seed & 0xFFFFFFFF, _ip(X), _ip(Y), X.shape[0],
                                     _dp(out), nthreads))
+    return out
+
+
+def simplex_at(ux: float, uy: float, octave: int, seed: int) -> float:
+    """Simplex-lattice gradient noise of one octave at lattice coordinates (ux, uy)."""
+    return float(lib().orc_simplex_at(ux, uy, octave, seed & 0xFFFFFFFF))
+
+
+def simplex_2d(octaves, pers, lac, f0, seed, x0, y0, nx, ny, nthreads=0) -> np.ndarray:
+    out = np.empty((ny, nx), dtype=np.float64)
+    _chk(lib().orc_simplex_2d(octaves, pers, lac, f0, seed & 0xFFFFFFFF, x0, y0, nx, ny, _dp(out), nthreads))
     return out
 
 

@@ -420,6 +420,40 @@ double orc_perlin_cell(int32_t fade_order, const double *grad, double x, double 
     return h0 + sy * (h1 - h0);
 }
 
+/* Simplex-lattice gradient noise (the comparison path standing for the paper's OpenSimplex
+ * timings, Sec. 5.2; the paper does not define it).  Written from the public mathematical
+ * description of 2D simplex noise: the point u is skewed by F2 = (sqrt 3 - 1) / 2 onto the
+ * square lattice (i, j) = floor(u + (ux + uy) F2), the cell's lower or upper triangle is
+ * chosen by comparing the unskewed offsets, and each of the three corners c (unskewed by
+ * G2 = (3 - sqrt 3) / 6) contributes max(0, 1/2 - |d|^2)^4 (g_c . d), d = u minus the
+ * corner, with g_c the unit gradient the lattice hash gives the skewed index; the sum is
+ * scaled by 70.  PARITY UNPINNED against any outside implementation: the tests pin only
+ * its own properties (zero at lattice points, gradient 70 / 16 g there, smoothness). */
+static double orc_simplex_corner(int64_t i, int64_t j, int32_t octave, uint32_t seed, double dx, double dy)
+{
+    const double t = 0.5 - dx * dx - dy * dy;
+    if (t <= 0.0) return 0.0;
+    double g[2];
+    orc_grad2(orc_key2(i, j, octave, seed), g);
+    const double t2 = t * t;
+    return t2 * t2 * (g[0] * dx + g[1] * dy);
+}
+
+double orc_simplex_at(double ux, double uy, int32_t octave, uint32_t seed)
+{
+    const double F2 = 0.5 * (sqrt(3.0) - 1.0), G2 = (3.0 - sqrt(3.0)) / 6.0;
+    const double s = (ux + uy) * F2;
+    const double fi = floor(ux + s), fj = floor(uy + s);
+    const double t = (fi + fj) * G2;
+    const double x0 = ux - (fi - t), y0 = uy - (fj - t);
+    const int i1 = x0 > y0 ? 1 : 0, j1 = 1 - i1;
+    const int64_t i = (int64_t)fi, j = (int64_t)fj;
+    double n = orc_simplex_corner(i, j, octave, seed, x0, y0);
+    n += orc_simplex_corner(i + i1, j + j1, octave, seed, x0 - i1 + G2, y0 - j1 + G2);
+    n += orc_simplex_corner(i + 1, j + 1, octave, seed, x0 - 1.0 + 2.0 * G2, y0 - 1.0 + 2.0 * G2);
+    return 70.0 * n;
+}
+
 /* ------------------------------------------------------------------------- */
 /* fBm over samples                                                          */
 /* ------------------------------------------------------------------------- */
@@ -573,6 +607,26 @@ int orc_perlin_2d(int32_t fade_order, int32_t octaves, double pers, double lac, 
                         orc_grad2(orc_key2(cx + dx, cy + dy, o, seed), &grad[2 * (dx + 2 * dy)]);
                 H += amp[o] * orc_perlin_cell(fade_order, grad, tx, ty);
             }
+            out[j * nx + i] = H;
+        }
+    return ORC_OK;
+}
+
+/* Simplex-lattice fBm (comparison path, parity unpinned): octave o at u = (X + 1/2) f_o. */
+int orc_simplex_2d(int32_t octaves, double pers, double lac, double f0, uint32_t seed, int64_t x0, int64_t y0,
+                   int64_t nx, int64_t ny, double *out, int32_t nthreads)
+{
+    if (orc_check(1, octaves, f0, lac, pers) != ORC_OK || nx < 0 || ny < 0 || !out) return ORC_EINVAL;
+    double freq[ORC_MAX_OCTAVES], amp[ORC_MAX_OCTAVES];
+    orc_octave_params(f0, lac, pers, octaves, freq, amp);
+    orc_set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i) {
+            double H = 0.0;
+            for (int32_t o = 0; o < octaves; ++o)
+                H += amp[o] * orc_simplex_at(((double)(x0 + i) + 0.5) * freq[o], ((double)(y0 + j) + 0.5) * freq[o],
+                                             o, seed);
             out[j * nx + i] = H;
         }
     return ORC_OK;

@@ -32,10 +32,12 @@ PTG_F16 = 1
 FORMS = {"plain": 0, "mfma_f16": 1, "mfma_bf16": 2}
 BASES = {"monomial": 0, "centred": 1, "hermite": 2}
 PATHS = {"auto": 0, "general": 1, "dyadic": 2}
-MODELS = {"gradient": 0, "zero_gradient": 1, "height_gradient": 2}
+MODELS = {"gradient": 0, "zero_gradient": 1, "height_gradient": 2, "perlin": 3, "simplex": 4}
 PTG_MODEL_GRADIENT = 0
 PTG_MODEL_ZERO_GRADIENT = 1
 PTG_MODEL_HEIGHT_GRADIENT = 2
+PTG_MODEL_PERLIN = 3
+PTG_MODEL_SIMPLEX = 4
 
 
 class PtgError(RuntimeError):

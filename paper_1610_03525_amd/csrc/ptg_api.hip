@@ -54,8 +54,15 @@ int validate_params(const ptg_params *p, int dim)
         return fail(PTG_EINVAL, "the matrix-core forms write FP16 output");
     if (p->path != PTG_PATH_AUTO && p->path != PTG_PATH_GENERAL && p->path != PTG_PATH_DYADIC)
         return fail(PTG_EINVAL, "unknown path %d", p->path);
-    if (p->model != PTG_MODEL_GRADIENT && p->model != PTG_MODEL_ZERO_GRADIENT && p->model != PTG_MODEL_HEIGHT_GRADIENT)
+    if (p->model != PTG_MODEL_GRADIENT && p->model != PTG_MODEL_ZERO_GRADIENT && p->model != PTG_MODEL_HEIGHT_GRADIENT &&
+        p->model != PTG_MODEL_PERLIN && p->model != PTG_MODEL_SIMPLEX)
         return fail(PTG_EINVAL, "unknown model %d", p->model);
+    if (p->model == PTG_MODEL_SIMPLEX &&
+        (dim != 2 || p->smoothness != 1 || p->form != PTG_FORM_PLAIN || p->path == PTG_PATH_DYADIC))
+        return fail(PTG_EINVAL, "the simplex-lattice noise is 2D, smoothness 1, plain form, its own kernel");
+    if (p->model == PTG_MODEL_PERLIN &&
+        (dim != 2 || p->smoothness > 2 || p->form != PTG_FORM_PLAIN || p->path == PTG_PATH_DYADIC))
+        return fail(PTG_EINVAL, "Perlin's noise is 2D, fade S3 or S5 (smoothness 1, 2), plain form, general kernel");
     if (p->model == PTG_MODEL_HEIGHT_GRADIENT && p->form != PTG_FORM_PLAIN)
         return fail(PTG_EINVAL, "the height-and-gradient model is plain form");
     if (p->model == PTG_MODEL_HEIGHT_GRADIENT && !std::isfinite(p->gradient_weight))
@@ -160,6 +167,8 @@ int ptg_fbm_2d_grad(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int
     if (rc) return rc;
     if (p->form != PTG_FORM_PLAIN) return fail(PTG_EINVAL, "the gradient output is computed in the plain form");
     if (p->smoothness > 3) return fail(PTG_EINVAL, "the gradient output takes smoothness 1..3");
+    if (p->model == PTG_MODEL_PERLIN || p->model == PTG_MODEL_SIMPLEX)
+        return fail(PTG_EINVAL, "the gradient output takes the cell models");
     if ((rc = validate_extent("x", x0, nx))) return rc;
     if ((rc = validate_extent("y", y0, ny))) return rc;
     if (nx == 0 || ny == 0) return PTG_OK;

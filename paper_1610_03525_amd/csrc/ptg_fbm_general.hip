@@ -52,6 +52,11 @@ static hipError_t launch_2d_high(const Fbm2dArgs &a, bool f16, dim3 grid, size_t
 template <int TH>
 static hipError_t launch_2d_th(const Fbm2dArgs &a, int smooth, bool f16, dim3 grid, size_t lds, hipStream_t s)
 {
+    if (a.model == 3)  // Perlin's noise (fade S3 / S5: smoothness 1 / 2, validated)
+        return smooth == 1 ? (f16 ? launch_dyn(k_fbm2d_general<1, __half, TH, 3>, grid, lds, s, a)
+                                  : launch_dyn(k_fbm2d_general<1, float, TH, 3>, grid, lds, s, a))
+                           : (f16 ? launch_dyn(k_fbm2d_general<2, __half, TH, 3>, grid, lds, s, a)
+                                  : launch_dyn(k_fbm2d_general<2, float, TH, 3>, grid, lds, s, a));
     if (a.model == 1)  // zero-gradient model (smoothness 1, validated)
         return f16 ? launch_dyn(k_fbm2d_general<1, __half, TH, 1>, grid, lds, s, a)
                    : launch_dyn(k_fbm2d_general<1, float, TH, 1>, grid, lds, s, a);

@@ -73,6 +73,11 @@ struct LatCache {
 // so the row evaluation is the gradient model's with Q0 = Q1 = dQ.
 // MD = 2: heights and w-weighted gradients (tensor Hermite): gh holds the heights, gx / gy
 // the gradients times w, and a node row's value term gains h0j (1 - S(x)) + h1j S(x).
+// MD = 3: Perlin's gradient noise (Sec. 3.2; the comparison path), fade S3 (M = 1) or S5
+// (M = 2): v_c = g_c . (t - c), h = lerp_y(lerp_x(v00, v10, S(x)), lerp_x(v01, v11, S(x)), S(y)).
+// At the lane's column h = a0 + a1 y + S(y) (b0 - b1 - a0) + S(y) y (b1 - a1) with
+// h0 = a0 + a1 y and h1 = b0 + b1 (y - 1) the x-lerps of the node rows, so the row table
+// holds (S(y), y, S(y) y) and the row evaluation keeps its shape.
 // GRAD: also the analytic gradient dH/dX, dH/dY (to a.out_dx, a.out_dy): per octave the
 // cell's derivatives in its local coordinates times the octave frequency; the x-derivative
 // is the same row form with the x-bases differentiated, the y-derivative the row form with
@@ -125,6 +130,10 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
             const Coord c = coord_step(Yf + r, f);
             float s, b10, b11;
             Basis<M>::eval(c.t, s, b10, b11);
+            if (MD == 3) {  // Perlin: (S(y), y, S(y) y)
+                b10 = c.t;
+                b11 = s * c.t;
+            }
             rowt[tid] = make_float4(__int_as_float((int)(c.cell - cyf)), s, b10, b11);
             if constexpr (GRAD) {
                 float ds, db10, db11;
@@ -216,6 +225,18 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
                     Q0x = (dsx - 1.0f) * (d1 - d0);
                     Q1x = Q0x;
                 }
+            } else if (lcy != prev && MD == 3) {  // Perlin (see above)
+                prev = lcy;
+                const int q = lcy * nnx + lcx;
+                const float fx00 = gx[q], fx10 = gx[q + 1], fx01 = gx[q + nnx], fx11 = gx[q + nnx + 1];
+                const float fy00 = gy[q], fy10 = gy[q + 1], fy01 = gy[q + nnx], fy11 = gy[q + nnx + 1];
+                const float tx = cc.t, tx1 = cc.t - 1.0f;
+                const float a0 = fx00 * tx + sx * (fx10 * tx1 - fx00 * tx), a1 = fy00 + sx * (fy10 - fy00);
+                const float b0 = fx01 * tx + sx * (fx11 * tx1 - fx01 * tx), b1 = fy01 + sx * (fy11 - fy01);
+                E0 = a0;
+                dE = b0 - b1 - a0;
+                Q0 = a1;
+                Q1 = b1 - a1;
             } else if (lcy != prev) {
                 prev = lcy;
                 const int q = lcy * nnx + lcx;

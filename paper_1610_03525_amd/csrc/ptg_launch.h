@@ -227,6 +227,12 @@ hipError_t launch_fbm2d_strip_mx(const Fbm2dStripArgs &a, int prec, int grid, in
 int strip_mx_wgs_per_cu(int prec, int lo, int waves, size_t lds_bytes);
 hipError_t launch_fbm3d_general(const Fbm3dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fbm2d_general_grad(const Fbm2dArgs &a, int smooth, bool f16, size_t lds_bytes, hipStream_t s);
+// Simplex-lattice comparison path (ptg_simplex.hip): 64 x 64 tiles; a tile's skewed lattice
+// footprint is staged in LDS when it has at most kSimplexKeys nodes per axis and
+// kSimplexCap nodes.
+constexpr int kSimplexCap = 6144;
+constexpr int kSimplexKeys = 128;
+hipError_t launch_simplex2d(const Fbm2dArgs &a, bool f16, hipStream_t s);
 hipError_t launch_fbm3d_strip(const Fbm3dStripArgs &a, int smooth, bool f16, int grid, int waves, size_t lds_bytes,
                               hipStream_t s);
 int strip3_wgs_per_cu(int smooth, int model, bool f16, int lo, int waves, size_t lds_bytes);

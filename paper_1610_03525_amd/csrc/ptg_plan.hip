@@ -255,13 +255,22 @@ size_t general_args_3d(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, 
 int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out, int64_t pitch,
                 hipStream_t s)
 {
+    if (p->model == PTG_MODEL_SIMPLEX) {  // comparison path: its own kernel for any ladder
+        Fbm2dArgs a{};
+        (void)general_args_2d(p, x0, y0, nx, ny, out, pitch, kTile2, &a);
+        (void)tune_pick(TuneKey{PTG_TUNE_GENERAL_2D, p->smoothness + 2 * p->model, p->out_dtype == PTG_F16, size_class(nx * ny), 0},
+                        kTile2);
+        if (tune_dry()) return PTG_OK;
+        hipError_t e = launch_simplex2d(a, p->out_dtype == PTG_F16, s);
+        return e == hipSuccess ? PTG_OK : hip_fail(e, "simplex launch");
+    }
     int k = 0;
     const bool dy = dyadic_shift(p, &k);
     if (p->path == PTG_PATH_DYADIC && !dy)
         return fail(PTG_EINVAL, "the dyadic kernel needs base_freq = 2^-k (k <= %d) and lacunarity 2", kDyMaxShift);
     if (p->path == PTG_PATH_DYADIC && p->smoothness > 3)
         return fail(PTG_EINVAL, "smoothness orders above 3 run on the general kernel only");
-    if (dy && p->path != PTG_PATH_GENERAL && p->smoothness <= 3) {
+    if (dy && p->path != PTG_PATH_GENERAL && p->smoothness <= 3 && p->model != PTG_MODEL_PERLIN) {
         int rc = fbm2d_strip(p, k, x0, y0, nx, ny, out, pitch, s);
         if (rc <= 0) return rc;
         // the tile kernel (the strip kernel's fallback when a strip's footprint does not fit

@@ -33,7 +33,8 @@ def test_model_validation():
     ok = ptg.params(model="zero_gradient", base_freq=1 / 64, octaves=3)
     assert ptg.lib().ptg_tune_query_2d(ctypes.byref(ok), 64, 64, ctypes.byref(ctypes.c_int32()),
                                        ctypes.byref(ctypes.c_int32())) == ptg.PTG_OK
-    for kw in (dict(model=3), dict(model=-1), dict(model="zero_gradient", smoothness=2),
+    for kw in (dict(model=5), dict(model=-1), dict(model="zero_gradient", smoothness=2),
+               dict(model="perlin", smoothness=3), dict(model="perlin", path="dyadic"), dict(model="simplex", smoothness=2),
                dict(model="zero_gradient", form="mfma_f16"), dict(model="height_gradient", form="mfma_bf16"),
                dict(model="height_gradient", gradient_weight=float("inf")),
                dict(model="height_gradient", gradient_weight=float("nan"))):
