@@ -525,8 +525,23 @@ def run_serving(n):
         out["bytes_peak"] = st["bytes_peak"]
         return out
 
+    def solo():
+        arr, done, st = i64(np.zeros(n)), i64(np.zeros(n)), i64(np.zeros(3))
+        rc = lg.ptg_lg_plain(treq, ptr(arr), n, arena.data_ptr(), arena_bytes, 2, 1, ptr(done), ptr(st))
+        if rc != 0:
+            raise RuntimeError(f"solo pass failed ({rc}): {ptg.last_error()}")
+        total = done.sum() / 1e9
+        out = {"kernel_s_sum": round(float(total), 6), "tiles_s_bound": round(n / total, 1),
+               "octave_samples_s_bound": osamp / total,
+               "kernel_ms_p50": round(float(np.percentile(done / 1e6, 50)), 4)}
+        progress(f"solo kernels: {out}")
+        return out
+
     zero = np.zeros(n)
+    bound = solo()
     cap = {"plain": plain(zero, 0), "plain_graph": plain(zero, 1), "served": served(zero, 4 << 30)}
+    for v in cap.values():
+        v["frac_of_solo_bound"] = round(v["tiles_s"] / bound["tiles_s_bound"], 4)
     rate = cap["plain"]["tiles_s"]
     gaps = np.random.default_rng(1611).exponential(1.0, size=n)
     loads = []
@@ -553,6 +568,10 @@ def run_serving(n):
                       "batch shape, arguments updated when a shape recurs)",
         "served_path": "ptg_tiles_submit into one persistent kernel (dyadic 2D / 3D requests on the strip "
                        "code, the rest on general tiles), HBM budget 4 GiB",
+        "solo_bound": bound,
+        "solo_bound_note": "each request's kernels timed alone between two events (plain path, auto kernel "
+                           "choice), one after the other; the sum is the GPU time the stream needs without "
+                           "overlap between requests",
         "capacity": cap,
         "open_loop": loads,
         "served_budget_at_0.8": budgets,

@@ -436,7 +436,11 @@ PTG_API int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out);
 PTG_API int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n, uint64_t *tickets_out);
 
 /* Wait up to timeout_ns (0: poll, < 0: forever) for a ticket and fill *res.
- * Errors: PTG_ETIMEDOUT (still pending), PTG_ENOENT (unknown or released ticket). */
+ * Errors: PTG_ETIMEDOUT (still pending), PTG_ENOENT (unknown or released ticket),
+ * PTG_EAGAIN (the request cannot be admitted until the caller releases completed outputs:
+ * it is pending, nothing is in flight, and the arena bytes it needs are held by completed
+ * requests not yet released -- reported once that state has lasted a few milliseconds;
+ * release some, then wait again). */
 PTG_API int ptg_tiles_wait(ptg_server *s, uint64_t ticket, int64_t timeout_ns, ptg_tile_result *res);
 
 /* Return a completed ticket's arena bytes to the server (its out_dev becomes invalid).

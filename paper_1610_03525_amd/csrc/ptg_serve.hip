@@ -386,6 +386,12 @@ class Arena {
         }
         return -1;
     }
+    int64_t largest_free() const
+    {
+        int64_t m = 0;
+        for (const auto &kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
     void release(int64_t off, int64_t bytes)
     {
         bytes = (bytes + 255) & ~int64_t(255);
@@ -1241,10 +1247,39 @@ int ptg_tiles_wait(ptg_server *s, uint64_t ticket, int64_t timeout_ns, ptg_tile_
         auto j = s->by_ticket.find(ticket);
         return j == s->by_ticket.end() || j->second.status <= 0;
     };
-    if (timeout_ns < 0)
-        s->cv_done.wait(lk, ready);
-    else if (timeout_ns > 0)
-        s->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), ready);
+    // The request waits for arena bytes that only the caller can free: it is pending, no
+    // request is in flight (nothing will complete and free bytes), and the largest free
+    // range is too small while completed outputs still hold arena bytes.
+    auto blocked_by_caller = [&] {
+        auto j = s->by_ticket.find(ticket);
+        if (j == s->by_ticket.end() || j->second.status != 1 || !s->inflight.empty()) return false;
+        bool held = false;
+        for (const auto &kv : s->by_ticket)
+            if (kv.second.status <= 0 && kv.second.arena_off >= 0) {
+                held = true;
+                break;
+            }
+        return held && s->arena->largest_free() < round256(j->second.bytes);
+    };
+    // wait in slices; the blocked state must last across a slice (the scheduler makes an
+    // admission pass in well under one) before it is reported
+    const auto slice = std::chrono::milliseconds(2);
+    const auto t_end = std::chrono::steady_clock::now() + std::chrono::nanoseconds(timeout_ns < 0 ? 0 : timeout_ns);
+    bool was_blocked = false;
+    while (!ready()) {
+        if (timeout_ns == 0) break;
+        auto until = std::chrono::steady_clock::now() + slice;
+        if (timeout_ns > 0 && until > t_end) until = t_end;
+        s->cv_done.wait_until(lk, until, ready);
+        if (ready()) break;
+        const bool b = blocked_by_caller();
+        if (b && was_blocked)
+            return fail(PTG_EAGAIN, "ticket %llu waits for arena bytes held by completed outputs that have not been "
+                                    "released (release some, then wait again)",
+                        (unsigned long long)ticket);
+        was_blocked = b;
+        if (timeout_ns > 0 && std::chrono::steady_clock::now() >= t_end) break;
+    }
     it = s->by_ticket.find(ticket);
     if (it == s->by_ticket.end()) return fail(PTG_ENOENT, "ticket released");
     const Request &r = it->second;

@@ -78,7 +78,19 @@ int ptg_lg_served(ptg_server *s, const ptg_tile_req *reqs, const int64_t *arriva
         }
     });
     int rc = PTG_OK;
+    std::vector<char> taken((size_t)n, 0);
+    auto take = [&](int32_t k, const ptg_tile_result &res) {
+        int r = res.status;
+        if (r == PTG_OK) {
+            done_ns[k] = res.t_done_ns - t0;
+            if (admit_ns) admit_ns[k] = res.t_admit_ns - t0;
+            r = ptg_tile_release(s, tickets[(size_t)k]);
+        }
+        taken[(size_t)k] = 1;
+        return r;
+    };
     for (int32_t i = 0; i < n && rc == PTG_OK; ++i) {
+        if (taken[(size_t)i]) continue;
         while (published.load(std::memory_order_acquire) <= i) {
             if (err.load() != PTG_OK) break;
             std::this_thread::yield();
@@ -89,12 +101,21 @@ int ptg_lg_served(ptg_server *s, const ptg_tile_req *reqs, const int64_t *arriva
         }
         ptg_tile_result res;
         rc = ptg_tiles_wait(s, tickets[(size_t)i], 120000000000LL, &res);
-        if (rc == PTG_OK && res.status != PTG_OK) rc = res.status;
-        if (rc == PTG_OK) {
-            done_ns[i] = res.t_done_ns - t0;
-            if (admit_ns) admit_ns[i] = res.t_admit_ns - t0;
-            rc = ptg_tile_release(s, tickets[(size_t)i]);
+        while (rc == PTG_EAGAIN) {
+            // request i waits for bytes held by later requests that completed first: take
+            // (and release) those, then wait again
+            const int32_t pub = published.load(std::memory_order_acquire);
+            for (int32_t k = i + 1; k < pub && rc == PTG_EAGAIN; ++k) {
+                if (taken[(size_t)k]) continue;
+                ptg_tile_result rk;
+                if (ptg_tiles_wait(s, tickets[(size_t)k], 0, &rk) == PTG_OK) {
+                    const int rt = take(k, rk);
+                    if (rt != PTG_OK) rc = rt;
+                }
+            }
+            if (rc == PTG_EAGAIN) rc = ptg_tiles_wait(s, tickets[(size_t)i], 120000000000LL, &res);
         }
+        if (rc == PTG_OK) rc = take(i, res);
     }
     if (rc != PTG_OK) err.store(rc);
     sub.join();
@@ -105,7 +126,7 @@ int ptg_lg_plain(const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n,
                  int32_t mode, int32_t max_batch, int64_t *done_ns, int64_t *stats)
 {
     if (!reqs || !arrival_ns || !done_ns || !arena || n < 1 || !arrivals_ok(arrival_ns, n) ||
-        (mode != PTG_LG_DIRECT && mode != PTG_LG_GRAPH) || max_batch < 1)
+        (mode != PTG_LG_DIRECT && mode != PTG_LG_GRAPH && mode != PTG_LG_SOLO) || max_batch < 1)
         return PTG_EINVAL;
     std::vector<int64_t> off((size_t)n);
     int64_t o = 0;
@@ -119,6 +140,27 @@ int ptg_lg_plain(const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n,
     }
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return PTG_EHIP;
+    if (mode == PTG_LG_SOLO) {  // each request alone: its kernel time between two events
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int rc = (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) ? PTG_OK : PTG_EHIP;
+        for (int32_t i = 0; i < n && rc == PTG_OK; ++i) {
+            if (hipEventRecord(e0, st) != hipSuccess) rc = PTG_EHIP;
+            if (rc == PTG_OK) rc = plain_call(reqs[i], (char *)arena + off[(size_t)i], st);
+            if (rc == PTG_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                rc = PTG_EHIP;
+            float ms = 0.0f;
+            if (rc == PTG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = PTG_EHIP;
+            done_ns[i] = (int64_t)((double)ms * 1e6);
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamDestroy(st);
+        if (stats) {
+            stats[0] = n;
+            stats[1] = stats[2] = 0;
+        }
+        return rc;
+    }
     // graph mode: the library's batch object (instantiates a graph once per batch shape and
     // updates its arguments for later batches of that shape)
     ptg_batch *batch = nullptr;

@@ -19,11 +19,17 @@ extern "C" {
                         /* ptg_batch and launched as one HIP graph (instantiated once per   */
                         /* batch shape, arguments updated for later batches of that shape); */
                         /* its requests complete together                                    */
+#define PTG_LG_SOLO 2   /* each request launched alone, one after the other (arrivals        */
+                        /* ignored): done_ns[i] receives request i's kernel time (ns)        */
+                        /* between two events on the stream; their sum bounds what any       */
+                        /* batching of the same requests can save                            */
 
 /* Through server s: requests are submitted at their arrival times (all that have arrived
  * in one ptg_tiles_submit call); completions are taken in request order and released at
- * once.  done_ns is the server's completion time (t_done_ns); admit_ns (optional) its
- * admission time.  Returns PTG_OK or the first error of the server calls. */
+ * once (when a request waits for bytes held by later requests that completed first, those
+ * are taken and released first).  done_ns is the server's completion time (t_done_ns);
+ * admit_ns (optional) its admission time.  Returns PTG_OK or the first error of the server
+ * calls. */
 PTG_API int ptg_lg_served(ptg_server *s, const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n,
                           int64_t *done_ns, int64_t *admit_ns);
 
@@ -31,8 +37,8 @@ PTG_API int ptg_lg_served(ptg_server *s, const ptg_tile_req *reqs, const int64_t
  * arena (device memory, arena_bytes) at an offset that wraps around in arrival order; the
  * single stream orders the reuse.  stats (optional, 3 entries) receives the number of launch
  * units (requests, or graph launches), and in graph mode the graphs instantiated and the
- * launches that reused an instance with updated arguments.  Returns PTG_OK, PTG_EINVAL, PTG_E2BIG (a request larger than the
- * arena) or PTG_EHIP. */
+ * launches that reused an instance with updated arguments.  Returns PTG_OK, PTG_EINVAL,
+ * PTG_E2BIG (a request larger than the arena) or PTG_EHIP. */
 PTG_API int ptg_lg_plain(const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n, void *arena,
                          int64_t arena_bytes, int32_t mode, int32_t max_batch, int64_t *done_ns, int64_t *stats);
 

@@ -130,6 +130,40 @@ def test_wait_release_rules():
         assert e.value.code == ptg.PTG_ENOENT
 
 
+def test_wait_reports_a_client_that_blocks_itself():
+    """Budget for one 256^2 output: A completes and holds the arena; B cannot be admitted
+    until A is released, so waiting on B (in submission order, without releasing A) is
+    reported as PTG_EAGAIN instead of running into the timeout; after the release B
+    completes."""
+    with _srv(256 * 256 * 4, tile_ns=100_000) as s:
+        ta, tb = s.submit([_req(256, tag=1), _req(256, tag=2)])
+        assert s.wait(ta, int(5e9)).status == ptg.PTG_OK
+        t0 = time.time()
+        with pytest.raises(ptg.PtgError) as e:
+            s.wait(tb, int(10e9))
+        assert e.value.code == ptg.PTG_EAGAIN and time.time() - t0 < 2.0
+        s.release(ta)
+        assert s.wait(tb, int(5e9)).status == ptg.PTG_OK
+        s.release(tb)
+
+
+def test_wait_does_not_report_a_request_that_work_in_flight_will_admit():
+    """While A is in flight, a wait on B (which needs A's bytes) times out as usual: the
+    work in flight will complete, so B is not blocked by the caller yet."""
+    with _srv(256 * 256 * 4, tile_ns=50_000_000) as s:
+        ta, tb = s.submit([_req(256, tag=1), _req(256, tag=2)])
+        with pytest.raises(ptg.PtgError) as e:
+            s.wait(tb, 20_000_000)  # 20 ms: A is still in flight
+        assert e.value.code == ptg.PTG_ETIMEDOUT
+        assert s.wait(ta, int(10e9)).status == ptg.PTG_OK
+        with pytest.raises(ptg.PtgError) as e:
+            s.wait(tb, int(10e9))
+        assert e.value.code == ptg.PTG_EAGAIN
+        s.release(ta)
+        assert s.wait(tb, int(10e9)).status == ptg.PTG_OK
+        s.release(tb)
+
+
 def test_shutdown_with_work_queued_does_not_hang():
     s = _srv(256 * 256 * 4, tile_ns=1_000_000)
     s.submit([_req(256) for _ in range(50)])
