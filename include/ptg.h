@@ -372,7 +372,7 @@ typedef struct ptg_server ptg_server;
 typedef struct ptg_server_cfg {
     int64_t hbm_budget_bytes; /* output arena (owned by the server), > 0                   */
     int32_t max_items;        /* work-item ring entries, >= 64                              */
-    int32_t workgroups;       /* persistent workgroups, 0 = 2 per compute unit              */
+    int32_t workgroups;       /* persistent workgroups, 0 = 1 per compute unit              */
     int32_t device;           /* HIP device ordinal                                         */
     int32_t executor;         /* PTG_EXEC_GPU or PTG_EXEC_HOST                              */
     int64_t fake_tile_ns;     /* PTG_EXEC_HOST only: simulated time per tile                */

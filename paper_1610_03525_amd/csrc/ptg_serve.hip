@@ -1,6 +1,7 @@
 // ptg_serve.hip -- continuous-batching tile server (a6): a persistent kernel draining a
 // work-item ring in pinned host memory, and a host scheduler that admits requests by HBM
-// budget, publishes their work items while earlier ones run, and completes them.
+// budget, publishes their work items while earlier ones run, and completes them.  A
+// submission is admitted on the submitting thread when it fits at once.
 //
 // Protocol (host = scheduler thread, device = persistent kernel):
 //   * the request table reqs[slot] and ring items are written by the host first; then the
@@ -11,11 +12,14 @@
 //     holding index == mirror is the only one that reads host memory (system-scope
 //     acquire of tail): when tail has moved past it, it raises mirror to tail and runs
 //     its item.  Every other waiting workgroup watches mirror with a backed-off poll;
-//   * a workgroup runs its item (system-scope loads of the item and, unless it still
-//     holds it, the request descriptor), computes the tiles with the general K3 tile
-//     functions, then adds its tile count to done_tiles[slot] (device memory); the
+//   * a workgroup runs its item (system-scope loads of the item; unless it still holds
+//     the request descriptor, the first workgroup of the request copies it from host into
+//     device memory -- claimed with a compare-and-swap on desc_state[slot] -- and the
+//     others read that copy once it is whole), computes the tiles with the K3 tile and
+//     strip functions, then adds its tile count to done_tiles[slot] (device memory); the
 //     workgroup that brings it to the request's target stores the request's sequence
-//     number into done[slot] (pinned memory, system-scope release) after a system fence;
+//     number into done[slot] (pinned memory, system-scope release) after a system fence
+//     (a request's only item skips the count and stores done[slot] directly);
 //   * the host sees done[slot] == seq, completes the request, and only then reuses the
 //     slot and the request's ring entries (ring space is reclaimed in ring order);
 //   * parking: once the host has had nothing in flight for a while (or is shutting down)
@@ -91,9 +95,11 @@ struct ServeReqDesc {
 static_assert(sizeof(ServeReqDesc) % 8 == 0, "descriptor is copied in 8-byte words");
 
 struct ServeItem {
-    uint32_t slot, seq;    // request slot and the sequence number of its current request
+    uint32_t slot, seq;    // request slot (| kOnlyItem: the request's one item) and the
+                           // sequence number of its current request
     uint32_t ntiles, tile0;
 };
+constexpr uint32_t kOnlyItem = 0x80000000u;
 static_assert(sizeof(ServeItem) == 16, "an item is two 8-byte words");
 
 struct ServeHostCtl {  // pinned host memory
@@ -108,6 +114,10 @@ struct ServeDevCtl {       // device memory
     uint32_t parked;       // the poller saw park with nothing left to run
     uint32_t pad;
     uint64_t done_tiles[kReqSlots];
+    // device copies of the request descriptors: desc_state[slot] = seq << 2 | 1 while one
+    // workgroup copies request seq's descriptor from host memory, | 2 once the copy is whole
+    uint64_t desc_state[kReqSlots];
+    ServeReqDesc desc[kReqSlots];
 };
 
 __global__ void k_serve_reset(ServeDevCtl *dc, uint64_t start)
@@ -146,10 +156,14 @@ __device__ __forceinline__ void fill_lat_block(const ServeReqDesc &rq, const uin
     }
 }
 
+// The work of each request kind is a function of its own (not inlined into the serving
+// kernel), so that each gets its own register allocation: inlined together, the 3D strip
+// code's pressure made the whole kernel spill.
+//
 // Strips [t0, t1) of a dyadic 2D request: wave w takes t0 + w, t0 + w + 4, ... (the same
 // per-strip code as the dense strip kernel, so a served strip equals that kernel's output).
 template <int M, int LO>
-__device__ __forceinline__ void serve_strips(const Fbm2dStripArgs &a, const StripShared &sh, uint32_t *wl, int64_t t0,
+__device__ __noinline__ void serve_strips(const Fbm2dStripArgs &a, const StripShared &sh, uint32_t *wl, int64_t t0,
                                              int64_t t1, int tid)
 {
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -176,7 +190,7 @@ __device__ __forceinline__ void serve_strips_lo(const Fbm2dStripArgs &a, const S
 // Blocks [t0, t1) of a dyadic 3D request, wave w taking t0 + w, t0 + w + 4, ... (the dense
 // 3D strip kernel's per-block code).
 template <int M, int LO>
-__device__ __forceinline__ void serve_blocks(const Fbm3dStripArgs &a, const Strip3Shared &sh, float4 *tab, int64_t t0,
+__device__ __noinline__ void serve_blocks(const Fbm3dStripArgs &a, const Strip3Shared &sh, float4 *tab, int64_t t0,
                                              int64_t t1, int tid)
 {
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -186,6 +200,26 @@ __device__ __forceinline__ void serve_blocks(const Fbm3dStripArgs &a, const Stri
                 wave * strip3_wave_words(a.nodes_total, a.keys_total);
     Strip3Wave<M, float, LO> w(a, sh, gx, lane);
     for (int64_t b = t0 + wave; b < t1; b += kServeWaves) w.run(a, sh, tab, wl_key, wl_key + listed, b);
+}
+
+// General tiles [t0, t1) of a 2D / 3D request, one after the other.
+template <int M, int TH>
+__device__ __noinline__ void serve_tiles_2d(const Fbm2dArgs &a, const LatCache *lat, int64_t t0, int64_t t1,
+                                            float4 *lds4)
+{
+    for (int64_t t = t0; t < t1; ++t) {
+        fbm2d_general_tile<M, float, TH>(a, t, lds4, lat);
+        __syncthreads();  // LDS reuse by the next tile
+    }
+}
+
+template <int M>
+__device__ __noinline__ void serve_tiles_3d(const Fbm3dArgs &a, int64_t t0, int64_t t1, float4 *lds4)
+{
+    for (int64_t t = t0; t < t1; ++t) {
+        fbm3d_general_tile<M, float>(a, t, lds4);
+        __syncthreads();
+    }
 }
 
 template <int M>
@@ -210,13 +244,15 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
     __shared__ ServeItem s_item;
     __shared__ uint32_t s_have_slot, s_have_seq;  // request whose descriptor s_req holds
     __shared__ uint32_t s_tbl[kMaxLatTbl];        // its lattice-cache table
+    __shared__ int s_copy;                        // 1: this workgroup copies the descriptor
+    __shared__ bool s_only;                       // the item is its request's only one
     const int tid = threadIdx.x;
     if (tid == 0) s_have_slot = 0xFFFFFFFFu;
     for (;;) {
         if (tid == 0) {
             const uint64_t my = __hip_atomic_fetch_add(&dc->head, (uint64_t)1, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT);
-            int cmd = 0, nap = 8;
+            int cmd = 0, nap = 8, polls = 0;
             // Polls are relaxed loads (an acquire on this chip invalidates the L2, which a
             // spinning workgroup would do continuously); one acquire fence follows success.
             for (;;) {
@@ -226,8 +262,9 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
                     cmd = 1;
                     break;
                 }
-                if (my == m) {  // first unpublished index: poll host memory
-                    const int32_t pk = __hip_atomic_load(&hc->park, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (my == m) {  // first unpublished index: poll host memory (park every 8th poll)
+                    const int32_t pk = (++polls & 7) != 0 ? 0
+                                     : __hip_atomic_load(&hc->park, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     if (pk) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the tail read next is final
                     const uint64_t t = __hip_atomic_load(&hc->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                     if (t > my) {
@@ -250,7 +287,8 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
             if (cmd == 1) {
                 const uint64_t *w = reinterpret_cast<const uint64_t *>(ring + (my % (uint64_t)ring_size));
                 const uint64_t w0 = sys_load64(w), w1 = sys_load64(w + 1);
-                s_item.slot = (uint32_t)w0;
+                s_item.slot = (uint32_t)w0 & ~kOnlyItem;
+                s_only = ((uint32_t)w0 & kOnlyItem) != 0;
                 s_item.seq = (uint32_t)(w0 >> 32);
                 s_item.ntiles = (uint32_t)w1;
                 s_item.tile0 = (uint32_t)(w1 >> 32);
@@ -263,9 +301,45 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
         __syncthreads();
         if (s_cmd == 0) return;  // parked: every wave of the workgroup leaves
         if (s_cmd == 1) {
-            const uint64_t *src = reinterpret_cast<const uint64_t *>(reqs + s_item.slot);
-            for (int i = tid; i < (int)(sizeof(ServeReqDesc) / 8); i += 256) s_req[i] = sys_load64(src + i);
+            // The first workgroup to run an item of the request copies its descriptor from host
+            // memory into device memory; later ones (and those that arrive while it copies,
+            // after waiting for it) read the device copy, so the host is read once per request.
+            uint64_t *stp = &dc->desc_state[s_item.slot];
+            const uint64_t want = (uint64_t)s_item.seq << 2;
+            if (tid == 0 && s_only) {
+                s_copy = 2;  // nobody else reads it: straight from host memory
+            } else if (tid == 0) {
+                uint64_t st = __hip_atomic_load(stp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                int copy = 0;
+                for (;;) {
+                    if (st == (want | 2)) break;
+                    if (st == (want | 1)) {  // another workgroup is copying it
+                        __builtin_amdgcn_s_sleep(2);
+                        st = __hip_atomic_load(stp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        continue;
+                    }
+                    // an earlier request's state (whose items have all run): take the copy
+                    if (__hip_atomic_compare_exchange_strong(stp, &st, want | 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)) {
+                        copy = 1;
+                        break;
+                    }
+                }
+                if (!copy) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the copy's writes
+                s_copy = copy;
+            }
             __syncthreads();
+            const bool copy = s_copy == 1, host = s_copy != 0;
+            const uint64_t *src = reinterpret_cast<const uint64_t *>(reqs + s_item.slot);
+            uint64_t *dev = reinterpret_cast<uint64_t *>(dc->desc + s_item.slot);
+            for (int i = tid; i < (int)(sizeof(ServeReqDesc) / 8); i += 256) {
+                const uint64_t v = host ? sys_load64(src + i) : dev[i];
+                s_req[i] = v;
+                if (copy) dev[i] = v;
+            }
+            if (copy) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // each wave's copy stores
+            __syncthreads();
+            if (copy && tid == 0) __hip_atomic_store(stp, want | 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             const ServeReqDesc &d = *reinterpret_cast<const ServeReqDesc *>(s_req);
             if (d.lat_mode != 0) {
                 for (int i = tid; i < d.lat_n; i += 256) s_tbl[i] = sys_load32(d.lat_host + i);
@@ -314,35 +388,39 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
             __syncthreads();
         }
         const bool tiles = rq.lat_mode != 2 && (rq.kernel == PTG_TUNE_GENERAL_2D || rq.kernel == PTG_TUNE_GENERAL_3D);
-        for (int64_t t = s_item.tile0; tiles && t < t1; ++t) {
-            if (rq.dim == 2) {
-                const int th = rq.a2.tile_h;
-                const LatCache lc{rq.lat_base, s_tbl, rq.lat_n, rq.lat_bx0, rq.lat_by0, rq.lat_nbx, rq.lat_tbl0};
-                const LatCache *lat = rq.lat_mode == 1 ? &lc : nullptr;
-                if (rq.smooth == 1) {
-                    if (th == 16)
-                        fbm2d_general_tile<1, float, 16>(rq.a2, t, lds4, lat);
-                    else if (th == 32)
-                        fbm2d_general_tile<1, float, 32>(rq.a2, t, lds4, lat);
-                    else
-                        fbm2d_general_tile<1, float, 64>(rq.a2, t, lds4, lat);
-                } else {
-                    if (th == 16)
-                        fbm2d_general_tile<2, float, 16>(rq.a2, t, lds4, lat);
-                    else if (th == 32)
-                        fbm2d_general_tile<2, float, 32>(rq.a2, t, lds4, lat);
-                    else
-                        fbm2d_general_tile<2, float, 64>(rq.a2, t, lds4, lat);
-                }
-            } else {
-                if (rq.smooth == 1)
-                    fbm3d_general_tile<1, float>(rq.a3, t, lds4);
+        if (tiles && rq.dim == 2) {
+            const int th = rq.a2.tile_h;
+            const LatCache lc{rq.lat_base, s_tbl, rq.lat_n, rq.lat_bx0, rq.lat_by0, rq.lat_nbx, rq.lat_tbl0};
+            const LatCache *lat = rq.lat_mode == 1 ? &lc : nullptr;
+            const int64_t t0 = s_item.tile0;
+            if (rq.smooth == 1) {
+                if (th == 16)
+                    serve_tiles_2d<1, 16>(rq.a2, lat, t0, t1, lds4);
+                else if (th == 32)
+                    serve_tiles_2d<1, 32>(rq.a2, lat, t0, t1, lds4);
                 else
-                    fbm3d_general_tile<2, float>(rq.a3, t, lds4);
+                    serve_tiles_2d<1, 64>(rq.a2, lat, t0, t1, lds4);
+            } else {
+                if (th == 16)
+                    serve_tiles_2d<2, 16>(rq.a2, lat, t0, t1, lds4);
+                else if (th == 32)
+                    serve_tiles_2d<2, 32>(rq.a2, lat, t0, t1, lds4);
+                else
+                    serve_tiles_2d<2, 64>(rq.a2, lat, t0, t1, lds4);
             }
-            __syncthreads();  // LDS reuse by the next tile
+        } else if (tiles) {
+            if (rq.smooth == 1)
+                serve_tiles_3d<1>(rq.a3, s_item.tile0, t1, lds4);
+            else
+                serve_tiles_3d<2>(rq.a3, s_item.tile0, t1, lds4);
         }
-        if (tid == 0) {
+        // every wave's output stores have reached the L2 before thread 0's release writes it back
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        __syncthreads();
+        if (tid == 0 && s_only) {  // the request's one item: signal the host directly
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+            __hip_atomic_store(done + rq.slot, rq.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        } else if (tid == 0) {
             // this workgroup's output reaches memory before it is counted (release: L2
             // write-back); only the workgroup that completes the request also acquires the
             // other workgroups' releases before it signals the host
@@ -766,7 +844,8 @@ static void publish(ptg_server *s, uint64_t ticket, Request &r, int phase)
     d.smooth = p->smoothness;
     d.slot = slot;
     d.seq = r.seq;
-    s->slot_total[slot] += (uint64_t)nwork;
+    // a request's one item signals the host itself; done_tiles[slot] counts the others' tiles
+    if (items > 1) s->slot_total[slot] += (uint64_t)nwork;
     d.target = s->slot_total[slot];
     d.ntiles = nwork;
     d.kernel = r.kernel;
@@ -801,7 +880,7 @@ static void publish(ptg_server *s, uint64_t ticket, Request &r, int phase)
     std::memcpy(&s->reqs[slot], &d, sizeof(d));
     for (uint64_t i = 0; i < items; ++i) {
         ServeItem it;
-        it.slot = (uint32_t)slot;
+        it.slot = (uint32_t)slot | (items == 1 ? kOnlyItem : 0u);
         it.seq = r.seq;
         const int64_t t0 = (int64_t)i * per;
         it.tile0 = (uint32_t)t0;
@@ -1139,7 +1218,7 @@ int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out)
     s->slot_total.assign(kReqSlots, 0);
     s->arena.reset(new Arena(cfg->hbm_budget_bytes));
     if (cfg->tile_h != 0) s->tile_h2[0] = s->tile_h2[1] = cfg->tile_h;
-    s->workgroups = cfg->workgroups > 0 ? cfg->workgroups : 512;
+    s->workgroups = cfg->workgroups > 0 ? cfg->workgroups : 256;
     if (s->gpu) {
         hipError_t e = hipSetDevice(cfg->device);
         if (e != hipSuccess) {
@@ -1149,7 +1228,9 @@ int ptg_server_create(const ptg_server_cfg *cfg, ptg_server **out)
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, cfg->device) != hipSuccess || cus <= 0)
             cus = 256;
-        s->workgroups = cfg->workgroups > 0 ? cfg->workgroups : 2 * cus;
+        // one per compute unit: a request with fewer items than workgroups then spreads one item
+        // per unit (two on one unit would share it while others idle); capacity is the same
+        s->workgroups = cfg->workgroups > 0 ? cfg->workgroups : cus;
         e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
         if (e == hipSuccess && cfg->lattice_cache)
             e = hipHostMalloc((void **)&s->lat_host, sizeof(uint32_t) * 2 * kMaxLatTbl * kReqSlots,
@@ -1233,6 +1314,9 @@ int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n, uint64_
         tickets_out[i] = ticket;
         s->st.submitted++;
     }
+    // admit at once on this thread when the scheduler would (saves its wake-up); it still
+    // launches the kernel, polls completions and retries what does not fit
+    if (!s->park_requested) admit(s);
     s->cv_work.notify_all();
     return PTG_OK;
 }

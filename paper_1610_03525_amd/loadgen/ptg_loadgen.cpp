@@ -125,8 +125,13 @@ int ptg_lg_served(ptg_server *s, const ptg_tile_req *reqs, const int64_t *arriva
 int ptg_lg_plain(const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n, void *arena, int64_t arena_bytes,
                  int32_t mode, int32_t max_batch, int64_t *done_ns, int64_t *stats)
 {
+    // Graph mode is switched off: one stream of thousands of one-request graph launches with
+    // in-place node updates ended the process with a segmentation fault whose cause has not
+    // been established (the batch object's own use of the graph API has been checked by
+    // reading; its GPU tests pass).  The code below stays for when the cause is known.
+    if (mode == PTG_LG_GRAPH) return PTG_EINVAL;
     if (!reqs || !arrival_ns || !done_ns || !arena || n < 1 || !arrivals_ok(arrival_ns, n) ||
-        (mode != PTG_LG_DIRECT && mode != PTG_LG_GRAPH && mode != PTG_LG_SOLO) || max_batch < 1)
+        (mode != PTG_LG_DIRECT && mode != PTG_LG_SOLO) || max_batch < 1)
         return PTG_EINVAL;
     std::vector<int64_t> off((size_t)n);
     int64_t o = 0;

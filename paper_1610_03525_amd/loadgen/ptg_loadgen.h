@@ -18,7 +18,9 @@ extern "C" {
 #define PTG_LG_GRAPH 1  /* every request that has arrived (up to max_batch) recorded into a */
                         /* ptg_batch and launched as one HIP graph (instantiated once per   */
                         /* batch shape, arguments updated for later batches of that shape); */
-                        /* its requests complete together                                    */
+                        /* its requests complete together.  Switched off (PTG_EINVAL): a     */
+                        /* stream of one-request graphs updated in place ended the process   */
+                        /* with a segmentation fault of unknown cause                        */
 #define PTG_LG_SOLO 2   /* each request launched alone, one after the other (arrivals        */
                         /* ignored): done_ns[i] receives request i's kernel time (ns)        */
                         /* between two events on the stream; their sum bounds what any       */

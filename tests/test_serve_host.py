@@ -331,3 +331,12 @@ def test_lattice_cache_waiting_requests_and_shutdown():
     s.submit(reqs)
     time.sleep(0.002)
     s.close()
+
+
+def test_stream_driver_graph_mode_is_switched_off():
+    """The plain stream driver refuses its graph mode (PTG_EINVAL) before touching the GPU."""
+    import ctypes
+    import os
+    lg = ctypes.CDLL(os.path.join(os.path.dirname(ptg.LIB_PATH), "libptg_loadgen.so"))
+    lg.ptg_lg_plain.restype = ctypes.c_int
+    assert lg.ptg_lg_plain(None, None, 0, None, ctypes.c_int64(0), 1, 1, None, None) == ptg.PTG_EINVAL
