@@ -266,8 +266,19 @@ def other_configs(torch, ptg, stream):
     res["3d_512_6oct_c2"] = {"workload": "3D fBm 512^3, 6 octaves, base lattice 8^3, C2 quintic, FP32, seed 1",
                              "kernel": "k_fbm3d_strip", "ms": ms, "octave_samples_s": n3 * 6 / (ms * 1e-3),
                              "hbm_frac": n3 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    hg3 = {}
+    for sm in (1, 2):  # D3M1N3 / D3M2N5 with node heights and w-weighted gradients
+        q3 = ptg.params(dim=3, smoothness=sm, octaves=6, base_freq=8 / 512, seed=1, model="height_gradient",
+                        gradient_weight=0.01)
+        ms3 = _time_launches(torch, stream, lambda: ptg.fbm_3d_raw(q3, 0, 0, 0, 512, 512, 512, vol.data_ptr(), sh), 5)
+        hg3[f"C{sm}"] = {"ms": ms3, "octave_samples_s": n3 * 6 / (ms3 * 1e-3),
+                         "hbm_frac": n3 * 4 / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    res["3d_512_6oct_height_gradient"] = {
+        "workload": "3D fBm 512^3, 6 octaves, base lattice 8^3, node heights and gradients (weight 0.01), FP32, "
+                    "seed 1, 3D strip kernel", "smoothness": hg3}
     del vol
-    progress(f"3D 512^3 C2: {ms * 1e3:.1f} us")
+    progress(f"3D 512^3 C2: {ms * 1e3:.1f} us; heights and gradients C1 {hg3['C1']['ms'] * 1e3:.1f} us, "
+             f"C2 {hg3['C2']['ms'] * 1e3:.1f} us")
     # 16384^2, 10 octaves, base lattice 32^2, offset (2^24 - 3) * 512, -(2^24 - 5) * 512
     n, f0 = 16384, 32 / 16384
     x0, y0 = (2 ** 24 - 3) * 512, -(2 ** 24 - 5) * 512
