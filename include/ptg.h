@@ -443,6 +443,15 @@ PTG_API int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n,
  * release some, then wait again). */
 PTG_API int ptg_tiles_wait(ptg_server *s, uint64_t ticket, int64_t timeout_ns, ptg_tile_result *res);
 
+/* Wait up to timeout_ns (0: poll, < 0: forever) for the next request to complete, in
+ * completion order, whatever its ticket: *ticket_out and *res receive it.  Each completion
+ * is returned once (completions released through ptg_tile_release before they were
+ * returned are skipped); the ticket stays valid for ptg_tiles_wait and ptg_tile_release.
+ * Errors: PTG_ETIMEDOUT (none completed in time), PTG_ENOENT (no request is pending or in
+ * flight: nothing can complete), PTG_EAGAIN (the pending requests wait for arena bytes held
+ * by completed outputs that have not been released; as for ptg_tiles_wait). */
+PTG_API int ptg_tiles_wait_any(ptg_server *s, int64_t timeout_ns, uint64_t *ticket_out, ptg_tile_result *res);
+
 /* Return a completed ticket's arena bytes to the server (its out_dev becomes invalid).
  * Errors: PTG_ENOENT, PTG_EAGAIN (not complete yet). */
 PTG_API int ptg_tile_release(ptg_server *s, uint64_t ticket);

@@ -160,6 +160,7 @@ def lib():
     L.ptg_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]
     L.ptg_tiles_submit.argtypes = [_vp, ctypes.POINTER(TileReq), _i32, ctypes.POINTER(ctypes.c_uint64)]
     L.ptg_tiles_wait.argtypes = [_vp, ctypes.c_uint64, _i64, ctypes.POINTER(TileResult)]
+    L.ptg_tiles_wait_any.argtypes = [_vp, _i64, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(TileResult)]
     L.ptg_tile_release.argtypes = [_vp, ctypes.c_uint64]
     L.ptg_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
     L.ptg_server_destroy.argtypes = [_vp]
@@ -539,6 +540,14 @@ class Server:
         res = TileResult()
         _check(lib().ptg_tiles_wait(self.h, ticket, timeout_ns, ctypes.byref(res)))
         return res
+
+    def wait_any(self, timeout_ns=-1):
+        """(ticket, TileResult) of the next request to complete, in completion order; raises
+        PtgError(PTG_ETIMEDOUT) when none completes in time, PTG_ENOENT when none can."""
+        res = TileResult()
+        t = ctypes.c_uint64()
+        _check(lib().ptg_tiles_wait_any(self.h, timeout_ns, ctypes.byref(t), ctypes.byref(res)))
+        return t.value, res
 
     def release(self, ticket):
         _check(lib().ptg_tile_release(self.h, ticket))

@@ -565,6 +565,7 @@ struct ptg_server {
 
     std::mutex mu;
     std::condition_variable cv_done, cv_work;
+    std::deque<uint64_t> done_q;  // completed tickets in completion order (ptg_tiles_wait_any)
     std::map<uint64_t, ptg::Request> by_ticket;
     std::deque<uint64_t> pending;
     std::vector<uint64_t> inflight;
@@ -810,6 +811,7 @@ static void complete(ptg_server *s, uint64_t ticket, int status)
     s->st.completed++;
     if (status == PTG_OK) s->st.tiles_done += r.ntiles;
     s->st.bytes_in_use = s->arena->used();
+    s->done_q.push_back(ticket);
     s->cv_done.notify_all();
 }
 
@@ -1321,6 +1323,35 @@ int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n, uint64_
     return PTG_OK;
 }
 
+static void fill_result(const ptg_server *s, const Request &r, ptg_tile_result *res)
+{
+    std::memset(res, 0, sizeof(*res));
+    res->status = r.status;
+    res->kernel = r.kernel;
+    res->out_dev = (r.status == PTG_OK) ? s->arena_mem + r.arena_off : nullptr;
+    res->bytes = r.bytes;
+    res->user_tag = r.req.user_tag;
+    res->t_submit_ns = r.t_submit;
+    res->t_admit_ns = r.t_admit;
+    res->t_done_ns = r.t_done;
+}
+
+// The pending request at the head of admission waits for arena bytes that only the caller
+// can free: nothing is in flight (nothing will complete and free bytes), completed outputs
+// still hold arena bytes, and the largest free range is too small for it.
+static bool head_blocked_by_caller(const ptg_server *s, uint64_t ticket)
+{
+    auto j = s->by_ticket.find(ticket);
+    if (j == s->by_ticket.end() || j->second.status != 1 || !s->inflight.empty()) return false;
+    bool held = false;
+    for (const auto &kv : s->by_ticket)
+        if (kv.second.status <= 0 && kv.second.arena_off >= 0) {
+            held = true;
+            break;
+        }
+    return held && s->arena->largest_free() < round256(j->second.bytes);
+}
+
 int ptg_tiles_wait(ptg_server *s, uint64_t ticket, int64_t timeout_ns, ptg_tile_result *res)
 {
     if (!s || !res) return fail(PTG_EINVAL, "bad arguments");
@@ -1331,20 +1362,7 @@ int ptg_tiles_wait(ptg_server *s, uint64_t ticket, int64_t timeout_ns, ptg_tile_
         auto j = s->by_ticket.find(ticket);
         return j == s->by_ticket.end() || j->second.status <= 0;
     };
-    // The request waits for arena bytes that only the caller can free: it is pending, no
-    // request is in flight (nothing will complete and free bytes), and the largest free
-    // range is too small while completed outputs still hold arena bytes.
-    auto blocked_by_caller = [&] {
-        auto j = s->by_ticket.find(ticket);
-        if (j == s->by_ticket.end() || j->second.status != 1 || !s->inflight.empty()) return false;
-        bool held = false;
-        for (const auto &kv : s->by_ticket)
-            if (kv.second.status <= 0 && kv.second.arena_off >= 0) {
-                held = true;
-                break;
-            }
-        return held && s->arena->largest_free() < round256(j->second.bytes);
-    };
+    auto blocked_by_caller = [&] { return head_blocked_by_caller(s, ticket); };
     // wait in slices; the blocked state must last across a slice (the scheduler makes an
     // admission pass in well under one) before it is reported
     const auto slice = std::chrono::milliseconds(2);
@@ -1368,15 +1386,44 @@ int ptg_tiles_wait(ptg_server *s, uint64_t ticket, int64_t timeout_ns, ptg_tile_
     if (it == s->by_ticket.end()) return fail(PTG_ENOENT, "ticket released");
     const Request &r = it->second;
     if (r.status > 0) return fail(PTG_ETIMEDOUT, "request still pending");
-    std::memset(res, 0, sizeof(*res));
-    res->status = r.status;
-    res->kernel = r.kernel;
-    res->out_dev = (r.status == PTG_OK) ? s->arena_mem + r.arena_off : nullptr;
-    res->bytes = r.bytes;
-    res->user_tag = r.req.user_tag;
-    res->t_submit_ns = r.t_submit;
-    res->t_admit_ns = r.t_admit;
-    res->t_done_ns = r.t_done;
+    fill_result(s, r, res);
+    return PTG_OK;
+}
+
+int ptg_tiles_wait_any(ptg_server *s, int64_t timeout_ns, uint64_t *ticket_out, ptg_tile_result *res)
+{
+    if (!s || !res || !ticket_out) return fail(PTG_EINVAL, "bad arguments");
+    std::unique_lock<std::mutex> lk(s->mu);
+    // completions already released through their ticket are dropped from the queue
+    auto ready = [&] {
+        while (!s->done_q.empty() && s->by_ticket.find(s->done_q.front()) == s->by_ticket.end())
+            s->done_q.pop_front();
+        return !s->done_q.empty();
+    };
+    // nothing left that could complete: no request pending or in flight
+    auto idle = [&] { return s->pending.empty() && s->inflight.empty() && s->lat_waiting.empty(); };
+    const auto slice = std::chrono::milliseconds(2);
+    const auto t_end = std::chrono::steady_clock::now() + std::chrono::nanoseconds(timeout_ns < 0 ? 0 : timeout_ns);
+    bool was_blocked = false;
+    while (!ready()) {
+        if (idle()) return fail(PTG_ENOENT, "no request is pending or in flight");
+        if (timeout_ns == 0) return fail(PTG_ETIMEDOUT, "no request completed");
+        auto until = std::chrono::steady_clock::now() + slice;
+        if (timeout_ns > 0 && until > t_end) until = t_end;
+        s->cv_done.wait_until(lk, until, ready);
+        if (ready()) break;
+        const bool b = !s->pending.empty() && head_blocked_by_caller(s, s->pending.front());
+        if (b && was_blocked)
+            return fail(PTG_EAGAIN, "the pending requests wait for arena bytes held by completed outputs that have "
+                                    "not been released (release some, then wait again)");
+        was_blocked = b;
+        if (timeout_ns > 0 && std::chrono::steady_clock::now() >= t_end)
+            return fail(PTG_ETIMEDOUT, "no request completed");
+    }
+    const uint64_t t = s->done_q.front();
+    s->done_q.pop_front();
+    *ticket_out = t;
+    fill_result(s, s->by_ticket.find(t)->second, res);
     return PTG_OK;
 }
 
@@ -1389,6 +1436,7 @@ int ptg_tile_release(ptg_server *s, uint64_t ticket)
     if (it->second.status > 0) return fail(PTG_EAGAIN, "request not complete");
     if (it->second.arena_off >= 0) s->arena->release(it->second.arena_off, round256(it->second.bytes));
     s->by_ticket.erase(it);
+    while (!s->done_q.empty() && s->by_ticket.find(s->done_q.front()) == s->by_ticket.end()) s->done_q.pop_front();
     s->st.released++;
     s->st.bytes_in_use = s->arena->used();
     s->cv_work.notify_all();

@@ -54,7 +54,7 @@ int plain_call(const ptg_tile_req &r, void *out, hipStream_t s)
 extern "C" {
 
 int ptg_lg_served(ptg_server *s, const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n, int64_t *done_ns,
-                  int64_t *admit_ns)
+                  int64_t *admit_ns, int32_t any_order)
 {
     if (!s || !reqs || !arrival_ns || !done_ns || n < 1 || !arrivals_ok(arrival_ns, n)) return PTG_EINVAL;
     std::vector<uint64_t> tickets((size_t)n);
@@ -78,44 +78,80 @@ int ptg_lg_served(ptg_server *s, const ptg_tile_req *reqs, const int64_t *arriva
         }
     });
     int rc = PTG_OK;
-    std::vector<char> taken((size_t)n, 0);
-    auto take = [&](int32_t k, const ptg_tile_result &res) {
-        int r = res.status;
-        if (r == PTG_OK) {
-            done_ns[k] = res.t_done_ns - t0;
-            if (admit_ns) admit_ns[k] = res.t_admit_ns - t0;
-            r = ptg_tile_release(s, tickets[(size_t)k]);
-        }
-        taken[(size_t)k] = 1;
-        return r;
-    };
-    for (int32_t i = 0; i < n && rc == PTG_OK; ++i) {
-        if (taken[(size_t)i]) continue;
-        while (published.load(std::memory_order_acquire) <= i) {
-            if (err.load() != PTG_OK) break;
-            std::this_thread::yield();
-        }
-        if (err.load() != PTG_OK) {
-            rc = err.load();
-            break;
-        }
-        ptg_tile_result res;
-        rc = ptg_tiles_wait(s, tickets[(size_t)i], 120000000000LL, &res);
-        while (rc == PTG_EAGAIN) {
-            // request i waits for bytes held by later requests that completed first: take
-            // (and release) those, then wait again
-            const int32_t pub = published.load(std::memory_order_acquire);
-            for (int32_t k = i + 1; k < pub && rc == PTG_EAGAIN; ++k) {
-                if (taken[(size_t)k]) continue;
-                ptg_tile_result rk;
-                if (ptg_tiles_wait(s, tickets[(size_t)k], 0, &rk) == PTG_OK) {
-                    const int rt = take(k, rk);
-                    if (rt != PTG_OK) rc = rt;
-                }
+    if (!any_order) {
+        std::vector<char> taken((size_t)n, 0);
+        auto take = [&](int32_t k, const ptg_tile_result &res) {
+            int r = res.status;
+            if (r == PTG_OK) {
+                done_ns[k] = res.t_done_ns - t0;
+                if (admit_ns) admit_ns[k] = res.t_admit_ns - t0;
+                r = ptg_tile_release(s, tickets[(size_t)k]);
             }
-            if (rc == PTG_EAGAIN) rc = ptg_tiles_wait(s, tickets[(size_t)i], 120000000000LL, &res);
+            taken[(size_t)k] = 1;
+            return r;
+        };
+        for (int32_t i = 0; i < n && rc == PTG_OK; ++i) {
+            if (taken[(size_t)i]) continue;
+            while (published.load(std::memory_order_acquire) <= i) {
+                if (err.load() != PTG_OK) break;
+                std::this_thread::yield();
+            }
+            if (err.load() != PTG_OK) {
+                rc = err.load();
+                break;
+            }
+            ptg_tile_result res;
+            rc = ptg_tiles_wait(s, tickets[(size_t)i], 120000000000LL, &res);
+            while (rc == PTG_EAGAIN) {
+                // request i waits for bytes held by later requests that completed first: take
+                // (and release) those, then wait again
+                const int32_t pub = published.load(std::memory_order_acquire);
+                for (int32_t k = i + 1; k < pub && rc == PTG_EAGAIN; ++k) {
+                    if (taken[(size_t)k]) continue;
+                    ptg_tile_result rk;
+                    if (ptg_tiles_wait(s, tickets[(size_t)k], 0, &rk) == PTG_OK) {
+                        const int rt = take(k, rk);
+                        if (rt != PTG_OK) rc = rt;
+                    }
+                }
+                if (rc == PTG_EAGAIN) rc = ptg_tiles_wait(s, tickets[(size_t)i], 120000000000LL, &res);
+            }
+            if (rc == PTG_OK) rc = take(i, res);
         }
-        if (rc == PTG_OK) rc = take(i, res);
+    } else {
+        // completions in completion order; a ticket is mapped back to its request by its place
+        // in tickets[] (increasing in submission order)
+        for (int32_t taken = 0; taken < n && rc == PTG_OK; ++taken) {
+            uint64_t t = 0;
+            ptg_tile_result res;
+            for (;;) {
+                rc = ptg_tiles_wait_any(s, 2000000LL, &t, &res);
+                if (rc != PTG_ENOENT && rc != PTG_ETIMEDOUT) break;
+                // still running, or nothing submitted yet (the next arrival is ahead): wait on,
+                // unless submission failed
+                if (err.load() != PTG_OK) {
+                    rc = err.load();
+                    break;
+                }
+                if (rc == PTG_ENOENT) std::this_thread::sleep_for(std::chrono::microseconds(20));
+                rc = PTG_OK;
+            }
+            if (rc != PTG_OK) break;
+            int32_t i = -1;
+            while (i < 0) {  // the submitting thread publishes tickets[] after the submit call returns
+                const int32_t pub = published.load(std::memory_order_acquire);
+                const auto it = std::lower_bound(tickets.begin(), tickets.begin() + pub, t);
+                if (it != tickets.begin() + pub && *it == t) i = (int32_t)(it - tickets.begin());
+                else std::this_thread::yield();
+            }
+            if (res.status != PTG_OK) {
+                rc = res.status;
+                break;
+            }
+            done_ns[i] = res.t_done_ns - t0;
+            if (admit_ns) admit_ns[i] = res.t_admit_ns - t0;
+            rc = ptg_tile_release(s, t);
+        }
     }
     if (rc != PTG_OK) err.store(rc);
     sub.join();

@@ -27,13 +27,14 @@ extern "C" {
                         /* batching of the same requests can save                            */
 
 /* Through server s: requests are submitted at their arrival times (all that have arrived
- * in one ptg_tiles_submit call); completions are taken in request order and released at
- * once (when a request waits for bytes held by later requests that completed first, those
- * are taken and released first).  done_ns is the server's completion time (t_done_ns);
- * admit_ns (optional) its admission time.  Returns PTG_OK or the first error of the server
- * calls. */
+ * in one ptg_tiles_submit call); completions are taken and released at once, in request
+ * order (any_order = 0: when a request waits for bytes held by later requests that
+ * completed first, those are taken and released first) or in completion order
+ * (any_order = 1, ptg_tiles_wait_any; the server must serve no other client during the
+ * call).  done_ns is the server's completion time (t_done_ns); admit_ns (optional) its
+ * admission time.  Returns PTG_OK or the first error of the server calls. */
 PTG_API int ptg_lg_served(ptg_server *s, const ptg_tile_req *reqs, const int64_t *arrival_ns, int32_t n,
-                          int64_t *done_ns, int64_t *admit_ns);
+                          int64_t *done_ns, int64_t *admit_ns, int32_t any_order);
 
 /* Through the plain path on a stream of its own: request i writes its dense output into
  * arena (device memory, arena_bytes) at an offset that wraps around in arrival order; the

@@ -86,6 +86,30 @@ def test_served_tiles_equal_solo_calls_bit_exact():
         assert st["completed"] == 40 and st["bytes_peak"] <= (1 << 30)
 
 
+def test_wait_any_returns_each_completion_once_in_completion_order():
+    """ptg_tiles_wait_any over a mix: every ticket comes back exactly once, completion times
+    never decrease, and each output equals the stand-alone call."""
+    reqs = _mix(30, 1611, non_dyadic=0.2)
+    with ptg.Server(1 << 30) as srv:
+        tickets = srv.submit([_tile_req(r) for r in reqs])
+        index = {t: i for i, t in enumerate(tickets)}
+        seen, last = [], 0
+        for _ in reqs:
+            t, res = srv.wait_any(int(60e9))
+            assert res.status == ptg.PTG_OK and t in index and t not in seen
+            assert res.t_done_ns >= last
+            last = res.t_done_ns
+            r = reqs[index[t]]
+            assert res.user_tag == r["user_tag"]
+            got = _fetch(res, r)
+            srv.release(t)
+            assert torch.equal(got, _solo(r, res.kernel)), r
+            seen.append(t)
+        with pytest.raises(ptg.PtgError) as e:
+            srv.wait_any(0)
+        assert e.value.code == ptg.PTG_ENOENT
+
+
 def _overlaps(results):
     """Pairs of requests whose [admission, completion] intervals intersect: both were on the
     device at once."""

@@ -186,13 +186,16 @@ def _loadgen():
     import os
     lg = ctypes.CDLL(os.path.join(os.path.dirname(ptg.LIB_PATH), "libptg_loadgen.so"))
     p64 = ctypes.POINTER(ctypes.c_int64)
-    lg.ptg_lg_served.argtypes = [ctypes.c_void_p, ctypes.POINTER(ptg.TileReq), p64, ctypes.c_int32, p64, p64]
+    lg.ptg_lg_served.argtypes = [ctypes.c_void_p, ctypes.POINTER(ptg.TileReq), p64, ctypes.c_int32, p64, p64,
+                                 ctypes.c_int32]
     return lg, p64
 
 
-def test_loadgen_drives_the_server_at_arrival_times():
+@pytest.mark.parametrize("any_order", [0, 1])
+def test_loadgen_drives_the_server_at_arrival_times(any_order):
     """The native open-loop driver submits each request no earlier than its arrival and
-    reports completions after admission, in a run whose length follows the arrivals."""
+    reports completions after admission, in a run whose length follows the arrivals (taking
+    completions in request order, or in completion order)."""
     import numpy as np
     lg, p64 = _loadgen()
     n = 300
@@ -202,7 +205,8 @@ def test_loadgen_drives_the_server_at_arrival_times():
     adm = np.zeros(n, dtype=np.int64)
     with _srv(1 << 26, tile_ns=1000) as s:
         t0 = time.time()
-        rc = lg.ptg_lg_served(s.h, reqs, arr.ctypes.data_as(p64), n, done.ctypes.data_as(p64), adm.ctypes.data_as(p64))
+        rc = lg.ptg_lg_served(s.h, reqs, arr.ctypes.data_as(p64), n, done.ctypes.data_as(p64), adm.ctypes.data_as(p64),
+                              any_order)
         wall = time.time() - t0
         assert rc == ptg.PTG_OK
         st = s.stats()
@@ -220,7 +224,7 @@ def test_loadgen_rejects_bad_arrivals():
     arr = np.ascontiguousarray([10, 5], dtype=np.int64)  # not non-decreasing
     done = np.zeros(2, dtype=np.int64)
     with _srv(1 << 24) as s:
-        assert lg.ptg_lg_served(s.h, reqs, arr.ctypes.data_as(p64), 2, done.ctypes.data_as(p64), None) == ptg.PTG_EINVAL
+        assert lg.ptg_lg_served(s.h, reqs, arr.ctypes.data_as(p64), 2, done.ctypes.data_as(p64), None, 0) == ptg.PTG_EINVAL
 
 
 def _lattice_blocks(origin, extent, octaves, f0, lac=2.0):
@@ -340,3 +344,43 @@ def test_stream_driver_graph_mode_is_switched_off():
     lg = ctypes.CDLL(os.path.join(os.path.dirname(ptg.LIB_PATH), "libptg_loadgen.so"))
     lg.ptg_lg_plain.restype = ctypes.c_int
     assert lg.ptg_lg_plain(None, None, 0, None, ctypes.c_int64(0), 1, 1, None, None) == ptg.PTG_EINVAL
+
+
+def test_wait_any_returns_completions_in_completion_order():
+    """ptg_tiles_wait_any hands out each completion once, in completion order (host executor:
+    a request's simulated time is proportional to its tiles), skips completions already
+    released through their ticket, and reports PTG_ENOENT once nothing can complete."""
+    with ptg.Server(64 << 20, executor=ptg.PTG_EXEC_HOST, fake_tile_ns=200_000) as s:
+        big = ptg.tile_req(dim=2, extent=(512, 512, 1), octaves=4, base_freq=1 / 64, user_tag=1)
+        small = ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=4, base_freq=1 / 64, user_tag=2)
+        t_big, t_small = s.submit([big, small])
+        t1, r1 = s.wait_any(int(5e9))
+        t2, r2 = s.wait_any(int(5e9))
+        assert {t1, t2} == {t_big, t_small}
+        assert r1.t_done_ns <= r2.t_done_ns
+        s.release(t1)
+        s.release(t2)
+        with pytest.raises(ptg.PtgError) as e:
+            s.wait_any(int(1e8))
+        assert e.value.code == ptg.PTG_ENOENT
+        (t3,) = s.submit([small])
+        s.wait(t3, int(5e9))
+        s.release(t3)  # released before wait_any saw it: skipped
+        with pytest.raises(ptg.PtgError) as e:
+            s.wait_any(0)
+        assert e.value.code == ptg.PTG_ENOENT
+
+
+def test_wait_any_reports_eagain_when_only_the_caller_can_unblock():
+    with ptg.Server(1 << 20, executor=ptg.PTG_EXEC_HOST, fake_tile_ns=1000) as s:
+        a = ptg.tile_req(dim=2, extent=(384, 384, 1), octaves=2, base_freq=1 / 64)  # 576 KiB
+        t1, t2 = s.submit([a, a])
+        t, _ = s.wait_any(int(5e9))
+        assert t == t1
+        with pytest.raises(ptg.PtgError) as e:
+            s.wait_any(int(2e9))
+        assert e.value.code == ptg.PTG_EAGAIN
+        s.release(t1)
+        t, _ = s.wait_any(int(5e9))
+        assert t == t2
+        s.release(t2)
