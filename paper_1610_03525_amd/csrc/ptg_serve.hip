@@ -592,8 +592,10 @@ struct ptg_server {
     int64_t idle_since = 0;   // when the in-flight set last became empty
     int64_t last_query = 0;   // last hipStreamQuery of the running kernel
     int64_t last_event = 0;   // last submission or completion
+    // work units (a tile, or a workgroup's kServeWaves strips / 3D blocks) of the requests in
+    // flight and of those waiting for admission: the load that sizes work items
     int64_t tiles_in_flight = 0;
-    int64_t tiles_pending = 0;  // tiles of the requests waiting for admission
+    int64_t tiles_pending = 0;
     int64_t fake_busy_until = 0;
     ptg_server_stats st{};
     std::thread th;
@@ -601,6 +603,14 @@ struct ptg_server {
 };
 
 namespace ptg {
+
+// Work units of a request: its tiles, or for strip requests its groups of kServeWaves strips
+// (3D blocks), one per wave of a workgroup.
+static int64_t work_units(int32_t kernel, int64_t ntiles)
+{
+    const bool strips = kernel == PTG_TUNE_STRIP_2D || kernel == PTG_TUNE_STRIP_3D;
+    return strips ? (ntiles + kServeWaves - 1) / kServeWaves : ntiles;
+}
 
 // Tiles per work item: the configured count; else sized to the load.  With little in
 // flight or waiting a request is cut into small items that spread over many workgroups
@@ -801,7 +811,7 @@ static void span_done(ptg_server *s, uint64_t ticket, int32_t phase)
 static void complete(ptg_server *s, uint64_t ticket, int status)
 {
     Request &r = s->by_ticket[ticket];
-    if (r.status == 2) s->tiles_in_flight -= r.ntiles;
+    if (r.status == 2) s->tiles_in_flight -= work_units(r.kernel, r.ntiles);
     if (r.lat) lat_unref(s, ticket, r, status != PTG_OK);
     r.status = status;
     r.t_done = now_ns();
@@ -825,7 +835,7 @@ static void publish(ptg_server *s, uint64_t ticket, Request &r, int phase)
     const int64_t nwork = phase == 1 ? (int64_t)r.lat_fill.size() : r.ntiles;
     const int64_t per = phase == 1 ? r.fill_per : r.per_item;
     const uint64_t items = (uint64_t)(phase == 1 ? r.fill_items : r.items);
-    if (phase == 2) s->tiles_in_flight += r.ntiles;
+    if (phase == 2) s->tiles_in_flight += work_units(r.kernel, r.ntiles);
     r.ring_begin = s->tail;
     r.ring_end = s->tail + items;
     s->ring_order.push_back({ticket, r.ring_end, phase, false});
@@ -957,7 +967,7 @@ static void admit(ptg_server *s)
             continue;
         }
         it = s->pending.erase(it);
-        s->tiles_pending -= r.ntiles;
+        s->tiles_pending -= work_units(r.kernel, r.ntiles);
         r.t_admit = now_ns();
         s->st.admitted++;
         if (r.lat) {
@@ -1312,7 +1322,7 @@ int ptg_tiles_submit(ptg_server *s, const ptg_tile_req *reqs, int32_t n, uint64_
         r.lat = lat[i];
         r.t_submit = t;
         s->pending.push_back(ticket);
-        s->tiles_pending += r.ntiles;
+        s->tiles_pending += work_units(r.kernel, r.ntiles);
         tickets_out[i] = ticket;
         s->st.submitted++;
     }
