@@ -295,6 +295,15 @@ PTG_API int ptg_tune_set_3d(const ptg_params *p, int64_t nx, int64_t ny, int64_t
 /* Forget every recorded shape. */
 PTG_API void ptg_tune_reset(void);
 
+/* Persist the recorded shapes: a text file whose first line names the current device
+ * (architecture name and compute-unit count; "none" without a device), then one line per
+ * class.  ptg_tune_load adds the file's shapes to the table when it was written for the
+ * same device, and skips it otherwise (*loaded, optional, receives the number of shapes
+ * taken: 0 for another device).  Errors: PTG_EINVAL (NULL path, not a table, a malformed
+ * or invalid entry: nothing is taken), PTG_ENOENT (the file cannot be opened or written). */
+PTG_API int ptg_tune_save(const char *path);
+PTG_API int ptg_tune_load(const char *path, int32_t *loaded);
+
 /* ---- a6: HIP-graph batches of dense fields ------------------------------------
  * A batch collects dense-field calls -- the one kernel launch each ptg_fbm_2d / ptg_fbm_3d
  * call makes, with its arguments -- and launches them together as the kernel nodes of one

@@ -174,6 +174,8 @@ def lib():
     L.ptg_tune_set_3d.argtypes = [_PP, _i64, _i64, _i64, _i32]
     L.ptg_tune_reset.argtypes = []
     L.ptg_tune_reset.restype = None
+    L.ptg_tune_save.argtypes = [ctypes.c_char_p]
+    L.ptg_tune_load.argtypes = [ctypes.c_char_p, _IP]
     L.ptg_batch_create.argtypes = [_i32, ctypes.POINTER(ctypes.c_void_p)]
     L.ptg_batch_add_2d.argtypes = [_vp, _PP, _i64, _i64, _i64, _i64, _vp, _i64]
     L.ptg_batch_add_3d.argtypes = [_vp, _PP, _i64, _i64, _i64, _i64, _i64, _i64, _vp]
@@ -455,6 +457,19 @@ def tune_set(shape, value, out_dtype=PTG_F32, **kw):
 
 def tune_reset():
     lib().ptg_tune_reset()
+
+
+def tune_save(path):
+    """Write the recorded shapes to `path`, keyed by the current device."""
+    _check(lib().ptg_tune_save(os.fsencode(path)))
+
+
+def tune_load(path) -> int:
+    """Add the shapes of a file written for this device; returns how many were taken (0 for
+    a table of another device)."""
+    n = ctypes.c_int32()
+    _check(lib().ptg_tune_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
 
 
 class Batch:

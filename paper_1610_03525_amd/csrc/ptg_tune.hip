@@ -9,6 +9,8 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -263,6 +265,80 @@ void ptg_tune_reset(void)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     g_table.clear();
+}
+
+// The device a table belongs to: its architecture name and compute-unit count ("none" when
+// no device is visible, e.g. on a build host).
+static void device_identity(char *arch, size_t n, int *cus)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        std::snprintf(arch, n, "%s", prop.gcnArchName);
+        for (char *c = arch; *c; ++c)
+            if (*c == ' ' || *c == '\n') *c = '_';
+        *cus = prop.multiProcessorCount;
+    } else {
+        (void)hipGetLastError();
+        std::snprintf(arch, n, "none");
+        *cus = 0;
+    }
+}
+
+int ptg_tune_save(const char *path)
+{
+    if (!path) return fail(PTG_EINVAL, "path is NULL");
+    char arch[256];
+    int cus = 0;
+    device_identity(arch, sizeof(arch), &cus);
+    std::FILE *f = std::fopen(path, "w");
+    if (!f) return fail(PTG_ENOENT, "cannot open %s for writing", path);
+    std::fprintf(f, "ptg_tune 1 %s %d\n", arch, cus);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (const auto &kv : g_table)
+            std::fprintf(f, "%d %d %d %d %d %d\n", kv.first.kernel, kv.first.smooth, kv.first.f16,
+                         kv.first.size_class, kv.first.ladder, kv.second);
+    }
+    const bool ok = std::fflush(f) == 0;
+    std::fclose(f);
+    return ok ? PTG_OK : fail(PTG_ENOENT, "writing %s failed", path);
+}
+
+int ptg_tune_load(const char *path, int32_t *loaded)
+{
+    if (!path) return fail(PTG_EINVAL, "path is NULL");
+    if (loaded) *loaded = 0;
+    std::FILE *f = std::fopen(path, "r");
+    if (!f) return fail(PTG_ENOENT, "cannot open %s", path);
+    char arch[256], farch[256];
+    int cus = 0, fcus = 0, ver = 0;
+    device_identity(arch, sizeof(arch), &cus);
+    if (std::fscanf(f, "ptg_tune %d %255s %d", &ver, farch, &fcus) != 3 || ver != 1) {
+        std::fclose(f);
+        return fail(PTG_EINVAL, "%s is not a tuning table", path);
+    }
+    // entries of another device are skipped; every entry is validated before any is kept
+    std::map<TuneKey, int> rows;
+    int k, sm, f16, sc, lad, v, n;
+    while ((n = std::fscanf(f, "%d %d %d %d %d %d", &k, &sm, &f16, &sc, &lad, &v)) == 6) {
+        if (!is_candidate(k, v) || sm < 0 || sm > 64 || (f16 != 0 && f16 != 1) || sc < 0 || sc > 62 || lad < 0 ||
+            lad > 64) {
+            std::fclose(f);
+            return fail(PTG_EINVAL, "%s: bad entry", path);
+        }
+        rows[TuneKey{k, sm, f16, sc, lad}] = v;
+    }
+    const bool clean = n == EOF;
+    std::fclose(f);
+    if (!clean) return fail(PTG_EINVAL, "%s: malformed entry", path);
+    if (std::strcmp(arch, farch) != 0 || cus != fcus) return PTG_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (const auto &kv : rows) g_table[kv.first] = kv.second;
+    }
+    if (loaded) *loaded = (int32_t)rows.size();
+    return PTG_OK;
 }
 
 }  // extern "C"

@@ -122,3 +122,17 @@ def test_server_with_fixed_and_tuned_tile_heights_serves_exact_tiles():
         th = srv.stats()["tile_h"]
         assert all(v in (16, 32, 64) for v in th)
         _served_equals_solo(srv)
+
+
+def test_tuned_table_saved_and_loaded_on_this_device(tmp_path):
+    """A table tuned here is written with this device's architecture name and CU count and
+    loads back in full."""
+    out = torch.empty((256, 300), dtype=torch.float32, device="cuda")
+    r = ptg.tune_2d(out, octaves=4, base_freq=0.013)
+    path = tmp_path / "t.txt"
+    ptg.tune_save(path)
+    head = path.read_text().splitlines()[0].split()
+    assert head[2].startswith("gfx") and int(head[3]) > 0
+    ptg.tune_reset()
+    assert ptg.tune_load(path) >= 1
+    assert ptg.tune_query((256, 300), octaves=4, base_freq=0.013)[1] == r["value"]

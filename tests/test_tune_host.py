@@ -98,3 +98,44 @@ def test_server_tile_height_sets_the_tile_count():
             assert s.wait(t, 10_000_000_000).kernel == ptg.PTG_TUNE_STRIP_3D  # periods 16..2
             (t,) = s.submit([ptg.tile_req(dim=3, extent=(64, 8, 8), octaves=4, base_freq=3e-4)])
             assert s.wait(t, 10_000_000_000).kernel == ptg.PTG_TUNE_GENERAL_3D  # not dyadic
+
+
+def test_save_load_roundtrip_keyed_by_device(tmp_path):
+    """A saved table loads back on the same device (on a host without a GPU the key is
+    "none"); a table written for another device is skipped; malformed tables and missing
+    files are errors, and nothing of a bad table is taken."""
+    kw2 = dict(octaves=4, base_freq=0.013)
+    kw3 = dict(smoothness=2, octaves=6, base_freq=8 / 512)
+    ptg.tune_set((256, 300), 32, **kw2)
+    ptg.tune_set((512, 512, 512), 2, **kw3)
+    path = tmp_path / "table.txt"
+    ptg.tune_save(path)
+    head = path.read_text().splitlines()[0].split()
+    assert head[:2] == ["ptg_tune", "1"] and len(head) == 4
+    ptg.tune_reset()
+    assert ptg.tune_query((256, 300), **kw2) == ("general_2d", 64)
+    assert ptg.tune_load(path) == 2
+    assert ptg.tune_query((256, 300), **kw2) == ("general_2d", 32)
+    assert ptg.tune_query((512, 512, 512), **kw3) == ("strip_3d", 2)
+
+    ptg.tune_reset()
+    lines = path.read_text().splitlines()
+    other = tmp_path / "other.txt"
+    other.write_text("\n".join(["ptg_tune 1 gfx000 7"] + lines[1:]) + "\n")
+    assert ptg.tune_load(other) == 0
+    assert ptg.tune_query((256, 300), **kw2) == ("general_2d", 64)
+
+    bad = tmp_path / "bad.txt"
+    bad.write_text("\n".join(lines[:1] + ["1 1 0 17 3 48"]) + "\n")  # 48 rows is no candidate
+    with pytest.raises(ptg.PtgError) as e:
+        ptg.tune_load(bad)
+    assert e.value.code == ptg.PTG_EINVAL
+    junk = tmp_path / "junk.txt"
+    junk.write_text("not a table\n")
+    with pytest.raises(ptg.PtgError) as e:
+        ptg.tune_load(junk)
+    assert e.value.code == ptg.PTG_EINVAL
+    with pytest.raises(ptg.PtgError) as e:
+        ptg.tune_load(tmp_path / "missing.txt")
+    assert e.value.code == ptg.PTG_ENOENT
+    assert ptg.tune_query((256, 300), **kw2) == ("general_2d", 64)
