@@ -196,32 +196,40 @@ PTG_API int ptg_fbm_3d(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, 
 
 /* ---- stage entry points (the same device code the fields run, exposed per stage) */
 
-/* a1. Coordinate step for n consecutive world samples x0 .. x0+n-1 and octaves
- * 0 .. octaves-1 of (base_freq, lacunarity): cells_dev[o*n + i] (int64) and
- * frac_dev[o*n + i] (float).  Errors: PTG_EINVAL, PTG_EHIP. */
+/* a1. Coordinate step (Sec. 4: octave o at frequency base_freq * lacunarity^o, by repeated
+ * FP64 multiplication) for n consecutive world samples x0 .. x0+n-1 and octaves
+ * 0 .. octaves-1, each sample at its centre: u = (X + 1/2) f_o in FP64, cell = floor(u),
+ * fraction u - cell: cells_dev[o*n + i] (int64) and frac_dev[o*n + i] (float, rounded to
+ * nearest).  Device buffers of octaves*n entries, owned by the caller.
+ * Errors: PTG_EINVAL, PTG_EHIP. */
 PTG_API int ptg_coords(double base_freq, double lacunarity, int32_t octaves, int64_t x0, int64_t n,
                int64_t *cells_dev, float *frac_dev, void *stream);
 
-/* a2. K1 for the zero-gradient model (Sec. 3.3): node heights of the node box
+/* a2. K1 for the zero-gradient model (Sec. 3.3, random node heights): node heights of the node box
  * ix0 <= ix < ix0+nx, iy0 <= iy < iy0+ny of octave `octave`, heights_dev[j*nx + i]
  * (FP32, exact: top 24 key bits / 2^23 - 1).  Errors: PTG_EINVAL, PTG_EHIP. */
 PTG_API int ptg_heights_2d(uint32_t seed, int32_t octave, int64_t ix0, int64_t iy0, int64_t nx, int64_t ny,
                    float *heights_dev, void *stream);
 
-/* a2. K1 lattice kernel, 2D: for the node box ix0 <= ix < ix0+nx, iy0 <= iy < iy0+ny of
- * octave `octave`: keys_dev[j*nx + i] (uint32, may be NULL) and the unit gradient,
+/* a2. K1 lattice kernel, 2D (Sec. 3.2: the grid of random gradients each octave's cells
+ * interpolate; the hash and the gradient map are stated above): for the node box
+ * ix0 <= ix < ix0+nx, iy0 <= iy < iy0+ny of octave `octave`: keys_dev[j*nx + i] (uint32,
+ * may be NULL) and the unit gradient,
  * SoA: grad_dev[j*nx + i] = x component, grad_dev[nx*ny + j*nx + i] = y component
  * (may be NULL).  Errors: PTG_EINVAL (negative sizes, octave < 0), PTG_EHIP. */
 PTG_API int ptg_lattice_2d(uint32_t seed, int32_t octave, int64_t ix0, int64_t iy0, int64_t nx,
                    int64_t ny, uint32_t *keys_dev, float *grad_dev, void *stream);
 
-/* a2. K1, 3D: node box of nx*ny*nz nodes, index q = (k*ny + j)*nx + i; keys_dev[q],
- * second words second_dev[q] (may be NULL), gradients SoA grad_dev[c*nx*ny*nz + q]. */
+/* a2. K1, 3D (Sec. 3.2 lattice, Sec. 3.4 D3 cells): node box of nx*ny*nz nodes, index
+ * q = (k*ny + j)*nx + i; keys_dev[q], second words second_dev[q] (may be NULL), unit
+ * gradients SoA grad_dev[c*nx*ny*nz + q] (may be NULL).  Device buffers owned by the
+ * caller.  Errors: PTG_EINVAL (negative sizes, octave < 0), PTG_EHIP. */
 PTG_API int ptg_lattice_3d(uint32_t seed, int32_t octave, int64_t ix0, int64_t iy0, int64_t iz0,
                    int64_t nx, int64_t ny, int64_t nz, uint32_t *keys_dev, uint32_t *second_dev,
                    float *grad_dev, void *stream);
 
-/* a3. K2 per-cell coefficient kernel, 2D: from a node-gradient box in the layout K1
+/* a3. K2 per-cell coefficient kernel, 2D (Sec. 2.2, the cell's polynomial from its corner
+ * constraints): from a node-gradient box in the layout K1
  * writes (nnx*nny nodes, SoA), the monomial coefficients c_ij of h = sum c_ij x^i y^j
  * (eq. polynomial, D = 2, n = 2*smoothness+1) of every cell of the box:
  * coeff_dev[(cj*(nnx-1) + ci)*(n+1)^2 + i*(n+1) + j], scaled by `amplitude`.
@@ -230,7 +238,7 @@ PTG_API int ptg_lattice_3d(uint32_t seed, int32_t octave, int64_t ix0, int64_t i
 PTG_API int ptg_cells_2d(int32_t smoothness, const float *grad_dev, int64_t nnx, int64_t nny,
                  float amplitude, float *coeff_dev, void *stream);
 
-/* a3. K2, 3D: coefficient c_ijk of x^i y^j z^k at
+/* a3. K2, 3D (Sec. 2.2, Sec. 3.4): coefficient c_ijk of x^i y^j z^k at
  * coeff_dev[cell*(n+1)^3 + (i*(n+1) + j)*(n+1) + k], cell = (ck*(nny-1) + cj)*(nnx-1) + ci. */
 PTG_API int ptg_cells_3d(int32_t smoothness, const float *grad_dev, int64_t nnx, int64_t nny,
                  int64_t nnz, float amplitude, float *coeff_dev, void *stream);
@@ -247,7 +255,7 @@ PTG_API int ptg_cells_3d(int32_t smoothness, const float *grad_dev, int64_t nnx,
  *                        model, else 64);
  *   PTG_TUNE_STRIP_2D    dyadic 2D kernel (64 x 64 strips, one per wave): waves per
  *                        workgroup, 1, 2 or 4;
- *   PTG_TUNE_STRIP_3D    dyadic 3D kernel (64 x 8 x 4 blocks, one per wave): waves per
+ *   PTG_TUNE_STRIP_3D    dyadic 3D kernel (64 x 8 x 16 blocks, one per wave): waves per
  *                        workgroup, 1, 2 or 4;
  *   PTG_TUNE_GENERAL_3D, PTG_TUNE_DYADIC_2D (precision forms, dyadic 2D tiles): fixed.
  * A class is keyed by (kernel, smoothness, output type, ceil(log2(samples)), ladder class:
