@@ -108,15 +108,15 @@ extern "C" {
                                    /* node (uniform on [-1, 1) from the node's key: top 24  */
                                    /* bits / 2^23 - 1), zero gradients at the corners;      */
                                    /* continuous across faces, its gradient pinned at the   */
-                                   /* nodes only.  2D, smoothness 1, plain form, fields only */
-                                   /* (not served)                                          */
+                                   /* nodes only.  2D, smoothness 1, plain form; fields and  */
+                                   /* served tiles                                          */
 #define PTG_MODEL_HEIGHT_GRADIENT 2 /* tensor Hermite cells with a random height per node    */
                                    /* (uniform on [-1, 1): in 2D from the node's second     */
                                    /* hash word, in 3D from its third, fmix32(second3 ^     */
                                    /* 0x165667B1)) and the lattice gradient times           */
                                    /* gradient_weight w (Sec. 3.1 heights, Sec. 3.4, Sec. 4 */
-                                   /* w); C1 / C2 across faces.  2D and 3D, plain form,     */
-                                   /* fields only (not served)                              */
+                                   /* w); C1 / C2 / C3 across faces.  2D and 3D, plain     */
+                                   /* form; fields and served tiles                         */
 
 #define PTG_MODEL_PERLIN 3          /* comparison path: Perlin's gradient noise (Sec. 3.2)  */
                                    /* on the same hashed unit gradients, corner            */
@@ -365,14 +365,17 @@ PTG_API int ptg_batch_destroy(ptg_batch *b);
 
 /* ---- a6: serving (continuous batching of terrain tiles) ----------------------- */
 /* A server owns an output arena of hbm_budget_bytes and one persistent kernel.  Requests
- * (terrain tiles of any size, 2D or 3D, C1 or C2, any octave parameters, FP32 output) are
+ * (terrain tiles of any size, 2D or 3D, any octave parameters, FP32 output, plain form, the
+ * gradient or height-and-gradient cells at C1, C2 or C3 or the zero-gradient cells (2D C1);
+ * not the comparison paths) are
  * queued by ptg_tiles_submit, admitted while arena bytes and request slots are free, cut
  * into work items and published into a ring that the persistent kernel's workgroups drain
  * while earlier requests are still running.  A 2D request whose ladder is dyadic (base_freq
  * 2^-k, lacunarity 2, finest period >= 2) and whose 64 x 64 strip footprint fits a serving
  * workgroup runs as strips, one per wave, with the same device code as ptg_fbm_2d with
- * PTG_PATH_DYADIC; a 3D request with a dyadic ladder of finest period >= 8 runs as 64 x 8 x 4
- * blocks with the device code of ptg_fbm_3d with PTG_PATH_DYADIC; every other request runs
+ * PTG_PATH_DYADIC; a 3D C1 / C2 request with a dyadic ladder of finest period >= 2 whose
+ * footprint fits runs as 64 x 8 x 16 blocks with the device code of ptg_fbm_3d with
+ * PTG_PATH_DYADIC; every other request runs
  * as 64 x tile_h (2D) or 64 x 8 x 8 (3D) sample tiles with the device code of
  * PTG_PATH_GENERAL.  A served tile equals the corresponding stand-alone call bit for bit
  * (ptg_tile_result.kernel says which).  With cfg->lattice_cache the general 2D tiles read

@@ -75,7 +75,7 @@ struct ServeReqDesc {
     int64_t ntiles;
     int32_t kernel;   // PTG_TUNE_GENERAL_2D / _GENERAL_3D (tiles), PTG_TUNE_STRIP_2D (64 x 64 strips),
                       // PTG_TUNE_STRIP_3D (64 x 8 x 16 blocks)
-    int32_t pad;
+    int32_t model;    // PTG_MODEL_GRADIENT, _ZERO_GRADIENT (2D, C1) or _HEIGHT_GRADIENT
     union {
         Fbm2dArgs a2;
         Fbm3dArgs a3;
@@ -162,78 +162,134 @@ __device__ __forceinline__ void fill_lat_block(const ServeReqDesc &rq, const uin
 //
 // Strips [t0, t1) of a dyadic 2D request: wave w takes t0 + w, t0 + w + 4, ... (the same
 // per-strip code as the dense strip kernel, so a served strip equals that kernel's output).
-template <int M, int LO>
+template <int M, int LO, int MD>
 __device__ __noinline__ void serve_strips(const Fbm2dStripArgs &a, const StripShared &sh, uint32_t *wl, int64_t t0,
-                                             int64_t t1, int tid)
+                                          int64_t t1, int tid)
 {
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     float2 *nodes = reinterpret_cast<float2 *>(wl + strip_shared_words(a.nodes_hashed, a.keys_total) +
-                                               wave * strip_wave_words(a.nodes_total, a.keys_total));
-    StripWave<M, float, LO> w(a, sh, nodes, lane);
+                                               wave * strip_wave_words(a.nodes_total, a.keys_total, MD == 2));
+    StripWave<M, float, LO, MD> w(a, sh, nodes, lane);
     for (int64_t st = t0 + wave; st < t1; st += kServeWaves) w.run(a, sh, wl, wl + a.keys_total, st);
 }
 
-template <int M>
+template <int M, int MD>
 __device__ __forceinline__ void serve_strips_lo(const Fbm2dStripArgs &a, const StripShared &sh, uint32_t *wl,
                                                 int64_t t0, int64_t t1, int tid)
 {
     switch (a.lo) {  // admission guarantees 1 <= lo <= 6
-    case 1: serve_strips<M, 1>(a, sh, wl, t0, t1, tid); break;
-    case 2: serve_strips<M, 2>(a, sh, wl, t0, t1, tid); break;
-    case 3: serve_strips<M, 3>(a, sh, wl, t0, t1, tid); break;
-    case 4: serve_strips<M, 4>(a, sh, wl, t0, t1, tid); break;
-    case 5: serve_strips<M, 5>(a, sh, wl, t0, t1, tid); break;
-    default: serve_strips<M, 6>(a, sh, wl, t0, t1, tid); break;
+    case 1: serve_strips<M, 1, MD>(a, sh, wl, t0, t1, tid); break;
+    case 2: serve_strips<M, 2, MD>(a, sh, wl, t0, t1, tid); break;
+    case 3: serve_strips<M, 3, MD>(a, sh, wl, t0, t1, tid); break;
+    case 4: serve_strips<M, 4, MD>(a, sh, wl, t0, t1, tid); break;
+    case 5: serve_strips<M, 5, MD>(a, sh, wl, t0, t1, tid); break;
+    default: serve_strips<M, 6, MD>(a, sh, wl, t0, t1, tid); break;
+    }
+}
+
+// A strip request of any served cell model and order (admission: the zero-gradient model
+// at C1 only; orders 1..3).
+__device__ __forceinline__ void serve_strips_req(const Fbm2dStripArgs &a, int model, int smooth,
+                                                 const StripShared &sh, uint32_t *wl, int64_t t0, int64_t t1, int tid)
+{
+    if (model == PTG_MODEL_ZERO_GRADIENT) {
+        serve_strips_lo<1, 1>(a, sh, wl, t0, t1, tid);
+    } else if (model == PTG_MODEL_HEIGHT_GRADIENT) {
+        if (smooth == 1) serve_strips_lo<1, 2>(a, sh, wl, t0, t1, tid);
+        else if (smooth == 2) serve_strips_lo<2, 2>(a, sh, wl, t0, t1, tid);
+        else serve_strips_lo<3, 2>(a, sh, wl, t0, t1, tid);
+    } else {
+        if (smooth == 1) serve_strips_lo<1, 0>(a, sh, wl, t0, t1, tid);
+        else if (smooth == 2) serve_strips_lo<2, 0>(a, sh, wl, t0, t1, tid);
+        else serve_strips_lo<3, 0>(a, sh, wl, t0, t1, tid);
     }
 }
 
 // Blocks [t0, t1) of a dyadic 3D request, wave w taking t0 + w, t0 + w + 4, ... (the dense
 // 3D strip kernel's per-block code).
-template <int M, int LO>
+template <int M, int LO, int MD>
 __device__ __noinline__ void serve_blocks(const Fbm3dStripArgs &a, const Strip3Shared &sh, float4 *tab, int64_t t0,
-                                             int64_t t1, int tid)
+                                          int64_t t1, int tid)
 {
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int listed = a.keys_col + 4 * a.n_coarse;
     const uint32_t *wl_key = reinterpret_cast<const uint32_t *>(tab) + strip3_tab_words(a.tab_total);
     float *gx = reinterpret_cast<float *>(tab) + strip3_shared_words(a.tab_total, listed, a.nodes_listed) +
-                wave * strip3_wave_words(a.nodes_total, a.keys_total);
-    Strip3Wave<M, float, LO> w(a, sh, gx, lane);
+                wave * strip3_wave_words(a.nodes_total, a.keys_total, MD == 2 ? 1 : 0);
+    Strip3Wave<M, float, LO, MD> w(a, sh, gx, lane);
     for (int64_t b = t0 + wave; b < t1; b += kServeWaves) w.run(a, sh, tab, wl_key, wl_key + listed, b);
 }
 
-// General tiles [t0, t1) of a 2D / 3D request, one after the other.
-template <int M, int TH>
-__device__ __noinline__ void serve_tiles_2d(const Fbm2dArgs &a, const LatCache *lat, int64_t t0, int64_t t1,
-                                            float4 *lds4)
-{
-    for (int64_t t = t0; t < t1; ++t) {
-        fbm2d_general_tile<M, float, TH>(a, t, lds4, lat);
-        __syncthreads();  // LDS reuse by the next tile
-    }
-}
-
-template <int M>
-__device__ __noinline__ void serve_tiles_3d(const Fbm3dArgs &a, int64_t t0, int64_t t1, float4 *lds4)
-{
-    for (int64_t t = t0; t < t1; ++t) {
-        fbm3d_general_tile<M, float>(a, t, lds4);
-        __syncthreads();
-    }
-}
-
-template <int M>
+template <int M, int MD>
 __device__ __forceinline__ void serve_blocks_lo(const Fbm3dStripArgs &a, const Strip3Shared &sh, float4 *tab,
                                                 int64_t t0, int64_t t1, int tid)
 {
     switch (a.lo) {
-    case 1: serve_blocks<M, 1>(a, sh, tab, t0, t1, tid); break;
-    case 2: serve_blocks<M, 2>(a, sh, tab, t0, t1, tid); break;
-    case 3: serve_blocks<M, 3>(a, sh, tab, t0, t1, tid); break;
-    default: serve_blocks<M, 4>(a, sh, tab, t0, t1, tid); break;
+    case 1: serve_blocks<M, 1, MD>(a, sh, tab, t0, t1, tid); break;
+    case 2: serve_blocks<M, 2, MD>(a, sh, tab, t0, t1, tid); break;
+    case 3: serve_blocks<M, 3, MD>(a, sh, tab, t0, t1, tid); break;
+    default: serve_blocks<M, 4, MD>(a, sh, tab, t0, t1, tid); break;
     }
 }
 
+// General tiles [t0, t1) of a 2D / 3D request, one after the other.
+template <int M, int TH, int MD>
+__device__ __noinline__ void serve_tiles_2d(const Fbm2dArgs &a, const LatCache *lat, int64_t t0, int64_t t1,
+                                            float4 *lds4)
+{
+    for (int64_t t = t0; t < t1; ++t) {
+        fbm2d_general_tile<M, float, TH, MD>(a, t, lds4, lat);
+        __syncthreads();  // LDS reuse by the next tile
+    }
+}
+
+template <int M, int MD>
+__device__ __forceinline__ void serve_tiles_2d_th(const Fbm2dArgs &a, const LatCache *lat, int64_t t0, int64_t t1,
+                                                  float4 *lds4)
+{
+    if (a.tile_h == 16) serve_tiles_2d<M, 16, MD>(a, lat, t0, t1, lds4);
+    else if (a.tile_h == 32) serve_tiles_2d<M, 32, MD>(a, lat, t0, t1, lds4);
+    else serve_tiles_2d<M, 64, MD>(a, lat, t0, t1, lds4);
+}
+
+__device__ __forceinline__ void serve_tiles_2d_req(const Fbm2dArgs &a, int model, int smooth, const LatCache *lat,
+                                                   int64_t t0, int64_t t1, float4 *lds4)
+{
+    if (model == PTG_MODEL_ZERO_GRADIENT) {
+        serve_tiles_2d_th<1, 1>(a, lat, t0, t1, lds4);
+    } else if (model == PTG_MODEL_HEIGHT_GRADIENT) {
+        if (smooth == 1) serve_tiles_2d_th<1, 2>(a, lat, t0, t1, lds4);
+        else if (smooth == 2) serve_tiles_2d_th<2, 2>(a, lat, t0, t1, lds4);
+        else serve_tiles_2d_th<3, 2>(a, lat, t0, t1, lds4);
+    } else {
+        if (smooth == 1) serve_tiles_2d_th<1, 0>(a, lat, t0, t1, lds4);
+        else if (smooth == 2) serve_tiles_2d_th<2, 0>(a, lat, t0, t1, lds4);
+        else serve_tiles_2d_th<3, 0>(a, lat, t0, t1, lds4);
+    }
+}
+
+template <int M, int MD>
+__device__ __noinline__ void serve_tiles_3d(const Fbm3dArgs &a, int64_t t0, int64_t t1, float4 *lds4)
+{
+    for (int64_t t = t0; t < t1; ++t) {
+        fbm3d_general_tile<M, float, MD>(a, t, lds4);
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void serve_tiles_3d_req(const Fbm3dArgs &a, int model, int smooth, int64_t t0, int64_t t1,
+                                                   float4 *lds4)
+{
+    if (model == PTG_MODEL_HEIGHT_GRADIENT) {
+        if (smooth == 1) serve_tiles_3d<1, 2>(a, t0, t1, lds4);
+        else if (smooth == 2) serve_tiles_3d<2, 2>(a, t0, t1, lds4);
+        else serve_tiles_3d<3, 2>(a, t0, t1, lds4);
+    } else {
+        if (smooth == 1) serve_tiles_3d<1, 0>(a, t0, t1, lds4);
+        else if (smooth == 2) serve_tiles_3d<2, 0>(a, t0, t1, lds4);
+        else serve_tiles_3d<3, 0>(a, t0, t1, lds4);
+    }
+}
 
 __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeItem *ring, const ServeReqDesc *reqs,
                                                uint32_t *done, ServeDevCtl *dc, int32_t ring_size)
@@ -356,10 +412,7 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
                 strip_prologue(rq.as, sh, wl, wl + rq.as.keys_total, tid, 256);
                 __syncthreads();
             }
-            if (rq.smooth == 1)
-                serve_strips_lo<1>(rq.as, sh, wl, s_item.tile0, t1, tid);
-            else
-                serve_strips_lo<2>(rq.as, sh, wl, s_item.tile0, t1, tid);
+            serve_strips_req(rq.as, rq.model, rq.smooth, sh, wl, s_item.tile0, t1, tid);
             __syncthreads();
         } else if (rq.kernel == PTG_TUNE_STRIP_3D) {
             Strip3Shared &sh = *reinterpret_cast<Strip3Shared *>(lds4);
@@ -373,10 +426,14 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
                     strip3_prologue<2>(rq.a3s, sh, tab, wl_key, wl_node, tid, 256);
                 __syncthreads();
             }
-            if (rq.smooth == 1)
-                serve_blocks_lo<1>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
-            else
-                serve_blocks_lo<2>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
+            const bool hg = rq.model == PTG_MODEL_HEIGHT_GRADIENT;  // admission: orders 1, 2
+            if (rq.smooth == 1) {
+                if (hg) serve_blocks_lo<1, 2>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
+                else serve_blocks_lo<1, 0>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
+            } else {
+                if (hg) serve_blocks_lo<2, 2>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
+                else serve_blocks_lo<2, 0>(rq.a3s, sh, tab, s_item.tile0, t1, tid);
+            }
             __syncthreads();
         }
         if (rq.lat_mode == 2) {
@@ -389,30 +446,11 @@ __global__ __launch_bounds__(256, 2) void k_serve(ServeHostCtl *hc, const ServeI
         }
         const bool tiles = rq.lat_mode != 2 && (rq.kernel == PTG_TUNE_GENERAL_2D || rq.kernel == PTG_TUNE_GENERAL_3D);
         if (tiles && rq.dim == 2) {
-            const int th = rq.a2.tile_h;
             const LatCache lc{rq.lat_base, s_tbl, rq.lat_n, rq.lat_bx0, rq.lat_by0, rq.lat_nbx, rq.lat_tbl0};
             const LatCache *lat = rq.lat_mode == 1 ? &lc : nullptr;
-            const int64_t t0 = s_item.tile0;
-            if (rq.smooth == 1) {
-                if (th == 16)
-                    serve_tiles_2d<1, 16>(rq.a2, lat, t0, t1, lds4);
-                else if (th == 32)
-                    serve_tiles_2d<1, 32>(rq.a2, lat, t0, t1, lds4);
-                else
-                    serve_tiles_2d<1, 64>(rq.a2, lat, t0, t1, lds4);
-            } else {
-                if (th == 16)
-                    serve_tiles_2d<2, 16>(rq.a2, lat, t0, t1, lds4);
-                else if (th == 32)
-                    serve_tiles_2d<2, 32>(rq.a2, lat, t0, t1, lds4);
-                else
-                    serve_tiles_2d<2, 64>(rq.a2, lat, t0, t1, lds4);
-            }
+            serve_tiles_2d_req(rq.a2, rq.model, rq.smooth, lat, s_item.tile0, t1, lds4);
         } else if (tiles) {
-            if (rq.smooth == 1)
-                serve_tiles_3d<1>(rq.a3, s_item.tile0, t1, lds4);
-            else
-                serve_tiles_3d<2>(rq.a3, s_item.tile0, t1, lds4);
+            serve_tiles_3d_req(rq.a3, rq.model, rq.smooth, s_item.tile0, t1, lds4);
         }
         // every wave's output stores have reached the L2 before thread 0's release writes it back
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
@@ -552,7 +590,7 @@ struct Request {
 struct ptg_server {
     ptg_server_cfg cfg{};
     bool gpu = true;
-    int tile_h2[2] = {ptg::kTile2, ptg::kTile2};  // 2D tile height for C1 / C2 requests
+    int tile_h2[2] = {ptg::kTile2, ptg::kTile2};  // 2D tile height for C1 / C2 requests (C3: 64)
     hipStream_t stream = nullptr;
     int workgroups = 0;
     ptg::ServeHostCtl *hc = nullptr;
@@ -825,6 +863,10 @@ static void complete(ptg_server *s, uint64_t ticket, int status)
     s->cv_done.notify_all();
 }
 
+// 2D general-tile height of a served request: the configured or tuned one for C1 / C2, 64
+// rows for higher orders.
+static int served_tile_h(const ptg_server *s, int smooth) { return smooth <= 2 ? s->tile_h2[smooth - 1] : kTile2; }
+
 // Publish one phase of an admitted request (slot held): 1 = the fills of its missing
 // lattice blocks, 2 = its tiles.
 static void publish(ptg_server *s, uint64_t ticket, Request &r, int phase)
@@ -861,6 +903,7 @@ static void publish(ptg_server *s, uint64_t ticket, Request &r, int phase)
     d.target = s->slot_total[slot];
     d.ntiles = nwork;
     d.kernel = r.kernel;
+    d.model = p->model;
     if (r.kernel == PTG_TUNE_STRIP_2D) {
         int k = 0;
         (void)dyadic_shift(p, &k);  // validated at submission
@@ -873,7 +916,7 @@ static void publish(ptg_server *s, uint64_t ticket, Request &r, int phase)
                           r.req.extent[2], out, &d.a3s);
     } else if (p->dim == 2)
         general_args_2d(p, r.req.origin[0], r.req.origin[1], r.req.extent[0], r.req.extent[1], out, r.req.extent[0],
-                        s->tile_h2[p->smoothness - 1], &d.a2);
+                        served_tile_h(s, p->smoothness), &d.a2);
     else
         general_args_3d(p, r.req.origin[0], r.req.origin[1], r.req.origin[2], r.req.extent[0], r.req.extent[1],
                         r.req.extent[2], out, &d.a3);
@@ -1112,8 +1155,9 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
     if (rc) return rc;
     if (p->form != PTG_FORM_PLAIN || p->out_dtype != PTG_F32)
         return fail(PTG_EINVAL, "served tiles use the plain form with FP32 output");
-    if (p->model != PTG_MODEL_GRADIENT) return fail(PTG_EINVAL, "served tiles use the gradient model");
-    if (p->smoothness > 2) return fail(PTG_EINVAL, "served tiles are C1 or C2");
+    if (p->model != PTG_MODEL_GRADIENT && p->model != PTG_MODEL_ZERO_GRADIENT && p->model != PTG_MODEL_HEIGHT_GRADIENT)
+        return fail(PTG_EINVAL, "served tiles use the gradient, zero-gradient or height-and-gradient cells");
+    if (p->smoothness > 3) return fail(PTG_EINVAL, "served tiles are C1, C2 or C3");
     const int nd = p->dim;
     for (int a = 0; a < 3; ++a) {
         if (a < nd) {
@@ -1126,18 +1170,16 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
     const int64_t nx = r->extent[0], ny = r->extent[1], nz = r->extent[2];
     if (nx > (1LL << 40) / ny || nx * ny > (1LL << 40) / nz) return fail(PTG_EINVAL, "request too large");
     *bytes = nx * ny * nz * 4;
-    double freq[kMaxOctaves];
-    float amp[kMaxOctaves];
-    octave_tables(p, freq, amp);
     size_t lds;
     int k = 0;
     Fbm2dStripArgs sa;
     Fbm3dStripArgs sb;
     *kernel = nd == 2 ? PTG_TUNE_GENERAL_2D : PTG_TUNE_GENERAL_3D;
-    if (nd == 3 && dyadic_shift(p, &k) &&
+    const int hw = p->model == PTG_MODEL_HEIGHT_GRADIENT ? 1 : 0;  // node blocks also hold heights
+    if (nd == 3 && p->smoothness <= 2 && dyadic_shift(p, &k) &&
         strip3_args(p, k, r->origin[0], r->origin[1], r->origin[2], nx, ny, nz, nullptr, &sb) == 0 &&
         (size_t)(kStrip3SharedWords + strip3_shared_words(sb.tab_total, sb.keys_col + 4 * sb.n_coarse, sb.nodes_listed) +
-                 kServeWaves * strip3_wave_words(sb.nodes_total, sb.keys_total)) * 4 <= kServeLds) {
+                 kServeWaves * strip3_wave_words(sb.nodes_total, sb.keys_total, hw)) * 4 <= kServeLds) {
         // dyadic ladder the 3D strip code takes (finest period >= 2) whose footprint fits a
         // serving workgroup
         *kernel = PTG_TUNE_STRIP_3D;
@@ -1146,21 +1188,20 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
     } else if (nd == 2 && dyadic_shift(p, &k) &&
         strip_args_2d(p, k, r->origin[0], r->origin[1], nx, ny, nullptr, nx, &sa) == 0 && sa.lo >= 1 &&
         (size_t)(kStripSharedWords + strip_shared_words(sa.nodes_hashed, sa.keys_total) +
-                 kServeWaves * strip_wave_words(sa.nodes_total, sa.keys_total)) * 4 <= kServeLds) {
+                 kServeWaves * strip_wave_words(sa.nodes_total, sa.keys_total, hw)) * 4 <= kServeLds) {
         // dyadic ladder whose strip footprint fits a serving workgroup: the strip code
         *kernel = PTG_TUNE_STRIP_2D;
         *ntiles = sa.strips;
         lds = 0;
     } else if (nd == 2) {
-        const int th = s->tile_h2[p->smoothness - 1];
+        const int th = served_tile_h(s, p->smoothness);
         *ntiles = ((nx + kTile2 - 1) / kTile2) * ((ny + th - 1) / th);
-        const int cx = footprint_cap(freq, p->octaves, kTile2), cy = footprint_cap(freq, p->octaves, th);
-        lds = (size_t)th * 16 + (size_t)cx * cy * 8 + (size_t)(cx + cy) * 4;
+        Fbm2dArgs ga;
+        lds = general_args_2d(p, r->origin[0], r->origin[1], nx, ny, nullptr, nx, th, &ga);
     } else {
         *ntiles = ((nx + kTile3X - 1) / kTile3X) * ((ny + kTile3Y - 1) / kTile3Y) * ((nz + kTile3Z - 1) / kTile3Z);
-        const int cx = footprint_cap(freq, p->octaves, kTile3X), cy = footprint_cap(freq, p->octaves, kTile3Y),
-                  cz = footprint_cap(freq, p->octaves, kTile3Z);
-        lds = (size_t)(kTile3Y + kTile3Z) * 16 + (size_t)cx * cy * cz * 12 + (size_t)(cx + cy * cz) * 4;
+        Fbm3dArgs ga;
+        lds = general_args_3d(p, r->origin[0], r->origin[1], r->origin[2], nx, ny, nz, nullptr, &ga);
     }
     if (lds > kServeLds) return fail(PTG_EINVAL, "the request's lattice is too fine for a serving workgroup");
     if (*ntiles > 0x7FFFFFFFLL) return fail(PTG_EINVAL, "request too large");
@@ -1173,7 +1214,7 @@ static int validate_req(const ptg_server *s, const ptg_tile_req *r, int64_t *byt
     // lattice cache: general 2D requests whose blocks fit the table and, all missing, the
     // budget beside the output (others hash their nodes)
     *lat = 0;
-    if (s->cfg.lattice_cache && *kernel == PTG_TUNE_GENERAL_2D) {
+    if (s->cfg.lattice_cache && *kernel == PTG_TUNE_GENERAL_2D && p->model == PTG_MODEL_GRADIENT) {
         const int n = lat_geometry(p, r->origin[0], r->origin[1], nx, ny, nullptr);
         if (n > 0 && round256(*bytes) + n * kLatBlockBytes <= s->cfg.hbm_budget_bytes) *lat = 1;
     }

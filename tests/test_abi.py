@@ -68,15 +68,24 @@ def test_model_validation():
     assert L.ptg_heights_2d(1, -1, 0, 0, 4, 4, ctypes.c_void_p(1), None) == ptg.PTG_EINVAL
     assert L.ptg_heights_2d(1, 0, 0, 0, 4, 4, None, None) == ptg.PTG_EINVAL
     assert L.ptg_heights_2d(1, 0, 0, 0, 0, 4, None, None) == ptg.PTG_OK  # empty box
+    # the server takes the three polynomial cell models at C1..C3 (zero-gradient: 2D C1);
+    # the comparison paths, orders above 3, other forms and FP16 output are rejected
     with ptg.Server(1 << 20, executor=ptg.PTG_EXEC_HOST) as s:
+        ok = [ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=1 / 64, model="zero_gradient"),
+              ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=1 / 64, model="height_gradient",
+                           smoothness=2),
+              ptg.tile_req(dim=3, extent=(16, 16, 16), octaves=3, base_freq=1 / 16, model="height_gradient"),
+              ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=1 / 64, smoothness=3)]
+        for t in s.submit(ok):
+            s.wait(t, int(5e9))
+            s.release(t)
+        for kw in (dict(model="perlin"), dict(model="simplex"), dict(smoothness=4), dict(form="mfma_f16", out_dtype=1),
+                   dict(out_dtype=1)):
+            with pytest.raises(ptg.PtgError) as e:
+                s.submit([ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=1 / 64, **kw)])
+            assert e.value.code == ptg.PTG_EINVAL, kw
         with pytest.raises(ptg.PtgError) as e:
-            s.submit([ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=1 / 64, model="zero_gradient")])
-        assert e.value.code == ptg.PTG_EINVAL
-        with pytest.raises(ptg.PtgError) as e:
-            s.submit([ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=1 / 64, model="height_gradient")])
-        assert e.value.code == ptg.PTG_EINVAL
-        with pytest.raises(ptg.PtgError) as e:
-            s.submit([ptg.tile_req(dim=2, extent=(64, 64, 1), octaves=3, base_freq=1 / 64, smoothness=3)])
+            s.submit([ptg.tile_req(dim=3, extent=(16, 16, 16), octaves=3, base_freq=1 / 16, model="zero_gradient")])
         assert e.value.code == ptg.PTG_EINVAL
 
 

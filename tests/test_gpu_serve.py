@@ -86,6 +86,61 @@ def test_served_tiles_equal_solo_calls_bit_exact():
         assert st["completed"] == 40 and st["bytes_peak"] <= (1 << 30)
 
 
+def _solo_model(r, kernel):
+    """The stand-alone call with the request's cell model and the kernel family the server
+    used."""
+    nx, ny, nz = r["extent"]
+    kw = dict(smoothness=r["smoothness"], octaves=r["octaves"], base_freq=r["base_freq"], seed=r["seed"],
+              model=r["model"], gradient_weight=r["gradient_weight"])
+    if r["dim"] == 2:
+        out = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+        path = "dyadic" if kernel == ptg.PTG_TUNE_STRIP_2D else "general"
+        ptg.fbm_2d(out, x0=r["origin"][0], y0=r["origin"][1], path=path, **kw)
+    else:
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
+        path = "dyadic" if kernel == ptg.PTG_TUNE_STRIP_3D else "general"
+        ptg.fbm_3d(out, x0=r["origin"][0], y0=r["origin"][1], z0=r["origin"][2], path=path, **kw)
+    torch.cuda.current_stream().synchronize()
+    return out
+
+
+def test_served_cell_models_and_orders_equal_solo_calls_bit_exact():
+    """Zero-gradient (2D C1), height-and-gradient (2D C1..C3, 3D C1 / C2 on the strip code and
+    C3 on general tiles) and septic gradient cells, on dyadic and non-dyadic ladders, in one
+    mix: each served tile equals the stand-alone call of the same kernel family bit for bit,
+    and the family is the one a dense call would take."""
+    rng = np.random.default_rng(1613)
+    cases = [(2, "zero_gradient", 1), (2, "height_gradient", 1), (2, "height_gradient", 2), (2, "height_gradient", 3),
+             (2, "gradient", 3), (3, "height_gradient", 1), (3, "height_gradient", 2), (3, "gradient", 3),
+             (3, "height_gradient", 3)]
+    reqs = []
+    for i, (dim, model, sm) in enumerate(cases * 2):
+        dyadic = i < len(cases)
+        f0 = F0 if dyadic else F0 * 1.37
+        if dim == 2:
+            ext = (int(rng.choice([100, 256, 300])), int(rng.choice([77, 128, 256])), 1)
+            octs = int(rng.integers(4, 10))
+        else:
+            ext = (int(rng.choice([32, 64])), int(rng.choice([16, 40])), int(rng.choice([16, 33])))
+            octs = int(rng.integers(3, 7))
+        org = tuple(int(v) for v in rng.integers(-(1 << 44), 1 << 44, size=dim)) + (0,) * (3 - dim)
+        reqs.append(dict(dim=dim, smoothness=sm, octaves=octs, base_freq=f0, persistence=0.5, lacunarity=2.0,
+                         seed=int(rng.integers(0, 1 << 32)), origin=org, extent=ext, user_tag=i, model=model,
+                         gradient_weight=float(rng.choice([0.01, 0.5]))))
+    with ptg.Server(1 << 30) as srv:
+        tickets = srv.submit([_tile_req(r) for r in reqs])
+        for t, r in zip(tickets, reqs):
+            res = srv.wait(t, int(60e9))
+            assert res.status == ptg.PTG_OK, r
+            got = _fetch(res, r)
+            srv.release(t)
+            shape = (r["extent"][0], r["extent"][1]) if r["dim"] == 2 else r["extent"]
+            kw = {k: r[k] for k in ("smoothness", "octaves", "base_freq", "model", "gradient_weight")}
+            dense_kind = ptg.tune_query(tuple(reversed(shape)), **kw)[0]
+            assert ptg.TUNE_NAMES[res.kernel] == dense_kind, (res.kernel, dense_kind, r)
+            assert torch.equal(got, _solo_model(r, res.kernel)), r
+
+
 def test_wait_any_returns_each_completion_once_in_completion_order():
     """ptg_tiles_wait_any over a mix: every ticket comes back exactly once, completion times
     never decrease, and each output equals the stand-alone call."""
