@@ -10,21 +10,7 @@ __global__ __launch_bounds__(256) void k_fbm2d_strip(const Fbm2dStripArgs a)
 {
     extern __shared__ float4 lds4[];
     __shared__ StripShared sh;
-    const int tid = threadIdx.x, lane = tid & 63, nthreads = blockDim.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wpg = nthreads >> 6;  // waves per workgroup
-    // LDS: [wl_key | wl_node] shared, then per wave [nodes (float2) | keys (u32)]
-    uint32_t *wl_key = reinterpret_cast<uint32_t *>(lds4);
-    uint32_t *wl_node = wl_key + a.keys_total;
-    const int shared_words = strip_shared_words(a.nodes_hashed, a.keys_total);
-    const int wave_words = strip_wave_words(a.nodes_total, a.keys_total, MD == 2);
-    float2 *nodes = reinterpret_cast<float2 *>(reinterpret_cast<uint32_t *>(lds4) + shared_words + wave * wave_words);
-
-    strip_prologue(a, sh, wl_key, wl_node, tid, nthreads);
-    __syncthreads();
-    StripWave<M, OutT, LO, MD, PREC> w(a, sh, nodes, lane);
-    const int64_t nwaves = (int64_t)gridDim.x * wpg;
-    for (int64_t st = (int64_t)blockIdx.x * wpg + wave; st < a.strips; st += nwaves) w.run(a, sh, wl_key, wl_node, st);
+    strip_field<M, OutT, LO, MD, PREC, 0>(a, reinterpret_cast<uint32_t *>(lds4), sh);
 }
 
 template <int M, typename OutT, int LO, int MD, int PREC = 0>

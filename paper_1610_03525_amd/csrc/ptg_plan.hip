@@ -175,31 +175,49 @@ int strip_args_2d(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx
     return 0;
 }
 
+// The strip kernel's arguments and launch shape for a dyadic field; returns 1 when a strip's
+// node footprint does not fit the workgroup's LDS.
+static int strip_plan(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out,
+                      int64_t pitch, Fbm2dStripArgs *a, int *waves_out, size_t *lds_out)
+{
+    if (strip_args_2d(p, k, x0, y0, nx, ny, out, pitch, a)) return 1;
+    const size_t shared_words = (size_t)strip_shared_words(a->nodes_hashed, a->keys_total);
+    const size_t wave_words =
+        (size_t)strip_wave_words(a->nodes_total, a->keys_total, p->model == PTG_MODEL_HEIGHT_GRADIENT);
+    // waves per workgroup: the tuned count (default 4), at most what the private node
+    // blocks allow in LDS
+    int waves = tune_pick(TuneKey{PTG_TUNE_STRIP_2D, p->smoothness + 2 * p->model, p->out_dtype == PTG_F16,
+                                  size_class(nx * ny), a->lo},
+                          kStripWavesPerWg);
+    while (waves > 1 && (shared_words + waves * wave_words) * 4 > kDyMaxLds) --waves;
+    const size_t lds = (shared_words + waves * wave_words) * 4;
+    if (lds > kDyMaxLds) return 1;
+    *waves_out = waves;
+    *lds_out = lds;
+    return 0;
+}
+
+// A persistent grid of exactly the resident workgroups (a partial second round would leave
+// most of the chip idle at the end).
+static int strip_grid(const Fbm2dStripArgs &a, int waves, int per_cu)
+{
+    const int64_t wgs = (a.strips + waves - 1) / waves;
+    return (int)std::min<int64_t>(wgs, (int64_t)device_cus() * per_cu);
+}
+
 // Plain FP32 dyadic field through the strip kernel; returns 1 when a strip's node
 // footprint does not fit the workgroup's LDS (the caller falls back).
 static int fbm2d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out,
                        int64_t pitch, hipStream_t s)
 {
     Fbm2dStripArgs a;
-    if (strip_args_2d(p, k, x0, y0, nx, ny, out, pitch, &a)) return 1;
-    const size_t shared_words = (size_t)strip_shared_words(a.nodes_hashed, a.keys_total);
-    const size_t wave_words =
-        (size_t)strip_wave_words(a.nodes_total, a.keys_total, p->model == PTG_MODEL_HEIGHT_GRADIENT);
-    // waves per workgroup: the tuned count (default 4), at most what the private node
-    // blocks allow in LDS
-    int waves = tune_pick(TuneKey{PTG_TUNE_STRIP_2D, p->smoothness + 2 * p->model, p->out_dtype == PTG_F16,
-                                  size_class(nx * ny), a.lo},
-                          kStripWavesPerWg);
-    while (waves > 1 && (shared_words + waves * wave_words) * 4 > kDyMaxLds) --waves;
-    const size_t lds = (shared_words + waves * wave_words) * 4;
-    if (lds > kDyMaxLds) return 1;
+    int waves = 0;
+    size_t lds = 0;
+    if (strip_plan(p, k, x0, y0, nx, ny, out, pitch, &a, &waves, &lds)) return 1;
     if (tune_dry()) return PTG_OK;
-    // a persistent grid of exactly the resident workgroups (a partial second round would
-    // leave most of the chip idle at the end)
-    const int64_t per_cu = strip_wgs_per_cu(p->smoothness, p->model, p->out_dtype == PTG_F16, a.lo, waves, lds);
-    const int64_t wgs = (a.strips + waves - 1) / waves;
-    const int grid = (int)std::min<int64_t>(wgs, (int64_t)device_cus() * per_cu);
-    hipError_t e = launch_fbm2d_strip(a, p->smoothness, p->model, p->out_dtype == PTG_F16, grid, waves, lds, s);
+    const bool f16 = p->out_dtype == PTG_F16;
+    const int grid = strip_grid(a, waves, strip_wgs_per_cu(p->smoothness, p->model, f16, a.lo, waves, lds));
+    hipError_t e = launch_fbm2d_strip(a, p->smoothness, p->model, f16, grid, waves, lds, s);
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d strip launch");
 }
 
@@ -304,11 +322,33 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d launch");
 }
 
-// The field and its analytic gradient: the general kernel with 64-row tiles (any model,
-// any ladder) and a second row table for the row-basis derivatives.
+// The field and its analytic gradient.  Dyadic ladders (unless the general path is asked
+// for) take the strip kernel: the field (the same launch as ptg_fbm_2d's), then dH/dX and
+// dH/dY, one launch each.  Otherwise, or when a strip's footprint does not fit LDS, the
+// general kernel with 64-row tiles (any model, any ladder) and a second row table for the
+// row-basis derivatives writes all three in one pass.
 int fbm2d_grad(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out, void *out_dx,
                void *out_dy, int64_t pitch, hipStream_t s)
 {
+    int k = 0;
+    if (dyadic_shift(p, &k) && p->path != PTG_PATH_GENERAL) {
+        Fbm2dStripArgs a;
+        int waves = 0;
+        size_t lds = 0;
+        if (!strip_plan(p, k, x0, y0, nx, ny, out, pitch, &a, &waves, &lds)) {
+            const bool f16 = p->out_dtype == PTG_F16;
+            const int sm = p->smoothness, md = p->model;
+            hipError_t e =
+                launch_fbm2d_strip(a, sm, md, f16, strip_grid(a, waves, strip_wgs_per_cu(sm, md, f16, a.lo, waves, lds)),
+                                   waves, lds, s);
+            for (int axis = 0; axis < 2 && e == hipSuccess; ++axis) {
+                a.out = axis == 0 ? out_dx : out_dy;
+                const int grid = strip_grid(a, waves, strip_grad_wgs_per_cu(axis, sm, md, f16, a.lo, waves, lds));
+                e = launch_fbm2d_strip_grad(a, axis, sm, md, f16, grid, waves, lds, s);
+            }
+            return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d strip gradient launch");
+        }
+    }
     Fbm2dArgs a{};
     const size_t lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, kTile2, &a) + (size_t)kTile2 * 16;
     a.out_dx = out_dx;

@@ -76,17 +76,28 @@ struct XA {
     float q0, q1, e0, e1, v0, v1;
 };
 
-template <int M, int MD = 0>
+// DX = true: the weights' derivatives d/dt (a node row's E and Q are linear in the lane's
+// weights, so the same row machinery then sums d/dt of every cell; the caller folds 1/P into
+// amp for d/dX in samples).
+template <int M, int MD = 0, bool DX = false>
 __device__ __forceinline__ XA xweights(float t, float amp, float gw = 1.0f)
 {
-    const XB b = xbases<M>(t);
+    XB b;
+    float tt = t, one = 1.0f;  // t and 1 - t, or their derivatives 1 and 0
+    if (DX) {
+        BasisD<M>::eval(t, b.s, b.b10, b.b11);
+        tt = 1.0f;
+        one = 0.0f;
+    } else {
+        b = xbases<M>(t);
+    }
     if (MD == 1)  // zero-gradient model: the nodes hold heights (E = h0 + S D, Q = (S - t) D)
-        return XA{amp * (t - b.s), amp * (b.s - t), amp * (1.0f - b.s), amp * b.s, 0.0f, 0.0f};
+        return XA{amp * (tt - b.s), amp * (b.s - tt), amp * (one - b.s), amp * b.s, 0.0f, 0.0f};
     if (MD == 2) {
         const float aw = amp * gw;
-        return XA{aw * (1.0f - b.s), aw * b.s, aw * b.b10, aw * b.b11, amp * (1.0f - b.s), amp * b.s};
+        return XA{aw * (one - b.s), aw * b.s, aw * b.b10, aw * b.b11, amp * (one - b.s), amp * b.s};
     }
-    return XA{amp * (1.0f - b.s), amp * b.s, amp * b.b10, amp * b.b11, 0.0f, 0.0f};
+    return XA{amp * (one - b.s), amp * b.s, amp * b.b10, amp * b.b11, 0.0f, 0.0f};
 }
 
 // Row bases at the fraction (j + 1/2) / P: constant once the row loop is unrolled.
@@ -106,6 +117,24 @@ __host__ __device__ constexpr XB row_bases(int j, int P)
     }
     return XB{t3 * (10.0f + t * (-15.0f + 6.0f * t)), t + t3 * (-6.0f + t * (8.0f - 3.0f * t)),
               t3 * (-4.0f + t * (7.0f - 3.0f * t))};
+}
+
+// Derivatives d/dt of the row bases at the fraction (j + 1/2) / P, times 1/P (d/dY in
+// samples).
+template <int M>
+__host__ __device__ constexpr XB row_dbases(int j, int P)
+{
+    const float t = (float)(2 * j + 1) / (float)(2 * P), ip = 1.0f / (float)P;
+    const float t2 = t * t;
+    if (M == 1) return XB{6.0f * t * (1.0f - t) * ip, (1.0f + t * (-4.0f + 3.0f * t)) * ip, t * (-2.0f + 3.0f * t) * ip};
+    if (M == 3) {
+        const float t3 = t2 * t;
+        return XB{t3 * (140.0f + t * (-420.0f + t * (420.0f - 140.0f * t))) * ip,
+                  (1.0f + t3 * (-80.0f + t * (225.0f + t * (-216.0f + 70.0f * t)))) * ip,
+                  t3 * (-60.0f + t * (195.0f + t * (-204.0f + 70.0f * t))) * ip};
+    }
+    return XB{t2 * (30.0f + t * (-60.0f + 30.0f * t)) * ip, (1.0f + t2 * (-18.0f + t * (32.0f - 15.0f * t))) * ip,
+              t2 * (-12.0f + t * (28.0f - 15.0f * t)) * ip};
 }
 
 // Septic cells: powers of u = t - 1/2 of S and b10 (exact binary fractions; b11(u) = -b10(-u),
@@ -363,10 +392,16 @@ struct SegRows {
 // direct octaves, centred on the segment (row k at w = (2 k - R + 1) / 128).  Rows are taken
 // in pairs symmetric about the centre, w and -w, from the even and odd parts of Cs; the
 // direct octaves' E0 terms go into each row's constant term, the rest is 3 FMA per octave.
-template <int M, typename OutT, int R, bool D8, bool D4, bool D2, bool D1, bool FULL, int MD = 0>
+// G = 2: the rows' d/dY instead (w = (Y - centre) / 64): the derivative of Cs, and the direct
+// octaves' row-basis derivatives (their E0 terms are constant along y).
+template <int M, typename OutT, int R, bool D8, bool D4, bool D2, bool D1, bool FULL, int MD = 0, int G = 0>
 __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[2 * M + 2], int r0, NR (&carry)[4],
                                              OutT *rp, int lane, int rlo, int rhi, bool lane_ok)
 {
+    constexpr int D = 2 * M + 1, DEG = G == 2 ? D - 1 : D;  // degree of the evaluated polynomial
+    float Pw[D + 1];
+#pragma unroll
+    for (int b = 0; b <= D; ++b) Pw[b] = G == 2 ? (b < D ? (float)(b + 1) * (1.0f / 64.0f) * Cs[b + 1] : 0.0f) : Cs[b];
     SegRows<8, R, MD> s8;
     SegRows<4, R, MD> s4;
     SegRows<2, R, MD> s2;
@@ -388,33 +423,38 @@ __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[
         const int rb = R / 2 + p;
         const float w = (float)(2 * rb - R + 1) * (1.0f / 128.0f);
         const float w2 = w * w;
-        float odd, even2 = 0.0f;
-        if (M == 1) {
-            odd = __builtin_fmaf(Cs[3], w2, Cs[1]);
-        } else {  // odd part in w^2 (C1, C3, ...) and the even part beyond C0 (C2, C4, ...)
-            constexpr int D = 2 * M + 1;
-            odd = Cs[D];
+        // odd part in w^2 (P1, P3, ...) and the even part beyond P0 (P2, P4, ...)
+        constexpr int TOPO = (DEG & 1) ? DEG : DEG - 1, TOPE = (DEG & 1) ? DEG - 1 : DEG;
+        float odd = Pw[TOPO];
 #pragma unroll
-            for (int e = D - 2; e >= 1; e -= 2) odd = __builtin_fmaf(odd, w2, Cs[e]);
-            even2 = Cs[D - 1];
+        for (int e = TOPO - 2; e >= 1; e -= 2) odd = __builtin_fmaf(odd, w2, Pw[e]);
+        float even2 = Pw[TOPE];
 #pragma unroll
-            for (int e = D - 3; e >= 2; e -= 2) even2 = __builtin_fmaf(even2, w2, Cs[e]);
-        }
+        for (int e = TOPE - 2; e >= 2; e -= 2) even2 = __builtin_fmaf(even2, w2, Pw[e]);
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const int k = side ? rb : R / 2 - 1 - p;  // row in the segment
             const int row = r0 + k;                   // row in the strip
-            float c0 = Cs[0];
-            if (D8) c0 += s8.n[k / 8].E;
-            if (D4) c0 += s4.n[k / 4].E;
-            if (D2) c0 += s2.n[k / 2].E;
-            if (D1) c0 += s1.n[k].E;
-            float val = __builtin_fmaf(M == 1 ? Cs[2] : even2, w2, c0);
+            float c0 = Pw[0];
+            if (G != 2) {
+                if (D8) c0 += s8.n[k / 8].E;
+                if (D4) c0 += s4.n[k / 4].E;
+                if (D2) c0 += s2.n[k / 2].E;
+                if (D1) c0 += s1.n[k].E;
+            }
+            float val = __builtin_fmaf(even2, w2, c0);
             val = __builtin_fmaf(side ? w : -w, odd, val);
-            if (D8) val = add_direct<MD>(val, s8.n[k / 8], s8.n[k / 8 + 1], row_bases<M>(row & 7, 8));
-            if (D4) val = add_direct<MD>(val, s4.n[k / 4], s4.n[k / 4 + 1], row_bases<M>(row & 3, 4));
-            if (D2) val = add_direct<MD>(val, s2.n[k / 2], s2.n[k / 2 + 1], row_bases<M>(row & 1, 2));
-            if (D1) val = add_direct<MD>(val, s1.n[k], s1.n[k + 1], row_bases<M>(0, 1));
+            if (G == 2) {
+                if (D8) val = add_direct<MD>(val, s8.n[k / 8], s8.n[k / 8 + 1], row_dbases<M>(row & 7, 8));
+                if (D4) val = add_direct<MD>(val, s4.n[k / 4], s4.n[k / 4 + 1], row_dbases<M>(row & 3, 4));
+                if (D2) val = add_direct<MD>(val, s2.n[k / 2], s2.n[k / 2 + 1], row_dbases<M>(row & 1, 2));
+                if (D1) val = add_direct<MD>(val, s1.n[k], s1.n[k + 1], row_dbases<M>(0, 1));
+            } else {
+                if (D8) val = add_direct<MD>(val, s8.n[k / 8], s8.n[k / 8 + 1], row_bases<M>(row & 7, 8));
+                if (D4) val = add_direct<MD>(val, s4.n[k / 4], s4.n[k / 4 + 1], row_bases<M>(row & 3, 4));
+                if (D2) val = add_direct<MD>(val, s2.n[k / 2], s2.n[k / 2 + 1], row_bases<M>(row & 1, 2));
+                if (D1) val = add_direct<MD>(val, s1.n[k], s1.n[k + 1], row_bases<M>(0, 1));
+            }
             OutT *const rrow = side ? pb : pa;
             if (FULL || (row >= rlo && row < rhi && lane_ok)) rrow[lane] = st_out<OutT>(val);
         }
@@ -434,7 +474,7 @@ __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[
 // cost less than evaluating the octave on its own at every row; for quintic cells (15 FMA
 // per re-centring) period 8 stays a direct octave.  No piece is evaluated away from its own
 // cell.  FULL = every sample of the strip is stored.
-template <int M, typename OutT, int LO, bool FULL, int MD = 0>
+template <int M, typename OutT, int LO, bool FULL, int MD = 0, int G = 0>
 __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 * M + 2], OutT *rp, int lane, int rlo,
                                            int rhi, bool lane_ok)
 {
@@ -488,11 +528,12 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
                     const NR lo = carry[0], hi = node_row<9, MD>(x.f8, 2 * q + e + 1);
                     add_piece<M, 8, MD>(Ce, lo, hi);
                     carry[0] = hi;
-                    segment_rows<M, OutT, 8, false, H4, H2, H1, FULL, MD>(x, Ce, 16 * q + 8 * e, carry, rp, lane, rlo,
-                                                                           rhi, lane_ok);
+                    segment_rows<M, OutT, 8, false, H4, H2, H1, FULL, MD, G>(x, Ce, 16 * q + 8 * e, carry, rp, lane,
+                                                                              rlo, rhi, lane_ok);
                 }
             } else {
-                segment_rows<M, OutT, 16, H8, H4, H2, H1, FULL, MD>(x, Cq, 16 * q, carry, rp, lane, rlo, rhi, lane_ok);
+                segment_rows<M, OutT, 16, H8, H4, H2, H1, FULL, MD, G>(x, Cq, 16 * q, carry, rp, lane, rlo, rhi,
+                                                                        lane_ok);
             }
         }
     }
@@ -544,9 +585,12 @@ __device__ __forceinline__ void strip_prologue(const Fbm2dStripArgs &a, StripSha
 }
 
 // One wave's strips of a field: the lane's x-weights of the fixed-period octaves (formed
-// once) and the strip column whose keys its LDS block holds.
-template <int M, typename OutT, int LO, int MD = 0, int PREC = 0>
+// once) and the strip column whose keys its LDS block holds.  G selects the output: 0 the
+// field H, 1 dH/dX (the x-weights' derivatives), 2 dH/dY (the rows' derivatives), both in
+// world units per sample.
+template <int M, typename OutT, int LO, int MD = 0, int PREC = 0, int G = 0>
 struct StripWave {
+    static_assert(PREC == 0 || G == 0, "the precision form writes the field only");
     static constexpr int D1 = 2 * M + 2;
     static constexpr bool H32 = LO <= 5, H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
     float2 *nodes;
@@ -567,7 +611,9 @@ struct StripWave {
             const int s = sh.shift[o];
             f.col = nodes + sh.noff[o] + (lane >> s) * sh.nbr[o];
             f.hcol = heights + sh.noff[o] + (lane >> s) * sh.nbr[o];
-            f.xa = xweights<M, MD>((float)(2 * (lane & ((1 << s) - 1)) + 1) * sh.inv2p[o], sh.amp[o], sh.gw);
+            const float inv2p = sh.inv2p[o];
+            f.xa = xweights<M, MD, G == 1>((float)(2 * (lane & ((1 << s) - 1)) + 1) * inv2p,
+                                           G == 1 ? sh.amp[o] * (2.0f * inv2p) : sh.amp[o], sh.gw);
         }
         return f;
     }
@@ -639,8 +685,8 @@ struct StripWave {
             const int s = a.shift[o];
             const uint32_t mask = (1u << s) - 1u;
             const float inv2p = a.inv2p[o];
-            const XA xa = xweights<M, MD>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p,
-                                          a.amp[o], a.gw);
+            const XA xa = xweights<M, MD, G == 1>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p,
+                                                  G == 1 ? a.amp[o] * (2.0f * inv2p) : a.amp[o], a.gw);
             const CF c = column_form<MD>(nodes + a.noff[o], 2, xa, heights + a.noff[o]);
             const float invp = 2.0f * inv2p;
             const float tau = (float)(((uint32_t)Y0 & mask) + (uint32_t)(kStripH / 2)) * invp - 0.5f;
@@ -661,12 +707,34 @@ struct StripWave {
             else
                 strip_rows_mx<OutT, LO, PREC, false>(rc0, C, row0, lane, rlo, rhi, lane >= clo && lane < chi, mc);
         } else if (rlo == 0 && rhi == kStripH && clo == 0 && chi == kStripW) {
-            strip_rows<M, OutT, LO, true, MD>(rc0, C, row0, lane, 0, kStripH, false);
+            strip_rows<M, OutT, LO, true, MD, G>(rc0, C, row0, lane, 0, kStripH, false);
         } else {
-            strip_rows<M, OutT, LO, false, MD>(rc0, C, row0, lane, rlo, rhi, lane >= clo && lane < chi);
+            strip_rows<M, OutT, LO, false, MD, G>(rc0, C, row0, lane, rlo, rhi, lane >= clo && lane < chi);
         }
         __builtin_amdgcn_wave_barrier();  // the next strip rewrites this wave's keys and nodes
     }
 };
+
+// A dense field's kernel body (one wave per 64 x 64 strip, a grid-stride walk over the
+// field's strips): lds is the dynamic LDS block, sh the workgroup's per-octave constants.
+template <int M, typename OutT, int LO, int MD, int PREC, int G>
+__device__ __forceinline__ void strip_field(const Fbm2dStripArgs &a, uint32_t *lds, StripShared &sh)
+{
+    const int tid = threadIdx.x, lane = tid & 63, nthreads = blockDim.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wpg = nthreads >> 6;  // waves per workgroup
+    // LDS: [wl_key | wl_node] shared, then per wave [nodes (float2) | keys (u32)]
+    uint32_t *wl_key = lds;
+    uint32_t *wl_node = wl_key + a.keys_total;
+    const int shared_words = strip_shared_words(a.nodes_hashed, a.keys_total);
+    const int wave_words = strip_wave_words(a.nodes_total, a.keys_total, MD == 2);
+    float2 *nodes = reinterpret_cast<float2 *>(lds + shared_words + wave * wave_words);
+
+    strip_prologue(a, sh, wl_key, wl_node, tid, nthreads);
+    __syncthreads();
+    StripWave<M, OutT, LO, MD, PREC, G> w(a, sh, nodes, lane);
+    const int64_t nwaves = (int64_t)gridDim.x * wpg;
+    for (int64_t st = (int64_t)blockIdx.x * wpg + wave; st < a.strips; st += nwaves) w.run(a, sh, wl_key, wl_node, st);
+}
 
 }  // namespace ptg
