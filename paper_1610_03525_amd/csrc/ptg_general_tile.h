@@ -44,6 +44,13 @@ __device__ __forceinline__ __half to_out<__half>(float v)
 // row loop (2D tile of 64 rows: 174 VGPRs instead of 54, two waves per SIMD instead of
 // eight).  The statement emits no instruction.
 __device__ __forceinline__ void keep_here(float &v) { asm volatile("" : "+v"(v)); }
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f32x4 load_here4(const float4 *p)
+{
+    f32x4 v = *reinterpret_cast<const f32x4 *>(p);
+    asm volatile("" : "+v"(v));
+    return v;
+}
 
 // Device-resident lattice cache (serving): the unit gradients of one octave's nodes in
 // blocks of kLatBlk x kLatBlk nodes, SoA per block (x components at [(iy & 31) * 32 +
@@ -64,9 +71,15 @@ struct LatCache {
 };
 
 // ---------------------------------------------------------------------------------
-// 2D: tile 64 x TH samples (TH = 16, 32 or 64 rows), 4 waves x TH/4 rows.
-// LDS: row table float4[TH] | gx[capx*capy] | gy[capx*capy] | kx[capx] | ky[capy]
+// 2D: tile 64 x TH samples (TH = 16, 32, 64 or 128 rows), 4 waves x TH/4 rows.
+// LDS: row table float4[TH] | (GRAD) row-derivative table float4[TH] | every octave's
+// footprint TileFoot[octaves] | gx[capx*capy] | gy[capx*capy] | (MD = 2) gh[capx*capy] |
+// every octave's keys kx[octaves*capx] | ky[octaves*capy]
 // ---------------------------------------------------------------------------------
+// Once per tile: the octaves' footprints (one lane per octave, FP64) and the keys of their
+// node columns and rows.  Per octave, between two barriers: the row table and the node
+// block; then each wave's rows, where a ballot over the row table marks the rows that
+// enter a new cell (a uniform bit test per row, no per-row lane-to-scalar move).
 // MD = 1: the zero-gradient model (Sec. 3.3; M = 1): gx holds the node heights, and a
 // cell at the lane's column x is E0 + dE S(y) + dQ (y - S(y)) with, per node row j,
 // E_j = h0j + S(x) D_j, Q_j = (S(x) - x) D_j, D_j = h1j - h0j; y - S(y) = b10(y) + b11(y),
@@ -82,20 +95,37 @@ struct LatCache {
 // cell's derivatives in its local coordinates times the octave frequency; the x-derivative
 // is the same row form with the x-bases differentiated, the y-derivative the row form with
 // the row bases differentiated (a second row table in LDS).
+struct TileFoot {  // one octave's lattice footprint over a tile: first node and node counts
+    int64_t cxf, cyf;
+    int32_t nnx, nny, pad0, pad1;
+};
+static_assert(sizeof(TileFoot) == kTileFootBytes, "footprint table entry size");
+
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform_i64(int64_t v)
+{
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 template <int M, typename OutT, int TH, int MD = 0, bool GRAD = false>
 __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t bid, float4 *lds4,
                                                    const LatCache *lat = nullptr)
 {
     constexpr int T = kTile2;
     constexpr int RPT = TH / 4;
+    static_assert(RPT <= 64, "a wave's rows are one ballot");
     float4 *rowt = lds4;
     float4 *rowd = lds4 + TH;  // GRAD only: row-basis derivatives
+    TileFoot *foot = reinterpret_cast<TileFoot *>(lds4 + (GRAD ? 2 * TH : TH));
     const int cap = a.capx * a.capy;
-    float *gx = reinterpret_cast<float *>(lds4 + (GRAD ? 2 * TH : TH));
+    float *gx = reinterpret_cast<float *>(foot + a.octaves);
     float *gy = gx + cap;
     float *gh = gy + cap;  // MD = 2 only
-    uint32_t *kx = reinterpret_cast<uint32_t *>(MD == 2 ? gh + cap : gy + cap);
-    uint32_t *ky = kx + a.capx;
+    uint32_t *kx_all = reinterpret_cast<uint32_t *>(MD == 2 ? gh + cap : gy + cap);
+    uint32_t *ky_all = kx_all + a.octaves * a.capx;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t tx0 = (bid % a.tiles_x) * T, ty0 = (bid / a.tiles_x) * TH;
@@ -106,6 +136,30 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
     const int64_t Xf = a.x0 + tx0, Xl = a.x0 + tx0 + w - 1;
     const int64_t Yf = a.y0 + ty0, Yl = a.y0 + ty0 + h - 1;
 
+    // ---- once per tile: every octave's footprint, then its column and row keys ----------
+    if (tid < a.octaves) {
+        const double f = a.freq[tid];
+        TileFoot ft;
+        ft.cxf = cell_of(Xf, f);
+        ft.cyf = cell_of(Yf, f);
+        ft.nnx = (int)(cell_of(Xl, f) - ft.cxf) + 2;
+        ft.nny = (int)(cell_of(Yl, f) - ft.cyf) + 2;
+        ft.pad0 = ft.pad1 = 0;
+        foot[tid] = ft;
+    }
+    __syncthreads();
+    if (!lat) {
+        for (int o = 0; o < a.octaves; ++o) {
+            const TileFoot ft = foot[o];
+            const int nnx = uniform_i32(ft.nnx), nny = uniform_i32(ft.nny);
+            const int64_t cxf = uniform_i64(ft.cxf), cyf = uniform_i64(ft.cyf);
+            uint32_t *kx = kx_all + o * a.capx, *ky = ky_all + o * a.capy;
+            const uint32_t pre = key_prefix(a.seed, o);
+            for (int i = tid; i < nnx; i += 256) kx[i] = key_xline(cxf + i);
+            for (int j = tid; j < nny; j += 256) ky[j] = absorb_index(pre, cyf + j);
+        }
+    }
+
     float acc[RPT], accx[GRAD ? RPT : 1], accy[GRAD ? RPT : 1];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) acc[r] = 0.0f;
@@ -115,16 +169,12 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
     for (int o = 0; o < a.octaves; ++o) {
         const double f = a.freq[o];
         const float amp = a.amp[o];
-        const int64_t cxf = cell_of(Xf, f), cyf = cell_of(Yf, f);
-        const int nnx = (int)(cell_of(Xl, f) - cxf) + 2;
-        const int nny = (int)(cell_of(Yl, f) - cyf) + 2;
+        const TileFoot ft = foot[o];
+        const int64_t cxf = uniform_i64(ft.cxf), cyf = uniform_i64(ft.cyf);
+        const int nnx = uniform_i32(ft.nnx), nny = uniform_i32(ft.nny);
+        const uint32_t *kx = kx_all + o * a.capx, *ky = ky_all + o * a.capy;
 
-        __syncthreads();  // the previous octave is done with LDS
-        if (!lat) {  // keys of the footprint's node columns and rows
-            const uint32_t pre = key_prefix(a.seed, o);
-            for (int i = tid; i < nnx; i += 256) kx[i] = key_xline(cxf + i);
-            for (int j = tid; j < nny; j += 256) ky[j] = absorb_index(pre, cyf + j);
-        }
+        __syncthreads();  // the previous octave is done with the row table and node block
         if (tid < TH) {
             const int r = min(tid, h - 1);
             const Coord c = coord_step(Yf + r, f);
@@ -141,7 +191,6 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
                 rowd[tid] = make_float4(ds, db10, db11, 0.0f);
             }
         }
-        __syncthreads();
         if (lat) {  // gradients from the cached lattice blocks
             // node (cxf + i, cyf + j) relative to the origin of the octave's first block
             const int ox = (int)(cxf - (lat->bx0[o] << kLatBlkLog)), oy = (int)(cyf - (lat->by0[o] << kLatBlkLog));
@@ -172,27 +221,27 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
                     }
                 }
             }
-        } else if (MD == 1) {
-            for (int q = tid; q < nnx * nny; q += 256) {
-                const int j = q / nnx, i = q - j * nnx;
-                gx[q] = height2(key_combine(ky[j], kx[i])) * amp;
-            }
-        } else if (MD == 2) {
-            const float aw = amp * a.gw;
-            for (int q = tid; q < nnx * nny; q += 256) {
-                const int j = q / nnx, i = q - j * nnx;
-                const uint32_t key = key_combine(ky[j], kx[i]);
-                const float2 g = grad2(key);
-                gx[q] = g.x * aw;
-                gy[q] = g.y * aw;
-                gh[q] = height2_second(key) * amp;
-            }
         } else {
-            for (int q = tid; q < nnx * nny; q += 256) {
-                const int j = q / nnx, i = q - j * nnx;
-                const float2 g = grad2(key_combine(ky[j], kx[i]));
-                gx[q] = g.x * amp;
-                gy[q] = g.y * amp;
+            // node q = j nnx + i; a thread's nodes step by 256 = dj rows and di columns
+            const int nn = nnx * nny, dj = 256 / nnx, di = 256 - dj * nnx;
+            int j = tid / nnx, i = tid - j * nnx;
+            const float aw = MD == 2 ? amp * a.gw : amp;
+            for (int q = tid; q < nn; q += 256) {
+                const uint32_t key = key_combine(ky[j], kx[i]);
+                if (MD == 1) {
+                    gx[q] = height2(key) * amp;
+                } else {
+                    const float2 g = grad2(key);
+                    gx[q] = g.x * aw;
+                    gy[q] = g.y * aw;
+                    if (MD == 2) gh[q] = height2_second(key) * amp;
+                }
+                i += di;
+                j += dj;
+                if (i >= nnx) {
+                    i -= nnx;
+                    ++j;
+                }
             }
         }
         const Coord cc = coord_step(X, f);
@@ -203,66 +252,88 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
         const float fo = (float)f;  // d/dX = f d/dt
         __syncthreads();
 
-        int prev = -1;
+        // rows of this wave that enter a new cell (the first always does)
+        uint64_t fresh;
+        {
+            const int rr = wave * RPT + min(lane, RPT - 1);
+            const int cy = __float_as_int(rowt[rr].x);
+            const int cp = (lane > 0 && lane < RPT) ? __float_as_int(rowt[rr - 1].x) : -1;
+            fresh = __ballot(lane < RPT && cy != cp);
+        }
+
+        // A node row collapsed along x at the lane's column (adjacent cells share one): value
+        // term E and y-slope term Q (zero-gradient model: Q = (S(x) - x) D, the cell's slope
+        // being the difference of its rows'; Perlin: the x-lerps A, B of the x- and
+        // y-gradient ramps), and their x-derivatives (GRAD).
+        struct NodeRow {
+            float E, Q, Ex, Qx;
+        };
+        auto node_row = [&](int q) {
+            NodeRow n{0.0f, 0.0f, 0.0f, 0.0f};
+            if (MD == 1) {
+                const float h0 = gx[q], d = gx[q + 1] - h0;
+                n.E = h0 + sx * d;
+                n.Q = (sx - cc.t) * d;
+                if (GRAD) {
+                    n.Ex = dsx * d;
+                    n.Qx = (dsx - 1.0f) * d;
+                }
+            } else if (MD == 3) {
+                const float fx0 = gx[q], fx1 = gx[q + 1], fy0 = gy[q], fy1 = gy[q + 1];
+                n.E = fx0 * cc.t + sx * (fx1 * (cc.t - 1.0f) - fx0 * cc.t);
+                n.Q = fy0 + sx * (fy1 - fy0);
+            } else {
+                const float fx0 = gx[q], fx1 = gx[q + 1], fy0 = gy[q], fy1 = gy[q + 1];
+                n.E = fx0 * b10x + fx1 * b11x;
+                if (MD == 2) n.E += gh[q] + sx * (gh[q + 1] - gh[q]);  // the heights' value term
+                n.Q = fy0 + sx * (fy1 - fy0);
+                if (GRAD) {
+                    n.Ex = fx0 * db10x + fx1 * db11x;
+                    if (MD == 2) n.Ex += dsx * (gh[q + 1] - gh[q]);
+                    n.Qx = dsx * (fy1 - fy0);
+                }
+            }
+            return n;
+        };
         float E0 = 0.0f, dE = 0.0f, Q0 = 0.0f, Q1 = 0.0f;
         float E0x = 0.0f, dEx = 0.0f, Q0x = 0.0f, Q1x = 0.0f;  // the x-derivative's row form (GRAD)
+        NodeRow lo{}, hi{};
+        int prev = -2;  // the current cell's row (uniform)
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            const float4 re = rowt[wave * RPT + r];
-            const int lcy = __builtin_amdgcn_readfirstlane(__float_as_int(re.x));
-            if (lcy != prev && MD == 1) {
-                prev = lcy;
+            // one 16-byte read per row (the cell index is used on fresh rows only)
+            const f32x4 re = load_here4(rowt + wave * RPT + r);
+            if ((fresh >> r) & 1u) {
+                const int lcy = __builtin_amdgcn_readfirstlane(__float_as_int(re.x));
                 const int q = lcy * nnx + lcx;
-                const float h00 = gx[q], h10 = gx[q + 1], h01 = gx[q + nnx], h11 = gx[q + nnx + 1];
-                const float d0 = h10 - h00, d1 = h11 - h01;
-                E0 = h00 + sx * d0;
-                dE = (h01 + sx * d1) - E0;
-                Q0 = (sx - cc.t) * (d1 - d0);
-                Q1 = Q0;
-                if (GRAD) {
-                    E0x = dsx * d0;
-                    dEx = dsx * (d1 - d0);
-                    Q0x = (dsx - 1.0f) * (d1 - d0);
-                    Q1x = Q0x;
-                }
-            } else if (lcy != prev && MD == 3) {  // Perlin (see above)
+                lo = lcy == prev + 1 ? hi : node_row(q);  // the next cell up shares its lower row
+                hi = node_row(q + nnx);
                 prev = lcy;
-                const int q = lcy * nnx + lcx;
-                const float fx00 = gx[q], fx10 = gx[q + 1], fx01 = gx[q + nnx], fx11 = gx[q + nnx + 1];
-                const float fy00 = gy[q], fy10 = gy[q + 1], fy01 = gy[q + nnx], fy11 = gy[q + nnx + 1];
-                const float tx = cc.t, tx1 = cc.t - 1.0f;
-                const float a0 = fx00 * tx + sx * (fx10 * tx1 - fx00 * tx), a1 = fy00 + sx * (fy10 - fy00);
-                const float b0 = fx01 * tx + sx * (fx11 * tx1 - fx01 * tx), b1 = fy01 + sx * (fy11 - fy01);
-                E0 = a0;
-                dE = b0 - b1 - a0;
-                Q0 = a1;
-                Q1 = b1 - a1;
-            } else if (lcy != prev) {
-                prev = lcy;
-                const int q = lcy * nnx + lcx;
-                const float fx00 = gx[q], fx10 = gx[q + 1], fx01 = gx[q + nnx], fx11 = gx[q + nnx + 1];
-                const float fy00 = gy[q], fy10 = gy[q + 1], fy01 = gy[q + nnx], fy11 = gy[q + nnx + 1];
-                float e0 = fx00 * b10x + fx10 * b11x;
-                float e1 = fx01 * b10x + fx11 * b11x;
-                if (MD == 2) {  // the heights' value term along the row
-                    e0 += gh[q] + sx * (gh[q + 1] - gh[q]);
-                    e1 += gh[q + nnx] + sx * (gh[q + nnx + 1] - gh[q + nnx]);
-                }
-                E0 = e0;
-                dE = e1 - e0;
-                Q0 = fy00 + sx * (fy10 - fy00);
-                Q1 = fy01 + sx * (fy11 - fy01);
-                if (GRAD) {
-                    float e0x = fx00 * db10x + fx10 * db11x;
-                    float e1x = fx01 * db10x + fx11 * db11x;
-                    if (MD == 2) {
-                        e0x += dsx * (gh[q + 1] - gh[q]);
-                        e1x += dsx * (gh[q + nnx + 1] - gh[q + nnx]);
+                if (MD == 1) {
+                    E0 = lo.E;
+                    dE = hi.E - lo.E;
+                    Q0 = Q1 = hi.Q - lo.Q;
+                    if (GRAD) {
+                        E0x = lo.Ex;
+                        dEx = hi.Ex - lo.Ex;
+                        Q0x = Q1x = hi.Qx - lo.Qx;
                     }
-                    E0x = e0x;
-                    dEx = e1x - e0x;
-                    Q0x = dsx * (fy10 - fy00);
-                    Q1x = dsx * (fy11 - fy01);
+                } else if (MD == 3) {  // Perlin: E0 = A0, dE = A1 - B1 - A0, Q0 = B0, Q1 = B1 - B0
+                    E0 = lo.E;
+                    dE = hi.E - hi.Q - lo.E;
+                    Q0 = lo.Q;
+                    Q1 = hi.Q - lo.Q;
+                } else {
+                    E0 = lo.E;
+                    dE = hi.E - lo.E;
+                    Q0 = lo.Q;
+                    Q1 = hi.Q;
+                    if (GRAD) {
+                        E0x = lo.Ex;
+                        dEx = hi.Ex - lo.Ex;
+                        Q0x = lo.Qx;
+                        Q1x = hi.Qx;
+                    }
                 }
             }
             acc[r] += E0 + dE * re.y + Q0 * re.z + Q1 * re.w;

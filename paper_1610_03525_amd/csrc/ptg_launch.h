@@ -15,6 +15,14 @@ constexpr int kTile3X = 64;
 constexpr int kTile3Y = 8;
 constexpr int kTile3Z = 8;
 
+// LDS of the general 2D tile beyond its row tables and one octave's node block: a footprint
+// entry (kTileFootBytes) and the column and row keys of every octave.
+constexpr int kTileFootBytes = 32;
+__host__ __device__ inline size_t general2d_octave_lds(int octaves, int capx, int capy)
+{
+    return (size_t)octaves * ((size_t)kTileFootBytes + (size_t)(capx + capy) * 4);
+}
+
 struct Fbm2dArgs {
     int64_t x0, y0, nx, ny, pitch;
     void *out;
