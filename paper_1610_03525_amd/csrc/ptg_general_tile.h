@@ -366,13 +366,23 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
 }
 
 // ---------------------------------------------------------------------------------
-// 3D: tile 64 x 8 x 8 samples; wave w owns slabs z = 2w, 2w+1, all 8 rows of each.
+// 3D: tile 64 x 8 x TZ samples; wave w owns TZ / 4 slabs, all 8 rows of each.
 // For a fixed column the cell is collapsed along x (a, b, c per (cy, cz) corner pair),
 // then along z, leaving the 1D Hermite form in y evaluated per sample.
-// LDS: y table float4[8] | z table float4[8] | g{x,y,z}[cap] | kx[capx] | kzy[capy*capz]
+// LDS: y table float4[8] | z table float4[TZ] | every octave's footprint TileFoot3[octaves] |
+// g{x,y,z}[cap] | (MD = 2) h[cap] | every octave's keys kx[octaves*capx] | kzy[octaves*capy*capz]
 // ---------------------------------------------------------------------------------
+// Once per tile: the octaves' footprints (one lane per octave, FP64) and the keys of their
+// node columns and (z, y) node rows; per octave, between two barriers, the y and z tables
+// and the node block (node indices stepped, not divided); then each wave's slabs.
 // MD = 2: node heights (third key word) and w-weighted gradients; the x collapse adds the
 // heights' value term to each corner's a.
+struct TileFoot3 {  // one octave's lattice footprint over a 3D tile
+    int64_t cxf, cyf, czf;
+    int32_t nnx, nny, nnz, pad;
+};
+static_assert(sizeof(TileFoot3) == kTileFoot3Bytes, "3D footprint table entry size");
+
 template <int M, typename OutT, int MD = 0>
 __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t bid, float4 *lds4)
 {
@@ -381,13 +391,14 @@ __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t b
     constexpr int RPT = ZPW * TY;
     float4 *yt = lds4;
     float4 *zt = lds4 + TY;
-    const int cap = a.capx * a.capy * a.capz;
-    float *gxs = reinterpret_cast<float *>(lds4 + TY + TZ);
+    TileFoot3 *foot = reinterpret_cast<TileFoot3 *>(lds4 + TY + TZ);
+    const int cap = a.capx * a.capy * a.capz, capzy = a.capy * a.capz;
+    float *gxs = reinterpret_cast<float *>(foot + a.octaves);
     float *gys = gxs + cap;
     float *gzs = gys + cap;
     float *hs = gzs + cap;  // node heights (MD = 2)
-    uint32_t *kx = reinterpret_cast<uint32_t *>(gzs + (MD == 2 ? 2 : 1) * cap);
-    uint32_t *kzy = kx + a.capx;
+    uint32_t *kx_all = reinterpret_cast<uint32_t *>(gzs + (MD == 2 ? 2 : 1) * cap);
+    uint32_t *kzy_all = kx_all + a.octaves * a.capx;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t tpl = (int64_t)a.tiles_x * a.tiles_y;
@@ -401,6 +412,33 @@ __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t b
     const int64_t X = a.x0 + tx0 + col;
     const int64_t Xf = a.x0 + tx0, Yf = a.y0 + ty0, Zf = a.z0 + tz0;
 
+    // ---- once per tile: every octave's footprint, then its column and (z, y) row keys -----
+    if (tid < a.octaves) {
+        const double f = a.freq[tid];
+        TileFoot3 ft;
+        ft.cxf = cell_of(Xf, f);
+        ft.cyf = cell_of(Yf, f);
+        ft.czf = cell_of(Zf, f);
+        ft.nnx = (int)(cell_of(Xf + w - 1, f) - ft.cxf) + 2;
+        ft.nny = (int)(cell_of(Yf + hy - 1, f) - ft.cyf) + 2;
+        ft.nnz = (int)(cell_of(Zf + hz - 1, f) - ft.czf) + 2;
+        ft.pad = 0;
+        foot[tid] = ft;
+    }
+    __syncthreads();
+    for (int o = 0; o < a.octaves; ++o) {
+        const TileFoot3 ft = foot[o];
+        const int nnx = uniform_i32(ft.nnx), nny = uniform_i32(ft.nny), nnz = uniform_i32(ft.nnz);
+        const int64_t cxf = uniform_i64(ft.cxf), cyf = uniform_i64(ft.cyf), czf = uniform_i64(ft.czf);
+        uint32_t *kx = kx_all + o * a.capx, *kzy = kzy_all + o * capzy;
+        const uint32_t pre = key_prefix(a.seed, o);
+        for (int i = tid; i < nnx; i += 256) kx[i] = key_xline(cxf + i);
+        for (int q = tid; q < nny * nnz; q += 256) {
+            const int k = q / nny, j = q - k * nny;
+            kzy[q] = absorb_index(absorb_index(pre, czf + k), cyf + j);
+        }
+    }
+
     float acc[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) acc[r] = 0.0f;
@@ -408,18 +446,12 @@ __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t b
     for (int o = 0; o < a.octaves; ++o) {
         const double f = a.freq[o];
         const float amp = a.amp[o];
-        const int64_t cxf = cell_of(Xf, f), cyf = cell_of(Yf, f), czf = cell_of(Zf, f);
-        const int nnx = (int)(cell_of(Xf + w - 1, f) - cxf) + 2;
-        const int nny = (int)(cell_of(Yf + hy - 1, f) - cyf) + 2;
-        const int nnz = (int)(cell_of(Zf + hz - 1, f) - czf) + 2;
+        const TileFoot3 ft = foot[o];
+        const int nnx = uniform_i32(ft.nnx), nny = uniform_i32(ft.nny), nnz = uniform_i32(ft.nnz);
+        const int64_t cxf = uniform_i64(ft.cxf), cyf = uniform_i64(ft.cyf), czf = uniform_i64(ft.czf);
+        const uint32_t *kx = kx_all + o * a.capx, *kzy = kzy_all + o * capzy;
 
-        __syncthreads();
-        const uint32_t pre = key_prefix(a.seed, o);
-        for (int i = tid; i < nnx; i += 256) kx[i] = key_xline(cxf + i);
-        for (int q = tid; q < nny * nnz; q += 256) {
-            const int k = q / nny, j = q - k * nny;
-            kzy[q] = absorb_index(absorb_index(pre, czf + k), cyf + j);
-        }
+        __syncthreads();  // the previous octave is done with the tables and node block
         if (tid < TY) {
             const int r = min(tid, hy - 1);
             const Coord c = coord_step(Yf + r, f);
@@ -433,17 +465,25 @@ __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t b
             Basis<M>::eval(c.t, s, b10, b11);
             zt[tid - 64] = make_float4(__int_as_float((int)(c.cell - czf)), s, b10, b11);
         }
-        __syncthreads();
-        const int plane = nnx * nny;
-        for (int q = tid; q < plane * nnz; q += 256) {
-            const int row = q / nnx, i = q - row * nnx;  // row = k * nny + j
-            const uint32_t key = key_combine(kzy[row], kx[i]), second = key3_second(key);
-            const float3 g = grad3_of(key, second);
+        {
+            // node q = row nnx + i (row = k nny + j); a thread's nodes step by 256
+            const int plane = nnx * nny, nn = plane * nnz, drow = 256 / nnx, di = 256 - drow * nnx;
+            int row = tid / nnx, i = tid - row * nnx;
             const float gsc = MD == 2 ? amp * a.gw : amp;
-            gxs[q] = g.x * gsc;
-            gys[q] = g.y * gsc;
-            gzs[q] = g.z * gsc;
-            if (MD == 2) hs[q] = height3_of_second(second) * amp;
+            for (int q = tid; q < nn; q += 256) {
+                const uint32_t key = key_combine(kzy[row], kx[i]), second = key3_second(key);
+                const float3 g = grad3_of(key, second);
+                gxs[q] = g.x * gsc;
+                gys[q] = g.y * gsc;
+                gzs[q] = g.z * gsc;
+                if (MD == 2) hs[q] = height3_of_second(second) * amp;
+                i += di;
+                row += drow;
+                if (i >= nnx) {
+                    i -= nnx;
+                    ++row;
+                }
+            }
         }
         const Coord cc = coord_step(X, f);
         const int lcx = (int)(cc.cell - cxf);

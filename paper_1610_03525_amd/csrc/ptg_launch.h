@@ -23,6 +23,13 @@ __host__ __device__ inline size_t general2d_octave_lds(int octaves, int capx, in
     return (size_t)octaves * ((size_t)kTileFootBytes + (size_t)(capx + capy) * 4);
 }
 
+// The 3D general tile's footprint entries and every octave's column and (z, y) row keys.
+constexpr int kTileFoot3Bytes = 40;
+__host__ __device__ inline size_t general3d_octave_lds(int octaves, int capx, int capy, int capz)
+{
+    return (size_t)octaves * ((size_t)kTileFoot3Bytes + (size_t)(capx + capy * capz) * 4);
+}
+
 struct Fbm2dArgs {
     int64_t x0, y0, nx, ny, pitch;
     void *out;

@@ -267,7 +267,7 @@ size_t general_args_3d(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, 
     a->gw = (float)p->gradient_weight;
     return (size_t)(kTile3Y + kTile3Z) * 16 +
            (size_t)a->capx * a->capy * a->capz * (p->model == PTG_MODEL_HEIGHT_GRADIENT ? 16 : 12) +
-           (size_t)(a->capx + a->capy * a->capz) * 4;
+           general3d_octave_lds(p->octaves, a->capx, a->capy, a->capz);
 }
 
 int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out, int64_t pitch,
