@@ -335,8 +335,7 @@ def other_configs(torch, ptg, stream):
     ms = _time_launches(torch, stream, lambda: ptg.lib().ptg_fbm_2d_grad(
         ctypes.byref(q), 0, 0, 8192, 8192, zf.data_ptr(), gx.data_ptr(), gy.data_ptr(), 8192, sh), 5)
     res["2d_8192_8oct_gradient_output"] = {
-        "workload": "H, dH/dX, dH/dY of the 8192^2 8-octave C1 field (three FP32 outputs; strip kernel, one "
-                    "launch per output)",
+        "workload": "H, dH/dX, dH/dY of the 8192^2 8-octave C1 field (three FP32 outputs; one strip-kernel launch)",
         "ms": ms, "octave_samples_s": 8192 * 8192 * 8 / (ms * 1e-3),
         "hbm_frac": 3 * 8192 * 8192 * 4 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     del gx, gy

@@ -184,8 +184,8 @@ PTG_API int ptg_fbm_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, 
  * out_dev[j*row_pitch + i] = H(X, Y), dx_dev[...] = dH/dX, dy_dev[...] = dH/dY in world
  * units (per sample: sum_o a_o f_o dh_o/dt), the three buffers of p->out_dtype with the same
  * layout.  The cell models at smoothness 1..3; plain form.  Dyadic ladders that the strip
- * kernel takes (p->path not PTG_PATH_GENERAL) run three launches on it: out_dev is the same
- * launch as ptg_fbm_2d's, then dH/dX, then dH/dY.  Other ladders, and p->path ==
+ * kernel takes (p->path not PTG_PATH_GENERAL) run one strip launch for the three outputs
+ * (out_dev bit-identical to ptg_fbm_2d's strip launch).  Other ladders, and p->path ==
  * PTG_PATH_GENERAL, run the general kernel, which writes the three in one pass.
  * Errors: as ptg_fbm_2d (PTG_EINVAL also for a NULL output or a matrix-core form). */
 PTG_API int ptg_fbm_2d_grad(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out_dev,

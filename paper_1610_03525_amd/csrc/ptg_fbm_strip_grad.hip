@@ -1,9 +1,10 @@
 // ptg_fbm_strip_grad.hip -- the analytic gradient of a 2D dyadic field (the gradient maps
-// of Sec. 5.1) on the strip kernel: dH/dX and dH/dY, one launch each, in world units per
-// sample.  H is linear in every lane's x-weights, so dH/dX is the strip computation with
-// the weights' t-derivatives (times 1/P per octave); dH/dY differentiates each row
-// segment's polynomial (w = (Y - centre) / 64) and takes the row-basis derivatives for the
-// directly evaluated octaves.
+// of Sec. 5.1) on the strip kernel: H, dH/dX and dH/dY in one launch, in world units per
+// sample.  Per strip, after one hashing of its footprint: the rows' values and their d/dY in
+// one pass (d/dY differentiates each row segment's polynomial, w = (Y - centre) / 64, and
+// takes the row-basis derivatives for the directly evaluated octaves), then dH/dX: H is
+// linear in every lane's x-weights, so it is the same strip computation with the weights'
+// t-derivatives (times 1/P per octave).
 #include "ptg_strip_tile.h"
 
 namespace ptg {
@@ -105,19 +106,16 @@ static hipError_t launch_g(const Fbm2dStripArgs &a, int smooth, int model, bool 
                        : launch_m<3, 0, G>(a, f16, grid, waves, lds, s);
 }
 
-// model 1 (zero-gradient) is smoothness 1 only; models 0 and 2 smoothness 1, 2 or 3;
-// axis 0 = d/dX, 1 = d/dY
-int strip_grad_wgs_per_cu(int axis, int smooth, int model, bool f16, int lo, int waves, size_t lds)
+// model 1 (zero-gradient) is smoothness 1 only; models 0 and 2 smoothness 1, 2 or 3
+int strip_grad_wgs_per_cu(int smooth, int model, bool f16, int lo, int waves, size_t lds)
 {
-    return axis == 0 ? resident_g<1>(smooth, model, f16, lo, waves, lds)
-                     : resident_g<2>(smooth, model, f16, lo, waves, lds);
+    return resident_g<4>(smooth, model, f16, lo, waves, lds);
 }
 
-hipError_t launch_fbm2d_strip_grad(const Fbm2dStripArgs &a, int axis, int smooth, int model, bool f16, int grid,
-                                   int waves, size_t lds, hipStream_t s)
+hipError_t launch_fbm2d_strip_grad(const Fbm2dStripArgs &a, int smooth, int model, bool f16, int grid, int waves,
+                                   size_t lds, hipStream_t s)
 {
-    return axis == 0 ? launch_g<1>(a, smooth, model, f16, grid, waves, lds, s)
-                     : launch_g<2>(a, smooth, model, f16, grid, waves, lds, s);
+    return launch_g<4>(a, smooth, model, f16, grid, waves, lds, s);
 }
 
 }  // namespace ptg

@@ -102,6 +102,7 @@ struct Fbm2dStripArgs {
     int64_t sx_base, sy_base;       // world origin of strip (0, 0), strip-aligned
     int64_t strips;
     void *out;
+    void *out_dx, *out_dy;                          // gradient outputs of the fused gradient kernel
     float amp[kMaxOctaves];
     float inv2p[kMaxOctaves];                       // 2^-(shift + 1)
     int32_t shift[kMaxOctaves];                     // period 2^shift; shift[o] = shift[0] - o
@@ -236,10 +237,11 @@ __host__ __device__ inline int strip3_wave_words(int nodes_total, int keys_total
 hipError_t launch_fbm2d_strip(const Fbm2dStripArgs &a, int smooth, int model, bool f16, int grid, int waves, size_t lds_bytes,
                               hipStream_t s);
 int strip_wgs_per_cu(int smooth, int model, bool f16, int lo, int waves, size_t lds_bytes);  // resident WGs per CU
-// The field's analytic gradient on the strip kernel: axis 0 = dH/dX, 1 = dH/dY (into a.out).
-hipError_t launch_fbm2d_strip_grad(const Fbm2dStripArgs &a, int axis, int smooth, int model, bool f16, int grid,
-                                   int waves, size_t lds_bytes, hipStream_t s);
-int strip_grad_wgs_per_cu(int axis, int smooth, int model, bool f16, int lo, int waves, size_t lds_bytes);
+// The field and its analytic gradient on the strip kernel, one launch: H to a.out, dH/dX to
+// a.out_dx, dH/dY to a.out_dy.
+hipError_t launch_fbm2d_strip_grad(const Fbm2dStripArgs &a, int smooth, int model, bool f16, int grid, int waves,
+                                   size_t lds_bytes, hipStream_t s);
+int strip_grad_wgs_per_cu(int smooth, int model, bool f16, int lo, int waves, size_t lds_bytes);
 // The FP16 / BF16 precision form on the strip kernel (prec 1 / 2; cubic cells, FP16 output).
 hipError_t launch_fbm2d_strip_mx(const Fbm2dStripArgs &a, int prec, int grid, int waves, size_t lds_bytes,
                                  hipStream_t s);

@@ -323,10 +323,11 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
 }
 
 // The field and its analytic gradient.  Dyadic ladders (unless the general path is asked
-// for) take the strip kernel: the field (the same launch as ptg_fbm_2d's), then dH/dX and
-// dH/dY, one launch each.  Otherwise, or when a strip's footprint does not fit LDS, the
-// general kernel with 64-row tiles (any model, any ladder) and a second row table for the
-// row-basis derivatives writes all three in one pass.
+// for) take the strip kernel in one launch: per strip the field and dH/dY in one pass, then
+// dH/dX (the field's arithmetic is that of ptg_fbm_2d's strip launch, bit for bit).
+// Otherwise, or when a strip's footprint does not fit LDS, the general kernel with 64-row
+// tiles (any model, any ladder) and a second row table for the row-basis derivatives writes
+// all three in one pass.
 int fbm2d_grad(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t ny, void *out, void *out_dx,
                void *out_dy, int64_t pitch, hipStream_t s)
 {
@@ -338,14 +339,10 @@ int fbm2d_grad(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t 
         if (!strip_plan(p, k, x0, y0, nx, ny, out, pitch, &a, &waves, &lds)) {
             const bool f16 = p->out_dtype == PTG_F16;
             const int sm = p->smoothness, md = p->model;
-            hipError_t e =
-                launch_fbm2d_strip(a, sm, md, f16, strip_grid(a, waves, strip_wgs_per_cu(sm, md, f16, a.lo, waves, lds)),
-                                   waves, lds, s);
-            for (int axis = 0; axis < 2 && e == hipSuccess; ++axis) {
-                a.out = axis == 0 ? out_dx : out_dy;
-                const int grid = strip_grid(a, waves, strip_grad_wgs_per_cu(axis, sm, md, f16, a.lo, waves, lds));
-                e = launch_fbm2d_strip_grad(a, axis, sm, md, f16, grid, waves, lds, s);
-            }
+            a.out_dx = out_dx;
+            a.out_dy = out_dy;
+            const int grid = strip_grid(a, waves, strip_grad_wgs_per_cu(sm, md, f16, a.lo, waves, lds));
+            hipError_t e = launch_fbm2d_strip_grad(a, sm, md, f16, grid, waves, lds, s);
             return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d strip gradient launch");
         }
     }

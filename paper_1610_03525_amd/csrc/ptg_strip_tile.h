@@ -392,16 +392,19 @@ struct SegRows {
 // direct octaves, centred on the segment (row k at w = (2 k - R + 1) / 128).  Rows are taken
 // in pairs symmetric about the centre, w and -w, from the even and odd parts of Cs; the
 // direct octaves' E0 terms go into each row's constant term, the rest is 3 FMA per octave.
-// G = 2: the rows' d/dY instead (w = (Y - centre) / 64): the derivative of Cs, and the direct
-// octaves' row-basis derivatives (their E0 terms are constant along y).
+// G selects what is written: 0 and 1 the rows' values (G = 1: the strip machinery run on the
+// x-weights' derivatives) to rp; 2 their d/dY to rp; 3 both, the values to rp and d/dY to
+// rp2.  d/dY (w = (Y - centre) / 64): the derivative of Cs, and the direct octaves' row-basis
+// derivatives (their E0 terms are constant along y).
 template <int M, typename OutT, int R, bool D8, bool D4, bool D2, bool D1, bool FULL, int MD = 0, int G = 0>
 __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[2 * M + 2], int r0, NR (&carry)[4],
-                                             OutT *rp, int lane, int rlo, int rhi, bool lane_ok)
+                                             OutT *rp, OutT *rp2, int lane, int rlo, int rhi, bool lane_ok)
 {
-    constexpr int D = 2 * M + 1, DEG = G == 2 ? D - 1 : D;  // degree of the evaluated polynomial
-    float Pw[D + 1];
+    constexpr int D = 2 * M + 1;
+    constexpr bool WV = G != 2, WD = G >= 2;  // values, derivatives
+    float Pd[D];  // d/dY of the segment polynomial, degree D - 1 (WD)
 #pragma unroll
-    for (int b = 0; b <= D; ++b) Pw[b] = G == 2 ? (b < D ? (float)(b + 1) * (1.0f / 64.0f) * Cs[b + 1] : 0.0f) : Cs[b];
+    for (int b = 0; b < D; ++b) Pd[b] = WD ? (float)(b + 1) * (1.0f / 64.0f) * Cs[b + 1] : 0.0f;
     SegRows<8, R, MD> s8;
     SegRows<4, R, MD> s4;
     SegRows<2, R, MD> s2;
@@ -418,48 +421,65 @@ __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[
     if (D1) s1.load_streamed(x.f1, carry[3]);
     // row pointers walk outwards from the centre pair (uniform, one add each per pair)
     OutT *pa = rp + (int64_t)(r0 + R / 2 - 1) * x.pitch, *pb = pa + x.pitch;
+    OutT *qa = (G == 3 ? rp2 : rp) + (int64_t)(r0 + R / 2 - 1) * x.pitch, *qb = qa + x.pitch;
 #pragma unroll
     for (int p = 0; p < R / 2; ++p) {
         const int rb = R / 2 + p;
         const float w = (float)(2 * rb - R + 1) * (1.0f / 128.0f);
         const float w2 = w * w;
-        // odd part in w^2 (P1, P3, ...) and the even part beyond P0 (P2, P4, ...)
-        constexpr int TOPO = (DEG & 1) ? DEG : DEG - 1, TOPE = (DEG & 1) ? DEG - 1 : DEG;
-        float odd = Pw[TOPO];
+        // odd part in w^2 (C1, C3, ...) and the even part beyond C0 (C2, C4, ...)
+        float odd = 0.0f, even2 = 0.0f, oddd = 0.0f, even2d = 0.0f;
+        if (WV) {
+            odd = Cs[D];
 #pragma unroll
-        for (int e = TOPO - 2; e >= 1; e -= 2) odd = __builtin_fmaf(odd, w2, Pw[e]);
-        float even2 = Pw[TOPE];
+            for (int e = D - 2; e >= 1; e -= 2) odd = __builtin_fmaf(odd, w2, Cs[e]);
+            even2 = Cs[D - 1];
 #pragma unroll
-        for (int e = TOPE - 2; e >= 2; e -= 2) even2 = __builtin_fmaf(even2, w2, Pw[e]);
+            for (int e = D - 3; e >= 2; e -= 2) even2 = __builtin_fmaf(even2, w2, Cs[e]);
+        }
+        if (WD) {  // degree D - 1 = 2M: odd part P1, P3, ..., P(D-2); even part P2, ..., P(D-1)
+            oddd = Pd[D - 2];
+#pragma unroll
+            for (int e = D - 4; e >= 1; e -= 2) oddd = __builtin_fmaf(oddd, w2, Pd[e]);
+            even2d = Pd[D - 1];
+#pragma unroll
+            for (int e = D - 3; e >= 2; e -= 2) even2d = __builtin_fmaf(even2d, w2, Pd[e]);
+        }
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const int k = side ? rb : R / 2 - 1 - p;  // row in the segment
             const int row = r0 + k;                   // row in the strip
-            float c0 = Pw[0];
-            if (G != 2) {
+            const bool keep = FULL || (row >= rlo && row < rhi && lane_ok);
+            if (WV) {
+                float c0 = Cs[0];
                 if (D8) c0 += s8.n[k / 8].E;
                 if (D4) c0 += s4.n[k / 4].E;
                 if (D2) c0 += s2.n[k / 2].E;
                 if (D1) c0 += s1.n[k].E;
-            }
-            float val = __builtin_fmaf(even2, w2, c0);
-            val = __builtin_fmaf(side ? w : -w, odd, val);
-            if (G == 2) {
-                if (D8) val = add_direct<MD>(val, s8.n[k / 8], s8.n[k / 8 + 1], row_dbases<M>(row & 7, 8));
-                if (D4) val = add_direct<MD>(val, s4.n[k / 4], s4.n[k / 4 + 1], row_dbases<M>(row & 3, 4));
-                if (D2) val = add_direct<MD>(val, s2.n[k / 2], s2.n[k / 2 + 1], row_dbases<M>(row & 1, 2));
-                if (D1) val = add_direct<MD>(val, s1.n[k], s1.n[k + 1], row_dbases<M>(0, 1));
-            } else {
+                float val = __builtin_fmaf(even2, w2, c0);
+                val = __builtin_fmaf(side ? w : -w, odd, val);
                 if (D8) val = add_direct<MD>(val, s8.n[k / 8], s8.n[k / 8 + 1], row_bases<M>(row & 7, 8));
                 if (D4) val = add_direct<MD>(val, s4.n[k / 4], s4.n[k / 4 + 1], row_bases<M>(row & 3, 4));
                 if (D2) val = add_direct<MD>(val, s2.n[k / 2], s2.n[k / 2 + 1], row_bases<M>(row & 1, 2));
                 if (D1) val = add_direct<MD>(val, s1.n[k], s1.n[k + 1], row_bases<M>(0, 1));
+                OutT *const rrow = side ? pb : pa;
+                if (keep) rrow[lane] = st_out<OutT>(val);
             }
-            OutT *const rrow = side ? pb : pa;
-            if (FULL || (row >= rlo && row < rhi && lane_ok)) rrow[lane] = st_out<OutT>(val);
+            if (WD) {
+                float val = __builtin_fmaf(even2d, w2, Pd[0]);
+                val = __builtin_fmaf(side ? w : -w, oddd, val);
+                if (D8) val = add_direct<MD>(val, s8.n[k / 8], s8.n[k / 8 + 1], row_dbases<M>(row & 7, 8));
+                if (D4) val = add_direct<MD>(val, s4.n[k / 4], s4.n[k / 4 + 1], row_dbases<M>(row & 3, 4));
+                if (D2) val = add_direct<MD>(val, s2.n[k / 2], s2.n[k / 2 + 1], row_dbases<M>(row & 1, 2));
+                if (D1) val = add_direct<MD>(val, s1.n[k], s1.n[k + 1], row_dbases<M>(0, 1));
+                OutT *const rrow = side ? qb : qa;
+                if (keep) rrow[lane] = st_out<OutT>(val);
+            }
         }
         pa -= x.pitch;
         pb += x.pitch;
+        qa -= x.pitch;
+        qb += x.pitch;
         // keep each pair's stores next to its arithmetic: without this the scheduler hoists
         // most of a strip's row arithmetic ahead of the first store and then issues the
         // stores in one burst, with the values held in registers
@@ -475,8 +495,8 @@ __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[
 // per re-centring) period 8 stays a direct octave.  No piece is evaluated away from its own
 // cell.  FULL = every sample of the strip is stored.
 template <int M, typename OutT, int LO, bool FULL, int MD = 0, int G = 0>
-__device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 * M + 2], OutT *rp, int lane, int rlo,
-                                           int rhi, bool lane_ok)
+__device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 * M + 2], OutT *rp, OutT *rp2, int lane,
+                                           int rlo, int rhi, bool lane_ok)
 {
     constexpr int D1 = 2 * M + 2;
     constexpr bool H32 = LO <= 5, H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
@@ -528,12 +548,12 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
                     const NR lo = carry[0], hi = node_row<9, MD>(x.f8, 2 * q + e + 1);
                     add_piece<M, 8, MD>(Ce, lo, hi);
                     carry[0] = hi;
-                    segment_rows<M, OutT, 8, false, H4, H2, H1, FULL, MD, G>(x, Ce, 16 * q + 8 * e, carry, rp, lane,
-                                                                              rlo, rhi, lane_ok);
+                    segment_rows<M, OutT, 8, false, H4, H2, H1, FULL, MD, G>(x, Ce, 16 * q + 8 * e, carry, rp, rp2,
+                                                                              lane, rlo, rhi, lane_ok);
                 }
             } else {
-                segment_rows<M, OutT, 16, H8, H4, H2, H1, FULL, MD, G>(x, Cq, 16 * q, carry, rp, lane, rlo, rhi,
-                                                                        lane_ok);
+                segment_rows<M, OutT, 16, H8, H4, H2, H1, FULL, MD, G>(x, Cq, 16 * q, carry, rp, rp2, lane, rlo,
+                                                                        rhi, lane_ok);
             }
         }
     }
@@ -587,7 +607,9 @@ __device__ __forceinline__ void strip_prologue(const Fbm2dStripArgs &a, StripSha
 // One wave's strips of a field: the lane's x-weights of the fixed-period octaves (formed
 // once) and the strip column whose keys its LDS block holds.  G selects the output: 0 the
 // field H, 1 dH/dX (the x-weights' derivatives), 2 dH/dY (the rows' derivatives), both in
-// world units per sample.
+// world units per sample; 4 all three (H to a.out, dH/dX to a.out_dx, dH/dY to a.out_dy)
+// from one hashing of each strip: the rows' values and d/dY in one pass, then the same
+// strip with the derivative x-weights.
 template <int M, typename OutT, int LO, int MD = 0, int PREC = 0, int G = 0>
 struct StripWave {
     static_assert(PREC == 0 || G == 0, "the precision form writes the field only");
@@ -604,6 +626,8 @@ struct StripWave {
     int64_t keyed_bsx = -1;
     MxConst<PREC ? PREC : 1> mc;  // precision form (PREC 1 / 2): the MFMA's row operands
 
+    // An octave's node column and the lane's x-weights (DX: their derivatives, times 1/P).
+    template <bool DX>
     __device__ __forceinline__ Fixed fixed(const StripShared &sh, int o) const
     {
         Fixed f{nodes, XA{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, heights};
@@ -612,8 +636,8 @@ struct StripWave {
             f.col = nodes + sh.noff[o] + (lane >> s) * sh.nbr[o];
             f.hcol = heights + sh.noff[o] + (lane >> s) * sh.nbr[o];
             const float inv2p = sh.inv2p[o];
-            f.xa = xweights<M, MD, G == 1>((float)(2 * (lane & ((1 << s) - 1)) + 1) * inv2p,
-                                           G == 1 ? sh.amp[o] * (2.0f * inv2p) : sh.amp[o], sh.gw);
+            f.xa = xweights<M, MD, DX>((float)(2 * (lane & ((1 << s) - 1)) + 1) * inv2p,
+                                       DX ? sh.amp[o] * (2.0f * inv2p) : sh.amp[o], sh.gw);
         }
         return f;
     }
@@ -628,14 +652,43 @@ struct StripWave {
         : nodes(nodes_), heights(reinterpret_cast<float *>(nodes_ + a.nodes_total)),
           keys(reinterpret_cast<uint32_t *>(nodes_ + a.nodes_total) + (MD == 2 ? a.nodes_total : 0)), lane(lane_)
     {
-        f64 = fixed(sh, a.o64);
+        f64 = fixed<G == 1>(sh, a.o64);
         if constexpr (PREC > 0) mc.init(a.basis, lane);
-        rc0 = RowCtx{fixed(sh, H32 ? a.o32 : -1), fixed(sh, H16 ? a.o16 : -1), fixed(sh, H8 ? a.o8 : -1),
-                     fixed(sh, H4 ? a.o4 : -1),   fixed(sh, H2 ? a.o2 : -1),   fixed(sh, H1 ? a.o1 : -1),
-                     a.pitch,
-                     keys,
-                     streamed(sh, a, H2 ? a.o2 : -1),
-                     streamed(sh, a, H1 ? a.o1 : -1)};
+        rc0 = ctx<G == 1>(a, sh);
+    }
+
+    template <bool DX>
+    __device__ __forceinline__ RowCtx ctx(const Fbm2dStripArgs &a, const StripShared &sh) const
+    {
+        return RowCtx{fixed<DX>(sh, H32 ? a.o32 : -1), fixed<DX>(sh, H16 ? a.o16 : -1), fixed<DX>(sh, H8 ? a.o8 : -1),
+                      fixed<DX>(sh, H4 ? a.o4 : -1),   fixed<DX>(sh, H2 ? a.o2 : -1),   fixed<DX>(sh, H1 ? a.o1 : -1),
+                      a.pitch,
+                      keys,
+                      streamed(sh, a, H2 ? a.o2 : -1),
+                      streamed(sh, a, H1 ? a.o1 : -1)};
+    }
+
+    // The polynomial in v of the octaves of period >= 64 at the lane's column (DX: with the
+    // x-weights' derivatives; fx is the period-64 octave's column with those weights).
+    template <bool DX>
+    __device__ __forceinline__ void coarse(const Fbm2dStripArgs &a, const Fixed &fx, int64_t X0, int64_t Y0,
+                                           float (&C)[D1]) const
+    {
+#pragma unroll
+        for (int b = 0; b < D1; ++b) C[b] = 0.0f;
+        for (int o = 0; o < a.n_generic; ++o) {  // period >= 128: the strip is inside one cell
+            // per-octave values from the arguments: uniform (scalar) in the dense kernel
+            const int s = a.shift[o];
+            const uint32_t mask = (1u << s) - 1u;
+            const float inv2p = a.inv2p[o];
+            const XA xa = xweights<M, MD, DX>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p,
+                                              DX ? a.amp[o] * (2.0f * inv2p) : a.amp[o], a.gw);
+            const CF c = column_form<MD>(nodes + a.noff[o], 2, xa, heights + a.noff[o]);
+            const float invp = 2.0f * inv2p;
+            const float tau = (float)(((uint32_t)Y0 & mask) + (uint32_t)(kStripH / 2)) * invp - 0.5f;
+            add_mapped<M>(C, c, tau, (float)kStripH * invp);
+        }
+        if (a.o64 >= 0) add_piece<M, 1, MD>(C, node_row<2, MD>(fx, 0), node_row<2, MD>(fx, 1));  // t - 1/2 = v
     }
 
     // Strip st of the field: hash its footprint, sum its coarse octaves, write its rows.
@@ -678,21 +731,7 @@ struct StripWave {
 
         // ---- octaves of period >= 64: one polynomial in v per lane ------------------------
         float C[D1];
-#pragma unroll
-        for (int b = 0; b < D1; ++b) C[b] = 0.0f;
-        for (int o = 0; o < a.n_generic; ++o) {  // period >= 128: the strip is inside one cell
-            // per-octave values from the arguments: uniform (scalar) in the dense kernel
-            const int s = a.shift[o];
-            const uint32_t mask = (1u << s) - 1u;
-            const float inv2p = a.inv2p[o];
-            const XA xa = xweights<M, MD, G == 1>((float)(2u * (((uint32_t)X0 & mask) + (uint32_t)lane) + 1u) * inv2p,
-                                                  G == 1 ? a.amp[o] * (2.0f * inv2p) : a.amp[o], a.gw);
-            const CF c = column_form<MD>(nodes + a.noff[o], 2, xa, heights + a.noff[o]);
-            const float invp = 2.0f * inv2p;
-            const float tau = (float)(((uint32_t)Y0 & mask) + (uint32_t)(kStripH / 2)) * invp - 0.5f;
-            add_mapped<M>(C, c, tau, (float)kStripH * invp);
-        }
-        if (a.o64 >= 0) add_piece<M, 1, MD>(C, node_row<2, MD>(f64, 0), node_row<2, MD>(f64, 1));  // t - 1/2 = v
+        coarse<G == 1>(a, f64, X0, Y0, C);
 
         // ---- rows: one store per row of the wave; interior strips take the unmasked path --
         const int64_t xe = a.x0 + a.nx, ye = a.y0 + a.ny;
@@ -700,16 +739,32 @@ struct StripWave {
         const int rhi = (int)max<int64_t>(0, min<int64_t>(kStripH, ye - Y0));
         const int clo = (int)max<int64_t>(0, min<int64_t>(kStripW, a.x0 - X0));
         const int chi = (int)max<int64_t>(0, min<int64_t>(kStripW, xe - X0));
-        OutT *row0 = reinterpret_cast<OutT *>(a.out) + (Y0 - a.y0) * a.pitch + (X0 - a.x0);
+        const int64_t at = (Y0 - a.y0) * a.pitch + (X0 - a.x0);
+        OutT *row0 = reinterpret_cast<OutT *>(a.out) + at;
         if constexpr (PREC > 0) {  // cubic cells, gradient model
             if (rlo == 0 && rhi == kStripH && clo == 0 && chi == kStripW)
                 strip_rows_mx<OutT, LO, PREC, true>(rc0, C, row0, lane, 0, kStripH, false, mc);
             else
                 strip_rows_mx<OutT, LO, PREC, false>(rc0, C, row0, lane, rlo, rhi, lane >= clo && lane < chi, mc);
+        } else if constexpr (G == 4) {
+            // the values and d/dY in one pass; then d/dX: the same rows with the x-weights'
+            // derivatives (formed here per strip, not held across strips)
+            OutT *rowy = reinterpret_cast<OutT *>(a.out_dy) + at, *rowx = reinterpret_cast<OutT *>(a.out_dx) + at;
+            float Cx[D1];
+            if (rlo == 0 && rhi == kStripH && clo == 0 && chi == kStripW) {
+                strip_rows<M, OutT, LO, true, MD, 3>(rc0, C, row0, rowy, lane, 0, kStripH, false);
+                coarse<true>(a, fixed<true>(sh, a.o64), X0, Y0, Cx);
+                strip_rows<M, OutT, LO, true, MD, 1>(ctx<true>(a, sh), Cx, rowx, nullptr, lane, 0, kStripH, false);
+            } else {
+                const bool lane_ok = lane >= clo && lane < chi;
+                strip_rows<M, OutT, LO, false, MD, 3>(rc0, C, row0, rowy, lane, rlo, rhi, lane_ok);
+                coarse<true>(a, fixed<true>(sh, a.o64), X0, Y0, Cx);
+                strip_rows<M, OutT, LO, false, MD, 1>(ctx<true>(a, sh), Cx, rowx, nullptr, lane, rlo, rhi, lane_ok);
+            }
         } else if (rlo == 0 && rhi == kStripH && clo == 0 && chi == kStripW) {
-            strip_rows<M, OutT, LO, true, MD, G>(rc0, C, row0, lane, 0, kStripH, false);
+            strip_rows<M, OutT, LO, true, MD, G>(rc0, C, row0, nullptr, lane, 0, kStripH, false);
         } else {
-            strip_rows<M, OutT, LO, false, MD, G>(rc0, C, row0, lane, rlo, rhi, lane >= clo && lane < chi);
+            strip_rows<M, OutT, LO, false, MD, G>(rc0, C, row0, nullptr, lane, rlo, rhi, lane >= clo && lane < chi);
         }
         __builtin_amdgcn_wave_barrier();  // the next strip rewrites this wave's keys and nodes
     }
