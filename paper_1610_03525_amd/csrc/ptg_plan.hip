@@ -315,8 +315,17 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     const int picked = tune_pick(TuneKey{PTG_TUNE_GENERAL_2D, p->smoothness + 2 * p->model, p->out_dtype == PTG_F16,
                                          size_class(nx * ny), ladder_class(freq, p->octaves)},
                                  p->smoothness >= 4 ? kTile2 : dflt);
-    const int tile_h = p->smoothness >= 4 ? kTile2 : picked;
-    const size_t lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, tile_h, &a);
+    int tile_h = p->smoothness >= 4 ? kTile2 : picked;
+    size_t lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, tile_h, &a);
+    // ladders whose cells are finer than a sample: shorter tiles until a tile's lattice
+    // footprint fits the workgroup's LDS
+    while (lds > kDyMaxLds && p->smoothness <= 3 && tile_h > 16) {
+        tile_h /= 2;
+        lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, tile_h, &a);
+    }
+    if (lds > kDyMaxLds)
+        return fail(PTG_EINVAL, "the ladder's finest cells are too small for a tile's lattice footprint in LDS "
+                                "(%zu bytes)", lds);
     if (tune_dry()) return PTG_OK;
     hipError_t e = launch_fbm2d_general(a, p->smoothness, p->out_dtype == PTG_F16, lds, s);
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm2d launch");
@@ -348,6 +357,9 @@ int fbm2d_grad(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t 
     }
     Fbm2dArgs a{};
     const size_t lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, kTile2, &a) + (size_t)kTile2 * 16;
+    if (lds > kDyMaxLds)
+        return fail(PTG_EINVAL, "the ladder's finest cells are too small for a tile's lattice footprint in LDS "
+                                "(%zu bytes)", lds);
     a.out_dx = out_dx;
     a.out_dy = out_dy;
     hipError_t e = launch_fbm2d_general_grad(a, p->smoothness, p->out_dtype == PTG_F16, lds, s);
@@ -483,6 +495,9 @@ int fbm3d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t z0, int64_t
     (void)tune_pick(TuneKey{PTG_TUNE_GENERAL_3D, p->smoothness, p->out_dtype == PTG_F16, size_class(nx * ny * nz),
                             ladder_class(a.freq, p->octaves)},
                     0);
+    if (lds > kDyMaxLds)
+        return fail(PTG_EINVAL, "the ladder's finest cells are too small for a tile's lattice footprint in LDS "
+                                "(%zu bytes)", lds);
     if (tune_dry()) return PTG_OK;
     hipError_t e = launch_fbm3d_general(a, p->smoothness, p->out_dtype == PTG_F16, lds, s);
     return e == hipSuccess ? PTG_OK : hip_fail(e, "fbm3d launch");
