@@ -66,6 +66,26 @@ def test_strip_gradient_full_size_sampled(M):
         assert np.max(np.abs(dy[y0:y0 + ny, x0:x0 + nx].cpu().numpy() - HY)) <= 4e-5 * gscale
 
 
+@pytest.mark.parametrize("M", [1, 2, 3])
+def test_strip_gradient_fp16_outputs(M):
+    """FP16 outputs of the one-launch strip gradient (a dyadic ladder with ragged edges):
+    the field equals ptg_fbm_2d's FP16 output bit for bit, the derivatives match the oracle
+    within their FP16 rounding."""
+    kw = dict(smoothness=M, octaves=6, base_freq=2.0 ** -7, seed=5)
+    nx, ny, x0, y0 = 200, 131, -(1 << 30) + 33, 77
+    h, dx, dy = (torch.empty((ny, nx), dtype=torch.float16, device="cuda") for _ in range(3))
+    ptg.fbm_2d_grad(h, dx, dy, x0=x0, y0=y0, **kw)
+    ref = torch.empty((ny, nx), dtype=torch.float16, device="cuda")
+    ptg.fbm_2d(ref, x0=x0, y0=y0, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(h, ref)
+    _, HX, HY = O.fbm_2d_grad("gradient", M, 6, 0.5, 2.0, 2.0 ** -7, 0.01, 5, x0, y0, nx, ny)
+    gscale = sum(0.5 ** o * 2.0 ** -7 * 2.0 ** o for o in range(6))
+    for got, want in ((dx, HX), (dy, HY)):
+        g = got.float().cpu().numpy()
+        assert np.all(np.abs(g - want) <= np.abs(want) * 2.0 ** -11 + 4e-5 * gscale)
+
+
 def test_fp16_outputs_and_validation():
     kw = dict(octaves=4, base_freq=2.0 ** -4, seed=2)
     h, dx, dy = (torch.empty((64, 96), dtype=torch.float16, device="cuda") for _ in range(3))
