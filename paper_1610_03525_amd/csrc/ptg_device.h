@@ -38,7 +38,8 @@ __host__ __device__ __forceinline__ uint32_t key_prefix(uint32_t seed, int32_t o
 }
 
 // Per-column part of every key (x index under its own salt).
-__host__ __device__ __forceinline__ uint32_t key_xline(int64_t ix) { return absorb_index(0x27D4EB2Fu, ix); }
+constexpr uint32_t kXSalt = 0x27D4EB2Fu;
+__host__ __device__ __forceinline__ uint32_t key_xline(int64_t ix) { return absorb_index(kXSalt, ix); }
 
 // key2 = fmix32(ky ^ kx) with ky = absorb_index(prefix, iy), kx = key_xline(ix);
 // key3 = fmix32(kzy ^ kx) with kzy = absorb_index(absorb_index(prefix, iz), iy).

@@ -148,15 +148,18 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
         foot[tid] = ft;
     }
     __syncthreads();
-    if (!lat) {
-        for (int o = 0; o < a.octaves; ++o) {
+    if (!lat) {  // octaves spread over the waves (the coarse ones have a few keys each)
+        for (int o = wave; o < a.octaves; o += 4) {
             const TileFoot ft = foot[o];
             const int nnx = uniform_i32(ft.nnx), nny = uniform_i32(ft.nny);
             const int64_t cxf = uniform_i64(ft.cxf), cyf = uniform_i64(ft.cyf);
             uint32_t *kx = kx_all + o * a.capx, *ky = ky_all + o * a.capy;
             const uint32_t pre = key_prefix(a.seed, o);
-            for (int i = tid; i < nnx; i += 256) kx[i] = key_xline(cxf + i);
-            for (int j = tid; j < nny; j += 256) ky[j] = absorb_index(pre, cyf + j);
+            for (int q = lane; q < nnx + nny; q += 64) {  // column keys, then row keys
+                const bool c = q < nnx;  // a column key is the x index absorbed under its salt
+                const uint32_t key = absorb_index(c ? kXSalt : pre, c ? cxf + q : cyf + (q - nnx));
+                (c ? kx + q : ky + (q - nnx))[0] = key;
+            }
         }
     }
 
@@ -224,7 +227,11 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
         } else {
             // node q = j nnx + i; a thread's nodes step by 256 = dj rows and di columns
             const int nn = nnx * nny, dj = 256 / nnx, di = 256 - dj * nnx;
-            int j = tid / nnx, i = tid - j * nnx;
+            // tid / nnx from the reciprocal (within one of the quotient), then corrected
+            int j = (int)(((float)tid + 0.5f) * __builtin_amdgcn_rcpf((float)nnx));
+            j -= j * nnx > tid ? 1 : 0;
+            j += (j + 1) * nnx <= tid ? 1 : 0;
+            int i = tid - j * nnx;
             const float aw = MD == 2 ? amp * a.gw : amp;
             for (int q = tid; q < nn; q += 256) {
                 const uint32_t key = key_combine(ky[j], kx[i]);
