@@ -112,8 +112,10 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v)
 
 template <int M, typename OutT, int TH, int MD = 0, bool GRAD = false>
 __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t bid, float4 *lds4,
-                                                   const LatCache *lat = nullptr)
+                                                   const LatCache *lat_in = nullptr)
 {
+    // the lattice cache holds unit gradients: the gradient model only (the others hash)
+    const LatCache *const lat = MD == 0 ? lat_in : nullptr;
     constexpr int T = kTile2;
     constexpr int RPT = TH / 4;
     static_assert(RPT <= 64, "a wave's rows are one ballot");
@@ -124,7 +126,8 @@ __device__ __forceinline__ void fbm2d_general_tile(const Fbm2dArgs &a, int64_t b
     float *gx = reinterpret_cast<float *>(foot + a.octaves);
     float *gy = gx + cap;
     float *gh = gy + cap;  // MD = 2 only
-    uint32_t *kx_all = reinterpret_cast<uint32_t *>(MD == 2 ? gh + cap : gy + cap);
+    // (the zero-gradient model's nodes hold a height only: no gy block)
+    uint32_t *kx_all = reinterpret_cast<uint32_t *>(MD == 2 ? gh + cap : MD == 1 ? gx + cap : gy + cap);
     uint32_t *ky_all = kx_all + a.octaves * a.capx;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

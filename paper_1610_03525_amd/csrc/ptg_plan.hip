@@ -240,7 +240,8 @@ size_t general_args_2d(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, 
     a->capx = footprint_cap(a->freq, p->octaves, kTile2);
     a->capy = footprint_cap(a->freq, p->octaves, tile_h);
     a->tiles_x = (int32_t)((nx + kTile2 - 1) / kTile2);
-    return (size_t)tile_h * 16 + (size_t)a->capx * a->capy * (p->model == PTG_MODEL_HEIGHT_GRADIENT ? 12 : 8) +
+    const size_t node_bytes = p->model == PTG_MODEL_HEIGHT_GRADIENT ? 12 : p->model == PTG_MODEL_ZERO_GRADIENT ? 4 : 8;
+    return (size_t)tile_h * 16 + (size_t)a->capx * a->capy * node_bytes +
            general2d_octave_lds(p->octaves, a->capx, a->capy);
 }
 
