@@ -436,14 +436,15 @@ __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t b
         foot[tid] = ft;
     }
     __syncthreads();
-    for (int o = 0; o < a.octaves; ++o) {
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+    for (int o = wave_u; o < a.octaves; o += 4) {  // octaves spread over the waves
         const TileFoot3 ft = foot[o];
         const int nnx = uniform_i32(ft.nnx), nny = uniform_i32(ft.nny), nnz = uniform_i32(ft.nnz);
         const int64_t cxf = uniform_i64(ft.cxf), cyf = uniform_i64(ft.cyf), czf = uniform_i64(ft.czf);
         uint32_t *kx = kx_all + o * a.capx, *kzy = kzy_all + o * capzy;
         const uint32_t pre = key_prefix(a.seed, o);
-        for (int i = tid; i < nnx; i += 256) kx[i] = key_xline(cxf + i);
-        for (int q = tid; q < nny * nnz; q += 256) {
+        for (int i = lane; i < nnx; i += 64) kx[i] = key_xline(cxf + i);
+        for (int q = lane; q < nny * nnz; q += 64) {
             const int k = q / nny, j = q - k * nny;
             kzy[q] = absorb_index(absorb_index(pre, czf + k), cyf + j);
         }
