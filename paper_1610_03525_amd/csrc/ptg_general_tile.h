@@ -502,6 +502,14 @@ __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t b
         Basis<M>::eval(cc.t, sx, b10x, b11x);
         __syncthreads();
 
+        // rows of the y table that enter a new y cell (the first always does)
+        uint64_t yfresh;
+        {
+            const int r = min(lane, TY - 1);
+            const int cy = __float_as_int(yt[r].x);
+            const int cp = (lane > 0 && lane < TY) ? __float_as_int(yt[r - 1].x) : -1;
+            yfresh = __ballot(lane < TY && cy != cp);
+        }
         int prev_cell = -1;
         float ca[2][2], cb[2][2], cc2[2][2];  // x-collapsed coefficients [cy][cz]
 #pragma unroll
@@ -509,28 +517,25 @@ __device__ __forceinline__ void fbm3d_general_tile(const Fbm3dArgs &a, int64_t b
             const float4 ze = zt[wave * ZPW + zz];
             const int lcz = __builtin_amdgcn_readfirstlane(__float_as_int(ze.x));
             float E0 = 0.0f, dE = 0.0f, Q0 = 0.0f, Q1 = 0.0f;
-            int prev_y = -1;
 #pragma unroll
             for (int yy = 0; yy < TY; ++yy) {
-                const float4 ye = yt[yy];
-                const int lcy = __builtin_amdgcn_readfirstlane(__float_as_int(ye.x));
-                const int cell = lcz * 65536 + lcy;
-                if (cell != prev_cell) {
-                    prev_cell = cell;
+                const f32x4 ye = load_here4(yt + yy);
+                if ((yfresh >> yy) & 1u) {  // a new y cell (or the slab's first row)
+                    const int lcy = __builtin_amdgcn_readfirstlane(__float_as_int(ye.x));
+                    const int cell = lcz * 65536 + lcy;
+                    if (cell != prev_cell) {
+                        prev_cell = cell;
 #pragma unroll
-                    for (int cz = 0; cz < 2; ++cz)
+                        for (int cz = 0; cz < 2; ++cz)
 #pragma unroll
-                        for (int cy = 0; cy < 2; ++cy) {
-                            const int q = ((lcz + cz) * nny + (lcy + cy)) * nnx + lcx;
-                            ca[cy][cz] = gxs[q] * b10x + gxs[q + 1] * b11x;
-                            if (MD == 2) ca[cy][cz] += hs[q] + sx * (hs[q + 1] - hs[q]);
-                            cb[cy][cz] = gys[q] + sx * (gys[q + 1] - gys[q]);
-                            cc2[cy][cz] = gzs[q] + sx * (gzs[q + 1] - gzs[q]);
-                        }
-                    prev_y = -1;
-                }
-                if (lcy != prev_y) {
-                    prev_y = lcy;
+                            for (int cy = 0; cy < 2; ++cy) {
+                                const int q = ((lcz + cz) * nny + (lcy + cy)) * nnx + lcx;
+                                ca[cy][cz] = gxs[q] * b10x + gxs[q + 1] * b11x;
+                                if (MD == 2) ca[cy][cz] += hs[q] + sx * (hs[q + 1] - hs[q]);
+                                cb[cy][cz] = gys[q] + sx * (gys[q + 1] - gys[q]);
+                                cc2[cy][cz] = gzs[q] + sx * (gzs[q + 1] - gzs[q]);
+                            }
+                    }
                     float Ev[2], Bq[2];
 #pragma unroll
                     for (int cy = 0; cy < 2; ++cy) {
