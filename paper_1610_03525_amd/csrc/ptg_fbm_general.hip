@@ -39,14 +39,21 @@ static hipError_t launch_dyn(void (*kernel)(Args), dim3 grid, size_t lds, hipStr
 }
 
 // Orders 4..6 (64-row tiles; gradient or height-and-gradient model).
+template <int M, int TH>
+static hipError_t launch_2d_high_th(const Fbm2dArgs &a, bool f16, dim3 grid, size_t lds, hipStream_t s)
+{
+    if (a.model == 2)
+        return f16 ? launch_dyn(k_fbm2d_general<M, __half, TH, 2>, grid, lds, s, a)
+                   : launch_dyn(k_fbm2d_general<M, float, TH, 2>, grid, lds, s, a);
+    return f16 ? launch_dyn(k_fbm2d_general<M, __half, TH>, grid, lds, s, a)
+               : launch_dyn(k_fbm2d_general<M, float, TH>, grid, lds, s, a);
+}
+
 template <int M>
 static hipError_t launch_2d_high(const Fbm2dArgs &a, bool f16, dim3 grid, size_t lds, hipStream_t s)
 {
-    if (a.model == 2)
-        return f16 ? launch_dyn(k_fbm2d_general<M, __half, 64, 2>, grid, lds, s, a)
-                   : launch_dyn(k_fbm2d_general<M, float, 64, 2>, grid, lds, s, a);
-    return f16 ? launch_dyn(k_fbm2d_general<M, __half, 64>, grid, lds, s, a)
-               : launch_dyn(k_fbm2d_general<M, float, 64>, grid, lds, s, a);
+    return a.tile_h == 128 ? launch_2d_high_th<M, 128>(a, f16, grid, lds, s)
+                           : launch_2d_high_th<M, 64>(a, f16, grid, lds, s);
 }
 
 template <int TH>
@@ -84,7 +91,7 @@ hipError_t launch_fbm2d_general(const Fbm2dArgs &a, int smooth, bool f16, size_t
 {
     const int64_t tiles = (int64_t)a.tiles_x * ((a.ny + a.tile_h - 1) / a.tile_h);
     dim3 grid((unsigned)tiles);
-    if (smooth >= 4)  // the plan gives these orders 64-row tiles
+    if (smooth >= 4)  // the plan gives these orders 64- or 128-row tiles
         return smooth == 4 ? launch_2d_high<4>(a, f16, grid, lds, s)
              : smooth == 5 ? launch_2d_high<5>(a, f16, grid, lds, s)
                            : launch_2d_high<6>(a, f16, grid, lds, s);

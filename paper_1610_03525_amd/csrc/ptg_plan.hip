@@ -312,15 +312,15 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     // twice the rows), except for the height-and-gradient model, whose larger per-tile LDS
     // block then limits the workgroups per compute unit
     const int dflt = (ny >= 1024 && p->model != PTG_MODEL_HEIGHT_GRADIENT) ? 2 * kTile2 : kTile2;
-    // (orders above 3: 64-row tiles, whatever the table holds)
+    // (orders above 3 have 64- and 128-row tiles only)
     const int picked = tune_pick(TuneKey{PTG_TUNE_GENERAL_2D, p->smoothness + 2 * p->model, p->out_dtype == PTG_F16,
                                          size_class(nx * ny), ladder_class(freq, p->octaves)},
-                                 p->smoothness >= 4 ? kTile2 : dflt);
-    int tile_h = p->smoothness >= 4 ? kTile2 : picked;
+                                 dflt);
+    int tile_h = p->smoothness >= 4 ? (picked >= 2 * kTile2 ? 2 * kTile2 : kTile2) : picked;
     size_t lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, tile_h, &a);
     // ladders whose cells are finer than a sample: shorter tiles until a tile's lattice
     // footprint fits the workgroup's LDS
-    while (lds > kDyMaxLds && p->smoothness <= 3 && tile_h > 16) {
+    while (lds > kDyMaxLds && tile_h > (p->smoothness >= 4 ? kTile2 : 16)) {
         tile_h /= 2;
         lds = general_args_2d(p, x0, y0, nx, ny, out, pitch, tile_h, &a);
     }
