@@ -309,9 +309,11 @@ int fbm2d_plain(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t
     float amp[kMaxOctaves];
     octave_tables(p, freq, amp);
     // untuned: 128-row tiles for tall fields (each octave's set-up per tile is amortised over
-    // twice the rows), except for the height-and-gradient model, whose larger per-tile LDS
-    // block then limits the workgroups per compute unit
-    const int dflt = (ny >= 1024 && p->model != PTG_MODEL_HEIGHT_GRADIENT) ? 2 * kTile2 : kTile2;
+    // twice the rows) while a tile's LDS block stays small enough for eight workgroups per
+    // compute unit; else 64 (on fine ladders the larger block would cost more occupancy)
+    Fbm2dArgs probe{};
+    const bool tall_ok = ny >= 1024 && general_args_2d(p, x0, y0, nx, ny, out, pitch, 2 * kTile2, &probe) <= 20 * 1024;
+    const int dflt = tall_ok ? 2 * kTile2 : kTile2;
     // (orders above 3 have 64- and 128-row tiles only)
     const int picked = tune_pick(TuneKey{PTG_TUNE_GENERAL_2D, p->smoothness + 2 * p->model, p->out_dtype == PTG_F16,
                                          size_class(nx * ny), ladder_class(freq, p->octaves)},
