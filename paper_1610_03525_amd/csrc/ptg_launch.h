@@ -145,7 +145,7 @@ struct Fbm3dStripArgs {
     int32_t nnx[kMaxOctaves];       // node columns of a block's footprint
     int32_t kxoff[kMaxOctaves];     // column keys of octave o in a wave's key block
     int32_t coff[kMaxOctaves];      // coarse octave: its nnx x 2 x 2 nodes (4 i + 2 k + j) from here
-    int32_t poff[kMaxOctaves];      // fine octave: its two z-plane slots (slot, then i * nny + j) from here
+    int32_t poff[kMaxOctaves];      // fine octave: its z-plane slots (slot, then i * nny + j) from here
     int32_t ytoff[kMaxOctaves], ztoff[kMaxOctaves];  // coarse octave: basis table (floats), or -1
     int32_t tab_total;              // floats of the basis table
     int32_t fwl[3];                 // fine octaves of period 8, 4, 2: their plane list in the node work list

@@ -441,7 +441,8 @@ int strip3_args(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t z0, 
         if (o < 0) continue;
         const int P = 8 >> f, plane = (BX / P + 1) * (BY / P + 1);
         a.poff[o] = nodes;
-        nodes += 2 * plane;
+        // plane slots: two, four for period 2 in the gradient model (hashed two planes ahead)
+        nodes += (f == 2 && p->model != PTG_MODEL_HEIGHT_GRADIENT ? 4 : 2) * plane;
         listed += plane;
     }
     a.nodes_total = nodes;

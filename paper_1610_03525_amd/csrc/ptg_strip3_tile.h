@@ -19,7 +19,8 @@
 //    in z (Horner), and the rows are evaluated in pairs +-v_y from its even and odd parts.
 //    Every expansion point (the block centre) lies inside the octave's own cell.
 //  * fine (periods 8, 4, 2): z-planes of nodes are hashed as the walk enters a new z cell
-//    (two plane slots per octave in the wave's LDS block); the lane's corners of the two
+//    (two plane slots per octave in the wave's LDS block; gradient model: period 2 two
+//    planes ahead at every period-4 cell, in four slots); the lane's corners of the two
 //    planes of the current z cell stay in registers; per slice each y node gives V, W and
 //    each row 4 operations, with compile-time row and slice bases.  Period 8 is one cell in
 //    y over the block: its slice cell is added to the coarse polynomial instead.
@@ -216,11 +217,18 @@ struct Strip3Wave {
     static constexpr bool H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1;
     static_assert(BY == 8 && BZ == 16, "the fine-octave classes assume 8-row, 16-slice blocks");
 
-    // A fine octave of period P: its node planes (two slots of NNX x NNY nodes, column-major),
-    // the lane's x-bases and node column, and its corners of the current z cell.
+    // Gradient model: the period-2 planes are hashed two at a time, at every other z cell of
+    // period 2, together with the period-4 (and period-8) plane due at the same slice, so the
+    // three octaves' nodes share wave iterations; period 2 then keeps four plane slots.
+    static constexpr bool AH = H2 && MD == 0;
+
+    // A fine octave of period P: its node planes (SLOTS slots of NNX x NNY nodes, column-major;
+    // plane iz in slot iz mod SLOTS), the lane's x-bases and node column, and its corners of
+    // the current z cell.
     template <int P>
     struct Fine {
         static constexpr int NNX = BX / P + 1, NNY = BY / P + 1, PLANE = NNX * NNY;
+        static constexpr int SLOTS = P == 2 && MD == 0 ? 4 : 2;
         int o = -1, s = 0, poff = 0, kx = 0, rk = 0;
         float sc = 0.0f, amp = 0.0f;
         B3 xb{0.0f, 0.0f, 0.0f};
@@ -297,19 +305,61 @@ struct Strip3Wave {
         }
     }
 
-    // Nodes of planes iz0 .. iz0 + np - 1 (np = 1, 2) into their slots (plane iz in slot
-    // iz & 1), from the octave's plane list.
+    // Nodes of planes iz0 .. iz0 + np - 1 (np = 1, 2, 3) into their slots, from the octave's
+    // plane list.
     // (ib = iz0 - Z0 / P: the plane's index in the block's row-key list)
     template <int P>
     __device__ __forceinline__ void fine_nodes(const Fine<P> &f, const uint32_t *wl, int64_t iz0, int ib, int np)
     {
-        constexpr int NNY = Fine<P>::NNY, PLANE = Fine<P>::PLANE;
-        const int slot0 = (int)(iz0 & 1) * PLANE;
+        constexpr int NNY = Fine<P>::NNY, PLANE = Fine<P>::PLANE, SM = Fine<P>::SLOTS - 1;
         for (int q = lane; q < np * PLANE; q += 64) {
-            const int pl = q >= PLANE ? 1 : 0, rem = q - pl * PLANE;
+            const int pl = q >= 2 * PLANE ? 2 : q >= PLANE ? 1 : 0, rem = q - pl * PLANE;
             const uint32_t it = wl[rem];
             const uint32_t key = key_combine(keys[f.rk + (ib + pl) * NNY + (int)(it >> 16)], keys[it & 0xFFFF]);
-            put_node(f.poff + (pl ? PLANE - slot0 : slot0) + rem, key, f.sc, f.amp);
+            put_node(f.poff + (int)((iz0 + pl) & SM) * PLANE + rem, key, f.sc, f.amp);
+        }
+    }
+
+    // Gradient model, a slice that starts a z cell of period 4 (q = Z - Z0): the period-2
+    // planes Z / 2 + 1 and Z / 2 + 2, the period-4 plane Z / 4 + 1 and, at the start of a
+    // period-8 cell, the period-8 plane Z / 8 + 1, as one list of nodes over the wave's lanes.
+    template <int Q>
+    __device__ __forceinline__ void fine_nodes_merged(const Fbm3dStripArgs &a, const uint32_t *wl_node, int64_t Z,
+                                                      int q)
+    {
+        constexpr int P2 = Fine<2>::PLANE, P4 = Fine<4>::PLANE, P8 = Fine<8>::PLANE;
+        constexpr int N2 = 2 * P2, N4 = N2 + P4, N = N4 + (Q == 0 ? P8 : 0), FULL = N2 / 64;
+        static_assert(64 * FULL >= P2, "the mixed iterations hold the second period-2 plane only");
+        const int64_t c2 = (Z >> 1) + 1, c4 = (Z >> 2) + 1, c8 = (Z >> 3) + 1;
+        const int ib2 = q / 2 + 1;
+        // iterations wholly inside the two period-2 planes
+#pragma unroll
+        for (int i = 0; i < FULL; ++i) {
+            const int t = 64 * i + lane;
+            const int pl = t >= P2 ? 1 : 0, rem = t - pl * P2;
+            const uint32_t it = wl_node[a.fwl[2] + rem];
+            const uint32_t key =
+                key_combine(keys[f2.rk + (ib2 + pl) * Fine<2>::NNY + (int)(it >> 16)], keys[it & 0xFFFF]);
+            put_node(f2.poff + (int)((c2 + pl) & 3) * P2 + rem, key, f2.sc, f2.amp);
+        }
+        // the rest: the second period-2 plane's last nodes, then period 4, then period 8; each
+        // lane picks its octave's work list, row keys, slot and scale (selected as values: a
+        // selection among the members themselves would place the octave records in scratch)
+        const int wl2 = a.fwl[2] - P2, wl4 = a.fwl[1] - N2, wl8 = a.fwl[0] - N4;
+        const int kr2 = f2.rk + (ib2 + 1) * Fine<2>::NNY, kr4 = f4.rk + (q / 4 + 1) * Fine<4>::NNY,
+                  kr8 = f8.rk + (q / 8 + 1) * Fine<8>::NNY;
+        const int d2 = f2.poff + (int)((c2 + 1) & 3) * P2 - P2, d4 = f4.poff + (int)(c4 & 1) * P4 - N2,
+                  d8 = f8.poff + (int)(c8 & 1) * P8 - N4;
+        const float s2 = f2.sc, s4 = f4.sc, s8 = f8.sc;
+        for (int t = 64 * FULL + lane; t < N; t += 64) {
+            const bool in2 = t < N2, in4 = t < N4;
+            const int wl = in2 ? wl2 : in4 ? wl4 : wl8;    // + t: the node's work-list entry
+            const int krow = in2 ? kr2 : in4 ? kr4 : kr8;  // its plane's row keys
+            const int dst = in2 ? d2 : in4 ? d4 : d8;      // + t: its place in the slot
+            const float sc = in2 ? s2 : in4 ? s4 : s8;
+            const uint32_t it = wl_node[wl + t];
+            const uint32_t key = key_combine(keys[krow + (int)(it >> 16)], keys[it & 0xFFFF]);
+            put_node(dst + t, key, sc, sc);  // (the height amplitude is unused in this model)
         }
     }
 
@@ -317,8 +367,8 @@ struct Strip3Wave {
     template <int P>
     __device__ __forceinline__ void fine_corners(const Fine<P> &f, int64_t iz, XC3 (&c)[Fine<P>::NNY]) const
     {
-        constexpr int NNY = Fine<P>::NNY, PLANE = Fine<P>::PLANE;
-        const int base = f.poff + (int)(iz & 1) * PLANE + f.col;
+        constexpr int NNY = Fine<P>::NNY, PLANE = Fine<P>::PLANE, SM = Fine<P>::SLOTS - 1;
+        const int base = f.poff + (int)(iz & SM) * PLANE + f.col;
 #pragma unroll
         for (int j = 0; j < NNY; ++j) c[j] = corner(base + j, NNY, f.xb);
     }
@@ -438,7 +488,7 @@ struct Strip3Wave {
         if (!carry) {
             if (H8) fine_nodes(f8, wl_node + a.fwl[0], Z0 >> 3, 0, 2);
             if (H4) fine_nodes(f4, wl_node + a.fwl[1], Z0 >> 2, 0, 2);
-            if (H2) fine_nodes(f2, wl_node + a.fwl[2], Z0 >> 1, 0, 2);
+            if (H2) fine_nodes(f2, wl_node + a.fwl[2], Z0 >> 1, 0, AH ? 3 : 2);
         }
         wave_sync3();
 
@@ -497,12 +547,20 @@ struct Strip3Wave {
         const int64_t Z = Z0 + q;
         // a new z cell of the fine octaves whose period divides q: its upper plane
         constexpr bool A8 = H8 && Q == 0, A4 = H4 && Q % 4 == 0, A2 = H2 && Q % 2 == 0;
+        // period-2 planes are hashed here (with AH: at every other period-2 cell, two planes)
+        constexpr bool N2 = A2 && (!AH || Q % 4 == 0);
         if ((A8 || A4 || A2) && (Q > 0 || g > 0 || carry)) {
-            wave_sync3();  // every lane has read the slot that is rewritten (two planes back)
-            if (A8) fine_nodes(f8, wl_node + a.fwl[0], (Z >> 3) + 1, q / 8 + 1, 1);
-            if (A4) fine_nodes(f4, wl_node + a.fwl[1], (Z >> 2) + 1, q / 4 + 1, 1);
-            if (A2) fine_nodes(f2, wl_node + a.fwl[2], (Z >> 1) + 1, q / 2 + 1, 1);
-            wave_sync3();
+            if (A8 || A4 || N2) {
+                wave_sync3();  // every lane has read the slots that are rewritten
+                if (AH && N2) {
+                    fine_nodes_merged<Q>(a, wl_node, Z, q);
+                } else {
+                    if (A8) fine_nodes(f8, wl_node + a.fwl[0], (Z >> 3) + 1, q / 8 + 1, 1);
+                    if (A4) fine_nodes(f4, wl_node + a.fwl[1], (Z >> 2) + 1, q / 4 + 1, 1);
+                    if (N2) fine_nodes(f2, wl_node + a.fwl[2], (Z >> 1) + 1, q / 2 + 1, 1);
+                }
+                wave_sync3();
+            }
             if (A8) {
 #pragma unroll
                 for (int j = 0; j < Fine<8>::NNY; ++j) f8.lo[j] = f8.hi[j];
