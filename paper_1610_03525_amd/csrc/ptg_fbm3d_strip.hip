@@ -29,10 +29,8 @@ __global__ __launch_bounds__(256) void k_fbm3d_strip(const Fbm3dStripArgs a)
     // node planes from a block to the next one above it
     const int64_t nwaves = (int64_t)gridDim.x * wpg, chunk = (a.blocks + nwaves - 1) / nwaves;
     const int64_t b0 = ((int64_t)blockIdx.x * wpg + wave) * chunk, b1 = min(b0 + chunk, a.blocks);
-    // (not for the height-and-gradient cells: their carried corners would keep the kernel
-    // above 256 registers)
     for (int64_t blk = b0; blk < b1; ++blk)
-        w.run(a, sh, lds4, wl_key, wl_node, blk, MD == 0 && blk > b0 && blk % a.blocks_z != 0);
+        w.run(a, sh, lds4, wl_key, wl_node, blk, blk > b0 && blk % a.blocks_z != 0);
 }
 
 template <int M, typename OutT, int LO, int MD>
