@@ -70,3 +70,16 @@ def test_fp16_output_and_crops():
     want = O.hg_fbm_3d(2, 6, 0.5, 2.0, 1 / 64, 0.3, 4, 60, -9, 5, 100, 20, 30)
     # FP16 output: round to nearest even, relative 2^-11 of |H| <= A
     assert np.max(np.abs(h.cpu().numpy().astype(np.float64) - want)) <= 2.0 ** -11 * _amp(6) + 1e-5 * _amp(6)
+
+
+@pytest.mark.parametrize("M", [1, 2])
+def test_full_size_volume_slabs(M):
+    """The 512^3 6-octave volume as the benchmark times it (base lattice 8^3, w = 0.01): every
+    sample of z-slabs that cross block boundaries inside a wave's run of consecutive blocks
+    (whose fine node planes are carried from one block to the next) and at its start and end."""
+    n, octaves, f0, seed, w = 512, 6, 8 / 512, 1, 0.01
+    got = _vol(n, n, n, 0, 0, 0, smoothness=M, octaves=octaves, base_freq=f0, seed=seed, gradient_weight=w)
+    for z0, nz in ((0, 32), (232, 32), (496, 16)):
+        want = O.hg_fbm_3d(M, octaves, 0.5, 2.0, f0, w, seed, 0, 0, z0, n, n, nz)
+        err = np.max(np.abs(got[z0:z0 + nz].cpu().numpy() - want))
+        assert err <= 1e-5 * _amp(octaves), (z0, err)
