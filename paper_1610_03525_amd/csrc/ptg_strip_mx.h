@@ -159,8 +159,12 @@ __device__ __forceinline__ void strip_rows_mx(const RowCtx &x, const float (&C)[
     if (H4) c4 = node_row<17>(x.f4, 0);
     if (H2 || H1) {
         wave_lds_sync();  // the previous strip has read its blocks
-        if (H2) stream_rows<2, R, 1>(x.keys, x.s2, 0, 0, lane);
-        if (H1) stream_rows<1, R, 1>(x.keys, x.s1, 0, 0, lane);
+        if (H2 && H1) {
+            stream_rows_21<R, 1, 1>(x.keys, x.s2, x.s1, 0, 0, 0, lane);
+        } else {
+            if (H2) stream_rows<2, R, 1>(x.keys, x.s2, 0, 0, lane);
+            if (H1) stream_rows<1, R, 1>(x.keys, x.s1, 0, 0, lane);
+        }
         wave_lds_sync();
     }
     if (H2) c2 = node_row<R / 2 + 1>(x.f2, 0);
@@ -193,8 +197,12 @@ __device__ __forceinline__ void strip_rows_mx(const RowCtx &x, const float (&C)[
             if (basis == PTG_BASIS_MONOMIAL) taylor_shift<1>(Cq, -0.125f);  // about the quarter's first row edge
             if (H2 || H1) {  // streamed periods: this quarter's node rows
                 wave_lds_sync();
-                if (H2) stream_rows<2, R, R / 2>(x.keys, x.s2, 8 * q + 1, 1, lane);
-                if (H1) stream_rows<1, R, R>(x.keys, x.s1, 16 * q + 1, 1, lane);
+                if (H2 && H1) {
+                    stream_rows_21<R, R / 2, R>(x.keys, x.s2, x.s1, 8 * q + 1, 16 * q + 1, 1, lane);
+                } else {
+                    if (H2) stream_rows<2, R, R / 2>(x.keys, x.s2, 8 * q + 1, 1, lane);
+                    if (H1) stream_rows<1, R, R>(x.keys, x.s1, 16 * q + 1, 1, lane);
+                }
                 wave_lds_sync();
             }
             typename Op::vec B;

@@ -291,6 +291,52 @@ __device__ __forceinline__ void stream_rows(const uint32_t *keys, const Streamed
     }
 }
 
+// Both streamed octaves at once (periods 2 and 1): NR2 node rows of period 2 from row j2
+// and NR1 of period 1 from row j1, into rows [l0, ...) of their blocks, as one list of nodes
+// -- period 1's first, then period 2's -- so that the lanes period 1 leaves idle in its last
+// iteration take period 2's first nodes (the same nodes, keys and values as two
+// stream_rows calls).
+template <int R, int NR2, int NR1, int MD = 0>
+__device__ __forceinline__ void stream_rows_21(const uint32_t *keys, const Streamed &s2, const Streamed &s1, int j2,
+                                               int j1, int l0, int lane)
+{
+    constexpr int NB2 = R / 2 + 1, NB1 = R + 1;
+    constexpr int N2 = (kStripW / 2 + 1) * NR2, N1 = (kStripW + 1) * NR1, FULL = N1 / 64;
+    static_assert((NR1 & (NR1 - 1)) == 0 && (NR2 * 2 == NR1 || NR2 == NR1), "row counts");
+    // iterations wholly inside period 1
+#pragma unroll
+    for (int it = 0; it < FULL; ++it) {
+        const int q = 64 * it + lane, i = q / NR1, jj = q - i * NR1;
+        const uint32_t key = key_combine(keys[s1.ky + j1 + jj], keys[s1.kx + i]);
+        s1.blk[i * NB1 + l0 + jj] = node_value<MD>(key);
+        if (MD == 2) s1.hblk[i * NB1 + l0 + jj] = height2_second(key);
+    }
+    // one iteration with period 1's last nodes and period 2's first: each lane picks its
+    // octave's keys and block (selected as values)
+    {
+        const int q = 64 * FULL + lane;
+        const bool in1 = q < N1;
+        const int qq = in1 ? q : q - N1;
+        const int i = in1 ? qq / NR1 : qq / NR2, jj = qq - i * (in1 ? NR1 : NR2);
+        float2 *const b1 = s1.blk, *const b2 = s2.blk;
+        float *const h1 = s1.hblk, *const h2 = s2.hblk;
+        const int ky1 = s1.ky + j1, ky2 = s2.ky + j2, kx1 = s1.kx, kx2 = s2.kx;
+        if (q < N1 + N2) {
+            const uint32_t key = key_combine(keys[(in1 ? ky1 : ky2) + jj], keys[(in1 ? kx1 : kx2) + i]);
+            const int at = i * (in1 ? NB1 : NB2) + l0 + jj;
+            (in1 ? b1 : b2)[at] = node_value<MD>(key);
+            if (MD == 2) (in1 ? h1 : h2)[at] = height2_second(key);
+        }
+    }
+    // the rest of period 2
+    for (int q = 64 * (FULL + 1) - N1 + lane; q < N2; q += 64) {
+        const int i = q / NR2, jj = q - i * NR2;
+        const uint32_t key = key_combine(keys[s2.ky + j2 + jj], keys[s2.kx + i]);
+        s2.blk[i * NB2 + l0 + jj] = node_value<MD>(key);
+        if (MD == 2) s2.hblk[i * NB2 + l0 + jj] = height2_second(key);
+    }
+}
+
 // A node row collapsed along x at the lane's column: value term E and y-slope term Q.  The
 // cell between node rows lo and hi has the column form E0 = lo.E, dE = hi.E - lo.E,
 // Q0 = lo.Q, Q1 = hi.Q, and adjacent cells share their common node row.
@@ -413,8 +459,12 @@ __device__ __forceinline__ void segment_rows(const RowCtx &x, const float (&Cs)[
     if (D4) s4.load(x.f4, r0, carry[1]);
     if (D2 || D1) {  // streamed periods: hash this segment's node rows first
         wave_lds_sync();  // the previous segment has read its rows
-        if (D2) stream_rows<2, R, R / 2, MD>(x.keys, x.s2, r0 / 2 + 1, 1, lane);
-        if (D1) stream_rows<1, R, R, MD>(x.keys, x.s1, r0 + 1, 1, lane);
+        if (D2 && D1) {
+            stream_rows_21<R, R / 2, R, MD>(x.keys, x.s2, x.s1, r0 / 2 + 1, r0 + 1, 1, lane);
+        } else {
+            if (D2) stream_rows<2, R, R / 2, MD>(x.keys, x.s2, r0 / 2 + 1, 1, lane);
+            if (D1) stream_rows<1, R, R, MD>(x.keys, x.s1, r0 + 1, 1, lane);
+        }
         wave_lds_sync();
     }
     if (D2) s2.load_streamed(x.f2, carry[2]);
@@ -507,8 +557,12 @@ __device__ __forceinline__ void strip_rows(const RowCtx &x, const float (&C)[2 *
     if (H4) carry[1] = node_row<17, MD>(x.f4, 0);
     if (H2 || H1) {  // streamed periods: node row 0 of the strip into block row 0
         wave_lds_sync();  // the previous strip has read its blocks
-        if (H2) stream_rows<2, R, 1, MD>(x.keys, x.s2, 0, 0, lane);
-        if (H1) stream_rows<1, R, 1, MD>(x.keys, x.s1, 0, 0, lane);
+        if (H2 && H1) {
+            stream_rows_21<R, 1, 1, MD>(x.keys, x.s2, x.s1, 0, 0, 0, lane);
+        } else {
+            if (H2) stream_rows<2, R, 1, MD>(x.keys, x.s2, 0, 0, lane);
+            if (H1) stream_rows<1, R, 1, MD>(x.keys, x.s1, 0, 0, lane);
+        }
         wave_lds_sync();
     }
     if (H2) carry[2] = node_row<R / 2 + 1, MD>(x.f2, 0);
