@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_fbm3d_strip(const Fbm3dStripArgs a)
 
     strip3_prologue<M>(a, sh, lds4, wl_key, wl_node, tid, nthreads);
     __syncthreads();
-    Strip3Wave<M, OutT, LO, MD> w(a, sh, gx, lane);
+    Strip3Wave<M, OutT, LO, MD, true> w(a, sh, gx, lane);
     // each wave takes a run of consecutive blocks (z fastest), carrying the fine octaves'
     // node planes from a block to the next one above it
     const int64_t nwaves = (int64_t)gridDim.x * wpg, chunk = (a.blocks + nwaves - 1) / nwaves;

@@ -32,8 +32,10 @@ int strip_args_2d(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx
 
 // Kernel arguments of the 3D strip kernel for a dyadic volume; returns 1 when it does not
 // apply (a ladder starting below period 4, too many keys).
+// ahead_all: period-2 plane slots for the period-2 planes hashed two ahead in every model
+// (the dense kernel); otherwise in the gradient model only (a serving workgroup).
 int strip3_args(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz,
-                void *out, Fbm3dStripArgs *a);
+                void *out, Fbm3dStripArgs *a, bool ahead_all = false);
 
 // ---- tile-shape tuning (a6) -----------------------------------------------------
 // A launch class: which kernel a call runs (PTG_TUNE_*), its cell order, output type,

@@ -370,7 +370,7 @@ int fbm2d_grad(const ptg_params *p, int64_t x0, int64_t y0, int64_t nx, int64_t 
 }
 
 int strip3_args(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t z0, int64_t nx, int64_t ny, int64_t nz,
-                void *out, Fbm3dStripArgs *ap)
+                void *out, Fbm3dStripArgs *ap, bool ahead_all)
 {
     constexpr int BX = k3BlockX, BY = k3BlockY, BZ = k3BlockZ;
     Fbm3dStripArgs &a = *ap;
@@ -441,8 +441,8 @@ int strip3_args(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t z0, 
         if (o < 0) continue;
         const int P = 8 >> f, plane = (BX / P + 1) * (BY / P + 1);
         a.poff[o] = nodes;
-        // plane slots: two, four for period 2 in the gradient model (hashed two planes ahead)
-        nodes += (f == 2 && p->model != PTG_MODEL_HEIGHT_GRADIENT ? 4 : 2) * plane;
+        // plane slots: two, four for period 2 when its planes are hashed two ahead
+        nodes += (f == 2 && (ahead_all || p->model != PTG_MODEL_HEIGHT_GRADIENT) ? 4 : 2) * plane;
         listed += plane;
     }
     a.nodes_total = nodes;
@@ -459,7 +459,7 @@ static int fbm3d_strip(const ptg_params *p, int k, int64_t x0, int64_t y0, int64
                        int64_t nz, void *out, hipStream_t s)
 {
     Fbm3dStripArgs a;
-    if (strip3_args(p, k, x0, y0, z0, nx, ny, nz, out, &a)) return 1;
+    if (strip3_args(p, k, x0, y0, z0, nx, ny, nz, out, &a, true)) return 1;
     const int hw = p->model == PTG_MODEL_HEIGHT_GRADIENT ? 1 : 0;
     const size_t shared_words =
         (size_t)strip3_shared_words(a.tab_total, a.keys_col + 4 * a.n_coarse, a.nodes_listed);

@@ -211,16 +211,19 @@ __device__ __forceinline__ void wave_sync3()
 
 // One wave's blocks of a volume.  MD = 0: gradient model; MD = 2: node heights and
 // w-weighted gradients (the height comes from the key's third word).
-template <int M, typename OutT, int LO, int MD = 0>
+// AHEAD: the period-2 planes two at a time (four plane slots for period 2 in the node block;
+// the plan sizes the block to match: the dense kernel takes it for both models, a serving
+// workgroup, whose LDS is smaller, for the gradient model only).
+template <int M, typename OutT, int LO, int MD = 0, bool AHEAD = MD == 0>
 struct Strip3Wave {
     static constexpr int BX = k3BlockX, BY = k3BlockY, BZ = k3BlockZ, D1 = 2 * M + 2;
     static constexpr bool H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1;
     static_assert(BY == 8 && BZ == 16, "the fine-octave classes assume 8-row, 16-slice blocks");
 
-    // Gradient model: the period-2 planes are hashed two at a time, at every other z cell of
-    // period 2, together with the period-4 (and period-8) plane due at the same slice, so the
-    // three octaves' nodes share wave iterations; period 2 then keeps four plane slots.
-    static constexpr bool AH = H2 && MD == 0;
+    // AHEAD: the period-2 planes are hashed two at a time, at every other z cell of period 2,
+    // together with the period-4 (and period-8) plane due at the same slice, so the three
+    // octaves' nodes share wave iterations; period 2 then keeps four plane slots.
+    static constexpr bool AH = H2 && AHEAD;
 
     // A fine octave of period P: its node planes (SLOTS slots of NNX x NNY nodes, column-major;
     // plane iz in slot iz mod SLOTS), the lane's x-bases and node column, and its corners of
@@ -228,7 +231,7 @@ struct Strip3Wave {
     template <int P>
     struct Fine {
         static constexpr int NNX = BX / P + 1, NNY = BY / P + 1, PLANE = NNX * NNY;
-        static constexpr int SLOTS = P == 2 && MD == 0 ? 4 : 2;
+        static constexpr int SLOTS = P == 2 && AHEAD ? 4 : 2;
         int o = -1, s = 0, poff = 0, kx = 0, rk = 0;
         float sc = 0.0f, amp = 0.0f;
         B3 xb{0.0f, 0.0f, 0.0f};
@@ -350,16 +353,16 @@ struct Strip3Wave {
                   kr8 = f8.rk + (q / 8 + 1) * Fine<8>::NNY;
         const int d2 = f2.poff + (int)((c2 + 1) & 3) * P2 - P2, d4 = f4.poff + (int)(c4 & 1) * P4 - N2,
                   d8 = f8.poff + (int)(c8 & 1) * P8 - N4;
-        const float s2 = f2.sc, s4 = f4.sc, s8 = f8.sc;
+        const float s2 = f2.sc, s4 = f4.sc, s8 = f8.sc, a2 = f2.amp, a4 = f4.amp, a8 = f8.amp;
         for (int t = 64 * FULL + lane; t < N; t += 64) {
             const bool in2 = t < N2, in4 = t < N4;
             const int wl = in2 ? wl2 : in4 ? wl4 : wl8;    // + t: the node's work-list entry
             const int krow = in2 ? kr2 : in4 ? kr4 : kr8;  // its plane's row keys
             const int dst = in2 ? d2 : in4 ? d4 : d8;      // + t: its place in the slot
-            const float sc = in2 ? s2 : in4 ? s4 : s8;
+            const float sc = in2 ? s2 : in4 ? s4 : s8, amp = in2 ? a2 : in4 ? a4 : a8;
             const uint32_t it = wl_node[wl + t];
             const uint32_t key = key_combine(keys[krow + (int)(it >> 16)], keys[it & 0xFFFF]);
-            put_node(dst + t, key, sc, sc);  // (the height amplitude is unused in this model)
+            put_node(dst + t, key, sc, amp);
         }
     }
 
