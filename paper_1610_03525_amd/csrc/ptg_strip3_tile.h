@@ -323,7 +323,7 @@ struct Strip3Wave {
         }
     }
 
-    // Gradient model, a slice that starts a z cell of period 4 (q = Z - Z0): the period-2
+    // AHEAD, a slice that starts a z cell of period 4 (q = Z - Z0): the period-2
     // planes Z / 2 + 1 and Z / 2 + 2, the period-4 plane Z / 4 + 1 and, at the start of a
     // period-8 cell, the period-8 plane Z / 8 + 1, as one list of nodes over the wave's lanes.
     template <int Q>
