@@ -137,9 +137,10 @@ int strip_args_2d(const ptg_params *p, int k, int64_t x0, int64_t y0, int64_t nx
     a.lo = std::min(smin, 6);
     int nodes = 0, keys = 0, kcol = 0;
     // periods 2 and 1 (ladders that reach them) are streamed: their node rows are hashed per
-    // row segment (8 rows for cubic cells, 16 for quintic) into a block of that height,
-    // instead of per strip (65 x 65 nodes at period 1 would hold 34 KB of LDS per wave)
-    const int seg_rows = (p->smoothness == 1 && p->form == PTG_FORM_PLAIN) ? 8 : 16;
+    // row segment (8 rows for cubic cells, in every form; 16 for higher orders) into a block
+    // of that height, instead of per strip (65 x 65 nodes at period 1 would hold 34 KB of LDS
+    // per wave)
+    const int seg_rows = p->smoothness == 1 ? 8 : 16;
     const bool stream = a.lo <= 1;
     for (int o = 0; o < p->octaves; ++o)  // column keys of every octave first, then row keys
         kcol += std::max(SW >> std::min(k - o, 30), 1) + 1;

@@ -145,14 +145,16 @@ struct MxConst {
 
 // The rows of a strip in the precision form (cubic cells): the same hashing, fused coarse
 // polynomial and node rows as strip_rows, row blocks of 4 evaluated by one MFMA each.
-// Streamed periods (2, 1) are hashed per 16-row quarter.
+// Streamed periods (2, 1) are hashed per 8-row half quarter.
 template <typename OutT, int LO, int PREC, bool FULL>
 __device__ __forceinline__ void strip_rows_mx(const RowCtx &x, const float (&C)[4], OutT *rp, int lane, int rlo,
                                               int rhi, bool lane_ok, const MxConst<PREC> &mc)
 {
     typedef MxOp<PREC> Op;
     constexpr bool H32 = LO <= 5, H16 = LO <= 4, H8 = LO <= 3, H4 = LO <= 2, H2 = LO <= 1, H1 = LO == 0;
-    constexpr int R = 16;
+    // streamed periods: node rows hashed per half quarter (8 rows, as in the plain C1 form),
+    // which keeps a wave's blocks small enough for three workgroups of four waves per CU
+    constexpr int RS = 8;
     const int basis = mc.basis;
     NR c8, c4, c2, c1;  // node row carried into the next quarter (or block)
     if (H8) c8 = node_row<9>(x.f8, 0);
@@ -160,15 +162,15 @@ __device__ __forceinline__ void strip_rows_mx(const RowCtx &x, const float (&C)[
     if (H2 || H1) {
         wave_lds_sync();  // the previous strip has read its blocks
         if (H2 && H1) {
-            stream_rows_21<R, 1, 1>(x.keys, x.s2, x.s1, 0, 0, 0, lane);
+            stream_rows_21<RS, 1, 1>(x.keys, x.s2, x.s1, 0, 0, 0, lane);
         } else {
-            if (H2) stream_rows<2, R, 1>(x.keys, x.s2, 0, 0, lane);
-            if (H1) stream_rows<1, R, 1>(x.keys, x.s1, 0, 0, lane);
+            if (H2) stream_rows<2, RS, 1>(x.keys, x.s2, 0, 0, lane);
+            if (H1) stream_rows<1, RS, 1>(x.keys, x.s1, 0, 0, lane);
         }
         wave_lds_sync();
     }
-    if (H2) c2 = node_row<R / 2 + 1>(x.f2, 0);
-    if (H1) c1 = node_row<R + 1>(x.f1, 0);
+    if (H2) c2 = node_row<RS / 2 + 1>(x.f2, 0);
+    if (H1) c1 = node_row<RS + 1>(x.f1, 0);
     NR n32[3], n16lo;
     if (H32) {
 #pragma unroll
@@ -195,16 +197,6 @@ __device__ __forceinline__ void strip_rows_mx(const RowCtx &x, const float (&C)[
                 n16lo = hi;
             }
             if (basis == PTG_BASIS_MONOMIAL) taylor_shift<1>(Cq, -0.125f);  // about the quarter's first row edge
-            if (H2 || H1) {  // streamed periods: this quarter's node rows
-                wave_lds_sync();
-                if (H2 && H1) {
-                    stream_rows_21<R, R / 2, R>(x.keys, x.s2, x.s1, 8 * q + 1, 16 * q + 1, 1, lane);
-                } else {
-                    if (H2) stream_rows<2, R, R / 2>(x.keys, x.s2, 8 * q + 1, 1, lane);
-                    if (H1) stream_rows<1, R, R>(x.keys, x.s1, 16 * q + 1, 1, lane);
-                }
-                wave_lds_sync();
-            }
             typename Op::vec B;
             B[0] = Op::cvt(Cq[1]);
             B[1] = Op::cvt(Cq[2]);
@@ -212,6 +204,17 @@ __device__ __forceinline__ void strip_rows_mx(const RowCtx &x, const float (&C)[
             float k80 = 0.0f;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
+                if ((H2 || H1) && (b & 1) == 0) {  // streamed periods: this half quarter's node rows
+                    const int r8 = 8 * (2 * q + (b >> 1));  // its first row in the strip
+                    wave_lds_sync();
+                    if (H2 && H1) {
+                        stream_rows_21<RS, RS / 2, RS>(x.keys, x.s2, x.s1, r8 / 2 + 1, r8 + 1, 1, lane);
+                    } else {
+                        if (H2) stream_rows<2, RS, RS / 2>(x.keys, x.s2, r8 / 2 + 1, 1, lane);
+                        if (H1) stream_rows<1, RS, RS>(x.keys, x.s1, r8 + 1, 1, lane);
+                    }
+                    wave_lds_sync();
+                }
                 if (H8 && (b & 1) == 0) {  // the period-8 cell of blocks b, b + 1
                     const NR hi = node_row<9>(x.f8, 2 * q + (b >> 1) + 1);
                     const MxK k8 = mx_cell_coeffs(basis, c8, hi);
@@ -235,18 +238,18 @@ __device__ __forceinline__ void strip_rows_mx(const RowCtx &x, const float (&C)[
                 } else if (b == 0) {
                     B[6] = B[7] = Op::cvt(0.0f);
                 }
-                // the block's node rows of the streamed periods (rows of the quarter's block)
+                // the block's node rows of the streamed periods (rows of the half quarter's block)
                 NR s2[3], s1[5];
                 if (H2) {
                     s2[0] = c2;
 #pragma unroll
-                    for (int j = 1; j <= 2; ++j) s2[j] = node_row<R / 2 + 1>(x.f2, 2 * b + j);
+                    for (int j = 1; j <= 2; ++j) s2[j] = node_row<RS / 2 + 1>(x.f2, 2 * (b & 1) + j);
                     c2 = s2[2];
                 }
                 if (H1) {
                     s1[0] = c1;
 #pragma unroll
-                    for (int j = 1; j <= 4; ++j) s1[j] = node_row<R + 1>(x.f1, 4 * b + j);
+                    for (int j = 1; j <= 4; ++j) s1[j] = node_row<RS + 1>(x.f1, 4 * (b & 1) + j);
                     c1 = s1[4];
                 }
                 mx_f4 acc;
